@@ -1,0 +1,536 @@
+/*
+ * Plain FP64 CPU oracle for one DUGKS time step of the nonlinear
+ * convection-diffusion equation (Shang, Chai, Wang, Shi, "Discrete unified gas
+ * kinetic scheme for nonlinear convection-diffusion equations", arXiv
+ * 1906.11036).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark load this file.  It shares no code,
+ * header, table or constant generator with the HIP library; neither includes
+ * or links the other.
+ *
+ * Everything is IEEE binary64, built with -O2 -ffp-contract=off, no fast-math,
+ * no intrinsics.  Sums over discrete directions run in index order 0..Q-1.
+ * The step follows the one-step summary at the end of Section 2 in the paper's
+ * order:
+ *   phi -> f~, E  (eq. 2.3)            -> f~+, fbar+  (eqs. 2.13, 2.21)
+ *   -> fbar+ at the face (eq. 2.20)    -> fbar(x_b, t+h) (eqs. 2.19, 2.26)
+ *   -> phi(x_b, t+h) = sum fbar        -> f(x_b, t+h) (eq. 2.22)
+ *   -> face flux J (eq. 2.9)           -> f~(t+dt) (eq. 2.24 with R = F = 0)
+ *   -> phi = sum f~.
+ *
+ * Readings of points the paper leaves open (each one also listed in the
+ * design notes):
+ *   - 2-D face gradient: the normal derivative is the two-cell difference of
+ *     eq. 2.20; the tangential derivative at the face is the mean of the two
+ *     adjacent cells' central differences along the face.
+ *   - Point values at cell centres stand for cell averages (eq. 2.10).
+ *   - dt = cfl * (smallest cell width in x or y) / c  (Sec. 2, after eq. 2.9).
+ *   - lambda = alpha / c_s^2 (Chapman-Enskog result, Sec. 3).
+ *   - C = integral from 0 to phi of B'(s) B'(s)^T ds (Sec. 2 after eq. 2.3
+ *     and Remark 3), integration constant zero.
+ *   - D2Q9 weights 4/9, 1/9 (x4), 1/36 (x4) (the printed second group label of
+ *     eq. 2.5 is a typo); D2Q5 weights 1/3, 1/6 (x4) with the linear
+ *     equilibrium of Remark 3, which requires D = phi I.
+ *   - Boundary ghosts, one cell wide, corners included:
+ *       periodic  : wrapped cell, wrapped width;
+ *       Dirichlet : non-equilibrium extrapolation,
+ *                   fbar+_g = E(phi_g) + (fbar+_a - E(phi_a)), a = adjacent
+ *                   interior cell (diagonal for corners), phi_g = boundary data
+ *                   at the ghost centre at t_n, supplied by the caller;
+ *       mirror    : specular zero-flux wall, fbar+_g,i = fbar+_a,m(i) with
+ *                   m(i) the direction whose normal component is reversed.
+ *     Wall ghosts take the width of the adjacent interior cell.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_MAXQ 9
+#define OR_MAXDEG 4
+
+enum { OR_PERIODIC = 0, OR_DIRICHLET = 1, OR_MIRROR = 2 };
+
+typedef struct {
+  int nx, ny, q;
+  double c, cfl, alpha;
+  int bcx, bcy;
+  /* lattice */
+  double cx[OR_MAXQ], cy[OR_MAXQ], w[OR_MAXQ], cs2;
+  int mirx[OR_MAXQ], miry[OR_MAXQ];
+  /* coefficient polynomials  B(phi) = sum_k b_k phi^k,  D(phi) = sum_k M_k phi^k */
+  int bdeg, ddeg;
+  double bx[OR_MAXDEG + 1], by[OR_MAXDEG + 1];
+  double dxx[OR_MAXDEG + 1], dxy[OR_MAXDEG + 1], dyy[OR_MAXDEG + 1];
+  /* time stepping constants */
+  double lambda, dt, h;
+  double a1, b1, a2, b2, a3, b3;
+  /* geometry, index shifted by one so that ghost -1 sits at [0] */
+  double *xf, *yf;        /* faces, nx+1 / ny+1 */
+  double *wx, *wy;        /* widths of cells -1..n */
+  double *xc, *yc;        /* centres of cells -1..n */
+  /* state */
+  double *f;              /* f~ [q][ny][nx] */
+  long step;
+  double t;
+} Oracle;
+
+/* ---------------------------------------------------------------- lattice */
+
+/* D2Q9 velocities of eq. 2.5 (columns of the 2x9 matrix) and D2Q5 (the first
+ * five of them, the D(2)Q(2d+1) set named in Remark 3). */
+static const int LAT_CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int LAT_CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+
+static void set_lattice(Oracle* o) {
+  int i, k;
+  o->cs2 = o->c * o->c / 3.0;                   /* c_s = c / sqrt(3), eq. 2.5 */
+  for (i = 0; i < o->q; ++i) {
+    o->cx[i] = o->c * LAT_CX[i];
+    o->cy[i] = o->c * LAT_CY[i];
+    if (o->q == 9)
+      o->w[i] = (i == 0) ? 4.0 / 9.0 : (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
+    else
+      o->w[i] = (i == 0) ? 1.0 / 3.0 : 1.0 / 6.0;
+  }
+  /* mirror maps: the direction with the reversed normal component */
+  for (i = 0; i < o->q; ++i) {
+    o->mirx[i] = o->miry[i] = -1;
+    for (k = 0; k < o->q; ++k) {
+      if (LAT_CX[k] == -LAT_CX[i] && LAT_CY[k] == LAT_CY[i]) o->mirx[i] = k;
+      if (LAT_CX[k] == LAT_CX[i] && LAT_CY[k] == -LAT_CY[i]) o->miry[i] = k;
+    }
+  }
+}
+
+/* ------------------------------------------------------------ equilibrium */
+
+static double poly(const double* a, int deg, double x) {
+  double s = 0.0, p = 1.0;
+  int k;
+  for (k = 0; k <= deg; ++k) { s += a[k] * p; p *= x; }
+  return s;
+}
+
+/* C(phi) = int_0^phi B'(s) B'(s)^T ds, written out term by term:
+ * B'(s) = sum_{k>=1} k b_k s^(k-1), so the (u,v) entry is
+ * sum_{k,l>=1} k l bu_k bv_l phi^(k+l-1) / (k+l-1). */
+static double c_moment(const Oracle* o, const double* bu, const double* bv, double phi) {
+  double s = 0.0;
+  int k, l, e, m;
+  for (k = 1; k <= o->bdeg; ++k)
+    for (l = 1; l <= o->bdeg; ++l) {
+      double p = 1.0;
+      e = k + l - 1;
+      for (m = 0; m < e; ++m) p *= phi;
+      s += (double)(k * l) * bu[k] * bv[l] * p / (double)e;
+    }
+  return s;
+}
+
+/* Equilibrium of eq. 2.3:
+ * E_i = w_i [ phi + c_i.B / cs2 + (cs2 D + C - cs2 phi I):(c_i c_i - cs2 I) / (2 cs2^2) ].
+ * D2Q5 uses the linear equilibrium of Remark 3: E_i = w_i (phi + c_i.B / cs2). */
+static void feq(const Oracle* o, double phi, double* E) {
+  int i;
+  double Bx = poly(o->bx, o->bdeg, phi), By = poly(o->by, o->bdeg, phi);
+  double cs2 = o->cs2;
+  if (o->q == 5) {
+    for (i = 0; i < o->q; ++i)
+      E[i] = o->w[i] * (phi + (o->cx[i] * Bx + o->cy[i] * By) / cs2);
+    return;
+  }
+  double Dxx = poly(o->dxx, o->ddeg, phi), Dxy = poly(o->dxy, o->ddeg, phi),
+         Dyy = poly(o->dyy, o->ddeg, phi);
+  double Cxx = c_moment(o, o->bx, o->bx, phi), Cxy = c_moment(o, o->bx, o->by, phi),
+         Cyy = c_moment(o, o->by, o->by, phi);
+  double Mxx = cs2 * Dxx + Cxx - cs2 * phi;
+  double Mxy = cs2 * Dxy + Cxy;
+  double Myy = cs2 * Dyy + Cyy - cs2 * phi;
+  for (i = 0; i < o->q; ++i) {
+    double cx = o->cx[i], cy = o->cy[i];
+    double contr = Mxx * (cx * cx - cs2) + 2.0 * Mxy * cx * cy + Myy * (cy * cy - cs2);
+    E[i] = o->w[i] * (phi + (cx * Bx + cy * By) / cs2 + contr / (2.0 * cs2 * cs2));
+  }
+}
+
+/* --------------------------------------------------------------- geometry */
+
+#define XW(o, i) ((o)->wx[(i) + 1])
+#define YW(o, j) ((o)->wy[(j) + 1])
+#define XC(o, i) ((o)->xc[(i) + 1])
+#define YC(o, j) ((o)->yc[(j) + 1])
+
+static void build_axis(int n, const double* f, int bc, double* w, double* c) {
+  int i;
+  for (i = 0; i < n; ++i) {
+    w[i + 1] = f[i + 1] - f[i];
+    c[i + 1] = 0.5 * (f[i] + f[i + 1]);
+  }
+  w[0] = (bc == OR_PERIODIC) ? w[n] : w[1];
+  w[n + 1] = (bc == OR_PERIODIC) ? w[1] : w[n];
+  c[0] = f[0] - 0.5 * w[0];
+  c[n + 1] = f[n] + 0.5 * w[n + 1];
+}
+
+/* ------------------------------------------------------------ public API */
+
+Oracle* or_create(int nx, int ny, const double* xf, const double* yf, int q, double c,
+                  double cfl, double alpha, int bcx, int bcy) {
+  Oracle* o;
+  int i;
+  double dmin;
+  if (nx < 1 || ny < 1 || (q != 9 && q != 5) || !(c > 0) || !(cfl > 0) || !(alpha > 0))
+    return NULL;
+  if (bcx < 0 || bcx > 2 || bcy < 0 || bcy > 2) return NULL;
+  /* a Dirichlet wall meeting a mirror wall has no defined corner rule */
+  if ((bcx == OR_DIRICHLET && bcy == OR_MIRROR) || (bcx == OR_MIRROR && bcy == OR_DIRICHLET))
+    return NULL;
+  o = (Oracle*)calloc(1, sizeof(Oracle));
+  o->nx = nx; o->ny = ny; o->q = q; o->c = c; o->cfl = cfl; o->alpha = alpha;
+  o->bcx = bcx; o->bcy = bcy;
+  set_lattice(o);
+  o->xf = (double*)malloc(sizeof(double) * (nx + 1));
+  o->yf = (double*)malloc(sizeof(double) * (ny + 1));
+  memcpy(o->xf, xf, sizeof(double) * (nx + 1));
+  memcpy(o->yf, yf, sizeof(double) * (ny + 1));
+  o->wx = (double*)malloc(sizeof(double) * (nx + 2));
+  o->xc = (double*)malloc(sizeof(double) * (nx + 2));
+  o->wy = (double*)malloc(sizeof(double) * (ny + 2));
+  o->yc = (double*)malloc(sizeof(double) * (ny + 2));
+  build_axis(nx, o->xf, bcx, o->wx, o->xc);
+  build_axis(ny, o->yf, bcy, o->wy, o->yc);
+  o->f = (double*)calloc((size_t)q * nx * ny, sizeof(double));
+  /* B = D = 0 until set */
+  /* constants (Sec. 2 and Sec. 3) */
+  o->lambda = alpha / o->cs2;
+  dmin = XW(o, 0);
+  for (i = 0; i < nx; ++i) if (XW(o, i) < dmin) dmin = XW(o, i);
+  for (i = 0; i < ny; ++i) if (YW(o, i) < dmin) dmin = YW(o, i);
+  o->dt = cfl * dmin / c;
+  o->h = 0.5 * o->dt;
+  {
+    double L = o->lambda, dt = o->dt, h = o->h;
+    o->a1 = (2.0 * L - h) / (2.0 * L + dt);   /* eq. 2.21 */
+    o->b1 = 3.0 * h / (2.0 * L + dt);
+    o->a2 = (2.0 * L - dt) / (2.0 * L + dt);  /* eq. 2.13 */
+    o->b2 = 2.0 * dt / (2.0 * L + dt);
+    o->a3 = 2.0 * L / (2.0 * L + h);          /* eq. 2.22 */
+    o->b3 = h / (2.0 * L + h);
+  }
+  return o;
+}
+
+void or_destroy(Oracle* o) {
+  if (!o) return;
+  free(o->xf); free(o->yf); free(o->wx); free(o->wy); free(o->xc); free(o->yc); free(o->f);
+  free(o);
+}
+
+int or_set_B(Oracle* o, int deg, const double* bx, const double* by) {
+  int k;
+  if (deg < 0 || deg > OR_MAXDEG) return -1;
+  memset(o->bx, 0, sizeof(o->bx)); memset(o->by, 0, sizeof(o->by));
+  for (k = 0; k <= deg; ++k) { o->bx[k] = bx[k]; o->by[k] = by[k]; }
+  o->bdeg = deg;
+  return 0;
+}
+
+int or_set_D(Oracle* o, int deg, const double* dxx, const double* dxy, const double* dyy) {
+  int k;
+  if (deg < 0 || deg > OR_MAXDEG) return -1;
+  memset(o->dxx, 0, sizeof(o->dxx)); memset(o->dxy, 0, sizeof(o->dxy));
+  memset(o->dyy, 0, sizeof(o->dyy));
+  for (k = 0; k <= deg; ++k) { o->dxx[k] = dxx[k]; o->dxy[k] = dxy[k]; o->dyy[k] = dyy[k]; }
+  o->ddeg = deg;
+  return 0;
+}
+
+/* constants: lambda, dt, h, a1, b1, a2, b2, a3, b3, cs2 */
+void or_constants(const Oracle* o, double* out) {
+  out[0] = o->lambda; out[1] = o->dt; out[2] = o->h;
+  out[3] = o->a1; out[4] = o->b1; out[5] = o->a2; out[6] = o->b2;
+  out[7] = o->a3; out[8] = o->b3; out[9] = o->cs2;
+}
+
+/* geometry with ghosts: widths and centres of cells -1..n along x and y */
+void or_geometry(const Oracle* o, double* wx, double* xc, double* wy, double* yc) {
+  memcpy(wx, o->wx, sizeof(double) * (o->nx + 2));
+  memcpy(xc, o->xc, sizeof(double) * (o->nx + 2));
+  memcpy(wy, o->wy, sizeof(double) * (o->ny + 2));
+  memcpy(yc, o->yc, sizeof(double) * (o->ny + 2));
+}
+
+void or_feq(const Oracle* o, double phi, double* E) { feq(o, phi, E); }
+
+/* Initialisation of Sec. 4: f~(x, t0) = E(phi(x, t0)), point values at centres. */
+void or_set_phi(Oracle* o, const double* phi) {
+  int i, j, k;
+  double E[OR_MAXQ];
+  size_t N = (size_t)o->nx * o->ny;
+  for (j = 0; j < o->ny; ++j)
+    for (i = 0; i < o->nx; ++i) {
+      feq(o, phi[(size_t)j * o->nx + i], E);
+      for (k = 0; k < o->q; ++k) o->f[k * N + (size_t)j * o->nx + i] = E[k];
+    }
+  o->step = 0; o->t = 0.0;
+}
+
+void or_set_f(Oracle* o, const double* f) {
+  memcpy(o->f, f, sizeof(double) * o->q * o->nx * o->ny);
+}
+void or_get_f(const Oracle* o, double* f) {
+  memcpy(f, o->f, sizeof(double) * o->q * o->nx * o->ny);
+}
+void or_set_clock(Oracle* o, long step, double t) { o->step = step; o->t = t; }
+long or_step_index(const Oracle* o) { return o->step; }
+double or_time(const Oracle* o) { return o->t; }
+
+/* phi = sum_i f~_i (Sec. 2, after eq. 2.13) */
+void or_get_phi(const Oracle* o, double* phi) {
+  int i, k;
+  size_t N = (size_t)o->nx * o->ny;
+  for (i = 0; i < (int)N; ++i) {
+    double s = 0.0;
+    for (k = 0; k < o->q; ++k) s += o->f[k * N + i];
+    phi[i] = s;
+  }
+}
+
+/* ------------------------------------------------------------------- step */
+
+static int ring_index(const Oracle* o, int i, int j) {
+  if (j == -1) return i + 1;
+  if (j == o->ny) return (o->nx + 2) + i + 1;
+  if (i == -1) return 2 * (o->nx + 2) + j;
+  return 2 * (o->nx + 2) + o->ny + j; /* i == nx */
+}
+
+static int wrap_or_clamp(int i, int n, int bc) {
+  if (i >= 0 && i < n) return i;
+  if (bc == OR_PERIODIC) return (i + n) % n;
+  return i < 0 ? 0 : n - 1;
+}
+
+/* fbar+ at cell (i, j), i in -1..nx, j in -1..ny, from the current f~ and the
+ * ghost rules.  fbar+ = a1 f~ + b1 E(phi)  (eq. 2.21). */
+static void fbar_plus(const Oracle* o, int i, int j, const double* ring, double* out) {
+  int si = wrap_or_clamp(i, o->nx, o->bcx), sj = wrap_or_clamp(j, o->ny, o->bcy);
+  size_t N = (size_t)o->nx * o->ny, c = (size_t)sj * o->nx + si;
+  double ft[OR_MAXQ], E[OR_MAXQ], phi = 0.0, tmp[OR_MAXQ];
+  int k;
+  int xwall = (i < 0 || i >= o->nx) && o->bcx != OR_PERIODIC;
+  int ywall = (j < 0 || j >= o->ny) && o->bcy != OR_PERIODIC;
+  for (k = 0; k < o->q; ++k) { ft[k] = o->f[k * N + c]; phi += ft[k]; }
+  feq(o, phi, E);
+  for (k = 0; k < o->q; ++k) out[k] = o->a1 * ft[k] + o->b1 * E[k];
+  if (!xwall && !ywall) return;
+  if ((xwall && o->bcx == OR_DIRICHLET) || (ywall && o->bcy == OR_DIRICHLET)) {
+    double phig = ring[ring_index(o, i, j)], Eg[OR_MAXQ];
+    feq(o, phig, Eg);
+    for (k = 0; k < o->q; ++k) out[k] = Eg[k] + (out[k] - E[k]);
+    return;
+  }
+  /* mirror walls */
+  memcpy(tmp, out, sizeof(tmp));
+  if (xwall) for (k = 0; k < o->q; ++k) out[k] = tmp[o->mirx[k]];
+  memcpy(tmp, out, sizeof(tmp));
+  if (ywall) for (k = 0; k < o->q; ++k) out[k] = tmp[o->miry[k]];
+}
+
+/* Half-step interface distribution and flux on one face.
+ *   fL, fR : fbar+ at the two cells across the face (L on the low side)
+ *   tL, tR : central-difference slopes of fbar+ along the face at L and R
+ *   dn     : distance between the two centres, wl : face minus L centre
+ *   (cn, ct) : velocity components normal / tangential to the face
+ * Linear reconstruction (eq. 2.20), Taylor shift back along the
+ * characteristic (eq. 2.19 in the form of eq. 2.26), interface phi (sum of
+ * fbar), f = a3 fbar + b3 E(phi_b)  (eq. 2.22), flux c_n f  (eq. 2.9). */
+static void face_flux(const Oracle* o, const double* cn, const double* ct, const double* fL,
+                      const double* fR, const double* tL, const double* tR, double dn,
+                      double wl, double* flux) {
+  double fb[OR_MAXQ], E[OR_MAXQ], phib = 0.0;
+  int k;
+  for (k = 0; k < o->q; ++k) {
+    double Gn = (fR[k] - fL[k]) / dn;
+    double v = fL[k] + wl * Gn;
+    double Gt = 0.5 * (tL[k] + tR[k]);
+    fb[k] = v - o->h * (cn[k] * Gn + ct[k] * Gt);
+  }
+  for (k = 0; k < o->q; ++k) phib += fb[k];
+  feq(o, phib, E);
+  for (k = 0; k < o->q; ++k) flux[k] = cn[k] * (o->a3 * fb[k] + o->b3 * E[k]);
+}
+
+static void slope(const Oracle* o, const double* fm, const double* fp, double dist, double* s) {
+  int k;
+  for (k = 0; k < o->q; ++k) s[k] = (fp[k] - fm[k]) / dist;
+}
+
+/* f~ update of eq. 2.24 on a Cartesian cell: the surface integral of eq. 2.9
+ * with the midpoint rule on each of the four faces, divided by |V|. */
+static void update_cell(const Oracle* o, size_t c, const double* ft_plus, const double* FW,
+                        const double* FE, const double* FS, const double* FN, double dxi,
+                        double dyj, double* out) {
+  int k;
+  (void)c;
+  for (k = 0; k < o->q; ++k)
+    out[k] = ft_plus[k] - o->dt * ((FE[k] - FW[k]) / dxi + (FN[k] - FS[k]) / dyj);
+}
+
+static void ftilde_plus(const Oracle* o, size_t c, double* out) {
+  size_t N = (size_t)o->nx * o->ny;
+  double ft[OR_MAXQ], E[OR_MAXQ], phi = 0.0;
+  int k;
+  for (k = 0; k < o->q; ++k) { ft[k] = o->f[k * N + c]; phi += ft[k]; }
+  feq(o, phi, E);
+  for (k = 0; k < o->q; ++k) out[k] = o->a2 * ft[k] + o->b2 * E[k]; /* eq. 2.13 */
+}
+
+/* One full step over the grid, phase by phase.  ring: boundary phi at ghost
+ * centres for this step (2(nx+ny)+4 values) or NULL without Dirichlet walls. */
+static void step_once(Oracle* o, const double* ring) {
+  const int nx = o->nx, ny = o->ny, q = o->q;
+  const size_t N = (size_t)nx * ny;
+  const int NX2 = nx + 2;
+  double* G = (double*)malloc(sizeof(double) * (size_t)(nx + 2) * (ny + 2) * q);
+  double* SY = (double*)malloc(sizeof(double) * (size_t)(nx + 2) * ny * q);
+  double* SX = (double*)malloc(sizeof(double) * (size_t)nx * (ny + 2) * q);
+  double* FX = (double*)malloc(sizeof(double) * (size_t)(nx + 1) * ny * q);
+  double* FY = (double*)malloc(sizeof(double) * (size_t)nx * (ny + 1) * q);
+  double* fn = (double*)malloc(sizeof(double) * N * q);
+  double zx[OR_MAXQ], zy[OR_MAXQ];
+  int i, j, k;
+#define GP(i, j) (G + ((size_t)((j) + 1) * NX2 + ((i) + 1)) * q)
+  for (k = 0; k < q; ++k) { zx[k] = o->cx[k]; zy[k] = o->cy[k]; }
+  /* 1-2: fbar+ on interior and ghost cells */
+#pragma omp parallel for private(i)
+  for (j = -1; j <= ny; ++j)
+    for (i = -1; i <= nx; ++i) fbar_plus(o, i, j, ring, GP(i, j));
+  /* 3: slopes along y at cells -1..nx, rows 0..ny-1; along x at 0..nx-1, rows -1..ny */
+#pragma omp parallel for private(i)
+  for (j = 0; j < ny; ++j)
+    for (i = -1; i <= nx; ++i)
+      slope(o, GP(i, j - 1), GP(i, j + 1), YC(o, j + 1) - YC(o, j - 1),
+            SY + ((size_t)j * NX2 + (i + 1)) * q);
+#pragma omp parallel for private(i)
+  for (j = -1; j <= ny; ++j)
+    for (i = 0; i < nx; ++i)
+      slope(o, GP(i - 1, j), GP(i + 1, j), XC(o, i + 1) - XC(o, i - 1),
+            SX + ((size_t)(j + 1) * nx + i) * q);
+  /* 4: x-faces between (i-1, j) and (i, j), i = 0..nx */
+#pragma omp parallel for private(i)
+  for (j = 0; j < ny; ++j)
+    for (i = 0; i <= nx; ++i)
+      face_flux(o, zx, zy, GP(i - 1, j), GP(i, j), SY + ((size_t)j * NX2 + i) * q,
+                SY + ((size_t)j * NX2 + i + 1) * q, XC(o, i) - XC(o, i - 1),
+                o->xf[i] - XC(o, i - 1), FX + ((size_t)j * (nx + 1) + i) * q);
+  /* y-faces between (i, j-1) and (i, j), j = 0..ny */
+#pragma omp parallel for private(i)
+  for (j = 0; j <= ny; ++j)
+    for (i = 0; i < nx; ++i)
+      face_flux(o, zy, zx, GP(i, j - 1), GP(i, j), SX + ((size_t)j * nx + i) * q,
+                SX + ((size_t)(j + 1) * nx + i) * q, YC(o, j) - YC(o, j - 1),
+                o->yf[j] - YC(o, j - 1), FY + ((size_t)j * nx + i) * q);
+  /* 5: update */
+#pragma omp parallel for private(i)
+  for (j = 0; j < ny; ++j)
+    for (i = 0; i < nx; ++i) {
+      size_t c = (size_t)j * nx + i;
+      double ftp[OR_MAXQ], out[OR_MAXQ];
+      ftilde_plus(o, c, ftp);
+      update_cell(o, c, ftp, FX + ((size_t)j * (nx + 1) + i) * q,
+                  FX + ((size_t)j * (nx + 1) + i + 1) * q, FY + ((size_t)j * nx + i) * q,
+                  FY + ((size_t)(j + 1) * nx + i) * q, XW(o, i), YW(o, j), out);
+      for (k = 0; k < q; ++k) fn[k * N + c] = out[k];
+    }
+#undef GP
+  memcpy(o->f, fn, sizeof(double) * N * q);
+  free(G); free(SY); free(SX); free(FX); free(FY); free(fn);
+  o->step += 1;
+  o->t += o->dt;
+}
+
+/* Advance nsteps.  rings: nsteps consecutive rings (step n uses rings + n*len)
+ * or NULL when no wall is Dirichlet. */
+void or_step(Oracle* o, int nsteps, const double* rings) {
+  int n;
+  int len = 2 * (o->nx + o->ny) + 4;
+  for (n = 0; n < nsteps; ++n) step_once(o, rings ? rings + (size_t)n * len : NULL);
+}
+
+/* One step evaluated only at the listed cells (pairs i, j), without changing
+ * the state.  Every value is computed with the same helpers and argument order
+ * as the full step, from the 3x3 neighbourhood of each cell. out: [ncells][q]. */
+void or_step_cells(const Oracle* o, int ncells, const int* cells, const double* ring,
+                   double* out) {
+  const int q = o->q;
+  double zx[OR_MAXQ], zy[OR_MAXQ];
+  int n, a, b, k;
+  for (k = 0; k < q; ++k) { zx[k] = o->cx[k]; zy[k] = o->cy[k]; }
+  for (n = 0; n < ncells; ++n) {
+    int i = cells[2 * n], j = cells[2 * n + 1];
+    double g[3][3][OR_MAXQ], sy[3][OR_MAXQ], sx[3][OR_MAXQ];
+    double fw[OR_MAXQ], fe[OR_MAXQ], fs[OR_MAXQ], fnn[OR_MAXQ], ftp[OR_MAXQ];
+    for (b = -1; b <= 1; ++b)
+      for (a = -1; a <= 1; ++a) fbar_plus(o, i + a, j + b, ring, g[b + 1][a + 1]);
+    /* y-slopes at (i-1, j), (i, j), (i+1, j); x-slopes at (i, j-1), (i, j), (i, j+1) */
+    for (a = -1; a <= 1; ++a)
+      slope(o, g[0][a + 1], g[2][a + 1], YC(o, j + 1) - YC(o, j - 1), sy[a + 1]);
+    for (b = -1; b <= 1; ++b)
+      slope(o, g[b + 1][0], g[b + 1][2], XC(o, i + 1) - XC(o, i - 1), sx[b + 1]);
+    face_flux(o, zx, zy, g[1][0], g[1][1], sy[0], sy[1], XC(o, i) - XC(o, i - 1),
+              o->xf[i] - XC(o, i - 1), fw);
+    face_flux(o, zx, zy, g[1][1], g[1][2], sy[1], sy[2], XC(o, i + 1) - XC(o, i),
+              o->xf[i + 1] - XC(o, i), fe);
+    face_flux(o, zy, zx, g[0][1], g[1][1], sx[0], sx[1], YC(o, j) - YC(o, j - 1),
+              o->yf[j] - YC(o, j - 1), fs);
+    face_flux(o, zy, zx, g[1][1], g[2][1], sx[1], sx[2], YC(o, j + 1) - YC(o, j),
+              o->yf[j + 1] - YC(o, j), fnn);
+    ftilde_plus(o, (size_t)j * o->nx + i, ftp);
+    update_cell(o, 0, ftp, fw, fe, fs, fnn, XW(o, i), YW(o, j), out + (size_t)n * q);
+  }
+}
+
+/* fbar+ on every cell including the ghost ring: out [(ny+2)][(nx+2)][q] */
+void or_fbar_plus_all(const Oracle* o, const double* ring, double* out) {
+  int i, j;
+  for (j = -1; j <= o->ny; ++j)
+    for (i = -1; i <= o->nx; ++i)
+      fbar_plus(o, i, j, ring, out + ((size_t)(j + 1) * (o->nx + 2) + (i + 1)) * o->q);
+}
+
+/* GRE of eq. 4.1 (unweighted sums over cells) and the relative L2 error
+ * weighted by cell area, against a reference field phi_a [ny][nx]. */
+void or_errors(const Oracle* o, const double* phi_a, double* gre, double* rel_l2) {
+  int i, j, k;
+  size_t N = (size_t)o->nx * o->ny;
+  double num = 0.0, den = 0.0, e2 = 0.0, r2 = 0.0;
+  for (j = 0; j < o->ny; ++j)
+    for (i = 0; i < o->nx; ++i) {
+      size_t c = (size_t)j * o->nx + i;
+      double phi = 0.0, v = XW(o, i) * YW(o, j);
+      for (k = 0; k < o->q; ++k) phi += o->f[k * N + c];
+      num += fabs(phi_a[c] - phi);
+      den += fabs(phi_a[c]);
+      e2 += v * (phi - phi_a[c]) * (phi - phi_a[c]);
+      r2 += v * phi_a[c] * phi_a[c];
+    }
+  *gre = num / den;
+  *rel_l2 = sqrt(e2 / r2);
+}
+
+/* mass = sum_j phi_j |V_j| */
+double or_mass(const Oracle* o) {
+  int i, j, k;
+  size_t N = (size_t)o->nx * o->ny;
+  double m = 0.0;
+  for (j = 0; j < o->ny; ++j)
+    for (i = 0; i < o->nx; ++i) {
+      size_t c = (size_t)j * o->nx + i;
+      double phi = 0.0;
+      for (k = 0; k < o->q; ++k) phi += o->f[k * N + c];
+      m += phi * XW(o, i) * YW(o, j);
+    }
+  return m;
+}

@@ -1,0 +1,344 @@
+"""Seeded synthetic inputs for the DUGKS hot path.
+
+This module only builds inputs: meshes, coefficient sets, initial fields,
+boundary data and the closed-form solutions they are sampled from.  It holds
+none of the scheme's arithmetic, so both the HIP path and the CPU oracle can
+take their inputs from it.
+
+Workloads (sizes and constants are those of the benchmark plan; where the
+paper fixes nothing, the choice is stated here):
+
+* ``gaussian_hill``   -- linear convection-diffusion, Gaussian hill of
+  Sec. 4, Example 4.4 (closed form eq. 4.4.3), periodic square.
+* ``burgers_wave``    -- 2-D viscous Burgers with a travelling tanh front,
+  Dirichlet walls fed from the exact solution.
+* ``nonlinear_diffusion`` -- phi_t = div(D0 (1 + phi^2) grad phi) on a
+  two-sided tanh-stretched mesh (the map of eqs. 4.3.4/4.3.5 made symmetric),
+  zero-flux mirror walls, 16-mode cosine initial field.
+* ``batch``           -- many independent periodic instances with log-uniform
+  sizes, random nonlinear convection and diffusion coefficients and
+  Fourier-mode initial fields.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Callable, List, Optional
+
+import numpy as np
+
+PERIODIC, DIRICHLET, MIRROR = 0, 1, 2
+
+
+# ----------------------------------------------------------------- meshes
+
+def uniform_faces(n: int, a: float, b: float) -> np.ndarray:
+    """n+1 equally spaced cell faces on [a, b]."""
+    return a + (b - a) * np.arange(n + 1, dtype=np.float64) / n
+
+
+def tanh_faces(n: int, k: float = 2.0) -> np.ndarray:
+    """Faces of a mesh on [0, 1] clustered toward both walls.
+
+    The one-sided map x = tanh(k eta)/tanh(k) of eqs. 4.3.4/4.3.5 applied to
+    eta = 2i/n - 1 in [-1, 1] and shifted onto [0, 1]; grid points are faces.
+    """
+    eta = 2.0 * np.arange(n + 1, dtype=np.float64) / n - 1.0
+    x = 0.5 * (1.0 + np.tanh(k * eta) / math.tanh(k))
+    x[0], x[-1] = 0.0, 1.0
+    return x
+
+
+def centres(faces: np.ndarray) -> np.ndarray:
+    return 0.5 * (faces[:-1] + faces[1:])
+
+
+def ghost_centres(faces: np.ndarray, bc: int) -> np.ndarray:
+    """Centres of cells -1..n including the one-cell ghost ring.
+
+    A wall ghost mirrors the adjacent interior cell's width; a periodic ghost
+    takes the width of the wrapped cell.  This is the location at which the
+    caller samples Dirichlet data.
+    """
+    w = np.diff(faces)
+    c = centres(faces)
+    wl = w[-1] if bc == PERIODIC else w[0]
+    wr = w[0] if bc == PERIODIC else w[-1]
+    return np.concatenate([[faces[0] - 0.5 * wl], c, [faces[-1] + 0.5 * wr]])
+
+
+def ring_points(xf: np.ndarray, yf: np.ndarray, bcx: int, bcy: int):
+    """(x, y) of the 2(nx+ny)+4 ghost centres in ring order.
+
+    Order: bottom row j=-1 (i=-1..nx), top row j=ny (i=-1..nx), left column
+    i=-1 (j=0..ny-1), right column i=nx (j=0..ny-1).
+    """
+    gx, gy = ghost_centres(xf, bcx), ghost_centres(yf, bcy)
+    nx, ny = len(xf) - 1, len(yf) - 1
+    xs = np.concatenate([gx, gx, np.full(ny, gx[0]), np.full(ny, gx[-1])])
+    ys = np.concatenate([np.full(nx + 2, gy[0]), np.full(nx + 2, gy[-1]),
+                         gy[1:-1], gy[1:-1]])
+    return xs, ys
+
+
+# ---------------------------------------------------------- closed forms
+
+def gaussian_hill(x, y, t, u, K, sigma0, period=None):
+    """Gaussian hill of eq. 4.4.3 with phi0 = 2 pi sigma0^2 (peak 1 at t = 0).
+
+    sigma(t) = sigma0^2 I + 2 K t.  On a periodic box of side ``period`` the
+    infinite-domain solution is summed over the 3x3 nearest images after
+    wrapping x - u t back into the box.
+    """
+    s = np.array([[sigma0 ** 2 + 2 * K[0][0] * t, 2 * K[0][1] * t],
+                  [2 * K[1][0] * t, sigma0 ** 2 + 2 * K[1][1] * t]])
+    det = s[0, 0] * s[1, 1] - s[0, 1] * s[1, 0]
+    inv = np.array([[s[1, 1], -s[0, 1]], [-s[1, 0], s[0, 0]]]) / det
+    phi0 = 2 * math.pi * sigma0 ** 2
+    x0 = np.asarray(x, dtype=np.float64) - u[0] * t
+    y0 = np.asarray(y, dtype=np.float64) - u[1] * t
+    shifts = [0.0]
+    if period is not None:
+        x0 = (x0 + 0.5 * period) % period - 0.5 * period
+        y0 = (y0 + 0.5 * period) % period - 0.5 * period
+        shifts = [-period, 0.0, period]
+    out = np.zeros(np.broadcast(x0, y0).shape)
+    for sx in shifts:
+        for sy in shifts:
+            dx, dy = x0 + sx, y0 + sy
+            q = inv[0, 0] * dx * dx + 2 * inv[0, 1] * dx * dy + inv[1, 1] * dy * dy
+            out += np.exp(-0.5 * q)
+    return phi0 / (2 * math.pi * math.sqrt(abs(det))) * out
+
+
+def burgers_front(x, y, t, nu, s0=0.5):
+    """Travelling front of phi_t + d_x(phi^2/2) + d_y(phi^2/2) = nu lap(phi).
+
+    phi = 1/2 - 1/2 tanh((x + y - t - s0) / (4 nu)); substituting
+    g(xi), xi = x + y - t - s0, gives -g' + 2 g g' = 2 nu g'', which this g
+    satisfies with zero integration constant.
+    """
+    return 0.5 - 0.5 * np.tanh((np.asarray(x) + np.asarray(y) - t - s0) / (4.0 * nu))
+
+
+def cosine_decay(x, y, t, alpha, mean=1.0, amp=0.5, period=1.0, neumann=False):
+    """Pure diffusion (B = 0, D = phi I) of one cosine mode.
+
+    Periodic: phi = mean + amp cos(2 pi x / L) cos(2 pi y / L) exp(-8 pi^2 alpha t / L^2).
+    Neumann on [0, L]^2: cos(pi x / L) cos(pi y / L) exp(-2 pi^2 alpha t / L^2).
+    """
+    kk = (math.pi if neumann else 2 * math.pi) / period
+    return mean + amp * np.cos(kk * np.asarray(x)) * np.cos(kk * np.asarray(y)) * \
+        math.exp(-2 * kk * kk * alpha * t)
+
+
+# ------------------------------------------------------------- problems
+
+@dataclasses.dataclass
+class Problem:
+    """One NCDE instance: mesh, lattice, constants, coefficients, initial field."""
+    name: str
+    xf: np.ndarray
+    yf: np.ndarray
+    q: int = 9
+    c: float = 1.0
+    cfl: float = 0.5
+    alpha: float = 1e-3
+    bcx: int = PERIODIC
+    bcy: int = PERIODIC
+    bx: tuple = (0.0,)
+    by: tuple = (0.0,)
+    dxx: tuple = (0.0, 1.0)
+    dxy: tuple = (0.0, 0.0)
+    dyy: tuple = (0.0, 1.0)
+    phi0: Optional[np.ndarray] = None        # [ny][nx], point values at centres
+    steps: int = 1
+    exact: Optional[Callable] = None         # (x, y, t) -> phi, or None
+    seed: Optional[int] = None
+
+    @property
+    def nx(self) -> int:
+        return len(self.xf) - 1
+
+    @property
+    def ny(self) -> int:
+        return len(self.yf) - 1
+
+    @property
+    def cells(self) -> int:
+        return self.nx * self.ny
+
+    def mesh(self):
+        """Cell-centre coordinates as [ny][nx] arrays."""
+        return np.meshgrid(centres(self.xf), centres(self.yf))
+
+    def dt(self) -> float:
+        """Time step for the workload's own bookkeeping (end time, ring times).
+
+        Mirrors the scheme's rule dt = cfl * min width / c so that the caller
+        can sample boundary data at t_n; the solver computes its own dt.
+        """
+        return self.cfl * min(np.diff(self.xf).min(), np.diff(self.yf).min()) / self.c
+
+    def rings(self, nsteps: int, start_step: int = 0) -> Optional[np.ndarray]:
+        """Dirichlet data at ghost centres for steps start..start+nsteps-1."""
+        if DIRICHLET not in (self.bcx, self.bcy):
+            return None
+        xs, ys = ring_points(self.xf, self.yf, self.bcx, self.bcy)
+        dt = self.dt()
+        return np.stack([self.exact(xs, ys, (start_step + n) * dt)
+                         for n in range(nsteps)]).astype(np.float64)
+
+
+def _poly_pad(p, n=5):
+    p = list(p) + [0.0] * (n - len(p))
+    return tuple(float(v) for v in p[:n])
+
+
+def gaussian_hill_problem(n=128, u=(0.1, 0.1), D=1e-3, sigma0=0.05, steps=500, cfl=0.5,
+                          c=1.0, K=None, q=9, name="gaussian_hill") -> Problem:
+    """Linear CDE on [-1, 1]^2, periodic: B = u phi, D = (K / alpha) phi."""
+    K = K if K is not None else [[D, 0.0], [0.0, D]]
+    alpha = D
+    xf = uniform_faces(n, -1.0, 1.0)
+    p = Problem(name=name, xf=xf, yf=xf.copy(), q=q, c=c, cfl=cfl, alpha=alpha,
+                bx=(0.0, u[0]), by=(0.0, u[1]),
+                dxx=(0.0, K[0][0] / alpha), dxy=(0.0, K[0][1] / alpha),
+                dyy=(0.0, K[1][1] / alpha), steps=steps)
+    p.exact = lambda x, y, t: gaussian_hill(x, y, t, u, K, sigma0, period=2.0)
+    X, Y = p.mesh()
+    p.phi0 = p.exact(X, Y, 0.0)
+    return p
+
+
+def burgers_problem(n=512, nu=0.01, c=4.0, cfl=0.5, steps=2000, s0=0.5,
+                    name="burgers_wave") -> Problem:
+    """phi_t + div((1,1) phi^2/2) = nu lap(phi) on [0,1]^2, Dirichlet from the front."""
+    xf = uniform_faces(n, 0.0, 1.0)
+    p = Problem(name=name, xf=xf, yf=xf.copy(), c=c, cfl=cfl, alpha=nu,
+                bcx=DIRICHLET, bcy=DIRICHLET, bx=(0.0, 0.0, 0.5), by=(0.0, 0.0, 0.5),
+                steps=steps)
+    p.exact = lambda x, y, t: burgers_front(x, y, t, nu, s0)
+    X, Y = p.mesh()
+    p.phi0 = p.exact(X, Y, 0.0)
+    return p
+
+
+def cosine_field(X, Y, seed, modes=4, total=0.5, wavenumber=math.pi, phases=False):
+    """Sum of modes x modes products of cosines with seeded amplitudes.
+
+    a_mn ~ U(-1, 1), rescaled so that sum |a_mn| = total; with ``phases`` each
+    factor gets a seeded phase (periodic fields), otherwise the field is
+    Neumann-compatible on [0, 1]^2.
+    """
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(-1.0, 1.0, size=(modes, modes))
+    a *= total / np.abs(a).sum()
+    th = rng.uniform(0, 2 * math.pi, size=(modes, modes)) if phases else np.zeros((modes, modes))
+    ps = rng.uniform(0, 2 * math.pi, size=(modes, modes)) if phases else np.zeros((modes, modes))
+    out = np.zeros_like(X)
+    for m in range(modes):
+        for k in range(modes):
+            out += a[m, k] * np.cos(wavenumber * m * X + th[m, k]) * \
+                np.cos(wavenumber * k * Y + ps[m, k])
+    return out
+
+
+def nonlinear_diffusion_problem(n=1024, D0=0.01, k=2.0, c=1.0, cfl=0.5, steps=1000, seed=3,
+                                name="nonlinear_diffusion") -> Problem:
+    """phi_t = div(D0 (1 + phi^2) grad phi): B = 0, D = (phi + phi^3/3) I, mirror walls."""
+    xf = tanh_faces(n, k)
+    p = Problem(name=name, xf=xf, yf=xf.copy(), c=c, cfl=cfl, alpha=D0, bcx=MIRROR,
+                bcy=MIRROR, dxx=(0.0, 1.0, 0.0, 1.0 / 3.0), dyy=(0.0, 1.0, 0.0, 1.0 / 3.0),
+                dxy=(0.0,), steps=steps, seed=seed)
+    X, Y = p.mesh()
+    p.phi0 = cosine_field(X, Y, seed)
+    return p
+
+
+def neumann_companion_problem(n=64, alpha=0.01, k=2.0, c=1.0, cfl=0.5, steps=100,
+                              name="neumann_cosine") -> Problem:
+    """Pure diffusion of one Neumann cosine mode on the stretched mesh, mirror walls."""
+    xf = tanh_faces(n, k)
+    p = Problem(name=name, xf=xf, yf=xf.copy(), c=c, cfl=cfl, alpha=alpha, bcx=MIRROR,
+                bcy=MIRROR, steps=steps)
+    p.exact = lambda x, y, t: cosine_decay(x, y, t, alpha, 1.0, 0.5, 1.0, neumann=True)
+    X, Y = p.mesh()
+    p.phi0 = p.exact(X, Y, 0.0)
+    return p
+
+
+def batch_problems(count=256, seed=5, nmin=64, nmax=1024, c=2.0, cfl=0.5, steps=500,
+                   max_cells=None) -> List[Problem]:
+    """Independent periodic instances on [0, 1]^2.
+
+    N = round(exp U(ln nmin, ln nmax)); B = a (1, 1) phi^2 / 2 with a ~ U(0, 1);
+    D = phi I with alpha ~ logU(1e-4, 1e-2); phi0 = seeded 16-mode Fourier field
+    with random phases, sum |a_mn| = 0.5.  Instance k draws its field from seed
+    seed*1000 + k.
+    """
+    rng = np.random.default_rng(seed)
+    ns = np.rint(np.exp(rng.uniform(math.log(nmin), math.log(nmax), size=count))).astype(int)
+    avals = rng.uniform(0.0, 1.0, size=count)
+    alphas = np.exp(rng.uniform(math.log(1e-4), math.log(1e-2), size=count))
+    out = []
+    for k in range(count):
+        n = int(ns[k])
+        if max_cells is not None:
+            n = min(n, int(math.isqrt(max_cells)))
+        xf = uniform_faces(n, 0.0, 1.0)
+        p = Problem(name=f"batch{k}", xf=xf, yf=xf.copy(), c=c, cfl=cfl,
+                    alpha=float(alphas[k]), bx=(0.0, 0.0, 0.5 * avals[k]),
+                    by=(0.0, 0.0, 0.5 * avals[k]), steps=steps, seed=seed * 1000 + k)
+        X, Y = p.mesh()
+        p.phi0 = cosine_field(X, Y, seed * 1000 + k, wavenumber=2 * math.pi, phases=True)
+        out.append(p)
+    return out
+
+
+def random_problem(seed: int, nx: int, ny: int, q: int = 9, bcx: int = PERIODIC,
+                   bcy: int = PERIODIC, stretched: bool = False, bdeg: int = 2,
+                   ddeg: int = 1) -> Problem:
+    """A small random instance for property tests: random polynomial B and D.
+
+    D's coefficients keep the diffusion tensor positive definite for |phi| <= 1;
+    the initial field is a smooth random cosine field of amplitude <= 0.5.
+    The Dirichlet data (if any) is a smooth field that moves with time.
+    """
+    rng = np.random.default_rng(seed)
+    xf = tanh_faces(nx, 1.5) if stretched else uniform_faces(nx, 0.0, 1.0)
+    yf = tanh_faces(ny, 1.5) if stretched else uniform_faces(ny, 0.0, 1.0)
+    bx = [0.0] + list(rng.uniform(-0.3, 0.3, size=bdeg))
+    by = [0.0] + list(rng.uniform(-0.3, 0.3, size=bdeg))
+    if q == 5:
+        dxx, dxy, dyy = (0.0, 1.0), (0.0,), (0.0, 1.0)
+    else:
+        d1 = rng.uniform(0.5, 1.5, size=2)
+        dxx = [0.0, d1[0]] + list(rng.uniform(0.0, 0.2, size=max(ddeg - 1, 0)))
+        dyy = [0.0, d1[1]] + list(rng.uniform(0.0, 0.2, size=max(ddeg - 1, 0)))
+        dxy = [0.0, rng.uniform(-0.3, 0.3)]
+    p = Problem(name=f"random{seed}", xf=xf, yf=yf, q=q, c=float(rng.uniform(1.0, 3.0)),
+                cfl=float(rng.uniform(0.3, 0.8)), alpha=float(np.exp(rng.uniform(-7, -3))),
+                bcx=bcx, bcy=bcy, bx=tuple(bx), by=tuple(by), dxx=tuple(dxx), dxy=tuple(dxy),
+                dyy=tuple(dyy), steps=3, seed=seed)
+    X, Y = p.mesh()
+    wn = 2 * math.pi if bcx == PERIODIC and bcy == PERIODIC else math.pi
+    p.phi0 = 0.5 + cosine_field(X, Y, seed + 17, modes=3, total=0.4, wavenumber=wn,
+                                phases=(bcx == PERIODIC and bcy == PERIODIC))
+    amp = float(rng.uniform(0.1, 0.3))
+    p.exact = lambda x, y, t: 0.5 + amp * np.sin(2.0 * np.asarray(x) + 3.0 * np.asarray(y)
+                                                 + 5.0 * t)
+    return p
+
+
+def workload(name: str, **kw):
+    """The named benchmark workloads."""
+    table = {
+        "gaussian_hill_128": lambda: gaussian_hill_problem(128, **kw),
+        "burgers_512": lambda: burgers_problem(512, **kw),
+        "nonlinear_diffusion_1024": lambda: nonlinear_diffusion_problem(1024, **kw),
+        "gaussian_hill_4096": lambda: gaussian_hill_problem(
+            4096, u=(0.05, 0.02), D=1e-4, steps=1000, name="gaussian_hill_4096", **kw),
+        "batch256": lambda: batch_problems(**kw),
+    }
+    return table[name]()
