@@ -1,0 +1,292 @@
+/*
+ * dugks.h -- C ABI of libdugks: the discrete unified gas kinetic scheme
+ * (DUGKS) step for the nonlinear convection-diffusion equation
+ *
+ *     d_t phi + div B(phi) = div(alpha div D(phi))            (eq. 2.1, F = 0)
+ *
+ * on 2-D Cartesian meshes (uniform or stretched) with the D2Q9 lattice of
+ * eq. 2.5 or the D2Q5 lattice of Remark 3, for MI355X (gfx950).
+ *
+ * Paper: J. Shang, Z. Chai, H. Wang, B. Shi, "Discrete unified gas kinetic
+ * scheme for nonlinear convection-diffusion equations", arXiv:1906.11036.
+ *
+ * ---------------------------------------------------------------- conventions
+ * - Every call returns int: DUGKS_OK (0) or a negative DUGKS_E_* code; the
+ *   message of the last failure is dugks_last_error(handle).  No C++
+ *   exception crosses this boundary.
+ * - Ownership: the caller owns all device memory.  The library asks for one
+ *   workspace of dugks_workspace_bytes() bytes (device, 256-byte aligned) and
+ *   keeps every device array of the instance in it; the library owns only
+ *   its opaque host handle.  Host arrays passed in are copied before the call
+ *   returns.  The library never frees caller memory.
+ * - Streams: work is enqueued on the hipStream_t given to dugks_bind (NULL =
+ *   the default stream).  Stepping is asynchronous; dugks_get_phi,
+ *   dugks_get_f, dugks_get_diag, dugks_error_norms and dugks_checkpoint
+ *   synchronise the stream.  A failure inside device work (a non-finite
+ *   value, FP16 overflow) is reported by the next synchronising call.
+ * - Arrays of cell values are row-major [ny][nx] (x fastest); distributions
+ *   are [q][ny][nx].  Direction i has velocity c*(cx_i, cy_i) with
+ *   (cx, cy) = (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1)
+ *   (eq. 2.5); D2Q5 uses the first five.
+ *
+ * ------------------------------------------------------------- the method
+ * Constants (Sec. 2, Sec. 3): c_s^2 = c^2/3, lambda = alpha / c_s^2,
+ * dt = cfl * min(cell width in x or y) / c, h = dt/2.
+ * Equilibrium (eq. 2.3):
+ *   E_i = w_i [phi + c_i.B/c_s^2 + (c_s^2 D + C - c_s^2 phi I):(c_i c_i - c_s^2 I)/(2 c_s^4)]
+ * with C(phi) = integral_0^phi B'(s) B'(s)^T ds (Remark 3); D2Q5 uses the
+ * linear equilibrium E_i = w_i (phi + c_i.B/c_s^2) of Remark 3, which needs
+ * D = phi I.  The library tracks f~ (eq. 2.11); one step is the summary at
+ * the end of Sec. 2:
+ *   fbar+ = (2L-h)/(2L+dt) f~ + 3h/(2L+dt) E          (eq. 2.21)
+ *   f~+   = 4/3 fbar+ - 1/3 f~                         (eq. 2.23)
+ *   fbar at each face centre from the two adjacent cells (eq. 2.20): normal
+ *     derivative (R - L)/(x_R - x_L), value L + (x_face - x_L) * derivative;
+ *     tangential derivative = mean of the two cells' central differences;
+ *     fbar_b = value - h c_i.grad (eq. 2.19 in the form of eq. 2.26)
+ *   phi_b = sum_i fbar_b,i ; f_b = 2L/(2L+h) fbar_b + h/(2L+h) E(phi_b)  (eq. 2.22)
+ *   f~(t+dt) = f~+ - dt [c_x (f_E - f_W)/dx + c_y (f_N - f_S)/dy]   (eqs. 2.9, 2.24)
+ * Boundaries use a one-cell ghost ring (corners included):
+ *   PERIODIC  wrapped cell;
+ *   DIRICHLET non-equilibrium extrapolation: fbar+_g = E(phi_g) + fbar+_a - E(phi_a),
+ *             a = adjacent interior cell (diagonal one for corners), phi_g
+ *             given by the caller at the ghost centre for each step;
+ *   MIRROR    zero-flux specular wall: fbar+_g,i = fbar+_a,m(i), m reverses
+ *             the wall-normal velocity component.
+ * Wall ghosts have the width of the adjacent interior cell; periodic ghosts
+ * the width of the wrapped cell.  A DIRICHLET axis may not meet a MIRROR axis.
+ * Initialisation (Sec. 4): f~ = E(phi).
+ */
+#ifndef DUGKS_H
+#define DUGKS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DUGKS_ABI_VERSION 1
+#define DUGKS_MAX_DEG 4        /* B and D: polynomials in phi of degree <= 4 */
+
+/* return codes */
+#define DUGKS_OK 0
+#define DUGKS_E_ARG (-1)         /* invalid argument */
+#define DUGKS_E_STATE (-2)       /* call not valid in the handle's state */
+#define DUGKS_E_HIP (-3)         /* a HIP runtime call failed */
+#define DUGKS_E_UNSTABLE (-4)    /* non-finite value or FP16 overflow seen on the device */
+#define DUGKS_E_UNSUPPORTED (-5) /* valid request outside what this build implements */
+#define DUGKS_E_NOMEM (-6)       /* workspace too small */
+#define DUGKS_E_FORMAT (-7)      /* checkpoint rejected */
+
+/* storage of f~ on the device */
+#define DUGKS_F64 0     /* f~ in binary64, binary64 arithmetic */
+#define DUGKS_F32 1     /* f~ in binary32, binary32 arithmetic, binary64 moment sums */
+#define DUGKS_F16NEQ 2  /* phi in binary32 + g_i = s (f~_i - E_i(phi)) in binary16 for
+                           i >= 1 (g_0 = -sum g_i); s a power of two chosen each step
+                           from the previous step's max |f~ - E|; binary32 arithmetic */
+#define DUGKS_BF16NEQ 3 /* as DUGKS_F16NEQ with bfloat16 */
+
+/* boundary kinds (per side: west, east, south, north) */
+#define DUGKS_BC_PERIODIC 0
+#define DUGKS_BC_DIRICHLET 1
+#define DUGKS_BC_MIRROR 2
+
+/* kernels */
+#define DUGKS_KERNEL_FUSED 0 /* one fused kernel per step, column strips marched in y */
+#define DUGKS_KERNEL_PLAIN 1 /* one cell per thread, neighbours read from global memory;
+                                binary64 storage only */
+
+/* launch schedules */
+#define DUGKS_SCHED_GRID 0       /* one wave per work item */
+#define DUGKS_SCHED_PERSISTENT 1 /* a fixed grid of waves striding over the work list */
+
+/* diagnostic flags */
+#define DUGKS_FLAG_NONFINITE 1
+#define DUGKS_FLAG_OVERFLOW 2
+
+typedef struct dugks_params {
+  int abi_version; /* must be DUGKS_ABI_VERSION */
+  int storage;     /* DUGKS_F64 / F32 / F16NEQ / BF16NEQ */
+  int bc[4];       /* west, east, south, north; periodic sides come in pairs and
+                      both walls of an axis are of one kind */
+  int kernel;      /* DUGKS_KERNEL_FUSED or DUGKS_KERNEL_PLAIN */
+  double c;        /* lattice speed, > 0 */
+  double cfl;      /* CFL number, 0 < cfl < 1 (Sec. 2, Sec. 4) */
+  double alpha;    /* diffusion coefficient of eq. 2.1, > 0 */
+} dugks_params;
+
+typedef struct dugks_info {
+  double dt, h, lambda, cs2;
+  double a1, b1, a2, b2, a3, b3; /* eqs. 2.21, 2.13, 2.22 */
+  int nx, ny, q, storage, pitch;
+  int eq_degree;          /* degree of E_i(phi) as a polynomial in phi */
+  int rows_per_wave;      /* current launch configuration */
+  int waves_per_block;
+  int schedule;
+  int xcd_remap;
+  long long work_items;
+  size_t state_bytes;     /* bytes of one f~ buffer (read once and written once per step) */
+} dugks_info;
+
+typedef struct dugks_diag {
+  long long step; /* steps taken since dugks_set_phi / dugks_set_f */
+  double t;       /* step * dt */
+  double dt;
+  double mass;    /* sum_j phi_j |V_j| */
+  double max_neq; /* max |f~ - E(phi)| of the last step's output (16-bit storage), else 0 */
+  double scale;   /* power-of-two scale of the stored state (16-bit storage), else 1 */
+  int flags;      /* DUGKS_FLAG_* */
+} dugks_diag;
+
+typedef struct dugks_ctx dugks_ctx;
+typedef struct dugks_batch dugks_batch;
+
+/* Create an instance on nx x ny cells with faces xf[0..nx], yf[0..ny]
+ * (strictly increasing, host, copied) and q in {9, 5}.  No device work.
+ * B = D = 0 until set.  Errors: E_ARG (sizes < 1, non-monotone faces, c,
+ * cfl or alpha out of range, bad abi_version), E_UNSUPPORTED (q, storage,
+ * kernel or boundary combination not built).  On an error other than a NULL
+ * out, *out still receives a handle whose dugks_last_error() names the
+ * problem; destroy it with dugks_destroy(). */
+int dugks_create(dugks_ctx** out, int nx, int ny, const double* xf, const double* yf, int q,
+                 const dugks_params* p);
+
+/* Device workspace needed by the instance, in bytes. */
+size_t dugks_workspace_bytes(const dugks_ctx* ctx);
+
+/* Attach the caller's workspace (device pointer, >= dugks_workspace_bytes,
+ * 256-byte aligned) and stream (hipStream_t as void*).  Uploads the mesh and
+ * coefficient tables.  May be called again to move the instance; the state
+ * is then undefined until set.  Errors: E_ARG, E_NOMEM, E_HIP. */
+int dugks_bind(dugks_ctx* ctx, void* dev_workspace, size_t bytes, void* hip_stream);
+
+/* B(phi) = sum_{k<=deg} (bx[k], by[k]) phi^k (host arrays of deg+1 values).
+ * C = int_0^phi B'B'^T is formed by the library (Remark 3).  deg <= 4.
+ * Call before dugks_set_phi.  Errors: E_ARG. */
+int dugks_set_B(dugks_ctx* ctx, int deg, const double* bx, const double* by);
+
+/* D(phi) = sum_{k<=deg} [[dxx[k], dxy[k]], [dxy[k], dyy[k]]] phi^k, deg <= 4.
+ * With q = 5 only D = phi I is accepted (Remark 3).  Errors: E_ARG, E_UNSUPPORTED. */
+int dugks_set_D(dugks_ctx* ctx, int deg, const double* dxx, const double* dxy, const double* dyy);
+
+/* Source term F of eq. 2.1.  Only F_dev == NULL (F = 0) is built; anything
+ * else returns E_UNSUPPORTED. */
+int dugks_set_source(dugks_ctx* ctx, const void* F_dev);
+
+/* Dirichlet data: ring_dev (device, caller-owned, must outlive the steps)
+ * holds nsteps rings of 2(nx+ny)+4 binary64 values, phi at the ghost
+ * centres at t_n = n dt for step n = 0..nsteps-1 counted from the last
+ * dugks_set_phi / dugks_set_f.  Ring order: row j = -1 (i = -1..nx), row
+ * j = ny (i = -1..nx), column i = -1 (j = 0..ny-1), column i = nx
+ * (j = 0..ny-1).  Stepping past nsteps returns E_STATE.  Errors: E_ARG. */
+int dugks_set_dirichlet(dugks_ctx* ctx, const double* ring_dev, int nsteps);
+
+/* Initialise f~ = E(phi) (Sec. 4) from phi [ny][nx] (binary64, host if
+ * on_device == 0, else device) and reset step and time to 0.  Errors: E_STATE
+ * (not bound), E_HIP. */
+int dugks_set_phi(dugks_ctx* ctx, const double* phi, int on_device);
+
+/* Set f~ directly from [q][ny][nx] binary64 values (encoded to the storage
+ * format) and reset step and time to 0. */
+int dugks_set_f(dugks_ctx* ctx, const double* f, int on_device);
+
+/* Advance nsteps >= 0 steps, asynchronously on the bound stream.  Errors:
+ * E_STATE (not initialised, Dirichlet data exhausted), E_HIP. */
+int dugks_step(dugks_ctx* ctx, int nsteps);
+
+/* phi = sum_i f~_i (Sec. 2) accumulated in binary64, into out [ny][nx]
+ * (host if on_device == 0, else device).  Synchronises. */
+int dugks_get_phi(dugks_ctx* ctx, double* out, int on_device);
+
+/* f~ decoded to binary64 [q][ny][nx].  Synchronises. */
+int dugks_get_f(dugks_ctx* ctx, double* out, int on_device);
+
+/* Step count, time, mass and flags; runs the device reductions and
+ * synchronises.  Returns E_UNSTABLE (with *out filled) if a flag is set. */
+int dugks_get_diag(dugks_ctx* ctx, dugks_diag* out);
+
+/* GRE of eq. 4.1 (unweighted sums over cells) and the area-weighted relative
+ * L2 error of phi against ref_dev [ny][nx] (device, binary64).  Binary64
+ * reductions in a fixed order.  Synchronises. */
+int dugks_error_norms(dugks_ctx* ctx, const double* ref_dev, double* rel_l2, double* gre);
+
+/* Serialise the state (header with ABI version, sizes, storage, step, time,
+ * scale slots and a hash of mesh, parameters and coefficients, then the
+ * active f~ buffer and a checksum) into host_buf.  With host_buf == NULL only
+ * *len is set to the size needed.  Synchronises.  Errors: E_ARG (buffer too
+ * small), E_STATE. */
+int dugks_checkpoint(dugks_ctx* ctx, void* host_buf, size_t* len);
+
+/* Restore a checkpoint taken from an instance with the same mesh,
+ * parameters and coefficients.  Errors: E_FORMAT (bad magic, version, size,
+ * hash or checksum), E_STATE (not bound). */
+int dugks_restore(dugks_ctx* ctx, const void* host_buf, size_t len);
+
+/* Launch configuration: rows_per_wave (rows each wave marches, 1..4096),
+ * waves_per_block (1, 2, 4 or 8), schedule (DUGKS_SCHED_*), xcd_remap (0/1:
+ * map consecutive work to one XCD's L2).  Results do not depend on it.
+ * Errors: E_ARG. */
+int dugks_set_launch(dugks_ctx* ctx, int rows_per_wave, int waves_per_block, int schedule,
+                     int xcd_remap);
+
+/* Time trial_steps steps for each candidate launch configuration and keep the
+ * fastest.  Writes only the inactive buffer: the state is unchanged.
+ * Synchronises.  Errors: E_STATE, E_HIP. */
+int dugks_autotune(dugks_ctx* ctx, int trial_steps);
+
+/* Constants and the launch configuration in use. */
+int dugks_get_info(const dugks_ctx* ctx, dugks_info* out);
+
+/* ------------------------------------------------------------ batches
+ * Many independent instances advanced by one launch per step (one work list
+ * over all instances' column strips).  Every instance uses the batch's
+ * storage and the fused kernel; Dirichlet walls are not built for batches. */
+typedef struct dugks_instance_desc {
+  int nx, ny, q;
+  const double* xf; /* host, nx+1 faces, copied */
+  const double* yf; /* host, ny+1 faces, copied */
+  dugks_params p;   /* storage and kernel fields are ignored */
+  int b_deg;
+  double bx[DUGKS_MAX_DEG + 1], by[DUGKS_MAX_DEG + 1];
+  int d_deg;
+  double dxx[DUGKS_MAX_DEG + 1], dxy[DUGKS_MAX_DEG + 1], dyy[DUGKS_MAX_DEG + 1];
+} dugks_instance_desc;
+
+/* Create a batch of n >= 1 instances (desc host array, copied).  Errors as
+ * dugks_create, per instance. */
+int dugks_batch_create(dugks_batch** out, int n, const dugks_instance_desc* desc, int storage);
+size_t dugks_batch_workspace_bytes(const dugks_batch* b);
+int dugks_batch_bind(dugks_batch* b, void* dev_workspace, size_t bytes, void* hip_stream);
+/* f~ = E(phi) for instance i (phi [ny_i][nx_i]); resets the batch clock. */
+int dugks_batch_set_phi(dugks_batch* b, int i, const double* phi, int on_device);
+int dugks_batch_autotune(dugks_batch* b, int trial_steps);
+int dugks_batch_set_launch(dugks_batch* b, int rows_per_wave, int waves_per_block, int schedule,
+                           int xcd_remap);
+/* Advance every instance nsteps steps (each with its own dt); the steps are
+ * replayed from a captured hipGraph when nsteps is large enough. */
+int dugks_batch_step(dugks_batch* b, int nsteps);
+int dugks_batch_get_phi(dugks_batch* b, int i, double* out, int on_device);
+int dugks_batch_get_info(const dugks_batch* b, int i, dugks_info* out);
+/* Total cells of all instances and bytes of one f~ buffer over all instances. */
+int dugks_batch_totals(const dugks_batch* b, long long* cells, size_t* state_bytes);
+/* Advance every instance nsteps steps like dugks_batch_step, with hipEvents
+ * recorded on the bound stream before the first and after the last launch;
+ * synchronises and returns the elapsed time in *ms_total. */
+int dugks_batch_time_steps(dugks_batch* b, int nsteps, float* ms_total);
+
+/* Single-instance counterpart of dugks_batch_time_steps. */
+int dugks_time_steps(dugks_ctx* ctx, int nsteps, float* ms_total);
+
+/* Message of the last failure on this handle (dugks_ctx* or dugks_batch*),
+ * owned by the handle; "" if none. */
+const char* dugks_last_error(const void* handle);
+
+/* Free a dugks_ctx* or dugks_batch* (not the caller's workspace). */
+void dugks_destroy(void* handle);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DUGKS_H */

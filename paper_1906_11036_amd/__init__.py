@@ -1,0 +1,302 @@
+"""DUGKS for nonlinear convection-diffusion equations on MI355X.
+
+Thin binding over libdugks.so (include/dugks.h): argument marshalling only.
+PyTorch provides the device workspace and the stream; every step of the
+method runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _lib as L
+from ._lib import (BC_DIRICHLET, BC_MIRROR, BC_PERIODIC, BF16NEQ, F16NEQ, F32, F64,  # noqa: F401
+                   KERNEL_FUSED, KERNEL_PLAIN, SCHED_GRID, SCHED_PERSISTENT, STORAGE, DugksError)
+
+__all__ = ["Solver", "Batch", "DugksError", "F64", "F32", "F16NEQ", "BF16NEQ"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(device):
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _poly(v, n=None):
+    v = [float(x) for x in v]
+    if n is not None:
+        v = v + [0.0] * (n - len(v))
+    return v
+
+
+def _params(problem, storage, kernel):
+    p = L.Params()
+    p.abi_version = L.ABI_VERSION
+    p.storage = storage
+    p.bc[0] = p.bc[1] = int(problem.bcx)
+    p.bc[2] = p.bc[3] = int(problem.bcy)
+    p.kernel = kernel
+    p.c, p.cfl, p.alpha = float(problem.c), float(problem.cfl), float(problem.alpha)
+    return p
+
+
+def _storage_code(storage):
+    return L.STORAGE[storage] if isinstance(storage, str) else int(storage)
+
+
+class Solver:
+    """One instance (``dugks_ctx``).
+
+    ``problem`` is any object with the fields of ``workloads.Problem`` (mesh
+    faces, q, c, cfl, alpha, bcx, bcy, B and D coefficients).
+    """
+
+    def __init__(self, problem, storage="f64", kernel=KERNEL_FUSED, device="cuda:0",
+                 launch: Optional[Sequence[int]] = None):
+        torch = _torch()
+        self.lib = L.lib()
+        self.device = torch.device(device)
+        self.problem = problem
+        self.storage = _storage_code(storage)
+        self.xf = np.ascontiguousarray(problem.xf, dtype=np.float64)
+        self.yf = np.ascontiguousarray(problem.yf, dtype=np.float64)
+        self.nx, self.ny, self.q = len(self.xf) - 1, len(self.yf) - 1, int(problem.q)
+        h = C.c_void_p()
+        p = _params(problem, self.storage, kernel)
+        rc = self.lib.dugks_create(C.byref(h), self.nx, self.ny, _dptr(self.xf), _dptr(self.yf),
+                                   self.q, C.byref(p))
+        self.h = h
+        L.check(rc, h, "dugks_create")
+        self.set_B(problem.bx, problem.by)
+        self.set_D(problem.dxx, problem.dxy, problem.dyy)
+        if launch is not None:
+            self.set_launch(*launch)
+        nbytes = self.lib.dugks_workspace_bytes(self.h)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            base = self.workspace.data_ptr()
+            self._ws_ptr = (base + 255) & ~255
+            L.check(self.lib.dugks_bind(self.h, C.c_void_p(self._ws_ptr), nbytes,
+                                        _stream_handle(self.device)), self.h, "dugks_bind")
+        self._ring = None
+
+    # -- coefficients
+    def set_B(self, bx, by):
+        deg = max(len(bx), len(by)) - 1
+        a, b = np.array(_poly(bx, deg + 1)), np.array(_poly(by, deg + 1))
+        L.check(self.lib.dugks_set_B(self.h, deg, _dptr(a), _dptr(b)), self.h, "dugks_set_B")
+
+    def set_D(self, dxx, dxy, dyy):
+        deg = max(len(dxx), len(dxy), len(dyy)) - 1
+        arrs = [np.array(_poly(v, deg + 1)) for v in (dxx, dxy, dyy)]
+        L.check(self.lib.dugks_set_D(self.h, deg, *[_dptr(a) for a in arrs]), self.h, "dugks_set_D")
+
+    def set_dirichlet(self, rings):
+        """rings: [nsteps][2(nx+ny)+4] binary64 (numpy or device tensor); kept alive here."""
+        torch = _torch()
+        t = torch.as_tensor(np.asarray(rings, dtype=np.float64) if not torch.is_tensor(rings)
+                            else rings, dtype=torch.float64, device=self.device).contiguous()
+        self._ring = t
+        L.check(self.lib.dugks_set_dirichlet(self.h, C.c_void_p(t.data_ptr()), int(t.shape[0])),
+                self.h, "dugks_set_dirichlet")
+
+    # -- state
+    def _dev64(self, a, shape):
+        torch = _torch()
+        if torch.is_tensor(a):
+            t = a.to(device=self.device, dtype=torch.float64).contiguous()
+        else:
+            t = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(self.device)
+        return t.reshape(shape)
+
+    def set_phi(self, phi):
+        t = self._dev64(phi, (self.ny, self.nx))
+        L.check(self.lib.dugks_set_phi(self.h, C.c_void_p(t.data_ptr()), 1), self.h, "dugks_set_phi")
+
+    def set_f(self, f):
+        t = self._dev64(f, (self.q, self.ny, self.nx))
+        L.check(self.lib.dugks_set_f(self.h, C.c_void_p(t.data_ptr()), 1), self.h, "dugks_set_f")
+
+    def step(self, nsteps=1):
+        L.check(self.lib.dugks_step(self.h, int(nsteps)), self.h, "dugks_step")
+
+    def time_steps(self, nsteps):
+        ms = C.c_float()
+        L.check(self.lib.dugks_time_steps(self.h, int(nsteps), C.byref(ms)), self.h, "dugks_time_steps")
+        return ms.value
+
+    def phi_tensor(self):
+        torch = _torch()
+        out = torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device)
+        L.check(self.lib.dugks_get_phi(self.h, C.c_void_p(out.data_ptr()), 1), self.h, "dugks_get_phi")
+        return out
+
+    def get_phi(self) -> np.ndarray:
+        return self.phi_tensor().cpu().numpy()
+
+    def get_f(self) -> np.ndarray:
+        torch = _torch()
+        out = torch.empty((self.q, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        L.check(self.lib.dugks_get_f(self.h, C.c_void_p(out.data_ptr()), 1), self.h, "dugks_get_f")
+        return out.cpu().numpy()
+
+    def diag(self, check=True) -> dict:
+        d = L.Diag()
+        rc = self.lib.dugks_get_diag(self.h, C.byref(d))
+        if check:
+            L.check(rc, self.h, "dugks_get_diag")
+        return {"step": d.step, "t": d.t, "dt": d.dt, "mass": d.mass, "max_neq": d.max_neq,
+                "scale": d.scale, "flags": d.flags, "rc": rc}
+
+    def error_norms(self, ref):
+        t = self._dev64(ref, (self.ny, self.nx))
+        l2, gre = C.c_double(), C.c_double()
+        L.check(self.lib.dugks_error_norms(self.h, C.c_void_p(t.data_ptr()), C.byref(l2), C.byref(gre)),
+                self.h, "dugks_error_norms")
+        return gre.value, l2.value
+
+    def checkpoint(self) -> bytes:
+        n = C.c_size_t()
+        L.check(self.lib.dugks_checkpoint(self.h, None, C.byref(n)), self.h, "dugks_checkpoint")
+        buf = (C.c_char * n.value)()
+        L.check(self.lib.dugks_checkpoint(self.h, buf, C.byref(n)), self.h, "dugks_checkpoint")
+        return bytes(buf[:n.value])
+
+    def restore(self, blob: bytes):
+        buf = (C.c_char * len(blob)).from_buffer_copy(blob)
+        L.check(self.lib.dugks_restore(self.h, buf, len(blob)), self.h, "dugks_restore")
+
+    def set_launch(self, rows_per_wave=64, waves_per_block=4, schedule=SCHED_GRID, xcd_remap=1):
+        L.check(self.lib.dugks_set_launch(self.h, rows_per_wave, waves_per_block, schedule, xcd_remap),
+                self.h, "dugks_set_launch")
+
+    def autotune(self, trial_steps=5):
+        L.check(self.lib.dugks_autotune(self.h, trial_steps), self.h, "dugks_autotune")
+
+    def info(self) -> dict:
+        i = L.Info()
+        L.check(self.lib.dugks_get_info(self.h, C.byref(i)), self.h, "dugks_get_info")
+        return {k: getattr(i, k) for k, _ in L.Info._fields_}
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            self.lib.dugks_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent instances advanced by one launch per step (``dugks_batch``)."""
+
+    def __init__(self, problems, storage="f32", device="cuda:0", launch=None):
+        torch = _torch()
+        self.lib = L.lib()
+        self.device = torch.device(device)
+        self.problems = list(problems)
+        self.storage = _storage_code(storage)
+        n = len(self.problems)
+        descs = (L.InstanceDesc * n)()
+        self._faces = []
+        for k, pb in enumerate(self.problems):
+            xf = np.ascontiguousarray(pb.xf, dtype=np.float64)
+            yf = np.ascontiguousarray(pb.yf, dtype=np.float64)
+            self._faces.append((xf, yf))
+            d = descs[k]
+            d.nx, d.ny, d.q = len(xf) - 1, len(yf) - 1, int(pb.q)
+            d.xf, d.yf = _dptr(xf), _dptr(yf)
+            d.p = _params(pb, self.storage, KERNEL_FUSED)
+            bdeg = max(len(pb.bx), len(pb.by)) - 1
+            ddeg = max(len(pb.dxx), len(pb.dxy), len(pb.dyy)) - 1
+            d.b_deg, d.d_deg = bdeg, ddeg
+            for name, v in (("bx", pb.bx), ("by", pb.by), ("dxx", pb.dxx), ("dxy", pb.dxy),
+                            ("dyy", pb.dyy)):
+                arr = getattr(d, name)
+                for i, x in enumerate(_poly(v, L.MAX_DEG + 1)):
+                    arr[i] = x
+        h = C.c_void_p()
+        rc = self.lib.dugks_batch_create(C.byref(h), n, descs, self.storage)
+        self.h = h
+        L.check(rc, h, "dugks_batch_create")
+        if launch is not None:
+            L.check(self.lib.dugks_batch_set_launch(self.h, *launch), self.h, "set_launch")
+        nbytes = self.lib.dugks_batch_workspace_bytes(self.h)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            self._ws_ptr = (self.workspace.data_ptr() + 255) & ~255
+            L.check(self.lib.dugks_batch_bind(self.h, C.c_void_p(self._ws_ptr), nbytes,
+                                              _stream_handle(self.device)), self.h, "dugks_batch_bind")
+
+    def __len__(self):
+        return len(self.problems)
+
+    def set_phi(self, i, phi):
+        torch = _torch()
+        pb = self.problems[i]
+        t = torch.from_numpy(np.ascontiguousarray(phi, dtype=np.float64)).to(self.device)
+        L.check(self.lib.dugks_batch_set_phi(self.h, i, C.c_void_p(t.data_ptr()), 1), self.h,
+                "dugks_batch_set_phi")
+        del pb
+
+    def set_all_phi(self):
+        for i, pb in enumerate(self.problems):
+            self.set_phi(i, pb.phi0)
+
+    def step(self, nsteps=1):
+        L.check(self.lib.dugks_batch_step(self.h, int(nsteps)), self.h, "dugks_batch_step")
+
+    def time_steps(self, nsteps):
+        ms = C.c_float()
+        L.check(self.lib.dugks_batch_time_steps(self.h, int(nsteps), C.byref(ms)), self.h,
+                "dugks_batch_time_steps")
+        return ms.value
+
+    def get_phi(self, i) -> np.ndarray:
+        torch = _torch()
+        pb = self.problems[i]
+        out = torch.empty((pb.ny, pb.nx), dtype=torch.float64, device=self.device)
+        L.check(self.lib.dugks_batch_get_phi(self.h, i, C.c_void_p(out.data_ptr()), 1), self.h,
+                "dugks_batch_get_phi")
+        return out.cpu().numpy()
+
+    def set_launch(self, rows_per_wave=64, waves_per_block=4, schedule=SCHED_GRID, xcd_remap=1):
+        L.check(self.lib.dugks_batch_set_launch(self.h, rows_per_wave, waves_per_block, schedule,
+                                                xcd_remap), self.h, "dugks_batch_set_launch")
+
+    def autotune(self, trial_steps=3):
+        L.check(self.lib.dugks_batch_autotune(self.h, trial_steps), self.h, "dugks_batch_autotune")
+
+    def info(self, i=0) -> dict:
+        inf = L.Info()
+        L.check(self.lib.dugks_batch_get_info(self.h, i, C.byref(inf)), self.h, "info")
+        return {k: getattr(inf, k) for k, _ in L.Info._fields_}
+
+    def totals(self):
+        cells, sb = C.c_longlong(), C.c_size_t()
+        L.check(self.lib.dugks_batch_totals(self.h, C.byref(cells), C.byref(sb)), self.h, "totals")
+        return cells.value, sb.value
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            self.lib.dugks_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,100 @@
+// Internal layout shared by the host runtime and the gfx950 kernels of libdugks.
+//
+// One f~ buffer of an instance is a set of planes [P][ny][pitch]; pitch is nx
+// rounded up to 64 elements so every row starts on a 128-byte boundary.
+//   DUGKS_F64   : P = q planes of double
+//   DUGKS_F32   : P = q planes of float
+//   16-bit neq  : plane 0 = phi (float, 4-byte elements), planes 1..q-1 = g_i
+//                 (2-byte elements, g_0 = -sum g_i is not stored)
+// Two buffers per instance (ping-pong): step n reads buffer n%2, writes the other.
+#pragma once
+
+#include <stdint.h>
+
+#include "dugks.h"
+
+namespace dugks {
+
+constexpr int kMaxQ = 9;
+constexpr int kMaxCoef = 8;     // E_i(phi) has degree <= 7 (C has degree 2*4-1)
+constexpr int kStripLanes = 64; // one wave covers 64 columns ...
+constexpr int kStripCols = 62;  // ... of which 62 are updated; lanes 0 and 63 are halo
+constexpr int kGeo = 5;         // per column / row: alpha(-), alpha(0), alpha(+), tau, k
+
+// Per-instance constants and pointers, read by the kernels with scalar loads.
+struct alignas(64) InstDev {
+  void* buf[2];            // ping-pong f~ buffers
+  const double* colgeo;    // (nx+2) x kGeo doubles, column c = -1..nx at [(c+1)*kGeo]
+  const double* rowgeo;    // (ny+2) x kGeo doubles, row r = -1..ny
+  const float* colgeo_f;   // float copies
+  const float* rowgeo_f;
+  const double* ring;      // Dirichlet data, ring_steps x ring_len (or null)
+  float* slots;            // 16-bit storage: 4 max|f~ - E| slots (unscaled)
+  unsigned* flags;         // DUGKS_FLAG_* bits, sticky
+  double* partial;         // reduction partials of this instance (set per launch)
+  long long plane;         // elements per plane = ny * pitch
+  int nx, ny, pitch, q;
+  int bcx, bcy;            // DUGKS_BC_* per axis
+  int ring_len, ring_steps;
+  int ncoef;               // number of used polynomial coefficients (degree + 1)
+  int storage;
+  double a1, a2, a3, b1, b2, b3, dt, inv_cs2;
+  float a1f, a2f, a3f;
+  float pad_f;
+  // E_i(phi) = sum_k e[i][k] phi^k ; p1 = b1 e (eq. 2.21) ; p3 = b3 e (eq. 2.22)
+  double e[kMaxQ][kMaxCoef];
+  double p1[kMaxQ][kMaxCoef];
+  double p3[kMaxQ][kMaxCoef];
+  float ef[kMaxQ][kMaxCoef];
+  float p1f[kMaxQ][kMaxCoef];
+  float p3f[kMaxQ][kMaxCoef];
+};
+
+// One unit of work: instance, first interior column of the strip, row range.
+struct WorkItem {
+  int inst, x0, y0, y1;
+};
+
+// Launch configuration.
+struct Launch {
+  int rows_per_wave = 64;
+  int waves_per_block = 4;
+  int schedule = DUGKS_SCHED_GRID;
+  int xcd_remap = 1;
+};
+
+// Kernel entry points (dugks_kernels.hip), all enqueued on `stream`; each
+// returns 0 or -1 when the launch failed.
+struct StepArgs {
+  const InstDev* insts;     // device table
+  const WorkItem* items;    // device work list
+  int nitems;
+  int parity;               // index of the buffer read by this step
+  long long step;           // step index of the input state
+  int q, storage, ncoef;    // template selectors, uniform over the launch
+  int persistent_blocks;    // blocks of the persistent schedule
+};
+
+int launch_step_fused(const StepArgs& a, const Launch& l, void* stream, int measure);
+int launch_step_plain(const StepArgs& a, int nx, int ny, void* stream);
+// zero slots[(step + which) & 3] of every instance
+int launch_clear_slot(const InstDev* insts, int ninst, long long step, int which, void* stream);
+int launch_init_eq(const InstDev* d, const InstDev& h, const double* phi, int parity, void* stream);
+// pass 0: max |f~ - E| into slots[slot]; pass 1: encode f~ with that slot's scale
+int launch_set_f_pass(const InstDev* d, const InstDev& h, const double* f, int parity, int pass,
+                      int slot, void* stream);
+int launch_get_phi(const InstDev* d, const InstDev& h, double* out, int parity, void* stream);
+int launch_get_f(const InstDev* d, const InstDev& h, double* out, int parity, long long step,
+                 void* stream);
+// Sums over cells into out[0..7] (device): [0] mass, [1] sum|phi-ref|, [2] sum|ref|,
+// [3] sum (phi-ref)^2 |V|, [4] sum ref^2 |V|, [5] non-finite cells.  partial
+// holds reduce_partials() * 8 doubles; widths = dx[0..nx) then dy[0..ny).
+int launch_reduce_widths(const InstDev* d, const InstDev& h, const double* ref, int parity,
+                         const double* widths, double* partial, double* out, void* stream);
+int reduce_partials();
+int launch_fill_u32(unsigned* p, unsigned v, long long n, void* stream);
+
+// Power-of-two scale of the 16-bit formats for a maximum |f~ - E| of m.
+float neq_scale_host(float m);
+
+}  // namespace dugks

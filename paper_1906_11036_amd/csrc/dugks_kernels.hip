@@ -1,0 +1,960 @@
+// gfx950 kernels of libdugks: the DUGKS step (summary at the end of Sec. 2 of
+// Shang, Chai, Wang, Shi, arXiv:1906.11036) for D2Q9 / D2Q5, plus the
+// initialisation, encode/decode and reduction kernels around it.
+//
+// Fused step design (one wave = one work item):
+//   - A wave owns a strip of 64 consecutive columns (lanes), of which lanes
+//     1..62 are updated and lanes 0 and 63 are halo columns; it marches down a
+//     chunk of rows.  f~ is read once per row per lane (coalesced 256-byte rows
+//     per plane) and the new f~ is written once: the state crosses HBM once in
+//     each direction per step, halo columns and the two halo rows per chunk
+//     aside.
+//   - fbar+ of three rows (j-1, j, j+1) lives in registers.  Neighbouring
+//     columns are reached with whole-wave DPP shifts (wave_shr:1 / wave_shl:1),
+//     so no LDS and no barrier is used.
+//   - Each lane computes exactly two faces per row: the face on its west side
+//     and the face above its cell.  The east face comes from the lane to the
+//     right; the face below was computed on the previous row.
+//   - The interface phi and the cell phi are accumulated in binary64 for the
+//     binary32 storage (the moment sums); everything else runs in the storage's
+//     arithmetic type.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include "dugks_internal.h"
+
+namespace dugks {
+
+// ------------------------------------------------------------------ lattice
+// D2Q9 of eq. 2.5 (integer components; velocities are c times these).
+__host__ __device__ constexpr int lat_cx(int k) {
+  return (k == 1 || k == 5 || k == 8) ? 1 : ((k == 3 || k == 6 || k == 7) ? -1 : 0);
+}
+__host__ __device__ constexpr int lat_cy(int k) {
+  return (k == 2 || k == 5 || k == 6) ? 1 : ((k == 4 || k == 7 || k == 8) ? -1 : 0);
+}
+// reversal of the x (resp. y) component: the specular mirror of a wall
+__host__ __device__ constexpr int mir_x(int k) {
+  return k == 1 ? 3 : k == 3 ? 1 : k == 5 ? 6 : k == 6 ? 5 : k == 7 ? 8 : k == 8 ? 7 : k;
+}
+__host__ __device__ constexpr int mir_y(int k) {
+  return k == 2 ? 4 : k == 4 ? 2 : k == 5 ? 8 : k == 8 ? 5 : k == 6 ? 7 : k == 7 ? 6 : k;
+}
+
+// ---------------------------------------------------------- storage traits
+template <int ST> struct Stor;
+template <> struct Stor<DUGKS_F64> { using T = double; static constexpr bool neq = false; };
+template <> struct Stor<DUGKS_F32> { using T = float; static constexpr bool neq = false; };
+template <> struct Stor<DUGKS_F16NEQ> { using T = float; static constexpr bool neq = true; };
+template <> struct Stor<DUGKS_BF16NEQ> { using T = float; static constexpr bool neq = true; };
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t u) {
+  return __uint_as_float(((uint32_t)u) << 16);
+}
+__device__ __forceinline__ uint16_t f32_to_bf16(float x) {  // round to nearest even
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float h16_to_f32(uint16_t u) {
+  return (float)__builtin_bit_cast(_Float16, u);
+}
+__device__ __forceinline__ uint16_t f32_to_h16(float x) {  // round to nearest even
+  return __builtin_bit_cast(uint16_t, (_Float16)x);
+}
+
+template <int ST> __device__ __forceinline__ float g_to_f32(uint16_t u) {
+  if constexpr (ST == DUGKS_F16NEQ) return h16_to_f32(u);
+  else return bf16_to_f32(u);
+}
+template <int ST> __device__ __forceinline__ uint16_t f32_to_g(float x) {
+  if constexpr (ST == DUGKS_F16NEQ) return f32_to_h16(x);
+  else return f32_to_bf16(x);
+}
+template <int ST> __device__ __forceinline__ float g_limit() {
+  return ST == DUGKS_F16NEQ ? 65504.0f : 3.0e38f;
+}
+
+// Power-of-two scale s such that max |f~ - E| * s lies in (2^13, 2^14].
+__host__ __device__ inline float neq_scale(float m) {
+  if (!(m > 0.0f) || !(m < 3.0e38f)) return 1.0f;
+  int e;
+  (void)frexpf(m, &e);  // m = f 2^e, f in [0.5, 1)
+  int k = 14 - e;
+  k = k > 100 ? 100 : (k < -100 ? -100 : k);
+  return ldexpf(1.0f, k);
+}
+
+// ------------------------------------------------------------ DPP helpers
+// wave_shr:1 -> lane l receives lane l-1; wave_shl:1 -> lane l receives lane l+1.
+__device__ __forceinline__ float shr1(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                               0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float shl1(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                               0x130, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double shr1(double v) {
+  int2 p = __builtin_bit_cast(int2, v);
+  p.x = __builtin_amdgcn_update_dpp(0, p.x, 0x138, 0xF, 0xF, false);
+  p.y = __builtin_amdgcn_update_dpp(0, p.y, 0x138, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, p);
+}
+__device__ __forceinline__ double shl1(double v) {
+  int2 p = __builtin_bit_cast(int2, v);
+  p.x = __builtin_amdgcn_update_dpp(0, p.x, 0x130, 0xF, 0xF, false);
+  p.y = __builtin_amdgcn_update_dpp(0, p.y, 0x130, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, p);
+}
+
+// ------------------------------------------------------------ coefficients
+template <typename T> struct Coef;
+template <> struct Coef<double> {
+  __device__ static const double* e(const InstDev* I, int k) { return I->e[k]; }
+  __device__ static const double* p1(const InstDev* I, int k) { return I->p1[k]; }
+  __device__ static const double* p3(const InstDev* I, int k) { return I->p3[k]; }
+  __device__ static double a1(const InstDev* I) { return I->a1; }
+  __device__ static double a3(const InstDev* I) { return I->a3; }
+  __device__ static const double* col(const InstDev* I) { return I->colgeo; }
+  __device__ static const double* row(const InstDev* I) { return I->rowgeo; }
+};
+template <> struct Coef<float> {
+  __device__ static const float* e(const InstDev* I, int k) { return I->ef[k]; }
+  __device__ static const float* p1(const InstDev* I, int k) { return I->p1f[k]; }
+  __device__ static const float* p3(const InstDev* I, int k) { return I->p3f[k]; }
+  __device__ static float a1(const InstDev* I) { return I->a1f; }
+  __device__ static float a3(const InstDev* I) { return I->a3f; }
+  __device__ static const float* col(const InstDev* I) { return I->colgeo_f; }
+  __device__ static const float* row(const InstDev* I) { return I->rowgeo_f; }
+};
+
+// p(x) = sum_{m < NC} c[m] x^m by Horner's rule
+template <int NC, typename T> __device__ __forceinline__ T horner(const T* c, T x) {
+  T r = c[NC - 1];
+#pragma unroll
+  for (int m = NC - 2; m >= 0; --m) r = fma(r, x, c[m]);
+  return r;
+}
+
+// ------------------------------------------------------------- cell state
+// Raw stored values of one cell.
+template <int Q, int ST> struct Raw;
+template <int Q> struct Raw<Q, DUGKS_F64> { double v[Q]; };
+template <int Q> struct Raw<Q, DUGKS_F32> { float v[Q]; };
+template <int Q> struct Raw<Q, DUGKS_F16NEQ> { float phi; uint16_t g[Q - 1]; };
+template <int Q> struct Raw<Q, DUGKS_BF16NEQ> { float phi; uint16_t g[Q - 1]; };
+
+template <int Q, int ST>
+__device__ __forceinline__ void load_raw(Raw<Q, ST>& r, const char* buf, long long plane,
+                                         long long off) {
+  if constexpr (ST == DUGKS_F64) {
+    const double* b = (const double*)buf;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) r.v[k] = __builtin_nontemporal_load(b + k * plane + off);
+  } else if constexpr (ST == DUGKS_F32) {
+    const float* b = (const float*)buf;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) r.v[k] = __builtin_nontemporal_load(b + k * plane + off);
+  } else {
+    r.phi = __builtin_nontemporal_load((const float*)buf + off);
+    const uint16_t* g = (const uint16_t*)(buf + 4 * plane);
+#pragma unroll
+    for (int k = 0; k < Q - 1; ++k) r.g[k] = __builtin_nontemporal_load(g + k * plane + off);
+  }
+}
+
+// Scale factors of the 16-bit formats for this step.
+struct Scales {
+  float inv_in;  // 1 / s of the input buffer
+  float out;     // s of the output buffer
+};
+
+// fbar+ (eq. 2.21) of the source cell, and f~+ (eq. 2.23) when wanted.
+// Also returns f~ - E (a1 times it is the non-equilibrium part of fbar+),
+// needed only by Dirichlet ghosts.
+template <int Q, int ST, int NC>
+__device__ __forceinline__ void cell_values(const InstDev* __restrict__ I, const Raw<Q, ST>& r,
+                                            const Scales& sc, typename Stor<ST>::T* fb,
+                                            typename Stor<ST>::T* ftp, bool want_ftp,
+                                            typename Stor<ST>::T& phi_out) {
+  using T = typename Stor<ST>::T;
+  using C = Coef<T>;
+  if constexpr (!Stor<ST>::neq) {
+    double phi = 0.0;  // phi = sum_i f~_i (Sec. 2), binary64
+#pragma unroll
+    for (int k = 0; k < Q; ++k) phi += (double)r.v[k];
+    const T p = (T)phi;
+    const T a1 = C::a1(I);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) fb[k] = fma(a1, r.v[k], horner<NC>(C::p1(I, k), p));
+    if (want_ftp) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) ftp[k] = fma((T)(4.0 / 3.0), fb[k], (T)(-1.0 / 3.0) * r.v[k]);
+    }
+    phi_out = p;
+  } else {
+    const float p = r.phi;
+    float g[Q];
+    float gs = 0.0f;
+#pragma unroll
+    for (int k = 1; k < Q; ++k) {
+      g[k] = g_to_f32<ST>(r.g[k - 1]);
+      gs += g[k];
+    }
+    g[0] = -gs;
+    const float a1s = I->a1f * sc.inv_in, a2s = I->a2f * sc.inv_in;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      const float E = horner<NC>(I->ef[k], p);
+      fb[k] = fma(a1s, g[k], E);
+      if (want_ftp) ftp[k] = fma(a2s, g[k], E);
+    }
+    phi_out = p;
+  }
+}
+
+// Ghost rules applied to fbar+ of the source cell a (already in fb).
+template <int Q, int ST, int NC>
+__device__ __forceinline__ void apply_ghost(const InstDev* __restrict__ I, typename Stor<ST>::T* fb,
+                                            typename Stor<ST>::T phi_a, bool wall_x, bool wall_y,
+                                            double phi_g) {
+  using T = typename Stor<ST>::T;
+  using C = Coef<T>;
+  const bool dir = (wall_x && I->bcx == DUGKS_BC_DIRICHLET) || (wall_y && I->bcy == DUGKS_BC_DIRICHLET);
+  if (dir) {
+    // non-equilibrium extrapolation: fbar+_g = E(phi_g) + (fbar+_a - E(phi_a))
+    const T pg = (T)phi_g;
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+      fb[k] = horner<NC>(C::e(I, k), pg) + (fb[k] - horner<NC>(C::e(I, k), phi_a));
+  } else {
+    T t[Q];
+    if (wall_x) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) t[k] = fb[mir_x(k)];
+#pragma unroll
+      for (int k = 0; k < Q; ++k) fb[k] = t[k];
+    }
+    if (wall_y) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) t[k] = fb[mir_y(k)];
+#pragma unroll
+      for (int k = 0; k < Q; ++k) fb[k] = t[k];
+    }
+  }
+}
+
+__device__ __forceinline__ int ring_index(int nx, int ny, int i, int j) {
+  if (j == -1) return i + 1;
+  if (j == ny) return (nx + 2) + i + 1;
+  if (i == -1) return 2 * (nx + 2) + j;
+  return 2 * (nx + 2) + ny + j;
+}
+
+__device__ __forceinline__ int src_index(int i, int n, int bc) {
+  if (i >= 0 && i < n) return i;
+  if (bc == DUGKS_BC_PERIODIC) {
+    int w = i < 0 ? i + n : i - n;
+    return w < 0 ? 0 : (w >= n ? n - 1 : w);
+  }
+  return i < 0 ? 0 : n - 1;
+}
+
+// Half-step interface distribution (eqs. 2.20, 2.19/2.26), interface phi,
+// f_b = a3 fbar_b + b3 E(phi_b) (eq. 2.22) for directions with a normal
+// velocity component.  NRM / TAN select the axis: NRM = 0 for x-faces.
+template <int Q, int NC, int NRM, typename T>
+__device__ __forceinline__ void face(const InstDev* __restrict__ I, const T* L, const T* R,
+                                     const T* dL, const T* dR, T am, T a0, T ap, T tau, T* out) {
+  using C = Coef<T>;
+  T fbb[Q];
+  double phib = 0.0;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    const int cn = NRM == 0 ? lat_cx(k) : lat_cy(k);
+    const int ct = NRM == 0 ? lat_cy(k) : lat_cx(k);
+    const T al = cn > 0 ? ap : (cn < 0 ? am : a0);
+    T v = fma(al, R[k] - L[k], L[k]);
+    if (ct != 0) v = fma((T)(-ct) * tau, dL[k] + dR[k], v);
+    fbb[k] = v;
+    phib += (double)v;  // phi(x_b, t + h) = sum_i fbar_i
+  }
+  const T pb = (T)phib;
+  const T a3 = C::a3(I);
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    const int cn = NRM == 0 ? lat_cx(k) : lat_cy(k);
+    if (cn != 0) out[k] = fma(a3, fbb[k], horner<NC>(C::p3(I, k), pb));
+  }
+}
+
+// Map a block index so that consecutive logical blocks land on one XCD
+// (blocks are dispatched round-robin over the 8 XCDs).
+__device__ __forceinline__ int xcd_logical(int b, int nblocks) {
+  const int q = nblocks >> 3, r = nblocks & 7;
+  const int x = b & 7, i = b >> 3;
+  return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+// ---------------------------------------------------------- fused step
+template <int Q, int ST, int NC>
+__device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const WorkItem it,
+                                          int parity, long long step, int lane, bool measure) {
+  using T = typename Stor<ST>::T;
+  using C = Coef<T>;
+  const int nx = I->nx, ny = I->ny, pitch = I->pitch, bcx = I->bcx, bcy = I->bcy;
+  const long long plane = I->plane;
+  const char* in = (const char*)I->buf[parity];
+  char* out = (char*)I->buf[parity ^ 1];
+
+  Scales sc{1.0f, 1.0f};
+  if constexpr (Stor<ST>::neq) {
+    sc.inv_in = 1.0f / neq_scale(I->slots[(step + 2) & 3]);
+    sc.out = neq_scale(I->slots[(step + 3) & 3]);
+  }
+
+  const int c = it.x0 - 1 + lane;
+  const int sc_col = src_index(c < nx + 1 ? c : nx, nx, bcx);
+  const bool wall_x = (c < 0 || c >= nx) && bcx != DUGKS_BC_PERIODIC;
+  const bool live = lane >= 1 && lane <= kStripCols && c < nx;
+  const bool strip_touches_x_wall = bcx != DUGKS_BC_PERIODIC && (it.x0 == 0 || it.x0 + kStripCols >= nx);
+
+  // per-column geometry: W-face coefficients, tangential factor, update factor
+  const T* cg = C::col(I) + (long long)((c + 1 < nx + 1 ? c + 1 : nx + 1)) * kGeo;
+  const T cam = cg[0], ca0 = cg[1], cap = cg[2], ctau = cg[3], ck = cg[4];
+  const T* rg = C::row(I);
+
+  const double* ring = (I->ring != nullptr) ? I->ring + step * I->ring_len : nullptr;
+
+  auto make_row = [&](const Raw<Q, ST>& raw, int r, T* fb, T* ftp, bool want_ftp) {
+    T phi_a;
+    cell_values<Q, ST, NC>(I, raw, sc, fb, ftp, want_ftp, phi_a);
+    const bool wall_y = (r < 0 || r >= ny) && bcy != DUGKS_BC_PERIODIC;
+    if (wall_y || strip_touches_x_wall) {
+      if (wall_x || wall_y) {
+        double pg = 0.0;
+        if (ring != nullptr) pg = ring[ring_index(nx, ny, c < -1 ? -1 : (c > nx ? nx : c), r)];
+        apply_ghost<Q, ST, NC>(I, fb, phi_a, wall_x, wall_y, pg);
+      }
+    }
+  };
+  auto row_off = [&](int r) -> long long {
+    return (long long)src_index(r, ny, bcy) * pitch + sc_col;
+  };
+  auto sigma_x = [&](const T* fb, T* sx) {
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+      if (lat_cx(k) != 0) sx[k] = shl1(fb[k]) - shr1(fb[k]);
+  };
+
+  const int y0 = it.y0, y1 = it.y1;
+  T fbm[Q], fb0[Q], fbp[Q], ftp0[Q], ftp1[Q], sxm[Q], sx0[Q], sxp[Q], fS[Q], fN[Q], fW[Q], fE[Q],
+      dy[Q], dL[Q], Lv[Q];
+  Raw<Q, ST> ra, rb;
+
+  // prologue: rows y0-1 and y0, the face below row y0
+  load_raw<Q, ST>(ra, in, plane, row_off(y0 - 1));
+  load_raw<Q, ST>(rb, in, plane, row_off(y0));
+  make_row(ra, y0 - 1, fbm, ftp1, false);
+  make_row(rb, y0, fb0, ftp0, true);
+  load_raw<Q, ST>(ra, in, plane, row_off(y0 + 1));
+  sigma_x(fbm, sxm);
+  sigma_x(fb0, sx0);
+  {
+    const T* g = rg + (long long)(y0 + 1) * kGeo;
+    face<Q, NC, 1>(I, fbm, fb0, sxm, sx0, g[0], g[1], g[2], ctau, fS);
+  }
+
+  bool bad = false, ovf = false;
+  float mx = 0.0f;
+  for (int j = y0; j < y1; ++j) {
+    // row j+1 (already loaded into ra); prefetch row j+2
+    Raw<Q, ST> rc = ra;
+    if (j + 2 <= y1) load_raw<Q, ST>(ra, in, plane, row_off(j + 2));
+    make_row(rc, j + 1, fbp, ftp1, true);
+    const T* gj = rg + (long long)(j + 1) * kGeo;   // row j: its S face and factors
+    const T* gn = rg + (long long)(j + 2) * kGeo;   // row j+1: S face = N face of row j
+    const T rtau = gj[3], rk = gj[4];
+    // central differences along y at row j (numerators of the y-slopes)
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+      if (lat_cy(k) != 0) dy[k] = fbp[k] - fbm[k];
+    sigma_x(fbp, sxp);
+    face<Q, NC, 1>(I, fb0, fbp, sx0, sxp, gn[0], gn[1], gn[2], ctau, fN);
+    // west face of this lane's cell: left state from lane-1
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      Lv[k] = shr1(fb0[k]);
+      if (lat_cy(k) != 0) dL[k] = shr1(dy[k]);
+    }
+    face<Q, NC, 0>(I, Lv, fb0, dL, dy, cam, ca0, cap, rtau, fW);
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+      if (lat_cx(k) != 0) fE[k] = shl1(fW[k]);
+    // update (eq. 2.24): f~(t+dt) = f~+ - dt c_i.(flux differences)/width
+    T o[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      T v = ftp0[k];
+      if (lat_cx(k) != 0) v = fma((T)(-lat_cx(k)) * ck, fE[k] - fW[k], v);
+      if (lat_cy(k) != 0) v = fma((T)(-lat_cy(k)) * rk, fN[k] - fS[k], v);
+      o[k] = v;
+    }
+    if (live) {
+      const long long off = (long long)j * pitch + c;
+      if constexpr (!Stor<ST>::neq) {
+        bad |= !__builtin_isfinite(o[0]);
+        T* ob = (T*)out;
+        if (!measure) {
+#pragma unroll
+          for (int k = 0; k < Q; ++k) __builtin_nontemporal_store(o[k], ob + k * plane + off);
+        }
+      } else {
+        double ps = 0.0;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) ps += (double)o[k];
+        const float pf = (float)ps;
+        bad |= !__builtin_isfinite(pf);
+        float m = 0.0f;
+        uint16_t gq[Q - 1];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          const float d = o[k] - horner<NC>(I->ef[k], pf);
+          m = fmaxf(m, fabsf(d));
+          if (k > 0) {
+            float s = d * sc.out;
+            if (!measure && fabsf(s) > g_limit<ST>()) {
+              ovf = true;
+              s = fminf(fmaxf(s, -g_limit<ST>()), g_limit<ST>());
+            }
+            gq[k - 1] = f32_to_g<ST>(s);
+          }
+        }
+        mx = fmaxf(mx, m);
+        if (!measure) {
+          __builtin_nontemporal_store(pf, (float*)out + off);
+          uint16_t* gb = (uint16_t*)(out + 4 * plane);
+#pragma unroll
+          for (int k = 0; k < Q - 1; ++k) __builtin_nontemporal_store(gq[k], gb + k * plane + off);
+        }
+      }
+    }
+    // rotate the window
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      fbm[k] = fb0[k];
+      fb0[k] = fbp[k];
+      ftp0[k] = ftp1[k];
+      if (lat_cx(k) != 0) sx0[k] = sxp[k];
+      if (lat_cy(k) != 0) fS[k] = fN[k];
+    }
+  }
+  if constexpr (Stor<ST>::neq) {
+    // wave maximum of |f~ - E| over updated cells -> the instance's slot
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+    if (lane == 0 && mx > 0.0f) {
+      const int slot = measure ? (int)((step + 3) & 3) : (int)(step & 3);
+      atomicMax((unsigned*)(I->slots + slot), __float_as_uint(mx));
+    }
+  }
+  if (__any(bad) && lane == 0) atomicOr(I->flags, (unsigned)DUGKS_FLAG_NONFINITE);
+  if (__any(ovf) && lane == 0) atomicOr(I->flags, (unsigned)DUGKS_FLAG_OVERFLOW);
+}
+
+template <int Q, int ST, int NC>
+__global__ __launch_bounds__(256) void k_step(const InstDev* __restrict__ insts,
+                                              const WorkItem* __restrict__ items, int nitems,
+                                              int parity, long long step, int xcd_remap,
+                                              int persistent, int measure) {
+  const int wpb = blockDim.x >> 6;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int b = xcd_remap ? xcd_logical(blockIdx.x, gridDim.x) : blockIdx.x;
+  int item = b * wpb + w;
+  const int stride = persistent ? gridDim.x * wpb : nitems;
+  for (; item < nitems; item += stride) {
+    const WorkItem it = items[item];
+    const InstDev* I = insts + it.inst;
+    step_item<Q, ST, NC>(I, it, parity, step, lane, measure != 0);
+    if (!persistent) break;
+  }
+}
+
+// Clear slot (step+1)&3 of every instance before a 16-bit step: that slot
+// collects the maximum of the next step's output.
+__global__ void k_clear_next_slot(const InstDev* __restrict__ insts, int ninst, long long step,
+                                  int which) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ninst) insts[i].slots[(step + which) & 3] = 0.0f;
+}
+
+// ------------------------------------------------------- plain FP64 step
+// One thread per cell; every neighbour value is read from global memory and
+// fbar+ of the 3x3 neighbourhood is recomputed per cell.
+template <int Q, int NC>
+__global__ __launch_bounds__(256) void k_step_plain(const InstDev* __restrict__ I, int parity,
+                                                    long long step) {
+  const int nx = I->nx, ny = I->ny, pitch = I->pitch;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= nx || j >= ny) return;
+  const long long plane = I->plane;
+  const char* in = (const char*)I->buf[parity];
+  double* out = (double*)I->buf[parity ^ 1];
+  const double* ring = (I->ring != nullptr) ? I->ring + step * I->ring_len : nullptr;
+  Scales sc{1.0f, 1.0f};
+  double g[3][3][Q];
+  for (int b = -1; b <= 1; ++b)
+    for (int a = -1; a <= 1; ++a) {
+      const int ci = i + a, cj = j + b;
+      Raw<Q, DUGKS_F64> raw;
+      load_raw<Q, DUGKS_F64>(raw, in, plane,
+                             (long long)src_index(cj, ny, I->bcy) * pitch + src_index(ci, nx, I->bcx));
+      double phi_a, dummy[Q];
+      cell_values<Q, DUGKS_F64, NC>(I, raw, sc, g[b + 1][a + 1], dummy, false, phi_a);
+      const bool wx = (ci < 0 || ci >= nx) && I->bcx != DUGKS_BC_PERIODIC;
+      const bool wy = (cj < 0 || cj >= ny) && I->bcy != DUGKS_BC_PERIODIC;
+      if (wx || wy) {
+        const double pg = ring != nullptr ? ring[ring_index(nx, ny, ci, cj)] : 0.0;
+        apply_ghost<Q, DUGKS_F64, NC>(I, g[b + 1][a + 1], phi_a, wx, wy, pg);
+      }
+    }
+  const double* cg = I->colgeo;
+  const double* rg = I->rowgeo;
+  // slope numerators
+  double sy[3][Q], sx[3][Q];
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int k = 0; k < Q; ++k) sy[a][k] = g[2][a][k] - g[0][a][k];
+  for (int b = 0; b < 3; ++b)
+#pragma unroll
+    for (int k = 0; k < Q; ++k) sx[b][k] = g[b][2][k] - g[b][0][k];
+  const double* cW = cg + (long long)(i + 1) * kGeo;   // W face of column i
+  const double* cE = cg + (long long)(i + 2) * kGeo;   // W face of column i+1
+  const double* rS = rg + (long long)(j + 1) * kGeo;
+  const double* rN = rg + (long long)(j + 2) * kGeo;
+  double fW[Q], fE[Q], fS[Q], fN[Q];
+  face<Q, NC, 0>(I, g[1][0], g[1][1], sy[0], sy[1], cW[0], cW[1], cW[2], rS[3], fW);
+  face<Q, NC, 0>(I, g[1][1], g[1][2], sy[1], sy[2], cE[0], cE[1], cE[2], rS[3], fE);
+  face<Q, NC, 1>(I, g[0][1], g[1][1], sx[0], sx[1], rS[0], rS[1], rS[2], cW[3], fS);
+  face<Q, NC, 1>(I, g[1][1], g[2][1], sx[1], sx[2], rN[0], rN[1], rN[2], cW[3], fN);
+  Raw<Q, DUGKS_F64> raw;
+  load_raw<Q, DUGKS_F64>(raw, in, plane, (long long)j * pitch + i);
+  double fb[Q], ftp[Q], phi;
+  cell_values<Q, DUGKS_F64, NC>(I, raw, sc, fb, ftp, true, phi);
+  const double kx = cW[4], ky = rS[4];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    double v = ftp[k];
+    if (lat_cx(k) != 0) v = fma(-lat_cx(k) * kx, fE[k] - fW[k], v);
+    if (lat_cy(k) != 0) v = fma(-lat_cy(k) * ky, fN[k] - fS[k], v);
+    out[k * plane + (long long)j * pitch + i] = v;
+  }
+}
+
+// -------------------------------------------------- init, encode, decode
+// Equilibrium of phi in binary64 (eq. 2.3 through the per-direction polynomial).
+template <int Q>
+__device__ __forceinline__ void feq64(const InstDev* __restrict__ I, double phi, double* E) {
+  const int nc = I->ncoef;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    double r = I->e[k][nc - 1];
+    for (int m = nc - 2; m >= 0; --m) r = fma(r, phi, I->e[k][m]);
+    E[k] = r;
+  }
+}
+
+// 16-bit encode of f~ (binary64 values) at one cell.
+template <int Q, int ST>
+__device__ __forceinline__ void encode_neq(const InstDev* __restrict__ I, char* buf, long long off,
+                                           const double* f, float s, float* maxdev) {
+  double ps = 0.0;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) ps += f[k];
+  const float pf = (float)ps;
+  const int nc = I->ncoef;
+  float m = 0.0f;
+  uint16_t* gb = (uint16_t*)(buf + 4 * I->plane);
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    float E = I->ef[k][nc - 1];
+    for (int mm = nc - 2; mm >= 0; --mm) E = fmaf(E, pf, I->ef[k][mm]);
+    const float d = (float)(f[k] - (double)E);
+    m = fmaxf(m, fabsf(d));
+    if (k > 0 && s > 0.0f) gb[(k - 1) * I->plane + off] = f32_to_g<ST>(d * s);
+  }
+  if (s > 0.0f) ((float*)buf)[off] = pf;
+  *maxdev = m;
+}
+
+template <int Q, int ST>
+__global__ void k_init_eq(const InstDev* __restrict__ I, const double* __restrict__ phi, int parity) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+  if (i >= I->nx || j >= I->ny) return;
+  const long long off = (long long)j * I->pitch + i;
+  const double p = phi[(long long)j * I->nx + i];
+  char* buf = (char*)I->buf[parity];
+  if constexpr (!Stor<ST>::neq) {
+    double E[Q];
+    feq64<Q>(I, p, E);
+    using T = typename Stor<ST>::T;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) ((T*)buf)[k * I->plane + off] = (T)E[k];
+  } else {
+    // f~ = E(phi) exactly for the stored phi: g = 0
+    ((float*)buf)[off] = (float)p;
+    uint16_t* gb = (uint16_t*)(buf + 4 * I->plane);
+#pragma unroll
+    for (int k = 0; k < Q - 1; ++k) gb[k * I->plane + off] = 0;
+  }
+}
+
+// pass 0: max |f~ - E| into slots[slot]; pass 1: encode with that slot's scale
+template <int Q, int ST>
+__global__ void k_set_f(const InstDev* __restrict__ I, const double* __restrict__ f, int parity,
+                        int pass, int slot) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+  const bool in = i < I->nx && j < I->ny;
+  const long long N = (long long)I->nx * I->ny;
+  const long long off = (long long)j * I->pitch + i;
+  char* buf = (char*)I->buf[parity];
+  double v[Q];
+  if (in) {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) v[k] = f[k * N + (long long)j * I->nx + i];
+  }
+  if constexpr (!Stor<ST>::neq) {
+    using T = typename Stor<ST>::T;
+    if (in && pass == 1) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) ((T*)buf)[k * I->plane + off] = (T)v[k];
+    }
+  } else {
+    float m = 0.0f;
+    if (in) encode_neq<Q, ST>(I, buf, off, v, pass == 1 ? neq_scale(I->slots[slot]) : 0.0f, &m);
+    if (pass == 0) {
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+      if ((threadIdx.x & 63) == 0 && m > 0.0f)
+        atomicMax((unsigned*)(I->slots + slot), __float_as_uint(m));
+    }
+  }
+}
+
+// f~ of one cell in binary64
+template <int Q, int ST>
+__device__ __forceinline__ void decode(const InstDev* __restrict__ I, const char* buf, long long off,
+                                       float inv_s, double* f) {
+  if constexpr (!Stor<ST>::neq) {
+    using T = typename Stor<ST>::T;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) f[k] = (double)((const T*)buf)[k * I->plane + off];
+  } else {
+    const float p = ((const float*)buf)[off];
+    const uint16_t* gb = (const uint16_t*)(buf + 4 * I->plane);
+    const int nc = I->ncoef;
+    float gs = 0.0f;
+    float g[Q];
+#pragma unroll
+    for (int k = 1; k < Q; ++k) {
+      g[k] = g_to_f32<ST>(gb[(k - 1) * I->plane + off]);
+      gs += g[k];
+    }
+    g[0] = -gs;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      float E = I->ef[k][nc - 1];
+      for (int m = nc - 2; m >= 0; --m) E = fmaf(E, p, I->ef[k][m]);
+      f[k] = (double)fmaf(g[k], inv_s, E);
+    }
+  }
+}
+
+template <int Q, int ST>
+__global__ void k_get_phi(const InstDev* __restrict__ I, double* __restrict__ out, int parity) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+  if (i >= I->nx || j >= I->ny) return;
+  const long long off = (long long)j * I->pitch + i;
+  const char* buf = (const char*)I->buf[parity];
+  double phi;
+  if constexpr (Stor<ST>::neq) {
+    phi = (double)((const float*)buf)[off];  // the stored moment; sum g_i = 0 by construction
+  } else {
+    double f[Q];
+    decode<Q, ST>(I, buf, off, 1.0f, f);
+    phi = 0.0;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) phi += f[k];
+  }
+  out[(long long)j * I->nx + i] = phi;
+}
+
+template <int Q, int ST>
+__global__ void k_get_f(const InstDev* __restrict__ I, double* __restrict__ out, int parity,
+                        long long step) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+  if (i >= I->nx || j >= I->ny) return;
+  const long long off = (long long)j * I->pitch + i;
+  const long long N = (long long)I->nx * I->ny;
+  float inv_s = 1.0f;
+  if constexpr (Stor<ST>::neq) inv_s = 1.0f / neq_scale(I->slots[(step + 2) & 3]);
+  double f[Q];
+  decode<Q, ST>(I, (const char*)I->buf[parity], off, inv_s, f);
+#pragma unroll
+  for (int k = 0; k < Q; ++k) out[k * N + (long long)j * I->nx + i] = f[k];
+}
+
+// ------------------------------------------------------------ reductions
+constexpr int kRedBlocks = 1024;
+constexpr int kRedThreads = 256;
+constexpr int kRedVals = 8;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+template <int Q, int ST>
+__global__ __launch_bounds__(kRedThreads) void k_reduce(const InstDev* __restrict__ I,
+                                                        const double* __restrict__ ref, int parity,
+                                                        const double* __restrict__ widths,
+                                                        double* __restrict__ partial) {
+  const long long N = (long long)I->nx * I->ny;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  const char* buf = (const char*)I->buf[parity];
+  for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N;
+       n += (long long)gridDim.x * blockDim.x) {
+    const int j = (int)(n / I->nx), i = (int)(n - (long long)j * I->nx);
+    const long long off = (long long)j * I->pitch + i;
+    double phi;
+    if constexpr (Stor<ST>::neq) {
+      phi = (double)((const float*)buf)[off];
+    } else {
+      double f[Q];
+      decode<Q, ST>(I, buf, off, 1.0f, f);
+      phi = 0.0;
+#pragma unroll
+      for (int k = 0; k < Q; ++k) phi += f[k];
+    }
+    const double vol = widths[i] * widths[I->nx + j];
+    if (!__builtin_isfinite(phi)) {
+      acc[5] += 1.0;
+      continue;
+    }
+    acc[0] += phi * vol;
+    if (ref != nullptr) {
+      const double r = ref[n], d = phi - r;
+      acc[1] += fabs(d);
+      acc[2] += fabs(r);
+      acc[3] += d * d * vol;
+      acc[4] += r * r * vol;
+    }
+  }
+  __shared__ double sh[kRedThreads / 64][6];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int v = 0; v < 6; ++v) {
+    const double s = wave_sum(acc[v]);
+    if (lane == 0) sh[w][v] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    double s = 0.0;
+    for (int ww = 0; ww < kRedThreads / 64; ++ww) s += sh[ww][threadIdx.x];
+    partial[blockIdx.x * kRedVals + threadIdx.x] = s;
+  }
+}
+
+__global__ void k_reduce_final(const double* __restrict__ partial, int nblocks,
+                               double* __restrict__ out) {
+  // one thread per value, partials summed in block order: deterministic
+  const int v = threadIdx.x;
+  if (v >= kRedVals) return;
+  double s = 0.0;
+  for (int b = 0; b < nblocks; ++b) s += partial[b * kRedVals + v];
+  out[v] = s;
+}
+
+__global__ void k_fill_u32(unsigned* p, unsigned v, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// --------------------------------------------------------------- launch
+static inline hipStream_t S(void* s) { return (hipStream_t)s; }
+
+#define DUGKS_CHECK_LAUNCH() return hipGetLastError() == hipSuccess ? 0 : -1
+
+template <int Q, int ST>
+static int launch_step_q_st(const StepArgs& a, const Launch& l, void* stream, int measure) {
+  const int wpb = l.waves_per_block;
+  const int blocks_needed = (a.nitems + wpb - 1) / wpb;
+  int blocks = blocks_needed;
+  const int persistent = (l.schedule == DUGKS_SCHED_PERSISTENT && a.persistent_blocks > 0 &&
+                          a.persistent_blocks < blocks_needed);
+  if (persistent) blocks = a.persistent_blocks;
+  if (blocks <= 0) return 0;
+  dim3 grid(blocks), block(64 * wpb);
+  switch (a.ncoef) {
+    case 2:
+      hipLaunchKernelGGL((k_step<Q, ST, 2>), grid, block, 0, S(stream), a.insts, a.items, a.nitems,
+                         a.parity, a.step, l.xcd_remap, persistent, measure);
+      break;
+    case 4:
+      hipLaunchKernelGGL((k_step<Q, ST, 4>), grid, block, 0, S(stream), a.insts, a.items, a.nitems,
+                         a.parity, a.step, l.xcd_remap, persistent, measure);
+      break;
+    default:
+      hipLaunchKernelGGL((k_step<Q, ST, 8>), grid, block, 0, S(stream), a.insts, a.items, a.nitems,
+                         a.parity, a.step, l.xcd_remap, persistent, measure);
+      break;
+  }
+  DUGKS_CHECK_LAUNCH();
+}
+
+template <int Q>
+static int launch_plain_q(const StepArgs& a, int nx, int ny, void* stream) {
+  dim3 grid((nx + 255) / 256, ny), block(256);
+  switch (a.ncoef) {
+    case 2:
+      hipLaunchKernelGGL((k_step_plain<Q, 2>), grid, block, 0, S(stream), a.insts, a.parity, a.step);
+      break;
+    case 4:
+      hipLaunchKernelGGL((k_step_plain<Q, 4>), grid, block, 0, S(stream), a.insts, a.parity, a.step);
+      break;
+    default:
+      hipLaunchKernelGGL((k_step_plain<Q, 8>), grid, block, 0, S(stream), a.insts, a.parity, a.step);
+      break;
+  }
+  DUGKS_CHECK_LAUNCH();
+}
+
+int launch_step_plain(const StepArgs& a, int nx, int ny, void* stream) {
+  return a.q == 9 ? launch_plain_q<9>(a, nx, ny, stream) : launch_plain_q<5>(a, nx, ny, stream);
+}
+
+template <int Q>
+static int launch_step_q(const StepArgs& a, const Launch& l, void* stream, int measure) {
+  switch (a.storage) {
+    case DUGKS_F64: return launch_step_q_st<Q, DUGKS_F64>(a, l, stream, measure);
+    case DUGKS_F32: return launch_step_q_st<Q, DUGKS_F32>(a, l, stream, measure);
+    case DUGKS_F16NEQ: return launch_step_q_st<Q, DUGKS_F16NEQ>(a, l, stream, measure);
+    default: return launch_step_q_st<Q, DUGKS_BF16NEQ>(a, l, stream, measure);
+  }
+}
+
+int launch_step_fused(const StepArgs& a, const Launch& l, void* stream, int measure) {
+  return a.q == 9 ? launch_step_q<9>(a, l, stream, measure) : launch_step_q<5>(a, l, stream, measure);
+}
+
+int launch_clear_slot(const InstDev* insts, int ninst, long long step, int which, void* stream) {
+  hipLaunchKernelGGL(k_clear_next_slot, dim3((ninst + 255) / 256), dim3(256), 0, S(stream), insts,
+                     ninst, step, which);
+  DUGKS_CHECK_LAUNCH();
+}
+
+template <int Q>
+static int init_q(const InstDev* d, const InstDev& h, const double* phi, int parity, void* stream) {
+  dim3 grid((h.nx + 255) / 256, h.ny), block(256);
+  switch (h.storage) {
+    case DUGKS_F64: hipLaunchKernelGGL((k_init_eq<Q, DUGKS_F64>), grid, block, 0, S(stream), d, phi, parity); break;
+    case DUGKS_F32: hipLaunchKernelGGL((k_init_eq<Q, DUGKS_F32>), grid, block, 0, S(stream), d, phi, parity); break;
+    case DUGKS_F16NEQ: hipLaunchKernelGGL((k_init_eq<Q, DUGKS_F16NEQ>), grid, block, 0, S(stream), d, phi, parity); break;
+    default: hipLaunchKernelGGL((k_init_eq<Q, DUGKS_BF16NEQ>), grid, block, 0, S(stream), d, phi, parity); break;
+  }
+  DUGKS_CHECK_LAUNCH();
+}
+int launch_init_eq(const InstDev* d, const InstDev& h, const double* phi, int parity, void* stream) {
+  return h.q == 9 ? init_q<9>(d, h, phi, parity, stream) : init_q<5>(d, h, phi, parity, stream);
+}
+
+template <int Q>
+static int set_f_q(const InstDev* d, const InstDev& h, const double* f, int parity, int pass,
+                   int slot, void* stream) {
+  dim3 grid((h.nx + 255) / 256, h.ny), block(256);
+  switch (h.storage) {
+    case DUGKS_F64: hipLaunchKernelGGL((k_set_f<Q, DUGKS_F64>), grid, block, 0, S(stream), d, f, parity, pass, slot); break;
+    case DUGKS_F32: hipLaunchKernelGGL((k_set_f<Q, DUGKS_F32>), grid, block, 0, S(stream), d, f, parity, pass, slot); break;
+    case DUGKS_F16NEQ: hipLaunchKernelGGL((k_set_f<Q, DUGKS_F16NEQ>), grid, block, 0, S(stream), d, f, parity, pass, slot); break;
+    default: hipLaunchKernelGGL((k_set_f<Q, DUGKS_BF16NEQ>), grid, block, 0, S(stream), d, f, parity, pass, slot); break;
+  }
+  DUGKS_CHECK_LAUNCH();
+}
+int launch_set_f_pass(const InstDev* d, const InstDev& h, const double* f, int parity, int pass,
+                      int slot, void* stream) {
+  return h.q == 9 ? set_f_q<9>(d, h, f, parity, pass, slot, stream)
+                  : set_f_q<5>(d, h, f, parity, pass, slot, stream);
+}
+
+template <int Q>
+static int get_phi_q(const InstDev* d, const InstDev& h, double* out, int parity, void* stream) {
+  dim3 grid((h.nx + 255) / 256, h.ny), block(256);
+  switch (h.storage) {
+    case DUGKS_F64: hipLaunchKernelGGL((k_get_phi<Q, DUGKS_F64>), grid, block, 0, S(stream), d, out, parity); break;
+    case DUGKS_F32: hipLaunchKernelGGL((k_get_phi<Q, DUGKS_F32>), grid, block, 0, S(stream), d, out, parity); break;
+    case DUGKS_F16NEQ: hipLaunchKernelGGL((k_get_phi<Q, DUGKS_F16NEQ>), grid, block, 0, S(stream), d, out, parity); break;
+    default: hipLaunchKernelGGL((k_get_phi<Q, DUGKS_BF16NEQ>), grid, block, 0, S(stream), d, out, parity); break;
+  }
+  DUGKS_CHECK_LAUNCH();
+}
+int launch_get_phi(const InstDev* d, const InstDev& h, double* out, int parity, void* stream) {
+  return h.q == 9 ? get_phi_q<9>(d, h, out, parity, stream) : get_phi_q<5>(d, h, out, parity, stream);
+}
+
+template <int Q>
+static int get_f_q(const InstDev* d, const InstDev& h, double* out, int parity, long long step,
+                   void* stream) {
+  dim3 grid((h.nx + 255) / 256, h.ny), block(256);
+  switch (h.storage) {
+    case DUGKS_F64: hipLaunchKernelGGL((k_get_f<Q, DUGKS_F64>), grid, block, 0, S(stream), d, out, parity, step); break;
+    case DUGKS_F32: hipLaunchKernelGGL((k_get_f<Q, DUGKS_F32>), grid, block, 0, S(stream), d, out, parity, step); break;
+    case DUGKS_F16NEQ: hipLaunchKernelGGL((k_get_f<Q, DUGKS_F16NEQ>), grid, block, 0, S(stream), d, out, parity, step); break;
+    default: hipLaunchKernelGGL((k_get_f<Q, DUGKS_BF16NEQ>), grid, block, 0, S(stream), d, out, parity, step); break;
+  }
+  DUGKS_CHECK_LAUNCH();
+}
+int launch_get_f(const InstDev* d, const InstDev& h, double* out, int parity, long long step,
+                 void* stream) {
+  return h.q == 9 ? get_f_q<9>(d, h, out, parity, step, stream)
+                  : get_f_q<5>(d, h, out, parity, step, stream);
+}
+
+int reduce_partials() { return kRedBlocks; }
+
+template <int Q>
+static int reduce_q(const InstDev* d, const InstDev& h, const double* ref, int parity,
+                    const double* widths, double* partial, void* stream) {
+  dim3 grid(kRedBlocks), block(kRedThreads);
+  switch (h.storage) {
+    case DUGKS_F64: hipLaunchKernelGGL((k_reduce<Q, DUGKS_F64>), grid, block, 0, S(stream), d, ref, parity, widths, partial); break;
+    case DUGKS_F32: hipLaunchKernelGGL((k_reduce<Q, DUGKS_F32>), grid, block, 0, S(stream), d, ref, parity, widths, partial); break;
+    case DUGKS_F16NEQ: hipLaunchKernelGGL((k_reduce<Q, DUGKS_F16NEQ>), grid, block, 0, S(stream), d, ref, parity, widths, partial); break;
+    default: hipLaunchKernelGGL((k_reduce<Q, DUGKS_BF16NEQ>), grid, block, 0, S(stream), d, ref, parity, widths, partial); break;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+int launch_reduce_widths(const InstDev* d, const InstDev& h, const double* ref, int parity,
+                         const double* widths, double* partial, double* out, void* stream) {
+  int rc = h.q == 9 ? reduce_q<9>(d, h, ref, parity, widths, partial, stream)
+                    : reduce_q<5>(d, h, ref, parity, widths, partial, stream);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, S(stream), partial, kRedBlocks, out);
+  DUGKS_CHECK_LAUNCH();
+}
+
+int launch_fill_u32(unsigned* p, unsigned v, long long n, void* stream) {
+  if (n <= 0) return 0;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, S(stream), p, v, n);
+  DUGKS_CHECK_LAUNCH();
+}
+
+}  // namespace dugks
+
+namespace dugks {
+float neq_scale_host(float m) { return neq_scale(m); }
+}  // namespace dugks

@@ -342,3 +342,28 @@ def workload(name: str, **kw):
         "batch256": lambda: batch_problems(**kw),
     }
     return table[name]()
+
+
+def random_distributions(seed: int, q: int, ny: int, nx: int, mean: float = 0.5,
+                         amp: float = 0.05) -> np.ndarray:
+    """Seeded smooth distributions f~ [q][ny][nx] (any f~ is a valid step input).
+
+    Direction k gets mean * (weight-like share) plus a smooth seeded cosine field of
+    amplitude ``amp`` and a small cell-scale seeded noise (so that every
+    neighbour difference is exercised).
+    """
+    rng = np.random.default_rng(seed)
+    share = np.full(q, 1.0 / (2.0 * q))
+    share[0] = 0.5
+    share /= share.sum()
+    y = (np.arange(ny) + 0.5) / ny
+    x = (np.arange(nx) + 0.5) / nx
+    X, Y = np.meshgrid(x, y)
+    out = np.empty((q, ny, nx))
+    for k in range(q):
+        a, b, ph = rng.uniform(-1, 1), rng.uniform(-1, 1), rng.uniform(0, 2 * math.pi, size=2)
+        m, n = rng.integers(1, 4, size=2)
+        out[k] = mean * share[k] + amp * share[k] * (
+            a * np.cos(2 * math.pi * m * X + ph[0]) + b * np.cos(2 * math.pi * n * Y + ph[1]))
+        out[k] += 1e-3 * amp * rng.standard_normal((ny, nx))
+    return out

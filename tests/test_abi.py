@@ -1,0 +1,130 @@
+"""Host-only checks of the C ABI: the library loads, exports every function of
+include/dugks.h, and validates arguments without touching a device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1906_11036_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dugks.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dugks_[A-Za-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = header_functions()
+    for must in ("dugks_create", "dugks_bind", "dugks_set_B", "dugks_set_D", "dugks_set_source",
+                 "dugks_set_phi", "dugks_step", "dugks_get_phi", "dugks_batch_step"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.lib()
+    names = header_functions()
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(names) == set(L.SIGNATURES), set(names) ^ set(L.SIGNATURES)
+
+
+def _params(**kw):
+    p = L.Params()
+    p.abi_version = L.ABI_VERSION
+    p.storage = kw.get("storage", L.F64)
+    for i, b in enumerate(kw.get("bc", (0, 0, 0, 0))):
+        p.bc[i] = b
+    p.kernel = kw.get("kernel", L.KERNEL_FUSED)
+    p.c, p.cfl, p.alpha = kw.get("c", 1.0), kw.get("cfl", 0.5), kw.get("alpha", 1e-3)
+    return p
+
+
+def _create(nx=8, ny=6, q=9, xf=None, yf=None, **kw):
+    lib = L.lib()
+    xf = np.linspace(0, 1, nx + 1) if xf is None else np.asarray(xf, float)
+    yf = np.linspace(0, 1, ny + 1) if yf is None else np.asarray(yf, float)
+    h = C.c_void_p()
+    p = _params(**kw)
+    rc = lib.dugks_create(C.byref(h), nx, ny, xf.ctypes.data_as(C.POINTER(C.c_double)),
+                          yf.ctypes.data_as(C.POINTER(C.c_double)), q, C.byref(p))
+    return rc, h
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(cfl=1.0), L.E_ARG), (dict(cfl=0.0), L.E_ARG), (dict(alpha=0.0), L.E_ARG),
+    (dict(c=-1.0), L.E_ARG), (dict(nx=0), L.E_ARG), (dict(q=7), L.E_UNSUPPORTED),
+    (dict(storage=9), L.E_UNSUPPORTED), (dict(bc=(0, 1, 0, 0)), L.E_UNSUPPORTED),
+    (dict(bc=(1, 1, 2, 2)), L.E_UNSUPPORTED), (dict(kernel=L.KERNEL_PLAIN, storage=L.F32), L.E_UNSUPPORTED),
+    (dict(xf=[0, 0.5, 0.4, 1.0], nx=3), L.E_ARG),
+])
+def test_create_rejects_bad_arguments(kw, code):
+    rc, h = _create(**kw)
+    assert rc == code
+    assert L.lib().dugks_last_error(h).decode()
+    L.lib().dugks_destroy(h)
+
+
+def test_create_and_workspace_size():
+    lib = L.lib()
+    for storage, per in ((L.F64, 8 * 9), (L.F32, 4 * 9), (L.F16NEQ, 4 + 2 * 8), (L.BF16NEQ, 4 + 2 * 8)):
+        rc, h = _create(nx=100, ny=30, storage=storage)
+        assert rc == L.OK
+        n = lib.dugks_workspace_bytes(h)
+        assert n >= 2 * per * 128 * 30   # two buffers of padded rows
+        info = L.Info()
+        assert lib.dugks_get_info(h, C.byref(info)) == L.OK
+        assert info.pitch == 128 and info.state_bytes == per * 128 * 30
+        lib.dugks_destroy(h)
+
+
+def test_calls_before_bind_report_state_errors():
+    lib = L.lib()
+    rc, h = _create()
+    assert rc == L.OK
+    assert lib.dugks_step(h, 1) == L.E_STATE
+    assert lib.dugks_set_phi(h, None, 0) == L.E_STATE
+    assert lib.dugks_set_source(h, C.c_void_p(1)) == L.E_UNSUPPORTED
+    assert lib.dugks_set_source(h, None) == L.OK
+    assert lib.dugks_set_launch(h, 0, 4, 0, 1) == L.E_ARG
+    assert lib.dugks_set_launch(h, 32, 3, 0, 1) == L.E_ARG
+    assert lib.dugks_set_launch(h, 32, 2, 1, 0) == L.OK
+    n = C.c_size_t()
+    assert lib.dugks_checkpoint(h, None, C.byref(n)) == L.OK and n.value > 0
+    assert lib.dugks_restore(h, b"short", 5) == L.E_FORMAT
+    lib.dugks_destroy(h)
+
+
+def test_d2q5_accepts_only_identity_diffusion():
+    lib = L.lib()
+    rc, h = _create(q=5)
+    assert rc == L.OK
+    d = np.array([0.0, 1.0]); z = np.zeros(2)
+    P = C.POINTER(C.c_double)
+    assert lib.dugks_set_D(h, 1, d.ctypes.data_as(P), z.ctypes.data_as(P), d.ctypes.data_as(P)) == L.OK
+    d2 = np.array([0.0, 2.0])
+    assert lib.dugks_set_D(h, 1, d2.ctypes.data_as(P), z.ctypes.data_as(P), d.ctypes.data_as(P)) \
+        == L.E_UNSUPPORTED
+    lib.dugks_destroy(h)
+
+
+def test_degree_limits():
+    lib = L.lib()
+    rc, h = _create()
+    a = np.zeros(6)
+    P = C.POINTER(C.c_double)
+    assert lib.dugks_set_B(h, 5, a.ctypes.data_as(P), a.ctypes.data_as(P)) == L.E_ARG
+    assert lib.dugks_set_B(h, 4, a.ctypes.data_as(P), a.ctypes.data_as(P)) == L.OK
+    lib.dugks_destroy(h)
+
+
+def test_invalid_handles():
+    lib = L.lib()
+    assert lib.dugks_step(None, 1) == L.E_ARG
+    assert lib.dugks_last_error(None) == b"invalid handle"
+    lib.dugks_destroy(None)
