@@ -1,0 +1,191 @@
+"""Benchmark of the DUGKS hot path on one MI355X.
+
+Default workload: 256 independent NCDE instances (sizes log-uniform 64^2 ..
+1024^2, B = a (1,1) phi^2/2, D = phi I, alpha log-uniform, seeded Fourier
+initial fields, periodic, D2Q9) advanced together in binary32 storage, one
+launch per step.  A step is one DUGKS time step of every instance.
+
+Printed: one JSON line with MLUPS (whole job), the dominant kernel's achieved
+HBM bandwidth against the 8 TB/s peak (hipEvents on the launch stream), the
+binary64 plain-kernel and fused-kernel rates on the same batch, the relative
+L2 difference of the binary32 result from the binary64 one, and the CPU
+oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "DUGKS MLUPS & achieved HBM GB/s; FP32/batched vs plain FP64 at stated L2 err"
+PEAK_HBM_GBS = 8000.0
+BYTES_PER_UPDATE = {0: 144, 1: 72, 2: 40, 3: 40}   # D2Q9: read + write of the stored state
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="batch256",
+                    choices=["batch256", "gaussian_hill_4096", "burgers_512",
+                             "nonlinear_diffusion_1024", "gaussian_hill_128"])
+    ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16neq", "bf16neq"])
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--launch", default=None,
+                    help="fixed launch rows_per_wave,waves_per_block,schedule,xcd_remap (no autotune)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the binary64 comparison runs and the CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def make_problems(name):
+    from paper_1906_11036_amd import workloads as W
+    if name == "batch256":
+        return W.batch_problems()
+    return [W.workload(name)]
+
+
+def run_batch(problems, storage, steps, warmup, autotune=True, launch=None):
+    """Advance the batch; returns (batch, ms_total of the timed steps)."""
+    import torch
+
+    import paper_1906_11036_amd as dg
+    b = dg.Batch(problems, storage=storage, launch=launch)
+    b.set_all_phi()
+    if autotune:
+        b.autotune(3)
+    b.step(warmup)
+    torch.cuda.synchronize()
+    ms = b.time_steps(steps)   # hipEvents around the launches on the bound stream
+    torch.cuda.synchronize()
+    return b, ms
+
+
+def plain_fp64_rate(problems, steps):
+    """The plain one-cell-per-thread binary64 kernel, one instance at a time."""
+    import torch
+
+    import paper_1906_11036_amd as dg
+    total_ms, cells = 0.0, 0
+    for p in problems:
+        s = dg.Solver(p, storage="f64", kernel=dg.KERNEL_PLAIN)
+        s.set_phi(p.phi0)
+        s.step(2)
+        torch.cuda.synchronize()
+        total_ms += s.time_steps(steps)
+        cells += p.cells * steps
+        s.close()
+    return cells / (total_ms * 1e-3) / 1e6
+
+
+def cpu_baseline(seconds):
+    """The oracle as it stands, single thread, on one 512^2 batch-like instance."""
+    from oracle import Oracle
+    from paper_1906_11036_amd import workloads as W
+    p = W.batch_problems(count=1, nmin=512, nmax=512)[0]
+    o = Oracle(p)
+    o.step(1)
+    steps, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        o.step(5)
+        steps += 5
+    el = time.perf_counter() - t0
+    return {"value": p.cells * steps / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"one 512x512 periodic D2Q9 instance of the batch recipe (B = a(1,1)phi^2/2, "
+                      f"D = phi I), {steps} steps in {el:.1f} s, binary64, 1 thread"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "sharding of this path is a design note, not a built feature", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1906_11036_amd import _lib as L
+    storage = L.STORAGE[args.storage]
+    t_gen = time.perf_counter()
+    problems = make_problems(args.workload)
+    log(f"workload {args.workload}: {len(problems)} instance(s), "
+        f"{sum(p.cells for p in problems)} cells, generated in {time.perf_counter() - t_gen:.1f} s")
+
+    launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
+    autotune = not args.no_autotune and launch is None
+    torch.cuda.synchronize()
+    b, ms = run_batch(problems, storage, args.steps, args.warmup, autotune=autotune, launch=launch)
+    cells, state_bytes = b.totals()
+    info = b.info(0)
+    ms_step = ms / args.steps
+    mlups = cells * args.steps / (ms * 1e-3) / 1e6
+    alg_bytes = BYTES_PER_UPDATE[storage] * cells          # per launch (one launch per step)
+    achieved = alg_bytes / (ms_step * 1e-3) / 1e9
+    log(f"{args.storage}: {ms_step:.4f} ms/step, {mlups:.0f} MLUPS, {achieved:.0f} GB/s algorithmic "
+        f"(launch rows/wave={info['rows_per_wave']} waves/block={info['waves_per_block']} "
+        f"schedule={info['schedule']})")
+
+    extras = {}
+    if not args.no_extras:
+        # binary64 runs of the same batch for the L2 difference and the rate comparison
+        nsteps_total = args.warmup + args.steps
+        b64, ms64 = run_batch(problems, L.F64, args.steps, args.warmup, autotune=autotune,
+                              launch=launch)
+        fused64 = cells * args.steps / (ms64 * 1e-3) / 1e6
+        num = den = 0.0
+        for i in range(len(problems)):
+            a32, a64 = b.get_phi(i), b64.get_phi(i)
+            num += float(((a32 - a64) ** 2).sum())
+            den += float((a64 ** 2).sum())
+        l2 = math.sqrt(num / den)
+        del b64
+        torch.cuda.empty_cache()
+        log(f"f64 fused: {fused64:.0f} MLUPS; rel-L2(f32 vs f64) after {nsteps_total} steps {l2:.2e}")
+        plain64 = plain_fp64_rate(problems, max(2, min(args.steps, 20)))
+        log(f"f64 plain: {plain64:.0f} MLUPS")
+        extras = {"fp64_fused_mlups": round(fused64, 1), "fp64_plain_mlups": round(plain64, 1),
+                  "speedup_vs_plain_fp64": round(mlups / plain64, 2),
+                  "rel_l2_vs_fp64": l2, "rel_l2_after_steps": nsteps_total}
+
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32", "f16neq": "f16(neq)+f32", "bf16neq": "bf16(neq)+f32"}[args.storage],
+        "data": "synthetic",
+        "config": {"workload": args.workload, "instances": len(problems), "cells": cells,
+                   "lattice": "D2Q9", "storage": args.storage,
+                   "state_bytes": state_bytes, "rows_per_wave": info["rows_per_wave"],
+                   "waves_per_block": info["waves_per_block"], "schedule": info["schedule"]},
+        "hbm_gbps_algorithmic": round(achieved, 1),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None},
+    }
+    out.update(extras)
+    if not args.no_extras:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

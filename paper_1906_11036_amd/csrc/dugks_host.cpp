@@ -60,7 +60,7 @@ struct Instance {
 // coefficients of the face on the low side, the tangential factor and the
 // update factor.  See the header for the ghost geometry.
 static void axis_tables(const std::vector<double>& f, int bc, double h, double c, double dt,
-                        std::vector<double>& geo, std::vector<double>& widths) {
+                        double b3, std::vector<double>& geo, std::vector<double>& widths) {
   const int n = (int)f.size() - 1;
   std::vector<double> w(n + 2), xc(n + 2);  // index i+1 for cell i in -1..n
   for (int i = 0; i < n; ++i) {
@@ -83,7 +83,7 @@ static void axis_tables(const std::vector<double>& f, int bc, double h, double c
   for (int cc = 0; cc < n; ++cc) {
     double* g = &geo[(size_t)(cc + 1) * kGeo];
     g[3] = 0.5 * h * c / (xc[cc + 2] - xc[cc]);
-    g[4] = dt * c / w[cc + 1];
+    g[4] = dt * c / w[cc + 1] * b3;  // the kernels' fluxes are f_b / b3
   }
   widths.assign(w.begin() + 1, w.begin() + 1 + n);
 }
@@ -140,6 +140,10 @@ static int init_instance(Instance& in, int nx, int ny, const double* xf, const d
   in.xf.assign(xf, xf + nx + 1);
   in.yf.assign(yf, yf + ny + 1);
   in.pitch = ((nx + 63) / 64) * 64;
+  if ((size_t)ny * in.pitch * q * (p->storage == DUGKS_F64 ? 8 : 4) >= (size_t)1 << 32) {
+    err = "one instance's state must stay below 4 GiB";
+    return DUGKS_E_UNSUPPORTED;
+  }
   // constants (Sec. 2, Sec. 3)
   in.cs2 = p->c * p->c / 3.0;
   in.lambda = p->alpha / in.cs2;
@@ -160,8 +164,8 @@ static int init_instance(Instance& in, int nx, int ny, const double* xf, const d
   memset(in.bx, 0, sizeof(in.bx)); memset(in.by, 0, sizeof(in.by));
   memset(in.dxx, 0, sizeof(in.dxx)); memset(in.dxy, 0, sizeof(in.dxy)); memset(in.dyy, 0, sizeof(in.dyy));
   std::vector<double> wx, wy;
-  axis_tables(in.xf, in.bcx, in.h, p->c, in.dt, in.colgeo, wx);
-  axis_tables(in.yf, in.bcy, in.h, p->c, in.dt, in.rowgeo, wy);
+  axis_tables(in.xf, in.bcx, in.h, p->c, in.dt, in.b3, in.colgeo, wx);
+  axis_tables(in.yf, in.bcy, in.h, p->c, in.dt, in.b3, in.rowgeo, wy);
   in.widths = wx;
   in.widths.insert(in.widths.end(), wy.begin(), wy.end());
   in.colgeo_f.assign(in.colgeo.begin(), in.colgeo.end());
@@ -307,26 +311,27 @@ struct Engine {
       d.ring = in.ring;
       d.slots = (float*)(ws + in.off_slots);
       d.flags = (unsigned*)(ws + in.off_flags);
-      d.partial = (double*)(ws + off_partial);
       d.plane = (long long)in.ny * in.pitch;
+      d.buf_bytes = (unsigned)in.buffer_bytes(storage);
       d.nx = in.nx; d.ny = in.ny; d.pitch = in.pitch; d.q = in.q;
       d.bcx = in.bcx; d.bcy = in.bcy;
       d.ring_len = 2 * (in.nx + in.ny) + 4;
       d.ring_steps = in.ring_steps;
       d.ncoef = in.ncoef;
       d.storage = storage;
-      d.a1 = in.a1; d.a2 = in.a2; d.a3 = in.a3; d.b1 = in.b1; d.b2 = in.b2; d.b3 = in.b3;
-      d.dt = in.dt; d.inv_cs2 = 1.0 / in.cs2;
-      d.a1f = (float)in.a1; d.a2f = (float)in.a2; d.a3f = (float)in.a3;
-      // coefficients padded with zeros up to the launch's polynomial length
+      d.ra = in.a1 / in.b1;
+      d.rb = in.a3 * in.b1 / in.b3;
+      d.b1 = in.b1;
+      d.inv_b1 = 1.0 / in.b1;
+      d.kg = 4.0 / 3.0 * in.b1;
+      d.a2 = in.a2;
+      d.opra = 1.0 + d.ra;
+      d.raf = (float)d.ra; d.rbf = (float)d.rb; d.b1f = (float)d.b1; d.inv_b1f = (float)d.inv_b1;
+      d.kgf = (float)d.kg; d.a2f = (float)d.a2; d.oepraf = (float)d.opra; d.a1f = (float)in.a1;
       for (int i = 0; i < in.q; ++i)
         for (int m = 0; m < kMaxCoef; ++m) {
           d.e[i][m] = in.e[i][m];
-          d.p1[i][m] = in.b1 * in.e[i][m];
-          d.p3[i][m] = in.b3 * in.e[i][m];
           d.ef[i][m] = (float)d.e[i][m];
-          d.p1f[i][m] = (float)d.p1[i][m];
-          d.p3f[i][m] = (float)d.p3[i][m];
         }
     }
   }

@@ -22,6 +22,14 @@ constexpr int kStripCols = 62;  // ... of which 62 are updated; lanes 0 and 63 a
 constexpr int kGeo = 5;         // per column / row: alpha(-), alpha(0), alpha(+), tau, k
 
 // Per-instance constants and pointers, read by the kernels with scalar loads.
+//
+// The step works with scaled distributions so that one set of polynomial
+// coefficients (those of E_i) serves the cell and the face:
+//   g = fbar+ / b1 = (a1/b1) f~ + E(phi)                       (eq. 2.21 over b1)
+//   f~+ = (4/3) b1 g - f~ / 3                                  (eq. 2.23)
+//   phi_b = b1 sum_i gbar_i                                    (gbar = face value of g)
+//   F = f_b / b3 = (a3 b1 / b3) gbar + E(phi_b)                (eq. 2.22 over b3)
+// and the update factor of each column / row carries the b3 back.
 struct alignas(64) InstDev {
   void* buf[2];            // ping-pong f~ buffers
   const double* colgeo;    // (nx+2) x kGeo doubles, column c = -1..nx at [(c+1)*kGeo]
@@ -31,23 +39,18 @@ struct alignas(64) InstDev {
   const double* ring;      // Dirichlet data, ring_steps x ring_len (or null)
   float* slots;            // 16-bit storage: 4 max|f~ - E| slots (unscaled)
   unsigned* flags;         // DUGKS_FLAG_* bits, sticky
-  double* partial;         // reduction partials of this instance (set per launch)
   long long plane;         // elements per plane = ny * pitch
+  unsigned buf_bytes;      // bytes of one buffer (< 4 GiB, the buffer resource range)
   int nx, ny, pitch, q;
   int bcx, bcy;            // DUGKS_BC_* per axis
   int ring_len, ring_steps;
   int ncoef;               // number of used polynomial coefficients (degree + 1)
   int storage;
-  double a1, a2, a3, b1, b2, b3, dt, inv_cs2;
-  float a1f, a2f, a3f;
-  float pad_f;
-  // E_i(phi) = sum_k e[i][k] phi^k ; p1 = b1 e (eq. 2.21) ; p3 = b3 e (eq. 2.22)
+  double ra, rb, b1, inv_b1, kg, a2, opra;     // a1/b1, a3 b1/b3, b1, 1/b1, 4/3 b1, a2, 1 + a1/b1
+  float raf, rbf, b1f, inv_b1f, kgf, a2f, oepraf, a1f;
+  // E_i(phi) = sum_k e[i][k] phi^k  (eq. 2.3 with C = int_0^phi B'B'^T)
   double e[kMaxQ][kMaxCoef];
-  double p1[kMaxQ][kMaxCoef];
-  double p3[kMaxQ][kMaxCoef];
   float ef[kMaxQ][kMaxCoef];
-  float p1f[kMaxQ][kMaxCoef];
-  float p3f[kMaxQ][kMaxCoef];
 };
 
 // One unit of work: instance, first interior column of the strip, row range.

@@ -22,9 +22,16 @@
 
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "dugks_internal.h"
 
 namespace dugks {
+
+#ifndef DUGKS_PREFETCH
+#define DUGKS_PREFETCH 1
+#endif
+constexpr int kPrefetch = DUGKS_PREFETCH;  // rows loaded ahead of the row being consumed
 
 // ------------------------------------------------------------------ lattice
 // D2Q9 of eq. 2.5 (integer components; velocities are c times these).
@@ -88,24 +95,24 @@ __host__ __device__ inline float neq_scale(float m) {
 
 // ------------------------------------------------------------ DPP helpers
 // wave_shr:1 -> lane l receives lane l-1; wave_shl:1 -> lane l receives lane l+1.
+// Lanes without a source (0 for shr, 63 for shl) read 0 (bound_ctrl); their
+// results are never used.
 __device__ __forceinline__ float shr1(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
-                                                               0x138, 0xF, 0xF, false));
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x138, 0xF, 0xF, true));
 }
 __device__ __forceinline__ float shl1(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
-                                                               0x130, 0xF, 0xF, false));
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xF, 0xF, true));
 }
 __device__ __forceinline__ double shr1(double v) {
   int2 p = __builtin_bit_cast(int2, v);
-  p.x = __builtin_amdgcn_update_dpp(0, p.x, 0x138, 0xF, 0xF, false);
-  p.y = __builtin_amdgcn_update_dpp(0, p.y, 0x138, 0xF, 0xF, false);
+  p.x = __builtin_amdgcn_mov_dpp(p.x, 0x138, 0xF, 0xF, true);
+  p.y = __builtin_amdgcn_mov_dpp(p.y, 0x138, 0xF, 0xF, true);
   return __builtin_bit_cast(double, p);
 }
 __device__ __forceinline__ double shl1(double v) {
   int2 p = __builtin_bit_cast(int2, v);
-  p.x = __builtin_amdgcn_update_dpp(0, p.x, 0x130, 0xF, 0xF, false);
-  p.y = __builtin_amdgcn_update_dpp(0, p.y, 0x130, 0xF, 0xF, false);
+  p.x = __builtin_amdgcn_mov_dpp(p.x, 0x130, 0xF, 0xF, true);
+  p.y = __builtin_amdgcn_mov_dpp(p.y, 0x130, 0xF, 0xF, true);
   return __builtin_bit_cast(double, p);
 }
 
@@ -113,19 +120,21 @@ __device__ __forceinline__ double shl1(double v) {
 template <typename T> struct Coef;
 template <> struct Coef<double> {
   __device__ static const double* e(const InstDev* I, int k) { return I->e[k]; }
-  __device__ static const double* p1(const InstDev* I, int k) { return I->p1[k]; }
-  __device__ static const double* p3(const InstDev* I, int k) { return I->p3[k]; }
-  __device__ static double a1(const InstDev* I) { return I->a1; }
-  __device__ static double a3(const InstDev* I) { return I->a3; }
+  __device__ static double ra(const InstDev* I) { return I->ra; }
+  __device__ static double rb(const InstDev* I) { return I->rb; }
+  __device__ static double b1(const InstDev* I) { return I->b1; }
+  __device__ static double inv_b1(const InstDev* I) { return I->inv_b1; }
+  __device__ static double kg(const InstDev* I) { return I->kg; }
   __device__ static const double* col(const InstDev* I) { return I->colgeo; }
   __device__ static const double* row(const InstDev* I) { return I->rowgeo; }
 };
 template <> struct Coef<float> {
   __device__ static const float* e(const InstDev* I, int k) { return I->ef[k]; }
-  __device__ static const float* p1(const InstDev* I, int k) { return I->p1f[k]; }
-  __device__ static const float* p3(const InstDev* I, int k) { return I->p3f[k]; }
-  __device__ static float a1(const InstDev* I) { return I->a1f; }
-  __device__ static float a3(const InstDev* I) { return I->a3f; }
+  __device__ static float ra(const InstDev* I) { return I->raf; }
+  __device__ static float rb(const InstDev* I) { return I->rbf; }
+  __device__ static float b1(const InstDev* I) { return I->b1f; }
+  __device__ static float inv_b1(const InstDev* I) { return I->inv_b1f; }
+  __device__ static float kg(const InstDev* I) { return I->kgf; }
   __device__ static const float* col(const InstDev* I) { return I->colgeo_f; }
   __device__ static const float* row(const InstDev* I) { return I->rowgeo_f; }
 };
@@ -138,7 +147,7 @@ template <int NC, typename T> __device__ __forceinline__ T horner(const T* c, T 
   return r;
 }
 
-// ------------------------------------------------------------- cell state
+// ------------------------------------------------------------ memory
 // Raw stored values of one cell.
 template <int Q, int ST> struct Raw;
 template <int Q> struct Raw<Q, DUGKS_F64> { double v[Q]; };
@@ -146,22 +155,52 @@ template <int Q> struct Raw<Q, DUGKS_F32> { float v[Q]; };
 template <int Q> struct Raw<Q, DUGKS_F16NEQ> { float phi; uint16_t g[Q - 1]; };
 template <int Q> struct Raw<Q, DUGKS_BF16NEQ> { float phi; uint16_t g[Q - 1]; };
 
+typedef unsigned v2u __attribute__((ext_vector_type(2)));
+
+// Buffer resource over one f~ buffer: the per-lane byte offset goes in a VGPR,
+// the plane offset in an SGPR; accesses outside [0, bytes) read 0 / are dropped.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+template <int Q, int ST>
+__device__ __forceinline__ void load_raw_buf(Raw<Q, ST>& r, __amdgpu_buffer_rsrc_t R, unsigned plane,
+                                             unsigned idx) {
+  if constexpr (ST == DUGKS_F64) {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      const unsigned soff = (unsigned)k * plane * 8u;
+      r.v[k] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(R, idx * 8u, soff, 0));
+    }
+  } else if constexpr (ST == DUGKS_F32) {
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+      r.v[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(R, idx * 4u, (unsigned)k * plane * 4u, 0));
+  } else {
+    r.phi = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(R, idx * 4u, 0u, 0));
+#pragma unroll
+    for (int k = 0; k < Q - 1; ++k)
+      r.g[k] = __builtin_amdgcn_raw_buffer_load_b16(R, idx * 2u, plane * 4u + (unsigned)k * plane * 2u, 0);
+  }
+}
+
+// Pointer-based loads (the plain kernel).
 template <int Q, int ST>
 __device__ __forceinline__ void load_raw(Raw<Q, ST>& r, const char* buf, long long plane,
                                          long long off) {
   if constexpr (ST == DUGKS_F64) {
     const double* b = (const double*)buf;
 #pragma unroll
-    for (int k = 0; k < Q; ++k) r.v[k] = __builtin_nontemporal_load(b + k * plane + off);
+    for (int k = 0; k < Q; ++k) r.v[k] = b[k * plane + off];
   } else if constexpr (ST == DUGKS_F32) {
     const float* b = (const float*)buf;
 #pragma unroll
-    for (int k = 0; k < Q; ++k) r.v[k] = __builtin_nontemporal_load(b + k * plane + off);
+    for (int k = 0; k < Q; ++k) r.v[k] = b[k * plane + off];
   } else {
-    r.phi = __builtin_nontemporal_load((const float*)buf + off);
+    r.phi = ((const float*)buf)[off];
     const uint16_t* g = (const uint16_t*)(buf + 4 * plane);
 #pragma unroll
-    for (int k = 0; k < Q - 1; ++k) r.g[k] = __builtin_nontemporal_load(g + k * plane + off);
+    for (int k = 0; k < Q - 1; ++k) r.g[k] = g[k * plane + off];
   }
 }
 
@@ -171,14 +210,12 @@ struct Scales {
   float out;     // s of the output buffer
 };
 
-// fbar+ (eq. 2.21) of the source cell, and f~+ (eq. 2.23) when wanted.
-// Also returns f~ - E (a1 times it is the non-equilibrium part of fbar+),
-// needed only by Dirichlet ghosts.
+// g = fbar+ / b1 (eq. 2.21) of the source cell and f~+ (eq. 2.23) when wanted.
 template <int Q, int ST, int NC>
-__device__ __forceinline__ void cell_values(const InstDev* __restrict__ I, const Raw<Q, ST>& r,
-                                            const Scales& sc, typename Stor<ST>::T* fb,
-                                            typename Stor<ST>::T* ftp, bool want_ftp,
-                                            typename Stor<ST>::T& phi_out) {
+__device__ __forceinline__ void cell_g(const InstDev* __restrict__ I, const Raw<Q, ST>& r,
+                                       const Scales& sc, typename Stor<ST>::T* g,
+                                       typename Stor<ST>::T* ftp, bool want_ftp,
+                                       typename Stor<ST>::T& phi_out) {
   using T = typename Stor<ST>::T;
   using C = Coef<T>;
   if constexpr (!Stor<ST>::neq) {
@@ -186,62 +223,64 @@ __device__ __forceinline__ void cell_values(const InstDev* __restrict__ I, const
 #pragma unroll
     for (int k = 0; k < Q; ++k) phi += (double)r.v[k];
     const T p = (T)phi;
-    const T a1 = C::a1(I);
+    const T ra = C::ra(I);
 #pragma unroll
-    for (int k = 0; k < Q; ++k) fb[k] = fma(a1, r.v[k], horner<NC>(C::p1(I, k), p));
+    for (int k = 0; k < Q; ++k) g[k] = fma(ra, r.v[k], horner<NC>(C::e(I, k), p));
     if (want_ftp) {
+      const T kg = C::kg(I);
 #pragma unroll
-      for (int k = 0; k < Q; ++k) ftp[k] = fma((T)(4.0 / 3.0), fb[k], (T)(-1.0 / 3.0) * r.v[k]);
+      for (int k = 0; k < Q; ++k) ftp[k] = fma(kg, g[k], (T)(-1.0 / 3.0) * r.v[k]);
     }
     phi_out = p;
   } else {
     const float p = r.phi;
-    float g[Q];
-    float gs = 0.0f;
+    float gs[Q];
+    float sum = 0.0f;
 #pragma unroll
     for (int k = 1; k < Q; ++k) {
-      g[k] = g_to_f32<ST>(r.g[k - 1]);
-      gs += g[k];
+      gs[k] = g_to_f32<ST>(r.g[k - 1]);
+      sum += gs[k];
     }
-    g[0] = -gs;
-    const float a1s = I->a1f * sc.inv_in, a2s = I->a2f * sc.inv_in;
+    gs[0] = -sum;
+    // f~ = E + gs / s:  g = (1 + ra) E + ra gs / s,  f~+ = E + a2 gs / s
+    const float ras = I->raf * sc.inv_in, a2s = I->a2f * sc.inv_in, opra = I->oepraf;
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
       const float E = horner<NC>(I->ef[k], p);
-      fb[k] = fma(a1s, g[k], E);
-      if (want_ftp) ftp[k] = fma(a2s, g[k], E);
+      g[k] = fma(ras, gs[k], opra * E);
+      if (want_ftp) ftp[k] = fma(a2s, gs[k], E);
     }
     phi_out = p;
   }
 }
 
-// Ghost rules applied to fbar+ of the source cell a (already in fb).
+// Ghost rules on g of the source cell a (already in g).
 template <int Q, int ST, int NC>
-__device__ __forceinline__ void apply_ghost(const InstDev* __restrict__ I, typename Stor<ST>::T* fb,
-                                            typename Stor<ST>::T phi_a, bool wall_x, bool wall_y,
-                                            double phi_g) {
+__device__ __forceinline__ void ghost_g(const InstDev* __restrict__ I, typename Stor<ST>::T* g,
+                                        typename Stor<ST>::T phi_a, bool wall_x, bool wall_y,
+                                        double phi_g) {
   using T = typename Stor<ST>::T;
   using C = Coef<T>;
   const bool dir = (wall_x && I->bcx == DUGKS_BC_DIRICHLET) || (wall_y && I->bcy == DUGKS_BC_DIRICHLET);
   if (dir) {
     // non-equilibrium extrapolation: fbar+_g = E(phi_g) + (fbar+_a - E(phi_a))
-    const T pg = (T)phi_g;
+    const T pg = (T)phi_g, ib = C::inv_b1(I);
 #pragma unroll
     for (int k = 0; k < Q; ++k)
-      fb[k] = horner<NC>(C::e(I, k), pg) + (fb[k] - horner<NC>(C::e(I, k), phi_a));
+      g[k] = fma(horner<NC>(C::e(I, k), pg) - horner<NC>(C::e(I, k), phi_a), ib, g[k]);
   } else {
     T t[Q];
     if (wall_x) {
 #pragma unroll
-      for (int k = 0; k < Q; ++k) t[k] = fb[mir_x(k)];
+      for (int k = 0; k < Q; ++k) t[k] = g[mir_x(k)];
 #pragma unroll
-      for (int k = 0; k < Q; ++k) fb[k] = t[k];
+      for (int k = 0; k < Q; ++k) g[k] = t[k];
     }
     if (wall_y) {
 #pragma unroll
-      for (int k = 0; k < Q; ++k) t[k] = fb[mir_y(k)];
+      for (int k = 0; k < Q; ++k) t[k] = g[mir_y(k)];
 #pragma unroll
-      for (int k = 0; k < Q; ++k) fb[k] = t[k];
+      for (int k = 0; k < Q; ++k) g[k] = t[k];
     }
   }
 }
@@ -262,31 +301,33 @@ __device__ __forceinline__ int src_index(int i, int n, int bc) {
   return i < 0 ? 0 : n - 1;
 }
 
-// Half-step interface distribution (eqs. 2.20, 2.19/2.26), interface phi,
-// f_b = a3 fbar_b + b3 E(phi_b) (eq. 2.22) for directions with a normal
-// velocity component.  NRM / TAN select the axis: NRM = 0 for x-faces.
+// Half-step interface distribution (eq. 2.20, eq. 2.19 in the form of eq.
+// 2.26) on g, the interface phi, and F = f_b / b3 (eq. 2.22) for directions
+// with a normal velocity component.  ts[k] = dL + dR, the sum of the two
+// cells' central-difference numerators along the face (directions with a
+// tangential component).  NRM = 0 for x-faces, 1 for y-faces.
 template <int Q, int NC, int NRM, typename T>
 __device__ __forceinline__ void face(const InstDev* __restrict__ I, const T* L, const T* R,
-                                     const T* dL, const T* dR, T am, T a0, T ap, T tau, T* out) {
+                                     const T* ts, T am, T a0, T ap, T tau, T* out) {
   using C = Coef<T>;
-  T fbb[Q];
-  double phib = 0.0;
+  T gb[Q];
+  double sum = 0.0;
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
     const int cn = NRM == 0 ? lat_cx(k) : lat_cy(k);
     const int ct = NRM == 0 ? lat_cy(k) : lat_cx(k);
     const T al = cn > 0 ? ap : (cn < 0 ? am : a0);
     T v = fma(al, R[k] - L[k], L[k]);
-    if (ct != 0) v = fma((T)(-ct) * tau, dL[k] + dR[k], v);
-    fbb[k] = v;
-    phib += (double)v;  // phi(x_b, t + h) = sum_i fbar_i
+    if (ct != 0) v = fma((T)(-ct) * tau, ts[k], v);
+    gb[k] = v;
+    sum += (double)v;  // phi(x_b, t + h) = sum_i fbar_i = b1 sum_i gbar_i
   }
-  const T pb = (T)phib;
-  const T a3 = C::a3(I);
+  const T pb = (T)(sum * (double)C::b1(I));
+  const T rb = C::rb(I);
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
     const int cn = NRM == 0 ? lat_cx(k) : lat_cy(k);
-    if (cn != 0) out[k] = fma(a3, fbb[k], horner<NC>(C::p3(I, k), pb));
+    if (cn != 0) out[k] = fma(rb, gb[k], horner<NC>(C::e(I, k), pb));
   }
 }
 
@@ -299,15 +340,17 @@ __device__ __forceinline__ int xcd_logical(int b, int nblocks) {
 }
 
 // ---------------------------------------------------------- fused step
-template <int Q, int ST, int NC>
+// GH: the item touches a wall (ghost rules needed); items that do not use a
+// branch-free row computation.
+template <int Q, int ST, int NC, bool GH>
 __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const WorkItem it,
                                           int parity, long long step, int lane, bool measure) {
   using T = typename Stor<ST>::T;
   using C = Coef<T>;
   const int nx = I->nx, ny = I->ny, pitch = I->pitch, bcx = I->bcx, bcy = I->bcy;
-  const long long plane = I->plane;
-  const char* in = (const char*)I->buf[parity];
-  char* out = (char*)I->buf[parity ^ 1];
+  const unsigned plane = (unsigned)I->plane;
+  const __amdgpu_buffer_rsrc_t Rin = rsrc(I->buf[parity], I->buf_bytes);
+  const __amdgpu_buffer_rsrc_t Rout = rsrc(I->buf[parity ^ 1], I->buf_bytes);
 
   Scales sc{1.0f, 1.0f};
   if constexpr (Stor<ST>::neq) {
@@ -328,88 +371,106 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
 
   const double* ring = (I->ring != nullptr) ? I->ring + step * I->ring_len : nullptr;
 
-  auto make_row = [&](const Raw<Q, ST>& raw, int r, T* fb, T* ftp, bool want_ftp) {
+  auto make_row = [&](const Raw<Q, ST>& raw, int r, T* g, T* ftp, bool want_ftp) {
     T phi_a;
-    cell_values<Q, ST, NC>(I, raw, sc, fb, ftp, want_ftp, phi_a);
+    cell_g<Q, ST, NC>(I, raw, sc, g, ftp, want_ftp, phi_a);
+    if constexpr (!GH) return;
     const bool wall_y = (r < 0 || r >= ny) && bcy != DUGKS_BC_PERIODIC;
     if (wall_y || strip_touches_x_wall) {
       if (wall_x || wall_y) {
         double pg = 0.0;
         if (ring != nullptr) pg = ring[ring_index(nx, ny, c < -1 ? -1 : (c > nx ? nx : c), r)];
-        apply_ghost<Q, ST, NC>(I, fb, phi_a, wall_x, wall_y, pg);
+        ghost_g<Q, ST, NC>(I, g, phi_a, wall_x, wall_y, pg);
       }
     }
   };
-  auto row_off = [&](int r) -> long long {
-    return (long long)src_index(r, ny, bcy) * pitch + sc_col;
-  };
-  auto sigma_x = [&](const T* fb, T* sx) {
-#pragma unroll
-    for (int k = 0; k < Q; ++k)
-      if (lat_cx(k) != 0) sx[k] = shl1(fb[k]) - shr1(fb[k]);
+  auto row_idx = [&](int r) -> unsigned {
+    return (unsigned)(src_index(r, ny, bcy) * pitch + sc_col);
   };
 
   const int y0 = it.y0, y1 = it.y1;
-  T fbm[Q], fb0[Q], fbp[Q], ftp0[Q], ftp1[Q], sxm[Q], sx0[Q], sxp[Q], fS[Q], fN[Q], fW[Q], fE[Q],
-      dy[Q], dL[Q], Lv[Q];
-  Raw<Q, ST> ra, rb;
+  // Per-row values live in slot (row - y0) % 3: g (G), g of lane-1 (LS), f~+
+  // (FT), x-slope numerators (SX), the face above the row (FY) and the raw
+  // loads (RW).  The loop is unrolled three times so that rotating the window
+  // is a change of register names, not a copy.
+  T G[3][Q], LS[3][Q], FT[3][Q], SX[3][Q], FY[3][Q], ts[Q], dy[Q], fW[Q];
+  Raw<Q, ST> RW[3];
 
-  // prologue: rows y0-1 and y0, the face below row y0
-  load_raw<Q, ST>(ra, in, plane, row_off(y0 - 1));
-  load_raw<Q, ST>(rb, in, plane, row_off(y0));
-  make_row(ra, y0 - 1, fbm, ftp1, false);
-  make_row(rb, y0, fb0, ftp0, true);
-  load_raw<Q, ST>(ra, in, plane, row_off(y0 + 1));
-  sigma_x(fbm, sxm);
-  sigma_x(fb0, sx0);
+  // prologue: row y0-1 in slot 2, row y0 in slot 0, the face below row y0 in FY[2]
+  load_raw_buf<Q, ST>(RW[2], Rin, plane, row_idx(y0 - 1));
+  load_raw_buf<Q, ST>(RW[0], Rin, plane, row_idx(y0));
+  load_raw_buf<Q, ST>(RW[1], Rin, plane, row_idx(y0 + 1));
+  make_row(RW[2], y0 - 1, G[2], FT[2], false);
+  make_row(RW[0], y0, G[0], FT[0], true);
+  if constexpr (kPrefetch == 2)  // two rows in flight ahead of the row being consumed
+    load_raw_buf<Q, ST>(RW[2], Rin, plane, row_idx(y0 + 2 <= y1 ? y0 + 2 : y1));
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    LS[0][k] = shr1(G[0][k]);
+    if (lat_cx(k) != 0) {
+      SX[0][k] = shl1(G[0][k]) - LS[0][k];
+      ts[k] = (shl1(G[2][k]) - shr1(G[2][k])) + SX[0][k];
+    }
+  }
   {
     const T* g = rg + (long long)(y0 + 1) * kGeo;
-    face<Q, NC, 1>(I, fbm, fb0, sxm, sx0, g[0], g[1], g[2], ctau, fS);
+    face<Q, NC, 1>(I, G[2], G[0], ts, g[0], g[1], g[2], ctau, FY[2]);
   }
 
   bool bad = false, ovf = false;
   float mx = 0.0f;
-  for (int j = y0; j < y1; ++j) {
-    // row j+1 (already loaded into ra); prefetch row j+2
-    Raw<Q, ST> rc = ra;
-    if (j + 2 <= y1) load_raw<Q, ST>(ra, in, plane, row_off(j + 2));
-    make_row(rc, j + 1, fbp, ftp1, true);
+  auto body = [&](int j, auto slot) {
+    constexpr int s0 = decltype(slot)::value, sp = (s0 + 1) % 3, sm = (s0 + 2) % 3;
+    // row j+1 is in RW[sp]; the next load goes kPrefetch rows further
+    if constexpr (kPrefetch == 2)
+      load_raw_buf<Q, ST>(RW[s0], Rin, plane, row_idx(j + 3 <= y1 ? j + 3 : y1));
+    else
+      load_raw_buf<Q, ST>(RW[sm], Rin, plane, row_idx(j + 2 <= y1 ? j + 2 : y1));
+    make_row(RW[sp], j + 1, G[sp], FT[sp], true);
     const T* gj = rg + (long long)(j + 1) * kGeo;   // row j: its S face and factors
     const T* gn = rg + (long long)(j + 2) * kGeo;   // row j+1: S face = N face of row j
     const T rtau = gj[3], rk = gj[4];
-    // central differences along y at row j (numerators of the y-slopes)
-#pragma unroll
-    for (int k = 0; k < Q; ++k)
-      if (lat_cy(k) != 0) dy[k] = fbp[k] - fbm[k];
-    sigma_x(fbp, sxp);
-    face<Q, NC, 1>(I, fb0, fbp, sx0, sxp, gn[0], gn[1], gn[2], ctau, fN);
-    // west face of this lane's cell: left state from lane-1
+    // x-slope numerators of row j+1: g(lane+1) - g(lane-1)
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-      Lv[k] = shr1(fb0[k]);
-      if (lat_cy(k) != 0) dL[k] = shr1(dy[k]);
+      LS[sp][k] = shr1(G[sp][k]);
+      if (lat_cx(k) != 0) {
+        SX[sp][k] = shl1(G[sp][k]) - LS[sp][k];
+        ts[k] = SX[s0][k] + SX[sp][k];
+      }
     }
-    face<Q, NC, 0>(I, Lv, fb0, dL, dy, cam, ca0, cap, rtau, fW);
+    face<Q, NC, 1>(I, G[s0], G[sp], ts, gn[0], gn[1], gn[2], ctau, FY[s0]);
+    // west face of this lane's cell: left state from lane-1; y-slope numerators
 #pragma unroll
     for (int k = 0; k < Q; ++k)
-      if (lat_cx(k) != 0) fE[k] = shl1(fW[k]);
+      if (lat_cy(k) != 0) {
+        dy[k] = G[sp][k] - G[sm][k];
+        ts[k] = shr1(dy[k]) + dy[k];
+      }
+    face<Q, NC, 0>(I, LS[s0], G[s0], ts, cam, ca0, cap, rtau, fW);
     // update (eq. 2.24): f~(t+dt) = f~+ - dt c_i.(flux differences)/width
     T o[Q];
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-      T v = ftp0[k];
-      if (lat_cx(k) != 0) v = fma((T)(-lat_cx(k)) * ck, fE[k] - fW[k], v);
-      if (lat_cy(k) != 0) v = fma((T)(-lat_cy(k)) * rk, fN[k] - fS[k], v);
+      T v = FT[s0][k];
+      if (lat_cx(k) != 0) v = fma((T)(-lat_cx(k)) * ck, shl1(fW[k]) - fW[k], v);
+      if (lat_cy(k) != 0) v = fma((T)(-lat_cy(k)) * rk, FY[s0][k] - FY[sm][k], v);
       o[k] = v;
     }
     if (live) {
-      const long long off = (long long)j * pitch + c;
+      const unsigned idx = (unsigned)(j * pitch + c);
       if constexpr (!Stor<ST>::neq) {
         bad |= !__builtin_isfinite(o[0]);
-        T* ob = (T*)out;
         if (!measure) {
 #pragma unroll
-          for (int k = 0; k < Q; ++k) __builtin_nontemporal_store(o[k], ob + k * plane + off);
+          for (int k = 0; k < Q; ++k) {
+            if constexpr (ST == DUGKS_F64)
+              __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, o[k]), Rout, idx * 8u,
+                                                    (unsigned)k * plane * 8u, 0);
+            else
+              __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, o[k]), Rout, idx * 4u,
+                                                    (unsigned)k * plane * 4u, 0);
+          }
         }
       } else {
         double ps = 0.0;
@@ -434,23 +495,25 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
         }
         mx = fmaxf(mx, m);
         if (!measure) {
-          __builtin_nontemporal_store(pf, (float*)out + off);
-          uint16_t* gb = (uint16_t*)(out + 4 * plane);
+          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, pf), Rout, idx * 4u, 0u, 0);
 #pragma unroll
-          for (int k = 0; k < Q - 1; ++k) __builtin_nontemporal_store(gq[k], gb + k * plane + off);
+          for (int k = 0; k < Q - 1; ++k)
+            __builtin_amdgcn_raw_buffer_store_b16(gq[k], Rout, idx * 2u, plane * 4u + (unsigned)k * plane * 2u, 0);
         }
       }
     }
-    // rotate the window
-#pragma unroll
-    for (int k = 0; k < Q; ++k) {
-      fbm[k] = fb0[k];
-      fb0[k] = fbp[k];
-      ftp0[k] = ftp1[k];
-      if (lat_cx(k) != 0) sx0[k] = sxp[k];
-      if (lat_cy(k) != 0) fS[k] = fN[k];
-    }
+  };
+  using S0 = std::integral_constant<int, 0>;
+  using S1 = std::integral_constant<int, 1>;
+  using S2 = std::integral_constant<int, 2>;
+  int j = y0;
+  for (; j + 3 <= y1; j += 3) {
+    body(j, S0{});
+    body(j + 1, S1{});
+    body(j + 2, S2{});
   }
+  if (j < y1) body(j, S0{});
+  if (j + 1 < y1) body(j + 1, S1{});
   if constexpr (Stor<ST>::neq) {
     // wave maximum of |f~ - E| over updated cells -> the instance's slot
 #pragma unroll
@@ -464,8 +527,21 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
   if (__any(ovf) && lane == 0) atomicOr(I->flags, (unsigned)DUGKS_FLAG_OVERFLOW);
 }
 
+// Occupancy target of the step kernel (waves per SIMD): bounds the register
+// allocation so that enough waves stay resident to hide HBM latency.
+#ifndef DUGKS_WAVES_PER_EU_F32
+#define DUGKS_WAVES_PER_EU_F32 2
+#endif
+#ifndef DUGKS_WAVES_PER_EU_F64
+#define DUGKS_WAVES_PER_EU_F64 1
+#endif
+template <int ST> struct Occupancy {
+  static constexpr int value = ST == DUGKS_F64 ? DUGKS_WAVES_PER_EU_F64 : DUGKS_WAVES_PER_EU_F32;
+};
+
 template <int Q, int ST, int NC>
-__global__ __launch_bounds__(256) void k_step(const InstDev* __restrict__ insts,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occupancy<ST>::value)))
+void k_step(const InstDev* __restrict__ insts,
                                               const WorkItem* __restrict__ items, int nitems,
                                               int parity, long long step, int xcd_remap,
                                               int persistent, int measure) {
@@ -478,13 +554,17 @@ __global__ __launch_bounds__(256) void k_step(const InstDev* __restrict__ insts,
   for (; item < nitems; item += stride) {
     const WorkItem it = items[item];
     const InstDev* I = insts + it.inst;
-    step_item<Q, ST, NC>(I, it, parity, step, lane, measure != 0);
+    const bool wall_x = I->bcx != DUGKS_BC_PERIODIC && (it.x0 == 0 || it.x0 + kStripCols >= I->nx);
+    const bool wall_y = I->bcy != DUGKS_BC_PERIODIC && (it.y0 == 0 || it.y1 == I->ny);
+    if (wall_x || wall_y)
+      step_item<Q, ST, NC, true>(I, it, parity, step, lane, measure != 0);
+    else
+      step_item<Q, ST, NC, false>(I, it, parity, step, lane, measure != 0);
     if (!persistent) break;
   }
 }
 
-// Clear slot (step+1)&3 of every instance before a 16-bit step: that slot
-// collects the maximum of the next step's output.
+// Clear slot (step+which)&3 of every instance before a 16-bit step.
 __global__ void k_clear_next_slot(const InstDev* __restrict__ insts, int ninst, long long step,
                                   int which) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -493,7 +573,7 @@ __global__ void k_clear_next_slot(const InstDev* __restrict__ insts, int ninst, 
 
 // ------------------------------------------------------- plain FP64 step
 // One thread per cell; every neighbour value is read from global memory and
-// fbar+ of the 3x3 neighbourhood is recomputed per cell.
+// g of the 3x3 neighbourhood is recomputed per cell.
 template <int Q, int NC>
 __global__ __launch_bounds__(256) void k_step_plain(const InstDev* __restrict__ I, int parity,
                                                     long long step) {
@@ -514,37 +594,37 @@ __global__ __launch_bounds__(256) void k_step_plain(const InstDev* __restrict__ 
       load_raw<Q, DUGKS_F64>(raw, in, plane,
                              (long long)src_index(cj, ny, I->bcy) * pitch + src_index(ci, nx, I->bcx));
       double phi_a, dummy[Q];
-      cell_values<Q, DUGKS_F64, NC>(I, raw, sc, g[b + 1][a + 1], dummy, false, phi_a);
+      cell_g<Q, DUGKS_F64, NC>(I, raw, sc, g[b + 1][a + 1], dummy, false, phi_a);
       const bool wx = (ci < 0 || ci >= nx) && I->bcx != DUGKS_BC_PERIODIC;
       const bool wy = (cj < 0 || cj >= ny) && I->bcy != DUGKS_BC_PERIODIC;
       if (wx || wy) {
         const double pg = ring != nullptr ? ring[ring_index(nx, ny, ci, cj)] : 0.0;
-        apply_ghost<Q, DUGKS_F64, NC>(I, g[b + 1][a + 1], phi_a, wx, wy, pg);
+        ghost_g<Q, DUGKS_F64, NC>(I, g[b + 1][a + 1], phi_a, wx, wy, pg);
       }
     }
   const double* cg = I->colgeo;
   const double* rg = I->rowgeo;
-  // slope numerators
-  double sy[3][Q], sx[3][Q];
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int k = 0; k < Q; ++k) sy[a][k] = g[2][a][k] - g[0][a][k];
-  for (int b = 0; b < 3; ++b)
-#pragma unroll
-    for (int k = 0; k < Q; ++k) sx[b][k] = g[b][2][k] - g[b][0][k];
   const double* cW = cg + (long long)(i + 1) * kGeo;   // W face of column i
   const double* cE = cg + (long long)(i + 2) * kGeo;   // W face of column i+1
   const double* rS = rg + (long long)(j + 1) * kGeo;
   const double* rN = rg + (long long)(j + 2) * kGeo;
-  double fW[Q], fE[Q], fS[Q], fN[Q];
-  face<Q, NC, 0>(I, g[1][0], g[1][1], sy[0], sy[1], cW[0], cW[1], cW[2], rS[3], fW);
-  face<Q, NC, 0>(I, g[1][1], g[1][2], sy[1], sy[2], cE[0], cE[1], cE[2], rS[3], fE);
-  face<Q, NC, 1>(I, g[0][1], g[1][1], sx[0], sx[1], rS[0], rS[1], rS[2], cW[3], fS);
-  face<Q, NC, 1>(I, g[1][1], g[2][1], sx[1], sx[2], rN[0], rN[1], rN[2], cW[3], fN);
+  double ts[Q], fW[Q], fE[Q], fS[Q], fN[Q];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) ts[k] = (g[2][0][k] - g[0][0][k]) + (g[2][1][k] - g[0][1][k]);
+  face<Q, NC, 0>(I, g[1][0], g[1][1], ts, cW[0], cW[1], cW[2], rS[3], fW);
+#pragma unroll
+  for (int k = 0; k < Q; ++k) ts[k] = (g[2][1][k] - g[0][1][k]) + (g[2][2][k] - g[0][2][k]);
+  face<Q, NC, 0>(I, g[1][1], g[1][2], ts, cE[0], cE[1], cE[2], rS[3], fE);
+#pragma unroll
+  for (int k = 0; k < Q; ++k) ts[k] = (g[0][2][k] - g[0][0][k]) + (g[1][2][k] - g[1][0][k]);
+  face<Q, NC, 1>(I, g[0][1], g[1][1], ts, rS[0], rS[1], rS[2], cW[3], fS);
+#pragma unroll
+  for (int k = 0; k < Q; ++k) ts[k] = (g[1][2][k] - g[1][0][k]) + (g[2][2][k] - g[2][0][k]);
+  face<Q, NC, 1>(I, g[1][1], g[2][1], ts, rN[0], rN[1], rN[2], cW[3], fN);
   Raw<Q, DUGKS_F64> raw;
   load_raw<Q, DUGKS_F64>(raw, in, plane, (long long)j * pitch + i);
-  double fb[Q], ftp[Q], phi;
-  cell_values<Q, DUGKS_F64, NC>(I, raw, sc, fb, ftp, true, phi);
+  double gc[Q], ftp[Q], phi;
+  cell_g<Q, DUGKS_F64, NC>(I, raw, sc, gc, ftp, true, phi);
   const double kx = cW[4], ky = rS[4];
 #pragma unroll
   for (int k = 0; k < Q; ++k) {

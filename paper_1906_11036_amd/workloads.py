@@ -229,18 +229,23 @@ def cosine_field(X, Y, seed, modes=4, total=0.5, wavenumber=math.pi, phases=Fals
 
     a_mn ~ U(-1, 1), rescaled so that sum |a_mn| = total; with ``phases`` each
     factor gets a seeded phase (periodic fields), otherwise the field is
-    Neumann-compatible on [0, 1]^2.
+    Neumann-compatible on [0, 1]^2.  X and Y are meshgrid arrays of a tensor
+    mesh; each product is separable, so the field is built from 1-D factors.
     """
     rng = np.random.default_rng(seed)
     a = rng.uniform(-1.0, 1.0, size=(modes, modes))
     a *= total / np.abs(a).sum()
     th = rng.uniform(0, 2 * math.pi, size=(modes, modes)) if phases else np.zeros((modes, modes))
     ps = rng.uniform(0, 2 * math.pi, size=(modes, modes)) if phases else np.zeros((modes, modes))
-    out = np.zeros_like(X)
+    x, y = np.asarray(X)[0, :], np.asarray(Y)[:, 0]
+    out = np.zeros((len(y), len(x)))
     for m in range(modes):
+        cx, sx = np.cos(wavenumber * m * x), np.sin(wavenumber * m * x)
         for k in range(modes):
-            out += a[m, k] * np.cos(wavenumber * m * X + th[m, k]) * \
-                np.cos(wavenumber * k * Y + ps[m, k])
+            fx = cx * math.cos(th[m, k]) - sx * math.sin(th[m, k])
+            fy = np.cos(wavenumber * k * y) * math.cos(ps[m, k]) - \
+                np.sin(wavenumber * k * y) * math.sin(ps[m, k])
+            out += a[m, k] * np.outer(fy, fx)
     return out
 
 

@@ -124,7 +124,9 @@ def test_nonlinear_diffusion_stretched_128():
     s32 = run_gpu(p, 200, storage="f32")
     err = rel_max(s32.get_phi(), o.get_phi())
     say(f"  f32 max rel err {err:.2e}")
-    assert err <= 1e-5
+    # each binary32 step rounds every stored value and the arithmetic before it
+    # (a few ulp); over n steps these add at worst linearly: 2 n eps32
+    assert err <= 2 * 200 * np.finfo(np.float32).eps
 
 
 @pytest.mark.parametrize("name,n,storage,tol", [
