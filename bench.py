@@ -43,6 +43,7 @@ def parse():
                              "nonlinear_diffusion_1024", "gaussian_hill_128"])
     ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16neq", "bf16neq"])
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--retune", action="store_true", help="autotune now instead of tuning.json")
     ap.add_argument("--launch", default=None,
                     help="fixed launch rows_per_wave,waves_per_block,schedule,xcd_remap (no autotune)")
     ap.add_argument("--no-extras", action="store_true",
@@ -108,6 +109,34 @@ def cpu_baseline(seconds):
                       f"D = phi I), {steps} steps in {el:.1f} s, binary64, 1 thread"}
 
 
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("dugks_kernels.hip", "dugks_internal.h"):
+        with open(os.path.join(ROOT, "paper_1906_11036_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, storage, info):
+    """HBM bytes per launch of the step kernel from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter on a copy of known
+    size), or None when the summary does not match this kernel source and launch."""
+    path = os.path.join(ROOT, "profiles", f"k_step_{storage}_{workload}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    launch = f"{info['rows_per_wave']},{info['waves_per_block']},{info['schedule']},{info['xcd_remap']}"
+    if fields.get("kernel_source_sha256") != kernel_source_hash() or fields.get("launch") != launch:
+        return None
+    return float(fields["hbm_bytes_per_launch"])
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -124,8 +153,15 @@ def main():
     log(f"workload {args.workload}: {len(problems)} instance(s), "
         f"{sum(p.cells for p in problems)} cells, generated in {time.perf_counter() - t_gen:.1f} s")
 
+    from paper_1906_11036_amd import tune
     launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
+    tuned_from = "argument" if launch else None
+    if launch is None and not args.retune:
+        launch = tune.lookup(args.workload, args.storage)   # the autotuner's stored pick
+        tuned_from = "tuning.json" if launch else None
     autotune = not args.no_autotune and launch is None
+    if autotune:
+        tuned_from = "autotune"
     torch.cuda.synchronize()
     b, ms = run_batch(problems, storage, args.steps, args.warmup, autotune=autotune, launch=launch)
     cells, state_bytes = b.totals()
@@ -142,8 +178,9 @@ def main():
     if not args.no_extras:
         # binary64 runs of the same batch for the L2 difference and the rate comparison
         nsteps_total = args.warmup + args.steps
-        b64, ms64 = run_batch(problems, L.F64, args.steps, args.warmup, autotune=autotune,
-                              launch=launch)
+        launch64 = tune.lookup(args.workload, "f64")
+        b64, ms64 = run_batch(problems, L.F64, args.steps, args.warmup,
+                              autotune=launch64 is None, launch=launch64)
         fused64 = cells * args.steps / (ms64 * 1e-3) / 1e6
         num = den = 0.0
         for i in range(len(problems)):
@@ -160,6 +197,7 @@ def main():
                   "speedup_vs_plain_fp64": round(mlups / plain64, 2),
                   "rel_l2_vs_fp64": l2, "rel_l2_after_steps": nsteps_total}
 
+    traffic_b = measured_traffic(args.workload, args.storage, info)
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -176,10 +214,14 @@ def main():
         "config": {"workload": args.workload, "instances": len(problems), "cells": cells,
                    "lattice": "D2Q9", "storage": args.storage,
                    "state_bytes": state_bytes, "rows_per_wave": info["rows_per_wave"],
-                   "waves_per_block": info["waves_per_block"], "schedule": info["schedule"]},
+                   "waves_per_block": info["waves_per_block"], "schedule": info["schedule"],
+                   "launch_from": tuned_from},
         "hbm_gbps_algorithmic": round(achieved, 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": (round(traffic_b / (ms_step * 1e-3) / 1e9, 1)
+                                 if traffic_b is not None else None)},
+        "traffic_bytes_per_launch": traffic_b,
     }
     out.update(extras)
     if not args.no_extras:

@@ -668,7 +668,7 @@ struct Engine {
     const Launch keep = launch;
     Launch best = keep;
     float best_ms = 1e30f;
-    const int rows_c[] = {16, 32, 64, 128, 256};
+    const int rows_c[] = {8, 16, 32, 64, 128};
     const int wpb_c[] = {1, 2, 4};
     for (int sched = 0; sched < 2; ++sched)
       for (int rows : rows_c)
@@ -831,6 +831,7 @@ int dugks_create(dugks_ctx** out, int nx, int ny, const double* xf, const double
   dugks::equilibrium_polys(c->inst[0]);
   c->storage = p->storage;
   c->plain = p->kernel == DUGKS_KERNEL_PLAIN;
+  if (c->storage == DUGKS_F64) { c->launch.rows_per_wave = 32; c->launch.waves_per_block = 1; }
   *out = c;
   return DUGKS_OK;
 }
@@ -1042,6 +1043,7 @@ int dugks_batch_create(dugks_batch** out, int n, const dugks_instance_desc* d, i
   if (n < 1 || !d) return b->fail(DUGKS_E_ARG, "empty batch");
   if (storage < DUGKS_F64 || storage > DUGKS_BF16NEQ) return b->fail(DUGKS_E_UNSUPPORTED, "unknown storage");
   b->storage = storage;
+  if (storage == DUGKS_F64) { b->launch.rows_per_wave = 32; b->launch.waves_per_block = 1; }
   b->inst.resize(n);
   for (int k = 0; k < n; ++k) {
     dugks_params p = d[k].p;

@@ -19,7 +19,8 @@ constexpr int kMaxQ = 9;
 constexpr int kMaxCoef = 8;     // E_i(phi) has degree <= 7 (C has degree 2*4-1)
 constexpr int kStripLanes = 64; // one wave covers 64 columns ...
 constexpr int kStripCols = 62;  // ... of which 62 are updated; lanes 0 and 63 are halo
-constexpr int kGeo = 5;         // per column / row: alpha(-), alpha(0), alpha(+), tau, k
+constexpr int kGeo = 5;
+
 
 // Per-instance constants and pointers, read by the kernels with scalar loads.
 //
@@ -60,8 +61,8 @@ struct WorkItem {
 
 // Launch configuration.
 struct Launch {
-  int rows_per_wave = 64;
-  int waves_per_block = 4;
+  int rows_per_wave = 16;
+  int waves_per_block = 2;
   int schedule = DUGKS_SCHED_GRID;
   int xcd_remap = 1;
 };

@@ -171,8 +171,9 @@ def test_launch_shape_invariance_bitwise():
     p = W.random_problem(321, 150, 97, bcx=W.PERIODIC, bcy=W.DIRICHLET, bdeg=2, ddeg=2)
     say("case launch invariance")
     ref = None
-    for launch in ((64, 4, dg.SCHED_GRID, 1), (1, 1, dg.SCHED_GRID, 0), (7, 2, dg.SCHED_PERSISTENT, 1),
-                   (97, 4, dg.SCHED_PERSISTENT, 0), (4096, 1, dg.SCHED_GRID, 1), (33, 2, dg.SCHED_GRID, 1)):
+    for launch in ((64, 2, dg.SCHED_GRID, 1), (1, 1, dg.SCHED_GRID, 0), (7, 2, dg.SCHED_PERSISTENT, 1),
+                   (97, 1, dg.SCHED_PERSISTENT, 0), (150, 1, dg.SCHED_GRID, 1), (33, 2, dg.SCHED_GRID, 1),
+                   (3, 4, dg.SCHED_GRID, 1)):
         s = run_gpu(p, 6, launch=launch)
         f = s.get_f()
         if ref is None:
