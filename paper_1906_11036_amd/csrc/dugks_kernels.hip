@@ -28,10 +28,15 @@
 
 namespace dugks {
 
+// Rows loaded ahead of the row being consumed by the step kernel.  A row of
+// the 16-bit formats is small (20 bytes a cell for D2Q9), so two rows stay in
+// flight to keep enough bytes outstanding per wave; the wider formats keep one.
 #ifndef DUGKS_PREFETCH
 #define DUGKS_PREFETCH 1
 #endif
-constexpr int kPrefetch = DUGKS_PREFETCH;  // rows loaded ahead of the row being consumed
+#ifndef DUGKS_PREFETCH_NEQ
+#define DUGKS_PREFETCH_NEQ 2
+#endif
 
 // ------------------------------------------------------------------ lattice
 // D2Q9 of eq. 2.5 (integer components; velocities are c times these).
@@ -60,9 +65,7 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t u) {
   return __uint_as_float(((uint32_t)u) << 16);
 }
 __device__ __forceinline__ uint16_t f32_to_bf16(float x) {  // round to nearest even
-  uint32_t u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+  return __builtin_bit_cast(uint16_t, (__bf16)x);
 }
 __device__ __forceinline__ float h16_to_f32(uint16_t u) {
   return (float)__builtin_bit_cast(_Float16, u);
@@ -147,7 +150,63 @@ template <int NC, typename T> __device__ __forceinline__ T horner(const T* c, T 
   return r;
 }
 
+// Coefficients of one instance for a work item.  Binary32 equilibria of
+// degree <= 3 (36 values for D2Q9) are loaded once into wave-uniform
+// registers and shared by the cell, the faces and the 16-bit encode; larger
+// sets are read through the scalar cache where they are used.
+template <typename T, int Q, int NC> struct Eq {
+  static constexpr bool kHeld = sizeof(T) == 4 && NC <= 4;
+  T c[kHeld ? Q : 1][kHeld ? NC : 1];
+  const InstDev* I;
+  T ra, rb, b1, inv_b1, kg;
+  __device__ __forceinline__ void load(const InstDev* __restrict__ inst) {
+    using C = Coef<T>;
+    I = inst;
+    if constexpr (kHeld) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k)
+#pragma unroll
+        for (int m = 0; m < NC; ++m) c[k][m] = C::e(I, k)[m];
+    }
+    ra = C::ra(I);
+    rb = C::rb(I);
+    b1 = C::b1(I);
+    inv_b1 = C::inv_b1(I);
+    kg = C::kg(I);
+  }
+  __device__ __forceinline__ T E(int k, T x) const {
+    if constexpr (kHeld) return horner<NC>(c[k], x);
+    else return horner<NC>(Coef<T>::e(I, k), x);
+  }
+};
+
+// Sum over directions of the interface values: binary64 for the binary64
+// path, a balanced binary32 tree otherwise.
+template <int Q> __device__ __forceinline__ double dir_sum(const double* v) {
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) s += v[k];
+  return s;
+}
+template <int Q> __device__ __forceinline__ float dir_sum(const float* v) {
+  float t[Q];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) t[k] = v[k];
+#pragma unroll
+  for (int w = 1; w < Q; w *= 2)
+#pragma unroll
+    for (int k = 0; k + w < Q; k += 2 * w) t[k] += t[k + w];
+  return t[0];
+}
+
 // ------------------------------------------------------------ memory
+// Pointer into the constant address space: uniform loads through it become
+// scalar loads.  Only for data that no kernel writes while it is read.
+template <typename T> using CPtr = const __attribute__((address_space(4))) T*;
+template <typename T> __device__ __forceinline__ CPtr<T> as_constant(const T* p) {
+  return (CPtr<T>)p;
+}
+
 // Raw stored values of one cell.
 template <int Q, int ST> struct Raw;
 template <int Q> struct Raw<Q, DUGKS_F64> { double v[Q]; };
@@ -212,22 +271,22 @@ struct Scales {
 
 // g = fbar+ / b1 (eq. 2.21) of the source cell and f~+ (eq. 2.23) when wanted.
 template <int Q, int ST, int NC>
-__device__ __forceinline__ void cell_g(const InstDev* __restrict__ I, const Raw<Q, ST>& r,
-                                       const Scales& sc, typename Stor<ST>::T* g,
-                                       typename Stor<ST>::T* ftp, bool want_ftp,
-                                       typename Stor<ST>::T& phi_out) {
+__device__ __forceinline__ void cell_g(const InstDev* __restrict__ I,
+                                       const Eq<typename Stor<ST>::T, Q, NC>& eq,
+                                       const Raw<Q, ST>& r, const Scales& sc,
+                                       typename Stor<ST>::T* g, typename Stor<ST>::T* ftp,
+                                       bool want_ftp, typename Stor<ST>::T& phi_out) {
   using T = typename Stor<ST>::T;
-  using C = Coef<T>;
   if constexpr (!Stor<ST>::neq) {
     double phi = 0.0;  // phi = sum_i f~_i (Sec. 2), binary64
 #pragma unroll
     for (int k = 0; k < Q; ++k) phi += (double)r.v[k];
     const T p = (T)phi;
-    const T ra = C::ra(I);
+    const T ra = eq.ra;
 #pragma unroll
-    for (int k = 0; k < Q; ++k) g[k] = fma(ra, r.v[k], horner<NC>(C::e(I, k), p));
+    for (int k = 0; k < Q; ++k) g[k] = fma(ra, r.v[k], eq.E(k, p));
     if (want_ftp) {
-      const T kg = C::kg(I);
+      const T kg = eq.kg;
 #pragma unroll
       for (int k = 0; k < Q; ++k) ftp[k] = fma(kg, g[k], (T)(-1.0 / 3.0) * r.v[k]);
     }
@@ -246,7 +305,7 @@ __device__ __forceinline__ void cell_g(const InstDev* __restrict__ I, const Raw<
     const float ras = I->raf * sc.inv_in, a2s = I->a2f * sc.inv_in, opra = I->oepraf;
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-      const float E = horner<NC>(I->ef[k], p);
+      const float E = eq.E(k, p);
       g[k] = fma(ras, gs[k], opra * E);
       if (want_ftp) ftp[k] = fma(a2s, gs[k], E);
     }
@@ -256,18 +315,17 @@ __device__ __forceinline__ void cell_g(const InstDev* __restrict__ I, const Raw<
 
 // Ghost rules on g of the source cell a (already in g).
 template <int Q, int ST, int NC>
-__device__ __forceinline__ void ghost_g(const InstDev* __restrict__ I, typename Stor<ST>::T* g,
-                                        typename Stor<ST>::T phi_a, bool wall_x, bool wall_y,
-                                        double phi_g) {
+__device__ __forceinline__ void ghost_g(const InstDev* __restrict__ I,
+                                        const Eq<typename Stor<ST>::T, Q, NC>& eq,
+                                        typename Stor<ST>::T* g, typename Stor<ST>::T phi_a,
+                                        bool wall_x, bool wall_y, double phi_g) {
   using T = typename Stor<ST>::T;
-  using C = Coef<T>;
   const bool dir = (wall_x && I->bcx == DUGKS_BC_DIRICHLET) || (wall_y && I->bcy == DUGKS_BC_DIRICHLET);
   if (dir) {
     // non-equilibrium extrapolation: fbar+_g = E(phi_g) + (fbar+_a - E(phi_a))
-    const T pg = (T)phi_g, ib = C::inv_b1(I);
+    const T pg = (T)phi_g, ib = eq.inv_b1;
 #pragma unroll
-    for (int k = 0; k < Q; ++k)
-      g[k] = fma(horner<NC>(C::e(I, k), pg) - horner<NC>(C::e(I, k), phi_a), ib, g[k]);
+    for (int k = 0; k < Q; ++k) g[k] = fma(eq.E(k, pg) - eq.E(k, phi_a), ib, g[k]);
   } else {
     T t[Q];
     if (wall_x) {
@@ -307,11 +365,9 @@ __device__ __forceinline__ int src_index(int i, int n, int bc) {
 // cells' central-difference numerators along the face (directions with a
 // tangential component).  NRM = 0 for x-faces, 1 for y-faces.
 template <int Q, int NC, int NRM, typename T>
-__device__ __forceinline__ void face(const InstDev* __restrict__ I, const T* L, const T* R,
-                                     const T* ts, T am, T a0, T ap, T tau, T* out) {
-  using C = Coef<T>;
+__device__ __forceinline__ void face(const Eq<T, Q, NC>& eq, const T* L, const T* R, const T* ts,
+                                     T am, T a0, T ap, T tau, T* out) {
   T gb[Q];
-  double sum = 0.0;
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
     const int cn = NRM == 0 ? lat_cx(k) : lat_cy(k);
@@ -320,14 +376,14 @@ __device__ __forceinline__ void face(const InstDev* __restrict__ I, const T* L, 
     T v = fma(al, R[k] - L[k], L[k]);
     if (ct != 0) v = fma((T)(-ct) * tau, ts[k], v);
     gb[k] = v;
-    sum += (double)v;  // phi(x_b, t + h) = sum_i fbar_i = b1 sum_i gbar_i
   }
-  const T pb = (T)(sum * (double)C::b1(I));
-  const T rb = C::rb(I);
+  // phi(x_b, t + h) = sum_i fbar_i = b1 sum_i gbar_i
+  const T pb = (T)(dir_sum<Q>(gb) * eq.b1);
+  const T rb = eq.rb;
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
     const int cn = NRM == 0 ? lat_cx(k) : lat_cy(k);
-    if (cn != 0) out[k] = fma(rb, gb[k], horner<NC>(C::e(I, k), pb));
+    if (cn != 0) out[k] = fma(rb, gb[k], eq.E(k, pb));
   }
 }
 
@@ -347,6 +403,10 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
                                           int parity, long long step, int lane, bool measure) {
   using T = typename Stor<ST>::T;
   using C = Coef<T>;
+  constexpr int PF = Stor<ST>::neq ? DUGKS_PREFETCH_NEQ : DUGKS_PREFETCH;
+  static_assert(PF == 1 || PF == 2, "one or two rows ahead");
+  Eq<T, Q, NC> eq;
+  eq.load(I);
   const int nx = I->nx, ny = I->ny, pitch = I->pitch, bcx = I->bcx, bcy = I->bcy;
   const unsigned plane = (unsigned)I->plane;
   const __amdgpu_buffer_rsrc_t Rin = rsrc(I->buf[parity], I->buf_bytes);
@@ -367,20 +427,23 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
   // per-column geometry: W-face coefficients, tangential factor, update factor
   const T* cg = C::col(I) + (long long)((c + 1 < nx + 1 ? c + 1 : nx + 1)) * kGeo;
   const T cam = cg[0], ca0 = cg[1], cap = cg[2], ctau = cg[3], ck = cg[4];
-  const T* rg = C::row(I);
+  // Row factors are wave-uniform: read them through the scalar cache (a
+  // generic pointer would give flat loads, whose completion can only be
+  // awaited together with every row load in flight).
+  const CPtr<T> rg = as_constant(C::row(I));
 
   const double* ring = (I->ring != nullptr) ? I->ring + step * I->ring_len : nullptr;
 
   auto make_row = [&](const Raw<Q, ST>& raw, int r, T* g, T* ftp, bool want_ftp) {
     T phi_a;
-    cell_g<Q, ST, NC>(I, raw, sc, g, ftp, want_ftp, phi_a);
+    cell_g<Q, ST, NC>(I, eq, raw, sc, g, ftp, want_ftp, phi_a);
     if constexpr (!GH) return;
     const bool wall_y = (r < 0 || r >= ny) && bcy != DUGKS_BC_PERIODIC;
     if (wall_y || strip_touches_x_wall) {
       if (wall_x || wall_y) {
         double pg = 0.0;
         if (ring != nullptr) pg = ring[ring_index(nx, ny, c < -1 ? -1 : (c > nx ? nx : c), r)];
-        ghost_g<Q, ST, NC>(I, g, phi_a, wall_x, wall_y, pg);
+        ghost_g<Q, ST, NC>(I, eq, g, phi_a, wall_x, wall_y, pg);
       }
     }
   };
@@ -402,7 +465,7 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
   load_raw_buf<Q, ST>(RW[1], Rin, plane, row_idx(y0 + 1));
   make_row(RW[2], y0 - 1, G[2], FT[2], false);
   make_row(RW[0], y0, G[0], FT[0], true);
-  if constexpr (kPrefetch == 2)  // two rows in flight ahead of the row being consumed
+  if constexpr (PF == 2)  // two rows in flight ahead of the row being consumed
     load_raw_buf<Q, ST>(RW[2], Rin, plane, row_idx(y0 + 2 <= y1 ? y0 + 2 : y1));
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
@@ -413,22 +476,22 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
     }
   }
   {
-    const T* g = rg + (long long)(y0 + 1) * kGeo;
-    face<Q, NC, 1>(I, G[2], G[0], ts, g[0], g[1], g[2], ctau, FY[2]);
+    const CPtr<T> g = rg + (long long)(y0 + 1) * kGeo;
+    face<Q, NC, 1>(eq, G[2], G[0], ts, g[0], g[1], g[2], ctau, FY[2]);
   }
 
   bool bad = false, ovf = false;
   float mx = 0.0f;
   auto body = [&](int j, auto slot) {
     constexpr int s0 = decltype(slot)::value, sp = (s0 + 1) % 3, sm = (s0 + 2) % 3;
-    // row j+1 is in RW[sp]; the next load goes kPrefetch rows further
-    if constexpr (kPrefetch == 2)
+    // row j+1 is in RW[sp]; the next load goes PF rows further
+    if constexpr (PF == 2)
       load_raw_buf<Q, ST>(RW[s0], Rin, plane, row_idx(j + 3 <= y1 ? j + 3 : y1));
     else
       load_raw_buf<Q, ST>(RW[sm], Rin, plane, row_idx(j + 2 <= y1 ? j + 2 : y1));
     make_row(RW[sp], j + 1, G[sp], FT[sp], true);
-    const T* gj = rg + (long long)(j + 1) * kGeo;   // row j: its S face and factors
-    const T* gn = rg + (long long)(j + 2) * kGeo;   // row j+1: S face = N face of row j
+    const CPtr<T> gj = rg + (long long)(j + 1) * kGeo;   // row j: its S face and factors
+    const CPtr<T> gn = rg + (long long)(j + 2) * kGeo;   // row j+1: S face = N face of row j
     const T rtau = gj[3], rk = gj[4];
     // x-slope numerators of row j+1: g(lane+1) - g(lane-1)
 #pragma unroll
@@ -439,7 +502,7 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
         ts[k] = SX[s0][k] + SX[sp][k];
       }
     }
-    face<Q, NC, 1>(I, G[s0], G[sp], ts, gn[0], gn[1], gn[2], ctau, FY[s0]);
+    face<Q, NC, 1>(eq, G[s0], G[sp], ts, gn[0], gn[1], gn[2], ctau, FY[s0]);
     // west face of this lane's cell: left state from lane-1; y-slope numerators
 #pragma unroll
     for (int k = 0; k < Q; ++k)
@@ -447,7 +510,7 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
         dy[k] = G[sp][k] - G[sm][k];
         ts[k] = shr1(dy[k]) + dy[k];
       }
-    face<Q, NC, 0>(I, LS[s0], G[s0], ts, cam, ca0, cap, rtau, fW);
+    face<Q, NC, 0>(eq, LS[s0], G[s0], ts, cam, ca0, cap, rtau, fW);
     // update (eq. 2.24): f~(t+dt) = f~+ - dt c_i.(flux differences)/width
     T o[Q];
 #pragma unroll
@@ -473,27 +536,22 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
           }
         }
       } else {
-        double ps = 0.0;
-#pragma unroll
-        for (int k = 0; k < Q; ++k) ps += (double)o[k];
-        const float pf = (float)ps;
+        const float pf = dir_sum<Q>(o);   // phi(t + dt) = sum_i f~_i
         bad |= !__builtin_isfinite(pf);
-        float m = 0.0f;
+        float m1 = 0.0f;                  // max |f~_i - E_i| over the stored i >= 1
         uint16_t gq[Q - 1];
 #pragma unroll
-        for (int k = 0; k < Q; ++k) {
-          const float d = o[k] - horner<NC>(I->ef[k], pf);
-          m = fmaxf(m, fabsf(d));
-          if (k > 0) {
-            float s = d * sc.out;
-            if (!measure && fabsf(s) > g_limit<ST>()) {
-              ovf = true;
-              s = fminf(fmaxf(s, -g_limit<ST>()), g_limit<ST>());
-            }
-            gq[k - 1] = f32_to_g<ST>(s);
-          }
+        for (int k = 1; k < Q; ++k) {
+          const float d = o[k] - eq.E(k, pf);
+          m1 = fmaxf(m1, fabsf(d));
+          float s = d * sc.out;
+          // binary16: saturate (an overflow is flagged below); bfloat16 has
+          // binary32's range
+          if constexpr (ST == DUGKS_F16NEQ) s = __builtin_amdgcn_fmed3f(s, -g_limit<ST>(), g_limit<ST>());
+          gq[k - 1] = f32_to_g<ST>(s);
         }
-        mx = fmaxf(mx, m);
+        ovf |= !measure && m1 * sc.out > g_limit<ST>();
+        mx = fmaxf(mx, fmaxf(m1, fabsf(o[0] - eq.E(0, pf))));
         if (!measure) {
           __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, pf), Rout, idx * 4u, 0u, 0);
 #pragma unroll
@@ -578,6 +636,8 @@ template <int Q, int NC>
 __global__ __launch_bounds__(256) void k_step_plain(const InstDev* __restrict__ I, int parity,
                                                     long long step) {
   const int nx = I->nx, ny = I->ny, pitch = I->pitch;
+  Eq<double, Q, NC> eq;
+  eq.load(I);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (i >= nx || j >= ny) return;
@@ -594,12 +654,12 @@ __global__ __launch_bounds__(256) void k_step_plain(const InstDev* __restrict__ 
       load_raw<Q, DUGKS_F64>(raw, in, plane,
                              (long long)src_index(cj, ny, I->bcy) * pitch + src_index(ci, nx, I->bcx));
       double phi_a, dummy[Q];
-      cell_g<Q, DUGKS_F64, NC>(I, raw, sc, g[b + 1][a + 1], dummy, false, phi_a);
+      cell_g<Q, DUGKS_F64, NC>(I, eq, raw, sc, g[b + 1][a + 1], dummy, false, phi_a);
       const bool wx = (ci < 0 || ci >= nx) && I->bcx != DUGKS_BC_PERIODIC;
       const bool wy = (cj < 0 || cj >= ny) && I->bcy != DUGKS_BC_PERIODIC;
       if (wx || wy) {
         const double pg = ring != nullptr ? ring[ring_index(nx, ny, ci, cj)] : 0.0;
-        ghost_g<Q, DUGKS_F64, NC>(I, g[b + 1][a + 1], phi_a, wx, wy, pg);
+        ghost_g<Q, DUGKS_F64, NC>(I, eq, g[b + 1][a + 1], phi_a, wx, wy, pg);
       }
     }
   const double* cg = I->colgeo;
@@ -611,20 +671,20 @@ __global__ __launch_bounds__(256) void k_step_plain(const InstDev* __restrict__ 
   double ts[Q], fW[Q], fE[Q], fS[Q], fN[Q];
 #pragma unroll
   for (int k = 0; k < Q; ++k) ts[k] = (g[2][0][k] - g[0][0][k]) + (g[2][1][k] - g[0][1][k]);
-  face<Q, NC, 0>(I, g[1][0], g[1][1], ts, cW[0], cW[1], cW[2], rS[3], fW);
+  face<Q, NC, 0>(eq, g[1][0], g[1][1], ts, cW[0], cW[1], cW[2], rS[3], fW);
 #pragma unroll
   for (int k = 0; k < Q; ++k) ts[k] = (g[2][1][k] - g[0][1][k]) + (g[2][2][k] - g[0][2][k]);
-  face<Q, NC, 0>(I, g[1][1], g[1][2], ts, cE[0], cE[1], cE[2], rS[3], fE);
+  face<Q, NC, 0>(eq, g[1][1], g[1][2], ts, cE[0], cE[1], cE[2], rS[3], fE);
 #pragma unroll
   for (int k = 0; k < Q; ++k) ts[k] = (g[0][2][k] - g[0][0][k]) + (g[1][2][k] - g[1][0][k]);
-  face<Q, NC, 1>(I, g[0][1], g[1][1], ts, rS[0], rS[1], rS[2], cW[3], fS);
+  face<Q, NC, 1>(eq, g[0][1], g[1][1], ts, rS[0], rS[1], rS[2], cW[3], fS);
 #pragma unroll
   for (int k = 0; k < Q; ++k) ts[k] = (g[1][2][k] - g[1][0][k]) + (g[2][2][k] - g[2][0][k]);
-  face<Q, NC, 1>(I, g[1][1], g[2][1], ts, rN[0], rN[1], rN[2], cW[3], fN);
+  face<Q, NC, 1>(eq, g[1][1], g[2][1], ts, rN[0], rN[1], rN[2], cW[3], fN);
   Raw<Q, DUGKS_F64> raw;
   load_raw<Q, DUGKS_F64>(raw, in, plane, (long long)j * pitch + i);
   double gc[Q], ftp[Q], phi;
-  cell_g<Q, DUGKS_F64, NC>(I, raw, sc, gc, ftp, true, phi);
+  cell_g<Q, DUGKS_F64, NC>(I, eq, raw, sc, gc, ftp, true, phi);
   const double kx = cW[4], ky = rS[4];
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
