@@ -16,8 +16,17 @@
  *   phi -> f~, E  (eq. 2.3)            -> f~+, fbar+  (eqs. 2.13, 2.21)
  *   -> fbar+ at the face (eq. 2.20)    -> fbar(x_b, t+h) (eqs. 2.19, 2.26)
  *   -> phi(x_b, t+h) = sum fbar        -> f(x_b, t+h) (eq. 2.22)
- *   -> face flux J (eq. 2.9)           -> f~(t+dt) (eq. 2.24 with R = F = 0)
- *   -> phi = sum f~.
+ *   -> face flux J (eq. 2.9)           -> f~(t+dt) (eq. 2.24)
+ *   -> phi = sum f~ (+ dt F / 2 with a source).
+ *
+ * Source term (eq. 2.1's F), when set: F(x, t) = exp(gamma t) G(x) with G
+ * given at the cell centres.  Its distributions are F_i = w_i F (eq. 2.3) and,
+ * with C = int B'B'^T, R_i = w_i c_i.B'(phi) F / c_s^2 (Remark 3); they enter
+ * through the shifted distributions of eqs. 2.25 and 2.27, which this file
+ * applies literally: f is recovered from f~ (first line of eq. 2.25), fbar
+ * and fbar+ follow from eq. 2.27, f~+ from the second line of eq. 2.25, and
+ * f at the face from the first line of eq. 2.27.  Without a source the step
+ * uses eqs. 2.13, 2.21 and 2.22 directly.
  *
  * Readings of points the paper leaves open (each one also listed in the
  * design notes):
@@ -41,6 +50,13 @@
  *       mirror    : specular zero-flux wall, fbar+_g,i = fbar+_a,m(i) with
  *                   m(i) the direction whose normal component is reversed.
  *     Wall ghosts take the width of the adjacent interior cell.
+ *   - With a source: the moments of eq. 2.7 (sum F_i = F, sum R_i = 0) give
+ *     phi = sum f~ + dt F / 2 in a cell and phi_b = sum fbar + h F / 2 at a
+ *     face (the paper's phi_b = sum fbar is the F = 0 case).  F at a face is
+ *     the linear interpolation of eq. 2.20 between the two cell centres, at
+ *     t_n + h; a ghost cell takes G of the cell its fbar+ comes from.  f~ is
+ *     initialised as f - dt (Omega + R + F) / 2 with f = E(phi_0), i.e.
+ *     E(phi_0) - dt S(phi_0, F(x, 0)) / 2.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -69,6 +85,9 @@ typedef struct {
   double *xf, *yf;        /* faces, nx+1 / ny+1 */
   double *wx, *wy;        /* widths of cells -1..n */
   double *xc, *yc;        /* centres of cells -1..n */
+  /* source F(x, t) = exp(src_gamma t) src_g(x); src_g [ny][nx] or NULL */
+  double *src_g;
+  double src_gamma;
   /* state */
   double *f;              /* f~ [q][ny][nx] */
   long step;
@@ -154,6 +173,29 @@ static void feq(const Oracle* o, double phi, double* E) {
   }
 }
 
+/* ----------------------------------------------------------------- source */
+
+/* S_i = R_i + F_i for a source value F at conserved value phi:
+ * F_i = w_i F (eq. 2.3); R_i = w_i c_i.B'(phi) F / cs2 (Remark 3, C = int B'B'^T).
+ * B'(phi) = sum_{k>=1} k b_k phi^(k-1). */
+static void source_dist(const Oracle* o, double phi, double F, double* S) {
+  double bpx = 0.0, bpy = 0.0, p = 1.0;
+  int k, i;
+  for (k = 1; k <= o->bdeg; ++k) {
+    bpx += (double)k * o->bx[k] * p;
+    bpy += (double)k * o->by[k] * p;
+    p *= phi;
+  }
+  for (i = 0; i < o->q; ++i)
+    S[i] = o->w[i] * F + o->w[i] * (o->cx[i] * bpx + o->cy[i] * bpy) * F / o->cs2;
+}
+
+/* F at the centre of interior cell c at time t (0 without a source) */
+static double source_at(const Oracle* o, size_t c, double t) {
+  if (!o->src_g) return 0.0;
+  return exp(o->src_gamma * t) * o->src_g[c];
+}
+
 /* --------------------------------------------------------------- geometry */
 
 #define XW(o, i) ((o)->wx[(i) + 1])
@@ -224,6 +266,7 @@ Oracle* or_create(int nx, int ny, const double* xf, const double* yf, int q, dou
 void or_destroy(Oracle* o) {
   if (!o) return;
   free(o->xf); free(o->yf); free(o->wx); free(o->wy); free(o->xc); free(o->yc); free(o->f);
+  free(o->src_g);
   free(o);
 }
 
@@ -246,6 +289,19 @@ int or_set_D(Oracle* o, int deg, const double* dxx, const double* dxy, const dou
   return 0;
 }
 
+/* Source F(x, t) = exp(gamma t) g(x), g [ny][nx] at the cell centres (copied);
+ * g == NULL removes it. */
+void or_set_source(Oracle* o, const double* g, double gamma) {
+  size_t N = (size_t)o->nx * o->ny;
+  free(o->src_g);
+  o->src_g = NULL;
+  o->src_gamma = 0.0;
+  if (!g) return;
+  o->src_g = (double*)malloc(sizeof(double) * N);
+  memcpy(o->src_g, g, sizeof(double) * N);
+  o->src_gamma = gamma;
+}
+
 /* constants: lambda, dt, h, a1, b1, a2, b2, a3, b3, cs2 */
 void or_constants(const Oracle* o, double* out) {
   out[0] = o->lambda; out[1] = o->dt; out[2] = o->h;
@@ -266,12 +322,18 @@ void or_feq(const Oracle* o, double phi, double* E) { feq(o, phi, E); }
 /* Initialisation of Sec. 4: f~(x, t0) = E(phi(x, t0)), point values at centres. */
 void or_set_phi(Oracle* o, const double* phi) {
   int i, j, k;
-  double E[OR_MAXQ];
+  double E[OR_MAXQ], S[OR_MAXQ];
   size_t N = (size_t)o->nx * o->ny;
   for (j = 0; j < o->ny; ++j)
     for (i = 0; i < o->nx; ++i) {
-      feq(o, phi[(size_t)j * o->nx + i], E);
-      for (k = 0; k < o->q; ++k) o->f[k * N + (size_t)j * o->nx + i] = E[k];
+      size_t c = (size_t)j * o->nx + i;
+      feq(o, phi[c], E);
+      for (k = 0; k < o->q; ++k) o->f[k * N + c] = E[k];
+      if (o->src_g) {
+        /* f = E at t = 0, Omega = 0: f~ = f - dt (R + F) / 2 (eq. 2.25) */
+        source_dist(o, phi[c], source_at(o, c, 0.0), S);
+        for (k = 0; k < o->q; ++k) o->f[k * N + c] = E[k] - 0.5 * o->dt * S[k];
+      }
     }
   o->step = 0; o->t = 0.0;
 }
@@ -286,15 +348,20 @@ void or_set_clock(Oracle* o, long step, double t) { o->step = step; o->t = t; }
 long or_step_index(const Oracle* o) { return o->step; }
 double or_time(const Oracle* o) { return o->t; }
 
-/* phi = sum_i f~_i (Sec. 2, after eq. 2.13) */
-void or_get_phi(const Oracle* o, double* phi) {
-  int i, k;
+/* phi of cell c at the current time: sum_i f~_i (Sec. 2, after eq. 2.13),
+ * plus dt F / 2 with a source (eq. 2.25 summed with the moments of eq. 2.7) */
+static double cell_phi(const Oracle* o, size_t c) {
   size_t N = (size_t)o->nx * o->ny;
-  for (i = 0; i < (int)N; ++i) {
-    double s = 0.0;
-    for (k = 0; k < o->q; ++k) s += o->f[k * N + i];
-    phi[i] = s;
-  }
+  double s = 0.0;
+  int k;
+  for (k = 0; k < o->q; ++k) s += o->f[k * N + c];
+  if (o->src_g) s += 0.5 * o->dt * source_at(o, c, o->t);
+  return s;
+}
+
+void or_get_phi(const Oracle* o, double* phi) {
+  size_t i, N = (size_t)o->nx * o->ny;
+  for (i = 0; i < N; ++i) phi[i] = cell_phi(o, i);
 }
 
 /* ------------------------------------------------------------------- step */
@@ -313,17 +380,33 @@ static int wrap_or_clamp(int i, int n, int bc) {
 }
 
 /* fbar+ at cell (i, j), i in -1..nx, j in -1..ny, from the current f~ and the
- * ghost rules.  fbar+ = a1 f~ + b1 E(phi)  (eq. 2.21). */
+ * ghost rules.  Without a source fbar+ = a1 f~ + b1 E(phi)  (eq. 2.21); with
+ * one, f from f~ (eq. 2.25), then fbar and fbar+ (eq. 2.27). */
 static void fbar_plus(const Oracle* o, int i, int j, const double* ring, double* out) {
   int si = wrap_or_clamp(i, o->nx, o->bcx), sj = wrap_or_clamp(j, o->ny, o->bcy);
   size_t N = (size_t)o->nx * o->ny, c = (size_t)sj * o->nx + si;
-  double ft[OR_MAXQ], E[OR_MAXQ], phi = 0.0, tmp[OR_MAXQ];
+  double ft[OR_MAXQ], E[OR_MAXQ], phi, tmp[OR_MAXQ];
   int k;
   int xwall = (i < 0 || i >= o->nx) && o->bcx != OR_PERIODIC;
   int ywall = (j < 0 || j >= o->ny) && o->bcy != OR_PERIODIC;
-  for (k = 0; k < o->q; ++k) { ft[k] = o->f[k * N + c]; phi += ft[k]; }
+  for (k = 0; k < o->q; ++k) ft[k] = o->f[k * N + c];
+  phi = cell_phi(o, c);
   feq(o, phi, E);
-  for (k = 0; k < o->q; ++k) out[k] = o->a1 * ft[k] + o->b1 * E[k];
+  if (!o->src_g) {
+    for (k = 0; k < o->q; ++k) out[k] = o->a1 * ft[k] + o->b1 * E[k];
+  } else {
+    double S[OR_MAXQ], L = o->lambda, dt = o->dt, h = o->h;
+    source_dist(o, phi, source_at(o, c, o->t), S);
+    for (k = 0; k < o->q; ++k) {
+      /* f~ = f - dt/2 Omega - dt/2 S with Omega = -(f - E)/lambda, solved for f */
+      double f = (2.0 * L * ft[k] + dt * E[k] + L * dt * S[k]) / (2.0 * L + dt);
+      /* fbar = f - h/2 Omega - h/2 S (eq. 2.27, first line) */
+      double fb = f + h / (2.0 * L) * (f - E[k]) - 0.5 * h * S[k];
+      /* eq. 2.27, second line */
+      out[k] = (2.0 * L - h) / (2.0 * L + h) * fb + 2.0 * h / (2.0 * L + h) * E[k] +
+               2.0 * L * h / (2.0 * L + h) * S[k];
+    }
+  }
   if (!xwall && !ywall) return;
   if ((xwall && o->bcx == OR_DIRICHLET) || (ywall && o->bcy == OR_DIRICHLET)) {
     double phig = ring[ring_index(o, i, j)], Eg[OR_MAXQ];
@@ -343,12 +426,14 @@ static void fbar_plus(const Oracle* o, int i, int j, const double* ring, double*
  *   tL, tR : central-difference slopes of fbar+ along the face at L and R
  *   dn     : distance between the two centres, wl : face minus L centre
  *   (cn, ct) : velocity components normal / tangential to the face
+ *   sL, sR : source G at the two cells (ignored without a source)
  * Linear reconstruction (eq. 2.20), Taylor shift back along the
  * characteristic (eq. 2.19 in the form of eq. 2.26), interface phi (sum of
- * fbar), f = a3 fbar + b3 E(phi_b)  (eq. 2.22), flux c_n f  (eq. 2.9). */
+ * fbar), f = a3 fbar + b3 E(phi_b)  (eq. 2.22; with a source, the first line
+ * of eq. 2.27 solved for f), flux c_n f  (eq. 2.9). */
 static void face_flux(const Oracle* o, const double* cn, const double* ct, const double* fL,
                       const double* fR, const double* tL, const double* tR, double dn,
-                      double wl, double* flux) {
+                      double wl, double sL, double sR, double* flux) {
   double fb[OR_MAXQ], E[OR_MAXQ], phib = 0.0;
   int k;
   for (k = 0; k < o->q; ++k) {
@@ -358,8 +443,26 @@ static void face_flux(const Oracle* o, const double* cn, const double* ct, const
     fb[k] = v - o->h * (cn[k] * Gn + ct[k] * Gt);
   }
   for (k = 0; k < o->q; ++k) phib += fb[k];
-  feq(o, phib, E);
-  for (k = 0; k < o->q; ++k) flux[k] = cn[k] * (o->a3 * fb[k] + o->b3 * E[k]);
+  if (!o->src_g) {
+    feq(o, phib, E);
+    for (k = 0; k < o->q; ++k) flux[k] = cn[k] * (o->a3 * fb[k] + o->b3 * E[k]);
+  } else {
+    double S[OR_MAXQ], L = o->lambda, h = o->h;
+    /* F at the face at t_n + h: linear interpolation between the centres */
+    double Fb = exp(o->src_gamma * (o->t + h)) * (sL + wl * (sR - sL) / dn);
+    phib += 0.5 * h * Fb;
+    feq(o, phib, E);
+    source_dist(o, phib, Fb, S);
+    for (k = 0; k < o->q; ++k)
+      flux[k] = cn[k] * (2.0 * L * fb[k] + h * E[k] + L * h * S[k]) / (2.0 * L + h);
+  }
+}
+
+/* source G of cell (i, j), i in -1..nx, j in -1..ny: a ghost takes the G of
+ * the cell its fbar+ comes from */
+static double src_g_at(const Oracle* o, int i, int j) {
+  if (!o->src_g) return 0.0;
+  return o->src_g[(size_t)wrap_or_clamp(j, o->ny, o->bcy) * o->nx + wrap_or_clamp(i, o->nx, o->bcx)];
 }
 
 static void slope(const Oracle* o, const double* fm, const double* fp, double dist, double* s) {
@@ -380,11 +483,18 @@ static void update_cell(const Oracle* o, size_t c, const double* ft_plus, const 
 
 static void ftilde_plus(const Oracle* o, size_t c, double* out) {
   size_t N = (size_t)o->nx * o->ny;
-  double ft[OR_MAXQ], E[OR_MAXQ], phi = 0.0;
+  double ft[OR_MAXQ], E[OR_MAXQ], S[OR_MAXQ], phi;
   int k;
-  for (k = 0; k < o->q; ++k) { ft[k] = o->f[k * N + c]; phi += ft[k]; }
+  for (k = 0; k < o->q; ++k) ft[k] = o->f[k * N + c];
+  phi = cell_phi(o, c);
   feq(o, phi, E);
-  for (k = 0; k < o->q; ++k) out[k] = o->a2 * ft[k] + o->b2 * E[k]; /* eq. 2.13 */
+  if (!o->src_g) {
+    for (k = 0; k < o->q; ++k) out[k] = o->a2 * ft[k] + o->b2 * E[k]; /* eq. 2.13 */
+    return;
+  }
+  source_dist(o, phi, source_at(o, c, o->t), S);
+  for (k = 0; k < o->q; ++k) /* eq. 2.25, second line */
+    out[k] = o->a2 * ft[k] + o->b2 * E[k] + 2.0 * o->lambda * o->dt / (2.0 * o->lambda + o->dt) * S[k];
 }
 
 /* One full step over the grid, phase by phase.  ring: boundary phi at ghost
@@ -424,14 +534,16 @@ static void step_once(Oracle* o, const double* ring) {
     for (i = 0; i <= nx; ++i)
       face_flux(o, zx, zy, GP(i - 1, j), GP(i, j), SY + ((size_t)j * NX2 + i) * q,
                 SY + ((size_t)j * NX2 + i + 1) * q, XC(o, i) - XC(o, i - 1),
-                o->xf[i] - XC(o, i - 1), FX + ((size_t)j * (nx + 1) + i) * q);
+                o->xf[i] - XC(o, i - 1), src_g_at(o, i - 1, j), src_g_at(o, i, j),
+                FX + ((size_t)j * (nx + 1) + i) * q);
   /* y-faces between (i, j-1) and (i, j), j = 0..ny */
 #pragma omp parallel for private(i)
   for (j = 0; j <= ny; ++j)
     for (i = 0; i < nx; ++i)
       face_flux(o, zy, zx, GP(i, j - 1), GP(i, j), SX + ((size_t)j * nx + i) * q,
                 SX + ((size_t)(j + 1) * nx + i) * q, YC(o, j) - YC(o, j - 1),
-                o->yf[j] - YC(o, j - 1), FY + ((size_t)j * nx + i) * q);
+                o->yf[j] - YC(o, j - 1), src_g_at(o, i, j - 1), src_g_at(o, i, j),
+                FY + ((size_t)j * nx + i) * q);
   /* 5: update */
 #pragma omp parallel for private(i)
   for (j = 0; j < ny; ++j)
@@ -480,13 +592,13 @@ void or_step_cells(const Oracle* o, int ncells, const int* cells, const double* 
     for (b = -1; b <= 1; ++b)
       slope(o, g[b + 1][0], g[b + 1][2], XC(o, i + 1) - XC(o, i - 1), sx[b + 1]);
     face_flux(o, zx, zy, g[1][0], g[1][1], sy[0], sy[1], XC(o, i) - XC(o, i - 1),
-              o->xf[i] - XC(o, i - 1), fw);
+              o->xf[i] - XC(o, i - 1), src_g_at(o, i - 1, j), src_g_at(o, i, j), fw);
     face_flux(o, zx, zy, g[1][1], g[1][2], sy[1], sy[2], XC(o, i + 1) - XC(o, i),
-              o->xf[i + 1] - XC(o, i), fe);
+              o->xf[i + 1] - XC(o, i), src_g_at(o, i, j), src_g_at(o, i + 1, j), fe);
     face_flux(o, zy, zx, g[0][1], g[1][1], sx[0], sx[1], YC(o, j) - YC(o, j - 1),
-              o->yf[j] - YC(o, j - 1), fs);
+              o->yf[j] - YC(o, j - 1), src_g_at(o, i, j - 1), src_g_at(o, i, j), fs);
     face_flux(o, zy, zx, g[1][1], g[2][1], sx[1], sx[2], YC(o, j + 1) - YC(o, j),
-              o->yf[j + 1] - YC(o, j), fnn);
+              o->yf[j + 1] - YC(o, j), src_g_at(o, i, j), src_g_at(o, i, j + 1), fnn);
     ftilde_plus(o, (size_t)j * o->nx + i, ftp);
     update_cell(o, 0, ftp, fw, fe, fs, fnn, XW(o, i), YW(o, j), out + (size_t)n * q);
   }
@@ -503,14 +615,12 @@ void or_fbar_plus_all(const Oracle* o, const double* ring, double* out) {
 /* GRE of eq. 4.1 (unweighted sums over cells) and the relative L2 error
  * weighted by cell area, against a reference field phi_a [ny][nx]. */
 void or_errors(const Oracle* o, const double* phi_a, double* gre, double* rel_l2) {
-  int i, j, k;
-  size_t N = (size_t)o->nx * o->ny;
+  int i, j;
   double num = 0.0, den = 0.0, e2 = 0.0, r2 = 0.0;
   for (j = 0; j < o->ny; ++j)
     for (i = 0; i < o->nx; ++i) {
       size_t c = (size_t)j * o->nx + i;
-      double phi = 0.0, v = XW(o, i) * YW(o, j);
-      for (k = 0; k < o->q; ++k) phi += o->f[k * N + c];
+      double phi = cell_phi(o, c), v = XW(o, i) * YW(o, j);
       num += fabs(phi_a[c] - phi);
       den += fabs(phi_a[c]);
       e2 += v * (phi - phi_a[c]) * (phi - phi_a[c]);
@@ -522,15 +632,12 @@ void or_errors(const Oracle* o, const double* phi_a, double* gre, double* rel_l2
 
 /* mass = sum_j phi_j |V_j| */
 double or_mass(const Oracle* o) {
-  int i, j, k;
-  size_t N = (size_t)o->nx * o->ny;
+  int i, j;
   double m = 0.0;
   for (j = 0; j < o->ny; ++j)
     for (i = 0; i < o->nx; ++i) {
       size_t c = (size_t)j * o->nx + i;
-      double phi = 0.0;
-      for (k = 0; k < o->q; ++k) phi += o->f[k * N + c];
-      m += phi * XW(o, i) * YW(o, j);
+      m += cell_phi(o, c) * XW(o, i) * YW(o, j);
     }
   return m;
 }

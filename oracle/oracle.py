@@ -49,6 +49,7 @@ def _lib(openmp: bool = False):
         lib.or_destroy.argtypes = [C.c_void_p]
         lib.or_set_B.argtypes = [C.c_void_p, C.c_int, _d, _d]
         lib.or_set_D.argtypes = [C.c_void_p, C.c_int, _d, _d, _d]
+        lib.or_set_source.argtypes = [C.c_void_p, _d, C.c_double]
         lib.or_constants.argtypes = [C.c_void_p, _d]
         lib.or_geometry.argtypes = [C.c_void_p, _d, _d, _d, _d]
         lib.or_feq.argtypes = [C.c_void_p, C.c_double, _d]
@@ -99,6 +100,8 @@ class Oracle:
             raise ValueError("oracle rejected the parameters")
         self.set_B(bx, by)
         self.set_D(dxx, dxy, dyy)
+        if problem is not None and getattr(problem, "src_g", None) is not None:
+            self.set_source(problem.src_g, problem.src_gamma)
         if problem is not None and problem.phi0 is not None:
             self.set_phi(problem.phi0)
 
@@ -122,6 +125,15 @@ class Oracle:
             arrs.append(a)
         if self.lib.or_set_D(self.h, deg, *[_p(a) for a in arrs]) != 0:
             raise ValueError("D degree out of range")
+
+    def set_source(self, g, gamma: float = 0.0):
+        """F(x, t) = exp(gamma t) g(x), g [ny][nx] at the cell centres; None removes it.
+        Takes effect for the next set_phi (initialisation) and step."""
+        if g is None:
+            self.lib.or_set_source(self.h, None, 0.0)
+            return
+        self._src = _f64(g).reshape(self.ny, self.nx)
+        self.lib.or_set_source(self.h, _p(self._src), float(gamma))
 
     @property
     def constants(self) -> dict:

@@ -155,6 +155,8 @@ class Problem:
     steps: int = 1
     exact: Optional[Callable] = None         # (x, y, t) -> phi, or None
     seed: Optional[int] = None
+    src_g: Optional[np.ndarray] = None       # source F = exp(src_gamma t) src_g, [ny][nx]
+    src_gamma: float = 0.0
 
     @property
     def nx(self) -> int:
@@ -334,6 +336,41 @@ def random_problem(seed: int, nx: int, ny: int, q: int = 9, bcx: int = PERIODIC,
     p.exact = lambda x, y, t: 0.5 + amp * np.sin(2.0 * np.asarray(x) + 3.0 * np.asarray(y)
                                                  + 5.0 * t)
     return p
+
+
+def source_wave_problem(n=200, Pe=100.0, u=(0.1, 0.1), L=2.0, c=1.0, cfl=0.5, t_end=3.0,
+                        q=9, rate=None, name="source_wave") -> Problem:
+    """Example 4.1: phi_t + div(u phi) = alpha lap(phi) + F on [0, 2]^2, periodic,
+    alpha = L u_x / Pe, F = exp(g t) [sin(pi(x+y)) + pi(u_x+u_y) cos(pi(x+y))] with
+    g = 1 - 2 pi^2 alpha (eq. 4.1.3), phi_0 = sin(pi(x+y)) (eq. 4.1.4), exact
+    solution exp(g t) sin(pi(x+y)) (eq. 4.1.5); B = u phi, D = phi I.
+
+    rate: another growth rate g of the same exact form; the source is then
+    exp(g t) [(g + 2 pi^2 alpha) sin(pi(x+y)) + pi(u_x+u_y) cos(pi(x+y))]."""
+    alpha = L * u[0] / Pe
+    gam = 1.0 - 2.0 * math.pi ** 2 * alpha if rate is None else float(rate)
+    xf = uniform_faces(n, 0.0, L)
+    p = Problem(name=name, xf=xf, yf=xf.copy(), q=q, c=c, cfl=cfl, alpha=alpha,
+                bx=(0.0, u[0]), by=(0.0, u[1]), dxx=(0.0, 1.0), dxy=(0.0, 0.0),
+                dyy=(0.0, 1.0))
+    p.exact = lambda x, y, t: math.exp(gam * t) * np.sin(math.pi * (np.asarray(x) + np.asarray(y)))
+    X, Y = p.mesh()
+    p.phi0 = p.exact(X, Y, 0.0)
+    p.src_g = ((gam + 2.0 * math.pi ** 2 * alpha) * np.sin(math.pi * (X + Y))
+               + math.pi * (u[0] + u[1]) * np.cos(math.pi * (X + Y)))
+    p.src_gamma = gam
+    p.steps = int(round(t_end / p.dt()))
+    return p
+
+
+def random_source(seed: int, p: Problem, amp: float = 0.5):
+    """A smooth seeded source shape G [ny][nx] and rate gamma for property tests."""
+    rng = np.random.default_rng(seed)
+    X, Y = p.mesh()
+    wn = 2 * math.pi if p.bcx == PERIODIC and p.bcy == PERIODIC else math.pi
+    g = amp * cosine_field(X, Y, seed + 29, modes=3, total=1.0, wavenumber=wn,
+                           phases=(p.bcx == PERIODIC and p.bcy == PERIODIC))
+    return g + float(rng.uniform(-0.2, 0.2)), float(rng.uniform(-1.0, 1.0))
 
 
 def workload(name: str, **kw):
