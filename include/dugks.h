@@ -66,7 +66,7 @@
 extern "C" {
 #endif
 
-#define DUGKS_ABI_VERSION 1
+#define DUGKS_ABI_VERSION 2
 #define DUGKS_MAX_DEG 4        /* B and D: polynomials in phi of degree <= 4 */
 
 /* return codes */
@@ -170,9 +170,20 @@ int dugks_set_B(dugks_ctx* ctx, int deg, const double* bx, const double* by);
  * With q = 5 only D = phi I is accepted (Remark 3).  Errors: E_ARG, E_UNSUPPORTED. */
 int dugks_set_D(dugks_ctx* ctx, int deg, const double* dxx, const double* dxy, const double* dyy);
 
-/* Source term F of eq. 2.1.  Only F_dev == NULL (F = 0) is built; anything
- * else returns E_UNSUPPORTED. */
-int dugks_set_source(dugks_ctx* ctx, const void* F_dev);
+/* Source term F of eq. 2.1, F(x, t) = exp(gamma t) G(x), with G given at the
+ * cell centres: g_dev is a device array [ny][nx] of binary64 values,
+ * caller-owned, read by every later initialisation, step and read-out (keep it
+ * alive and unchanged while the source is set); g_dev == NULL removes the
+ * source.  Its distributions are F_i = w_i F (eq. 2.3) and, since
+ * C = int B'B'^T, R_i = w_i c_i.B'(phi) F / c_s^2 (Remark 3); they enter
+ * through the shifted distributions of eqs. 2.24-2.27, so that
+ * phi = sum_i f~_i + dt F / 2.  F at a face is the linear interpolation of G
+ * between the two cell centres (as eq. 2.20), at t_n + h; a ghost cell takes
+ * the G of the cell whose distribution it copies.  Set the source before
+ * dugks_set_phi: the initial f~ is E(phi) - dt (F_i + R_i) / 2.  Steps with a
+ * source are launched one by one (no graph replay).  Errors: E_UNSUPPORTED
+ * (16-bit storage or the plain kernel), E_ARG (gamma not finite), E_HIP. */
+int dugks_set_source(dugks_ctx* ctx, const double* g_dev, double gamma);
 
 /* Dirichlet data: ring_dev (device, caller-owned, must outlive the steps)
  * holds nsteps rings of 2(nx+ny)+4 binary64 values, phi at the ghost
@@ -182,9 +193,9 @@ int dugks_set_source(dugks_ctx* ctx, const void* F_dev);
  * (j = 0..ny-1).  Stepping past nsteps returns E_STATE.  Errors: E_ARG. */
 int dugks_set_dirichlet(dugks_ctx* ctx, const double* ring_dev, int nsteps);
 
-/* Initialise f~ = E(phi) (Sec. 4) from phi [ny][nx] (binary64, host if
- * on_device == 0, else device) and reset step and time to 0.  Errors: E_STATE
- * (not bound), E_HIP. */
+/* Initialise f~ = E(phi) (Sec. 4; with a source E(phi) - dt (F_i + R_i) / 2)
+ * from phi [ny][nx] (binary64, host if on_device == 0, else device) and reset
+ * step and time to 0.  Errors: E_STATE (not bound), E_HIP. */
 int dugks_set_phi(dugks_ctx* ctx, const double* phi, int on_device);
 
 /* Set f~ directly from [q][ny][nx] binary64 values (encoded to the storage
@@ -195,8 +206,9 @@ int dugks_set_f(dugks_ctx* ctx, const double* f, int on_device);
  * E_STATE (not initialised, Dirichlet data exhausted), E_HIP. */
 int dugks_step(dugks_ctx* ctx, int nsteps);
 
-/* phi = sum_i f~_i (Sec. 2) accumulated in binary64, into out [ny][nx]
- * (host if on_device == 0, else device).  Synchronises. */
+/* phi = sum_i f~_i (Sec. 2; plus dt F / 2 at the current time with a source)
+ * accumulated in binary64, into out [ny][nx] (host if on_device == 0, else
+ * device).  Synchronises. */
 int dugks_get_phi(dugks_ctx* ctx, double* out, int on_device);
 
 /* f~ decoded to binary64 [q][ny][nx].  Synchronises. */
@@ -260,6 +272,11 @@ size_t dugks_batch_workspace_bytes(const dugks_batch* b);
 int dugks_batch_bind(dugks_batch* b, void* dev_workspace, size_t bytes, void* hip_stream);
 /* f~ = E(phi) for instance i (phi [ny_i][nx_i]); resets the batch clock. */
 int dugks_batch_set_phi(dugks_batch* b, int i, const double* phi, int on_device);
+/* Source of instance i, as dugks_set_source (g_dev [ny_i][nx_i]).  A launch
+ * over a batch in which some instance has a source evaluates the source path
+ * for every instance; those without one read G = 0 and give the same result
+ * as without it.  Errors: E_ARG (bad index), as dugks_set_source. */
+int dugks_batch_set_source(dugks_batch* b, int i, const double* g_dev, double gamma);
 int dugks_batch_autotune(dugks_batch* b, int trial_steps);
 int dugks_batch_set_launch(dugks_batch* b, int rows_per_wave, int waves_per_block, int schedule,
                            int xcd_remap);

@@ -89,6 +89,9 @@ class Solver:
             L.check(self.lib.dugks_bind(self.h, C.c_void_p(self._ws_ptr), nbytes,
                                         _stream_handle(self.device)), self.h, "dugks_bind")
         self._ring = None
+        self._src = None
+        if getattr(problem, "src_g", None) is not None:
+            self.set_source(problem.src_g, problem.src_gamma)
 
     # -- coefficients
     def set_B(self, bx, by):
@@ -109,6 +112,18 @@ class Solver:
         self._ring = t
         L.check(self.lib.dugks_set_dirichlet(self.h, C.c_void_p(t.data_ptr()), int(t.shape[0])),
                 self.h, "dugks_set_dirichlet")
+
+    def set_source(self, g, gamma=0.0):
+        """F(x, t) = exp(gamma t) g(x), g [ny][nx] at the cell centres (kept alive
+        here); None removes it.  Call before set_phi."""
+        if g is None:
+            self._src = None
+            L.check(self.lib.dugks_set_source(self.h, None, 0.0), self.h, "dugks_set_source")
+            return
+        t = self._dev64(g, (self.ny, self.nx))
+        L.check(self.lib.dugks_set_source(self.h, C.c_void_p(t.data_ptr()), float(gamma)), self.h,
+                "dugks_set_source")
+        self._src = t
 
     # -- state
     def _dev64(self, a, shape):
@@ -240,6 +255,10 @@ class Batch:
             self._ws_ptr = (self.workspace.data_ptr() + 255) & ~255
             L.check(self.lib.dugks_batch_bind(self.h, C.c_void_p(self._ws_ptr), nbytes,
                                               _stream_handle(self.device)), self.h, "dugks_batch_bind")
+        self._src = {}
+        for k, pb in enumerate(self.problems):
+            if getattr(pb, "src_g", None) is not None:
+                self.set_source(k, pb.src_g, pb.src_gamma)
 
     def __len__(self):
         return len(self.problems)
@@ -251,6 +270,19 @@ class Batch:
         L.check(self.lib.dugks_batch_set_phi(self.h, i, C.c_void_p(t.data_ptr()), 1), self.h,
                 "dugks_batch_set_phi")
         del pb
+
+    def set_source(self, i, g, gamma=0.0):
+        """Source of instance i (see Solver.set_source); None removes it."""
+        torch = _torch()
+        if g is None:
+            self._src.pop(i, None)
+            L.check(self.lib.dugks_batch_set_source(self.h, i, None, 0.0), self.h,
+                    "dugks_batch_set_source")
+            return
+        t = torch.from_numpy(np.ascontiguousarray(g, dtype=np.float64)).to(self.device).contiguous()
+        L.check(self.lib.dugks_batch_set_source(self.h, i, C.c_void_p(t.data_ptr()), float(gamma)),
+                self.h, "dugks_batch_set_source")
+        self._src[i] = t
 
     def set_all_phi(self):
         for i, pb in enumerate(self.problems):

@@ -10,7 +10,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdugks.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 MAX_DEG = 4
 OK, E_ARG, E_STATE, E_HIP, E_UNSTABLE, E_UNSUPPORTED, E_NOMEM, E_FORMAT = 0, -1, -2, -3, -4, -5, -6, -7
 F64, F32, F16NEQ, BF16NEQ = 0, 1, 2, 3
@@ -62,7 +62,7 @@ SIGNATURES = {
     "dugks_bind": (_int, [_vp, _vp, _sz, _vp]),
     "dugks_set_B": (_int, [_vp, _int, _dp, _dp]),
     "dugks_set_D": (_int, [_vp, _int, _dp, _dp, _dp]),
-    "dugks_set_source": (_int, [_vp, _vp]),
+    "dugks_set_source": (_int, [_vp, _vp, C.c_double]),
     "dugks_set_dirichlet": (_int, [_vp, _vp, _int]),
     "dugks_set_phi": (_int, [_vp, _vp, _int]),
     "dugks_set_f": (_int, [_vp, _vp, _int]),
@@ -81,6 +81,7 @@ SIGNATURES = {
     "dugks_batch_workspace_bytes": (_sz, [_vp]),
     "dugks_batch_bind": (_int, [_vp, _vp, _sz, _vp]),
     "dugks_batch_set_phi": (_int, [_vp, _int, _vp, _int]),
+    "dugks_batch_set_source": (_int, [_vp, _int, _vp, C.c_double]),
     "dugks_batch_autotune": (_int, [_vp, _int]),
     "dugks_batch_set_launch": (_int, [_vp, _int, _int, _int, _int]),
     "dugks_batch_step": (_int, [_vp, _int]),

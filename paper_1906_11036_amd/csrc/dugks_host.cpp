@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <math.h>
+
+#include <cmath>
 #include <stdint.h>
 #include <string.h>
 
@@ -37,6 +39,9 @@ struct Instance {
   std::vector<double> colgeo, rowgeo, widths;
   std::vector<float> colgeo_f, rowgeo_f;
   double e[kMaxQ][kMaxCoef] = {{0}};
+  double bp[2][kRhoCoef] = {{0}};         // c B'(phi) / cs2 per axis, see InstDev
+  const double* src_g = nullptr;          // source G [ny][nx] (device, caller-owned)
+  double src_gamma = 0.0;
   // workspace offsets
   size_t off_buf[2] = {0, 0}, off_colgeo = 0, off_rowgeo = 0, off_colgeo_f = 0, off_rowgeo_f = 0,
          off_widths = 0, off_slots = 0, off_flags = 0;
@@ -209,6 +214,13 @@ static void equilibrium_polys(Instance& in) {
     }
   }
   in.ncoef = deg + 1;
+  // F_i + R_i = F w_i (1 + c_i.B'(phi) / cs2) (eq. 2.3, Remark 3) with
+  // B'(phi) = sum_{k>=1} k b_k phi^(k-1); the kernels take c B' / cs2 per axis
+  memset(in.bp, 0, sizeof(in.bp));
+  for (int m = 0; m < kRhoCoef && m + 1 <= in.bdeg; ++m) {
+    in.bp[0][m] = c * (m + 1) * in.bx[m + 1] / cs2;
+    in.bp[1][m] = c * (m + 1) * in.by[m + 1] / cs2;
+  }
 }
 
 static int template_ncoef(int ncoef) { return ncoef <= 2 ? 2 : (ncoef <= 4 ? 4 : 8); }
@@ -245,6 +257,26 @@ struct Engine {
     int m = 2;
     for (auto& in : inst) m = std::max(m, template_ncoef(in.ncoef));
     return m;
+  }
+  bool any_source() const {
+    for (auto& in : inst)
+      if (in.src_g != nullptr) return true;
+    return false;
+  }
+  // A source on instance k (g == null removes it).  Sources run in binary64 /
+  // binary32 storage with the fused kernel.
+  int set_source(int k, const double* g, double gamma) {
+    if (g != nullptr) {
+      if (neq()) return fail(DUGKS_E_UNSUPPORTED, "sources need binary64 or binary32 storage");
+      if (plain) return fail(DUGKS_E_UNSUPPORTED, "the plain kernel takes no source");
+      if (!std::isfinite(gamma)) return fail(DUGKS_E_ARG, "source rate is not finite");
+      if (sizeof(double) * (double)inst[k].cells() >= 4294967296.0)
+        return fail(DUGKS_E_ARG, "source array exceeds 4 GiB");
+    }
+    inst[k].src_g = g;
+    inst[k].src_gamma = g ? gamma : 0.0;
+    drop_graph();
+    return bound() ? upload_tables() : DUGKS_OK;
   }
   bool any_dirichlet() const {
     for (auto& in : inst)
@@ -333,6 +365,19 @@ struct Engine {
           d.e[i][m] = in.e[i][m];
           d.ef[i][m] = (float)d.e[i][m];
         }
+      d.src_g = in.src_g;
+      d.src_bytes = in.src_g ? (unsigned)(sizeof(double) * in.cells()) : 0u;
+      d.src_gamma = in.src_gamma;
+      d.dt = in.dt;
+      d.lambda = in.lambda;
+      d.half_dt = 0.5 * in.dt;
+      d.half_h = 0.5 * in.h;
+      d.lambdaf = (float)d.lambda; d.half_dtf = (float)d.half_dt; d.half_hf = (float)d.half_h;
+      for (int a = 0; a < 2; ++a)
+        for (int m = 0; m < kRhoCoef; ++m) {
+          d.bp[a][m] = in.bp[a][m];
+          d.bpf[a][m] = (float)in.bp[a][m];
+        }
     }
   }
 
@@ -412,6 +457,7 @@ struct Engine {
     a.storage = storage;
     a.ncoef = ncoef_launch();
     a.persistent_blocks = persistent_blocks;
+    a.src = any_source() ? 1 : 0;
     return a;
   }
 
@@ -464,7 +510,9 @@ struct Engine {
           (in.ring == nullptr || step + nsteps > in.ring_steps))
         return fail(DUGKS_E_STATE, "Dirichlet data does not cover the requested steps");
     int remaining = nsteps;
-    const bool graphable = use_graph && !plain && !any_dirichlet();
+    // captured launches keep their step argument: steps whose kernels read the
+    // step's time (Dirichlet rings, sources) launch one by one
+    const bool graphable = use_graph && !plain && !any_dirichlet() && !any_source();
     while (remaining > 0) {
       if (need_measure) {
         int rc = enqueue_step(step, stream, true);
@@ -607,7 +655,7 @@ struct Engine {
     if (!out) return fail(DUGKS_E_ARG, "out is NULL");
     const Instance& in = inst[k];
     return read_out((size_t)in.cells() * sizeof(double), out, on_device, [&](double* dst) {
-      return launch_get_phi(dev_inst(k), host_table[k], dst, (int)(step & 1), stream);
+      return launch_get_phi(dev_inst(k), host_table[k], dst, (int)(step & 1), step, stream);
     });
   }
 
@@ -623,7 +671,7 @@ struct Engine {
   int reduce(int k, const double* ref, double out[8], unsigned* flags, float slots[4]) {
     if (!bound() || !initialised) return fail(DUGKS_E_STATE, "no state");
     Instance& in = inst[k];
-    int rc = launch_reduce_widths(dev_inst(k), host_table[k], ref, (int)(step & 1),
+    int rc = launch_reduce_widths(dev_inst(k), host_table[k], ref, (int)(step & 1), step,
                                   (const double*)(ws + in.off_widths), (double*)(ws + off_partial),
                                   (double*)(ws + off_redout), stream);
     if (rc) return fail(DUGKS_E_HIP, "reduce launch failed");
@@ -866,10 +914,9 @@ int dugks_set_D(dugks_ctx* ctx, int deg, const double* dxx, const double* dxy, c
   return rc;
 }
 
-int dugks_set_source(dugks_ctx* ctx, const void* F_dev) {
+int dugks_set_source(dugks_ctx* ctx, const double* g_dev, double gamma) {
   GUARD_CTX(ctx);
-  if (F_dev != nullptr) return ctx->fail(DUGKS_E_UNSUPPORTED, "source terms are not built (F = 0 only)");
-  return DUGKS_OK;
+  return ctx->set_source(0, g_dev, gamma);
 }
 
 int dugks_set_dirichlet(dugks_ctx* ctx, const double* ring_dev, int nsteps) {
@@ -1083,6 +1130,11 @@ int dugks_batch_set_phi(dugks_batch* b, int i, const double* phi, int on_device)
   return b->set_phi(i, phi, on_device);
 }
 
+int dugks_batch_set_source(dugks_batch* b, int i, const double* g_dev, double gamma) {
+  GUARD_BATCH(b);
+  if (i < 0 || i >= (int)b->inst.size()) return b->fail(DUGKS_E_ARG, "instance index");
+  return b->set_source(i, g_dev, gamma);
+}
 int dugks_batch_autotune(dugks_batch* b, int trial_steps) {
   GUARD_BATCH(b);
   return b->autotune(trial_steps);

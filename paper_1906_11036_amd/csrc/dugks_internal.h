@@ -20,7 +20,7 @@ constexpr int kMaxCoef = 8;     // E_i(phi) has degree <= 7 (C has degree 2*4-1)
 constexpr int kStripLanes = 64; // one wave covers 64 columns ...
 constexpr int kStripCols = 62;  // ... of which 62 are updated; lanes 0 and 63 are halo
 constexpr int kGeo = 5;
-
+constexpr int kRhoCoef = 4;     // B'(phi) has degree <= 3
 
 // Per-instance constants and pointers, read by the kernels with scalar loads.
 //
@@ -31,6 +31,15 @@ constexpr int kGeo = 5;
 //   phi_b = b1 sum_i gbar_i                                    (gbar = face value of g)
 //   F = f_b / b3 = (a3 b1 / b3) gbar + E(phi_b)                (eq. 2.22 over b3)
 // and the update factor of each column / row carries the b3 back.
+//
+// With a source F(x, t) = exp(gamma t) G(x) (eq. 2.1) its distributions are
+// S_i = F_i + R_i = F rho_i(phi), rho_i = w_i (1 + c_i.B'(phi) / c_s^2) (eq. 2.3,
+// Remark 3), evaluated as w_i (1 + e_xi bp_x(phi) + e_yi bp_y(phi)) with e_i the
+// integer lattice directions and bp = c B' / c_s^2; eqs. 2.25 / 2.27 add
+// lambda S to g and to F:
+//   phi = sum f~ + dt F / 2,  g += lambda F rho(phi),
+//   phi_b = b1 sum gbar + h F_b / 2,  F += lambda F_b rho(phi_b),
+// with F_b the linear interpolation of G between the two centres, at t + h.
 struct alignas(64) InstDev {
   void* buf[2];            // ping-pong f~ buffers
   const double* colgeo;    // (nx+2) x kGeo doubles, column c = -1..nx at [(c+1)*kGeo]
@@ -52,6 +61,13 @@ struct alignas(64) InstDev {
   // E_i(phi) = sum_k e[i][k] phi^k  (eq. 2.3 with C = int_0^phi B'B'^T)
   double e[kMaxQ][kMaxCoef];
   float ef[kMaxQ][kMaxCoef];
+  // source (src_g == null: none); G [ny][nx] binary64, caller-owned
+  const double* src_g;
+  unsigned src_bytes;       // nx * ny * 8
+  double src_gamma, dt, lambda, half_dt, half_h;
+  float lambdaf, half_dtf, half_hf;
+  double bp[2][kRhoCoef];    // c B'_x / c_s^2 and c B'_y / c_s^2 as polynomials in phi
+  float bpf[2][kRhoCoef];
 };
 
 // One unit of work: instance, first interior column of the strip, row range.
@@ -76,6 +92,7 @@ struct StepArgs {
   int parity;               // index of the buffer read by this step
   long long step;           // step index of the input state
   int q, storage, ncoef;    // template selectors, uniform over the launch
+  int src;                  // some instance has a source
   int persistent_blocks;    // blocks of the persistent schedule
 };
 
@@ -87,14 +104,17 @@ int launch_init_eq(const InstDev* d, const InstDev& h, const double* phi, int pa
 // pass 0: max |f~ - E| into slots[slot]; pass 1: encode f~ with that slot's scale
 int launch_set_f_pass(const InstDev* d, const InstDev& h, const double* f, int parity, int pass,
                       int slot, void* stream);
-int launch_get_phi(const InstDev* d, const InstDev& h, double* out, int parity, void* stream);
+// phi at step `step` (the source term, if any, is evaluated at t = step dt)
+int launch_get_phi(const InstDev* d, const InstDev& h, double* out, int parity, long long step,
+                   void* stream);
 int launch_get_f(const InstDev* d, const InstDev& h, double* out, int parity, long long step,
                  void* stream);
 // Sums over cells into out[0..7] (device): [0] mass, [1] sum|phi-ref|, [2] sum|ref|,
 // [3] sum (phi-ref)^2 |V|, [4] sum ref^2 |V|, [5] non-finite cells.  partial
 // holds reduce_partials() * 8 doubles; widths = dx[0..nx) then dy[0..ny).
 int launch_reduce_widths(const InstDev* d, const InstDev& h, const double* ref, int parity,
-                         const double* widths, double* partial, double* out, void* stream);
+                         long long step, const double* widths, double* partial, double* out,
+                         void* stream);
 int reduce_partials();
 int launch_fill_u32(unsigned* p, unsigned v, long long n, void* stream);
 

@@ -46,6 +46,10 @@ __host__ __device__ constexpr int lat_cx(int k) {
 __host__ __device__ constexpr int lat_cy(int k) {
   return (k == 2 || k == 5 || k == 6) ? 1 : ((k == 4 || k == 7 || k == 8) ? -1 : 0);
 }
+// lattice weights: D2Q9 4/9, 1/9 (x4), 1/36 (x4); D2Q5 1/3, 1/6 (x4)
+template <int Q> __host__ __device__ constexpr double lat_w(int k) {
+  return Q == 9 ? (k == 0 ? 4.0 / 9.0 : (k <= 4 ? 1.0 / 9.0 : 1.0 / 36.0)) : (k == 0 ? 1.0 / 3.0 : 1.0 / 6.0);
+}
 // reversal of the x (resp. y) component: the specular mirror of a wall
 __host__ __device__ constexpr int mir_x(int k) {
   return k == 1 ? 3 : k == 3 ? 1 : k == 5 ? 6 : k == 6 ? 5 : k == 7 ? 8 : k == 8 ? 7 : k;
@@ -130,6 +134,10 @@ template <> struct Coef<double> {
   __device__ static double kg(const InstDev* I) { return I->kg; }
   __device__ static const double* col(const InstDev* I) { return I->colgeo; }
   __device__ static const double* row(const InstDev* I) { return I->rowgeo; }
+  __device__ static const double* bp(const InstDev* I, int a) { return I->bp[a]; }
+  __device__ static double lambda(const InstDev* I) { return I->lambda; }
+  __device__ static double half_dt(const InstDev* I) { return I->half_dt; }
+  __device__ static double half_h(const InstDev* I) { return I->half_h; }
 };
 template <> struct Coef<float> {
   __device__ static const float* e(const InstDev* I, int k) { return I->ef[k]; }
@@ -140,6 +148,10 @@ template <> struct Coef<float> {
   __device__ static float kg(const InstDev* I) { return I->kgf; }
   __device__ static const float* col(const InstDev* I) { return I->colgeo_f; }
   __device__ static const float* row(const InstDev* I) { return I->rowgeo_f; }
+  __device__ static const float* bp(const InstDev* I, int a) { return I->bpf[a]; }
+  __device__ static float lambda(const InstDev* I) { return I->lambdaf; }
+  __device__ static float half_dt(const InstDev* I) { return I->half_dtf; }
+  __device__ static float half_h(const InstDev* I) { return I->half_hf; }
 };
 
 // p(x) = sum_{m < NC} c[m] x^m by Horner's rule
@@ -177,6 +189,41 @@ template <typename T, int Q, int NC> struct Eq {
   __device__ __forceinline__ T E(int k, T x) const {
     if constexpr (kHeld) return horner<NC>(c[k], x);
     else return horner<NC>(Coef<T>::e(I, k), x);
+  }
+};
+
+// Source constants of an instance (eq. 2.3's F_i and R_i through rho_i, eqs.
+// 2.25 and 2.27); empty without a source.
+template <typename T, int Q, bool SRC> struct SrcEq {
+  __device__ __forceinline__ void load(const InstDev*) {}
+};
+template <typename T, int Q> struct SrcEq<T, Q, true> {
+  T bx[kRhoCoef], by[kRhoCoef];
+  T lam, hdt, hh;
+  __device__ __forceinline__ void load(const InstDev* __restrict__ I) {
+#pragma unroll
+    for (int m = 0; m < kRhoCoef; ++m) {
+      bx[m] = Coef<T>::bp(I, 0)[m];
+      by[m] = Coef<T>::bp(I, 1)[m];
+    }
+    lam = Coef<T>::lambda(I);
+    hdt = Coef<T>::half_dt(I);
+    hh = Coef<T>::half_h(I);
+  }
+  // lambda S_i = lambda F w_i (1 + c_i.B'(x) / c_s^2) for the directions in MASK
+  // (bit k set: direction k wanted)
+  template <unsigned MASK>
+  __device__ __forceinline__ void lam_s(T F, T x, T* out) const {
+    const T lf = lam * F;
+    const T px = horner<kRhoCoef>(bx, x) * lf, py = horner<kRhoCoef>(by, x) * lf;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      if (!((MASK >> k) & 1u)) continue;
+      T v = lf;
+      if (lat_cx(k) != 0) v = lat_cx(k) > 0 ? v + px : v - px;
+      if (lat_cy(k) != 0) v = lat_cy(k) > 0 ? v + py : v - py;
+      out[k] = (T)lat_w<Q>(k) * v;
+    }
   }
 };
 
@@ -270,21 +317,34 @@ struct Scales {
 };
 
 // g = fbar+ / b1 (eq. 2.21) of the source cell and f~+ (eq. 2.23) when wanted.
-template <int Q, int ST, int NC>
+// With a source, Fc = F at the cell centre at t_n: phi = sum f~ + dt Fc / 2 and
+// g gains lambda Fc rho(phi) (eqs. 2.25, 2.27).
+template <int Q, int ST, int NC, bool SRC = false>
 __device__ __forceinline__ void cell_g(const InstDev* __restrict__ I,
                                        const Eq<typename Stor<ST>::T, Q, NC>& eq,
                                        const Raw<Q, ST>& r, const Scales& sc,
                                        typename Stor<ST>::T* g, typename Stor<ST>::T* ftp,
-                                       bool want_ftp, typename Stor<ST>::T& phi_out) {
+                                       bool want_ftp, typename Stor<ST>::T& phi_out,
+                                       const SrcEq<typename Stor<ST>::T, Q, SRC>& se = {},
+                                       typename Stor<ST>::T Fc = 0) {
   using T = typename Stor<ST>::T;
+  static_assert(!SRC || !Stor<ST>::neq, "sources run in binary64 / binary32 storage");
   if constexpr (!Stor<ST>::neq) {
     double phi = 0.0;  // phi = sum_i f~_i (Sec. 2), binary64
 #pragma unroll
     for (int k = 0; k < Q; ++k) phi += (double)r.v[k];
+    if constexpr (SRC) phi += (double)se.hdt * (double)Fc;
     const T p = (T)phi;
     const T ra = eq.ra;
+    if constexpr (SRC) {
+      T ls[Q];
+      se.template lam_s<(1u << Q) - 1u>(Fc, p, ls);
 #pragma unroll
-    for (int k = 0; k < Q; ++k) g[k] = fma(ra, r.v[k], eq.E(k, p));
+      for (int k = 0; k < Q; ++k) g[k] = fma(ra, r.v[k], eq.E(k, p) + ls[k]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) g[k] = fma(ra, r.v[k], eq.E(k, p));
+    }
     if (want_ftp) {
       const T kg = eq.kg;
 #pragma unroll
@@ -359,14 +419,26 @@ __device__ __forceinline__ int src_index(int i, int n, int bc) {
   return i < 0 ? 0 : n - 1;
 }
 
+// Directions with a velocity component normal to an x-face (NRM 0) or a
+// y-face (NRM 1), as a bit mask.
+template <int Q, int NRM> constexpr unsigned normal_mask() {
+  unsigned m = 0;
+  for (int k = 0; k < Q; ++k)
+    if ((NRM == 0 ? lat_cx(k) : lat_cy(k)) != 0) m |= 1u << k;
+  return m;
+}
+
 // Half-step interface distribution (eq. 2.20, eq. 2.19 in the form of eq.
 // 2.26) on g, the interface phi, and F = f_b / b3 (eq. 2.22) for directions
 // with a normal velocity component.  ts[k] = dL + dR, the sum of the two
 // cells' central-difference numerators along the face (directions with a
 // tangential component).  NRM = 0 for x-faces, 1 for y-faces.
-template <int Q, int NC, int NRM, typename T>
+// With a source, Fb = F at the face point at t_n + h: phi_b gains h Fb / 2 and
+// F gains lambda Fb rho(phi_b) (eq. 2.27 solved for f).
+template <int Q, int NC, int NRM, typename T, bool SRC = false>
 __device__ __forceinline__ void face(const Eq<T, Q, NC>& eq, const T* L, const T* R, const T* ts,
-                                     T am, T a0, T ap, T tau, T* out) {
+                                     T am, T a0, T ap, T tau, T* out,
+                                     const SrcEq<T, Q, SRC>& se = {}, T Fb = 0) {
   T gb[Q];
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
@@ -377,13 +449,21 @@ __device__ __forceinline__ void face(const Eq<T, Q, NC>& eq, const T* L, const T
     if (ct != 0) v = fma((T)(-ct) * tau, ts[k], v);
     gb[k] = v;
   }
-  // phi(x_b, t + h) = sum_i fbar_i = b1 sum_i gbar_i
-  const T pb = (T)(dir_sum<Q>(gb) * eq.b1);
+  // phi(x_b, t + h) = sum_i fbar_i = b1 sum_i gbar_i  (+ h F_b / 2)
+  T pb = (T)(dir_sum<Q>(gb) * eq.b1);
+  if constexpr (SRC) pb = fma(se.hh, Fb, pb);
   const T rb = eq.rb;
+  T ls[Q];
+  if constexpr (SRC) se.template lam_s<normal_mask<Q, NRM>()>(Fb, pb, ls);
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
     const int cn = NRM == 0 ? lat_cx(k) : lat_cy(k);
-    if (cn != 0) out[k] = fma(rb, gb[k], eq.E(k, pb));
+    if (cn != 0) {
+      if constexpr (SRC)
+        out[k] = fma(rb, gb[k], eq.E(k, pb) + ls[k]);
+      else
+        out[k] = fma(rb, gb[k], eq.E(k, pb));
+    }
   }
 }
 
@@ -398,15 +478,19 @@ __device__ __forceinline__ int xcd_logical(int b, int nblocks) {
 // ---------------------------------------------------------- fused step
 // GH: the item touches a wall (ghost rules needed); items that do not use a
 // branch-free row computation.
-template <int Q, int ST, int NC, bool GH>
+// SRC: the launch carries a source (an instance without one reads G = 0).
+template <int Q, int ST, int NC, bool GH, bool SRC>
 __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const WorkItem it,
                                           int parity, long long step, int lane, bool measure) {
   using T = typename Stor<ST>::T;
   using C = Coef<T>;
   constexpr int PF = Stor<ST>::neq ? DUGKS_PREFETCH_NEQ : DUGKS_PREFETCH;
   static_assert(PF == 1 || PF == 2, "one or two rows ahead");
+  static_assert(!SRC || PF == 1, "source rows follow the one-row prefetch");
   Eq<T, Q, NC> eq;
   eq.load(I);
+  SrcEq<T, Q, SRC> se;
+  se.load(I);
   const int nx = I->nx, ny = I->ny, pitch = I->pitch, bcx = I->bcx, bcy = I->bcy;
   const unsigned plane = (unsigned)I->plane;
   const __amdgpu_buffer_rsrc_t Rin = rsrc(I->buf[parity], I->buf_bytes);
@@ -434,9 +518,24 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
 
   const double* ring = (I->ring != nullptr) ? I->ring + step * I->ring_len : nullptr;
 
-  auto make_row = [&](const Raw<Q, ST>& raw, int r, T* g, T* ftp, bool want_ftp) {
+  // Source: G of each row's cells (a ghost takes the G of the cell it copies),
+  // scaled by exp(gamma t) at t_n for the cells and at t_n + h for the faces.
+  __amdgpu_buffer_rsrc_t Rg = rsrc(nullptr, 0u);
+  T en = 0, eh = 0;
+  if constexpr (SRC) {
+    Rg = rsrc(I->src_g, I->src_bytes);
+    const double tn = (double)step * I->dt;
+    en = (T)exp(I->src_gamma * tn);
+    eh = (T)exp(I->src_gamma * (tn + I->half_dt));
+  }
+  auto load_gsrc = [&](int r) -> T {
+    return (T)__builtin_bit_cast(
+        double, __builtin_amdgcn_raw_buffer_load_b64(Rg, (unsigned)(src_index(r, ny, bcy) * nx + sc_col) * 8u, 0u, 0));
+  };
+
+  auto make_row = [&](const Raw<Q, ST>& raw, int r, T* g, T* ftp, bool want_ftp, T gsrc) {
     T phi_a;
-    cell_g<Q, ST, NC>(I, eq, raw, sc, g, ftp, want_ftp, phi_a);
+    cell_g<Q, ST, NC, SRC>(I, eq, raw, sc, g, ftp, want_ftp, phi_a, se, en * gsrc);
     if constexpr (!GH) return;
     const bool wall_y = (r < 0 || r >= ny) && bcy != DUGKS_BC_PERIODIC;
     if (wall_y || strip_touches_x_wall) {
@@ -458,13 +557,19 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
   // is a change of register names, not a copy.
   T G[3][Q], LS[3][Q], FT[3][Q], SX[3][Q], FY[3][Q], ts[Q], dy[Q], fW[Q];
   Raw<Q, ST> RW[3];
+  T GQ[3] = {0, 0, 0};   // source G of the row whose raw values sit in RW[.]
 
   // prologue: row y0-1 in slot 2, row y0 in slot 0, the face below row y0 in FY[2]
   load_raw_buf<Q, ST>(RW[2], Rin, plane, row_idx(y0 - 1));
   load_raw_buf<Q, ST>(RW[0], Rin, plane, row_idx(y0));
   load_raw_buf<Q, ST>(RW[1], Rin, plane, row_idx(y0 + 1));
-  make_row(RW[2], y0 - 1, G[2], FT[2], false);
-  make_row(RW[0], y0, G[0], FT[0], true);
+  if constexpr (SRC) {
+    GQ[2] = load_gsrc(y0 - 1);
+    GQ[0] = load_gsrc(y0);
+    GQ[1] = load_gsrc(y0 + 1);
+  }
+  make_row(RW[2], y0 - 1, G[2], FT[2], false, GQ[2]);
+  make_row(RW[0], y0, G[0], FT[0], true, GQ[0]);
   if constexpr (PF == 2)  // two rows in flight ahead of the row being consumed
     load_raw_buf<Q, ST>(RW[2], Rin, plane, row_idx(y0 + 2 <= y1 ? y0 + 2 : y1));
 #pragma unroll
@@ -477,7 +582,8 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
   }
   {
     const CPtr<T> g = rg + (long long)(y0 + 1) * kGeo;
-    face<Q, NC, 1>(eq, G[2], G[0], ts, g[0], g[1], g[2], ctau, FY[2]);
+    face<Q, NC, 1, T, SRC>(eq, G[2], G[0], ts, g[0], g[1], g[2], ctau, FY[2], se,
+                           eh * fma(g[1], GQ[0] - GQ[2], GQ[2]));
   }
 
   bool bad = false, ovf = false;
@@ -489,7 +595,8 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
       load_raw_buf<Q, ST>(RW[s0], Rin, plane, row_idx(j + 3 <= y1 ? j + 3 : y1));
     else
       load_raw_buf<Q, ST>(RW[sm], Rin, plane, row_idx(j + 2 <= y1 ? j + 2 : y1));
-    make_row(RW[sp], j + 1, G[sp], FT[sp], true);
+    if constexpr (SRC) GQ[sm] = load_gsrc(j + 2 <= y1 ? j + 2 : y1);
+    make_row(RW[sp], j + 1, G[sp], FT[sp], true, GQ[sp]);
     const CPtr<T> gj = rg + (long long)(j + 1) * kGeo;   // row j: its S face and factors
     const CPtr<T> gn = rg + (long long)(j + 2) * kGeo;   // row j+1: S face = N face of row j
     const T rtau = gj[3], rk = gj[4];
@@ -502,7 +609,8 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
         ts[k] = SX[s0][k] + SX[sp][k];
       }
     }
-    face<Q, NC, 1>(eq, G[s0], G[sp], ts, gn[0], gn[1], gn[2], ctau, FY[s0]);
+    face<Q, NC, 1, T, SRC>(eq, G[s0], G[sp], ts, gn[0], gn[1], gn[2], ctau, FY[s0], se,
+                           eh * fma(gn[1], GQ[sp] - GQ[s0], GQ[s0]));
     // west face of this lane's cell: left state from lane-1; y-slope numerators
 #pragma unroll
     for (int k = 0; k < Q; ++k)
@@ -510,7 +618,13 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
         dy[k] = G[sp][k] - G[sm][k];
         ts[k] = shr1(dy[k]) + dy[k];
       }
-    face<Q, NC, 0>(eq, LS[s0], G[s0], ts, cam, ca0, cap, rtau, fW);
+    if constexpr (SRC) {
+      const T gl = shr1(GQ[s0]);
+      face<Q, NC, 0, T, SRC>(eq, LS[s0], G[s0], ts, cam, ca0, cap, rtau, fW, se,
+                             eh * fma(ca0, GQ[s0] - gl, gl));
+    } else {
+      face<Q, NC, 0>(eq, LS[s0], G[s0], ts, cam, ca0, cap, rtau, fW);
+    }
     // update (eq. 2.24): f~(t+dt) = f~+ - dt c_i.(flux differences)/width
     T o[Q];
 #pragma unroll
@@ -593,12 +707,14 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
 #ifndef DUGKS_WAVES_PER_EU_F64
 #define DUGKS_WAVES_PER_EU_F64 1
 #endif
-template <int ST> struct Occupancy {
-  static constexpr int value = ST == DUGKS_F64 ? DUGKS_WAVES_PER_EU_F64 : DUGKS_WAVES_PER_EU_F32;
+// The source path holds more per row (G and its window): one wave per SIMD,
+// the full register file, no spills.
+template <int ST, bool SRC> struct Occupancy {
+  static constexpr int value = SRC ? 1 : (ST == DUGKS_F64 ? DUGKS_WAVES_PER_EU_F64 : DUGKS_WAVES_PER_EU_F32);
 };
 
-template <int Q, int ST, int NC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occupancy<ST>::value)))
+template <int Q, int ST, int NC, bool SRC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occupancy<ST, SRC>::value)))
 void k_step(const InstDev* __restrict__ insts,
                                               const WorkItem* __restrict__ items, int nitems,
                                               int parity, long long step, int xcd_remap,
@@ -615,9 +731,9 @@ void k_step(const InstDev* __restrict__ insts,
     const bool wall_x = I->bcx != DUGKS_BC_PERIODIC && (it.x0 == 0 || it.x0 + kStripCols >= I->nx);
     const bool wall_y = I->bcy != DUGKS_BC_PERIODIC && (it.y0 == 0 || it.y1 == I->ny);
     if (wall_x || wall_y)
-      step_item<Q, ST, NC, true>(I, it, parity, step, lane, measure != 0);
+      step_item<Q, ST, NC, true, SRC>(I, it, parity, step, lane, measure != 0);
     else
-      step_item<Q, ST, NC, false>(I, it, parity, step, lane, measure != 0);
+      step_item<Q, ST, NC, false, SRC>(I, it, parity, step, lane, measure != 0);
     if (!persistent) break;
   }
 }
@@ -708,6 +824,14 @@ __device__ __forceinline__ void feq64(const InstDev* __restrict__ I, double phi,
   }
 }
 
+// dt F / 2 at interior cell (i, j) at step `step` (0 without a source): with a
+// source phi = sum f~ + dt F / 2 (eq. 2.25 summed with the moments of eq. 2.7).
+__device__ __forceinline__ double src_phi_shift(const InstDev* __restrict__ I, int i, int j,
+                                                long long step) {
+  if (I->src_g == nullptr) return 0.0;
+  return I->half_dt * exp(I->src_gamma * ((double)step * I->dt)) * I->src_g[(long long)j * I->nx + i];
+}
+
 // 16-bit encode of f~ (binary64 values) at one cell.
 template <int Q, int ST>
 __device__ __forceinline__ void encode_neq(const InstDev* __restrict__ I, char* buf, long long off,
@@ -741,6 +865,14 @@ __global__ void k_init_eq(const InstDev* __restrict__ I, const double* __restric
   if constexpr (!Stor<ST>::neq) {
     double E[Q];
     feq64<Q>(I, p, E);
+    if (I->src_g != nullptr) {
+      // f = E at t = 0 (Omega = 0): f~ = E - dt S / 2 with S_i = G rho_i(phi) (eq. 2.25)
+      const double G = I->src_g[(long long)j * I->nx + i];
+      const double px = horner<kRhoCoef>(I->bp[0], p), py = horner<kRhoCoef>(I->bp[1], p);
+#pragma unroll
+      for (int k = 0; k < Q; ++k)
+        E[k] -= I->half_dt * G * lat_w<Q>(k) * (1.0 + lat_cx(k) * px + lat_cy(k) * py);
+    }
     using T = typename Stor<ST>::T;
 #pragma unroll
     for (int k = 0; k < Q; ++k) ((T*)buf)[k * I->plane + off] = (T)E[k];
@@ -815,7 +947,8 @@ __device__ __forceinline__ void decode(const InstDev* __restrict__ I, const char
 }
 
 template <int Q, int ST>
-__global__ void k_get_phi(const InstDev* __restrict__ I, double* __restrict__ out, int parity) {
+__global__ void k_get_phi(const InstDev* __restrict__ I, double* __restrict__ out, int parity,
+                          long long step) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
   if (i >= I->nx || j >= I->ny) return;
   const long long off = (long long)j * I->pitch + i;
@@ -829,6 +962,7 @@ __global__ void k_get_phi(const InstDev* __restrict__ I, double* __restrict__ ou
     phi = 0.0;
 #pragma unroll
     for (int k = 0; k < Q; ++k) phi += f[k];
+    phi += src_phi_shift(I, i, j, step);
   }
   out[(long long)j * I->nx + i] = phi;
 }
@@ -862,6 +996,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 template <int Q, int ST>
 __global__ __launch_bounds__(kRedThreads) void k_reduce(const InstDev* __restrict__ I,
                                                         const double* __restrict__ ref, int parity,
+                                                        long long step,
                                                         const double* __restrict__ widths,
                                                         double* __restrict__ partial) {
   const long long N = (long long)I->nx * I->ny;
@@ -880,6 +1015,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const InstDev* __restric
       phi = 0.0;
 #pragma unroll
       for (int k = 0; k < Q; ++k) phi += f[k];
+      phi += src_phi_shift(I, i, j, step);
     }
     const double vol = widths[i] * widths[I->nx + j];
     if (!__builtin_isfinite(phi)) {
@@ -940,20 +1076,30 @@ static int launch_step_q_st(const StepArgs& a, const Launch& l, void* stream, in
   if (persistent) blocks = a.persistent_blocks;
   if (blocks <= 0) return 0;
   dim3 grid(blocks), block(64 * wpb);
-  switch (a.ncoef) {
-    case 2:
-      hipLaunchKernelGGL((k_step<Q, ST, 2>), grid, block, 0, S(stream), a.insts, a.items, a.nitems,
-                         a.parity, a.step, l.xcd_remap, persistent, measure);
-      break;
-    case 4:
-      hipLaunchKernelGGL((k_step<Q, ST, 4>), grid, block, 0, S(stream), a.insts, a.items, a.nitems,
-                         a.parity, a.step, l.xcd_remap, persistent, measure);
-      break;
-    default:
-      hipLaunchKernelGGL((k_step<Q, ST, 8>), grid, block, 0, S(stream), a.insts, a.items, a.nitems,
-                         a.parity, a.step, l.xcd_remap, persistent, measure);
-      break;
+#define DUGKS_STEP_LAUNCH(NC_, SRC_)                                                          \
+  hipLaunchKernelGGL((k_step<Q, ST, NC_, SRC_>), grid, block, 0, S(stream), a.insts, a.items, \
+                     a.nitems, a.parity, a.step, l.xcd_remap, persistent, measure)
+  if constexpr (Stor<ST>::neq) {
+    if (a.src) return -1;  // sources run in binary64 / binary32 storage only
+    switch (a.ncoef) {
+      case 2: DUGKS_STEP_LAUNCH(2, false); break;
+      case 4: DUGKS_STEP_LAUNCH(4, false); break;
+      default: DUGKS_STEP_LAUNCH(8, false); break;
+    }
+  } else if (a.src) {
+    switch (a.ncoef) {
+      case 2: DUGKS_STEP_LAUNCH(2, true); break;
+      case 4: DUGKS_STEP_LAUNCH(4, true); break;
+      default: DUGKS_STEP_LAUNCH(8, true); break;
+    }
+  } else {
+    switch (a.ncoef) {
+      case 2: DUGKS_STEP_LAUNCH(2, false); break;
+      case 4: DUGKS_STEP_LAUNCH(4, false); break;
+      default: DUGKS_STEP_LAUNCH(8, false); break;
+    }
   }
+#undef DUGKS_STEP_LAUNCH
   DUGKS_CHECK_LAUNCH();
 }
 
@@ -1032,18 +1178,21 @@ int launch_set_f_pass(const InstDev* d, const InstDev& h, const double* f, int p
 }
 
 template <int Q>
-static int get_phi_q(const InstDev* d, const InstDev& h, double* out, int parity, void* stream) {
+static int get_phi_q(const InstDev* d, const InstDev& h, double* out, int parity, long long step,
+                     void* stream) {
   dim3 grid((h.nx + 255) / 256, h.ny), block(256);
   switch (h.storage) {
-    case DUGKS_F64: hipLaunchKernelGGL((k_get_phi<Q, DUGKS_F64>), grid, block, 0, S(stream), d, out, parity); break;
-    case DUGKS_F32: hipLaunchKernelGGL((k_get_phi<Q, DUGKS_F32>), grid, block, 0, S(stream), d, out, parity); break;
-    case DUGKS_F16NEQ: hipLaunchKernelGGL((k_get_phi<Q, DUGKS_F16NEQ>), grid, block, 0, S(stream), d, out, parity); break;
-    default: hipLaunchKernelGGL((k_get_phi<Q, DUGKS_BF16NEQ>), grid, block, 0, S(stream), d, out, parity); break;
+    case DUGKS_F64: hipLaunchKernelGGL((k_get_phi<Q, DUGKS_F64>), grid, block, 0, S(stream), d, out, parity, step); break;
+    case DUGKS_F32: hipLaunchKernelGGL((k_get_phi<Q, DUGKS_F32>), grid, block, 0, S(stream), d, out, parity, step); break;
+    case DUGKS_F16NEQ: hipLaunchKernelGGL((k_get_phi<Q, DUGKS_F16NEQ>), grid, block, 0, S(stream), d, out, parity, step); break;
+    default: hipLaunchKernelGGL((k_get_phi<Q, DUGKS_BF16NEQ>), grid, block, 0, S(stream), d, out, parity, step); break;
   }
   DUGKS_CHECK_LAUNCH();
 }
-int launch_get_phi(const InstDev* d, const InstDev& h, double* out, int parity, void* stream) {
-  return h.q == 9 ? get_phi_q<9>(d, h, out, parity, stream) : get_phi_q<5>(d, h, out, parity, stream);
+int launch_get_phi(const InstDev* d, const InstDev& h, double* out, int parity, long long step,
+                   void* stream) {
+  return h.q == 9 ? get_phi_q<9>(d, h, out, parity, step, stream)
+                  : get_phi_q<5>(d, h, out, parity, step, stream);
 }
 
 template <int Q>
@@ -1068,20 +1217,21 @@ int reduce_partials() { return kRedBlocks; }
 
 template <int Q>
 static int reduce_q(const InstDev* d, const InstDev& h, const double* ref, int parity,
-                    const double* widths, double* partial, void* stream) {
+                    long long step, const double* widths, double* partial, void* stream) {
   dim3 grid(kRedBlocks), block(kRedThreads);
   switch (h.storage) {
-    case DUGKS_F64: hipLaunchKernelGGL((k_reduce<Q, DUGKS_F64>), grid, block, 0, S(stream), d, ref, parity, widths, partial); break;
-    case DUGKS_F32: hipLaunchKernelGGL((k_reduce<Q, DUGKS_F32>), grid, block, 0, S(stream), d, ref, parity, widths, partial); break;
-    case DUGKS_F16NEQ: hipLaunchKernelGGL((k_reduce<Q, DUGKS_F16NEQ>), grid, block, 0, S(stream), d, ref, parity, widths, partial); break;
-    default: hipLaunchKernelGGL((k_reduce<Q, DUGKS_BF16NEQ>), grid, block, 0, S(stream), d, ref, parity, widths, partial); break;
+    case DUGKS_F64: hipLaunchKernelGGL((k_reduce<Q, DUGKS_F64>), grid, block, 0, S(stream), d, ref, parity, step, widths, partial); break;
+    case DUGKS_F32: hipLaunchKernelGGL((k_reduce<Q, DUGKS_F32>), grid, block, 0, S(stream), d, ref, parity, step, widths, partial); break;
+    case DUGKS_F16NEQ: hipLaunchKernelGGL((k_reduce<Q, DUGKS_F16NEQ>), grid, block, 0, S(stream), d, ref, parity, step, widths, partial); break;
+    default: hipLaunchKernelGGL((k_reduce<Q, DUGKS_BF16NEQ>), grid, block, 0, S(stream), d, ref, parity, step, widths, partial); break;
   }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 int launch_reduce_widths(const InstDev* d, const InstDev& h, const double* ref, int parity,
-                         const double* widths, double* partial, double* out, void* stream) {
-  int rc = h.q == 9 ? reduce_q<9>(d, h, ref, parity, widths, partial, stream)
-                    : reduce_q<5>(d, h, ref, parity, widths, partial, stream);
+                         long long step, const double* widths, double* partial, double* out,
+                         void* stream) {
+  int rc = h.q == 9 ? reduce_q<9>(d, h, ref, parity, step, widths, partial, stream)
+                    : reduce_q<5>(d, h, ref, parity, step, widths, partial, stream);
   if (rc) return rc;
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, S(stream), partial, kRedBlocks, out);
   DUGKS_CHECK_LAUNCH();

@@ -382,6 +382,8 @@ def workload(name: str, **kw):
         "gaussian_hill_4096": lambda: gaussian_hill_problem(
             4096, u=(0.05, 0.02), D=1e-4, steps=1000, name="gaussian_hill_4096", **kw),
         "batch256": lambda: batch_problems(**kw),
+        "source_wave_4096": lambda: source_wave_problem(4096, Pe=1000.0, t_end=0.05,
+                                                        name="source_wave_4096", **kw),
     }
     return table[name]()
 

@@ -89,8 +89,8 @@ def test_calls_before_bind_report_state_errors():
     assert rc == L.OK
     assert lib.dugks_step(h, 1) == L.E_STATE
     assert lib.dugks_set_phi(h, None, 0) == L.E_STATE
-    assert lib.dugks_set_source(h, C.c_void_p(1)) == L.E_UNSUPPORTED
-    assert lib.dugks_set_source(h, None) == L.OK
+    assert lib.dugks_set_source(h, None, 0.0) == L.OK
+    assert lib.dugks_set_source(h, C.c_void_p(8), float("nan")) == L.E_ARG
     assert lib.dugks_set_launch(h, 0, 4, 0, 1) == L.E_ARG
     assert lib.dugks_set_launch(h, 32, 3, 0, 1) == L.E_ARG
     assert lib.dugks_set_launch(h, 32, 2, 1, 0) == L.OK
@@ -128,3 +128,17 @@ def test_invalid_handles():
     assert lib.dugks_step(None, 1) == L.E_ARG
     assert lib.dugks_last_error(None) == b"invalid handle"
     lib.dugks_destroy(None)
+
+
+def test_source_is_refused_where_it_is_not_built():
+    """Sources run in binary64 / binary32 storage with the fused kernel; the
+    host refuses the other combinations before any device work."""
+    lib = L.lib()
+    for kw in (dict(storage=L.F16NEQ), dict(storage=L.BF16NEQ),
+               dict(storage=L.F64, kernel=L.KERNEL_PLAIN)):
+        rc, h = _create(**kw)
+        assert rc == L.OK
+        assert lib.dugks_set_source(h, C.c_void_p(8), 0.5) == L.E_UNSUPPORTED
+        assert "source" in lib.dugks_last_error(h).decode()
+        assert lib.dugks_set_source(h, None, 0.0) == L.OK
+        lib.dugks_destroy(h)
