@@ -1,0 +1,500 @@
+/*
+ * Plain FP64 CPU oracle for one DUGKS time step on three-dimensional lattices
+ * (D3Q15 of eq. 2.28, D3Q19 of eq. 2.6, D3Q7 of Remark 3) of the nonlinear
+ * convection-diffusion equation (Shang, Chai, Wang, Shi, arXiv 1906.11036).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark load this file.  It shares no code,
+ * header, table or constant generator with the HIP library (nor with the
+ * two-dimensional oracle); neither includes or links the other.
+ *
+ * IEEE binary64, built with -O2 -ffp-contract=off, no fast-math, no
+ * intrinsics.  Sums over discrete directions run in index order 0..Q-1.
+ * The step is the one-step summary at the end of Section 2, in the paper's
+ * order, on a Cartesian mesh of nx x ny x nz cells:
+ *   phi -> E (eq. 2.3) -> fbar+ (eq. 2.21), f~+ (eq. 2.13)
+ *   -> fbar+ at each face (eq. 2.20) -> fbar(x_b, t+h) (eqs. 2.19, 2.26)
+ *   -> phi_b = sum fbar -> f(x_b, t+h) (eq. 2.22) -> flux (eq. 2.9)
+ *   -> f~(t+dt) (eq. 2.24) -> phi = sum f~.
+ *
+ * Readings (each also listed in the design notes):
+ *   - the face gradient: the normal derivative is the two-cell difference of
+ *     eq. 2.20; each tangential derivative is the mean of the two adjacent
+ *     cells' central differences along that axis (the 2-D reading, per axis);
+ *   - point values at cell centres stand for cell averages (eq. 2.10);
+ *   - dt = cfl * (smallest cell width along any axis) / c, lambda = alpha/c_s^2;
+ *   - C = int_0^phi B'(s) B'(s)^T ds (Remark 3), integration constant 0;
+ *   - D3Q7: weights 0 (rest) and 1/6 (x6) with c_s^2 = c^2/3 and the linear
+ *     equilibrium E_i = w_i (phi + c_i.B / c_s^2) of Remark 3 (needs D = phi I);
+ *   - walls: periodic (wrapped ghost cell and width) or zero-flux mirror
+ *     (fbar+ of the adjacent interior cell with the wall-normal velocity
+ *     component reversed, width of the adjacent cell), per axis; a ghost shell
+ *     one cell wide, edges and corners included.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define O3_MAXQ 19
+#define O3_MAXDEG 4
+
+enum { O3_PERIODIC = 0, O3_MIRROR = 2 };
+
+/* D3Q15 (eq. 2.28) and D3Q19 (eq. 2.6): the columns of the printed matrices */
+static const int Q15[15][3] = {{0, 0, 0},  {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
+                               {0, 0, 1},  {0, 0, -1},  {1, 1, 1},  {1, 1, -1}, {1, -1, 1},
+                               {-1, 1, 1}, {-1, -1, -1}, {-1, -1, 1}, {-1, 1, -1}, {1, -1, -1}};
+static const int Q19[19][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},   {0, -1, 0},
+                               {0, 0, 1},  {0, 0, -1}, {1, 1, 0},  {-1, -1, 0}, {1, -1, 0},
+                               {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {-1, 0, 1}, {1, 0, -1},
+                               {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+
+typedef struct {
+  int n[3];               /* cells along x, y, z */
+  int q;
+  double c, cfl, alpha;
+  int bc[3];
+  int e[O3_MAXQ][3];      /* integer directions */
+  double cv[O3_MAXQ][3];  /* velocities c e_i */
+  double w[O3_MAXQ], cs2;
+  int mir[3][O3_MAXQ];    /* direction with component a reversed */
+  int bdeg, ddeg;
+  double b[3][O3_MAXDEG + 1];  /* B_a(phi) = sum_k b[a][k] phi^k */
+  double d[3][3][O3_MAXDEG + 1];
+  double lambda, dt, h, a1, b1, a2, b2, a3, b3;
+  double* fc[3];          /* faces, n+1 per axis */
+  double* wd[3];          /* widths of cells -1..n (index +1) */
+  double* cc[3];          /* centres of cells -1..n (index +1) */
+  double* f;              /* f~ [q][nz][ny][nx] */
+  long step;
+  double t;
+} Oracle3;
+
+/* ------------------------------------------------------------ lattice */
+
+static void set_lattice(Oracle3* o) {
+  int i, a, k;
+  o->cs2 = o->c * o->c / 3.0; /* c_s = c / sqrt(3), eqs. 2.28 and 2.6 */
+  for (i = 0; i < o->q; ++i) {
+    for (a = 0; a < 3; ++a) o->e[i][a] = (o->q == 19) ? Q19[i][a] : Q15[i][a];
+    for (a = 0; a < 3; ++a) o->cv[i][a] = o->c * o->e[i][a];
+    if (o->q == 15)
+      o->w[i] = i == 0 ? 2.0 / 9.0 : (i <= 6 ? 1.0 / 9.0 : 1.0 / 72.0);
+    else if (o->q == 19)
+      o->w[i] = i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+    else
+      o->w[i] = i == 0 ? 0.0 : 1.0 / 6.0;
+  }
+  for (a = 0; a < 3; ++a)
+    for (i = 0; i < o->q; ++i) {
+      o->mir[a][i] = -1;
+      for (k = 0; k < o->q; ++k) {
+        int same = 1, b;
+        for (b = 0; b < 3; ++b) {
+          int want = (b == a) ? -o->e[i][b] : o->e[i][b];
+          if (o->e[k][b] != want) same = 0;
+        }
+        if (same) o->mir[a][i] = k;
+      }
+    }
+}
+
+/* ------------------------------------------------------------ equilibrium */
+
+static double poly(const double* p, int deg, double x) {
+  double s = 0.0, m = 1.0;
+  int k;
+  for (k = 0; k <= deg; ++k) { s += p[k] * m; m *= x; }
+  return s;
+}
+
+/* C_ab(phi) = int_0^phi B'_a B'_b ds = sum_{k,l>=1} k l b_ak b_bl phi^(k+l-1)/(k+l-1) */
+static double c_moment(const Oracle3* o, int a, int b, double phi) {
+  double s = 0.0;
+  int k, l, m;
+  for (k = 1; k <= o->bdeg; ++k)
+    for (l = 1; l <= o->bdeg; ++l) {
+      int e = k + l - 1;
+      double p = 1.0;
+      for (m = 0; m < e; ++m) p *= phi;
+      s += (double)(k * l) * o->b[a][k] * o->b[b][l] * p / (double)e;
+    }
+  return s;
+}
+
+/* eq. 2.3: E_i = w_i [phi + c_i.B/cs2 + M:(c_i c_i - cs2 I)/(2 cs2^2)],
+ * M = cs2 D + C - cs2 phi I; D3Q7 uses the linear equilibrium of Remark 3. */
+static void feq(const Oracle3* o, double phi, double* E) {
+  double B[3], M[3][3];
+  int i, a, b;
+  const double cs2 = o->cs2;
+  for (a = 0; a < 3; ++a) B[a] = poly(o->b[a], o->bdeg, phi);
+  if (o->q == 7) {
+    for (i = 0; i < o->q; ++i) {
+      double cb = 0.0;
+      for (a = 0; a < 3; ++a) cb += o->cv[i][a] * B[a];
+      E[i] = o->w[i] * (phi + cb / cs2);
+    }
+    return;
+  }
+  for (a = 0; a < 3; ++a)
+    for (b = 0; b < 3; ++b)
+      M[a][b] = cs2 * poly(o->d[a][b], o->ddeg, phi) + c_moment(o, a, b, phi) - (a == b ? cs2 * phi : 0.0);
+  for (i = 0; i < o->q; ++i) {
+    double cb = 0.0, contr = 0.0;
+    for (a = 0; a < 3; ++a) cb += o->cv[i][a] * B[a];
+    for (a = 0; a < 3; ++a)
+      for (b = 0; b < 3; ++b)
+        contr += M[a][b] * (o->cv[i][a] * o->cv[i][b] - (a == b ? cs2 : 0.0));
+    E[i] = o->w[i] * (phi + cb / cs2 + contr / (2.0 * cs2 * cs2));
+  }
+}
+
+/* ------------------------------------------------------------ geometry */
+
+#define WD(o, a, i) ((o)->wd[a][(i) + 1])
+#define CC(o, a, i) ((o)->cc[a][(i) + 1])
+
+static void build_axis(int n, const double* f, int bc, double* w, double* c) {
+  int i;
+  for (i = 0; i < n; ++i) {
+    w[i + 1] = f[i + 1] - f[i];
+    c[i + 1] = 0.5 * (f[i] + f[i + 1]);
+  }
+  w[0] = bc == O3_PERIODIC ? w[n] : w[1];
+  w[n + 1] = bc == O3_PERIODIC ? w[1] : w[n];
+  c[0] = f[0] - 0.5 * w[0];
+  c[n + 1] = f[n] + 0.5 * w[n + 1];
+}
+
+/* ------------------------------------------------------------ public API */
+
+Oracle3* or3_create(int nx, int ny, int nz, const double* xf, const double* yf, const double* zf,
+                    int q, double c, double cfl, double alpha, int bcx, int bcy, int bcz) {
+  Oracle3* o;
+  int a, i;
+  const double* fs[3] = {xf, yf, zf};
+  int bcs[3] = {bcx, bcy, bcz};
+  double dmin;
+  if (nx < 1 || ny < 1 || nz < 1 || (q != 15 && q != 19 && q != 7) || !(c > 0) || !(cfl > 0) ||
+      !(alpha > 0))
+    return NULL;
+  for (a = 0; a < 3; ++a)
+    if (bcs[a] != O3_PERIODIC && bcs[a] != O3_MIRROR) return NULL;
+  o = (Oracle3*)calloc(1, sizeof(Oracle3));
+  o->n[0] = nx; o->n[1] = ny; o->n[2] = nz;
+  o->q = q; o->c = c; o->cfl = cfl; o->alpha = alpha;
+  set_lattice(o);
+  dmin = 1e300;
+  for (a = 0; a < 3; ++a) {
+    int n = o->n[a];
+    o->bc[a] = bcs[a];
+    o->fc[a] = (double*)malloc(sizeof(double) * (n + 1));
+    memcpy(o->fc[a], fs[a], sizeof(double) * (n + 1));
+    o->wd[a] = (double*)malloc(sizeof(double) * (n + 2));
+    o->cc[a] = (double*)malloc(sizeof(double) * (n + 2));
+    build_axis(n, o->fc[a], bcs[a], o->wd[a], o->cc[a]);
+    for (i = 0; i < n; ++i) if (WD(o, a, i) < dmin) dmin = WD(o, a, i);
+  }
+  o->f = (double*)calloc((size_t)q * nx * ny * nz, sizeof(double));
+  o->lambda = alpha / o->cs2;
+  o->dt = cfl * dmin / c;
+  o->h = 0.5 * o->dt;
+  {
+    double L = o->lambda, dt = o->dt, h = o->h;
+    o->a1 = (2.0 * L - h) / (2.0 * L + dt); /* eq. 2.21 */
+    o->b1 = 3.0 * h / (2.0 * L + dt);
+    o->a2 = (2.0 * L - dt) / (2.0 * L + dt); /* eq. 2.13 */
+    o->b2 = 2.0 * dt / (2.0 * L + dt);
+    o->a3 = 2.0 * L / (2.0 * L + h); /* eq. 2.22 */
+    o->b3 = h / (2.0 * L + h);
+  }
+  return o;
+}
+
+void or3_destroy(Oracle3* o) {
+  int a;
+  if (!o) return;
+  for (a = 0; a < 3; ++a) { free(o->fc[a]); free(o->wd[a]); free(o->cc[a]); }
+  free(o->f);
+  free(o);
+}
+
+/* B_a(phi) = sum_k b[a*(deg+1) + k] phi^k, a = x, y, z */
+int or3_set_B(Oracle3* o, int deg, const double* b) {
+  int a, k;
+  if (deg < 0 || deg > O3_MAXDEG) return -1;
+  memset(o->b, 0, sizeof(o->b));
+  for (a = 0; a < 3; ++a)
+    for (k = 0; k <= deg; ++k) o->b[a][k] = b[a * (deg + 1) + k];
+  o->bdeg = deg;
+  return 0;
+}
+
+/* D(phi): six components xx, yy, zz, xy, xz, yz, each deg+1 coefficients */
+int or3_set_D(Oracle3* o, int deg, const double* d) {
+  static const int AB[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
+  int m, k;
+  if (deg < 0 || deg > O3_MAXDEG) return -1;
+  memset(o->d, 0, sizeof(o->d));
+  for (m = 0; m < 6; ++m)
+    for (k = 0; k <= deg; ++k) {
+      o->d[AB[m][0]][AB[m][1]][k] = d[m * (deg + 1) + k];
+      o->d[AB[m][1]][AB[m][0]][k] = d[m * (deg + 1) + k];
+    }
+  o->ddeg = deg;
+  return 0;
+}
+
+/* lambda, dt, h, a1, b1, a2, b2, a3, b3, cs2 */
+void or3_constants(const Oracle3* o, double* out) {
+  out[0] = o->lambda; out[1] = o->dt; out[2] = o->h;
+  out[3] = o->a1; out[4] = o->b1; out[5] = o->a2; out[6] = o->b2;
+  out[7] = o->a3; out[8] = o->b3; out[9] = o->cs2;
+}
+
+void or3_feq(const Oracle3* o, double phi, double* E) { feq(o, phi, E); }
+
+static size_t ncells(const Oracle3* o) { return (size_t)o->n[0] * o->n[1] * o->n[2]; }
+static size_t cidx(const Oracle3* o, int i, int j, int k) {
+  return ((size_t)k * o->n[1] + j) * o->n[0] + i;
+}
+
+/* Initialisation (Sec. 4): f~ = E(phi) with point values at the centres. */
+void or3_set_phi(Oracle3* o, const double* phi) {
+  size_t c, N = ncells(o);
+  int k;
+  double E[O3_MAXQ];
+  for (c = 0; c < N; ++c) {
+    feq(o, phi[c], E);
+    for (k = 0; k < o->q; ++k) o->f[k * N + c] = E[k];
+  }
+  o->step = 0; o->t = 0.0;
+}
+
+void or3_set_f(Oracle3* o, const double* f) { memcpy(o->f, f, sizeof(double) * o->q * ncells(o)); }
+void or3_get_f(const Oracle3* o, double* f) { memcpy(f, o->f, sizeof(double) * o->q * ncells(o)); }
+double or3_time(const Oracle3* o) { return o->t; }
+
+/* phi = sum_i f~_i (Sec. 2, after eq. 2.13) */
+void or3_get_phi(const Oracle3* o, double* phi) {
+  size_t c, N = ncells(o);
+  int k;
+  for (c = 0; c < N; ++c) {
+    double s = 0.0;
+    for (k = 0; k < o->q; ++k) s += o->f[k * N + c];
+    phi[c] = s;
+  }
+}
+
+/* ------------------------------------------------------------ step */
+
+static int wrap_or_clamp(int i, int n, int bc) {
+  if (i >= 0 && i < n) return i;
+  if (bc == O3_PERIODIC) return (i + n) % n;
+  return i < 0 ? 0 : n - 1;
+}
+
+/* fbar+ = a1 f~ + b1 E(phi) (eq. 2.21) at cell (i, j, k) of the ghost shell */
+static void fbar_plus(const Oracle3* o, int i, int j, int k, double* out) {
+  int idx[3] = {i, j, k}, s[3], a, m;
+  size_t N = ncells(o), c;
+  double ft[O3_MAXQ], E[O3_MAXQ], phi = 0.0, tmp[O3_MAXQ];
+  for (a = 0; a < 3; ++a) s[a] = wrap_or_clamp(idx[a], o->n[a], o->bc[a]);
+  c = cidx(o, s[0], s[1], s[2]);
+  for (m = 0; m < o->q; ++m) { ft[m] = o->f[m * N + c]; phi += ft[m]; }
+  feq(o, phi, E);
+  for (m = 0; m < o->q; ++m) out[m] = o->a1 * ft[m] + o->b1 * E[m];
+  for (a = 0; a < 3; ++a) {
+    int wall = (idx[a] < 0 || idx[a] >= o->n[a]) && o->bc[a] == O3_MIRROR;
+    if (!wall) continue;
+    memcpy(tmp, out, sizeof(tmp));
+    for (m = 0; m < o->q; ++m) out[m] = tmp[o->mir[a][m]];
+  }
+}
+
+/* f~+ = a2 f~ + b2 E(phi) (eq. 2.13) at interior cell c */
+static void ftilde_plus(const Oracle3* o, size_t c, double* out) {
+  size_t N = ncells(o);
+  double ft[O3_MAXQ], E[O3_MAXQ], phi = 0.0;
+  int m;
+  for (m = 0; m < o->q; ++m) { ft[m] = o->f[m * N + c]; phi += ft[m]; }
+  feq(o, phi, E);
+  for (m = 0; m < o->q; ++m) out[m] = o->a2 * ft[m] + o->b2 * E[m];
+}
+
+/* Access to fbar+ of the ghost shell through a callback so that the full
+ * step (a precomputed array) and the sampled step (a local block) share the
+ * face and update code. */
+typedef const double* (*GetG)(const void* ctx, int i, int j, int k);
+
+/* central-difference slope of fbar+ along axis b at cell (i, j, k) */
+static void slope(const Oracle3* o, GetG G, const void* ctx, int i, int j, int k, int b, double* s) {
+  int lo[3] = {i, j, k}, hi[3] = {i, j, k}, m;
+  const double *fm, *fp;
+  double dist;
+  lo[b] -= 1; hi[b] += 1;
+  fm = G(ctx, lo[0], lo[1], lo[2]);
+  fp = G(ctx, hi[0], hi[1], hi[2]);
+  dist = CC(o, b, hi[b]) - CC(o, b, lo[b]);
+  for (m = 0; m < o->q; ++m) s[m] = (fp[m] - fm[m]) / dist;
+}
+
+/* Flux c_n f_b through the face of axis a between the cell below (i, j, k)
+ * minus one along a and the cell (i, j, k): reconstruction (eq. 2.20),
+ * characteristic shift (eq. 2.19 as eq. 2.26), phi_b = sum fbar,
+ * f_b = a3 fbar + b3 E(phi_b) (eq. 2.22), flux (eq. 2.9). */
+static void face_flux(const Oracle3* o, GetG G, const void* ctx, int a, int i, int j, int k,
+                      double* flux) {
+  int L[3] = {i, j, k}, R[3] = {i, j, k}, m, b;
+  const double *fL, *fR;
+  double sL[2][O3_MAXQ], sR[2][O3_MAXQ], fb[O3_MAXQ], E[O3_MAXQ], phib = 0.0, dn, wl;
+  int tb[2], nt = 0;
+  L[a] -= 1;
+  fL = G(ctx, L[0], L[1], L[2]);
+  fR = G(ctx, R[0], R[1], R[2]);
+  dn = CC(o, a, R[a]) - CC(o, a, L[a]);
+  wl = o->fc[a][R[a]] - CC(o, a, L[a]);
+  for (b = 0; b < 3; ++b)
+    if (b != a) {
+      slope(o, G, ctx, L[0], L[1], L[2], b, sL[nt]);
+      slope(o, G, ctx, R[0], R[1], R[2], b, sR[nt]);
+      tb[nt++] = b;
+    }
+  for (m = 0; m < o->q; ++m) {
+    double Gn = (fR[m] - fL[m]) / dn;
+    double v = fL[m] + wl * Gn;
+    double shift = o->cv[m][a] * Gn;
+    int t;
+    for (t = 0; t < 2; ++t) shift += o->cv[m][tb[t]] * 0.5 * (sL[t][m] + sR[t][m]);
+    fb[m] = v - o->h * shift;
+  }
+  for (m = 0; m < o->q; ++m) phib += fb[m];
+  feq(o, phib, E);
+  for (m = 0; m < o->q; ++m) flux[m] = o->cv[m][a] * (o->a3 * fb[m] + o->b3 * E[m]);
+}
+
+/* eq. 2.24 on a Cartesian cell: the surface integral of eq. 2.9 with the
+ * midpoint rule on each of the six faces, over |V| */
+static void update_cell(const Oracle3* o, GetG G, const void* ctx, int i, int j, int k,
+                        double* out) {
+  double ftp[O3_MAXQ], lo[O3_MAXQ], hi[O3_MAXQ], div[O3_MAXQ];
+  int a, m, idx[3] = {i, j, k};
+  for (m = 0; m < o->q; ++m) div[m] = 0.0;
+  for (a = 0; a < 3; ++a) {
+    int up[3] = {i, j, k};
+    up[a] += 1;
+    face_flux(o, G, ctx, a, i, j, k, lo);
+    face_flux(o, G, ctx, a, up[0], up[1], up[2], hi);
+    for (m = 0; m < o->q; ++m) div[m] += (hi[m] - lo[m]) / WD(o, a, idx[a]);
+  }
+  ftilde_plus(o, cidx(o, i, j, k), ftp);
+  for (m = 0; m < o->q; ++m) out[m] = ftp[m] - o->dt * div[m];
+}
+
+typedef struct {
+  const Oracle3* o;
+  double* g;  /* fbar+ on cells -1..n per axis, [(k+1)][(j+1)][(i+1)][q] */
+} FullCtx;
+
+static const double* full_get(const void* ctx, int i, int j, int k) {
+  const FullCtx* F = (const FullCtx*)ctx;
+  const Oracle3* o = F->o;
+  return F->g + ((((size_t)(k + 1) * (o->n[1] + 2)) + (j + 1)) * (o->n[0] + 2) + (i + 1)) * o->q;
+}
+
+static void step_once(Oracle3* o) {
+  const int nx = o->n[0], ny = o->n[1], nz = o->n[2], q = o->q;
+  const size_t N = ncells(o);
+  FullCtx F;
+  double* fn = (double*)malloc(sizeof(double) * N * q);
+  int i, j, k, m;
+  F.o = o;
+  F.g = (double*)malloc(sizeof(double) * (size_t)(nx + 2) * (ny + 2) * (nz + 2) * q);
+#pragma omp parallel for private(i, j)
+  for (k = -1; k <= nz; ++k)
+    for (j = -1; j <= ny; ++j)
+      for (i = -1; i <= nx; ++i) fbar_plus(o, i, j, k, (double*)full_get(&F, i, j, k));
+#pragma omp parallel for private(i, j, m)
+  for (k = 0; k < nz; ++k)
+    for (j = 0; j < ny; ++j)
+      for (i = 0; i < nx; ++i) {
+        double out[O3_MAXQ];
+        update_cell(o, full_get, &F, i, j, k, out);
+        for (m = 0; m < q; ++m) fn[m * N + cidx(o, i, j, k)] = out[m];
+      }
+  memcpy(o->f, fn, sizeof(double) * N * q);
+  free(F.g);
+  free(fn);
+  o->step += 1;
+  o->t += o->dt;
+}
+
+void or3_step(Oracle3* o, int nsteps) {
+  int s;
+  for (s = 0; s < nsteps; ++s) step_once(o);
+}
+
+typedef struct {
+  const Oracle3* o;
+  int ci, cj, ck;
+  double g[3][3][3][O3_MAXQ];  /* fbar+ on the 3^3 block around the cell */
+} LocalCtx;
+
+static const double* local_get(const void* ctx, int i, int j, int k) {
+  const LocalCtx* L = (const LocalCtx*)ctx;
+  return L->g[k - L->ck + 1][j - L->cj + 1][i - L->ci + 1];
+}
+
+/* One step evaluated only at the listed cells (triples i, j, k), without
+ * changing the state; the same face and update code as the full step.
+ * out: [ncells][q]. */
+void or3_step_cells(const Oracle3* o, int ncells_, const int* cells, double* out) {
+  int n, a, b, c;
+  LocalCtx* L = (LocalCtx*)malloc(sizeof(LocalCtx));
+  L->o = o;
+  for (n = 0; n < ncells_; ++n) {
+    int i = cells[3 * n], j = cells[3 * n + 1], k = cells[3 * n + 2];
+    L->ci = i; L->cj = j; L->ck = k;
+    for (c = -1; c <= 1; ++c)
+      for (b = -1; b <= 1; ++b)
+        for (a = -1; a <= 1; ++a) fbar_plus(o, i + a, j + b, k + c, L->g[c + 1][b + 1][a + 1]);
+    update_cell(o, local_get, L, i, j, k, out + (size_t)n * o->q);
+  }
+  free(L);
+}
+
+/* GRE (eq. 4.1, unweighted) and area-weighted relative L2 against phi_a */
+void or3_errors(const Oracle3* o, const double* phi_a, double* gre, double* rel_l2) {
+  int i, j, k, m;
+  size_t N = ncells(o);
+  double num = 0.0, den = 0.0, e2 = 0.0, r2 = 0.0;
+  for (k = 0; k < o->n[2]; ++k)
+    for (j = 0; j < o->n[1]; ++j)
+      for (i = 0; i < o->n[0]; ++i) {
+        size_t c = cidx(o, i, j, k);
+        double phi = 0.0, v = WD(o, 0, i) * WD(o, 1, j) * WD(o, 2, k);
+        for (m = 0; m < o->q; ++m) phi += o->f[m * N + c];
+        num += fabs(phi_a[c] - phi);
+        den += fabs(phi_a[c]);
+        e2 += v * (phi - phi_a[c]) * (phi - phi_a[c]);
+        r2 += v * phi_a[c] * phi_a[c];
+      }
+  *gre = num / den;
+  *rel_l2 = sqrt(e2 / r2);
+}
+
+double or3_mass(const Oracle3* o) {
+  int i, j, k, m;
+  size_t N = ncells(o);
+  double s = 0.0;
+  for (k = 0; k < o->n[2]; ++k)
+    for (j = 0; j < o->n[1]; ++j)
+      for (i = 0; i < o->n[0]; ++i) {
+        size_t c = cidx(o, i, j, k);
+        double phi = 0.0;
+        for (m = 0; m < o->q; ++m) phi += o->f[m * N + c];
+        s += phi * WD(o, 0, i) * WD(o, 1, j) * WD(o, 2, k);
+      }
+  return s;
+}

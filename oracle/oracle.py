@@ -19,17 +19,25 @@ def library_path(openmp: bool = False) -> str:
     return os.path.join(HERE, "liboracle_omp.so" if openmp else "liboracle.so")
 
 
+SRC3 = os.path.join(HERE, "dugks_oracle3d.c")
+
+
+def library_path3(openmp: bool = False) -> str:
+    return os.path.join(HERE, "liboracle3d_omp.so" if openmp else "liboracle3d.so")
+
+
 def build(verbose: bool = False) -> None:
-    """Compile the oracle: plain -O2, no FMA contraction, no fast-math."""
-    for omp in (False, True):
-        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-fPIC",
-               "-shared", "-o", library_path(omp) + ".tmp", SRC, "-lm"]
-        if omp:
-            cmd.insert(1, "-fopenmp")
-        if verbose:
-            print(" ".join(cmd))
-        subprocess.check_call(cmd)
-        os.replace(library_path(omp) + ".tmp", library_path(omp))
+    """Compile the oracles (2-D and 3-D): plain -O2, no FMA contraction, no fast-math."""
+    for src, path in ((SRC, library_path), (SRC3, library_path3)):
+        for omp in (False, True):
+            cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-fPIC",
+                   "-shared", "-o", path(omp) + ".tmp", src, "-lm"]
+            if omp:
+                cmd.insert(1, "-fopenmp")
+            if verbose:
+                print(" ".join(cmd))
+            subprocess.check_call(cmd)
+            os.replace(path(omp) + ".tmp", path(omp))
 
 
 _LIBS = {}

@@ -411,3 +411,125 @@ def random_distributions(seed: int, q: int, ny: int, nx: int, mean: float = 0.5,
             a * np.cos(2 * math.pi * m * X + ph[0]) + b * np.cos(2 * math.pi * n * Y + ph[1]))
         out[k] += 1e-3 * amp * rng.standard_normal((ny, nx))
     return out
+
+
+# ------------------------------------------------------------ three dimensions
+@dataclasses.dataclass
+class Problem3D:
+    """One three-dimensional NCDE instance (D3Q15, D3Q19 or D3Q7).
+
+    b: (B_x, B_y, B_z) coefficient tuples of B(phi) = sum_k b_k phi^k;
+    d: (D_xx, D_yy, D_zz, D_xy, D_xz, D_yz) coefficient tuples of D(phi);
+    bc: per axis PERIODIC or MIRROR."""
+    name: str
+    xf: np.ndarray
+    yf: np.ndarray
+    zf: np.ndarray
+    q: int = 19
+    c: float = 1.0
+    cfl: float = 0.5
+    alpha: float = 1e-3
+    bc: tuple = (PERIODIC, PERIODIC, PERIODIC)
+    b: tuple = ((0.0,), (0.0,), (0.0,))
+    d: tuple = ((0.0, 1.0), (0.0, 1.0), (0.0, 1.0), (0.0,), (0.0,), (0.0,))
+    phi0: Optional[np.ndarray] = None        # [nz][ny][nx]
+    steps: int = 1
+    exact: Optional[Callable] = None         # (x, y, z, t) -> phi
+    seed: Optional[int] = None
+
+    @property
+    def nx(self) -> int:
+        return len(self.xf) - 1
+
+    @property
+    def ny(self) -> int:
+        return len(self.yf) - 1
+
+    @property
+    def nz(self) -> int:
+        return len(self.zf) - 1
+
+    @property
+    def cells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def mesh(self):
+        """Cell-centre coordinates as [nz][ny][nx] arrays (X, Y, Z)."""
+        Z, Y, X = np.meshgrid(centres(self.zf), centres(self.yf), centres(self.xf), indexing="ij")
+        return X, Y, Z
+
+    def dt(self) -> float:
+        w = min(np.diff(self.xf).min(), np.diff(self.yf).min(), np.diff(self.zf).min())
+        return self.cfl * float(w) / self.c
+
+
+def gaussian_hill3d(x, y, z, t, u, K, sigma0, period=2.0, images=1):
+    """Closed form of phi_t + u.grad(phi) = div(K grad(phi)) for a Gaussian of
+    width sigma0 (amplitude (2 pi sigma0^2)^(3/2) normalised to peak 1 at t = 0),
+    constant u and constant symmetric positive definite K, with periodic images
+    on the cube [-period/2, period/2]^3."""
+    x, y, z = (np.asarray(v, dtype=np.float64) for v in (x, y, z))
+    S = sigma0 ** 2 * np.eye(3) + 2.0 * t * np.asarray(K, dtype=np.float64)
+    Si = np.linalg.inv(S)
+    norm = sigma0 ** 3 / math.sqrt(np.linalg.det(S))
+    out = np.zeros(np.broadcast(x, y, z).shape)
+    r = range(-images, images + 1)
+    for a in r:
+        for b in r:
+            for c in r:
+                dx = x - u[0] * t - a * period
+                dy = y - u[1] * t - b * period
+                dz = z - u[2] * t - c * period
+                qf = (Si[0, 0] * dx * dx + Si[1, 1] * dy * dy + Si[2, 2] * dz * dz
+                      + 2 * (Si[0, 1] * dx * dy + Si[0, 2] * dx * dz + Si[1, 2] * dy * dz))
+                out += norm * np.exp(-0.5 * qf)
+    return out
+
+
+def gaussian_hill3d_problem(n=64, q=19, u=(0.1, 0.05, 0.02), D=1e-3, K=None, sigma0=0.15,
+                            c=1.0, cfl=0.5, steps=100, name="gaussian_hill3d") -> Problem3D:
+    """Linear CDE on [-1, 1]^3, periodic: B = u phi, D = (K / alpha) phi."""
+    K = np.asarray(K if K is not None else np.eye(3) * D, dtype=np.float64)
+    alpha = D
+    f = uniform_faces(n, -1.0, 1.0)
+    kd = K / alpha
+    p = Problem3D(name=name, xf=f, yf=f.copy(), zf=f.copy(), q=q, c=c, cfl=cfl, alpha=alpha,
+                  b=((0.0, u[0]), (0.0, u[1]), (0.0, u[2])),
+                  d=((0.0, kd[0, 0]), (0.0, kd[1, 1]), (0.0, kd[2, 2]), (0.0, kd[0, 1]),
+                     (0.0, kd[0, 2]), (0.0, kd[1, 2])), steps=steps)
+    p.exact = lambda x, y, z, t: gaussian_hill3d(x, y, z, t, u, K, sigma0)
+    X, Y, Z = p.mesh()
+    p.phi0 = p.exact(X, Y, Z, 0.0)
+    return p
+
+
+def random_problem3d(seed: int, nx: int, ny: int, nz: int, q: int = 19,
+                     bc=(PERIODIC, PERIODIC, PERIODIC), stretched: bool = False, bdeg: int = 2,
+                     ddeg: int = 1) -> Problem3D:
+    """A small random 3-D instance for property tests (random polynomial B and D,
+    D positive definite for |phi| <= 1, smooth random initial field)."""
+    rng = np.random.default_rng(seed)
+    faces = [tanh_faces(n, 1.5) if stretched else uniform_faces(n, 0.0, 1.0) for n in (nx, ny, nz)]
+    b = tuple(tuple([0.0] + list(rng.uniform(-0.3, 0.3, size=bdeg))) for _ in range(3))
+    if q == 7:
+        d = ((0.0, 1.0), (0.0, 1.0), (0.0, 1.0), (0.0,), (0.0,), (0.0,))
+    else:
+        diag = [tuple([0.0, float(rng.uniform(0.6, 1.4))] + list(rng.uniform(0.0, 0.2, size=max(ddeg - 1, 0))))
+                for _ in range(3)]
+        off = [(0.0, float(rng.uniform(-0.2, 0.2))) for _ in range(3)]
+        d = (diag[0], diag[1], diag[2], off[0], off[1], off[2])
+    p = Problem3D(name=f"random3d_{seed}", xf=faces[0], yf=faces[1], zf=faces[2], q=q,
+                  c=float(rng.uniform(1.0, 3.0)), cfl=float(rng.uniform(0.3, 0.7)),
+                  alpha=float(np.exp(rng.uniform(-7, -3))), bc=tuple(bc), b=b, d=d, steps=3,
+                  seed=seed)
+    X, Y, Z = p.mesh()
+    periodic = all(v == PERIODIC for v in bc)
+    wn = 2 * math.pi if periodic else math.pi
+    field = np.zeros_like(X)
+    for m in range(4):
+        a = rng.uniform(-0.1, 0.1)
+        kx, ky, kz = rng.integers(0, 3, size=3)
+        ph = rng.uniform(0, 2 * math.pi, size=3) if periodic else np.zeros(3)
+        field += a * np.cos(wn * kx * X + ph[0]) * np.cos(wn * ky * Y + ph[1]) * np.cos(wn * kz * Z + ph[2])
+    p.phi0 = 0.5 + field
+    return p
