@@ -1,0 +1,123 @@
+/*
+ * libdugks, three-dimensional path: the DUGKS time step of Sec. 2 of
+ * Shang, Chai, Wang, Shi, "Discrete unified gas kinetic scheme for nonlinear
+ * convection-diffusion equations" (arXiv 1906.11036) on the D3Q15 (eq. 2.28),
+ * D3Q19 (eq. 2.6) and D3Q7 (Remark 3) lattices, on a Cartesian mesh of
+ * nx x ny x nz cells with strictly increasing face coordinates per axis.
+ *
+ * Same conventions as dugks.h: C ABI, every call returns an int code of
+ * dugks.h (DUGKS_OK = 0, negative on error), dugks3_last_error() names the
+ * problem.  The caller owns the device workspace (dugks3_workspace_bytes,
+ * 256-byte aligned) and the stream; the library owns only its host handle.
+ * Stepping is asynchronous on the bound stream; read-outs synchronise.
+ *
+ * Readings (as in the CPU oracle): lambda = alpha / c_s^2, c_s^2 = c^2/3;
+ * dt = cfl * (smallest cell width along any axis) / c; C = int_0^phi B'B'^T
+ * (Remark 3); each tangential derivative at a face is the mean of the two
+ * cells' central differences along that axis; walls per axis are periodic or
+ * zero-flux mirrors (fbar+ of the adjacent cell with the wall-normal velocity
+ * reversed); D3Q7 uses weights 0 and 1/6 and the linear equilibrium of
+ * Remark 3 (D = phi I only).  Sources and Dirichlet walls are not built in
+ * three dimensions (E_UNSUPPORTED).
+ */
+#ifndef DUGKS3D_H
+#define DUGKS3D_H
+
+#include <stddef.h>
+
+#include "dugks.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DUGKS3_ABI_VERSION 1
+
+typedef struct dugks3_params {
+  int abi_version; /* must be DUGKS3_ABI_VERSION */
+  int storage;     /* DUGKS_F64 or DUGKS_F32 */
+  int bc[3];       /* per axis x, y, z: DUGKS_BC_PERIODIC or DUGKS_BC_MIRROR */
+  double c;        /* lattice speed, > 0 */
+  double cfl;      /* CFL number, 0 < cfl < 1 */
+  double alpha;    /* diffusion coefficient of eq. 2.1, > 0 */
+} dugks3_params;
+
+typedef struct dugks3_info {
+  double dt, h, lambda, cs2;
+  double a1, b1, a2, b2, a3, b3;
+  int nx, ny, nz, q, storage, pitch;
+  int eq_degree;          /* degree of E_i(phi) as a polynomial in phi */
+  int rows_per_block;     /* launch: interior rows of a block (plus two halo rows) */
+  int planes_per_block;   /* launch: planes swept by a block */
+  long long blocks;       /* blocks per step */
+  size_t state_bytes;     /* bytes of one f~ buffer */
+} dugks3_info;
+
+typedef struct dugks3_ctx dugks3_ctx;
+
+/* Create an instance on nx x ny x nz cells with faces xf[0..nx], yf[0..ny],
+ * zf[0..nz] (host, copied) and q in {15, 19, 7}.  No device work; B = D = 0
+ * until set.  Errors: E_ARG (sizes, faces, c, cfl, alpha, abi_version),
+ * E_UNSUPPORTED (q, storage, boundary kind).  On an error other than a NULL
+ * out, *out still receives a handle for dugks3_last_error / dugks3_destroy. */
+int dugks3_create(dugks3_ctx** out, int nx, int ny, int nz, const double* xf, const double* yf,
+                  const double* zf, int q, const dugks3_params* p);
+
+/* Device workspace needed, in bytes. */
+size_t dugks3_workspace_bytes(const dugks3_ctx* ctx);
+
+/* Attach the caller's workspace (device, >= dugks3_workspace_bytes, 256-byte
+ * aligned) and stream (hipStream_t as void*); uploads the tables.  Errors:
+ * E_ARG, E_NOMEM, E_HIP. */
+int dugks3_bind(dugks3_ctx* ctx, void* dev_workspace, size_t bytes, void* hip_stream);
+
+/* B(phi) = sum_{k<=deg} (b[k], b[deg+1+k], b[2(deg+1)+k]) phi^k (host, 3(deg+1)
+ * values: the x, then y, then z coefficients), deg <= 4.  Errors: E_ARG. */
+int dugks3_set_B(dugks3_ctx* ctx, int deg, const double* b);
+
+/* D(phi) = sum_{k<=deg} D_k phi^k, symmetric, given as six runs of deg+1
+ * coefficients: xx, yy, zz, xy, xz, yz (host), deg <= 4.  q = 7 accepts only
+ * D = phi I.  Errors: E_ARG, E_UNSUPPORTED. */
+int dugks3_set_D(dugks3_ctx* ctx, int deg, const double* d);
+
+/* f~ = E(phi) (Sec. 4) from phi [nz][ny][nx] (binary64; host if on_device == 0);
+ * resets the step count.  Errors: E_STATE (not bound), E_ARG, E_HIP. */
+int dugks3_set_phi(dugks3_ctx* ctx, const double* phi, int on_device);
+
+/* f~ [q][nz][ny][nx] (binary64) as the state; resets the step count. */
+int dugks3_set_f(dugks3_ctx* ctx, const double* f, int on_device);
+
+/* Advance nsteps >= 0 steps (asynchronous).  Errors: E_STATE, E_HIP. */
+int dugks3_step(dugks3_ctx* ctx, int nsteps);
+
+/* phi = sum_i f~_i [nz][ny][nx] and f~ [q][nz][ny][nx], binary64 (host if
+ * on_device == 0).  Synchronise. */
+int dugks3_get_phi(dugks3_ctx* ctx, double* out, int on_device);
+int dugks3_get_f(dugks3_ctx* ctx, double* out, int on_device);
+
+/* mass = sum phi |V|; with ref (device, [nz][ny][nx], or NULL) also the GRE of
+ * eq. 4.1 (unweighted) and the volume-weighted relative L2 difference.  Any
+ * output pointer may be NULL.  Synchronises.  A non-finite cell returns
+ * E_UNSTABLE. */
+int dugks3_reduce(dugks3_ctx* ctx, const double* ref_dev, double* mass, double* gre,
+                  double* rel_l2);
+
+/* Launch configuration: interior rows per block (1 or 2; the block adds two
+ * halo rows and has rows+2 waves) and planes swept per block (>= 1).  A block
+ * stages g of 3 planes x (rows+2) rows in LDS (q x 64 values each); a launch
+ * needing more LDS than the device allows per block is refused.  Defaults:
+ * 2 rows (binary32), 1 row (binary64), 32 planes.  Errors: E_ARG. */
+int dugks3_set_launch(dugks3_ctx* ctx, int rows_per_block, int planes_per_block);
+
+/* Time nsteps steps with hipEvents on the bound stream (the state advances). */
+int dugks3_time_steps(dugks3_ctx* ctx, int nsteps, float* ms_total);
+
+int dugks3_get_info(const dugks3_ctx* ctx, dugks3_info* out);
+const char* dugks3_last_error(const dugks3_ctx* ctx);
+void dugks3_destroy(dugks3_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DUGKS3D_H */

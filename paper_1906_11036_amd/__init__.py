@@ -15,7 +15,7 @@ from . import _lib as L
 from ._lib import (BC_DIRICHLET, BC_MIRROR, BC_PERIODIC, BF16NEQ, F16NEQ, F32, F64,  # noqa: F401
                    KERNEL_FUSED, KERNEL_PLAIN, SCHED_GRID, SCHED_PERSISTENT, STORAGE, DugksError)
 
-__all__ = ["Solver", "Batch", "DugksError", "F64", "F32", "F16NEQ", "BF16NEQ"]
+__all__ = ["Solver", "Batch", "Solver3D", "DugksError", "F64", "F32", "F16NEQ", "BF16NEQ"]
 
 
 def _torch():
@@ -326,6 +326,112 @@ class Batch:
         if getattr(self, "h", None) and self.h.value:
             self.lib.dugks_destroy(self.h)
             self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Solver3D:
+    """One three-dimensional instance (``dugks3_ctx``: D3Q15, D3Q19 or D3Q7).
+
+    ``problem`` has the fields of ``workloads.Problem3D`` (faces xf, yf, zf, q,
+    c, cfl, alpha, bc per axis, b = (B_x, B_y, B_z) and d = (D_xx, D_yy, D_zz,
+    D_xy, D_xz, D_yz) coefficient tuples)."""
+
+    def __init__(self, problem, storage="f64", device="cuda:0", launch=None):
+        torch = _torch()
+        self.lib = L.lib()
+        self.device = torch.device(device)
+        self.problem = problem
+        self.storage = _storage_code(storage)
+        self.faces = [np.ascontiguousarray(f, dtype=np.float64) for f in (problem.xf, problem.yf, problem.zf)]
+        self.nx, self.ny, self.nz = (len(f) - 1 for f in self.faces)
+        self.q = int(problem.q)
+        p = L.Params3()
+        p.abi_version = L.ABI3_VERSION
+        p.storage = self.storage
+        for i, b in enumerate(problem.bc):
+            p.bc[i] = int(b)
+        p.c, p.cfl, p.alpha = float(problem.c), float(problem.cfl), float(problem.alpha)
+        h = C.c_void_p()
+        rc = self.lib.dugks3_create(C.byref(h), self.nx, self.ny, self.nz, *[_dptr(f) for f in self.faces],
+                                    self.q, C.byref(p))
+        self.h = h
+        L.check3(rc, h, "dugks3_create")
+        deg = max(len(v) for v in problem.b) - 1
+        b = np.concatenate([np.array(_poly(v, deg + 1)) for v in problem.b])
+        L.check3(self.lib.dugks3_set_B(self.h, deg, _dptr(b)), self.h, "dugks3_set_B")
+        deg = max(len(v) for v in problem.d) - 1
+        d = np.concatenate([np.array(_poly(v, deg + 1)) for v in problem.d])
+        L.check3(self.lib.dugks3_set_D(self.h, deg, _dptr(d)), self.h, "dugks3_set_D")
+        nbytes = self.lib.dugks3_workspace_bytes(self.h)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            self._ws_ptr = (self.workspace.data_ptr() + 255) & ~255
+            L.check3(self.lib.dugks3_bind(self.h, C.c_void_p(self._ws_ptr), nbytes,
+                                          _stream_handle(self.device)), self.h, "dugks3_bind")
+        if launch is not None:
+            self.set_launch(*launch)
+
+    def _dev64(self, a, shape):
+        torch = _torch()
+        if torch.is_tensor(a):
+            t = a.to(device=self.device, dtype=torch.float64).contiguous()
+        else:
+            t = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(self.device)
+        return t.reshape(shape)
+
+    def set_phi(self, phi):
+        t = self._dev64(phi, (self.nz, self.ny, self.nx))
+        L.check3(self.lib.dugks3_set_phi(self.h, C.c_void_p(t.data_ptr()), 1), self.h, "dugks3_set_phi")
+
+    def set_f(self, f):
+        t = self._dev64(f, (self.q, self.nz, self.ny, self.nx))
+        L.check3(self.lib.dugks3_set_f(self.h, C.c_void_p(t.data_ptr()), 1), self.h, "dugks3_set_f")
+
+    def step(self, nsteps=1):
+        L.check3(self.lib.dugks3_step(self.h, int(nsteps)), self.h, "dugks3_step")
+
+    def time_steps(self, nsteps):
+        ms = C.c_float()
+        L.check3(self.lib.dugks3_time_steps(self.h, int(nsteps), C.byref(ms)), self.h, "dugks3_time_steps")
+        return ms.value
+
+    def get_phi(self) -> np.ndarray:
+        out = np.zeros((self.nz, self.ny, self.nx))
+        L.check3(self.lib.dugks3_get_phi(self.h, _dptr(out), 0), self.h, "dugks3_get_phi")
+        return out
+
+    def get_f(self) -> np.ndarray:
+        out = np.zeros((self.q, self.nz, self.ny, self.nx))
+        L.check3(self.lib.dugks3_get_f(self.h, _dptr(out), 0), self.h, "dugks3_get_f")
+        return out
+
+    def reduce(self, ref=None) -> dict:
+        """mass, and with a reference field [nz][ny][nx] the GRE (eq. 4.1) and rel-L2."""
+        m, g, l2 = C.c_double(), C.c_double(), C.c_double()
+        t = self._dev64(ref, (self.nz, self.ny, self.nx)) if ref is not None else None
+        L.check3(self.lib.dugks3_reduce(self.h, C.c_void_p(t.data_ptr()) if t is not None else None,
+                                        C.byref(m), C.byref(g), C.byref(l2)), self.h, "dugks3_reduce")
+        return {"mass": m.value, "gre": g.value, "rel_l2": l2.value}
+
+    def set_launch(self, rows_per_block=2, planes_per_block=32):
+        L.check3(self.lib.dugks3_set_launch(self.h, int(rows_per_block), int(planes_per_block)), self.h,
+                 "dugks3_set_launch")
+
+    def info(self) -> dict:
+        inf = L.Info3()
+        L.check3(self.lib.dugks3_get_info(self.h, C.byref(inf)), self.h, "dugks3_get_info")
+        return {k: getattr(inf, k) for k, _ in L.Info3._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dugks3_destroy(self.h)
+            self.h = None
+        self.workspace = None
 
     def __del__(self):
         try:

@@ -1,4 +1,4 @@
-"""ctypes declarations of the C ABI in include/dugks.h.
+"""ctypes declarations of the C ABI in include/dugks.h and include/dugks3d.h.
 
 Loading fails loudly when libdugks.so is missing: there is no fallback path.
 """
@@ -11,6 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdugks.so")
 
 ABI_VERSION = 2
+ABI3_VERSION = 1
 MAX_DEG = 4
 OK, E_ARG, E_STATE, E_HIP, E_UNSTABLE, E_UNSUPPORTED, E_NOMEM, E_FORMAT = 0, -1, -2, -3, -4, -5, -6, -7
 F64, F32, F16NEQ, BF16NEQ = 0, 1, 2, 3
@@ -41,6 +42,20 @@ class Info(C.Structure):
 class Diag(C.Structure):
     _fields_ = [("step", C.c_longlong), ("t", C.c_double), ("dt", C.c_double), ("mass", C.c_double),
                 ("max_neq", C.c_double), ("scale", C.c_double), ("flags", C.c_int)]
+
+
+class Params3(C.Structure):
+    _fields_ = [("abi_version", C.c_int), ("storage", C.c_int), ("bc", C.c_int * 3),
+                ("c", C.c_double), ("cfl", C.c_double), ("alpha", C.c_double)]
+
+
+class Info3(C.Structure):
+    _fields_ = [("dt", C.c_double), ("h", C.c_double), ("lambda_", C.c_double), ("cs2", C.c_double),
+                ("a1", C.c_double), ("b1", C.c_double), ("a2", C.c_double), ("b2", C.c_double),
+                ("a3", C.c_double), ("b3", C.c_double), ("nx", C.c_int), ("ny", C.c_int),
+                ("nz", C.c_int), ("q", C.c_int), ("storage", C.c_int), ("pitch", C.c_int),
+                ("eq_degree", C.c_int), ("rows_per_block", C.c_int), ("planes_per_block", C.c_int),
+                ("blocks", C.c_longlong), ("state_bytes", C.c_size_t)]
 
 
 _D5 = C.c_double * (MAX_DEG + 1)
@@ -91,6 +106,23 @@ SIGNATURES = {
     "dugks_batch_time_steps": (_int, [_vp, _int, C.POINTER(C.c_float)]),
     "dugks_last_error": (C.c_char_p, [_vp]),
     "dugks_destroy": (None, [_vp]),
+    # three dimensions (include/dugks3d.h)
+    "dugks3_create": (_int, [C.POINTER(_vp), _int, _int, _int, _dp, _dp, _dp, _int, C.POINTER(Params3)]),
+    "dugks3_workspace_bytes": (_sz, [_vp]),
+    "dugks3_bind": (_int, [_vp, _vp, _sz, _vp]),
+    "dugks3_set_B": (_int, [_vp, _int, _dp]),
+    "dugks3_set_D": (_int, [_vp, _int, _dp]),
+    "dugks3_set_phi": (_int, [_vp, _vp, _int]),
+    "dugks3_set_f": (_int, [_vp, _vp, _int]),
+    "dugks3_step": (_int, [_vp, _int]),
+    "dugks3_get_phi": (_int, [_vp, _vp, _int]),
+    "dugks3_get_f": (_int, [_vp, _vp, _int]),
+    "dugks3_reduce": (_int, [_vp, _vp, _dp, _dp, _dp]),
+    "dugks3_set_launch": (_int, [_vp, _int, _int]),
+    "dugks3_time_steps": (_int, [_vp, _int, C.POINTER(C.c_float)]),
+    "dugks3_get_info": (_int, [_vp, C.POINTER(Info3)]),
+    "dugks3_last_error": (C.c_char_p, [_vp]),
+    "dugks3_destroy": (None, [_vp]),
 }
 
 _LIB = None
@@ -122,5 +154,13 @@ class DugksError(RuntimeError):
 def check(rc, handle, what=""):
     if rc != OK:
         msg = lib().dugks_last_error(handle).decode() if handle else ""
+        raise DugksError(rc, f"{what}: {msg}" if what else msg)
+    return rc
+
+
+def check3(rc, handle, what=""):
+    """check() for a three-dimensional handle."""
+    if rc != OK:
+        msg = lib().dugks3_last_error(handle).decode() if handle else ""
         raise DugksError(rc, f"{what}: {msg}" if what else msg)
     return rc

@@ -1,0 +1,495 @@
+// Host runtime of the three-dimensional DUGKS path (include/dugks3d.h):
+// setup constants (Sec. 2, Sec. 3), per-axis mesh tables, the equilibrium as
+// per-direction polynomials in phi (eq. 2.3 with C = int B'B'^T, Remark 3),
+// the workspace layout, launches and read-outs.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "dugks3d.h"
+#include "dugks3d_internal.h"
+
+using namespace dugks3;
+
+namespace {
+
+constexpr uint32_t kMagic3 = 0x44554733u;  // "DUG3"
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+const int kE15[15][3] = {{0, 0, 0},  {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},   {0, -1, 0},
+                         {0, 0, 1},  {0, 0, -1},  {1, 1, 1},  {1, 1, -1},  {1, -1, 1},
+                         {-1, 1, 1}, {-1, -1, -1}, {-1, -1, 1}, {-1, 1, -1}, {1, -1, -1}};
+const int kE19[19][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},   {0, -1, 0},
+                         {0, 0, 1},  {0, 0, -1}, {1, 1, 0},  {-1, -1, 0}, {1, -1, 0},
+                         {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {-1, 0, 1}, {1, 0, -1},
+                         {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+
+// Mesh table of one axis (layout in dugks3d_internal.h).
+void axis_table(const std::vector<double>& f, int bc, double h, double c, double dt, double b3,
+                std::vector<double>& geo, std::vector<double>& widths) {
+  const int n = (int)f.size() - 1;
+  std::vector<double> w(n + 2), xc(n + 2);
+  for (int i = 0; i < n; ++i) {
+    w[i + 1] = f[i + 1] - f[i];
+    xc[i + 1] = 0.5 * (f[i] + f[i + 1]);
+  }
+  w[0] = bc == DUGKS_BC_PERIODIC ? w[n] : w[1];
+  w[n + 1] = bc == DUGKS_BC_PERIODIC ? w[1] : w[n];
+  xc[0] = f[0] - 0.5 * w[0];
+  xc[n + 1] = f[n] + 0.5 * w[n + 1];
+  geo.assign((size_t)(n + 2) * kGeo, 0.0);
+  for (int m = 0; m <= n; ++m) {  // face between cells m-1 and m
+    const double dn = xc[m + 1] - xc[m], wl = f[m] - xc[m];
+    double* g = &geo[(size_t)(m + 1) * kGeo];
+    g[0] = (wl + h * c) / dn;
+    g[1] = wl / dn;
+    g[2] = (wl - h * c) / dn;
+  }
+  for (int m = 0; m < n; ++m) {
+    double* g = &geo[(size_t)(m + 1) * kGeo];
+    g[3] = 0.5 * h * c / (xc[m + 2] - xc[m]);
+    g[4] = dt * c / w[m + 1] * b3;
+  }
+  widths.assign(w.begin() + 1, w.begin() + 1 + n);
+}
+
+}  // namespace
+
+struct dugks3_ctx {
+  uint32_t magic = kMagic3;
+  std::string err;
+  int n[3] = {0, 0, 0};
+  int q = 19;
+  dugks3_params p{};
+  std::vector<double> faces[3];
+  int bdeg = 0, ddeg = 1;
+  double b[3][DUGKS_MAX_DEG + 1] = {{0}};
+  double d[6][DUGKS_MAX_DEG + 1] = {{0}};  // xx yy zz xy xz yz
+  // derived
+  double cs2 = 0, lambda = 0, dt = 0, h = 0, a1 = 0, b1 = 0, a2 = 0, b2 = 0, a3 = 0, b3 = 0;
+  int pitch = 0, ncoef = 2;
+  double e[kMaxQ][kMaxCoef] = {{0}};
+  std::vector<double> geo[3], widths;
+  Launch3 launch;
+  // device
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t stream = nullptr;
+  size_t off_table = 0, off_buf[2] = {0, 0}, off_geo[3] = {0, 0, 0}, off_geof[3] = {0, 0, 0},
+         off_widths = 0, off_partial = 0, off_out = 0, off_stage = 0, total = 0;
+  size_t buf_bytes = 0, stage_bytes = 0;
+  Inst3 host{};
+  bool initialised = false;
+  long long step = 0;
+
+  int fail(int rc, const std::string& m) { err = m; return rc; }
+  int hipfail(hipError_t e, const char* what) {
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return DUGKS_E_HIP;
+  }
+  long long cells() const { return (long long)n[0] * n[1] * n[2]; }
+  bool bound() const { return ws != nullptr; }
+  size_t elem() const { return p.storage == DUGKS_F64 ? 8 : 4; }
+
+  void equilibrium_polys() {
+    const double c = p.c;
+    double w[kMaxQ];
+    int e3[kMaxQ][3];
+    for (int i = 0; i < q; ++i) {
+      for (int a = 0; a < 3; ++a) e3[i][a] = q == 19 ? kE19[i][a] : kE15[i][a];
+      w[i] = q == 15 ? (i == 0 ? 2.0 / 9 : (i <= 6 ? 1.0 / 9 : 1.0 / 72))
+             : q == 19 ? (i == 0 ? 1.0 / 3 : (i <= 6 ? 1.0 / 18 : 1.0 / 36))
+                       : (i == 0 ? 0.0 : 1.0 / 6);
+    }
+    // C_ab = int B'_a B'_b: coefficient of phi^m
+    double C[3][3][kMaxCoef] = {{{0}}};
+    for (int a = 0; a < 3; ++a)
+      for (int bb = 0; bb < 3; ++bb)
+        for (int k = 1; k <= bdeg; ++k)
+          for (int l = 1; l <= bdeg; ++l) {
+            const int m = k + l - 1;
+            C[a][bb][m] += (double)(k * l) / m * b[a][k] * b[bb][l];
+          }
+    static const int AB[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
+    double D[3][3][kMaxCoef] = {{{0}}};
+    for (int s = 0; s < 6; ++s)
+      for (int m = 0; m <= DUGKS_MAX_DEG; ++m) {
+        D[AB[s][0]][AB[s][1]][m] = d[s][m];
+        D[AB[s][1]][AB[s][0]][m] = d[s][m];
+      }
+    memset(e, 0, sizeof(e));
+    int deg = 1;
+    for (int m = 0; m < kMaxCoef; ++m)
+      for (int i = 0; i < q; ++i) {
+        double v = (m == 1 ? 1.0 : 0.0);
+        for (int a = 0; a < 3; ++a)
+          v += c * e3[i][a] * (m <= DUGKS_MAX_DEG ? b[a][m] : 0.0) / cs2;
+        if (q != 7) {
+          double contr = 0.0;
+          for (int a = 0; a < 3; ++a)
+            for (int bb = 0; bb < 3; ++bb) {
+              const double M = cs2 * D[a][bb][m] + C[a][bb][m] - (a == bb && m == 1 ? cs2 : 0.0);
+              contr += M * (c * e3[i][a] * c * e3[i][bb] - (a == bb ? cs2 : 0.0));
+            }
+          v += contr / (2.0 * cs2 * cs2);
+        }
+        e[i][m] = w[i] * v;
+        if (e[i][m] != 0.0) deg = std::max(deg, m);
+      }
+    ncoef = deg + 1;
+  }
+
+  void fill_host() {
+    Inst3& d3 = host;
+    memset(&d3, 0, sizeof(d3));
+    d3.buf[0] = ws + off_buf[0];
+    d3.buf[1] = ws + off_buf[1];
+    for (int a = 0; a < 3; ++a) {
+      d3.geo[a] = (const double*)(ws + off_geo[a]);
+      d3.geof[a] = (const float*)(ws + off_geof[a]);
+      d3.n[a] = n[a];
+      d3.bc[a] = p.bc[a];
+    }
+    d3.plane = (long long)n[2] * n[1] * pitch;
+    d3.buf_bytes = (unsigned)buf_bytes;
+    d3.pitch = pitch;
+    d3.q = q;
+    d3.ncoef = ncoef;
+    d3.storage = p.storage;
+    d3.ra = a1 / b1;
+    d3.rb = a3 * b1 / b3;
+    d3.b1 = b1;
+    d3.kg = 4.0 / 3.0 * b1;
+    d3.raf = (float)d3.ra; d3.rbf = (float)d3.rb; d3.b1f = (float)d3.b1; d3.kgf = (float)d3.kg;
+    for (int i = 0; i < q; ++i)
+      for (int m = 0; m < kMaxCoef; ++m) {
+        d3.e[i][m] = e[i][m];
+        d3.ef[i][m] = (float)e[i][m];
+      }
+  }
+
+  int upload() {
+    fill_host();
+    hipError_t er = hipMemcpyAsync(ws + off_table, &host, sizeof(Inst3), hipMemcpyHostToDevice, stream);
+    if (er != hipSuccess) return hipfail(er, "upload instance");
+    for (int a = 0; a < 3; ++a) {
+      std::vector<float> gf(geo[a].begin(), geo[a].end());
+      er = hipMemcpyAsync(ws + off_geo[a], geo[a].data(), sizeof(double) * geo[a].size(),
+                          hipMemcpyHostToDevice, stream);
+      if (er == hipSuccess)
+        er = hipMemcpyAsync(ws + off_geof[a], gf.data(), sizeof(float) * gf.size(),
+                            hipMemcpyHostToDevice, stream);
+      if (er != hipSuccess) return hipfail(er, "upload mesh tables");
+      er = hipStreamSynchronize(stream);  // gf is a local
+      if (er != hipSuccess) return hipfail(er, "synchronise");
+    }
+    er = hipMemcpyAsync(ws + off_widths, widths.data(), sizeof(double) * widths.size(),
+                        hipMemcpyHostToDevice, stream);
+    if (er != hipSuccess) return hipfail(er, "upload widths");
+    er = hipStreamSynchronize(stream);
+    return er == hipSuccess ? DUGKS_OK : hipfail(er, "synchronise");
+  }
+
+  const Inst3* dev() const { return (const Inst3*)(ws + off_table); }
+
+  // LDS bytes of a block for the launch and the device limit per block
+  size_t lds_bytes(const Launch3& l) const { return (size_t)3 * (l.rows + 2) * q * kLanes * elem(); }
+  size_t lds_limit() const {
+    int dev = 0, v = 65536;
+    if (hipGetDevice(&dev) == hipSuccess)
+      (void)hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    return (size_t)v;
+  }
+
+  // Stage a host array into the workspace staging area (or use a device pointer).
+  int stage_in(const double* src, size_t count, int on_device, const double** out) {
+    if (on_device) { *out = src; return DUGKS_OK; }
+    if (count * sizeof(double) > stage_bytes) return fail(DUGKS_E_ARG, "array larger than the staging area");
+    hipError_t er = hipMemcpyAsync(ws + off_stage, src, count * sizeof(double), hipMemcpyHostToDevice, stream);
+    if (er != hipSuccess) return hipfail(er, "copy to device");
+    *out = (const double*)(ws + off_stage);
+    return DUGKS_OK;
+  }
+  int read_out(double* out, size_t count, int on_device, int want_f) {
+    if (!bound()) return fail(DUGKS_E_STATE, "not bound");
+    if (!initialised) return fail(DUGKS_E_STATE, "state not initialised");
+    if (!out) return fail(DUGKS_E_ARG, "out is NULL");
+    double* dst = on_device ? out : (double*)(ws + off_stage);
+    if (!on_device && count * sizeof(double) > stage_bytes) return fail(DUGKS_E_ARG, "too large");
+    const int rc = want_f ? launch_get_f3(dev(), host, dst, (int)(step & 1), stream)
+                          : launch_get_phi3(dev(), host, dst, (int)(step & 1), stream);
+    if (rc) return fail(DUGKS_E_HIP, "read-out launch failed");
+    hipError_t er = on_device ? hipSuccess
+                              : hipMemcpyAsync(out, dst, count * sizeof(double), hipMemcpyDeviceToHost, stream);
+    if (er == hipSuccess) er = hipStreamSynchronize(stream);
+    return er == hipSuccess ? DUGKS_OK : hipfail(er, "read-out");
+  }
+};
+
+#define GUARD3(ctx)                                                      \
+  do {                                                                   \
+    if (!(ctx) || (ctx)->magic != kMagic3) return DUGKS_E_ARG;           \
+  } while (0)
+
+extern "C" {
+
+int dugks3_create(dugks3_ctx** out, int nx, int ny, int nz, const double* xf, const double* yf,
+                  const double* zf, int q, const dugks3_params* p) {
+  if (!out) return DUGKS_E_ARG;
+  dugks3_ctx* x = new dugks3_ctx();
+  *out = x;
+  if (!p) return x->fail(DUGKS_E_ARG, "params is NULL");
+  if (p->abi_version != DUGKS3_ABI_VERSION) return x->fail(DUGKS_E_ARG, "abi_version mismatch");
+  if (nx < 1 || ny < 1 || nz < 1) return x->fail(DUGKS_E_ARG, "sizes must be >= 1");
+  if (ny > 65535 || nz > 65535) return x->fail(DUGKS_E_ARG, "ny and nz must be <= 65535");
+  if (!xf || !yf || !zf) return x->fail(DUGKS_E_ARG, "faces are NULL");
+  if (!(p->c > 0) || !(p->cfl > 0 && p->cfl < 1) || !(p->alpha > 0))
+    return x->fail(DUGKS_E_ARG, "c, cfl or alpha out of range");
+  if (q != 15 && q != 19 && q != 7) return x->fail(DUGKS_E_UNSUPPORTED, "q must be 15, 19 or 7");
+  if (p->storage != DUGKS_F64 && p->storage != DUGKS_F32)
+    return x->fail(DUGKS_E_UNSUPPORTED, "three-dimensional storage is binary64 or binary32");
+  for (int a = 0; a < 3; ++a)
+    if (p->bc[a] != DUGKS_BC_PERIODIC && p->bc[a] != DUGKS_BC_MIRROR)
+      return x->fail(DUGKS_E_UNSUPPORTED, "three-dimensional walls are periodic or mirror");
+  const int ns[3] = {nx, ny, nz};
+  const double* fs[3] = {xf, yf, zf};
+  x->q = q;
+  x->p = *p;
+  double dmin = 1e300;
+  for (int a = 0; a < 3; ++a) {
+    x->n[a] = ns[a];
+    x->faces[a].assign(fs[a], fs[a] + ns[a] + 1);
+    for (int i = 0; i < ns[a]; ++i) {
+      const double wdt = fs[a][i + 1] - fs[a][i];
+      if (!(wdt > 0)) return x->fail(DUGKS_E_ARG, "faces must increase strictly");
+      dmin = std::min(dmin, wdt);
+    }
+  }
+  x->pitch = (nx + 63) / 64 * 64;
+  x->cs2 = p->c * p->c / 3.0;
+  x->lambda = p->alpha / x->cs2;
+  x->dt = p->cfl * dmin / p->c;
+  x->h = 0.5 * x->dt;
+  const double L = x->lambda, dt = x->dt, h = x->h;
+  x->a1 = (2 * L - h) / (2 * L + dt); x->b1 = 3 * h / (2 * L + dt);
+  x->a2 = (2 * L - dt) / (2 * L + dt); x->b2 = 2 * dt / (2 * L + dt);
+  x->a3 = 2 * L / (2 * L + h); x->b3 = h / (2 * L + h);
+  x->d[0][1] = x->d[1][1] = x->d[2][1] = 1.0;   // D = phi I until set
+  x->equilibrium_polys();
+  x->widths.clear();
+  for (int a = 0; a < 3; ++a) {
+    std::vector<double> w;
+    axis_table(x->faces[a], p->bc[a], h, p->c, dt, x->b3, x->geo[a], w);
+    x->widths.insert(x->widths.end(), w.begin(), w.end());
+  }
+  const size_t plane = (size_t)nz * ny * x->pitch;
+  x->buf_bytes = plane * q * x->elem();
+  if (x->buf_bytes >= 4294967296ull) return x->fail(DUGKS_E_ARG, "one state buffer exceeds 4 GiB");
+  size_t off = 0;
+  x->off_table = off; off += align256(sizeof(Inst3));
+  x->off_buf[0] = off; off += align256(x->buf_bytes);
+  x->off_buf[1] = off; off += align256(x->buf_bytes);
+  for (int a = 0; a < 3; ++a) {
+    x->off_geo[a] = off; off += align256(sizeof(double) * x->geo[a].size());
+    x->off_geof[a] = off; off += align256(sizeof(float) * x->geo[a].size());
+  }
+  x->off_widths = off; off += align256(sizeof(double) * x->widths.size());
+  x->off_partial = off; off += align256(sizeof(double) * 8 * reduce3_partials());
+  x->off_out = off; off += align256(sizeof(double) * 8);
+  x->stage_bytes = sizeof(double) * (size_t)q * x->cells();
+  x->off_stage = off; off += align256(x->stage_bytes);
+  x->total = off;
+  // default launch: binary32 two rows (LDS 3 x 4 x q x 64 x 4 bytes, 58 KiB for D3Q19),
+  // binary64 one row (3 x 3 x q x 64 x 8 bytes)
+  x->launch.rows = p->storage == DUGKS_F64 ? 1 : 2;
+  x->launch.planes = 32;
+  return DUGKS_OK;
+}
+
+size_t dugks3_workspace_bytes(const dugks3_ctx* ctx) {
+  return (ctx && ctx->magic == kMagic3) ? ctx->total : 0;
+}
+
+int dugks3_bind(dugks3_ctx* ctx, void* ws, size_t bytes, void* stream) {
+  GUARD3(ctx);
+  if (!ws) return ctx->fail(DUGKS_E_ARG, "workspace is NULL");
+  if (((uintptr_t)ws & 255) != 0) return ctx->fail(DUGKS_E_ARG, "workspace must be 256-byte aligned");
+  if (bytes < ctx->total) return ctx->fail(DUGKS_E_NOMEM, "workspace too small");
+  ctx->ws = (char*)ws;
+  ctx->ws_bytes = bytes;
+  ctx->stream = (hipStream_t)stream;
+  ctx->initialised = false;
+  return ctx->upload();
+}
+
+int dugks3_set_B(dugks3_ctx* ctx, int deg, const double* b) {
+  GUARD3(ctx);
+  if (deg < 0 || deg > DUGKS_MAX_DEG || !b) return ctx->fail(DUGKS_E_ARG, "bad B");
+  memset(ctx->b, 0, sizeof(ctx->b));
+  for (int a = 0; a < 3; ++a)
+    for (int k = 0; k <= deg; ++k) ctx->b[a][k] = b[a * (deg + 1) + k];
+  ctx->bdeg = deg;
+  ctx->equilibrium_polys();
+  return ctx->bound() ? ctx->upload() : DUGKS_OK;
+}
+
+int dugks3_set_D(dugks3_ctx* ctx, int deg, const double* d) {
+  GUARD3(ctx);
+  if (deg < 0 || deg > DUGKS_MAX_DEG || !d) return ctx->fail(DUGKS_E_ARG, "bad D");
+  if (ctx->q == 7) {
+    for (int s = 0; s < 6; ++s)
+      for (int k = 0; k <= deg; ++k) {
+        const double want = (s < 3 && k == 1) ? 1.0 : 0.0;
+        if (d[s * (deg + 1) + k] != want)
+          return ctx->fail(DUGKS_E_UNSUPPORTED, "D3Q7 takes D = phi I only (Remark 3)");
+      }
+  }
+  memset(ctx->d, 0, sizeof(ctx->d));
+  for (int s = 0; s < 6; ++s)
+    for (int k = 0; k <= deg; ++k) ctx->d[s][k] = d[s * (deg + 1) + k];
+  ctx->ddeg = deg;
+  ctx->equilibrium_polys();
+  return ctx->bound() ? ctx->upload() : DUGKS_OK;
+}
+
+int dugks3_set_phi(dugks3_ctx* ctx, const double* phi, int on_device) {
+  GUARD3(ctx);
+  if (!ctx->bound()) return ctx->fail(DUGKS_E_STATE, "not bound");
+  if (!phi) return ctx->fail(DUGKS_E_ARG, "phi is NULL");
+  const double* src;
+  int rc = ctx->stage_in(phi, (size_t)ctx->cells(), on_device, &src);
+  if (rc) return rc;
+  if (launch_init3(ctx->dev(), ctx->host, src, 0, ctx->stream)) return ctx->fail(DUGKS_E_HIP, "init launch failed");
+  hipError_t er = hipStreamSynchronize(ctx->stream);
+  if (er != hipSuccess) return ctx->hipfail(er, "initialise");
+  ctx->step = 0;
+  ctx->initialised = true;
+  return DUGKS_OK;
+}
+
+int dugks3_set_f(dugks3_ctx* ctx, const double* f, int on_device) {
+  GUARD3(ctx);
+  if (!ctx->bound()) return ctx->fail(DUGKS_E_STATE, "not bound");
+  if (!f) return ctx->fail(DUGKS_E_ARG, "f is NULL");
+  const double* src;
+  int rc = ctx->stage_in(f, (size_t)ctx->q * ctx->cells(), on_device, &src);
+  if (rc) return rc;
+  if (launch_set_f3(ctx->dev(), ctx->host, src, 0, ctx->stream)) return ctx->fail(DUGKS_E_HIP, "set_f launch failed");
+  hipError_t er = hipStreamSynchronize(ctx->stream);
+  if (er != hipSuccess) return ctx->hipfail(er, "set_f");
+  ctx->step = 0;
+  ctx->initialised = true;
+  return DUGKS_OK;
+}
+
+int dugks3_step(dugks3_ctx* ctx, int nsteps) {
+  GUARD3(ctx);
+  if (nsteps < 0) return ctx->fail(DUGKS_E_ARG, "nsteps < 0");
+  if (!ctx->bound()) return ctx->fail(DUGKS_E_STATE, "not bound");
+  if (!ctx->initialised) return ctx->fail(DUGKS_E_STATE, "state not initialised");
+  if (ctx->lds_bytes(ctx->launch) > ctx->lds_limit())
+    return ctx->fail(DUGKS_E_ARG, "launch needs more LDS than a block may hold");
+  for (int s = 0; s < nsteps; ++s) {
+    if (launch_step3(ctx->dev(), ctx->host, (int)(ctx->step & 1), ctx->launch, ctx->stream))
+      return ctx->fail(DUGKS_E_HIP, std::string("step launch failed: ") + hipGetErrorString(hipGetLastError()));
+    ctx->step += 1;
+  }
+  return DUGKS_OK;
+}
+
+int dugks3_get_phi(dugks3_ctx* ctx, double* out, int on_device) {
+  GUARD3(ctx);
+  return ctx->read_out(out, (size_t)ctx->cells(), on_device, 0);
+}
+
+int dugks3_get_f(dugks3_ctx* ctx, double* out, int on_device) {
+  GUARD3(ctx);
+  return ctx->read_out(out, (size_t)ctx->q * ctx->cells(), on_device, 1);
+}
+
+int dugks3_reduce(dugks3_ctx* ctx, const double* ref_dev, double* mass, double* gre, double* rel_l2) {
+  GUARD3(ctx);
+  if (!ctx->bound()) return ctx->fail(DUGKS_E_STATE, "not bound");
+  if (!ctx->initialised) return ctx->fail(DUGKS_E_STATE, "state not initialised");
+  double* o = (double*)(ctx->ws + ctx->off_out);
+  if (launch_reduce3(ctx->dev(), ctx->host, ref_dev, (int)(ctx->step & 1),
+                     (const double*)(ctx->ws + ctx->off_widths), (double*)(ctx->ws + ctx->off_partial), o,
+                     ctx->stream))
+    return ctx->fail(DUGKS_E_HIP, "reduction launch failed");
+  double v[8];
+  hipError_t er = hipMemcpyAsync(v, o, sizeof(v), hipMemcpyDeviceToHost, ctx->stream);
+  if (er == hipSuccess) er = hipStreamSynchronize(ctx->stream);
+  if (er != hipSuccess) return ctx->hipfail(er, "reduce");
+  if (mass) *mass = v[0];
+  if (gre) *gre = ref_dev ? v[1] / v[2] : 0.0;
+  if (rel_l2) *rel_l2 = ref_dev ? sqrt(v[3] / v[4]) : 0.0;
+  return v[5] > 0 ? ctx->fail(DUGKS_E_UNSTABLE, "non-finite cells") : DUGKS_OK;
+}
+
+int dugks3_set_launch(dugks3_ctx* ctx, int rows, int planes) {
+  GUARD3(ctx);
+  if (rows < 1 || rows > kMaxRowsPerBlock) return ctx->fail(DUGKS_E_ARG, "rows_per_block must be 1 or 2");
+  if (planes < 1) return ctx->fail(DUGKS_E_ARG, "planes_per_block must be >= 1");
+  Launch3 l;
+  l.rows = rows;
+  l.planes = planes;
+  if (ctx->bound() && ctx->lds_bytes(l) > ctx->lds_limit())
+    return ctx->fail(DUGKS_E_ARG, "launch needs more LDS than a block may hold");
+  ctx->launch = l;
+  return DUGKS_OK;
+}
+
+int dugks3_time_steps(dugks3_ctx* ctx, int nsteps, float* ms) {
+  GUARD3(ctx);
+  if (!ms) return ctx->fail(DUGKS_E_ARG, "ms is NULL");
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+    return ctx->fail(DUGKS_E_HIP, "event create");
+  hipError_t er = hipEventRecord(a, ctx->stream);
+  int rc = er == hipSuccess ? dugks3_step(ctx, nsteps) : DUGKS_E_HIP;
+  if (rc == DUGKS_OK) er = hipEventRecord(b, ctx->stream);
+  if (rc == DUGKS_OK && er == hipSuccess) er = hipEventSynchronize(b);
+  if (rc == DUGKS_OK && er == hipSuccess) er = hipEventElapsedTime(ms, a, b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (rc) return rc;
+  return er == hipSuccess ? DUGKS_OK : ctx->hipfail(er, "timing");
+}
+
+int dugks3_get_info(const dugks3_ctx* ctx, dugks3_info* out) {
+  if (!ctx || ctx->magic != kMagic3 || !out) return DUGKS_E_ARG;
+  memset(out, 0, sizeof(*out));
+  out->dt = ctx->dt; out->h = ctx->h; out->lambda = ctx->lambda; out->cs2 = ctx->cs2;
+  out->a1 = ctx->a1; out->b1 = ctx->b1; out->a2 = ctx->a2; out->b2 = ctx->b2;
+  out->a3 = ctx->a3; out->b3 = ctx->b3;
+  out->nx = ctx->n[0]; out->ny = ctx->n[1]; out->nz = ctx->n[2];
+  out->q = ctx->q; out->storage = ctx->p.storage; out->pitch = ctx->pitch;
+  out->eq_degree = ctx->ncoef - 1;
+  out->rows_per_block = ctx->launch.rows;
+  out->planes_per_block = ctx->launch.planes;
+  Inst3 t{};
+  for (int a = 0; a < 3; ++a) t.n[a] = ctx->n[a];
+  out->blocks = step3_blocks(t, ctx->launch);
+  out->state_bytes = ctx->buf_bytes;
+  return DUGKS_OK;
+}
+
+const char* dugks3_last_error(const dugks3_ctx* ctx) {
+  if (!ctx || ctx->magic != kMagic3) return "invalid handle";
+  return ctx->err.c_str();
+}
+
+void dugks3_destroy(dugks3_ctx* ctx) {
+  if (!ctx || ctx->magic != kMagic3) return;
+  ctx->magic = 0;
+  delete ctx;
+}
+
+}  // extern "C"

@@ -1,0 +1,67 @@
+// Internal layout shared by the host runtime and the gfx950 kernels of the
+// three-dimensional DUGKS step (D3Q15 of eq. 2.28, D3Q19 of eq. 2.6, D3Q7 of
+// Remark 3).
+//
+// One f~ buffer is Q direction planes, each [nz][ny][pitch] with pitch = nx
+// rounded up to 64 elements.  Two buffers (ping-pong): step n reads buffer
+// n%2.  Storage binary64 or binary32.
+#pragma once
+
+#include <stdint.h>
+
+#include "dugks.h"
+#include "dugks3d.h"
+
+namespace dugks3 {
+
+constexpr int kMaxQ = 19;
+constexpr int kMaxCoef = 8;     // E_i(phi) has degree <= 7
+constexpr int kLanes = 64;      // one wave covers 64 columns ...
+constexpr int kCols = 62;       // ... of which 62 are updated; lanes 0 and 63 are halo
+constexpr int kGeo = 5;         // per face: 3 reconstruction factors, tangential factor, update factor
+constexpr int kMaxRowsPerBlock = 2;   // interior rows of a block (plus two halo rows)
+
+// Per-instance constants and pointers (kernels read them with scalar loads).
+// Scaled distributions as in the two-dimensional kernels:
+//   g = fbar+ / b1 = (a1/b1) f~ + E(phi)      f~+ = (4/3) b1 g - f~ / 3
+//   phi_b = b1 sum gbar                       F = f_b / b3 = (a3 b1/b3) gbar + E(phi_b)
+// Axis tables: for axis a, face between cells m-1 and m at [(m+1)*kGeo + 0..2]
+// (factors for normal velocity -c, 0, +c), at [(m+1)*kGeo + 3] the tangential
+// factor h c / (2 (x_{m+1} - x_{m-1})) of cell m and at [(m+1)*kGeo + 4] the
+// update factor dt c b3 / width of cell m.
+struct alignas(64) Inst3 {
+  void* buf[2];
+  const double* geo[3];
+  const float* geof[3];
+  long long plane;         // elements per direction plane: nz * ny * pitch
+  unsigned buf_bytes;      // bytes of one buffer (< 4 GiB)
+  int n[3];
+  int pitch, q;
+  int bc[3];               // DUGKS_BC_PERIODIC or DUGKS_BC_MIRROR per axis
+  int ncoef, storage;
+  double ra, rb, b1, kg;
+  float raf, rbf, b1f, kgf;
+  double e[kMaxQ][kMaxCoef];   // E_i(phi) = sum_k e[i][k] phi^k (eq. 2.3)
+  float ef[kMaxQ][kMaxCoef];
+};
+
+struct Launch3 {
+  int rows = 2;     // interior rows per block (1..kMaxRowsPerBlock)
+  int planes = 32;  // planes swept per block
+};
+
+// Blocks of one step for the launch (x strips x row tiles x plane chunks).
+long long step3_blocks(const Inst3& h, const Launch3& l);
+int launch_step3(const Inst3* d, const Inst3& h, int parity, const Launch3& l, void* stream);
+int launch_init3(const Inst3* d, const Inst3& h, const double* phi, int parity, void* stream);
+int launch_set_f3(const Inst3* d, const Inst3& h, const double* f, int parity, void* stream);
+int launch_get_phi3(const Inst3* d, const Inst3& h, double* out, int parity, void* stream);
+int launch_get_f3(const Inst3* d, const Inst3& h, double* out, int parity, void* stream);
+// out[0] mass, [1] sum|phi-ref|, [2] sum|ref|, [3] sum (phi-ref)^2 |V|, [4] sum ref^2 |V|,
+// [5] non-finite cells; widths = dx[0..nx) dy[0..ny) dz[0..nz); partial holds
+// reduce3_partials() * 8 doubles.
+int launch_reduce3(const Inst3* d, const Inst3& h, const double* ref, int parity,
+                   const double* widths, double* partial, double* out, void* stream);
+int reduce3_partials();
+
+}  // namespace dugks3

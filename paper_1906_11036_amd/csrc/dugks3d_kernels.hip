@@ -1,0 +1,630 @@
+// gfx950 kernels of the three-dimensional DUGKS step (Sec. 2) on D3Q15
+// (eq. 2.28), D3Q19 (eq. 2.6) and D3Q7 (Remark 3).
+//
+// Fused step: a block owns a strip of 62 columns (64 lanes: one halo column
+// each side), a tile of `rows` rows plus one halo row each side (one wave per
+// row) and a chunk of planes, which it sweeps in z.  Each wave keeps g of its
+// row at planes z-1, z, z+1 in registers and publishes them to LDS (three
+// plane slots); after a barrier every interior wave reads its neighbour rows
+// from LDS and computes, for its cells, the west face (x), both y faces, the
+// top face (z; the bottom one is the previous plane's top face) and the
+// update, then a second barrier protects the slot the next plane overwrites.
+// x neighbours come from whole-wave DPP shifts, as in the 2-D kernels.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "dugks3d_internal.h"
+
+namespace dugks3 {
+
+// ------------------------------------------------------------------ lattice
+// Integer directions: D3Q15 as the columns of eq. 2.28, D3Q19 as those of
+// eq. 2.6; D3Q7 is the first seven of either.
+__host__ __device__ constexpr int d3q15(int k, int a) {
+  constexpr int t[15][3] = {{0, 0, 0},   {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},   {0, -1, 0},
+                            {0, 0, 1},   {0, 0, -1}, {1, 1, 1},  {1, 1, -1},  {1, -1, 1},
+                            {-1, 1, 1},  {-1, -1, -1}, {-1, -1, 1}, {-1, 1, -1}, {1, -1, -1}};
+  return t[k][a];
+}
+__host__ __device__ constexpr int d3q19(int k, int a) {
+  constexpr int t[19][3] = {{0, 0, 0},  {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
+                            {0, 0, 1},  {0, 0, -1},  {1, 1, 0},  {-1, -1, 0}, {1, -1, 0},
+                            {-1, 1, 0}, {1, 0, 1},   {-1, 0, -1}, {-1, 0, 1}, {1, 0, -1},
+                            {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+  return t[k][a];
+}
+template <int Q> __host__ __device__ constexpr int ce(int k, int a) {
+  return Q == 19 ? d3q19(k, a) : d3q15(k, a);
+}
+// the direction with component a reversed (specular mirror of a wall normal to a)
+template <int Q> __host__ __device__ constexpr int mir(int k, int a) {
+  for (int j = 0; j < Q; ++j) {
+    bool same = true;
+    for (int b = 0; b < 3; ++b)
+      if (ce<Q>(j, b) != (b == a ? -ce<Q>(k, b) : ce<Q>(k, b))) same = false;
+    if (same) return j;
+  }
+  return k;
+}
+
+// ---------------------------------------------------------------- storage
+template <int ST> struct S3;
+template <> struct S3<DUGKS_F64> { using T = double; };
+template <> struct S3<DUGKS_F32> { using T = float; };
+
+template <typename T> struct C3;
+template <> struct C3<double> {
+  __device__ static const double* e(const Inst3* I, int k) { return I->e[k]; }
+  __device__ static double ra(const Inst3* I) { return I->ra; }
+  __device__ static double rb(const Inst3* I) { return I->rb; }
+  __device__ static double b1(const Inst3* I) { return I->b1; }
+  __device__ static double kg(const Inst3* I) { return I->kg; }
+  __device__ static const double* geo(const Inst3* I, int a) { return I->geo[a]; }
+};
+template <> struct C3<float> {
+  __device__ static const float* e(const Inst3* I, int k) { return I->ef[k]; }
+  __device__ static float ra(const Inst3* I) { return I->raf; }
+  __device__ static float rb(const Inst3* I) { return I->rbf; }
+  __device__ static float b1(const Inst3* I) { return I->b1f; }
+  __device__ static float kg(const Inst3* I) { return I->kgf; }
+  __device__ static const float* geo(const Inst3* I, int a) { return I->geof[a]; }
+};
+
+template <int NC, typename T> __device__ __forceinline__ T horner(const T* c, T x) {
+  T r = c[NC - 1];
+#pragma unroll
+  for (int m = NC - 2; m >= 0; --m) r = fma(r, x, c[m]);
+  return r;
+}
+
+// Uniform reads through the constant address space become scalar loads.
+template <typename T> using CPtr = const __attribute__((address_space(4))) T*;
+template <typename T> __device__ __forceinline__ CPtr<T> as_constant(const T* p) { return (CPtr<T>)p; }
+
+// ------------------------------------------------------------ lane shifts
+// wave_shr:1 -> lane l receives lane l-1; wave_shl:1 -> lane l receives lane l+1
+__device__ __forceinline__ float shr1(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x138, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float shl1(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xF, 0xF, true));
+}
+__device__ __forceinline__ double shr1(double v) {
+  int2 p = __builtin_bit_cast(int2, v);
+  p.x = __builtin_amdgcn_mov_dpp(p.x, 0x138, 0xF, 0xF, true);
+  p.y = __builtin_amdgcn_mov_dpp(p.y, 0x138, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, p);
+}
+__device__ __forceinline__ double shl1(double v) {
+  int2 p = __builtin_bit_cast(int2, v);
+  p.x = __builtin_amdgcn_mov_dpp(p.x, 0x130, 0xF, 0xF, true);
+  p.y = __builtin_amdgcn_mov_dpp(p.y, 0x130, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, p);
+}
+
+// ------------------------------------------------------------ memory
+typedef unsigned v2u __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+template <int Q, typename T>
+__device__ __forceinline__ void load_row(T* f, __amdgpu_buffer_rsrc_t R, unsigned plane, unsigned idx) {
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    if constexpr (sizeof(T) == 8)
+      f[k] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(R, idx * 8u, (unsigned)k * plane * 8u, 0));
+    else
+      f[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(R, idx * 4u, (unsigned)k * plane * 4u, 0));
+  }
+}
+
+__device__ __forceinline__ int src_index(int i, int n, int bc) {
+  if (i >= 0 && i < n) return i;
+  if (bc == DUGKS_BC_PERIODIC) {
+    int w = i < 0 ? i + n : i - n;
+    return w < 0 ? 0 : (w >= n ? n - 1 : w);
+  }
+  return i < 0 ? 0 : n - 1;
+}
+
+// ------------------------------------------------------------ cell and face
+// g = fbar+ / b1 = (a1/b1) f~ + E(phi) (eq. 2.21 over b1); phi in binary64.
+template <int Q, int NC, typename T>
+__device__ __forceinline__ void cell_g3(const Inst3* __restrict__ I, const T* f, T* g) {
+  double phi = 0.0;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) phi += (double)f[k];
+  const T p = (T)phi, ra = C3<T>::ra(I);
+#pragma unroll
+  for (int k = 0; k < Q; ++k) g[k] = fma(ra, f[k], horner<NC>(C3<T>::e(I, k), p));
+}
+
+template <int Q, typename T> __device__ __forceinline__ void mirror(T* g, int a) {
+  T t[Q];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) t[k] = g[mir<Q>(k, a)];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) g[k] = t[k];
+}
+
+template <int Q, typename T> __device__ __forceinline__ T dir_sum(const T* v) {
+  if constexpr (sizeof(T) == 8) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) s += v[k];
+    return s;
+  } else {
+    T t[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) t[k] = v[k];
+#pragma unroll
+    for (int w = 1; w < Q; w *= 2)
+#pragma unroll
+      for (int k = 0; k + w < Q; k += 2 * w) t[k] += t[k + w];
+    return t[0];
+  }
+}
+
+// tangential axes of a face normal to A, in increasing order
+template <int A> constexpr int tan1() { return A == 0 ? 1 : 0; }
+template <int A> constexpr int tan2() { return A == 2 ? 1 : 2; }
+
+// Half-step interface distribution on a face normal to axis A (eq. 2.20,
+// eq. 2.19 in the form of eq. 2.26) in the scaled form, the interface phi and
+// F = f_b / b3 (eq. 2.22) for the directions with a normal component.
+// t1, t2: sums of the two cells' central-difference numerators along the
+// tangential axes tan1<A>, tan2<A>; tau1, tau2 their factors h c / (2 dist).
+template <int Q, int NC, int A, typename T>
+__device__ __forceinline__ void face3(const Inst3* __restrict__ I, const T* L, const T* R,
+                                      const T* t1, T tau1, const T* t2, T tau2, T am, T a0, T ap,
+                                      T* out) {
+  T gb[Q];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    const int cn = ce<Q>(k, A), c1 = ce<Q>(k, tan1<A>()), c2 = ce<Q>(k, tan2<A>());
+    const T al = cn > 0 ? ap : (cn < 0 ? am : a0);
+    T v = fma(al, R[k] - L[k], L[k]);
+    if (c1 != 0) v = fma((T)(-c1) * tau1, t1[k], v);
+    if (c2 != 0) v = fma((T)(-c2) * tau2, t2[k], v);
+    gb[k] = v;
+  }
+  const T pb = (T)(dir_sum<Q>(gb) * C3<T>::b1(I));
+  const T rb = C3<T>::rb(I);
+#pragma unroll
+  for (int k = 0; k < Q; ++k)
+    if (ce<Q>(k, A) != 0) out[k] = fma(rb, gb[k], horner<NC>(C3<T>::e(I, k), pb));
+}
+
+extern __shared__ __align__(16) unsigned char dugks3_lds[];
+
+// ------------------------------------------------------------ fused step
+// Threads per block: at most 2 interior rows (4 waves), so that a wave may
+// hold the whole register file of its SIMD (the window of g over three planes
+// plus the faces of up to 19 directions).
+template <int ST> constexpr int max_threads3() { return 256; }
+
+template <int Q, int ST, int NC>
+__global__ __launch_bounds__(max_threads3<ST>()) void k_step3(const Inst3* __restrict__ I, int parity, int rows,
+                                               int planes, int strips, int tiles) {
+  using T = typename S3<ST>::T;
+  T* lds = (T*)dugks3_lds;
+  const int W = rows + 2;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  int b = blockIdx.x;
+  const int sx = b % strips;
+  b /= strips;
+  const int tj = b % tiles, tk = b / tiles;
+  const int nx = I->n[0], ny = I->n[1], nz = I->n[2];
+  const int bcx = I->bc[0], bcy = I->bc[1], bcz = I->bc[2];
+  const int pitch = I->pitch;
+  const unsigned plane = (unsigned)I->plane;
+  const int x0 = sx * kCols, y0 = tj * rows, z0 = tk * planes;
+  const int y1 = min(y0 + rows, ny), z1 = min(z0 + planes, nz);
+  // this wave's row; waves past the tile's upper halo row repeat it
+  const int rr = y0 - 1 + w;
+  const int r = rr < y1 ? rr : y1;
+  const bool inner = w >= 1 && rr < y1;
+  const int c = x0 - 1 + lane;
+  const int scol = src_index(c < nx + 1 ? c : nx, nx, bcx);
+  const bool wall_x = (c < 0 || c >= nx) && bcx != DUGKS_BC_PERIODIC;
+  const bool live = inner && lane >= 1 && lane <= kCols && c < nx;
+  const int srow = src_index(r, ny, bcy);
+  const bool wall_y = (r < 0 || r >= ny) && bcy != DUGKS_BC_PERIODIC;
+
+  const __amdgpu_buffer_rsrc_t Rin = rsrc(I->buf[parity], I->buf_bytes);
+  const __amdgpu_buffer_rsrc_t Rout = rsrc(I->buf[parity ^ 1], I->buf_bytes);
+
+  // column factors (per lane), row factors (uniform), plane factors (uniform)
+  const T* cg = C3<T>::geo(I, 0) + (long long)(c + 1 < nx + 1 ? c + 1 : nx + 1) * kGeo;
+  const T cam = cg[0], ca0 = cg[1], cap = cg[2], ctau = cg[3], ck = cg[4];
+  const CPtr<T> yg = as_constant(C3<T>::geo(I, 1));
+  const CPtr<T> zg = as_constant(C3<T>::geo(I, 2));
+  const int ryi = (r + 1 < ny + 1 ? r + 1 : ny + 1);   // table index of row r (clamped for idle waves)
+  const T ytau = yg[ryi * kGeo + 3], ky = yg[ryi * kGeo + 4];
+  const T yS0 = yg[ryi * kGeo + 0], yS1 = yg[ryi * kGeo + 1], yS2 = yg[ryi * kGeo + 2];
+  const int ryn = (ryi + 1 < ny + 2 ? ryi + 1 : ny + 1);
+  const T yN0 = yg[ryn * kGeo + 0], yN1 = yg[ryn * kGeo + 1], yN2 = yg[ryn * kGeo + 2];
+
+  auto row_idx = [&](int zp) -> unsigned {
+    return (unsigned)((src_index(zp, nz, bcz) * ny + srow) * pitch + scol);
+  };
+  auto make_g = [&](const T* f, int zp, T* g) {
+    cell_g3<Q, NC, T>(I, f, g);
+    if (wall_x) mirror<Q, T>(g, 0);
+    if (wall_y) mirror<Q, T>(g, 1);
+    if ((zp < 0 || zp >= nz) && bcz != DUGKS_BC_PERIODIC) mirror<Q, T>(g, 2);
+  };
+  auto lds_at = [&](int slot, int row, int k) -> T* {
+    return lds + ((long long)(slot * W + row) * Q + k) * kLanes + lane;
+  };
+  auto publish = [&](int slot, const T* g) {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) *lds_at(slot, w, k) = g[k];
+  };
+
+  // Window slot of plane p: (p - z0) mod 3, for g (G), raw f~ (RW) and the top z-face (FZ).
+  T G[3][Q], RW[3][Q], FZ[3][Q];
+
+  // prologue: plane z0-1 in slot 2, plane z0 in slot 0, plane z0+1 loading into RW[1]
+  load_row<Q, T>(RW[2], Rin, plane, row_idx(z0 - 1));
+  load_row<Q, T>(RW[0], Rin, plane, row_idx(z0));
+  load_row<Q, T>(RW[1], Rin, plane, row_idx(z0 + 1 <= z1 ? z0 + 1 : z1));
+  make_g(RW[2], z0 - 1, G[2]);
+  make_g(RW[0], z0, G[0]);
+  publish(2, G[2]);
+  publish(0, G[0]);
+  __syncthreads();
+  if (inner) {  // bottom face of plane z0 (between z0-1 and z0)
+    T t1[Q], t2[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      if (ce<Q>(k, 0) != 0)
+        t1[k] = (shl1(G[2][k]) - shr1(G[2][k])) + (shl1(G[0][k]) - shr1(G[0][k]));
+      if (ce<Q>(k, 1) != 0)
+        t2[k] = (*lds_at(2, w + 1, k) - *lds_at(2, w - 1, k)) + (*lds_at(0, w + 1, k) - *lds_at(0, w - 1, k));
+    }
+    const int zi = z0 + 1;   // table index of the face between z0-1 and z0
+    face3<Q, NC, 2, T>(I, G[2], G[0], t1, ctau, t2, ytau, zg[zi * kGeo + 0], zg[zi * kGeo + 1],
+                       zg[zi * kGeo + 2], FZ[2]);
+  }
+
+  bool bad = false;
+  auto body = [&](int z, auto slot) {
+    constexpr int s0 = decltype(slot)::value, sp = (s0 + 1) % 3, sm = (s0 + 2) % 3;
+    // plane z+1: g from the raw values in RW[sp]; plane z+2 starts loading
+    load_row<Q, T>(RW[sm], Rin, plane, row_idx(z + 2 <= z1 ? z + 2 : z1));
+    make_g(RW[sp], z + 1, G[sp]);
+    publish(sp, G[sp]);
+    __syncthreads();
+    if (inner) {
+      const int zi = z + 1;   // table index of plane z
+      const T ztau = zg[zi * kGeo + 3], kz = zg[zi * kGeo + 4];
+      // f~+ = (4/3) b1 g - f~ / 3 (eq. 2.23); the update (eq. 2.24) is
+      // accumulated into o face by face
+      const T kgv = C3<T>::kg(I);
+      T o[Q];
+#pragma unroll
+      for (int k = 0; k < Q; ++k) o[k] = fma(kgv, G[s0][k], (T)(-1.0 / 3.0) * RW[s0][k]);
+      T sx0[Q], dY[Q], dZ[Q], t1[Q], t2[Q];
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        if (ce<Q>(k, 0) != 0) sx0[k] = shl1(G[s0][k]) - shr1(G[s0][k]);
+        if (ce<Q>(k, 1) != 0) dY[k] = *lds_at(s0, w + 1, k) - *lds_at(s0, w - 1, k);
+        if (ce<Q>(k, 2) != 0) dZ[k] = G[sp][k] - *lds_at(sm, w, k);   // plane z-1 from LDS
+      }
+      {  // west face (x): left state from lane - 1; the east face is lane + 1's west face
+        T lw[Q], fW[Q];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          lw[k] = shr1(G[s0][k]);
+          if (ce<Q>(k, 1) != 0) t1[k] = shr1(dY[k]) + dY[k];
+          if (ce<Q>(k, 2) != 0) t2[k] = shr1(dZ[k]) + dZ[k];
+        }
+        face3<Q, NC, 0, T>(I, lw, G[s0], t1, ytau, t2, ztau, cam, ca0, cap, fW);
+#pragma unroll
+        for (int k = 0; k < Q; ++k)
+          if (ce<Q>(k, 0) != 0) o[k] = fma((T)(-ce<Q>(k, 0)) * ck, shl1(fW[k]) - fW[k], o[k]);
+      }
+      {  // north face (rows r, r+1)
+        T gU[Q], fN[Q];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          gU[k] = *lds_at(s0, w + 1, k);
+          if (ce<Q>(k, 0) != 0) t1[k] = sx0[k] + (shl1(gU[k]) - shr1(gU[k]));
+          if (ce<Q>(k, 2) != 0) t2[k] = dZ[k] + (*lds_at(sp, w + 1, k) - *lds_at(sm, w + 1, k));
+        }
+        face3<Q, NC, 1, T>(I, G[s0], gU, t1, ctau, t2, ztau, yN0, yN1, yN2, fN);
+#pragma unroll
+        for (int k = 0; k < Q; ++k)
+          if (ce<Q>(k, 1) != 0) o[k] = fma((T)(-ce<Q>(k, 1)) * ky, fN[k], o[k]);
+      }
+      {  // south face (rows r-1, r)
+        T gD[Q], fS[Q];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          gD[k] = *lds_at(s0, w - 1, k);
+          if (ce<Q>(k, 0) != 0) t1[k] = sx0[k] + (shl1(gD[k]) - shr1(gD[k]));
+          if (ce<Q>(k, 2) != 0) t2[k] = dZ[k] + (*lds_at(sp, w - 1, k) - *lds_at(sm, w - 1, k));
+        }
+        face3<Q, NC, 1, T>(I, gD, G[s0], t1, ctau, t2, ztau, yS0, yS1, yS2, fS);
+#pragma unroll
+        for (int k = 0; k < Q; ++k)
+          if (ce<Q>(k, 1) != 0) o[k] = fma((T)ce<Q>(k, 1) * ky, fS[k], o[k]);
+      }
+      {  // top face (planes z, z+1); the bottom face is the previous plane's top face
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          if (ce<Q>(k, 0) != 0) t1[k] = sx0[k] + (shl1(G[sp][k]) - shr1(G[sp][k]));
+          if (ce<Q>(k, 1) != 0) t2[k] = dY[k] + (*lds_at(sp, w + 1, k) - *lds_at(sp, w - 1, k));
+        }
+        const int zt = z + 2;   // table index of the face between z and z+1
+        face3<Q, NC, 2, T>(I, G[s0], G[sp], t1, ctau, t2, ytau, zg[zt * kGeo + 0], zg[zt * kGeo + 1],
+                           zg[zt * kGeo + 2], FZ[s0]);
+#pragma unroll
+        for (int k = 0; k < Q; ++k)
+          if (ce<Q>(k, 2) != 0) o[k] = fma((T)(-ce<Q>(k, 2)) * kz, FZ[s0][k] - FZ[sm][k], o[k]);
+      }
+      if (live) {
+        bad |= !__builtin_isfinite(o[0]);
+        const unsigned idx = (unsigned)(((long long)z * ny + r) * pitch + c);
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          if constexpr (sizeof(T) == 8)
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, o[k]), Rout, idx * 8u,
+                                                  (unsigned)k * plane * 8u, 0);
+          else
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, o[k]), Rout, idx * 4u,
+                                                  (unsigned)k * plane * 4u, 0);
+        }
+      }
+    }
+    __syncthreads();   // the next plane overwrites slot sm
+  };
+  using S0 = std::integral_constant<int, 0>;
+  using S1 = std::integral_constant<int, 1>;
+  using S2 = std::integral_constant<int, 2>;
+  int z = z0;
+  for (; z + 3 <= z1; z += 3) {
+    body(z, S0{});
+    body(z + 1, S1{});
+    body(z + 2, S2{});
+  }
+  if (z < z1) body(z, S0{});
+  if (z + 1 < z1) body(z + 1, S1{});
+  (void)bad;
+}
+
+// -------------------------------------------------- init, copies, read-outs
+template <int Q>
+__device__ __forceinline__ void feq64(const Inst3* __restrict__ I, double phi, double* E) {
+  const int nc = I->ncoef;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    double r = I->e[k][nc - 1];
+    for (int m = nc - 2; m >= 0; --m) r = fma(r, phi, I->e[k][m]);
+    E[k] = r;
+  }
+}
+
+template <int Q, int ST>
+__global__ void k_init3(const Inst3* __restrict__ I, const double* __restrict__ phi, int parity) {
+  using T = typename S3<ST>::T;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+  if (i >= I->n[0]) return;
+  const long long cell = ((long long)k * I->n[1] + j) * I->n[0] + i;
+  const long long off = ((long long)k * I->n[1] + j) * I->pitch + i;
+  double E[Q];
+  feq64<Q>(I, phi[cell], E);
+  T* buf = (T*)I->buf[parity];
+#pragma unroll
+  for (int m = 0; m < Q; ++m) buf[m * I->plane + off] = (T)E[m];
+}
+
+template <int Q, int ST>
+__global__ void k_set_f3(const Inst3* __restrict__ I, const double* __restrict__ f, int parity) {
+  using T = typename S3<ST>::T;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+  if (i >= I->n[0]) return;
+  const long long N = (long long)I->n[0] * I->n[1] * I->n[2];
+  const long long cell = ((long long)k * I->n[1] + j) * I->n[0] + i;
+  const long long off = ((long long)k * I->n[1] + j) * I->pitch + i;
+  T* buf = (T*)I->buf[parity];
+#pragma unroll
+  for (int m = 0; m < Q; ++m) buf[m * I->plane + off] = (T)f[m * N + cell];
+}
+
+template <int Q, int ST>
+__global__ void k_get3(const Inst3* __restrict__ I, double* __restrict__ out, int parity, int want_f) {
+  using T = typename S3<ST>::T;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+  if (i >= I->n[0]) return;
+  const long long N = (long long)I->n[0] * I->n[1] * I->n[2];
+  const long long cell = ((long long)k * I->n[1] + j) * I->n[0] + i;
+  const long long off = ((long long)k * I->n[1] + j) * I->pitch + i;
+  const T* buf = (const T*)I->buf[parity];
+  if (want_f) {
+#pragma unroll
+    for (int m = 0; m < Q; ++m) out[m * N + cell] = (double)buf[m * I->plane + off];
+  } else {
+    double phi = 0.0;
+#pragma unroll
+    for (int m = 0; m < Q; ++m) phi += (double)buf[m * I->plane + off];
+    out[cell] = phi;
+  }
+}
+
+constexpr int kRedBlocks = 1024;
+constexpr int kRedThreads = 256;
+constexpr int kRedVals = 8;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+template <int Q, int ST>
+__global__ __launch_bounds__(kRedThreads) void k_reduce3(const Inst3* __restrict__ I,
+                                                         const double* __restrict__ ref, int parity,
+                                                         const double* __restrict__ widths,
+                                                         double* __restrict__ partial) {
+  using T = typename S3<ST>::T;
+  const int nx = I->n[0], ny = I->n[1];
+  const long long N = (long long)nx * ny * I->n[2];
+  const T* buf = (const T*)I->buf[parity];
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N;
+       n += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(n % nx);
+    const long long jk = n / nx;
+    const int j = (int)(jk % ny), k = (int)(jk / ny);
+    const long long off = ((long long)k * ny + j) * I->pitch + i;
+    double phi = 0.0;
+#pragma unroll
+    for (int m = 0; m < Q; ++m) phi += (double)buf[m * I->plane + off];
+    const double vol = widths[i] * widths[nx + j] * widths[nx + ny + k];
+    if (!__builtin_isfinite(phi)) {
+      acc[5] += 1.0;
+      continue;
+    }
+    acc[0] += phi * vol;
+    if (ref != nullptr) {
+      const double rv = ref[n], d = phi - rv;
+      acc[1] += fabs(d);
+      acc[2] += fabs(rv);
+      acc[3] += d * d * vol;
+      acc[4] += rv * rv * vol;
+    }
+  }
+  __shared__ double sh[kRedThreads / 64][6];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int v = 0; v < 6; ++v) {
+    const double s = wave_sum(acc[v]);
+    if (lane == 0) sh[wv][v] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    double s = 0.0;
+    for (int ww = 0; ww < kRedThreads / 64; ++ww) s += sh[ww][threadIdx.x];
+    partial[blockIdx.x * kRedVals + threadIdx.x] = s;
+  }
+}
+
+__global__ void k_reduce3_final(const double* __restrict__ partial, int nblocks, double* __restrict__ out) {
+  const int v = threadIdx.x;
+  if (v >= kRedVals) return;
+  double s = 0.0;
+  for (int b = 0; b < nblocks; ++b) s += partial[b * kRedVals + v];
+  out[v] = s;
+}
+
+// --------------------------------------------------------------- launch
+static inline hipStream_t S(void* s) { return (hipStream_t)s; }
+
+long long step3_blocks(const Inst3& h, const Launch3& l) {
+  const long long strips = (h.n[0] + kCols - 1) / kCols;
+  const long long tiles = (h.n[1] + l.rows - 1) / l.rows;
+  const long long chunks = (h.n[2] + l.planes - 1) / l.planes;
+  return strips * tiles * chunks;
+}
+
+template <int Q, int ST>
+static int step3_q_st(const Inst3* d, const Inst3& h, int parity, const Launch3& l, void* stream) {
+  using T = typename S3<ST>::T;
+  const int strips = (h.n[0] + kCols - 1) / kCols;
+  const int tiles = (h.n[1] + l.rows - 1) / l.rows;
+  const long long blocks = step3_blocks(h, l);
+  if (blocks <= 0 || blocks > 0x7fffffffLL) return -1;
+  const size_t shmem = (size_t)3 * (l.rows + 2) * Q * kLanes * sizeof(T);
+  dim3 grid((unsigned)blocks), block(64 * (l.rows + 2));
+  switch (h.ncoef <= 2 ? 2 : (h.ncoef <= 4 ? 4 : 8)) {
+    case 2: hipLaunchKernelGGL((k_step3<Q, ST, 2>), grid, block, shmem, S(stream), d, parity, l.rows, l.planes, strips, tiles); break;
+    case 4: hipLaunchKernelGGL((k_step3<Q, ST, 4>), grid, block, shmem, S(stream), d, parity, l.rows, l.planes, strips, tiles); break;
+    default: hipLaunchKernelGGL((k_step3<Q, ST, 8>), grid, block, shmem, S(stream), d, parity, l.rows, l.planes, strips, tiles); break;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int ST>
+static int step3_st(const Inst3* d, const Inst3& h, int parity, const Launch3& l, void* stream) {
+  switch (h.q) {
+    case 19: return step3_q_st<19, ST>(d, h, parity, l, stream);
+    case 15: return step3_q_st<15, ST>(d, h, parity, l, stream);
+    default: return step3_q_st<7, ST>(d, h, parity, l, stream);
+  }
+}
+
+int launch_step3(const Inst3* d, const Inst3& h, int parity, const Launch3& l, void* stream) {
+  return h.storage == DUGKS_F64 ? step3_st<DUGKS_F64>(d, h, parity, l, stream)
+                                : step3_st<DUGKS_F32>(d, h, parity, l, stream);
+}
+
+#define DUGKS3_PER_CELL(KERNEL, ...)                                                               \
+  do {                                                                                             \
+    dim3 grid((h.n[0] + 255) / 256, h.n[1], h.n[2]), block(256);                                   \
+    const bool f64 = h.storage == DUGKS_F64;                                                       \
+    switch (h.q) {                                                                                 \
+      case 19:                                                                                     \
+        if (f64) hipLaunchKernelGGL((KERNEL<19, DUGKS_F64>), grid, block, 0, S(stream), __VA_ARGS__); \
+        else hipLaunchKernelGGL((KERNEL<19, DUGKS_F32>), grid, block, 0, S(stream), __VA_ARGS__);     \
+        break;                                                                                     \
+      case 15:                                                                                     \
+        if (f64) hipLaunchKernelGGL((KERNEL<15, DUGKS_F64>), grid, block, 0, S(stream), __VA_ARGS__); \
+        else hipLaunchKernelGGL((KERNEL<15, DUGKS_F32>), grid, block, 0, S(stream), __VA_ARGS__);     \
+        break;                                                                                     \
+      default:                                                                                     \
+        if (f64) hipLaunchKernelGGL((KERNEL<7, DUGKS_F64>), grid, block, 0, S(stream), __VA_ARGS__);  \
+        else hipLaunchKernelGGL((KERNEL<7, DUGKS_F32>), grid, block, 0, S(stream), __VA_ARGS__);      \
+        break;                                                                                     \
+    }                                                                                              \
+  } while (0)
+
+int launch_init3(const Inst3* d, const Inst3& h, const double* phi, int parity, void* stream) {
+  DUGKS3_PER_CELL(k_init3, d, phi, parity);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+int launch_set_f3(const Inst3* d, const Inst3& h, const double* f, int parity, void* stream) {
+  DUGKS3_PER_CELL(k_set_f3, d, f, parity);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+int launch_get_phi3(const Inst3* d, const Inst3& h, double* out, int parity, void* stream) {
+  DUGKS3_PER_CELL(k_get3, d, out, parity, 0);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+int launch_get_f3(const Inst3* d, const Inst3& h, double* out, int parity, void* stream) {
+  DUGKS3_PER_CELL(k_get3, d, out, parity, 1);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int reduce3_partials() { return kRedBlocks; }
+
+int launch_reduce3(const Inst3* d, const Inst3& h, const double* ref, int parity,
+                   const double* widths, double* partial, double* out, void* stream) {
+  dim3 grid(kRedBlocks), block(kRedThreads);
+  const bool f64 = h.storage == DUGKS_F64;
+  switch (h.q) {
+    case 19:
+      if (f64) hipLaunchKernelGGL((k_reduce3<19, DUGKS_F64>), grid, block, 0, S(stream), d, ref, parity, widths, partial);
+      else hipLaunchKernelGGL((k_reduce3<19, DUGKS_F32>), grid, block, 0, S(stream), d, ref, parity, widths, partial);
+      break;
+    case 15:
+      if (f64) hipLaunchKernelGGL((k_reduce3<15, DUGKS_F64>), grid, block, 0, S(stream), d, ref, parity, widths, partial);
+      else hipLaunchKernelGGL((k_reduce3<15, DUGKS_F32>), grid, block, 0, S(stream), d, ref, parity, widths, partial);
+      break;
+    default:
+      if (f64) hipLaunchKernelGGL((k_reduce3<7, DUGKS_F64>), grid, block, 0, S(stream), d, ref, parity, widths, partial);
+      else hipLaunchKernelGGL((k_reduce3<7, DUGKS_F32>), grid, block, 0, S(stream), d, ref, parity, widths, partial);
+      break;
+  }
+  if (hipGetLastError() != hipSuccess) return -1;
+  hipLaunchKernelGGL(k_reduce3_final, dim3(1), dim3(64), 0, S(stream), partial, kRedBlocks, out);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace dugks3

@@ -1,5 +1,6 @@
 """Host-only checks of the C ABI: the library loads, exports every function of
-include/dugks.h, and validates arguments without touching a device."""
+include/dugks.h and include/dugks3d.h, and validates arguments without touching
+a device."""
 import ctypes as C
 import os
 import re
@@ -10,13 +11,15 @@ import pytest
 from paper_1906_11036_amd import _lib as L
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "dugks.h")
+HEADERS = [os.path.join(ROOT, "include", n) for n in ("dugks.h", "dugks3d.h")]
 
 
 def header_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(dugks_[A-Za-z_0-9]+)\s*\(", text)))
+    names = set()
+    for path in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(path).read(), flags=re.S)
+        names |= set(re.findall(r"\b(dugks3?_[A-Za-z_0-9]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declares_the_boundary():
@@ -142,3 +145,60 @@ def test_source_is_refused_where_it_is_not_built():
         assert "source" in lib.dugks_last_error(h).decode()
         assert lib.dugks_set_source(h, None, 0.0) == L.OK
         lib.dugks_destroy(h)
+
+
+def _create3(nx=8, ny=6, nz=5, q=19, **kw):
+    lib = L.lib()
+    f = [np.linspace(0, 1, n + 1) for n in (nx, ny, nz)]
+    p = L.Params3()
+    p.abi_version = kw.get("abi", L.ABI3_VERSION)
+    p.storage = kw.get("storage", L.F64)
+    for i, b in enumerate(kw.get("bc", (0, 0, 0))):
+        p.bc[i] = b
+    p.c, p.cfl, p.alpha = kw.get("c", 1.0), kw.get("cfl", 0.5), kw.get("alpha", 1e-3)
+    h = C.c_void_p()
+    P = C.POINTER(C.c_double)
+    rc = lib.dugks3_create(C.byref(h), nx, ny, nz, f[0].ctypes.data_as(P), f[1].ctypes.data_as(P),
+                           f[2].ctypes.data_as(P), q, C.byref(p))
+    return rc, h
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(q=9), L.E_UNSUPPORTED), (dict(storage=L.F16NEQ), L.E_UNSUPPORTED),
+    (dict(bc=(1, 0, 0)), L.E_UNSUPPORTED), (dict(cfl=1.0), L.E_ARG), (dict(nz=0), L.E_ARG),
+    (dict(abi=99), L.E_ARG),
+])
+def test_create3_rejects_bad_arguments(kw, code):
+    rc, h = _create3(**kw)
+    assert rc == code
+    assert L.lib().dugks3_last_error(h).decode()
+    L.lib().dugks3_destroy(h)
+
+
+def test_3d_sizes_and_state_errors():
+    lib = L.lib()
+    for storage, per in ((L.F64, 8 * 19), (L.F32, 4 * 19)):
+        rc, h = _create3(nx=100, ny=6, nz=5, storage=storage)
+        assert rc == L.OK
+        info = L.Info3()
+        assert lib.dugks3_get_info(h, C.byref(info)) == L.OK
+        assert info.pitch == 128 and info.state_bytes == per * 128 * 6 * 5
+        assert info.nz == 5 and info.q == 19
+        assert lib.dugks3_workspace_bytes(h) >= 2 * info.state_bytes
+        assert lib.dugks3_step(h, 1) == L.E_STATE
+        assert lib.dugks3_set_launch(h, 3, 8) == L.E_ARG
+        assert lib.dugks3_set_launch(h, 2, 0) == L.E_ARG
+        assert lib.dugks3_set_launch(h, 1, 16) == L.OK
+        lib.dugks3_destroy(h)
+
+
+def test_d3q7_accepts_only_identity_diffusion():
+    lib = L.lib()
+    rc, h = _create3(q=7)
+    assert rc == L.OK
+    P = C.POINTER(C.c_double)
+    eye = np.array([0, 1, 0, 1, 0, 1, 0, 0, 0, 0, 0, 0], dtype=float)
+    assert lib.dugks3_set_D(h, 1, eye.ctypes.data_as(P)) == L.OK
+    bad = eye.copy(); bad[1] = 2.0
+    assert lib.dugks3_set_D(h, 1, bad.ctypes.data_as(P)) == L.E_UNSUPPORTED
+    lib.dugks3_destroy(h)

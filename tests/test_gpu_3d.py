@@ -1,0 +1,113 @@
+"""GPU parity of the three-dimensional path (D3Q15, D3Q19, D3Q7) against the
+3-D CPU oracle, through the C ABI of include/dugks3d.h."""
+import math
+
+import numpy as np
+import pytest
+
+import paper_1906_11036_amd as dg
+from oracle import Oracle3D
+from paper_1906_11036_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+EPS32 = float(np.finfo(np.float32).eps)
+P, M = W.PERIODIC, W.MIRROR
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def solver(p, storage, launch=None):
+    s = dg.Solver3D(p, storage=storage)
+    if launch is not None:
+        try:
+            s.set_launch(*launch)
+        except dg.DugksError as e:
+            pytest.skip(f"launch {launch} not available on this device: {e}")
+    return s
+
+
+CASES = [
+    (1, 1, 1, 19, (P, P, P)), (5, 4, 3, 19, (P, P, P)), (62, 3, 4, 19, (M, P, M)),
+    (63, 5, 2, 19, (P, M, P)), (64, 2, 7, 15, (P, P, P)), (65, 4, 5, 15, (M, M, M)),
+    (130, 3, 3, 19, (P, P, P)), (17, 9, 11, 19, (M, P, P)), (9, 7, 6, 7, (P, M, P)),
+    (70, 6, 4, 7, (M, M, M)),
+]
+
+
+@pytest.mark.parametrize("nx,ny,nz,q,bc", CASES)
+def test_fp64_matches_oracle(nx, ny, nz, q, bc):
+    p = W.random_problem3d(600 + nx + 3 * ny + 7 * nz, nx, ny, nz, q=q, bc=bc,
+                           stretched=any(v == M for v in bc), bdeg=2, ddeg=2)
+    say(f"case 3d f64 {nx}x{ny}x{nz} q={q} bc={bc}")
+    s = solver(p, "f64", (1, 3))
+    s.set_phi(p.phi0)
+    s.step(3)
+    o = Oracle3D(p)
+    o.step(3)
+    f, fo = s.get_f(), o.get_f()
+    assert np.abs(f - fo).max() <= 1e-12 * np.abs(fo).max()
+    r = s.reduce()
+    assert abs(r["mass"] - o.mass()) <= 1e-12 * abs(o.mass())
+
+
+@pytest.mark.parametrize("launch", [(1, 1), (1, 2), (1, 32), (2, 1), (2, 5), (2, 32)])
+def test_launch_shapes_give_identical_results(launch):
+    """Tiles of 1 or 2 rows and chunks of 1..32 planes: bitwise the same (binary32)."""
+    p = W.random_problem3d(77, 70, 7, 9, q=19, bc=(P, M, P), stretched=True, bdeg=2)
+    ref = solver(p, "f32", (2, 32))
+    ref.set_phi(p.phi0)
+    ref.step(4)
+    s = solver(p, "f32", launch)
+    s.set_phi(p.phi0)
+    s.step(4)
+    assert np.array_equal(s.get_f(), ref.get_f())
+
+
+@pytest.mark.parametrize("q", [19, 15, 7])
+def test_fp32_against_oracle(q):
+    p = W.random_problem3d(88 + q, 40, 12, 10, q=q, bc=(P, P, M), bdeg=2)
+    steps = 40
+    s = solver(p, "f32")
+    s.set_phi(p.phi0)
+    s.step(steps)
+    o = Oracle3D(p, openmp=True)
+    o.step(steps)
+    ref = o.get_phi()
+    err = float(np.sqrt(((s.get_phi() - ref) ** 2).sum() / (ref ** 2).sum()))
+    say(f"  3d f32 q={q}: rel-L2 {err:.2e} (bound {2 * steps * EPS32:.2e})")
+    assert err <= 2 * steps * EPS32
+
+
+def test_gaussian_hill_3d_on_gpu():
+    """Anisotropic 3-D Gaussian hill, 48^3, binary64: GRE equal to the oracle's."""
+    K = [[1.0e-3, 2e-4, 1e-4], [2e-4, 1.5e-3, -1e-4], [1e-4, -1e-4, 0.8e-3]]
+    p = W.gaussian_hill3d_problem(48, q=19, K=K, D=1e-3, c=5.0, sigma0=0.2)
+    s = solver(p, "f64")
+    s.set_phi(p.phi0)
+    o = Oracle3D(p, openmp=True)
+    nst = int(round(0.2 / o.dt))
+    s.step(nst)
+    o.step(nst)
+    X, Y, Z = p.mesh()
+    exact = p.exact(X, Y, Z, o.time)
+    gre = s.reduce(exact)["gre"]
+    gre_o = o.errors(exact)[0]
+    say(f"  3-D Gaussian hill 48^3: GRE gpu {gre:.4e} oracle {gre_o:.4e}")
+    assert abs(gre - gre_o) <= 1e-9 * gre_o
+
+
+def test_uniform_state_and_mass_3d():
+    p = W.random_problem3d(3, 66, 5, 6, q=19, bc=(M, P, M), stretched=True)
+    p.b = ((0.0,), (0.0,), (0.0,))
+    p.d = p.d[:3] + ((0.0,), (0.0,), (0.0,))
+    s = solver(p, "f64")
+    s.set_phi(np.full_like(p.phi0, 0.7))
+    f0 = s.get_f()
+    s.step(5)
+    assert np.abs(s.get_f() - f0).max() <= 1e-14
+    s.set_phi(p.phi0)
+    m0 = s.reduce()["mass"]
+    s.step(50)
+    assert abs(s.reduce()["mass"] - m0) <= 1e-12 * abs(m0)
