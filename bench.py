@@ -40,8 +40,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="batch256",
                     choices=["batch256", "gaussian_hill_4096", "burgers_512",
-                             "nonlinear_diffusion_1024", "gaussian_hill_128", "source_wave_4096"])
+                             "nonlinear_diffusion_1024", "gaussian_hill_128", "source_wave_4096",
+                             "gaussian_hill3d_256"])
     ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16neq", "bf16neq"])
+    ap.add_argument("--launch3", default=None,
+                    help="three-dimensional launch rows_per_block,planes_per_block")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--retune", action="store_true", help="autotune now instead of tuning.json")
     ap.add_argument("--launch", default=None,
@@ -109,20 +112,114 @@ def cpu_baseline(seconds):
                       f"D = phi I), {steps} steps in {el:.1f} s, binary64, 1 thread"}
 
 
-def kernel_source_hash():
+def cpu_baseline3d(seconds):
+    """The 3-D oracle as it stands, single thread, on a 64^3 instance of the
+    Gaussian-hill recipe."""
+    from oracle import Oracle3D
+    from paper_1906_11036_amd import workloads as W
+    p = W.gaussian_hill3d_problem(64, q=19, u=(0.05, 0.02, 0.01), D=1e-4, sigma0=0.15, images0=0)
+    o = Oracle3D(p)
+    o.step(1)
+    steps, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        o.step(1)
+        steps += 1
+    el = time.perf_counter() - t0
+    return {"value": p.cells * steps / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"one 64^3 periodic D3Q19 Gaussian-hill instance, {steps} steps in {el:.1f} s, "
+                      f"binary64, 1 thread"}
+
+
+BYTES_PER_UPDATE3 = {0: 2 * 19 * 8, 1: 2 * 19 * 4}   # D3Q19: read + write of the stored state
+
+
+def main3d(args):
+    """Three-dimensional workload: one D3Q19 instance stepped by the 3-D kernel."""
+    import numpy as np
+    import torch
+
+    import paper_1906_11036_amd as dg
+    from paper_1906_11036_amd import _lib as L
+    from paper_1906_11036_amd import workloads as W
+    storage = L.STORAGE[args.storage]
+    if storage not in BYTES_PER_UPDATE3:
+        print("the three-dimensional path stores binary64 or binary32 only", file=sys.stderr)
+        sys.exit(2)
+    t_gen = time.perf_counter()
+    p = W.workload3d(args.workload)
+    log(f"workload {args.workload}: {p.cells} cells, generated in {time.perf_counter() - t_gen:.1f} s")
+    launch = tuple(int(v) for v in args.launch3.split(",")) if args.launch3 else None
+
+    def run(st, launch=None):
+        s = dg.Solver3D(p, storage=st, launch=launch)
+        s.set_phi(p.phi0)
+        s.step(args.warmup)
+        torch.cuda.synchronize()
+        ms = s.time_steps(args.steps)   # hipEvents around the launches on the bound stream
+        torch.cuda.synchronize()
+        return s, ms
+
+    s, ms = run(args.storage, launch)
+    info = s.info()
+    ms_step = ms / args.steps
+    mlups = p.cells * args.steps / (ms * 1e-3) / 1e6
+    alg_bytes = BYTES_PER_UPDATE3[storage] * p.cells
+    achieved = alg_bytes / (ms_step * 1e-3) / 1e9
+    log(f"{args.storage}: {ms_step:.4f} ms/step, {mlups:.0f} MLUPS, {achieved:.0f} GB/s algorithmic "
+        f"(rows/block={info['rows_per_block']} planes/block={info['planes_per_block']})")
+    extras = {}
+    if not args.no_extras:
+        phi32 = s.get_phi()
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+        s64, ms64 = run("f64")
+        fused64 = p.cells * args.steps / (ms64 * 1e-3) / 1e6
+        phi64 = s64.get_phi()
+        s64.close()
+        l2 = float(np.sqrt(((phi32 - phi64) ** 2).sum() / (phi64 ** 2).sum()))
+        log(f"f64 fused: {fused64:.0f} MLUPS; rel-L2(f32 vs f64) after {args.warmup + args.steps} steps {l2:.2e}")
+        extras = {"fp64_fused_mlups": round(fused64, 1), "rel_l2_vs_fp64": l2,
+                  "rel_l2_after_steps": args.warmup + args.steps}
+    launch_s = f"{info['rows_per_block']},{info['planes_per_block']}"
+    traffic_b = measured_traffic(args.workload, args.storage, launch_s, kernel="k_step3",
+                                 sources=("dugks3d_kernels.hip", "dugks3d_internal.h"))
+    out = {
+        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.storage, "data": "synthetic",
+        "config": {"workload": args.workload, "instances": 1, "cells": p.cells, "lattice": "D3Q19",
+                   "storage": args.storage, "state_bytes": info["state_bytes"],
+                   "rows_per_block": info["rows_per_block"], "planes_per_block": info["planes_per_block"]},
+        "hbm_gbps_algorithmic": round(achieved, 1),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": (round(traffic_b / (ms_step * 1e-3) / 1e9, 1)
+                                 if traffic_b is not None else None)},
+        "traffic_bytes_per_launch": traffic_b,
+    }
+    out.update(extras)
+    if not args.no_extras:
+        out["cpu_baseline"] = cpu_baseline3d(args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def kernel_source_hash(sources=("dugks_kernels.hip", "dugks_internal.h")):
     import hashlib
     h = hashlib.sha256()
-    for name in ("dugks_kernels.hip", "dugks_internal.h"):
+    for name in sources:
         with open(os.path.join(ROOT, "paper_1906_11036_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, storage, info):
+def measured_traffic(workload, storage, launch, kernel="k_step",
+                     sources=("dugks_kernels.hip", "dugks_internal.h")):
     """HBM bytes per launch of the step kernel from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter on a copy of known
     size), or None when the summary does not match this kernel source and launch."""
-    path = os.path.join(ROOT, "profiles", f"k_step_{storage}_{workload}_traffic.md")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{storage}_{workload}_traffic.md")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -131,8 +228,7 @@ def measured_traffic(workload, storage, info):
             if line.startswith("- ") and ": " in line:
                 k, v = line[2:].split(": ", 1)
                 fields[k.strip()] = v.strip().strip("`")
-    launch = f"{info['rows_per_wave']},{info['waves_per_block']},{info['schedule']},{info['xcd_remap']}"
-    if fields.get("kernel_source_sha256") != kernel_source_hash() or fields.get("launch") != launch:
+    if fields.get("kernel_source_sha256") != kernel_source_hash(sources) or fields.get("launch") != launch:
         return None
     return float(fields["hbm_bytes_per_launch"])
 
@@ -143,6 +239,8 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "sharding of this path is a design note, not a built feature", file=sys.stderr)
         sys.exit(2)
+    if args.workload.startswith("gaussian_hill3d"):
+        return main3d(args)
     import numpy as np
     import torch
 
@@ -201,7 +299,8 @@ def main():
                   "speedup_vs_plain_fp64": round(mlups / plain64, 2) if plain64 else None,
                   "rel_l2_vs_fp64": l2, "rel_l2_after_steps": nsteps_total}
 
-    traffic_b = measured_traffic(args.workload, args.storage, info)
+    launch_s = f"{info['rows_per_wave']},{info['waves_per_block']},{info['schedule']},{info['xcd_remap']}"
+    traffic_b = measured_traffic(args.workload, args.storage, launch_s)
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),

@@ -47,7 +47,7 @@ typedef struct dugks3_info {
   double a1, b1, a2, b2, a3, b3;
   int nx, ny, nz, q, storage, pitch;
   int eq_degree;          /* degree of E_i(phi) as a polynomial in phi */
-  int rows_per_block;     /* launch: interior rows of a block (plus two halo rows) */
+  int rows_per_block;     /* launch: rows of a block (see dugks3_set_launch) */
   int planes_per_block;   /* launch: planes swept by a block */
   long long blocks;       /* blocks per step */
   size_t state_bytes;     /* bytes of one f~ buffer */
@@ -102,11 +102,13 @@ int dugks3_get_f(dugks3_ctx* ctx, double* out, int on_device);
 int dugks3_reduce(dugks3_ctx* ctx, const double* ref_dev, double* mass, double* gre,
                   double* rel_l2);
 
-/* Launch configuration: interior rows per block (1 or 2; the block adds two
- * halo rows and has rows+2 waves) and planes swept per block (>= 1).  A block
- * stages g of 3 planes x (rows+2) rows in LDS (q x 64 values each); a launch
- * needing more LDS than the device allows per block is refused.  Defaults:
- * 2 rows (binary32), 1 row (binary64), 32 planes.  Errors: E_ARG. */
+/* Launch configuration: rows per block and planes swept per block (>= 1).
+ * binary32: 2 to 4 rows, one wave each (raw f~ and g of the rows and the two
+ * halo rows staged in LDS, 5 x (rows + 2) x q x 64 x 4 bytes); binary64: 1 or
+ * 2 interior rows plus one wave per halo row (g in LDS, 3 x (rows + 2) x q x
+ * 64 x 8 bytes).  A launch needing more LDS than the device allows per block
+ * is refused.  Defaults: 4 rows (binary32), 2 rows (binary64), 32 planes.
+ * Errors: E_ARG. */
 int dugks3_set_launch(dugks3_ctx* ctx, int rows_per_block, int planes_per_block);
 
 /* Time nsteps steps with hipEvents on the bound stream (the state advances). */

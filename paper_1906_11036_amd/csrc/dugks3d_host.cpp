@@ -200,7 +200,7 @@ struct dugks3_ctx {
   const Inst3* dev() const { return (const Inst3*)(ws + off_table); }
 
   // LDS bytes of a block for the launch and the device limit per block
-  size_t lds_bytes(const Launch3& l) const { return (size_t)3 * (l.rows + 2) * q * kLanes * elem(); }
+  size_t lds_bytes(const Launch3& l) const { return step3_lds_bytes(p.storage, q, l); }
   size_t lds_limit() const {
     int dev = 0, v = 65536;
     if (hipGetDevice(&dev) == hipSuccess)
@@ -306,9 +306,9 @@ int dugks3_create(dugks3_ctx** out, int nx, int ny, int nz, const double* xf, co
   x->stage_bytes = sizeof(double) * (size_t)q * x->cells();
   x->off_stage = off; off += align256(x->stage_bytes);
   x->total = off;
-  // default launch: binary32 two rows (LDS 3 x 4 x q x 64 x 4 bytes, 58 KiB for D3Q19),
-  // binary64 one row (3 x 3 x q x 64 x 8 bytes)
-  x->launch.rows = p->storage == DUGKS_F64 ? 1 : 2;
+  // default launch: binary32 four rows (LDS 5 x 6 x q x 64 x 4 bytes, 143 KiB for
+  // D3Q19), binary64 two interior rows (3 x 4 x q x 64 x 8 bytes, 114 KiB)
+  x->launch.rows = p->storage == DUGKS_F64 ? 2 : 4;
   x->launch.planes = 32;
   return DUGKS_OK;
 }
@@ -435,7 +435,10 @@ int dugks3_reduce(dugks3_ctx* ctx, const double* ref_dev, double* mass, double* 
 
 int dugks3_set_launch(dugks3_ctx* ctx, int rows, int planes) {
   GUARD3(ctx);
-  if (rows < 1 || rows > kMaxRowsPerBlock) return ctx->fail(DUGKS_E_ARG, "rows_per_block must be 1 or 2");
+  if (ctx->p.storage == DUGKS_F64 ? (rows < kMinRows64 || rows > kMaxRows64)
+                                   : (rows < kMinRows32 || rows > kMaxRows32))
+    return ctx->fail(DUGKS_E_ARG, ctx->p.storage == DUGKS_F64 ? "rows_per_block must be 1 or 2 (binary64)"
+                                                            : "rows_per_block must be 2, 3 or 4 (binary32)");
   if (planes < 1) return ctx->fail(DUGKS_E_ARG, "planes_per_block must be >= 1");
   Launch3 l;
   l.rows = rows;

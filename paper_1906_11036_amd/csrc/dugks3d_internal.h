@@ -19,7 +19,10 @@ constexpr int kMaxCoef = 8;     // E_i(phi) has degree <= 7
 constexpr int kLanes = 64;      // one wave covers 64 columns ...
 constexpr int kCols = 62;       // ... of which 62 are updated; lanes 0 and 63 are halo
 constexpr int kGeo = 5;         // per face: 3 reconstruction factors, tangential factor, update factor
-constexpr int kMaxRowsPerBlock = 2;   // interior rows of a block (plus two halo rows)
+// rows of a block: binary32 2..4 (one wave per row, the halo rows staged by
+// all waves); binary64 1..2 interior rows plus one wave per halo row
+constexpr int kMinRows32 = 2, kMaxRows32 = 4;
+constexpr int kMinRows64 = 1, kMaxRows64 = 2;
 
 // Per-instance constants and pointers (kernels read them with scalar loads).
 // Scaled distributions as in the two-dimensional kernels:
@@ -46,13 +49,15 @@ struct alignas(64) Inst3 {
 };
 
 struct Launch3 {
-  int rows = 2;     // interior rows per block (1..kMaxRowsPerBlock)
+  int rows = 4;     // rows per block (see kMinRows32 .. kMaxRows64)
   int planes = 32;  // planes swept per block
 };
 
 // Blocks of one step for the launch (x strips x row tiles x plane chunks).
 long long step3_blocks(const Inst3& h, const Launch3& l);
 int launch_step3(const Inst3* d, const Inst3& h, int parity, const Launch3& l, void* stream);
+// LDS bytes of one block of the step kernel
+size_t step3_lds_bytes(int storage, int q, const Launch3& l);
 int launch_init3(const Inst3* d, const Inst3& h, const double* phi, int parity, void* stream);
 int launch_set_f3(const Inst3* d, const Inst3& h, const double* f, int parity, void* stream);
 int launch_get_phi3(const Inst3* d, const Inst3& h, double* out, int parity, void* stream);

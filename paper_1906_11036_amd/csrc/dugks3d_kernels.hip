@@ -2,20 +2,22 @@
 // (eq. 2.28), D3Q19 (eq. 2.6) and D3Q7 (Remark 3).
 //
 // Fused step: a block owns a strip of 62 columns (64 lanes: one halo column
-// each side), a tile of `rows` rows plus one halo row each side (one wave per
-// row) and a chunk of planes, which it sweeps in z.  Each wave keeps g of its
-// row at planes z-1, z, z+1 in registers and publishes them to LDS (three
-// plane slots); after a barrier every interior wave reads its neighbour rows
-// from LDS and computes, for its cells, the west face (x), both y faces, the
-// top face (z; the bottom one is the previous plane's top face) and the
-// update, then a second barrier protects the slot the next plane overwrites.
-// x neighbours come from whole-wave DPP shifts, as in the 2-D kernels.
+// each side), a tile of rows (one wave per row) and a chunk of planes, which
+// it sweeps in z, with g of three planes of its rows and the two halo rows in
+// LDS.  Per plane and cell it computes the west face (x; the east face is the
+// next lane's west face), both y faces and the top face (z; the bottom face is
+// the previous plane's top face) and the update.  x neighbours come from
+// whole-wave DPP shifts, as in the 2-D kernels.  Two variants: binary32 stages
+// raw f~ through LDS with direct buffer-to-LDS loads (every wave owns an
+// interior row); binary64 holds its window in registers and spends one wave
+// on each halo row.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include <type_traits>
 
 #include "dugks3d_internal.h"
+
 
 namespace dugks3 {
 
@@ -132,15 +134,26 @@ __device__ __forceinline__ int src_index(int i, int n, int bc) {
 }
 
 // ------------------------------------------------------------ cell and face
+// E_i(phi) (eq. 2.3) evaluated from the instance's scalar table ...
+template <int NC, typename T> struct EqScalar {
+  const Inst3* __restrict__ I;
+  __device__ __forceinline__ T operator()(int k, T x) const { return horner<NC>(C3<T>::e(I, k), x); }
+};
+// ... or from coefficients held in vector registers
+template <int Q, int NC> struct EqVec {
+  float c[Q][NC];
+  __device__ __forceinline__ float operator()(int k, float x) const { return horner<NC>(c[k], x); }
+};
+
 // g = fbar+ / b1 = (a1/b1) f~ + E(phi) (eq. 2.21 over b1); phi in binary64.
-template <int Q, int NC, typename T>
-__device__ __forceinline__ void cell_g3(const Inst3* __restrict__ I, const T* f, T* g) {
+template <int Q, typename T, typename EQ>
+__device__ __forceinline__ void cell_g3(const Inst3* __restrict__ I, const EQ& E, const T* f, T* g) {
   double phi = 0.0;
 #pragma unroll
   for (int k = 0; k < Q; ++k) phi += (double)f[k];
   const T p = (T)phi, ra = C3<T>::ra(I);
 #pragma unroll
-  for (int k = 0; k < Q; ++k) g[k] = fma(ra, f[k], horner<NC>(C3<T>::e(I, k), p));
+  for (int k = 0; k < Q; ++k) g[k] = fma(ra, f[k], E(k, p));
 }
 
 template <int Q, typename T> __device__ __forceinline__ void mirror(T* g, int a) {
@@ -178,8 +191,8 @@ template <int A> constexpr int tan2() { return A == 2 ? 1 : 2; }
 // F = f_b / b3 (eq. 2.22) for the directions with a normal component.
 // t1, t2: sums of the two cells' central-difference numerators along the
 // tangential axes tan1<A>, tan2<A>; tau1, tau2 their factors h c / (2 dist).
-template <int Q, int NC, int A, typename T>
-__device__ __forceinline__ void face3(const Inst3* __restrict__ I, const T* L, const T* R,
+template <int Q, int A, typename T, typename EQ>
+__device__ __forceinline__ void face3(const Inst3* __restrict__ I, const EQ& E, const T* L, const T* R,
                                       const T* t1, T tau1, const T* t2, T tau2, T am, T a0, T ap,
                                       T* out) {
   T gb[Q];
@@ -196,19 +209,24 @@ __device__ __forceinline__ void face3(const Inst3* __restrict__ I, const T* L, c
   const T rb = C3<T>::rb(I);
 #pragma unroll
   for (int k = 0; k < Q; ++k)
-    if (ce<Q>(k, A) != 0) out[k] = fma(rb, gb[k], horner<NC>(C3<T>::e(I, k), pb));
+    if (ce<Q>(k, A) != 0) out[k] = fma(rb, gb[k], E(k, pb));
 }
 
 extern __shared__ __align__(16) unsigned char dugks3_lds[];
 
-// ------------------------------------------------------------ fused step
-// Threads per block: at most 2 interior rows (4 waves), so that a wave may
-// hold the whole register file of its SIMD (the window of g over three planes
-// plus the faces of up to 19 directions).
-template <int ST> constexpr int max_threads3() { return 256; }
-
+// ------------------------------------------- fused step, binary64 storage
+// A block owns a strip of 62 columns (64 lanes: one halo column each side), a
+// tile of `rows` rows plus one halo row each side (one wave per row) and a
+// chunk of planes, which it sweeps in z.  Each wave keeps g of its row at
+// planes z-1, z, z+1 in registers and publishes them to LDS (three plane
+// slots); after a barrier every interior wave reads its neighbour rows from
+// LDS and computes, for its cells, the west face (x), both y faces, the top
+// face (z; the bottom one is the previous plane's top face) and the update,
+// then a second barrier protects the slot the next plane overwrites.  At most
+// 2 interior rows (4 waves): a wave may hold the whole register file of its
+// SIMD.
 template <int Q, int ST, int NC>
-__global__ __launch_bounds__(max_threads3<ST>()) void k_step3(const Inst3* __restrict__ I, int parity, int rows,
+__global__ __launch_bounds__(256) void k_step3h(const Inst3* __restrict__ I, int parity, int rows,
                                                int planes, int strips, int tiles) {
   using T = typename S3<ST>::T;
   T* lds = (T*)dugks3_lds;
@@ -254,7 +272,7 @@ __global__ __launch_bounds__(max_threads3<ST>()) void k_step3(const Inst3* __res
     return (unsigned)((src_index(zp, nz, bcz) * ny + srow) * pitch + scol);
   };
   auto make_g = [&](const T* f, int zp, T* g) {
-    cell_g3<Q, NC, T>(I, f, g);
+    cell_g3<Q, T>(I, EqScalar<NC, T>{I}, f, g);
     if (wall_x) mirror<Q, T>(g, 0);
     if (wall_y) mirror<Q, T>(g, 1);
     if ((zp < 0 || zp >= nz) && bcz != DUGKS_BC_PERIODIC) mirror<Q, T>(g, 2);
@@ -289,7 +307,7 @@ __global__ __launch_bounds__(max_threads3<ST>()) void k_step3(const Inst3* __res
         t2[k] = (*lds_at(2, w + 1, k) - *lds_at(2, w - 1, k)) + (*lds_at(0, w + 1, k) - *lds_at(0, w - 1, k));
     }
     const int zi = z0 + 1;   // table index of the face between z0-1 and z0
-    face3<Q, NC, 2, T>(I, G[2], G[0], t1, ctau, t2, ytau, zg[zi * kGeo + 0], zg[zi * kGeo + 1],
+    face3<Q, 2, T>(I, EqScalar<NC, T>{I}, G[2], G[0], t1, ctau, t2, ytau, zg[zi * kGeo + 0], zg[zi * kGeo + 1],
                        zg[zi * kGeo + 2], FZ[2]);
   }
 
@@ -325,7 +343,7 @@ __global__ __launch_bounds__(max_threads3<ST>()) void k_step3(const Inst3* __res
           if (ce<Q>(k, 1) != 0) t1[k] = shr1(dY[k]) + dY[k];
           if (ce<Q>(k, 2) != 0) t2[k] = shr1(dZ[k]) + dZ[k];
         }
-        face3<Q, NC, 0, T>(I, lw, G[s0], t1, ytau, t2, ztau, cam, ca0, cap, fW);
+        face3<Q, 0, T>(I, EqScalar<NC, T>{I}, lw, G[s0], t1, ytau, t2, ztau, cam, ca0, cap, fW);
 #pragma unroll
         for (int k = 0; k < Q; ++k)
           if (ce<Q>(k, 0) != 0) o[k] = fma((T)(-ce<Q>(k, 0)) * ck, shl1(fW[k]) - fW[k], o[k]);
@@ -338,7 +356,7 @@ __global__ __launch_bounds__(max_threads3<ST>()) void k_step3(const Inst3* __res
           if (ce<Q>(k, 0) != 0) t1[k] = sx0[k] + (shl1(gU[k]) - shr1(gU[k]));
           if (ce<Q>(k, 2) != 0) t2[k] = dZ[k] + (*lds_at(sp, w + 1, k) - *lds_at(sm, w + 1, k));
         }
-        face3<Q, NC, 1, T>(I, G[s0], gU, t1, ctau, t2, ztau, yN0, yN1, yN2, fN);
+        face3<Q, 1, T>(I, EqScalar<NC, T>{I}, G[s0], gU, t1, ctau, t2, ztau, yN0, yN1, yN2, fN);
 #pragma unroll
         for (int k = 0; k < Q; ++k)
           if (ce<Q>(k, 1) != 0) o[k] = fma((T)(-ce<Q>(k, 1)) * ky, fN[k], o[k]);
@@ -351,7 +369,7 @@ __global__ __launch_bounds__(max_threads3<ST>()) void k_step3(const Inst3* __res
           if (ce<Q>(k, 0) != 0) t1[k] = sx0[k] + (shl1(gD[k]) - shr1(gD[k]));
           if (ce<Q>(k, 2) != 0) t2[k] = dZ[k] + (*lds_at(sp, w - 1, k) - *lds_at(sm, w - 1, k));
         }
-        face3<Q, NC, 1, T>(I, gD, G[s0], t1, ctau, t2, ztau, yS0, yS1, yS2, fS);
+        face3<Q, 1, T>(I, EqScalar<NC, T>{I}, gD, G[s0], t1, ctau, t2, ztau, yS0, yS1, yS2, fS);
 #pragma unroll
         for (int k = 0; k < Q; ++k)
           if (ce<Q>(k, 1) != 0) o[k] = fma((T)ce<Q>(k, 1) * ky, fS[k], o[k]);
@@ -363,7 +381,7 @@ __global__ __launch_bounds__(max_threads3<ST>()) void k_step3(const Inst3* __res
           if (ce<Q>(k, 1) != 0) t2[k] = dY[k] + (*lds_at(sp, w + 1, k) - *lds_at(sp, w - 1, k));
         }
         const int zt = z + 2;   // table index of the face between z and z+1
-        face3<Q, NC, 2, T>(I, G[s0], G[sp], t1, ctau, t2, ytau, zg[zt * kGeo + 0], zg[zt * kGeo + 1],
+        face3<Q, 2, T>(I, EqScalar<NC, T>{I}, G[s0], G[sp], t1, ctau, t2, ytau, zg[zt * kGeo + 0], zg[zt * kGeo + 1],
                            zg[zt * kGeo + 2], FZ[s0]);
 #pragma unroll
         for (int k = 0; k < Q; ++k)
@@ -397,6 +415,276 @@ __global__ __launch_bounds__(max_threads3<ST>()) void k_step3(const Inst3* __res
   if (z < z1) body(z, S0{});
   if (z + 1 < z1) body(z + 1, S1{});
   (void)bad;
+}
+
+// ------------------------------------------- fused step, binary32 storage
+// A block of `ROWS` waves owns ROWS rows of a 62-column strip (one row per
+// wave) and sweeps a chunk of planes in z.  Raw f~ of planes z+1 and z+2 is
+// staged in LDS by direct buffer-to-LDS loads (no registers held while in
+// flight): each wave loads its own row, and the two halo rows are split
+// between all waves.  g of planes z-1, z, z+1 sits in three LDS slots; each
+// wave keeps g of its row at z and z+1 and f~+ (eq. 2.23) of z in registers.
+// Per plane: stage z+2, make g of z+1 (waves 0 and 1 also the halo rows),
+// barrier, faces and update of plane z, barrier.
+
+#define LDS_PTR(p) ((__attribute__((address_space(3))) void*)(p))
+
+// Barrier for LDS traffic only: this wave's LDS reads and writes are complete,
+// then the workgroup barrier.  Outstanding global loads stay in flight.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0), vmcnt and expcnt unconstrained
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+__device__ __forceinline__ void wait_vm_all() {
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+  asm volatile("" ::: "memory");
+}
+
+template <int Q, int NC, int ROWS>
+__global__ __launch_bounds__(64 * ROWS) void k_step3s(const Inst3* __restrict__ I, int parity, int planes,
+                                                       int strips, int tiles) {
+  constexpr int W = ROWS + 2;                 // LDS rows: y0-1 .. y0+ROWS
+  constexpr int HX = (2 * Q + ROWS - 1) / ROWS;   // halo-row loads per wave
+  __shared__ float gsl[3][W][Q][kLanes];      // g of plane p in slot (p - z0) mod 3
+  __shared__ float raw0[W][Q][kLanes];        // raw f~ of planes with (p - z0) even
+  __shared__ float raw1[W][Q][kLanes];        // ... and odd
+  __shared__ float ecoef[Q * NC];             // E_i coefficients, read into vector registers
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  int b = blockIdx.x;
+  const int sx = b % strips;
+  b /= strips;
+  const int tj = b % tiles, tk = b / tiles;
+  const int nx = I->n[0], ny = I->n[1], nz = I->n[2];
+  const int bcx = I->bc[0], bcy = I->bc[1], bcz = I->bc[2];
+  const int pitch = I->pitch;
+  const unsigned plane = (unsigned)I->plane;
+  const int x0 = sx * kCols, y0 = tj * ROWS, z0 = tk * planes;
+  const int y1 = min(y0 + ROWS, ny), z1 = min(z0 + planes, nz);
+  // this wave's row (LDS row w + 1); in a short last tile the waves past it
+  // take the upper halo row y1
+  const int rr = y0 + w;
+  const int r = rr < y1 ? rr : y1;
+  const bool inner = rr < y1;
+  const int me = w + 1;
+  const int c = x0 - 1 + lane;
+  const int scol = src_index(c < nx + 1 ? c : nx, nx, bcx);
+  const bool wall_x = (c < 0 || c >= nx) && bcx != DUGKS_BC_PERIODIC;
+  const bool live = inner && lane >= 1 && lane <= kCols && c < nx;
+  const int srow = src_index(r, ny, bcy);
+  const bool wall_y = (r < 0 || r >= ny) && bcy != DUGKS_BC_PERIODIC;
+  // halo rows: y0-1 in LDS row 0 and y1 in LDS row W-1 (unused when the tile is short)
+  const int slo = src_index(y0 - 1, ny, bcy), shi = src_index(y1, ny, bcy);
+  const bool wall_lo = y0 - 1 < 0 && bcy != DUGKS_BC_PERIODIC;
+  const bool wall_hi = y1 >= ny && bcy != DUGKS_BC_PERIODIC;
+
+  const __amdgpu_buffer_rsrc_t Rin = rsrc(I->buf[parity], I->buf_bytes);
+  const __amdgpu_buffer_rsrc_t Rout = rsrc(I->buf[parity ^ 1], I->buf_bytes);
+
+  const float* cg = I->geof[0] + (long long)(c + 1 < nx + 1 ? c + 1 : nx + 1) * kGeo;
+  const float cam = cg[0], ca0 = cg[1], cap = cg[2], ctau = cg[3], ck = cg[4];
+  const CPtr<float> yg = as_constant(I->geof[1]);
+  const CPtr<float> zg = as_constant(I->geof[2]);
+  const int ryi = (r + 1 < ny + 1 ? r + 1 : ny + 1);
+  const float ytau = yg[ryi * kGeo + 3], ky = yg[ryi * kGeo + 4];
+  const float yS0 = yg[ryi * kGeo + 0], yS1 = yg[ryi * kGeo + 1], yS2 = yg[ryi * kGeo + 2];
+  const int ryn = (ryi + 1 < ny + 2 ? ryi + 1 : ny + 1);
+  const float yN0 = yg[ryn * kGeo + 0], yN1 = yg[ryn * kGeo + 1], yN2 = yg[ryn * kGeo + 2];
+  const float kgv = I->kgf;
+  const unsigned plane4 = plane * 4u;
+  // E_i coefficients in vector registers for up to 4 per direction (filled
+  // from ecoef after the first barrier), else read from the scalar table
+  using EV = std::conditional_t<(NC <= 4), EqVec<Q, NC>, EqScalar<NC, float>>;
+  EV ev;
+  if constexpr (NC > 4) ev.I = I;
+  if (w == 0)
+    for (int i = lane; i < Q * NC; i += kLanes) ecoef[i] = I->ef[i / NC][i % NC];
+
+  auto cell_index = [&](int sr, int zp) __attribute__((always_inline)) -> unsigned {
+    return (unsigned)((src_index(zp, nz, bcz) * ny + sr) * pitch + scol);
+  };
+  // stage plane zp: this wave's row, and its share of the two halo rows
+  // (per-direction offsets advance in a vector register: no scalar register per direction)
+  auto stage = [&](float (*raw)[Q][kLanes], int zp) __attribute__((always_inline)) {
+    unsigned o = cell_index(srow, zp) * 4u;
+    const int wme = me;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(Rin, LDS_PTR(&raw[wme][k][0]), 4, o, 0, 0, 0);
+      o += plane4;
+    }
+    const unsigned ilo = cell_index(slo, zp) * 4u, ihi = cell_index(shi, zp) * 4u;
+    const int j0 = w * HX;
+#pragma unroll
+    for (int t = 0; t < HX; ++t) {
+      int j = j0 + t;
+      j = j < 2 * Q ? j : j - 2 * Q;   // the few surplus loads repeat earlier ones
+      const bool hi = j >= Q;
+      const int k = hi ? j - Q : j;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(Rin, LDS_PTR(&raw[hi ? W - 1 : 0][k][0]), 4,
+                                               (hi ? ihi : ilo) + (unsigned)k * plane4, 0, 0, 0);
+    }
+  };
+  auto make_g = [&](const float (*raw)[Q][kLanes], int row, bool wy, int zp, float* g, float* f) __attribute__((always_inline)) {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) f[k] = raw[row][k][lane];
+    cell_g3<Q, float>(I, ev, f, g);
+    if (wall_x) mirror<Q, float>(g, 0);
+    if (wy) mirror<Q, float>(g, 1);
+    if ((zp < 0 || zp >= nz) && bcz != DUGKS_BC_PERIODIC) mirror<Q, float>(g, 2);
+  };
+  auto publish = [&](int slot, int row, const float* g) __attribute__((always_inline)) {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) gsl[slot][row][k][lane] = g[k];
+  };
+  // g of plane zp for this wave's row (G, and f~+ in FT) and, for waves 0 and
+  // 1, the halo rows; all published to slot `slot`
+  auto plane_g = [&](const float (*raw)[Q][kLanes], int zp, int slot, float* G, float* FT) __attribute__((always_inline)) {
+    float f[Q];
+    make_g(raw, me, wall_y, zp, G, f);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) FT[k] = fmaf(kgv, G[k], (-1.0f / 3.0f) * f[k]);
+    publish(slot, me, G);
+    if (w <= 1) {
+      float gx[Q];
+      const int row = w == 0 ? 0 : W - 1;
+      make_g(raw, row, w == 0 ? wall_lo : wall_hi, zp, gx, f);
+      publish(slot, row, gx);
+    }
+  };
+
+  float G0[Q], G1[Q], O[Q], FT1[Q], FZb[Q], FZt[Q];
+
+  // prologue: planes z0-1 (raw1, slot 2) and z0 (raw0, slot 0); then z0+1 into raw1
+  stage(raw1, z0 - 1);
+  stage(raw0, z0);
+  wait_vm_all();
+  lds_barrier();
+  if constexpr (NC <= 4) {
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+#pragma unroll
+      for (int m = 0; m < NC; ++m) ev.c[k][m] = ecoef[k * NC + m];
+  }
+  plane_g(raw1, z0 - 1, 2, G1, FT1);
+  plane_g(raw0, z0, 0, G0, O);
+  lds_barrier();
+  stage(raw1, z0 + 1);   // z1 >= z0 + 1
+  if (inner) {  // bottom face of plane z0
+    float t1[Q], t2[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      if (ce<Q>(k, 0) != 0)
+        t1[k] = (shl1(G1[k]) - shr1(G1[k])) + (shl1(G0[k]) - shr1(G0[k]));
+      if (ce<Q>(k, 1) != 0)
+        t2[k] = (gsl[2][me + 1][k][lane] - gsl[2][me - 1][k][lane]) + (gsl[0][me + 1][k][lane] - gsl[0][me - 1][k][lane]);
+    }
+    const int zi = z0 + 1;
+    face3<Q, 2, float>(I, ev, G1, G0, t1, ctau, t2, ytau, zg[zi * kGeo + 0], zg[zi * kGeo + 1],
+                           zg[zi * kGeo + 2], FZb);
+  }
+  wait_vm_all();
+  lds_barrier();
+
+  auto body = [&](int z, auto rsl) __attribute__((always_inline)) {
+    constexpr int RS = decltype(rsl)::value;   // raw slot of plane z+1
+    float (*rawN)[Q][kLanes] = RS ? raw1 : raw0;
+    float (*rawF)[Q][kLanes] = RS ? raw0 : raw1;
+    const int d = z - z0;
+    const int s0 = d % 3, sp = (d + 1) % 3, sm = (d + 2) % 3;
+    plane_g(rawN, z + 1, sp, G1, FT1);
+    if (z + 2 <= z1) stage(rawF, z + 2);
+    lds_barrier();
+    if (inner) {
+      const int zi = z + 1;
+      const float ztau = zg[zi * kGeo + 3], kz = zg[zi * kGeo + 4];
+      float sx0[Q], dY[Q], dZ[Q], t1[Q], t2[Q];
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        if (ce<Q>(k, 0) != 0) sx0[k] = shl1(G0[k]) - shr1(G0[k]);
+        if (ce<Q>(k, 1) != 0) dY[k] = gsl[s0][me + 1][k][lane] - gsl[s0][me - 1][k][lane];
+        if (ce<Q>(k, 2) != 0) dZ[k] = G1[k] - gsl[sm][me][k][lane];
+      }
+      {  // west face (x); the east face is lane + 1's west face
+        float lw[Q], fW[Q];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          lw[k] = shr1(G0[k]);
+          if (ce<Q>(k, 1) != 0) t1[k] = shr1(dY[k]) + dY[k];
+          if (ce<Q>(k, 2) != 0) t2[k] = shr1(dZ[k]) + dZ[k];
+        }
+        face3<Q, 0, float>(I, ev, lw, G0, t1, ytau, t2, ztau, cam, ca0, cap, fW);
+#pragma unroll
+        for (int k = 0; k < Q; ++k)
+          if (ce<Q>(k, 0) != 0) O[k] = fmaf((float)(-ce<Q>(k, 0)) * ck, shl1(fW[k]) - fW[k], O[k]);
+      }
+      {  // north face (rows r, r+1)
+        float gU[Q], fN[Q];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          gU[k] = gsl[s0][me + 1][k][lane];
+          if (ce<Q>(k, 0) != 0) t1[k] = sx0[k] + (shl1(gU[k]) - shr1(gU[k]));
+          if (ce<Q>(k, 2) != 0) t2[k] = dZ[k] + (gsl[sp][me + 1][k][lane] - gsl[sm][me + 1][k][lane]);
+        }
+        face3<Q, 1, float>(I, ev, G0, gU, t1, ctau, t2, ztau, yN0, yN1, yN2, fN);
+#pragma unroll
+        for (int k = 0; k < Q; ++k)
+          if (ce<Q>(k, 1) != 0) O[k] = fmaf((float)(-ce<Q>(k, 1)) * ky, fN[k], O[k]);
+      }
+      {  // south face (rows r-1, r)
+        float gD[Q], fS[Q];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          gD[k] = gsl[s0][me - 1][k][lane];
+          if (ce<Q>(k, 0) != 0) t1[k] = sx0[k] + (shl1(gD[k]) - shr1(gD[k]));
+          if (ce<Q>(k, 2) != 0) t2[k] = dZ[k] + (gsl[sp][me - 1][k][lane] - gsl[sm][me - 1][k][lane]);
+        }
+        face3<Q, 1, float>(I, ev, gD, G0, t1, ctau, t2, ztau, yS0, yS1, yS2, fS);
+#pragma unroll
+        for (int k = 0; k < Q; ++k)
+          if (ce<Q>(k, 1) != 0) O[k] = fmaf((float)ce<Q>(k, 1) * ky, fS[k], O[k]);
+      }
+      {  // top face (planes z, z+1); the bottom face is the previous plane's top face
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          if (ce<Q>(k, 0) != 0) t1[k] = sx0[k] + (shl1(G1[k]) - shr1(G1[k]));
+          if (ce<Q>(k, 1) != 0) t2[k] = dY[k] + (gsl[sp][me + 1][k][lane] - gsl[sp][me - 1][k][lane]);
+        }
+        const int zt = z + 2;
+        face3<Q, 2, float>(I, ev, G0, G1, t1, ctau, t2, ytau, zg[zt * kGeo + 0], zg[zt * kGeo + 1],
+                               zg[zt * kGeo + 2], FZt);
+#pragma unroll
+        for (int k = 0; k < Q; ++k)
+          if (ce<Q>(k, 2) != 0) O[k] = fmaf((float)(-ce<Q>(k, 2)) * kz, FZt[k] - FZb[k], O[k]);
+      }
+    }
+    wait_vm_all();   // the staged plane z+2 is in LDS (and older stores are done)
+    if (live) {
+      unsigned o = (unsigned)(((long long)z * ny + r) * pitch + c) * 4u;
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, O[k]), Rout, o, 0, 0);
+        o += plane4;
+      }
+    }
+    lds_barrier();   // the next plane overwrites slot sm and reads the staged rows
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      G0[k] = G1[k];
+      O[k] = FT1[k];
+      if (ce<Q>(k, 2) != 0) FZb[k] = FZt[k];
+    }
+  };
+  using R0 = std::integral_constant<int, 0>;
+  using R1 = std::integral_constant<int, 1>;
+  int z = z0;
+  for (; z + 2 <= z1; z += 2) {
+    body(z, R1{});       // (z - z0) even: plane z+1 is in raw1
+    body(z + 1, R0{});
+  }
+  if (z < z1) body(z, R1{});
 }
 
 // -------------------------------------------------- init, copies, read-outs
@@ -534,35 +822,55 @@ long long step3_blocks(const Inst3& h, const Launch3& l) {
   return strips * tiles * chunks;
 }
 
-template <int Q, int ST>
-static int step3_q_st(const Inst3* d, const Inst3& h, int parity, const Launch3& l, void* stream) {
-  using T = typename S3<ST>::T;
+template <int Q, int NC>
+static void step3s_rows(const Inst3* d, int parity, const Launch3& l, int strips, int tiles, dim3 grid,
+                        hipStream_t st) {
+  switch (l.rows) {
+    case 2: hipLaunchKernelGGL((k_step3s<Q, NC, 2>), grid, dim3(128), 0, st, d, parity, l.planes, strips, tiles); break;
+    case 3: hipLaunchKernelGGL((k_step3s<Q, NC, 3>), grid, dim3(192), 0, st, d, parity, l.planes, strips, tiles); break;
+    default: hipLaunchKernelGGL((k_step3s<Q, NC, 4>), grid, dim3(256), 0, st, d, parity, l.planes, strips, tiles); break;
+  }
+}
+
+template <int Q>
+static int step3_q(const Inst3* d, const Inst3& h, int parity, const Launch3& l, void* stream) {
   const int strips = (h.n[0] + kCols - 1) / kCols;
   const int tiles = (h.n[1] + l.rows - 1) / l.rows;
   const long long blocks = step3_blocks(h, l);
   if (blocks <= 0 || blocks > 0x7fffffffLL) return -1;
-  const size_t shmem = (size_t)3 * (l.rows + 2) * Q * kLanes * sizeof(T);
-  dim3 grid((unsigned)blocks), block(64 * (l.rows + 2));
-  switch (h.ncoef <= 2 ? 2 : (h.ncoef <= 4 ? 4 : 8)) {
-    case 2: hipLaunchKernelGGL((k_step3<Q, ST, 2>), grid, block, shmem, S(stream), d, parity, l.rows, l.planes, strips, tiles); break;
-    case 4: hipLaunchKernelGGL((k_step3<Q, ST, 4>), grid, block, shmem, S(stream), d, parity, l.rows, l.planes, strips, tiles); break;
-    default: hipLaunchKernelGGL((k_step3<Q, ST, 8>), grid, block, shmem, S(stream), d, parity, l.rows, l.planes, strips, tiles); break;
+  const dim3 grid((unsigned)blocks);
+  const int nc = h.ncoef <= 2 ? 2 : (h.ncoef <= 4 ? 4 : 8);
+  if (h.storage == DUGKS_F64) {
+    const size_t shmem = step3_lds_bytes(h.storage, Q, l);
+    const dim3 block(64 * (l.rows + 2));
+    switch (nc) {
+      case 2: hipLaunchKernelGGL((k_step3h<Q, DUGKS_F64, 2>), grid, block, shmem, S(stream), d, parity, l.rows, l.planes, strips, tiles); break;
+      case 4: hipLaunchKernelGGL((k_step3h<Q, DUGKS_F64, 4>), grid, block, shmem, S(stream), d, parity, l.rows, l.planes, strips, tiles); break;
+      default: hipLaunchKernelGGL((k_step3h<Q, DUGKS_F64, 8>), grid, block, shmem, S(stream), d, parity, l.rows, l.planes, strips, tiles); break;
+    }
+  } else {
+    switch (nc) {
+      case 2: step3s_rows<Q, 2>(d, parity, l, strips, tiles, grid, S(stream)); break;
+      case 4: step3s_rows<Q, 4>(d, parity, l, strips, tiles, grid, S(stream)); break;
+      default: step3s_rows<Q, 8>(d, parity, l, strips, tiles, grid, S(stream)); break;
+    }
   }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-template <int ST>
-static int step3_st(const Inst3* d, const Inst3& h, int parity, const Launch3& l, void* stream) {
+int launch_step3(const Inst3* d, const Inst3& h, int parity, const Launch3& l, void* stream) {
   switch (h.q) {
-    case 19: return step3_q_st<19, ST>(d, h, parity, l, stream);
-    case 15: return step3_q_st<15, ST>(d, h, parity, l, stream);
-    default: return step3_q_st<7, ST>(d, h, parity, l, stream);
+    case 19: return step3_q<19>(d, h, parity, l, stream);
+    case 15: return step3_q<15>(d, h, parity, l, stream);
+    default: return step3_q<7>(d, h, parity, l, stream);
   }
 }
 
-int launch_step3(const Inst3* d, const Inst3& h, int parity, const Launch3& l, void* stream) {
-  return h.storage == DUGKS_F64 ? step3_st<DUGKS_F64>(d, h, parity, l, stream)
-                                : step3_st<DUGKS_F32>(d, h, parity, l, stream);
+size_t step3_lds_bytes(int storage, int q, const Launch3& l) {
+  // binary64: g of 3 planes x (rows + 2) rows (dynamic); binary32: g of 3
+  // planes and raw f~ of 2 planes x (rows + 2) rows (static)
+  return storage == DUGKS_F64 ? (size_t)3 * (l.rows + 2) * q * kLanes * 8
+                              : (size_t)5 * (l.rows + 2) * q * kLanes * 4;
 }
 
 #define DUGKS3_PER_CELL(KERNEL, ...)                                                               \

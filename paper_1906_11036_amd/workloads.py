@@ -487,8 +487,11 @@ def gaussian_hill3d(x, y, z, t, u, K, sigma0, period=2.0, images=1):
 
 
 def gaussian_hill3d_problem(n=64, q=19, u=(0.1, 0.05, 0.02), D=1e-3, K=None, sigma0=0.15,
-                            c=1.0, cfl=0.5, steps=100, name="gaussian_hill3d") -> Problem3D:
-    """Linear CDE on [-1, 1]^3, periodic: B = u phi, D = (K / alpha) phi."""
+                            c=1.0, cfl=0.5, steps=100, name="gaussian_hill3d",
+                            images0=1) -> Problem3D:
+    """Linear CDE on [-1, 1]^3, periodic: B = u phi, D = (K / alpha) phi.
+    images0: periodic images summed for the initial field (0 is exact to
+    rounding while sigma0 <= 0.2: the nearest image is 2 / sigma0 widths away)."""
     K = np.asarray(K if K is not None else np.eye(3) * D, dtype=np.float64)
     alpha = D
     f = uniform_faces(n, -1.0, 1.0)
@@ -499,8 +502,40 @@ def gaussian_hill3d_problem(n=64, q=19, u=(0.1, 0.05, 0.02), D=1e-3, K=None, sig
                      (0.0, kd[0, 2]), (0.0, kd[1, 2])), steps=steps)
     p.exact = lambda x, y, z, t: gaussian_hill3d(x, y, z, t, u, K, sigma0)
     X, Y, Z = p.mesh()
-    p.phi0 = p.exact(X, Y, Z, 0.0)
+    p.phi0 = gaussian_hill3d(X, Y, Z, 0.0, u, K, sigma0, images=images0)
     return p
+
+
+def workload3d(name: str, **kw) -> Problem3D:
+    """The named three-dimensional benchmark workloads."""
+    table = {
+        # anisotropic Gaussian hill on a periodic 256^3 D3Q19 mesh (16.8 M cells)
+        "gaussian_hill3d_256": lambda: gaussian_hill3d_problem(
+            256, q=19, u=(0.05, 0.02, 0.01),
+            K=[[1.0e-4, 2e-5, 1e-5], [2e-5, 1.5e-4, -1e-5], [1e-5, -1e-5, 0.8e-4]], D=1e-4,
+            sigma0=0.15, steps=1000, name="gaussian_hill3d_256", images0=0, **kw),
+    }
+    return table[name]()
+
+
+def random_distributions3d(seed: int, q: int, nz: int, ny: int, nx: int, mean: float = 0.5,
+                           amp: float = 0.05) -> np.ndarray:
+    """Seeded distributions f~ [q][nz][ny][nx]: per direction a share of ``mean``,
+    a smooth seeded cosine field of amplitude ``amp`` and a small cell-scale noise."""
+    rng = np.random.default_rng(seed)
+    share = np.full(q, 1.0 / (2.0 * q))
+    share[0] = 0.5
+    share /= share.sum()
+    axes = [(np.arange(n) + 0.5) / n for n in (nx, ny, nz)]
+    out = np.empty((q, nz, ny, nx))
+    for k in range(q):
+        a = rng.uniform(-1, 1, size=3)
+        ph = rng.uniform(0, 2 * math.pi, size=3)
+        m = rng.integers(1, 4, size=3)
+        cx, cy, cz = (a[i] * np.cos(2 * math.pi * m[i] * axes[i] + ph[i]) for i in range(3))
+        out[k] = mean * share[k] + amp * share[k] * (cx[None, None, :] + cy[None, :, None] + cz[:, None, None])
+        out[k] += 1e-3 * amp * rng.standard_normal((nz, ny, nx))
+    return out
 
 
 def random_problem3d(seed: int, nx: int, ny: int, nz: int, q: int = 19,

@@ -186,9 +186,13 @@ def test_3d_sizes_and_state_errors():
         assert info.nz == 5 and info.q == 19
         assert lib.dugks3_workspace_bytes(h) >= 2 * info.state_bytes
         assert lib.dugks3_step(h, 1) == L.E_STATE
-        assert lib.dugks3_set_launch(h, 3, 8) == L.E_ARG
-        assert lib.dugks3_set_launch(h, 2, 0) == L.E_ARG
-        assert lib.dugks3_set_launch(h, 1, 16) == L.OK
+        # rows per block: binary64 1..2 interior rows, binary32 2..4 rows
+        bad, good = ((3, 0), (1, 2)) if storage == L.F64 else ((5, 1), (2, 4))
+        for rows in bad:
+            assert lib.dugks3_set_launch(h, rows, 8) == L.E_ARG
+        assert lib.dugks3_set_launch(h, good[0], 0) == L.E_ARG
+        for rows in good:
+            assert lib.dugks3_set_launch(h, rows, 16) == L.OK
         lib.dugks3_destroy(h)
 
 

@@ -41,7 +41,7 @@ def test_fp64_matches_oracle(nx, ny, nz, q, bc):
     p = W.random_problem3d(600 + nx + 3 * ny + 7 * nz, nx, ny, nz, q=q, bc=bc,
                            stretched=any(v == M for v in bc), bdeg=2, ddeg=2)
     say(f"case 3d f64 {nx}x{ny}x{nz} q={q} bc={bc}")
-    s = solver(p, "f64", (1, 3))
+    s = solver(p, "f64", (2, 3))
     s.set_phi(p.phi0)
     s.step(3)
     o = Oracle3D(p)
@@ -52,16 +52,29 @@ def test_fp64_matches_oracle(nx, ny, nz, q, bc):
     assert abs(r["mass"] - o.mass()) <= 1e-12 * abs(o.mass())
 
 
-@pytest.mark.parametrize("launch", [(1, 1), (1, 2), (1, 32), (2, 1), (2, 5), (2, 32)])
+@pytest.mark.parametrize("launch", [(2, 1), (2, 5), (3, 2), (3, 7), (4, 1), (4, 3), (2, 32)])
 def test_launch_shapes_give_identical_results(launch):
-    """Tiles of 1 or 2 rows and chunks of 1..32 planes: bitwise the same (binary32)."""
+    """Tiles of 2 to 4 rows and chunks of 1..32 planes: bitwise the same (binary32)."""
     p = W.random_problem3d(77, 70, 7, 9, q=19, bc=(P, M, P), stretched=True, bdeg=2)
-    ref = solver(p, "f32", (2, 32))
+    ref = solver(p, "f32", (4, 32))
     ref.set_phi(p.phi0)
     ref.step(4)
     s = solver(p, "f32", launch)
     s.set_phi(p.phi0)
     s.step(4)
+    assert np.array_equal(s.get_f(), ref.get_f())
+
+
+@pytest.mark.parametrize("launch", [(1, 1), (1, 4), (2, 2), (2, 32)])
+def test_fp64_launch_shapes_give_identical_results(launch):
+    """binary64: tiles of 1 or 2 interior rows and chunks of 1..32 planes, bitwise the same."""
+    p = W.random_problem3d(78, 66, 5, 7, q=15, bc=(M, P, M), stretched=True, bdeg=2)
+    ref = solver(p, "f64", (2, 32))
+    ref.set_phi(p.phi0)
+    ref.step(3)
+    s = solver(p, "f64", launch)
+    s.set_phi(p.phi0)
+    s.step(3)
     assert np.array_equal(s.get_f(), ref.get_f())
 
 
@@ -111,3 +124,38 @@ def test_uniform_state_and_mass_3d():
     m0 = s.reduce()["mass"]
     s.step(50)
     assert abs(s.reduce()["mass"] - m0) <= 1e-12 * abs(m0)
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 2e-6), ("f64", 1e-12)])
+def test_full_size_one_step_sampled_3d(storage, tol):
+    """The 256^3 D3Q19 benchmark mesh in its default launch: one step from a
+    seeded non-equilibrium state, checked at sampled cells (faces, edges,
+    corners, strip seams, tile and chunk seams, random interior cells) against
+    the oracle."""
+    p = W.workload3d("gaussian_hill3d_256")
+    n = p.nx
+    say(f"case full size 3-D {n}^3 {storage}")
+    f0 = W.random_distributions3d(4242, p.q, p.nz, p.ny, p.nx)
+    s = solver(p, storage)
+    s.set_f(f0)
+    s.step(1)
+    gpu = s.get_f()
+    s.close()
+    o = Oracle3D(p)
+    o.set_f(f0)
+    del f0
+    rng = np.random.default_rng(n)
+    pts = set()
+    edge = (0, 1, 31, 32, 61, 62, 63, 123, 124, n - 2, n - 1)
+    for i in edge:
+        for j in (0, 1, 2, n - 1, n // 2):
+            for k in (0, 31, 32, 33, n - 1):
+                pts.add((i, j, k))
+    for _ in range(400):
+        pts.add(tuple(int(v) for v in rng.integers(0, n, size=3)))
+    cells = np.array(sorted(pts))
+    ref = o.step_cells(cells)
+    got = gpu[:, cells[:, 2], cells[:, 1], cells[:, 0]].T
+    err = float(np.abs(got - ref).max() / np.abs(ref).max())
+    say(f"  sampled max rel err {err:.2e} over {len(cells)} cells")
+    assert err <= tol
