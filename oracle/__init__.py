@@ -5,3 +5,4 @@ import this package.  The product library never loads it.
 """
 from .oracle import Oracle, build, library_path  # noqa: F401
 from .oracle3d import Oracle3D  # noqa: F401
+from .oracle1d import Oracle1D  # noqa: F401

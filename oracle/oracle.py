@@ -26,9 +26,16 @@ def library_path3(openmp: bool = False) -> str:
     return os.path.join(HERE, "liboracle3d_omp.so" if openmp else "liboracle3d.so")
 
 
+SRC1 = os.path.join(HERE, "dugks_oracle1d.c")
+
+
+def library_path1(openmp: bool = False) -> str:
+    return os.path.join(HERE, "liboracle1d_omp.so" if openmp else "liboracle1d.so")
+
+
 def build(verbose: bool = False) -> None:
-    """Compile the oracles (2-D and 3-D): plain -O2, no FMA contraction, no fast-math."""
-    for src, path in ((SRC, library_path), (SRC3, library_path3)):
+    """Compile the oracles (1-D, 2-D, 3-D): plain -O2, no FMA contraction, no fast-math."""
+    for src, path in ((SRC, library_path), (SRC3, library_path3), (SRC1, library_path1)):
         for omp in (False, True):
             cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-fPIC",
                    "-shared", "-o", path(omp) + ".tmp", src, "-lm"]

@@ -568,3 +568,112 @@ def random_problem3d(seed: int, nx: int, ny: int, nz: int, q: int = 19,
         field += a * np.cos(wn * kx * X + ph[0]) * np.cos(wn * ky * Y + ph[1]) * np.cos(wn * kz * Z + ph[2])
     p.phi0 = 0.5 + field
     return p
+
+
+# ------------------------------------------------------------- one dimension
+DIRICHLET1 = 1   # one-dimensional walls: 0 periodic, 1 Dirichlet
+
+
+@dataclasses.dataclass
+class Problem1D:
+    """One-dimensional D1Q3 problem with B(phi, x, t) = b(x, t) phi,
+    b = (p0 + p1 t) x + q0 exp(q1 t + q2 t^2), and D = (r0 + r1 t) phi.
+
+    coef: (p0, p1, q0, q1, q2, r0, r1); bc: PERIODIC or DIRICHLET1; for
+    Dirichlet walls ghost(t) gives phi at the two ghost centres."""
+    name: str
+    xf: np.ndarray
+    coef: tuple = (0.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0)
+    c: float = 1.0
+    cfl: float = 0.5
+    alpha: float = 1e-3
+    bc: int = PERIODIC
+    t0: float = 0.0
+    phi0: Optional[np.ndarray] = None
+    exact: Optional[Callable] = None          # (x, t) -> phi
+    ghost: Optional[Callable] = None          # t -> (phi_left_ghost, phi_right_ghost)
+    steps: int = 1
+    seed: Optional[int] = None
+
+    @property
+    def nx(self) -> int:
+        return len(self.xf) - 1
+
+    @property
+    def cells(self) -> int:
+        return self.nx
+
+    def centres(self) -> np.ndarray:
+        return centres(self.xf)
+
+    def ghost_centres(self):
+        w0, w1 = self.xf[1] - self.xf[0], self.xf[-1] - self.xf[-2]
+        return self.xf[0] - 0.5 * w0, self.xf[-1] + 0.5 * w1
+
+    def dt(self) -> float:
+        return self.cfl * float(np.diff(self.xf).min()) / self.c
+
+
+def fokker_planck_exact(x, t):
+    """Closed form eq. 4.6.3 of the nonlinear Fokker-Planck equation eq. 4.6.1
+    (Example 4.6): a Gaussian of mean <x(t)> = exp(t + t^2/2) and variance
+    2 eta(t) exp(t^2), eta = 1 - exp(-t^2)."""
+    x = np.asarray(x, dtype=np.float64)
+    m = math.exp(t + 0.5 * t * t)
+    v = 2.0 * (1.0 - math.exp(-t * t)) * math.exp(t * t)   # 2 eta e^{t^2}
+    return np.exp(-(x - m) ** 2 / (2.0 * v)) / math.sqrt(2.0 * math.pi * v)
+
+
+def fokker_planck_problem(n=400, t0=0.5, c=10.0, cfl=0.5, a=-2.0, b=8.0, alpha=1.0,
+                          name="fokker_planck") -> Problem1D:
+    """Example 4.6 on [a, b] with n uniform cells, started from the closed form
+    at t0 > 0 (eq. 4.6.3) with Dirichlet walls from the closed form:
+    B = (t x + exp(t + t^2/2)) phi, alpha D = 2 t phi (alpha = 1: D = 2 t phi)."""
+    f = uniform_faces(n, a, b)
+    p = Problem1D(name=name, xf=f, coef=(0.0, 1.0, 1.0, 1.0, 0.5, 0.0, 2.0 / alpha), c=c, cfl=cfl,
+                  alpha=alpha, bc=DIRICHLET1, t0=t0)
+    p.exact = fokker_planck_exact
+    gl, gr = p.ghost_centres()
+    p.ghost = lambda t: (float(fokker_planck_exact(gl, t)), float(fokker_planck_exact(gr, t)))
+    p.phi0 = fokker_planck_exact(p.centres(), t0)
+    return p
+
+
+def fokker_planck_delta_initial(p: Problem1D, x0: float = 1.0) -> np.ndarray:
+    """The discrete delta of eq. 4.6.4: mass 1 at x0, held by the cell that
+    contains x0, or split evenly between the two cells when x0 is a face."""
+    phi = np.zeros(p.nx)
+    k = int(np.searchsorted(p.xf, x0))
+    w = np.diff(p.xf)
+    if k < len(p.xf) and abs(p.xf[k] - x0) <= 1e-12 * max(1.0, abs(x0)) and 0 < k < p.nx:
+        phi[k - 1] = 0.5 / w[k - 1]
+        phi[k] = 0.5 / w[k]
+    else:
+        j = min(max(k - 1, 0), p.nx - 1)
+        phi[j] = 1.0 / w[j]
+    return phi
+
+
+def random_problem1d(seed: int, n: int, bc: int = PERIODIC, stretched: bool = False) -> Problem1D:
+    """A small random D1Q3 instance for property tests: random coefficients of
+    b(x, t) (no x-dependence with periodic walls) and d(t), random c, CFL,
+    alpha, a smooth random initial field; Dirichlet walls take a seeded smooth
+    function of t."""
+    rng = np.random.default_rng(seed)
+    f = tanh_faces(n, 1.5) if stretched else uniform_faces(n, 0.0, 1.0)
+    coef = (float(rng.uniform(-0.5, 0.5)), float(rng.uniform(-0.5, 0.5)), float(rng.uniform(-0.5, 0.5)),
+            float(rng.uniform(-1, 1)), float(rng.uniform(-0.5, 0.5)), float(rng.uniform(0.5, 1.5)),
+            float(rng.uniform(-0.5, 0.5)))
+    if bc == PERIODIC:   # periodic walls: b must not depend on x
+        coef = (0.0, 0.0) + coef[2:]
+    p = Problem1D(name=f"random1d_{seed}", xf=f, coef=coef, c=float(rng.uniform(1.0, 3.0)),
+                  cfl=float(rng.uniform(0.3, 0.7)), alpha=float(np.exp(rng.uniform(-6, -3))), bc=bc,
+                  t0=float(rng.uniform(0.0, 0.5)), seed=seed)
+    x = p.centres()
+    field = 1.0 + 0.2 * np.cos(2 * math.pi * x + rng.uniform(0, 2 * math.pi))
+    field += 0.05 * np.cos(6 * math.pi * x + rng.uniform(0, 2 * math.pi))
+    p.phi0 = field
+    if bc == DIRICHLET1:
+        a0, a1, w0 = rng.uniform(0.8, 1.2), rng.uniform(0.8, 1.2), rng.uniform(0.5, 2.0)
+        p.ghost = lambda t: (float(a0 + 0.1 * math.sin(w0 * t)), float(a1 + 0.1 * math.cos(w0 * t)))
+    return p
