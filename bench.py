@@ -52,7 +52,25 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the binary64 comparison runs and the CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run 5 device-to-device copies of COPY_BYTES (HBM counter calibration)")
     return ap.parse_args()
+
+
+COPY_BYTES = 4096 * 4096 * 9 * 4   # 576 MiB
+
+
+def copy_calibration():
+    """Five device-to-device copies of COPY_BYTES: a kernel of known traffic
+    (COPY_BYTES read and COPY_BYTES written) against which the HBM counters
+    FETCH_SIZE and WRITE_SIZE of the step kernels are scaled."""
+    import torch
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES, "copies": 5}), flush=True)
 
 
 def make_problems(name):
@@ -182,7 +200,7 @@ def main3d(args):
         extras = {"fp64_fused_mlups": round(fused64, 1), "rel_l2_vs_fp64": l2,
                   "rel_l2_after_steps": args.warmup + args.steps}
     launch_s = f"{info['rows_per_block']},{info['planes_per_block']}"
-    traffic_b = measured_traffic(args.workload, args.storage, launch_s, kernel="k_step3",
+    traffic_b = measured_traffic(args.workload, args.storage, launch_s, kernel="k_step3s" if storage else "k_step3h",
                                  sources=("dugks3d_kernels.hip", "dugks3d_internal.h"))
     out = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
@@ -235,6 +253,8 @@ def measured_traffic(workload, storage, launch, kernel="k_step",
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        return copy_calibration()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "sharding of this path is a design note, not a built feature", file=sys.stderr)

@@ -418,7 +418,7 @@ class Solver3D:
                                         C.byref(m), C.byref(g), C.byref(l2)), self.h, "dugks3_reduce")
         return {"mass": m.value, "gre": g.value, "rel_l2": l2.value}
 
-    def set_launch(self, rows_per_block=4, planes_per_block=32):
+    def set_launch(self, rows_per_block=4, planes_per_block=64):
         L.check3(self.lib.dugks3_set_launch(self.h, int(rows_per_block), int(planes_per_block)), self.h,
                  "dugks3_set_launch")
 

@@ -309,7 +309,7 @@ int dugks3_create(dugks3_ctx** out, int nx, int ny, int nz, const double* xf, co
   // default launch: binary32 four rows (LDS 5 x 6 x q x 64 x 4 bytes, 143 KiB for
   // D3Q19), binary64 two interior rows (3 x 4 x q x 64 x 8 bytes, 114 KiB)
   x->launch.rows = p->storage == DUGKS_F64 ? 2 : 4;
-  x->launch.planes = 32;
+  x->launch.planes = 64;
   return DUGKS_OK;
 }
 

@@ -50,7 +50,7 @@ struct alignas(64) Inst3 {
 
 struct Launch3 {
   int rows = 4;     // rows per block (see kMinRows32 .. kMaxRows64)
-  int planes = 32;  // planes swept per block
+  int planes = 64;  // planes swept per block
 };
 
 // Blocks of one step for the launch (x strips x row tiles x plane chunks).

@@ -429,6 +429,16 @@ __global__ __launch_bounds__(256) void k_step3h(const Inst3* __restrict__ I, int
 
 #define LDS_PTR(p) ((__attribute__((address_space(3))) void*)(p))
 
+// Blocks are dispatched round-robin over the 8 XCDs, each with its own L2.
+// Renumber them so that each XCD takes a contiguous run of (strip, tile,
+// chunk) indices: neighbouring strips and tiles, which read each other's
+// edge columns and halo rows, then run side by side under one L2.
+__device__ __forceinline__ int xcd_contiguous(int b, int nblocks) {
+  const int q = nblocks >> 3, r = nblocks & 7;
+  const int x = b & 7, i = b >> 3;
+  return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 // Barrier for LDS traffic only: this wave's LDS reads and writes are complete,
 // then the workgroup barrier.  Outstanding global loads stay in flight.
 __device__ __forceinline__ void lds_barrier() {
@@ -453,7 +463,7 @@ __global__ __launch_bounds__(64 * ROWS) void k_step3s(const Inst3* __restrict__ 
   __shared__ float ecoef[Q * NC];             // E_i coefficients, read into vector registers
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  int b = blockIdx.x;
+  int b = xcd_contiguous(blockIdx.x, gridDim.x);
   const int sx = b % strips;
   b /= strips;
   const int tj = b % tiles, tk = b / tiles;
