@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--workload", default="batch256",
                     choices=["batch256", "gaussian_hill_4096", "burgers_512",
                              "nonlinear_diffusion_1024", "gaussian_hill_128", "source_wave_4096",
-                             "gaussian_hill3d_256"])
+                             "gaussian_hill3d_256", "fokker_planck_64m"])
     ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16neq", "bf16neq"])
     ap.add_argument("--launch3", default=None,
                     help="three-dimensional launch rows_per_block,planes_per_block")
@@ -149,6 +149,93 @@ def cpu_baseline3d(seconds):
 
 
 BYTES_PER_UPDATE3 = {0: 2 * 19 * 8, 1: 2 * 19 * 4}   # D3Q19: read + write of the stored state
+BYTES_PER_UPDATE1 = {0: 2 * 4 * 8, 1: 2 * 4 * 4}     # D1Q3: f~ (3) and phi^{n-1}, read + write
+
+
+def cpu_baseline1d(seconds):
+    """The 1-D oracle as it stands, single thread, on 2^18 cells of the
+    Fokker-Planck workload recipe."""
+    from oracle import Oracle1D
+    from paper_1906_11036_amd import workloads as W
+    p = W.fokker_planck_problem(1 << 18, t0=0.5, c=50.0, cfl=0.5)
+    o = Oracle1D(p)
+    o.step(1)
+    steps, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        o.step(1)
+        steps += 1
+    el = time.perf_counter() - t0
+    return {"value": p.cells * steps / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"one 2^18-cell D1Q3 instance of the Fokker-Planck recipe (Example 4.6, Dirichlet "
+                      f"walls), {steps} steps in {el:.1f} s, binary64, 1 thread"}
+
+
+def main1d(args):
+    """One-dimensional workload: one D1Q3 instance stepped by the 1-D kernel."""
+    import numpy as np
+    import torch
+
+    import paper_1906_11036_amd as dg
+    from paper_1906_11036_amd import _lib as L
+    from paper_1906_11036_amd import workloads as W
+    storage = L.STORAGE[args.storage]
+    if storage not in BYTES_PER_UPDATE1:
+        print("the one-dimensional path stores binary64 or binary32 only", file=sys.stderr)
+        sys.exit(2)
+    t_gen = time.perf_counter()
+    p = W.workload1d(args.workload)
+    log(f"workload {args.workload}: {p.cells} cells, generated in {time.perf_counter() - t_gen:.1f} s")
+
+    def run(st):
+        s = dg.Solver1D(p, storage=st)
+        s.set_phi(p.phi0)
+        s.step(args.warmup)
+        torch.cuda.synchronize()
+        ms = s.time_steps(args.steps)   # hipEvents around the launches on the bound stream
+        torch.cuda.synchronize()
+        return s, ms
+
+    s, ms = run(args.storage)
+    info = s.info()
+    ms_step = ms / args.steps
+    mlups = p.cells * args.steps / (ms * 1e-3) / 1e6
+    achieved = BYTES_PER_UPDATE1[storage] * p.cells / (ms_step * 1e-3) / 1e9
+    log(f"{args.storage}: {ms_step:.4f} ms/step, {mlups:.0f} MLUPS, {achieved:.0f} GB/s algorithmic")
+    extras = {}
+    if not args.no_extras:
+        phi32 = s.get_phi()
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+        s64, ms64 = run("f64")
+        fused64 = p.cells * args.steps / (ms64 * 1e-3) / 1e6
+        phi64 = s64.get_phi()
+        s64.close()
+        l2 = float(np.sqrt(((phi32 - phi64) ** 2).sum() / (phi64 ** 2).sum()))
+        log(f"f64: {fused64:.0f} MLUPS; rel-L2(f32 vs f64) after {args.warmup + args.steps} steps {l2:.2e}")
+        extras = {"fp64_fused_mlups": round(fused64, 1), "rel_l2_vs_fp64": l2,
+                  "rel_l2_after_steps": args.warmup + args.steps}
+    kname = "k_step1"
+    traffic_b = measured_traffic(args.workload, args.storage, "one wave per 62 cells, 4 waves a block",
+                                 kernel=kname, sources=("dugks1d.hip",))
+    out = {
+        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.storage, "data": "synthetic",
+        "config": {"workload": args.workload, "instances": 1, "cells": p.cells, "lattice": "D1Q3",
+                   "storage": args.storage, "state_bytes": info["state_bytes"]},
+        "hbm_gbps_algorithmic": round(achieved, 1),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": (round(traffic_b / (ms_step * 1e-3) / 1e9, 1)
+                                 if traffic_b is not None else None)},
+        "traffic_bytes_per_launch": traffic_b,
+    }
+    out.update(extras)
+    if not args.no_extras:
+        out["cpu_baseline"] = cpu_baseline1d(args.cpu_seconds)
+    print(json.dumps(out), flush=True)
 
 
 def main3d(args):
@@ -261,6 +348,8 @@ def main():
         sys.exit(2)
     if args.workload.startswith("gaussian_hill3d"):
         return main3d(args)
+    if args.workload.startswith("fokker_planck"):
+        return main1d(args)
     import numpy as np
     import torch
 

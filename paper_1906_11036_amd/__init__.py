@@ -15,7 +15,7 @@ from . import _lib as L
 from ._lib import (BC_DIRICHLET, BC_MIRROR, BC_PERIODIC, BF16NEQ, F16NEQ, F32, F64,  # noqa: F401
                    KERNEL_FUSED, KERNEL_PLAIN, SCHED_GRID, SCHED_PERSISTENT, STORAGE, DugksError)
 
-__all__ = ["Solver", "Batch", "Solver3D", "DugksError", "F64", "F32", "F16NEQ", "BF16NEQ"]
+__all__ = ["Solver", "Batch", "Solver3D", "Solver1D", "DugksError", "F64", "F32", "F16NEQ", "BF16NEQ"]
 
 
 def _torch():
@@ -432,6 +432,127 @@ class Solver3D:
             self.lib.dugks3_destroy(self.h)
             self.h = None
         self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Solver1D:
+    """One D1Q3 instance on the GPU through include/dugks1d.h: B = b(x, t) phi with
+    b = (p0 + p1 t) x + q0 exp(q1 t + q2 t^2), D = (r0 + r1 t) phi, C = 0, R from
+    dB/dt (Remark 3).
+
+    ``problem`` has the fields of ``workloads.Problem1D`` (faces xf, coef, c, cfl,
+    alpha, bc, t0 and, for Dirichlet walls, ghost(t))."""
+
+    def __init__(self, problem, storage="f64", device="cuda:0"):
+        torch = _torch()
+        self.lib = L.lib()
+        self.device = torch.device(device)
+        self.problem = problem
+        self.storage = _storage_code(storage)
+        self.xf = np.ascontiguousarray(problem.xf, dtype=np.float64)
+        self.nx = len(self.xf) - 1
+        p = L.Params1()
+        p.abi_version = L.ABI1_VERSION
+        p.storage = self.storage
+        p.bc = int(problem.bc)
+        p.c, p.cfl, p.alpha = float(problem.c), float(problem.cfl), float(problem.alpha)
+        for k in range(7):
+            p.coef[k] = float(problem.coef[k])
+        p.t0 = float(getattr(problem, "t0", 0.0))
+        h = C.c_void_p()
+        rc = self.lib.dugks1_create(C.byref(h), self.nx, _dptr(self.xf), C.byref(p))
+        self.h = h
+        L.check1(rc, h, "dugks1_create")
+        nbytes = self.lib.dugks1_workspace_bytes(self.h)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            self._ws_ptr = (self.workspace.data_ptr() + 255) & ~255
+            L.check1(self.lib.dugks1_bind(self.h, C.c_void_p(self._ws_ptr), nbytes,
+                                          _stream_handle(self.device)), self.h, "dugks1_bind")
+        self._ghosts = None
+
+    def _dev64(self, a, shape):
+        torch = _torch()
+        if torch.is_tensor(a):
+            t = a.to(device=self.device, dtype=torch.float64).contiguous()
+        else:
+            t = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(self.device)
+        return t.reshape(shape)
+
+    def info(self) -> dict:
+        inf = L.Info1()
+        L.check1(self.lib.dugks1_get_info(self.h, C.byref(inf)), self.h, "dugks1_get_info")
+        return {k: getattr(inf, k) for k, _ in L.Info1._fields_}
+
+    def set_phi(self, phi):
+        t = self._dev64(phi, (self.nx,))
+        L.check1(self.lib.dugks1_set_phi(self.h, C.c_void_p(t.data_ptr()), 1), self.h, "dugks1_set_phi")
+
+    def set_state(self, f, phi_prev):
+        tf = self._dev64(f, (3, self.nx))
+        tp = self._dev64(phi_prev, (self.nx,))
+        L.check1(self.lib.dugks1_set_state(self.h, C.c_void_p(tf.data_ptr()), C.c_void_p(tp.data_ptr()), 1),
+                 self.h, "dugks1_set_state")
+
+    def set_dirichlet(self, ghosts):
+        """ghosts: [nsteps][2] phi at the two ghost centres for the next steps."""
+        g = np.ascontiguousarray(ghosts, dtype=np.float64).reshape(-1, 2)
+        old = self._ghosts          # the library may still read its last pair
+        self._ghosts = self._dev64(g, (g.shape[0] * 2,))   # kept alive while stepping
+        L.check1(self.lib.dugks1_set_dirichlet(self.h, C.c_void_p(self._ghosts.data_ptr()), g.shape[0]),
+                 self.h, "dugks1_set_dirichlet")
+        del old
+
+    def ghost_table(self, nsteps):
+        """Ghost data of the problem for the next nsteps steps (Dirichlet walls)."""
+        inf = self.info()
+        t0, dt = inf["time"], inf["dt"]
+        return np.array([self.problem.ghost(t0 + s * dt) for s in range(nsteps)], dtype=np.float64)
+
+    def step(self, nsteps=1, auto_ghosts=True):
+        if int(self.problem.bc) == 1 and auto_ghosts and nsteps > 0:
+            self.set_dirichlet(self.ghost_table(nsteps))
+        L.check1(self.lib.dugks1_step(self.h, int(nsteps)), self.h, "dugks1_step")
+
+    def time_steps(self, nsteps):
+        if int(self.problem.bc) == 1 and nsteps > 0:
+            self.set_dirichlet(self.ghost_table(nsteps))
+        ms = C.c_float()
+        L.check1(self.lib.dugks1_time_steps(self.h, int(nsteps), C.byref(ms)), self.h, "dugks1_time_steps")
+        return ms.value
+
+    def _read(self, fn, shape):
+        out = np.zeros(shape)
+        L.check1(fn(self.h, _dptr(out), 0), self.h, "dugks1 read-out")
+        return out
+
+    def get_phi(self) -> np.ndarray:
+        return self._read(self.lib.dugks1_get_phi, (self.nx,))
+
+    def get_f(self) -> np.ndarray:
+        return self._read(self.lib.dugks1_get_f, (3, self.nx))
+
+    def get_phi_prev(self) -> np.ndarray:
+        return self._read(self.lib.dugks1_get_phi_prev, (self.nx,))
+
+    def reduce(self, ref=None) -> dict:
+        m, g, l2 = C.c_double(), C.c_double(), C.c_double()
+        t = self._dev64(ref, (self.nx,)) if ref is not None else None
+        L.check1(self.lib.dugks1_reduce(self.h, C.c_void_p(t.data_ptr()) if t is not None else None,
+                                        C.byref(m), C.byref(g), C.byref(l2)), self.h, "dugks1_reduce")
+        return {"mass": m.value, "gre": g.value, "rel_l2": l2.value}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dugks1_destroy(self.h)
+            self.h = None
+        self.workspace = None
+        self._ghosts = None
 
     def __del__(self):
         try:

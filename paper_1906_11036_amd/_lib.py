@@ -12,6 +12,7 @@ LIB_PATH = os.path.join(HERE, "libdugks.so")
 
 ABI_VERSION = 2
 ABI3_VERSION = 1
+ABI1_VERSION = 1
 MAX_DEG = 4
 OK, E_ARG, E_STATE, E_HIP, E_UNSTABLE, E_UNSUPPORTED, E_NOMEM, E_FORMAT = 0, -1, -2, -3, -4, -5, -6, -7
 F64, F32, F16NEQ, BF16NEQ = 0, 1, 2, 3
@@ -56,6 +57,18 @@ class Info3(C.Structure):
                 ("nz", C.c_int), ("q", C.c_int), ("storage", C.c_int), ("pitch", C.c_int),
                 ("eq_degree", C.c_int), ("rows_per_block", C.c_int), ("planes_per_block", C.c_int),
                 ("blocks", C.c_longlong), ("state_bytes", C.c_size_t)]
+
+
+class Params1(C.Structure):
+    _fields_ = [("abi_version", C.c_int), ("storage", C.c_int), ("bc", C.c_int),
+                ("c", C.c_double), ("cfl", C.c_double), ("alpha", C.c_double),
+                ("coef", C.c_double * 7), ("t0", C.c_double)]
+
+
+class Info1(C.Structure):
+    _fields_ = [("dt", C.c_double), ("h", C.c_double), ("lambda_", C.c_double), ("cs2", C.c_double),
+                ("time", C.c_double), ("steps", C.c_longlong), ("nx", C.c_int), ("storage", C.c_int),
+                ("bc", C.c_int), ("dirichlet_left", C.c_int), ("state_bytes", C.c_size_t)]
 
 
 _D5 = C.c_double * (MAX_DEG + 1)
@@ -123,6 +136,21 @@ SIGNATURES = {
     "dugks3_get_info": (_int, [_vp, C.POINTER(Info3)]),
     "dugks3_last_error": (C.c_char_p, [_vp]),
     "dugks3_destroy": (None, [_vp]),
+    "dugks1_create": (_int, [C.POINTER(_vp), _int, _dp, C.POINTER(Params1)]),
+    "dugks1_workspace_bytes": (_sz, [_vp]),
+    "dugks1_bind": (_int, [_vp, _vp, _sz, _vp]),
+    "dugks1_set_phi": (_int, [_vp, _vp, _int]),
+    "dugks1_set_state": (_int, [_vp, _vp, _vp, _int]),
+    "dugks1_set_dirichlet": (_int, [_vp, _vp, _int]),
+    "dugks1_step": (_int, [_vp, _int]),
+    "dugks1_get_phi": (_int, [_vp, _vp, _int]),
+    "dugks1_get_f": (_int, [_vp, _vp, _int]),
+    "dugks1_get_phi_prev": (_int, [_vp, _vp, _int]),
+    "dugks1_reduce": (_int, [_vp, _vp, _dp, _dp, _dp]),
+    "dugks1_time_steps": (_int, [_vp, _int, C.POINTER(C.c_float)]),
+    "dugks1_get_info": (_int, [_vp, C.POINTER(Info1)]),
+    "dugks1_last_error": (C.c_char_p, [_vp]),
+    "dugks1_destroy": (None, [_vp]),
 }
 
 _LIB = None
@@ -154,6 +182,14 @@ class DugksError(RuntimeError):
 def check(rc, handle, what=""):
     if rc != OK:
         msg = lib().dugks_last_error(handle).decode() if handle else ""
+        raise DugksError(rc, f"{what}: {msg}" if what else msg)
+    return rc
+
+
+def check1(rc, handle, what=""):
+    """check() for a one-dimensional handle."""
+    if rc != OK:
+        msg = lib().dugks1_last_error(handle).decode() if handle else ""
         raise DugksError(rc, f"{what}: {msg}" if what else msg)
     return rc
 

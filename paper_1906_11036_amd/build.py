@@ -9,7 +9,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdugks.so")
 SOURCES = [os.path.join(CSRC, "dugks_kernels.hip"), os.path.join(CSRC, "dugks_host.cpp"),
-           os.path.join(CSRC, "dugks3d_kernels.hip"), os.path.join(CSRC, "dugks3d_host.cpp")]
+           os.path.join(CSRC, "dugks3d_kernels.hip"), os.path.join(CSRC, "dugks3d_host.cpp"),
+           os.path.join(CSRC, "dugks1d.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # no packed binary32 instructions in device code

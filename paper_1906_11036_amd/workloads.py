@@ -677,3 +677,14 @@ def random_problem1d(seed: int, n: int, bc: int = PERIODIC, stretched: bool = Fa
         a0, a1, w0 = rng.uniform(0.8, 1.2), rng.uniform(0.8, 1.2), rng.uniform(0.5, 2.0)
         p.ghost = lambda t: (float(a0 + 0.1 * math.sin(w0 * t)), float(a1 + 0.1 * math.cos(w0 * t)))
     return p
+
+
+def workload1d(name: str, **kw) -> Problem1D:
+    """The named one-dimensional benchmark workloads."""
+    table = {
+        # Example 4.6 on [-2, 8] with 2^26 uniform cells, from the closed form at
+        # t = 0.5; c = 50 keeps max |b| / c_s below 0.45
+        "fokker_planck_64m": lambda: fokker_planck_problem(1 << 26, t0=0.5, c=50.0, cfl=0.5,
+                                                           name="fokker_planck_64m", **kw),
+    }
+    return table[name]()

@@ -1,7 +1,8 @@
 """Host-only checks of the C ABI: the library loads, exports every function of
-include/dugks.h and include/dugks3d.h, and validates arguments without touching
-a device."""
+include/dugks.h, include/dugks3d.h and include/dugks1d.h, and validates
+arguments without touching a device."""
 import ctypes as C
+import math
 import os
 import re
 
@@ -11,14 +12,14 @@ import pytest
 from paper_1906_11036_amd import _lib as L
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADERS = [os.path.join(ROOT, "include", n) for n in ("dugks.h", "dugks3d.h")]
+HEADERS = [os.path.join(ROOT, "include", n) for n in ("dugks.h", "dugks3d.h", "dugks1d.h")]
 
 
 def header_functions():
     names = set()
     for path in HEADERS:
         text = re.sub(r"/\*.*?\*/", "", open(path).read(), flags=re.S)
-        names |= set(re.findall(r"\b(dugks3?_[A-Za-z_0-9]+)\s*\(", text))
+        names |= set(re.findall(r"\b(dugks[13]?_[A-Za-z_0-9]+)\s*\(", text))
     return sorted(names)
 
 
@@ -206,3 +207,54 @@ def test_d3q7_accepts_only_identity_diffusion():
     bad = eye.copy(); bad[1] = 2.0
     assert lib.dugks3_set_D(h, 1, bad.ctypes.data_as(P)) == L.E_UNSUPPORTED
     lib.dugks3_destroy(h)
+
+
+def _create1(nx=10, **kw):
+    lib = L.lib()
+    xf = kw.get("xf", np.linspace(0, 1, nx + 1))
+    p = L.Params1()
+    p.abi_version = kw.get("abi", L.ABI1_VERSION)
+    p.storage = kw.get("storage", L.F64)
+    p.bc = kw.get("bc", 1)
+    p.c, p.cfl, p.alpha = kw.get("c", 1.0), kw.get("cfl", 0.5), kw.get("alpha", 1e-3)
+    for k, v in enumerate(kw.get("coef", (0.1, 0.2, 1.0, 0.5, 0.1, 1.0, 0.3))):
+        p.coef[k] = v
+    p.t0 = kw.get("t0", 0.0)
+    h = C.c_void_p()
+    rc = lib.dugks1_create(C.byref(h), nx, np.ascontiguousarray(xf, dtype=np.float64).ctypes.data_as(
+        C.POINTER(C.c_double)), C.byref(p))
+    return rc, h
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(storage=L.F16NEQ), L.E_UNSUPPORTED), (dict(bc=2), L.E_UNSUPPORTED), (dict(cfl=1.0), L.E_ARG),
+    (dict(nx=0), L.E_ARG), (dict(abi=99), L.E_ARG), (dict(c=-1.0), L.E_ARG), (dict(alpha=0.0), L.E_ARG),
+    (dict(bc=0), L.E_ARG),                       # periodic walls with an x-dependent b
+    (dict(xf=np.array([0, 0.5, 0.4, 1.0]), nx=3), L.E_ARG),
+    (dict(coef=(0, 0, float("nan"), 0, 0, 1, 0)), L.E_ARG),
+])
+def test_create1_rejects_bad_arguments(kw, code):
+    rc, h = _create1(**kw)
+    assert rc == code
+    assert L.lib().dugks1_last_error(h).decode()
+    L.lib().dugks1_destroy(h)
+
+
+def test_1d_sizes_and_state_errors():
+    lib = L.lib()
+    for storage, per in ((L.F64, 8), (L.F32, 4)):
+        rc, h = _create1(nx=100, storage=storage)
+        assert rc == L.OK
+        info = L.Info1()
+        assert lib.dugks1_get_info(h, C.byref(info)) == L.OK
+        assert info.nx == 100 and info.state_bytes == 4 * 128 * per
+        assert math.isclose(info.dt, 0.5 * 0.01 / 1.0) and math.isclose(info.lambda_, 1e-3 * 3.0)
+        assert lib.dugks1_workspace_bytes(h) >= 2 * info.state_bytes
+        assert lib.dugks1_step(h, 1) == L.E_STATE
+        assert lib.dugks1_set_dirichlet(h, None, 3) == L.E_ARG
+        lib.dugks1_destroy(h)
+    rc, h = _create1(nx=16, bc=0, coef=(0, 0, 1.0, 0.5, 0.1, 1.0, 0.3))
+    assert rc == L.OK
+    g = np.zeros(4)
+    assert lib.dugks1_set_dirichlet(h, g.ctypes.data_as(C.POINTER(C.c_double)), 2) == L.E_STATE
+    lib.dugks1_destroy(h)
