@@ -75,7 +75,7 @@ extern "C" {
 #define DUGKS_E_STATE (-2)       /* call not valid in the handle's state */
 #define DUGKS_E_HIP (-3)         /* a HIP runtime call failed */
 #define DUGKS_E_UNSTABLE (-4)    /* non-finite value or FP16 overflow seen on the device */
-#define DUGKS_E_UNSUPPORTED (-5) /* valid request outside what this build implements */
+#define DUGKS_E_UNSUPPORTED (-5) /* valid request outside what this library implements */
 #define DUGKS_E_NOMEM (-6)       /* workspace too small */
 #define DUGKS_E_FORMAT (-7)      /* checkpoint rejected */
 
