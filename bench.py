@@ -216,7 +216,7 @@ def main1d(args):
         extras = {"fp64_fused_mlups": round(fused64, 1), "rel_l2_vs_fp64": l2,
                   "rel_l2_after_steps": args.warmup + args.steps}
     kname = "k_step1"
-    traffic_b = measured_traffic(args.workload, args.storage, "one wave per 62 cells, 4 waves a block",
+    traffic_b = measured_traffic(args.workload, args.storage, "one wave per 62 cells, 16 waves a block",
                                  kernel=kname, sources=("dugks1d.hip",))
     out = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,

@@ -32,7 +32,7 @@
 namespace dugks1 {
 
 constexpr int kCols = 62;
-constexpr int kWavesPerBlock = 4;
+constexpr int kWavesPerBlock = 16;   // large blocks: fewer block dispatches for a streaming kernel
 constexpr int kRedThreads = 256;
 constexpr int kRedBlocks = 512;
 
