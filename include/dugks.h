@@ -236,8 +236,10 @@ int dugks_checkpoint(dugks_ctx* ctx, void* host_buf, size_t* len);
 int dugks_restore(dugks_ctx* ctx, const void* host_buf, size_t len);
 
 /* Launch configuration: rows_per_wave (rows each wave marches, 1..4096),
- * waves_per_block (1, 2, 4 or 8), schedule (DUGKS_SCHED_*), xcd_remap (0/1:
- * map consecutive work to one XCD's L2).  Results do not depend on it.
+ * waves_per_block (1, 2 or 4; also 8 for binary32 and 16-bit storage without
+ * a source, whose step kernel runs two waves per SIMD; setting a source later
+ * turns an 8 into 4), schedule (DUGKS_SCHED_*), xcd_remap (0/1: map
+ * consecutive work to one XCD's L2).  Results do not depend on it.
  * Errors: E_ARG. */
 int dugks_set_launch(dugks_ctx* ctx, int rows_per_wave, int waves_per_block, int schedule,
                      int xcd_remap);

@@ -276,8 +276,14 @@ struct Engine {
     inst[k].src_g = g;
     inst[k].src_gamma = g ? gamma : 0.0;
     drop_graph();
+    if (launch.waves_per_block > 4 && !wide_blocks_ok()) {   // the source path runs 4-wave blocks
+      const int rc = set_launch(launch.rows_per_wave, 4, launch.schedule, launch.xcd_remap);
+      if (rc) return rc;
+    }
     return bound() ? upload_tables() : DUGKS_OK;
   }
+  // 8-wave blocks need the step kernels compiled for two waves per SIMD
+  bool wide_blocks_ok() const { return storage != DUGKS_F64 && !any_source(); }
   bool any_dirichlet() const {
     for (auto& in : inst)
       if (in.bcx == DUGKS_BC_DIRICHLET || in.bcy == DUGKS_BC_DIRICHLET) return true;
@@ -540,7 +546,8 @@ struct Engine {
 
   int set_launch(int rows, int wpb, int sched, int xcd) {
     if (rows < 1 || rows > 4096) return fail(DUGKS_E_ARG, "rows_per_wave out of range");
-    if (wpb != 1 && wpb != 2 && wpb != 4) return fail(DUGKS_E_ARG, "waves_per_block must be 1, 2 or 4");
+    if (wpb != 1 && wpb != 2 && wpb != 4 && !(wpb == 8 && wide_blocks_ok()))
+      return fail(DUGKS_E_ARG, "waves_per_block must be 1, 2 or 4 (8: binary32 or 16-bit storage without a source)");
     if (sched != DUGKS_SCHED_GRID && sched != DUGKS_SCHED_PERSISTENT) return fail(DUGKS_E_ARG, "bad schedule");
     launch.rows_per_wave = rows;
     launch.waves_per_block = wpb;
@@ -717,10 +724,11 @@ struct Engine {
     Launch best = keep;
     float best_ms = 1e30f;
     const int rows_c[] = {8, 16, 32, 64, 128};
-    const int wpb_c[] = {1, 2, 4};
+    const int wpb_c[] = {1, 2, 4, 8};
     for (int sched = 0; sched < 2; ++sched)
       for (int rows : rows_c)
         for (int wpb : wpb_c) {
+          if (wpb == 8 && !wide_blocks_ok()) continue;
           if (set_launch(rows, wpb, sched, 1)) return DUGKS_E_ARG;
           // warm-up
           for (int t = 0; t < 2; ++t)

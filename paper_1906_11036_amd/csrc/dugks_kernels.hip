@@ -712,9 +712,14 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
 template <int ST, bool SRC> struct Occupancy {
   static constexpr int value = SRC ? 1 : (ST == DUGKS_F64 ? DUGKS_WAVES_PER_EU_F64 : DUGKS_WAVES_PER_EU_F32);
 };
+// Threads per block: at two waves per SIMD a block may hold 8 waves (fewer,
+// larger blocks to dispatch); at one wave per SIMD at most 4.
+template <int ST, bool SRC> constexpr int step_max_threads() {
+  return Occupancy<ST, SRC>::value >= 2 ? 512 : 256;
+}
 
 template <int Q, int ST, int NC, bool SRC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occupancy<ST, SRC>::value)))
+__global__ __launch_bounds__((step_max_threads<ST, SRC>())) __attribute__((amdgpu_waves_per_eu(Occupancy<ST, SRC>::value)))
 void k_step(const InstDev* __restrict__ insts,
                                               const WorkItem* __restrict__ items, int nitems,
                                               int parity, long long step, int xcd_remap,

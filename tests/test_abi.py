@@ -98,6 +98,7 @@ def test_calls_before_bind_report_state_errors():
     assert lib.dugks_set_launch(h, 0, 4, 0, 1) == L.E_ARG
     assert lib.dugks_set_launch(h, 32, 3, 0, 1) == L.E_ARG
     assert lib.dugks_set_launch(h, 32, 2, 1, 0) == L.OK
+    assert lib.dugks_set_launch(h, 32, 16, 0, 1) == L.E_ARG
     n = C.c_size_t()
     assert lib.dugks_checkpoint(h, None, C.byref(n)) == L.OK and n.value > 0
     assert lib.dugks_restore(h, b"short", 5) == L.E_FORMAT
@@ -258,3 +259,21 @@ def test_1d_sizes_and_state_errors():
     g = np.zeros(4)
     assert lib.dugks1_set_dirichlet(h, g.ctypes.data_as(C.POINTER(C.c_double)), 2) == L.E_STATE
     lib.dugks1_destroy(h)
+
+
+def test_eight_wave_blocks_only_at_two_waves_per_simd():
+    """8-wave blocks: binary32 / 16-bit storage without a source; binary64 and
+    the source path (one wave per SIMD) refuse them, and a source set later
+    turns an 8 into 4."""
+    lib = L.lib()
+    for storage, ok in ((L.F64, False), (L.F32, True), (L.BF16NEQ, True)):
+        rc, h = _create(storage=storage)
+        assert rc == L.OK
+        assert (lib.dugks_set_launch(h, 8, 8, 0, 1) == L.OK) == ok
+        if storage == L.F32:
+            assert lib.dugks_set_source(h, C.c_void_p(256), 0.0) == L.OK
+            info = L.Info()
+            assert lib.dugks_get_info(h, C.byref(info)) == L.OK
+            assert info.waves_per_block == 4
+            assert lib.dugks_set_launch(h, 8, 8, 0, 1) == L.E_ARG
+        lib.dugks_destroy(h)

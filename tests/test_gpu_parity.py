@@ -182,6 +182,16 @@ def test_launch_shape_invariance_bitwise():
             assert np.array_equal(f, ref), launch
 
 
+@pytest.mark.parametrize("storage", ["f32", "bf16neq"])
+def test_eight_wave_blocks_bitwise(storage):
+    """Binary32 and 16-bit storage: 8-wave blocks give the 4-wave results bit for
+    bit (every wave runs its own work item), grid and persistent schedules."""
+    p = W.random_problem(322, 150, 97, bcx=W.PERIODIC, bcy=W.DIRICHLET, bdeg=2, ddeg=2)
+    ref = run_gpu(p, 5, storage=storage, launch=(8, 4, dg.SCHED_GRID, 1)).get_f()
+    for launch in ((8, 8, dg.SCHED_GRID, 1), (3, 8, dg.SCHED_PERSISTENT, 1), (16, 8, dg.SCHED_GRID, 0)):
+        assert np.array_equal(run_gpu(p, 5, storage=storage, launch=launch).get_f(), ref), launch
+
+
 def test_checkpoint_round_trip_bitwise():
     p = W.random_problem(77, 90, 40, bdeg=2, ddeg=2)
     say("case checkpoint")
