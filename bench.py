@@ -29,6 +29,14 @@ PEAK_HBM_GBS = 8000.0
 BYTES_PER_UPDATE = {0: 144, 1: 72, 2: 40, 3: 40}   # D2Q9: read + write of the stored state
 
 
+def bytes_per_update(storage, q):
+    """Algorithmic bytes of one cell update: the stored state read and written
+    once (binary64 / binary32: q values; 16-bit: phi in binary32 and q-1
+    scaled non-equilibrium values in 16 bits)."""
+    per = {0: 8 * q, 1: 4 * q}.get(storage, 4 + 2 * (q - 1))
+    return 2 * per
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -41,7 +49,8 @@ def parse():
     ap.add_argument("--workload", default="batch256",
                     choices=["batch256", "gaussian_hill_4096", "burgers_512",
                              "nonlinear_diffusion_1024", "gaussian_hill_128", "source_wave_4096",
-                             "gaussian_hill3d_256", "fokker_planck_64m"])
+                             "gaussian_hill3d_256", "fokker_planck_64m", "gaussian_hill_4096_d2q5",
+                             "gaussian_hill3d_256_d3q15", "gaussian_hill3d_256_d3q7"])
     ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16neq", "bf16neq"])
     ap.add_argument("--launch3", default=None,
                     help="three-dimensional launch rows_per_block,planes_per_block")
@@ -268,7 +277,7 @@ def main3d(args):
     info = s.info()
     ms_step = ms / args.steps
     mlups = p.cells * args.steps / (ms * 1e-3) / 1e6
-    alg_bytes = BYTES_PER_UPDATE3[storage] * p.cells
+    alg_bytes = 2 * p.q * (8 if storage == 0 else 4) * p.cells
     achieved = alg_bytes / (ms_step * 1e-3) / 1e9
     log(f"{args.storage}: {ms_step:.4f} ms/step, {mlups:.0f} MLUPS, {achieved:.0f} GB/s algorithmic "
         f"(rows/block={info['rows_per_block']} planes/block={info['planes_per_block']})")
@@ -294,7 +303,7 @@ def main3d(args):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.storage, "data": "synthetic",
-        "config": {"workload": args.workload, "instances": 1, "cells": p.cells, "lattice": "D3Q19",
+        "config": {"workload": args.workload, "instances": 1, "cells": p.cells, "lattice": f"D3Q{p.q}",
                    "storage": args.storage, "state_bytes": info["state_bytes"],
                    "rows_per_block": info["rows_per_block"], "planes_per_block": info["planes_per_block"]},
         "hbm_gbps_algorithmic": round(achieved, 1),
@@ -377,7 +386,7 @@ def main():
     mlups = cells * args.steps / (ms * 1e-3) / 1e6
     # per launch (one launch per step); a source adds its G read (8 B a cell)
     src_cells = sum(p.cells for p in problems if getattr(p, "src_g", None) is not None)
-    alg_bytes = BYTES_PER_UPDATE[storage] * cells + 8 * src_cells
+    alg_bytes = sum(bytes_per_update(storage, p.q) * p.cells for p in problems) + 8 * src_cells
     achieved = alg_bytes / (ms_step * 1e-3) / 1e9
     log(f"{args.storage}: {ms_step:.4f} ms/step, {mlups:.0f} MLUPS, {achieved:.0f} GB/s algorithmic "
         f"(launch rows/wave={info['rows_per_wave']} waves/block={info['waves_per_block']} "
@@ -424,7 +433,7 @@ def main():
         "dtype": {"f64": "f64", "f32": "f32", "f16neq": "f16(neq)+f32", "bf16neq": "bf16(neq)+f32"}[args.storage],
         "data": "synthetic",
         "config": {"workload": args.workload, "instances": len(problems), "cells": cells,
-                   "lattice": "D2Q9", "storage": args.storage,
+                   "lattice": f"D2Q{problems[0].q}", "storage": args.storage,
                    "state_bytes": state_bytes, "rows_per_wave": info["rows_per_wave"],
                    "waves_per_block": info["waves_per_block"], "schedule": info["schedule"],
                    "launch_from": tuned_from},

@@ -384,6 +384,9 @@ def workload(name: str, **kw):
         "batch256": lambda: batch_problems(**kw),
         "source_wave_4096": lambda: source_wave_problem(4096, Pe=1000.0, t_end=0.05,
                                                         name="source_wave_4096", **kw),
+        # the 4096^2 Gaussian hill on D2Q5 (linear equilibrium of Remark 3, D = phi I)
+        "gaussian_hill_4096_d2q5": lambda: gaussian_hill_problem(
+            4096, u=(0.05, 0.02), D=1e-4, steps=1000, q=5, name="gaussian_hill_4096_d2q5", **kw),
     }
     return table[name]()
 
@@ -514,6 +517,14 @@ def workload3d(name: str, **kw) -> Problem3D:
             256, q=19, u=(0.05, 0.02, 0.01),
             K=[[1.0e-4, 2e-5, 1e-5], [2e-5, 1.5e-4, -1e-5], [1e-5, -1e-5, 0.8e-4]], D=1e-4,
             sigma0=0.15, steps=1000, name="gaussian_hill3d_256", images0=0, **kw),
+        # the same mesh on D3Q15, and on D3Q7 with isotropic diffusion (D = phi I)
+        "gaussian_hill3d_256_d3q15": lambda: gaussian_hill3d_problem(
+            256, q=15, u=(0.05, 0.02, 0.01),
+            K=[[1.0e-4, 2e-5, 1e-5], [2e-5, 1.5e-4, -1e-5], [1e-5, -1e-5, 0.8e-4]], D=1e-4,
+            sigma0=0.15, steps=1000, name="gaussian_hill3d_256_d3q15", images0=0, **kw),
+        "gaussian_hill3d_256_d3q7": lambda: gaussian_hill3d_problem(
+            256, q=7, u=(0.05, 0.02, 0.01), D=1e-4, sigma0=0.15, steps=1000,
+            name="gaussian_hill3d_256_d3q7", images0=0, **kw),
     }
     return table[name]()
 
