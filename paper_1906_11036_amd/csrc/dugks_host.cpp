@@ -723,7 +723,7 @@ struct Engine {
     const Launch keep = launch;
     Launch best = keep;
     float best_ms = 1e30f;
-    const int rows_c[] = {8, 16, 32, 64, 128};
+    const int rows_c[] = {2, 4, 8, 16, 32, 64, 128};   // short items: more waves on small grids
     const int wpb_c[] = {1, 2, 4, 8};
     for (int sched = 0; sched < 2; ++sched)
       for (int rows : rows_c)
