@@ -107,7 +107,8 @@ int dugks3_reduce(dugks3_ctx* ctx, const double* ref_dev, double* mass, double* 
  * halo rows staged in LDS, 5 x (rows + 2) x q x 64 x 4 bytes); binary64: 1 or
  * 2 interior rows plus one wave per halo row (g in LDS, 3 x (rows + 2) x q x
  * 64 x 8 bytes).  A launch needing more LDS than the device allows per block
- * is refused.  Defaults: 4 rows (binary32), 2 rows (binary64), 64 planes.
+ * is refused.  Defaults: 4 rows (binary32), 2 rows (binary64), 64 planes
+ * (halved down to 4 while the grid would have fewer than 512 blocks).
  * Errors: E_ARG. */
 int dugks3_set_launch(dugks3_ctx* ctx, int rows_per_block, int planes_per_block);
 
