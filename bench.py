@@ -280,7 +280,7 @@ def main1d(args):
 
 
 def main3d(args):
-    """Three-dimensional workload: one D3Q19 instance stepped by the 3-D kernel."""
+    """Three-dimensional workload: one instance stepped by the 3-D kernel."""
     import numpy as np
     import torch
 
@@ -328,7 +328,8 @@ def main3d(args):
         extras = {"fp64_fused_mlups": round(fused64, 1), "rel_l2_vs_fp64": l2,
                   "rel_l2_after_steps": args.warmup + args.steps}
     launch_s = f"{info['rows_per_block']},{info['planes_per_block']}"
-    traffic_b = measured_traffic(args.workload, args.storage, launch_s, kernel="k_step3s" if storage else "k_step3h",
+    kernel = "k_step3p" if p.q != 7 else ("k_step3s" if storage else "k_step3h")
+    traffic_b = measured_traffic(args.workload, args.storage, launch_s, kernel=kernel,
                                  sources=("dugks3d_kernels.hip", "dugks3d_internal.h"))
     out = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,

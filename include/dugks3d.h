@@ -103,12 +103,16 @@ int dugks3_reduce(dugks3_ctx* ctx, const double* ref_dev, double* mass, double* 
                   double* rel_l2);
 
 /* Launch configuration: rows per block and planes swept per block (>= 1).
- * binary32: 2 to 4 rows, one wave each (raw f~ and g of the rows and the two
- * halo rows staged in LDS, 5 x (rows + 2) x q x 64 x 4 bytes); binary64: 1 or
- * 2 interior rows plus one wave per halo row (g in LDS, 3 x (rows + 2) x q x
- * 64 x 8 bytes).  A launch needing more LDS than the device allows per block
- * is refused.  Defaults: 4 rows (binary32), 2 rows (binary64), 64 planes
- * (halved down to 4 while the grid would have fewer than 512 blocks).
+ * binary32: 2 to 4 rows; binary64: 1 or 2 rows.  D3Q15 and D3Q19 give each
+ * row two waves, one per half of the directions (g of 3 planes, raw f~ of 2
+ * (binary32) or 1 (binary64) planes of the rows and the two halo rows, and 4
+ * face sums per row, in LDS: (5 or 4) x (rows + 2) x q x 64 x s + 4 x rows x
+ * 2 x 64 x s bytes, s the element size).  D3Q7 gives each row one wave
+ * (binary32: 5 x (rows + 2) x q x 64 x 4 bytes of LDS; binary64: one more
+ * wave per halo row, 3 x (rows + 2) x q x 64 x 8 bytes).  A launch needing
+ * more LDS than the device allows per block is refused.  Defaults: 2 rows
+ * (binary64), 4 rows (binary32; D3Q15: 2); 64 planes (D3Q7: 32), halved down
+ * to 4 while the grid would have fewer than 512 blocks.
  * Errors: E_ARG. */
 int dugks3_set_launch(dugks3_ctx* ctx, int rows_per_block, int planes_per_block);
 

@@ -7,10 +7,12 @@
 // LDS.  Per plane and cell it computes the west face (x; the east face is the
 // next lane's west face), both y faces and the top face (z; the bottom face is
 // the previous plane's top face) and the update.  x neighbours come from
-// whole-wave DPP shifts, as in the 2-D kernels.  Two variants: binary32 stages
-// raw f~ through LDS with direct buffer-to-LDS loads (every wave owns an
-// interior row); binary64 holds its window in registers and spends one wave
-// on each halo row.
+// whole-wave DPP shifts, as in the 2-D kernels.  D3Q15 and D3Q19 (both
+// storages) stage raw f~ through LDS with direct buffer-to-LDS loads and give
+// each row two waves, one per half of the directions (k_step3p).  D3Q7, whose
+// registers are no constraint, gives each row one wave: binary32 staged the
+// same way (k_step3s), binary64 with its window in registers and one wave on
+// each halo row (k_step3h).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -214,7 +216,7 @@ __device__ __forceinline__ void face3(const Inst3* __restrict__ I, const EQ& E, 
 
 extern __shared__ __align__(16) unsigned char dugks3_lds[];
 
-// ------------------------------------------- fused step, binary64 storage
+// --------------------------------- fused step, binary64 storage (D3Q7)
 // A block owns a strip of 62 columns (64 lanes: one halo column each side), a
 // tile of `rows` rows plus one halo row each side (one wave per row) and a
 // chunk of planes, which it sweeps in z.  Each wave keeps g of its row at
@@ -417,7 +419,7 @@ __global__ __launch_bounds__(256) void k_step3h(const Inst3* __restrict__ I, int
   (void)bad;
 }
 
-// ------------------------------------------- fused step, binary32 storage
+// --------------------------------- fused step, binary32 storage (D3Q7)
 // A block of `ROWS` waves owns ROWS rows of a 62-column strip (one row per
 // wave) and sweeps a chunk of planes in z.  Raw f~ of planes z+1 and z+2 is
 // staged in LDS by direct buffer-to-LDS loads (no registers held while in
@@ -697,6 +699,454 @@ __global__ __launch_bounds__(64 * ROWS) void k_step3s(const Inst3* __restrict__ 
   if (z < z1) body(z, R1{});
 }
 
+// ------------------------------------ fused step, directions split in two
+// The staged kernels above give one wave a whole row and need all of its
+// directions in registers, so a wave fills its SIMD's register file and LDS
+// limits a block to a few waves.  Here two waves share a row, each taking one
+// half of the directions, closed under the wall mirrors (a wall reflection
+// keeps which components of c_i are zero): the cell's phi is summed from all
+// directions of the staged row in LDS, and the interface phi of each face
+// (eq. 2.22) from the two halves' sums, exchanged through LDS.
+template <int Q> __host__ __device__ constexpr int half_of(int k) {
+  const int x = ce<Q>(k, 0), y = ce<Q>(k, 1), z = ce<Q>(k, 2);
+  const int nnz = (x != 0) + (y != 0) + (z != 0);
+  if (Q == 19) return (nnz == 1 || (x == 0 && nnz == 2)) ? 1 : 0;   // 9 + 10
+  if (Q == 15) return nnz == 3 ? 1 : 0;                              // 7 + 8
+  return (x == 0 && nnz == 1) ? 1 : 0;                               // 3 + 4
+}
+template <int Q, int H> __host__ __device__ constexpr int half_count() {
+  int n = 0;
+  for (int k = 0; k < Q; ++k) n += half_of<Q>(k) == H;
+  return n;
+}
+
+// sum over this half's directions: in order in binary64, pairwise in binary32
+template <int Q, int H, typename T> __device__ __forceinline__ T half_sum(const T* v) {
+  constexpr int N = half_count<Q, H>();
+  T t[N];
+  int n = 0;
+#pragma unroll
+  for (int k = 0; k < Q; ++k)
+    if (half_of<Q>(k) == H) t[n++] = v[k];
+  if constexpr (sizeof(T) == 8) {
+    T s = t[0];
+#pragma unroll
+    for (int j = 1; j < N; ++j) s += t[j];
+    return s;
+  } else {
+#pragma unroll
+    for (int w = 1; w < N; w *= 2)
+#pragma unroll
+      for (int j = 0; j + w < N; j += 2 * w) t[j] += t[j + w];
+    return t[0];
+  }
+}
+
+template <int Q, int H, typename T> __device__ __forceinline__ void mirror_half(T* g, int a) {
+  T t[Q];
+#pragma unroll
+  for (int k = 0; k < Q; ++k)
+    if (half_of<Q>(k) == H) t[k] = g[mir<Q>(k, a)];
+#pragma unroll
+  for (int k = 0; k < Q; ++k)
+    if (half_of<Q>(k) == H) g[k] = t[k];
+}
+
+// face3 in two parts: the interface g of this half's directions and their
+// sum, then F from the interface phi of the two halves' sums (s0 + s1)
+template <int Q, int H, int A, typename T>
+__device__ __forceinline__ T face_gb(const T* L, const T* R, const T* t1, T tau1, const T* t2, T tau2, T am,
+                                     T a0, T ap, T* gb) {
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    if (half_of<Q>(k) != H) continue;
+    const int cn = ce<Q>(k, A), c1 = ce<Q>(k, tan1<A>()), c2 = ce<Q>(k, tan2<A>());
+    const T al = cn > 0 ? ap : (cn < 0 ? am : a0);
+    T v = fma(al, R[k] - L[k], L[k]);
+    if (c1 != 0) v = fma((T)(-c1) * tau1, t1[k], v);
+    if (c2 != 0) v = fma((T)(-c2) * tau2, t2[k], v);
+    gb[k] = v;
+  }
+  return half_sum<Q, H>(gb);
+}
+template <int Q, int H, int A, typename T, typename EQ>
+__device__ __forceinline__ void face_out(const Inst3* __restrict__ I, const EQ& E, const T* gb, T s0, T s1,
+                                         T* out) {
+  const T pb = (T)((s0 + s1) * C3<T>::b1(I));
+  const T rb = C3<T>::rb(I);
+#pragma unroll
+  for (int k = 0; k < Q; ++k)
+    if (half_of<Q>(k) == H && ce<Q>(k, A) != 0) out[k] = fma(rb, gb[k], E(k, pb));
+}
+
+template <int Q, int ROWS, typename T> struct LdsP {
+  static constexpr int W = ROWS + 2;             // LDS rows: y0-1 .. y0+ROWS
+  static constexpr int WD = sizeof(T) / 4;       // words per element
+  static constexpr int NS = WD == 1 ? 2 : 1;     // staging slots
+  T gsl[3][W][Q][kLanes];                        // g of plane p in slot (p - z0) mod 3
+  unsigned raw[NS][W][Q][WD][kLanes];            // staged f~, binary64 as low and high words
+  T psum[4][ROWS][2][kLanes];                    // the halves' interface-g sums of four faces
+};
+
+// One wave: row rw of the tile, directions of half H.  Binary32 stages plane
+// z+2 into the second slot while plane z+1 is read from the first; binary64
+// has one slot, refilled once every wave has read it.
+template <int Q, int NC, int ROWS, typename T, int H>
+__device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int parity, int planes, int strips,
+                                            int tiles, LdsP<Q, ROWS, T>& L, const float* ecoef, int rw) {
+  using LP = LdsP<Q, ROWS, T>;
+  constexpr int W = LP::W, WD = LP::WD;
+  constexpr int NW = 2 * ROWS;                   // waves per block
+  constexpr int HX = (2 * Q + NW - 1) / NW;      // halo-row loads per wave
+  constexpr unsigned ES = sizeof(T);
+  constexpr bool kVecE = sizeof(T) == 4 && NC <= 4;
+  const int w = 2 * rw + H;
+  const int lane = threadIdx.x & 63;
+  int b = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int sx = b % strips;
+  b /= strips;
+  const int tj = b % tiles, tk = b / tiles;
+  const int nx = I->n[0], ny = I->n[1], nz = I->n[2];
+  const int bcx = I->bc[0], bcy = I->bc[1], bcz = I->bc[2];
+  const int pitch = I->pitch;
+  const unsigned plane = (unsigned)I->plane;
+  const int x0 = sx * kCols, y0 = tj * ROWS, z0 = tk * planes;
+  const int y1 = min(y0 + ROWS, ny), z1 = min(z0 + planes, nz);
+  // this wave's row (LDS row rw + 1); in a short last tile the rows past it
+  // take the upper halo row y1
+  const int rr = y0 + rw;
+  const int r = rr < y1 ? rr : y1;
+  const bool inner = rr < y1;
+  const int me = rw + 1;
+  const int c = x0 - 1 + lane;
+  const int scol = src_index(c < nx + 1 ? c : nx, nx, bcx);
+  const bool wall_x = (c < 0 || c >= nx) && bcx != DUGKS_BC_PERIODIC;
+  const bool live = inner && lane >= 1 && lane <= kCols && c < nx;
+  const int srow = src_index(r, ny, bcy);
+  const bool wall_y = (r < 0 || r >= ny) && bcy != DUGKS_BC_PERIODIC;
+  // halo rows: y0-1 in LDS row 0 and y1 in LDS row W-1 (unused when the tile is short)
+  const int slo = src_index(y0 - 1, ny, bcy), shi = src_index(y1, ny, bcy);
+  const bool wall_lo = y0 - 1 < 0 && bcy != DUGKS_BC_PERIODIC;
+  const bool wall_hi = y1 >= ny && bcy != DUGKS_BC_PERIODIC;
+
+  const __amdgpu_buffer_rsrc_t Rin = rsrc(I->buf[parity], I->buf_bytes);
+  const __amdgpu_buffer_rsrc_t Rout = rsrc(I->buf[parity ^ 1], I->buf_bytes);
+
+  const T* cg = C3<T>::geo(I, 0) + (long long)(c + 1 < nx + 1 ? c + 1 : nx + 1) * kGeo;
+  const T cam = cg[0], ca0 = cg[1], cap = cg[2], ctau = cg[3], ck = cg[4];
+  const CPtr<T> yg = as_constant(C3<T>::geo(I, 1));
+  const CPtr<T> zg = as_constant(C3<T>::geo(I, 2));
+  const int ryi = (r + 1 < ny + 1 ? r + 1 : ny + 1);
+  const T ytau = yg[ryi * kGeo + 3], ky = yg[ryi * kGeo + 4];
+  const T yS0 = yg[ryi * kGeo + 0], yS1 = yg[ryi * kGeo + 1], yS2 = yg[ryi * kGeo + 2];
+  const int ryn = (ryi + 1 < ny + 2 ? ryi + 1 : ny + 1);
+  const T yN0 = yg[ryn * kGeo + 0], yN1 = yg[ryn * kGeo + 1], yN2 = yg[ryn * kGeo + 2];
+  const T kgv = C3<T>::kg(I);
+  const unsigned planeB = plane * ES;
+  using EV = std::conditional_t<kVecE, EqVec<Q, NC>, EqScalar<NC, T>>;
+  EV ev;
+  if constexpr (!kVecE) ev.I = I;
+
+  auto cell_index = [&](int sr, int zp) __attribute__((always_inline)) -> unsigned {
+    return (unsigned)((src_index(zp, nz, bcz) * ny + sr) * pitch + scol);
+  };
+  // stage plane zp: this wave's directions of its row, and its share of the
+  // two halo rows (offsets advance in a vector register)
+  auto stage = [&](int slot, int zp) __attribute__((always_inline)) {
+    unsigned o = cell_index(srow, zp) * ES;
+    const int wme = me;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      if (half_of<Q>(k) == H) {
+#pragma unroll
+        for (int h = 0; h < WD; ++h)
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(Rin, LDS_PTR(&L.raw[slot][wme][k][h][0]), 4, o + 4u * h, 0, 0, 0);
+      }
+      o += planeB;
+    }
+    const unsigned ilo = cell_index(slo, zp) * ES, ihi = cell_index(shi, zp) * ES;
+    const int j0 = w * HX;
+#pragma unroll
+    for (int t = 0; t < HX; ++t) {
+      int j = j0 + t;
+      j = j < 2 * Q ? j : j - 2 * Q;   // the few surplus loads repeat earlier ones
+      const bool hi = j >= Q;
+      const int k = hi ? j - Q : j;
+      const unsigned oh = (hi ? ihi : ilo) + (unsigned)k * planeB;
+#pragma unroll
+      for (int h = 0; h < WD; ++h)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(Rin, LDS_PTR(&L.raw[slot][hi ? W - 1 : 0][k][h][0]), 4,
+                                                 oh + 4u * h, 0, 0, 0);
+    }
+  };
+  auto raw_at = [&](int slot, int row, int k) __attribute__((always_inline)) -> T {
+    if constexpr (WD == 1)
+      return __builtin_bit_cast(float, L.raw[slot][row][k][0][lane]);
+    else
+      return __builtin_bit_cast(double, (unsigned long long)L.raw[slot][row][k][0][lane] |
+                                            ((unsigned long long)L.raw[slot][row][k][1][lane] << 32));
+  };
+  // g = fbar+ / b1 (eq. 2.21 over b1) of this half's directions; phi (binary64) from all of them
+  auto make_g = [&](int slot, int row, bool wy, int zp, T* g, T* f) __attribute__((always_inline)) {
+    double phi = 0.0;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      const T v = raw_at(slot, row, k);
+      phi += (double)v;
+      if (half_of<Q>(k) == H) f[k] = v;
+    }
+    const T p = (T)phi, ra = C3<T>::ra(I);
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+      if (half_of<Q>(k) == H) g[k] = fma(ra, f[k], ev(k, p));
+    if (wall_x) mirror_half<Q, H, T>(g, 0);
+    if (wy) mirror_half<Q, H, T>(g, 1);
+    if ((zp < 0 || zp >= nz) && bcz != DUGKS_BC_PERIODIC) mirror_half<Q, H, T>(g, 2);
+  };
+  auto publish = [&](int slot, int row, const T* g) __attribute__((always_inline)) {
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+      if (half_of<Q>(k) == H) L.gsl[slot][row][k][lane] = g[k];
+  };
+  // g of plane zp for this wave's row (G, and f~+ in FT) and, for the waves
+  // of rows 0 and 1, the halo rows; all published to slot `slot`
+  auto plane_g = [&](int rs, int zp, int slot, T* G, T* FT) __attribute__((always_inline)) {
+    T f[Q];
+    make_g(rs, me, wall_y, zp, G, f);
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+      if (half_of<Q>(k) == H) FT[k] = fma(kgv, G[k], (T)(-1.0 / 3.0) * f[k]);
+    publish(slot, me, G);
+    if (rw <= 1) {
+      T gx[Q];
+      const int row = rw == 0 ? 0 : W - 1;
+      make_g(rs, row, rw == 0 ? wall_lo : wall_hi, zp, gx, f);
+      publish(slot, row, gx);
+      if (ROWS == 1) {  // one row: its waves make both halo rows
+        make_g(rs, W - 1, wall_hi, zp, gx, f);
+        publish(slot, W - 1, gx);
+      }
+    }
+  };
+  auto put_sum = [&](int face, T s) __attribute__((always_inline)) { L.psum[face][rw][H][lane] = s; };
+  auto sums = [&](int face, T mine, T& s0, T& s1) __attribute__((always_inline)) {
+    const T other = L.psum[face][rw][1 - H][lane];
+    s0 = H == 0 ? mine : other;
+    s1 = H == 0 ? other : mine;
+  };
+
+  T G0[Q], G1[Q], O[Q], FT1[Q], FZb[Q], FZt[Q];
+  // one part of the pipeline differs: binary32 stages plane z+2 before the
+  // first barrier of plane z (other slot), binary64 after it (same slot)
+  constexpr bool two = LP::NS == 2;
+
+  // prologue: planes z0-1 (slot 2 of g) and z0 (slot 0), plane z0+1 staged,
+  // the bottom face of plane z0
+  if constexpr (two) {
+    stage(1, z0 - 1);
+    stage(0, z0);
+    wait_vm_all();
+    lds_barrier();
+    if constexpr (kVecE) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k)
+        if (half_of<Q>(k) == H)
+#pragma unroll
+          for (int m = 0; m < NC; ++m) ev.c[k][m] = ecoef[k * NC + m];
+    }
+    plane_g(1, z0 - 1, 2, G1, FT1);
+    plane_g(0, z0, 0, G0, O);
+    lds_barrier();
+    stage(1, z0 + 1);   // z1 >= z0 + 1
+  } else {
+    stage(0, z0 - 1);
+    wait_vm_all();
+    lds_barrier();
+    plane_g(0, z0 - 1, 2, G1, FT1);
+    lds_barrier();
+    stage(0, z0);
+    wait_vm_all();
+    lds_barrier();
+    plane_g(0, z0, 0, G0, O);
+    lds_barrier();
+    stage(0, z0 + 1);
+  }
+  T gbB[Q], sB = 0;
+  const int zb = z0 + 1;
+  if (inner) {  // bottom face of plane z0
+    T t1[Q], t2[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      if (half_of<Q>(k) != H) continue;
+      if (ce<Q>(k, 0) != 0)
+        t1[k] = (shl1(G1[k]) - shr1(G1[k])) + (shl1(G0[k]) - shr1(G0[k]));
+      if (ce<Q>(k, 1) != 0)
+        t2[k] = (L.gsl[2][me + 1][k][lane] - L.gsl[2][me - 1][k][lane]) +
+                (L.gsl[0][me + 1][k][lane] - L.gsl[0][me - 1][k][lane]);
+    }
+    sB = face_gb<Q, H, 2>(G1, G0, t1, ctau, t2, ytau, (T)zg[zb * kGeo + 0], (T)zg[zb * kGeo + 1],
+                          (T)zg[zb * kGeo + 2], gbB);
+    put_sum(0, sB);
+  }
+  lds_barrier();
+  if (inner) {
+    T s0, s1;
+    sums(0, sB, s0, s1);
+    face_out<Q, H, 2>(I, ev, gbB, s0, s1, FZb);
+  }
+  wait_vm_all();
+  lds_barrier();
+
+  auto body = [&](int z, auto rsl) __attribute__((always_inline)) {
+    constexpr int RS = decltype(rsl)::value;   // staging slot of plane z+1
+    const int d = z - z0;
+    const int s0 = d % 3, sp = (d + 1) % 3, sm = (d + 2) % 3;
+    plane_g(RS, z + 1, sp, G1, FT1);
+    if constexpr (two) {
+      if (z + 2 <= z1) stage(1 - RS, z + 2);
+      lds_barrier();
+    } else {
+      lds_barrier();   // every wave has read plane z+1 from the slot
+      if (z + 2 <= z1) stage(0, z + 2);
+    }
+    T gbW[Q], gbN[Q], gbS[Q], gbT[Q], sW = 0, sN = 0, sS = 0, sT = 0;
+    if (inner) {
+      T sx0[Q], dY[Q], dZ[Q], t1[Q], t2[Q];
+      const int zi = z + 1;
+      const T ztau = zg[zi * kGeo + 3];
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        if (half_of<Q>(k) != H) continue;
+        if (ce<Q>(k, 0) != 0) sx0[k] = shl1(G0[k]) - shr1(G0[k]);
+        if (ce<Q>(k, 1) != 0) dY[k] = L.gsl[s0][me + 1][k][lane] - L.gsl[s0][me - 1][k][lane];
+        if (ce<Q>(k, 2) != 0) dZ[k] = G1[k] - L.gsl[sm][me][k][lane];
+      }
+      {  // west face (x); the east face is lane + 1's west face
+        T lw[Q];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          if (half_of<Q>(k) != H) continue;
+          lw[k] = shr1(G0[k]);
+          if (ce<Q>(k, 1) != 0) t1[k] = shr1(dY[k]) + dY[k];
+          if (ce<Q>(k, 2) != 0) t2[k] = shr1(dZ[k]) + dZ[k];
+        }
+        sW = face_gb<Q, H, 0>(lw, G0, t1, ytau, t2, ztau, cam, ca0, cap, gbW);
+      }
+      {  // north face (rows r, r+1)
+        T gU[Q];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          if (half_of<Q>(k) != H) continue;
+          gU[k] = L.gsl[s0][me + 1][k][lane];
+          if (ce<Q>(k, 0) != 0) t1[k] = sx0[k] + (shl1(gU[k]) - shr1(gU[k]));
+          if (ce<Q>(k, 2) != 0) t2[k] = dZ[k] + (L.gsl[sp][me + 1][k][lane] - L.gsl[sm][me + 1][k][lane]);
+        }
+        sN = face_gb<Q, H, 1>(G0, gU, t1, ctau, t2, ztau, yN0, yN1, yN2, gbN);
+      }
+      {  // south face (rows r-1, r)
+        T gD[Q];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          if (half_of<Q>(k) != H) continue;
+          gD[k] = L.gsl[s0][me - 1][k][lane];
+          if (ce<Q>(k, 0) != 0) t1[k] = sx0[k] + (shl1(gD[k]) - shr1(gD[k]));
+          if (ce<Q>(k, 2) != 0) t2[k] = dZ[k] + (L.gsl[sp][me - 1][k][lane] - L.gsl[sm][me - 1][k][lane]);
+        }
+        sS = face_gb<Q, H, 1>(gD, G0, t1, ctau, t2, ztau, yS0, yS1, yS2, gbS);
+      }
+      {  // top face (planes z, z+1); the bottom face is the previous plane's top face
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          if (half_of<Q>(k) != H) continue;
+          if (ce<Q>(k, 0) != 0) t1[k] = sx0[k] + (shl1(G1[k]) - shr1(G1[k]));
+          if (ce<Q>(k, 1) != 0) t2[k] = dY[k] + (L.gsl[sp][me + 1][k][lane] - L.gsl[sp][me - 1][k][lane]);
+        }
+        const int zt = z + 2;
+        sT = face_gb<Q, H, 2>(G0, G1, t1, ctau, t2, ytau, (T)zg[zt * kGeo + 0], (T)zg[zt * kGeo + 1],
+                              (T)zg[zt * kGeo + 2], gbT);
+      }
+      put_sum(0, sW);
+      put_sum(1, sN);
+      put_sum(2, sS);
+      put_sum(3, sT);
+    }
+    lds_barrier();   // both halves' sums are in LDS
+    if (inner) {
+      const int zi = z + 1;
+      const T kz = zg[zi * kGeo + 4];
+      T a, bb, fW[Q], fN[Q], fS[Q];
+      sums(0, sW, a, bb);
+      face_out<Q, H, 0>(I, ev, gbW, a, bb, fW);
+      sums(1, sN, a, bb);
+      face_out<Q, H, 1>(I, ev, gbN, a, bb, fN);
+      sums(2, sS, a, bb);
+      face_out<Q, H, 1>(I, ev, gbS, a, bb, fS);
+      sums(3, sT, a, bb);
+      face_out<Q, H, 2>(I, ev, gbT, a, bb, FZt);
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        if (half_of<Q>(k) != H) continue;
+        if (ce<Q>(k, 0) != 0) O[k] = fma((T)(-ce<Q>(k, 0)) * ck, shl1(fW[k]) - fW[k], O[k]);
+        if (ce<Q>(k, 1) != 0) O[k] = fma((T)(-ce<Q>(k, 1)) * ky, fN[k], O[k]);
+        if (ce<Q>(k, 1) != 0) O[k] = fma((T)ce<Q>(k, 1) * ky, fS[k], O[k]);
+        if (ce<Q>(k, 2) != 0) O[k] = fma((T)(-ce<Q>(k, 2)) * kz, FZt[k] - FZb[k], O[k]);
+      }
+    }
+    wait_vm_all();   // the staged plane z+2 is in LDS (and older stores are done)
+    if (live) {
+      unsigned o = (unsigned)(((long long)z * ny + r) * pitch + c) * ES;
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        if (half_of<Q>(k) == H) {
+          if constexpr (WD == 1)
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, O[k]), Rout, o, 0, 0);
+          else
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, O[k]), Rout, o, 0, 0);
+        }
+        o += planeB;
+      }
+    }
+    lds_barrier();   // the next plane overwrites slot sm and reads the staged rows
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      if (half_of<Q>(k) != H) continue;
+      G0[k] = G1[k];
+      O[k] = FT1[k];
+      if (ce<Q>(k, 2) != 0) FZb[k] = FZt[k];
+    }
+  };
+  using R0 = std::integral_constant<int, 0>;
+  using R1 = std::integral_constant<int, 1>;
+  int z = z0;
+  if constexpr (two) {
+    for (; z + 2 <= z1; z += 2) {
+      body(z, R1{});       // (z - z0) even: plane z+1 is in slot 1
+      body(z + 1, R0{});
+    }
+    if (z < z1) body(z, R1{});
+  } else {
+    for (; z < z1; ++z) body(z, R0{});
+  }
+}
+
+template <int Q, int NC, int ROWS, typename T>
+__global__ __launch_bounds__(128 * ROWS) void k_step3p(const Inst3* __restrict__ I, int parity, int planes,
+                                                        int strips, int tiles) {
+  __shared__ LdsP<Q, ROWS, T> L;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int rw = w >> 1;
+  if constexpr (sizeof(T) == 4 && NC <= 4) {
+    __shared__ float ecoef[Q * NC];   // E_i coefficients, read into vector registers
+    if (w == 0)
+      for (int i = threadIdx.x; i < Q * NC; i += kLanes) ecoef[i] = I->ef[i / NC][i % NC];
+    if (w & 1) step3p_half<Q, NC, ROWS, T, 1>(I, parity, planes, strips, tiles, L, ecoef, rw);
+    else step3p_half<Q, NC, ROWS, T, 0>(I, parity, planes, strips, tiles, L, ecoef, rw);
+  } else {
+    if (w & 1) step3p_half<Q, NC, ROWS, T, 1>(I, parity, planes, strips, tiles, L, nullptr, rw);
+    else step3p_half<Q, NC, ROWS, T, 0>(I, parity, planes, strips, tiles, L, nullptr, rw);
+  }
+}
+
 // -------------------------------------------------- init, copies, read-outs
 template <int Q>
 __device__ __forceinline__ void feq64(const Inst3* __restrict__ I, double phi, double* E) {
@@ -832,6 +1282,8 @@ long long step3_blocks(const Inst3& h, const Launch3& l) {
   return strips * tiles * chunks;
 }
 
+static size_t step3h_lds_bytes(int q, const Launch3& l) { return (size_t)3 * (l.rows + 2) * q * kLanes * 8; }
+
 template <int Q, int NC>
 static void step3s_rows(const Inst3* d, int parity, const Launch3& l, int strips, int tiles, dim3 grid,
                         hipStream_t st) {
@@ -839,6 +1291,23 @@ static void step3s_rows(const Inst3* d, int parity, const Launch3& l, int strips
     case 2: hipLaunchKernelGGL((k_step3s<Q, NC, 2>), grid, dim3(128), 0, st, d, parity, l.planes, strips, tiles); break;
     case 3: hipLaunchKernelGGL((k_step3s<Q, NC, 3>), grid, dim3(192), 0, st, d, parity, l.planes, strips, tiles); break;
     default: hipLaunchKernelGGL((k_step3s<Q, NC, 4>), grid, dim3(256), 0, st, d, parity, l.planes, strips, tiles); break;
+  }
+}
+
+template <int Q, int NC, typename T>
+static void step3p_rows(const Inst3* d, int parity, const Launch3& l, int strips, int tiles, dim3 grid,
+                        hipStream_t st) {
+  if constexpr (sizeof(T) == 8) {   // rows 1 and 2 fit the LDS
+    if (l.rows == 1)
+      hipLaunchKernelGGL((k_step3p<Q, NC, 1, T>), grid, dim3(128), 0, st, d, parity, l.planes, strips, tiles);
+    else
+      hipLaunchKernelGGL((k_step3p<Q, NC, 2, T>), grid, dim3(256), 0, st, d, parity, l.planes, strips, tiles);
+  } else {
+    switch (l.rows) {
+      case 2: hipLaunchKernelGGL((k_step3p<Q, NC, 2, T>), grid, dim3(256), 0, st, d, parity, l.planes, strips, tiles); break;
+      case 3: hipLaunchKernelGGL((k_step3p<Q, NC, 3, T>), grid, dim3(384), 0, st, d, parity, l.planes, strips, tiles); break;
+      default: hipLaunchKernelGGL((k_step3p<Q, NC, 4, T>), grid, dim3(512), 0, st, d, parity, l.planes, strips, tiles); break;
+    }
   }
 }
 
@@ -850,8 +1319,22 @@ static int step3_q(const Inst3* d, const Inst3& h, int parity, const Launch3& l,
   if (blocks <= 0 || blocks > 0x7fffffffLL) return -1;
   const dim3 grid((unsigned)blocks);
   const int nc = h.ncoef <= 2 ? 2 : (h.ncoef <= 4 ? 4 : 8);
-  if (h.storage == DUGKS_F64) {
-    const size_t shmem = step3_lds_bytes(h.storage, Q, l);
+  if constexpr (Q != 7) {   // split directions
+    if (h.storage == DUGKS_F64) {
+      switch (nc) {
+        case 2: step3p_rows<Q, 2, double>(d, parity, l, strips, tiles, grid, S(stream)); break;
+        case 4: step3p_rows<Q, 4, double>(d, parity, l, strips, tiles, grid, S(stream)); break;
+        default: step3p_rows<Q, 8, double>(d, parity, l, strips, tiles, grid, S(stream)); break;
+      }
+    } else {
+      switch (nc) {
+        case 2: step3p_rows<Q, 2, float>(d, parity, l, strips, tiles, grid, S(stream)); break;
+        case 4: step3p_rows<Q, 4, float>(d, parity, l, strips, tiles, grid, S(stream)); break;
+        default: step3p_rows<Q, 8, float>(d, parity, l, strips, tiles, grid, S(stream)); break;
+      }
+    }
+  } else if (h.storage == DUGKS_F64) {   // D3Q7: a whole row per wave
+    const size_t shmem = step3h_lds_bytes(Q, l);
     const dim3 block(64 * (l.rows + 2));
     switch (nc) {
       case 2: hipLaunchKernelGGL((k_step3h<Q, DUGKS_F64, 2>), grid, block, shmem, S(stream), d, parity, l.rows, l.planes, strips, tiles); break;
@@ -877,10 +1360,14 @@ int launch_step3(const Inst3* d, const Inst3& h, int parity, const Launch3& l, v
 }
 
 size_t step3_lds_bytes(int storage, int q, const Launch3& l) {
-  // binary64: g of 3 planes x (rows + 2) rows (dynamic); binary32: g of 3
-  // planes and raw f~ of 2 planes x (rows + 2) rows (static)
-  return storage == DUGKS_F64 ? (size_t)3 * (l.rows + 2) * q * kLanes * 8
-                              : (size_t)5 * (l.rows + 2) * q * kLanes * 4;
+  if (q == 7)   // binary64: g of 3 planes (dynamic); binary32: g of 3 planes and f~ of 2
+    return storage == DUGKS_F64 ? step3h_lds_bytes(q, l) : (size_t)5 * (l.rows + 2) * q * kLanes * 4;
+  // g of 3 planes and staged f~ of 1 (binary64) or 2 (binary32) planes, each
+  // of rows + 2 rows, and the halves' sums of 4 faces per row (static; the
+  // binary32 E coefficients aside)
+  const size_t e = storage == DUGKS_F64 ? 8 : 4;
+  const size_t planes = storage == DUGKS_F64 ? 4 : 5;
+  return planes * (l.rows + 2) * q * kLanes * e + (size_t)4 * l.rows * 2 * kLanes * e;
 }
 
 #define DUGKS3_PER_CELL(KERNEL, ...)                                                               \
