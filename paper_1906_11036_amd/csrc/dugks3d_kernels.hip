@@ -779,18 +779,27 @@ __device__ __forceinline__ void face_out(const Inst3* __restrict__ I, const EQ& 
     if (half_of<Q>(k) == H && ce<Q>(k, A) != 0) out[k] = fma(rb, gb[k], E(k, pb));
 }
 
+// LDS bytes of a block with ns staging slots (E coefficients aside)
+template <int Q, int ROWS, typename T> constexpr int lds_p_bytes(int ns) {
+  return (3 + ns) * (ROWS + 2) * Q * kLanes * (int)sizeof(T) + 4 * ROWS * 2 * kLanes * (int)sizeof(T);
+}
 template <int Q, int ROWS, typename T> struct LdsP {
   static constexpr int W = ROWS + 2;             // LDS rows: y0-1 .. y0+ROWS
   static constexpr int WD = sizeof(T) / 4;       // words per element
-  static constexpr int NS = WD == 1 ? 2 : 1;     // staging slots
+  // staging slots: binary32 two, unless one slot lets two blocks share a
+  // CU's 160 KiB where two slots would not; binary64 one
+  static constexpr int NS = WD == 2 ? 1
+                            : (lds_p_bytes<Q, ROWS, T>(2) > 81920 && lds_p_bytes<Q, ROWS, T>(1) <= 81920) ? 1 : 2;
+  // E coefficients in vector registers (from LDS) with two slots
+  static constexpr bool kVecE = WD == 1 && NS == 2;
   T gsl[3][W][Q][kLanes];                        // g of plane p in slot (p - z0) mod 3
   unsigned raw[NS][W][Q][WD][kLanes];            // staged f~, binary64 as low and high words
   T psum[4][ROWS][2][kLanes];                    // the halves' interface-g sums of four faces
 };
 
-// One wave: row rw of the tile, directions of half H.  Binary32 stages plane
-// z+2 into the second slot while plane z+1 is read from the first; binary64
-// has one slot, refilled once every wave has read it.
+// One wave: row rw of the tile, directions of half H.  With two slots plane
+// z+2 is staged into the second while plane z+1 is read from the first; one
+// slot is refilled once every wave has read it.
 template <int Q, int NC, int ROWS, typename T, int H>
 __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int parity, int planes, int strips,
                                             int tiles, LdsP<Q, ROWS, T>& L, const float* ecoef, int rw) {
@@ -799,7 +808,7 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
   constexpr int NW = 2 * ROWS;                   // waves per block
   constexpr int HX = (2 * Q + NW - 1) / NW;      // halo-row loads per wave
   constexpr unsigned ES = sizeof(T);
-  constexpr bool kVecE = sizeof(T) == 4 && NC <= 4;
+  constexpr bool kVecE = LP::kVecE && NC <= 4;
   const int w = 2 * rw + H;
   const int lane = threadIdx.x & 63;
   int b = xcd_contiguous(blockIdx.x, gridDim.x);
@@ -1135,7 +1144,7 @@ __global__ __launch_bounds__(128 * ROWS) void k_step3p(const Inst3* __restrict__
   __shared__ LdsP<Q, ROWS, T> L;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int rw = w >> 1;
-  if constexpr (sizeof(T) == 4 && NC <= 4) {
+  if constexpr (LdsP<Q, ROWS, T>::kVecE && NC <= 4) {
     __shared__ float ecoef[Q * NC];   // E_i coefficients, read into vector registers
     if (w == 0)
       for (int i = threadIdx.x; i < Q * NC; i += kLanes) ecoef[i] = I->ef[i / NC][i % NC];
@@ -1362,12 +1371,13 @@ int launch_step3(const Inst3* d, const Inst3& h, int parity, const Launch3& l, v
 size_t step3_lds_bytes(int storage, int q, const Launch3& l) {
   if (q == 7)   // binary64: g of 3 planes (dynamic); binary32: g of 3 planes and f~ of 2
     return storage == DUGKS_F64 ? step3h_lds_bytes(q, l) : (size_t)5 * (l.rows + 2) * q * kLanes * 4;
-  // g of 3 planes and staged f~ of 1 (binary64) or 2 (binary32) planes, each
-  // of rows + 2 rows, and the halves' sums of 4 faces per row (static; the
-  // binary32 E coefficients aside)
+  // g of 3 planes and staged f~ of 1 or 2 planes (LdsP), each of rows + 2
+  // rows, and the halves' sums of 4 faces per row (static; the binary32 E
+  // coefficients aside)
   const size_t e = storage == DUGKS_F64 ? 8 : 4;
-  const size_t planes = storage == DUGKS_F64 ? 4 : 5;
-  return planes * (l.rows + 2) * q * kLanes * e + (size_t)4 * l.rows * 2 * kLanes * e;
+  auto bytes = [&](size_t ns) { return (3 + ns) * (l.rows + 2) * q * kLanes * e + (size_t)4 * l.rows * 2 * kLanes * e; };
+  if (storage == DUGKS_F64) return bytes(1);
+  return (bytes(2) > 81920 && bytes(1) <= 81920) ? bytes(1) : bytes(2);
 }
 
 #define DUGKS3_PER_CELL(KERNEL, ...)                                                               \
