@@ -65,10 +65,11 @@ def test_launch_shapes_give_identical_results(launch):
     assert np.array_equal(s.get_f(), ref.get_f())
 
 
+@pytest.mark.parametrize("q", [15, 19, 7])
 @pytest.mark.parametrize("launch", [(1, 1), (1, 4), (2, 2), (2, 32)])
-def test_fp64_launch_shapes_give_identical_results(launch):
+def test_fp64_launch_shapes_give_identical_results(launch, q):
     """binary64: tiles of 1 or 2 interior rows and chunks of 1..32 planes, bitwise the same."""
-    p = W.random_problem3d(78, 66, 5, 7, q=15, bc=(M, P, M), stretched=True, bdeg=2)
+    p = W.random_problem3d(78, 66, 5, 7, q=q, bc=(M, P, M), stretched=True, bdeg=2)
     ref = solver(p, "f64", (2, 32))
     ref.set_phi(p.phi0)
     ref.step(3)
@@ -90,6 +91,31 @@ def test_fp32_against_oracle(q):
     ref = o.get_phi()
     err = float(np.sqrt(((s.get_phi() - ref) ** 2).sum() / (ref ** 2).sum()))
     say(f"  3d f32 q={q}: rel-L2 {err:.2e} (bound {2 * steps * EPS32:.2e})")
+    assert err <= 2 * steps * EPS32
+
+
+@pytest.mark.parametrize("q", [19, 15, 7])
+def test_high_degree_3d(q):
+    """B of degree 4 (so C of degree 7: eight coefficients per equilibrium
+    polynomial), mirror walls on x and z, stretched mesh: binary64 to 1e-12 and
+    binary32 within the rounding bound, against the oracle."""
+    p = W.random_problem3d(950 + q, 67, 6, 5, q=q, bc=(M, P, M), stretched=True, bdeg=4, ddeg=3)
+    steps = 10
+    say(f"case 3d degree 4 q={q}")
+    o = Oracle3D(p)
+    o.step(steps)
+    fo = o.get_f()
+    s = solver(p, "f64")
+    s.set_phi(p.phi0)
+    s.step(steps)
+    assert np.abs(s.get_f() - fo).max() <= 1e-12 * np.abs(fo).max()
+    s.close()
+    s = solver(p, "f32")
+    s.set_phi(p.phi0)
+    s.step(steps)
+    ref = o.get_phi()
+    err = float(np.sqrt(((s.get_phi() - ref) ** 2).sum() / (ref ** 2).sum()))
+    say(f"  binary32 rel-L2 {err:.2e} (bound {2 * steps * EPS32:.2e})")
     assert err <= 2 * steps * EPS32
 
 
