@@ -720,7 +720,7 @@ template <int Q, int H> __host__ __device__ constexpr int half_count() {
   return n;
 }
 
-// sum over this half's directions: in order in binary64, pairwise in binary32
+// pairwise sum over this half's directions (short dependency chains)
 template <int Q, int H, typename T> __device__ __forceinline__ T half_sum(const T* v) {
   constexpr int N = half_count<Q, H>();
   T t[N];
@@ -728,18 +728,11 @@ template <int Q, int H, typename T> __device__ __forceinline__ T half_sum(const 
 #pragma unroll
   for (int k = 0; k < Q; ++k)
     if (half_of<Q>(k) == H) t[n++] = v[k];
-  if constexpr (sizeof(T) == 8) {
-    T s = t[0];
 #pragma unroll
-    for (int j = 1; j < N; ++j) s += t[j];
-    return s;
-  } else {
+  for (int w = 1; w < N; w *= 2)
 #pragma unroll
-    for (int w = 1; w < N; w *= 2)
-#pragma unroll
-      for (int j = 0; j + w < N; j += 2 * w) t[j] += t[j + w];
-    return t[0];
-  }
+    for (int j = 0; j + w < N; j += 2 * w) t[j] += t[j + w];
+  return t[0];
 }
 
 template <int Q, int H, typename T> __device__ __forceinline__ void mirror_half(T* g, int a) {
@@ -800,7 +793,7 @@ template <int Q, int ROWS, typename T> struct LdsP {
 // One wave: row rw of the tile, directions of half H.  With two slots plane
 // z+2 is staged into the second while plane z+1 is read from the first; one
 // slot is refilled once every wave has read it.
-template <int Q, int NC, int ROWS, typename T, int H>
+template <int Q, int NC, int ROWS, typename T, int H, bool WALLS>
 __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int parity, int planes, int strips,
                                             int tiles, LdsP<Q, ROWS, T>& L, const float* ecoef, int rw) {
   using LP = LdsP<Q, ROWS, T>;
@@ -897,20 +890,29 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
   };
   // g = fbar+ / b1 (eq. 2.21 over b1) of this half's directions; phi (binary64) from all of them
   auto make_g = [&](int slot, int row, bool wy, int zp, T* g, T* f) __attribute__((always_inline)) {
-    double phi = 0.0;
+    // binary64: four chains, then a pairwise combine (one wave per SIMD
+    // waits out every link of a chain); binary32: one chain
+    constexpr int NA = WD == 2 ? 4 : 1;
+    double acc[NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) acc[a] = 0.0;
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
       const T v = raw_at(slot, row, k);
-      phi += (double)v;
+      acc[k % NA] += (double)v;
       if (half_of<Q>(k) == H) f[k] = v;
     }
+    double phi = acc[0];
+    if constexpr (NA == 4) phi = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     const T p = (T)phi, ra = C3<T>::ra(I);
 #pragma unroll
     for (int k = 0; k < Q; ++k)
       if (half_of<Q>(k) == H) g[k] = fma(ra, f[k], ev(k, p));
-    if (wall_x) mirror_half<Q, H, T>(g, 0);
-    if (wy) mirror_half<Q, H, T>(g, 1);
-    if ((zp < 0 || zp >= nz) && bcz != DUGKS_BC_PERIODIC) mirror_half<Q, H, T>(g, 2);
+    if constexpr (WALLS) {
+      if (wall_x) mirror_half<Q, H, T>(g, 0);
+      if (wy) mirror_half<Q, H, T>(g, 1);
+      if ((zp < 0 || zp >= nz) && bcz != DUGKS_BC_PERIODIC) mirror_half<Q, H, T>(g, 2);
+    }
   };
   auto publish = [&](int slot, int row, const T* g) __attribute__((always_inline)) {
 #pragma unroll
@@ -1079,7 +1081,10 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
       put_sum(2, sS);
       put_sum(3, sT);
     }
-    lds_barrier();   // both halves' sums are in LDS
+    wait_vm_all();   // this wave's loads of plane z+2 (and its older stores) are done
+    // both halves' sums and the whole staged plane z+2 are in LDS; slot sm
+    // (read only above) is free for the next plane's g
+    lds_barrier();
     if (inner) {
       const int zi = z + 1;
       const T kz = zg[zi * kGeo + 4];
@@ -1101,7 +1106,6 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
         if (ce<Q>(k, 2) != 0) O[k] = fma((T)(-ce<Q>(k, 2)) * kz, FZt[k] - FZb[k], O[k]);
       }
     }
-    wait_vm_all();   // the staged plane z+2 is in LDS (and older stores are done)
     if (live) {
       unsigned o = (unsigned)(((long long)z * ny + r) * pitch + c) * ES;
 #pragma unroll
@@ -1115,7 +1119,8 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
         o += planeB;
       }
     }
-    lds_barrier();   // the next plane overwrites slot sm and reads the staged rows
+    // no third barrier: the next plane's first barrier separates these reads
+    // of the sums from its writes of them
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
       if (half_of<Q>(k) != H) continue;
@@ -1138,7 +1143,8 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
   }
 }
 
-template <int Q, int NC, int ROWS, typename T>
+// WALLS = false: every axis periodic, no mirror code
+template <int Q, int NC, int ROWS, typename T, bool WALLS>
 __global__ __launch_bounds__(128 * ROWS) void k_step3p(const Inst3* __restrict__ I, int parity, int planes,
                                                         int strips, int tiles) {
   __shared__ LdsP<Q, ROWS, T> L;
@@ -1148,11 +1154,11 @@ __global__ __launch_bounds__(128 * ROWS) void k_step3p(const Inst3* __restrict__
     __shared__ float ecoef[Q * NC];   // E_i coefficients, read into vector registers
     if (w == 0)
       for (int i = threadIdx.x; i < Q * NC; i += kLanes) ecoef[i] = I->ef[i / NC][i % NC];
-    if (w & 1) step3p_half<Q, NC, ROWS, T, 1>(I, parity, planes, strips, tiles, L, ecoef, rw);
-    else step3p_half<Q, NC, ROWS, T, 0>(I, parity, planes, strips, tiles, L, ecoef, rw);
+    if (w & 1) step3p_half<Q, NC, ROWS, T, 1, WALLS>(I, parity, planes, strips, tiles, L, ecoef, rw);
+    else step3p_half<Q, NC, ROWS, T, 0, WALLS>(I, parity, planes, strips, tiles, L, ecoef, rw);
   } else {
-    if (w & 1) step3p_half<Q, NC, ROWS, T, 1>(I, parity, planes, strips, tiles, L, nullptr, rw);
-    else step3p_half<Q, NC, ROWS, T, 0>(I, parity, planes, strips, tiles, L, nullptr, rw);
+    if (w & 1) step3p_half<Q, NC, ROWS, T, 1, WALLS>(I, parity, planes, strips, tiles, L, nullptr, rw);
+    else step3p_half<Q, NC, ROWS, T, 0, WALLS>(I, parity, planes, strips, tiles, L, nullptr, rw);
   }
 }
 
@@ -1303,21 +1309,30 @@ static void step3s_rows(const Inst3* d, int parity, const Launch3& l, int strips
   }
 }
 
-template <int Q, int NC, typename T>
-static void step3p_rows(const Inst3* d, int parity, const Launch3& l, int strips, int tiles, dim3 grid,
-                        hipStream_t st) {
+template <int Q, int NC, typename T, bool WALLS>
+static void step3p_launch(const Inst3* d, int parity, const Launch3& l, int strips, int tiles, dim3 grid,
+                          hipStream_t st) {
   if constexpr (sizeof(T) == 8) {   // rows 1 and 2 fit the LDS
     if (l.rows == 1)
-      hipLaunchKernelGGL((k_step3p<Q, NC, 1, T>), grid, dim3(128), 0, st, d, parity, l.planes, strips, tiles);
+      hipLaunchKernelGGL((k_step3p<Q, NC, 1, T, WALLS>), grid, dim3(128), 0, st, d, parity, l.planes, strips, tiles);
     else
-      hipLaunchKernelGGL((k_step3p<Q, NC, 2, T>), grid, dim3(256), 0, st, d, parity, l.planes, strips, tiles);
+      hipLaunchKernelGGL((k_step3p<Q, NC, 2, T, WALLS>), grid, dim3(256), 0, st, d, parity, l.planes, strips, tiles);
   } else {
     switch (l.rows) {
-      case 2: hipLaunchKernelGGL((k_step3p<Q, NC, 2, T>), grid, dim3(256), 0, st, d, parity, l.planes, strips, tiles); break;
-      case 3: hipLaunchKernelGGL((k_step3p<Q, NC, 3, T>), grid, dim3(384), 0, st, d, parity, l.planes, strips, tiles); break;
-      default: hipLaunchKernelGGL((k_step3p<Q, NC, 4, T>), grid, dim3(512), 0, st, d, parity, l.planes, strips, tiles); break;
+      case 2: hipLaunchKernelGGL((k_step3p<Q, NC, 2, T, WALLS>), grid, dim3(256), 0, st, d, parity, l.planes, strips, tiles); break;
+      case 3: hipLaunchKernelGGL((k_step3p<Q, NC, 3, T, WALLS>), grid, dim3(384), 0, st, d, parity, l.planes, strips, tiles); break;
+      default: hipLaunchKernelGGL((k_step3p<Q, NC, 4, T, WALLS>), grid, dim3(512), 0, st, d, parity, l.planes, strips, tiles); break;
     }
   }
+}
+// the wall-free instantiation for degrees below 4 (eight coefficients always
+// take the general one)
+template <int Q, int NC, typename T>
+static void step3p_rows(const Inst3* d, const Inst3& h, int parity, const Launch3& l, int strips, int tiles,
+                        dim3 grid, hipStream_t st) {
+  const bool walls = h.bc[0] != DUGKS_BC_PERIODIC || h.bc[1] != DUGKS_BC_PERIODIC || h.bc[2] != DUGKS_BC_PERIODIC;
+  if (NC == 8 || walls) step3p_launch<Q, NC, T, true>(d, parity, l, strips, tiles, grid, st);
+  else if constexpr (NC != 8) step3p_launch<Q, NC, T, false>(d, parity, l, strips, tiles, grid, st);
 }
 
 template <int Q>
@@ -1331,15 +1346,15 @@ static int step3_q(const Inst3* d, const Inst3& h, int parity, const Launch3& l,
   if constexpr (Q != 7) {   // split directions
     if (h.storage == DUGKS_F64) {
       switch (nc) {
-        case 2: step3p_rows<Q, 2, double>(d, parity, l, strips, tiles, grid, S(stream)); break;
-        case 4: step3p_rows<Q, 4, double>(d, parity, l, strips, tiles, grid, S(stream)); break;
-        default: step3p_rows<Q, 8, double>(d, parity, l, strips, tiles, grid, S(stream)); break;
+        case 2: step3p_rows<Q, 2, double>(d, h, parity, l, strips, tiles, grid, S(stream)); break;
+        case 4: step3p_rows<Q, 4, double>(d, h, parity, l, strips, tiles, grid, S(stream)); break;
+        default: step3p_rows<Q, 8, double>(d, h, parity, l, strips, tiles, grid, S(stream)); break;
       }
     } else {
       switch (nc) {
-        case 2: step3p_rows<Q, 2, float>(d, parity, l, strips, tiles, grid, S(stream)); break;
-        case 4: step3p_rows<Q, 4, float>(d, parity, l, strips, tiles, grid, S(stream)); break;
-        default: step3p_rows<Q, 8, float>(d, parity, l, strips, tiles, grid, S(stream)); break;
+        case 2: step3p_rows<Q, 2, float>(d, h, parity, l, strips, tiles, grid, S(stream)); break;
+        case 4: step3p_rows<Q, 4, float>(d, h, parity, l, strips, tiles, grid, S(stream)); break;
+        default: step3p_rows<Q, 8, float>(d, h, parity, l, strips, tiles, grid, S(stream)); break;
       }
     }
   } else if (h.storage == DUGKS_F64) {   // D3Q7: a whole row per wave

@@ -65,6 +65,21 @@ def test_launch_shapes_give_identical_results(launch):
     assert np.array_equal(s.get_f(), ref.get_f())
 
 
+@pytest.mark.parametrize("storage,launch", [("f32", (2, 1)), ("f32", (3, 7)), ("f32", (4, 3)),
+                                            ("f64", (1, 4)), ("f64", (2, 5))])
+@pytest.mark.parametrize("q", [19, 15])
+def test_periodic_launch_shapes_give_identical_results(storage, launch, q):
+    """All axes periodic (the instantiation without mirror code): launch shapes bitwise the same."""
+    p = W.random_problem3d(79, 67, 7, 9, q=q, bc=(P, P, P), bdeg=2)
+    ref = solver(p, storage, (4, 32) if storage == "f32" else (2, 32))
+    ref.set_phi(p.phi0)
+    ref.step(3)
+    s = solver(p, storage, launch)
+    s.set_phi(p.phi0)
+    s.step(3)
+    assert np.array_equal(s.get_f(), ref.get_f())
+
+
 @pytest.mark.parametrize("q", [15, 19, 7])
 @pytest.mark.parametrize("launch", [(1, 1), (1, 4), (2, 2), (2, 32)])
 def test_fp64_launch_shapes_give_identical_results(launch, q):
