@@ -308,14 +308,14 @@ int dugks3_create(dugks3_ctx** out, int nx, int ny, int nz, const double* xf, co
   x->total = off;
   // default launch (fastest measured at 256^3): binary64 two rows; binary32
   // four rows (D3Q15: two, which lets two blocks share a CU); 64 planes a
-  // block (D3Q7: 32)
+  // block (D3Q7: 32; D3Q15 and D3Q19 in binary64: 128)
   x->launch.rows = p->storage == DUGKS_F64 ? 2 : (q == 15 ? 2 : 4);
   // shorter chunks on small grids until there are at least two blocks per CU
   // of a 256-CU device (a chunk restages two halo planes; 64^3: 233 -> 42 us
   // a step, 128^3: 240 -> 193 us)
   {
     const long long strips = (nx + kCols - 1) / kCols, tiles = (ny + x->launch.rows - 1) / x->launch.rows;
-    int planes = q == 7 ? 32 : 64;
+    int planes = q == 7 ? 32 : (p->storage == DUGKS_F64 ? 128 : 64);
     while (planes > 4 && strips * tiles * ((nz + planes - 1) / planes) < 512) planes /= 2;
     x->launch.planes = planes;
   }

@@ -227,7 +227,7 @@ extern __shared__ __align__(16) unsigned char dugks3_lds[];
 // then a second barrier protects the slot the next plane overwrites.  At most
 // 2 interior rows (4 waves): a wave may hold the whole register file of its
 // SIMD.
-template <int Q, int ST, int NC>
+template <int Q, int ST, int NC, bool WALLS>
 __global__ __launch_bounds__(256) void k_step3h(const Inst3* __restrict__ I, int parity, int rows,
                                                int planes, int strips, int tiles) {
   using T = typename S3<ST>::T;
@@ -275,9 +275,11 @@ __global__ __launch_bounds__(256) void k_step3h(const Inst3* __restrict__ I, int
   };
   auto make_g = [&](const T* f, int zp, T* g) {
     cell_g3<Q, T>(I, EqScalar<NC, T>{I}, f, g);
-    if (wall_x) mirror<Q, T>(g, 0);
-    if (wall_y) mirror<Q, T>(g, 1);
-    if ((zp < 0 || zp >= nz) && bcz != DUGKS_BC_PERIODIC) mirror<Q, T>(g, 2);
+    if constexpr (WALLS) {
+      if (wall_x) mirror<Q, T>(g, 0);
+      if (wall_y) mirror<Q, T>(g, 1);
+      if ((zp < 0 || zp >= nz) && bcz != DUGKS_BC_PERIODIC) mirror<Q, T>(g, 2);
+    }
   };
   auto lds_at = [&](int slot, int row, int k) -> T* {
     return lds + ((long long)(slot * W + row) * Q + k) * kLanes + lane;
@@ -454,7 +456,7 @@ __device__ __forceinline__ void wait_vm_all() {
   asm volatile("" ::: "memory");
 }
 
-template <int Q, int NC, int ROWS>
+template <int Q, int NC, int ROWS, bool WALLS>
 __global__ __launch_bounds__(64 * ROWS) void k_step3s(const Inst3* __restrict__ I, int parity, int planes,
                                                        int strips, int tiles) {
   constexpr int W = ROWS + 2;                 // LDS rows: y0-1 .. y0+ROWS
@@ -543,9 +545,11 @@ __global__ __launch_bounds__(64 * ROWS) void k_step3s(const Inst3* __restrict__ 
 #pragma unroll
     for (int k = 0; k < Q; ++k) f[k] = raw[row][k][lane];
     cell_g3<Q, float>(I, ev, f, g);
-    if (wall_x) mirror<Q, float>(g, 0);
-    if (wy) mirror<Q, float>(g, 1);
-    if ((zp < 0 || zp >= nz) && bcz != DUGKS_BC_PERIODIC) mirror<Q, float>(g, 2);
+    if constexpr (WALLS) {
+      if (wall_x) mirror<Q, float>(g, 0);
+      if (wy) mirror<Q, float>(g, 1);
+      if ((zp < 0 || zp >= nz) && bcz != DUGKS_BC_PERIODIC) mirror<Q, float>(g, 2);
+    }
   };
   auto publish = [&](int slot, int row, const float* g) __attribute__((always_inline)) {
 #pragma unroll
@@ -1299,13 +1303,32 @@ long long step3_blocks(const Inst3& h, const Launch3& l) {
 
 static size_t step3h_lds_bytes(int q, const Launch3& l) { return (size_t)3 * (l.rows + 2) * q * kLanes * 8; }
 
-template <int Q, int NC>
+template <int Q, int NC, bool WALLS>
 static void step3s_rows(const Inst3* d, int parity, const Launch3& l, int strips, int tiles, dim3 grid,
                         hipStream_t st) {
   switch (l.rows) {
-    case 2: hipLaunchKernelGGL((k_step3s<Q, NC, 2>), grid, dim3(128), 0, st, d, parity, l.planes, strips, tiles); break;
-    case 3: hipLaunchKernelGGL((k_step3s<Q, NC, 3>), grid, dim3(192), 0, st, d, parity, l.planes, strips, tiles); break;
-    default: hipLaunchKernelGGL((k_step3s<Q, NC, 4>), grid, dim3(256), 0, st, d, parity, l.planes, strips, tiles); break;
+    case 2: hipLaunchKernelGGL((k_step3s<Q, NC, 2, WALLS>), grid, dim3(128), 0, st, d, parity, l.planes, strips, tiles); break;
+    case 3: hipLaunchKernelGGL((k_step3s<Q, NC, 3, WALLS>), grid, dim3(192), 0, st, d, parity, l.planes, strips, tiles); break;
+    default: hipLaunchKernelGGL((k_step3s<Q, NC, 4, WALLS>), grid, dim3(256), 0, st, d, parity, l.planes, strips, tiles); break;
+  }
+}
+template <int Q, int NC, bool WALLS>
+static void step3h_launch(const Inst3* d, const Inst3& h, int parity, const Launch3& l, int strips, int tiles,
+                          dim3 grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_step3h<Q, DUGKS_F64, NC, WALLS>), grid, dim3(64 * (l.rows + 2)), step3h_lds_bytes(Q, l),
+                     st, d, parity, l.rows, l.planes, strips, tiles);
+}
+// D3Q7, one wave a row: the wall-free instantiation for degrees below 4
+template <int Q, int NC>
+static void step3_row_waves(const Inst3* d, const Inst3& h, int parity, const Launch3& l, int strips,
+                            int tiles, dim3 grid, hipStream_t st) {
+  const bool walls = h.bc[0] != DUGKS_BC_PERIODIC || h.bc[1] != DUGKS_BC_PERIODIC || h.bc[2] != DUGKS_BC_PERIODIC;
+  if (h.storage == DUGKS_F64) {
+    if (NC == 8 || walls) step3h_launch<Q, NC, true>(d, h, parity, l, strips, tiles, grid, st);
+    else if constexpr (NC != 8) step3h_launch<Q, NC, false>(d, h, parity, l, strips, tiles, grid, st);
+  } else {
+    if (NC == 8 || walls) step3s_rows<Q, NC, true>(d, parity, l, strips, tiles, grid, st);
+    else if constexpr (NC != 8) step3s_rows<Q, NC, false>(d, parity, l, strips, tiles, grid, st);
   }
 }
 
@@ -1357,19 +1380,11 @@ static int step3_q(const Inst3* d, const Inst3& h, int parity, const Launch3& l,
         default: step3p_rows<Q, 8, float>(d, h, parity, l, strips, tiles, grid, S(stream)); break;
       }
     }
-  } else if (h.storage == DUGKS_F64) {   // D3Q7: a whole row per wave
-    const size_t shmem = step3h_lds_bytes(Q, l);
-    const dim3 block(64 * (l.rows + 2));
+  } else {   // D3Q7: a whole row per wave
     switch (nc) {
-      case 2: hipLaunchKernelGGL((k_step3h<Q, DUGKS_F64, 2>), grid, block, shmem, S(stream), d, parity, l.rows, l.planes, strips, tiles); break;
-      case 4: hipLaunchKernelGGL((k_step3h<Q, DUGKS_F64, 4>), grid, block, shmem, S(stream), d, parity, l.rows, l.planes, strips, tiles); break;
-      default: hipLaunchKernelGGL((k_step3h<Q, DUGKS_F64, 8>), grid, block, shmem, S(stream), d, parity, l.rows, l.planes, strips, tiles); break;
-    }
-  } else {
-    switch (nc) {
-      case 2: step3s_rows<Q, 2>(d, parity, l, strips, tiles, grid, S(stream)); break;
-      case 4: step3s_rows<Q, 4>(d, parity, l, strips, tiles, grid, S(stream)); break;
-      default: step3s_rows<Q, 8>(d, parity, l, strips, tiles, grid, S(stream)); break;
+      case 2: step3_row_waves<Q, 2>(d, h, parity, l, strips, tiles, grid, S(stream)); break;
+      case 4: step3_row_waves<Q, 4>(d, h, parity, l, strips, tiles, grid, S(stream)); break;
+      default: step3_row_waves<Q, 8>(d, h, parity, l, strips, tiles, grid, S(stream)); break;
     }
   }
   return hipGetLastError() == hipSuccess ? 0 : -1;

@@ -32,7 +32,7 @@ CASES = [
     (1, 1, 1, 19, (P, P, P)), (5, 4, 3, 19, (P, P, P)), (62, 3, 4, 19, (M, P, M)),
     (63, 5, 2, 19, (P, M, P)), (64, 2, 7, 15, (P, P, P)), (65, 4, 5, 15, (M, M, M)),
     (130, 3, 3, 19, (P, P, P)), (17, 9, 11, 19, (M, P, P)), (9, 7, 6, 7, (P, M, P)),
-    (70, 6, 4, 7, (M, M, M)),
+    (70, 6, 4, 7, (M, M, M)), (33, 5, 4, 7, (P, P, P)),
 ]
 
 
@@ -67,7 +67,7 @@ def test_launch_shapes_give_identical_results(launch):
 
 @pytest.mark.parametrize("storage,launch", [("f32", (2, 1)), ("f32", (3, 7)), ("f32", (4, 3)),
                                             ("f64", (1, 4)), ("f64", (2, 5))])
-@pytest.mark.parametrize("q", [19, 15])
+@pytest.mark.parametrize("q", [19, 15, 7])
 def test_periodic_launch_shapes_give_identical_results(storage, launch, q):
     """All axes periodic (the instantiation without mirror code): launch shapes bitwise the same."""
     p = W.random_problem3d(79, 67, 7, 9, q=q, bc=(P, P, P), bdeg=2)
