@@ -2,7 +2,7 @@
 // (eq. 2.28), D3Q19 (eq. 2.6) and D3Q7 (Remark 3).
 //
 // Fused step: a block owns a strip of 62 columns (64 lanes: one halo column
-// each side), a tile of rows (one wave per row) and a chunk of planes, which
+// each side), a tile of rows (one or two waves per row) and a chunk of planes, which
 // it sweeps in z, with g of three planes of its rows and the two halo rows in
 // LDS.  Per plane and cell it computes the west face (x; the east face is the
 // next lane's west face), both y faces and the top face (z; the bottom face is
@@ -1318,7 +1318,8 @@ static void step3h_launch(const Inst3* d, const Inst3& h, int parity, const Laun
   hipLaunchKernelGGL((k_step3h<Q, DUGKS_F64, NC, WALLS>), grid, dim3(64 * (l.rows + 2)), step3h_lds_bytes(Q, l),
                      st, d, parity, l.rows, l.planes, strips, tiles);
 }
-// D3Q7, one wave a row: the wall-free instantiation for degrees below 4
+// D3Q7, one wave a row: the wall-free instantiation when every axis is
+// periodic and the equilibrium polynomials have at most 4 coefficients
 template <int Q, int NC>
 static void step3_row_waves(const Inst3* d, const Inst3& h, int parity, const Launch3& l, int strips,
                             int tiles, dim3 grid, hipStream_t st) {
@@ -1348,8 +1349,8 @@ static void step3p_launch(const Inst3* d, int parity, const Launch3& l, int stri
     }
   }
 }
-// the wall-free instantiation for degrees below 4 (eight coefficients always
-// take the general one)
+// the wall-free instantiation when every axis is periodic and the
+// equilibrium polynomials have at most 4 coefficients
 template <int Q, int NC, typename T>
 static void step3p_rows(const Inst3* d, const Inst3& h, int parity, const Launch3& l, int strips, int tiles,
                         dim3 grid, hipStream_t st) {
