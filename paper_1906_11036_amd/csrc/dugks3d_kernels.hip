@@ -718,45 +718,84 @@ template <int Q> __host__ __device__ constexpr int half_of(int k) {
   if (Q == 15) return nnz == 3 ? 1 : 0;                              // 7 + 8
   return (x == 0 && nnz == 1) ? 1 : 0;                               // 3 + 4
 }
-template <int Q, int H> __host__ __device__ constexpr int half_count() {
+// D3Q19 in binary32 with 3 or more rows splits each row four ways: {rest,
+// (+-1,+-1,0)}, {(+-1,0,+-1)}, {(0,+-1,+-1)}, {axis directions}; otherwise
+// in halves
+template <int Q, typename T, int ROWS> constexpr int parts() {
+  return (Q == 19 && sizeof(T) == 4 && ROWS >= 3) ? 4 : 2;
+}
+template <int Q, int P> __host__ __device__ constexpr int part_of(int k) {
+  if (P == 2) return half_of<Q>(k);
+  const int x = ce<Q>(k, 0), y = ce<Q>(k, 1), z = ce<Q>(k, 2);
+  const int nnz = (x != 0) + (y != 0) + (z != 0);
+  if (nnz <= 1) return nnz == 0 ? 0 : 3;
+  return z == 0 ? 0 : (y == 0 ? 1 : 2);
+}
+template <int Q, int P, int H> __host__ __device__ constexpr int part_count() {
   int n = 0;
-  for (int k = 0; k < Q; ++k) n += half_of<Q>(k) == H;
+  for (int k = 0; k < Q; ++k) n += part_of<Q, P>(k) == H;
   return n;
 }
 
-// pairwise sum over this half's directions (short dependency chains)
-template <int Q, int H, typename T> __device__ __forceinline__ T half_sum(const T* v) {
-  constexpr int N = half_count<Q, H>();
+// pairwise sum over the directions d with sel(d) (short dependency chains)
+template <int Q, int N, typename T, typename SEL> __device__ __forceinline__ T sel_sum(const T* v, SEL sel) {
   T t[N];
   int n = 0;
 #pragma unroll
   for (int k = 0; k < Q; ++k)
-    if (half_of<Q>(k) == H) t[n++] = v[k];
+    if (sel(k)) t[n++] = v[k];
 #pragma unroll
   for (int w = 1; w < N; w *= 2)
 #pragma unroll
     for (int j = 0; j + w < N; j += 2 * w) t[j] += t[j + w];
   return t[0];
 }
+// Sum over this part's directions.  D3Q19 sums each of its four quarters
+// pairwise, a half being quarters 0 + 1 or 2 + 3, so that the total over the
+// parts, (q0 + q1) + (q2 + q3), is the same for two and for four parts.
+template <int Q, int P, int H, typename T> __device__ __forceinline__ T part_sum(const T* v) {
+  if constexpr (Q == 19) {
+    auto quarter = [&](auto jc) __attribute__((always_inline)) -> T {
+      constexpr int J = decltype(jc)::value;
+      return sel_sum<Q, part_count<Q, 4, J>()>(v, [](int k) { return part_of<Q, 4>(k) == J; });
+    };
+    using J0 = std::integral_constant<int, 0>;
+    using J1 = std::integral_constant<int, 1>;
+    using J2 = std::integral_constant<int, 2>;
+    using J3 = std::integral_constant<int, 3>;
+    if constexpr (P == 4) {
+      if constexpr (H == 0) return quarter(J0{});
+      else if constexpr (H == 1) return quarter(J1{});
+      else if constexpr (H == 2) return quarter(J2{});
+      else return quarter(J3{});
+    } else if constexpr (H == 0) {
+      return quarter(J0{}) + quarter(J1{});
+    } else {
+      return quarter(J2{}) + quarter(J3{});
+    }
+  } else {
+    return sel_sum<Q, part_count<Q, P, H>()>(v, [](int k) { return part_of<Q, P>(k) == H; });
+  }
+}
 
-template <int Q, int H, typename T> __device__ __forceinline__ void mirror_half(T* g, int a) {
+template <int Q, int P, int H, typename T> __device__ __forceinline__ void mirror_part(T* g, int a) {
   T t[Q];
 #pragma unroll
   for (int k = 0; k < Q; ++k)
-    if (half_of<Q>(k) == H) t[k] = g[mir<Q>(k, a)];
+    if (part_of<Q, P>(k) == H) t[k] = g[mir<Q>(k, a)];
 #pragma unroll
   for (int k = 0; k < Q; ++k)
-    if (half_of<Q>(k) == H) g[k] = t[k];
+    if (part_of<Q, P>(k) == H) g[k] = t[k];
 }
 
-// face3 in two parts: the interface g of this half's directions and their
-// sum, then F from the interface phi of the two halves' sums (s0 + s1)
-template <int Q, int H, int A, typename T>
+// face3 in two parts: the interface g of this part's directions and their
+// sum, then F from the interface phi of the sum s over all parts
+template <int Q, int P, int H, int A, typename T>
 __device__ __forceinline__ T face_gb(const T* L, const T* R, const T* t1, T tau1, const T* t2, T tau2, T am,
                                      T a0, T ap, T* gb) {
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
-    if (half_of<Q>(k) != H) continue;
+    if (part_of<Q, P>(k) != H) continue;
     const int cn = ce<Q>(k, A), c1 = ce<Q>(k, tan1<A>()), c2 = ce<Q>(k, tan2<A>());
     const T al = cn > 0 ? ap : (cn < 0 ? am : a0);
     T v = fma(al, R[k] - L[k], L[k]);
@@ -764,21 +803,20 @@ __device__ __forceinline__ T face_gb(const T* L, const T* R, const T* t1, T tau1
     if (c2 != 0) v = fma((T)(-c2) * tau2, t2[k], v);
     gb[k] = v;
   }
-  return half_sum<Q, H>(gb);
+  return part_sum<Q, P, H>(gb);
 }
-template <int Q, int H, int A, typename T, typename EQ>
-__device__ __forceinline__ void face_out(const Inst3* __restrict__ I, const EQ& E, const T* gb, T s0, T s1,
-                                         T* out) {
-  const T pb = (T)((s0 + s1) * C3<T>::b1(I));
+template <int Q, int P, int H, int A, typename T, typename EQ>
+__device__ __forceinline__ void face_out(const Inst3* __restrict__ I, const EQ& E, const T* gb, T s, T* out) {
+  const T pb = (T)(s * C3<T>::b1(I));
   const T rb = C3<T>::rb(I);
 #pragma unroll
   for (int k = 0; k < Q; ++k)
-    if (half_of<Q>(k) == H && ce<Q>(k, A) != 0) out[k] = fma(rb, gb[k], E(k, pb));
+    if (part_of<Q, P>(k) == H && ce<Q>(k, A) != 0) out[k] = fma(rb, gb[k], E(k, pb));
 }
 
 // LDS bytes of a block with ns staging slots (E coefficients aside)
 template <int Q, int ROWS, typename T> constexpr int lds_p_bytes(int ns) {
-  return (3 + ns) * (ROWS + 2) * Q * kLanes * (int)sizeof(T) + 4 * ROWS * 2 * kLanes * (int)sizeof(T);
+  return (3 + ns) * (ROWS + 2) * Q * kLanes * (int)sizeof(T) + 4 * ROWS * parts<Q, T, ROWS>() * kLanes * (int)sizeof(T);
 }
 template <int Q, int ROWS, typename T> struct LdsP {
   static constexpr int W = ROWS + 2;             // LDS rows: y0-1 .. y0+ROWS
@@ -791,7 +829,7 @@ template <int Q, int ROWS, typename T> struct LdsP {
   static constexpr bool kVecE = WD == 1 && NS == 2;
   T gsl[3][W][Q][kLanes];                        // g of plane p in slot (p - z0) mod 3
   unsigned raw[NS][W][Q][WD][kLanes];            // staged f~, binary64 as low and high words
-  T psum[4][ROWS][2][kLanes];                    // the halves' interface-g sums of four faces
+  T psum[4][ROWS][parts<Q, T, ROWS>()][kLanes];  // the parts' interface-g sums of four faces
 };
 
 // One wave: row rw of the tile, directions of half H.  With two slots plane
@@ -799,14 +837,14 @@ template <int Q, int ROWS, typename T> struct LdsP {
 // slot is refilled once every wave has read it.
 template <int Q, int NC, int ROWS, typename T, int H, bool WALLS>
 __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int parity, int planes, int strips,
-                                            int tiles, LdsP<Q, ROWS, T>& L, const float* ecoef, int rw) {
+                                            int tiles, LdsP<Q, ROWS, T>& L, const float* ecoef, int w, int rw) {
   using LP = LdsP<Q, ROWS, T>;
+  constexpr int P = parts<Q, T, ROWS>();
   constexpr int W = LP::W, WD = LP::WD;
-  constexpr int NW = 2 * ROWS;                   // waves per block
+  constexpr int NW = P * ROWS;                   // waves per block
   constexpr int HX = (2 * Q + NW - 1) / NW;      // halo-row loads per wave
   constexpr unsigned ES = sizeof(T);
   constexpr bool kVecE = LP::kVecE && NC <= 4;
-  const int w = 2 * rw + H;
   const int lane = threadIdx.x & 63;
   int b = xcd_contiguous(blockIdx.x, gridDim.x);
   const int sx = b % strips;
@@ -863,7 +901,7 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
     const int wme = me;
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-      if (half_of<Q>(k) == H) {
+      if (part_of<Q, P>(k) == H) {
 #pragma unroll
         for (int h = 0; h < WD; ++h)
           __builtin_amdgcn_raw_ptr_buffer_load_lds(Rin, LDS_PTR(&L.raw[slot][wme][k][h][0]), 4, o + 4u * h, 0, 0, 0);
@@ -904,24 +942,24 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
     for (int k = 0; k < Q; ++k) {
       const T v = raw_at(slot, row, k);
       acc[k % NA] += (double)v;
-      if (half_of<Q>(k) == H) f[k] = v;
+      if (part_of<Q, P>(k) == H) f[k] = v;
     }
     double phi = acc[0];
     if constexpr (NA == 4) phi = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     const T p = (T)phi, ra = C3<T>::ra(I);
 #pragma unroll
     for (int k = 0; k < Q; ++k)
-      if (half_of<Q>(k) == H) g[k] = fma(ra, f[k], ev(k, p));
+      if (part_of<Q, P>(k) == H) g[k] = fma(ra, f[k], ev(k, p));
     if constexpr (WALLS) {
-      if (wall_x) mirror_half<Q, H, T>(g, 0);
-      if (wy) mirror_half<Q, H, T>(g, 1);
-      if ((zp < 0 || zp >= nz) && bcz != DUGKS_BC_PERIODIC) mirror_half<Q, H, T>(g, 2);
+      if (wall_x) mirror_part<Q, P, H, T>(g, 0);
+      if (wy) mirror_part<Q, P, H, T>(g, 1);
+      if ((zp < 0 || zp >= nz) && bcz != DUGKS_BC_PERIODIC) mirror_part<Q, P, H, T>(g, 2);
     }
   };
   auto publish = [&](int slot, int row, const T* g) __attribute__((always_inline)) {
 #pragma unroll
     for (int k = 0; k < Q; ++k)
-      if (half_of<Q>(k) == H) L.gsl[slot][row][k][lane] = g[k];
+      if (part_of<Q, P>(k) == H) L.gsl[slot][row][k][lane] = g[k];
   };
   // g of plane zp for this wave's row (G, and f~+ in FT) and, for the waves
   // of rows 0 and 1, the halo rows; all published to slot `slot`
@@ -930,7 +968,7 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
     make_g(rs, me, wall_y, zp, G, f);
 #pragma unroll
     for (int k = 0; k < Q; ++k)
-      if (half_of<Q>(k) == H) FT[k] = fma(kgv, G[k], (T)(-1.0 / 3.0) * f[k]);
+      if (part_of<Q, P>(k) == H) FT[k] = fma(kgv, G[k], (T)(-1.0 / 3.0) * f[k]);
     publish(slot, me, G);
     if (rw <= 1) {
       T gx[Q];
@@ -944,10 +982,14 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
     }
   };
   auto put_sum = [&](int face, T s) __attribute__((always_inline)) { L.psum[face][rw][H][lane] = s; };
-  auto sums = [&](int face, T mine, T& s0, T& s1) __attribute__((always_inline)) {
-    const T other = L.psum[face][rw][1 - H][lane];
-    s0 = H == 0 ? mine : other;
-    s1 = H == 0 ? other : mine;
+  // the sum over all parts: p0 + p1, or (p0 + p1) + (p2 + p3); every part
+  // forms the same value
+  auto total = [&](int face, T mine) __attribute__((always_inline)) -> T {
+    T v[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) v[q] = q == H ? mine : L.psum[face][rw][q][lane];
+    if constexpr (P == 4) return (v[0] + v[1]) + (v[2] + v[3]);
+    else return v[0] + v[1];
   };
 
   T G0[Q], G1[Q], O[Q], FT1[Q], FZb[Q], FZt[Q];
@@ -965,7 +1007,7 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
     if constexpr (kVecE) {
 #pragma unroll
       for (int k = 0; k < Q; ++k)
-        if (half_of<Q>(k) == H)
+        if (part_of<Q, P>(k) == H)
 #pragma unroll
           for (int m = 0; m < NC; ++m) ev.c[k][m] = ecoef[k * NC + m];
     }
@@ -992,23 +1034,19 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
     T t1[Q], t2[Q];
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-      if (half_of<Q>(k) != H) continue;
+      if (part_of<Q, P>(k) != H) continue;
       if (ce<Q>(k, 0) != 0)
         t1[k] = (shl1(G1[k]) - shr1(G1[k])) + (shl1(G0[k]) - shr1(G0[k]));
       if (ce<Q>(k, 1) != 0)
         t2[k] = (L.gsl[2][me + 1][k][lane] - L.gsl[2][me - 1][k][lane]) +
                 (L.gsl[0][me + 1][k][lane] - L.gsl[0][me - 1][k][lane]);
     }
-    sB = face_gb<Q, H, 2>(G1, G0, t1, ctau, t2, ytau, (T)zg[zb * kGeo + 0], (T)zg[zb * kGeo + 1],
+    sB = face_gb<Q, P, H, 2>(G1, G0, t1, ctau, t2, ytau, (T)zg[zb * kGeo + 0], (T)zg[zb * kGeo + 1],
                           (T)zg[zb * kGeo + 2], gbB);
     put_sum(0, sB);
   }
   lds_barrier();
-  if (inner) {
-    T s0, s1;
-    sums(0, sB, s0, s1);
-    face_out<Q, H, 2>(I, ev, gbB, s0, s1, FZb);
-  }
+  if (inner) face_out<Q, P, H, 2>(I, ev, gbB, total(0, sB), FZb);
   wait_vm_all();
   lds_barrier();
 
@@ -1031,7 +1069,7 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
       const T ztau = zg[zi * kGeo + 3];
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
-        if (half_of<Q>(k) != H) continue;
+        if (part_of<Q, P>(k) != H) continue;
         if (ce<Q>(k, 0) != 0) sx0[k] = shl1(G0[k]) - shr1(G0[k]);
         if (ce<Q>(k, 1) != 0) dY[k] = L.gsl[s0][me + 1][k][lane] - L.gsl[s0][me - 1][k][lane];
         if (ce<Q>(k, 2) != 0) dZ[k] = G1[k] - L.gsl[sm][me][k][lane];
@@ -1040,44 +1078,44 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
         T lw[Q];
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
-          if (half_of<Q>(k) != H) continue;
+          if (part_of<Q, P>(k) != H) continue;
           lw[k] = shr1(G0[k]);
           if (ce<Q>(k, 1) != 0) t1[k] = shr1(dY[k]) + dY[k];
           if (ce<Q>(k, 2) != 0) t2[k] = shr1(dZ[k]) + dZ[k];
         }
-        sW = face_gb<Q, H, 0>(lw, G0, t1, ytau, t2, ztau, cam, ca0, cap, gbW);
+        sW = face_gb<Q, P, H, 0>(lw, G0, t1, ytau, t2, ztau, cam, ca0, cap, gbW);
       }
       {  // north face (rows r, r+1)
         T gU[Q];
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
-          if (half_of<Q>(k) != H) continue;
+          if (part_of<Q, P>(k) != H) continue;
           gU[k] = L.gsl[s0][me + 1][k][lane];
           if (ce<Q>(k, 0) != 0) t1[k] = sx0[k] + (shl1(gU[k]) - shr1(gU[k]));
           if (ce<Q>(k, 2) != 0) t2[k] = dZ[k] + (L.gsl[sp][me + 1][k][lane] - L.gsl[sm][me + 1][k][lane]);
         }
-        sN = face_gb<Q, H, 1>(G0, gU, t1, ctau, t2, ztau, yN0, yN1, yN2, gbN);
+        sN = face_gb<Q, P, H, 1>(G0, gU, t1, ctau, t2, ztau, yN0, yN1, yN2, gbN);
       }
       {  // south face (rows r-1, r)
         T gD[Q];
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
-          if (half_of<Q>(k) != H) continue;
+          if (part_of<Q, P>(k) != H) continue;
           gD[k] = L.gsl[s0][me - 1][k][lane];
           if (ce<Q>(k, 0) != 0) t1[k] = sx0[k] + (shl1(gD[k]) - shr1(gD[k]));
           if (ce<Q>(k, 2) != 0) t2[k] = dZ[k] + (L.gsl[sp][me - 1][k][lane] - L.gsl[sm][me - 1][k][lane]);
         }
-        sS = face_gb<Q, H, 1>(gD, G0, t1, ctau, t2, ztau, yS0, yS1, yS2, gbS);
+        sS = face_gb<Q, P, H, 1>(gD, G0, t1, ctau, t2, ztau, yS0, yS1, yS2, gbS);
       }
       {  // top face (planes z, z+1); the bottom face is the previous plane's top face
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
-          if (half_of<Q>(k) != H) continue;
+          if (part_of<Q, P>(k) != H) continue;
           if (ce<Q>(k, 0) != 0) t1[k] = sx0[k] + (shl1(G1[k]) - shr1(G1[k]));
           if (ce<Q>(k, 1) != 0) t2[k] = dY[k] + (L.gsl[sp][me + 1][k][lane] - L.gsl[sp][me - 1][k][lane]);
         }
         const int zt = z + 2;
-        sT = face_gb<Q, H, 2>(G0, G1, t1, ctau, t2, ytau, (T)zg[zt * kGeo + 0], (T)zg[zt * kGeo + 1],
+        sT = face_gb<Q, P, H, 2>(G0, G1, t1, ctau, t2, ytau, (T)zg[zt * kGeo + 0], (T)zg[zt * kGeo + 1],
                               (T)zg[zt * kGeo + 2], gbT);
       }
       put_sum(0, sW);
@@ -1092,18 +1130,14 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
     if (inner) {
       const int zi = z + 1;
       const T kz = zg[zi * kGeo + 4];
-      T a, bb, fW[Q], fN[Q], fS[Q];
-      sums(0, sW, a, bb);
-      face_out<Q, H, 0>(I, ev, gbW, a, bb, fW);
-      sums(1, sN, a, bb);
-      face_out<Q, H, 1>(I, ev, gbN, a, bb, fN);
-      sums(2, sS, a, bb);
-      face_out<Q, H, 1>(I, ev, gbS, a, bb, fS);
-      sums(3, sT, a, bb);
-      face_out<Q, H, 2>(I, ev, gbT, a, bb, FZt);
+      T fW[Q], fN[Q], fS[Q];
+      face_out<Q, P, H, 0>(I, ev, gbW, total(0, sW), fW);
+      face_out<Q, P, H, 1>(I, ev, gbN, total(1, sN), fN);
+      face_out<Q, P, H, 1>(I, ev, gbS, total(2, sS), fS);
+      face_out<Q, P, H, 2>(I, ev, gbT, total(3, sT), FZt);
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
-        if (half_of<Q>(k) != H) continue;
+        if (part_of<Q, P>(k) != H) continue;
         if (ce<Q>(k, 0) != 0) O[k] = fma((T)(-ce<Q>(k, 0)) * ck, shl1(fW[k]) - fW[k], O[k]);
         if (ce<Q>(k, 1) != 0) O[k] = fma((T)(-ce<Q>(k, 1)) * ky, fN[k], O[k]);
         if (ce<Q>(k, 1) != 0) O[k] = fma((T)ce<Q>(k, 1) * ky, fS[k], O[k]);
@@ -1114,7 +1148,7 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
       unsigned o = (unsigned)(((long long)z * ny + r) * pitch + c) * ES;
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
-        if (half_of<Q>(k) == H) {
+        if (part_of<Q, P>(k) == H) {
           if constexpr (WD == 1)
             __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, O[k]), Rout, o, 0, 0);
           else
@@ -1127,7 +1161,7 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
     // of the sums from its writes of them
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-      if (half_of<Q>(k) != H) continue;
+      if (part_of<Q, P>(k) != H) continue;
       G0[k] = G1[k];
       O[k] = FT1[k];
       if (ce<Q>(k, 2) != 0) FZb[k] = FZt[k];
@@ -1149,20 +1183,31 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
 
 // WALLS = false: every axis periodic, no mirror code
 template <int Q, int NC, int ROWS, typename T, bool WALLS>
-__global__ __launch_bounds__(128 * ROWS) void k_step3p(const Inst3* __restrict__ I, int parity, int planes,
-                                                        int strips, int tiles) {
+__global__ __launch_bounds__((64 * parts<Q, T, ROWS>() * ROWS)) void k_step3p(const Inst3* __restrict__ I, int parity,
+                                                                       int planes, int strips, int tiles) {
+  constexpr int P = parts<Q, T, ROWS>();
   __shared__ LdsP<Q, ROWS, T> L;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int rw = w >> 1;
+  const int rw = w / P;
+  // part of wave w: with four parts rotated by the row, so that each SIMD
+  // (waves w, w+4, ...) runs every part once
+  const int part = P == 2 ? (w & 1) : ((w + rw) & 3);
+  const float* ec = nullptr;
   if constexpr (LdsP<Q, ROWS, T>::kVecE && NC <= 4) {
     __shared__ float ecoef[Q * NC];   // E_i coefficients, read into vector registers
     if (w == 0)
       for (int i = threadIdx.x; i < Q * NC; i += kLanes) ecoef[i] = I->ef[i / NC][i % NC];
-    if (w & 1) step3p_half<Q, NC, ROWS, T, 1, WALLS>(I, parity, planes, strips, tiles, L, ecoef, rw);
-    else step3p_half<Q, NC, ROWS, T, 0, WALLS>(I, parity, planes, strips, tiles, L, ecoef, rw);
-  } else {
-    if (w & 1) step3p_half<Q, NC, ROWS, T, 1, WALLS>(I, parity, planes, strips, tiles, L, nullptr, rw);
-    else step3p_half<Q, NC, ROWS, T, 0, WALLS>(I, parity, planes, strips, tiles, L, nullptr, rw);
+    ec = ecoef;
+  }
+  switch (part) {
+    case 0: step3p_half<Q, NC, ROWS, T, 0, WALLS>(I, parity, planes, strips, tiles, L, ec, w, rw); break;
+    case 1: step3p_half<Q, NC, ROWS, T, 1, WALLS>(I, parity, planes, strips, tiles, L, ec, w, rw); break;
+    case 2:
+      if constexpr (P > 2) step3p_half<Q, NC, ROWS, T, 2, WALLS>(I, parity, planes, strips, tiles, L, ec, w, rw);
+      break;
+    default:
+      if constexpr (P > 2) step3p_half<Q, NC, ROWS, T, 3, WALLS>(I, parity, planes, strips, tiles, L, ec, w, rw);
+      break;
   }
 }
 
@@ -1333,24 +1378,26 @@ static void step3_row_waves(const Inst3* d, const Inst3& h, int parity, const La
   }
 }
 
+template <int Q, int NC, int ROWS, typename T, bool WALLS>
+static void step3p_go(const Inst3* d, int parity, const Launch3& l, int strips, int tiles, dim3 grid,
+                      hipStream_t st) {
+  hipLaunchKernelGGL((k_step3p<Q, NC, ROWS, T, WALLS>), grid, dim3(64 * parts<Q, T, ROWS>() * ROWS), 0, st, d,
+                     parity, l.planes, strips, tiles);
+}
 template <int Q, int NC, typename T, bool WALLS>
 static void step3p_launch(const Inst3* d, int parity, const Launch3& l, int strips, int tiles, dim3 grid,
                           hipStream_t st) {
   if constexpr (sizeof(T) == 8) {   // rows 1 and 2 fit the LDS
-    if (l.rows == 1)
-      hipLaunchKernelGGL((k_step3p<Q, NC, 1, T, WALLS>), grid, dim3(128), 0, st, d, parity, l.planes, strips, tiles);
-    else
-      hipLaunchKernelGGL((k_step3p<Q, NC, 2, T, WALLS>), grid, dim3(256), 0, st, d, parity, l.planes, strips, tiles);
+    if (l.rows == 1) step3p_go<Q, NC, 1, T, WALLS>(d, parity, l, strips, tiles, grid, st);
+    else step3p_go<Q, NC, 2, T, WALLS>(d, parity, l, strips, tiles, grid, st);
   } else {
     switch (l.rows) {
-      case 2: hipLaunchKernelGGL((k_step3p<Q, NC, 2, T, WALLS>), grid, dim3(256), 0, st, d, parity, l.planes, strips, tiles); break;
-      case 3: hipLaunchKernelGGL((k_step3p<Q, NC, 3, T, WALLS>), grid, dim3(384), 0, st, d, parity, l.planes, strips, tiles); break;
-      default: hipLaunchKernelGGL((k_step3p<Q, NC, 4, T, WALLS>), grid, dim3(512), 0, st, d, parity, l.planes, strips, tiles); break;
+      case 2: step3p_go<Q, NC, 2, T, WALLS>(d, parity, l, strips, tiles, grid, st); break;
+      case 3: step3p_go<Q, NC, 3, T, WALLS>(d, parity, l, strips, tiles, grid, st); break;
+      default: step3p_go<Q, NC, 4, T, WALLS>(d, parity, l, strips, tiles, grid, st); break;
     }
   }
 }
-// the wall-free instantiation when every axis is periodic and the
-// equilibrium polynomials have at most 4 coefficients
 template <int Q, int NC, typename T>
 static void step3p_rows(const Inst3* d, const Inst3& h, int parity, const Launch3& l, int strips, int tiles,
                         dim3 grid, hipStream_t st) {
@@ -1403,10 +1450,11 @@ size_t step3_lds_bytes(int storage, int q, const Launch3& l) {
   if (q == 7)   // binary64: g of 3 planes (dynamic); binary32: g of 3 planes and f~ of 2
     return storage == DUGKS_F64 ? step3h_lds_bytes(q, l) : (size_t)5 * (l.rows + 2) * q * kLanes * 4;
   // g of 3 planes and staged f~ of 1 or 2 planes (LdsP), each of rows + 2
-  // rows, and the halves' sums of 4 faces per row (static; the binary32 E
+  // rows, and the parts' sums of 4 faces per row (static; the binary32 E
   // coefficients aside)
   const size_t e = storage == DUGKS_F64 ? 8 : 4;
-  auto bytes = [&](size_t ns) { return (3 + ns) * (l.rows + 2) * q * kLanes * e + (size_t)4 * l.rows * 2 * kLanes * e; };
+  const size_t np = (q == 19 && storage != DUGKS_F64 && l.rows >= 3) ? 4 : 2;   // parts<Q, T, ROWS>()
+  auto bytes = [&](size_t ns) { return (3 + ns) * (l.rows + 2) * q * kLanes * e + (size_t)4 * l.rows * np * kLanes * e; };
   if (storage == DUGKS_F64) return bytes(1);
   return (bytes(2) > 81920 && bytes(1) <= 81920) ? bytes(1) : bytes(2);
 }
