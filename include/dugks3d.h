@@ -111,7 +111,7 @@ int dugks3_reduce(dugks3_ctx* ctx, const double* ref_dev, double* mass, double* 
  * (binary32: 5 x (rows + 2) x q x 64 x 4 bytes of LDS; binary64: one more
  * wave per halo row, 3 x (rows + 2) x q x 64 x 8 bytes).  A launch needing
  * more LDS than the device allows per block is refused.  Defaults: 2 rows
- * (binary64), 4 rows (binary32; D3Q15: 2); 64 planes (D3Q7: 32; D3Q15 and
+ * (binary64), 4 rows (binary32; D3Q15 with walls: 2); 64 planes (D3Q7: 32; D3Q15 and
  * D3Q19 in binary64: 128), halved down to 4 while the grid would have fewer
  * than 512 blocks.
  * Errors: E_ARG. */

@@ -200,7 +200,10 @@ struct dugks3_ctx {
   const Inst3* dev() const { return (const Inst3*)(ws + off_table); }
 
   // LDS bytes of a block for the launch and the device limit per block
-  size_t lds_bytes(const Launch3& l) const { return step3_lds_bytes(p.storage, q, l); }
+  size_t lds_bytes(const Launch3& l) const {
+    const bool walls = p.bc[0] != DUGKS_BC_PERIODIC || p.bc[1] != DUGKS_BC_PERIODIC || p.bc[2] != DUGKS_BC_PERIODIC;
+    return step3_lds_bytes(p.storage, q, walls, l);
+  }
   size_t lds_limit() const {
     int dev = 0, v = 65536;
     if (hipGetDevice(&dev) == hipSuccess)
@@ -307,9 +310,10 @@ int dugks3_create(dugks3_ctx** out, int nx, int ny, int nz, const double* xf, co
   x->off_stage = off; off += align256(x->stage_bytes);
   x->total = off;
   // default launch (fastest measured at 256^3): binary64 two rows; binary32
-  // four rows (D3Q15: two, which lets two blocks share a CU); 64 planes a
-  // block (D3Q7: 32; D3Q15 and D3Q19 in binary64: 128)
-  x->launch.rows = p->storage == DUGKS_F64 ? 2 : (q == 15 ? 2 : 4);
+  // four rows (D3Q15 with walls: two, which lets two blocks share a CU); 64
+  // planes a block (D3Q7: 32; D3Q15 and D3Q19 in binary64: 128)
+  const bool walls = p->bc[0] != DUGKS_BC_PERIODIC || p->bc[1] != DUGKS_BC_PERIODIC || p->bc[2] != DUGKS_BC_PERIODIC;
+  x->launch.rows = p->storage == DUGKS_F64 ? 2 : ((q == 15 && walls) ? 2 : 4);
   // shorter chunks on small grids until there are at least two blocks per CU
   // of a 256-CU device (a chunk restages two halo planes; 64^3: 233 -> 42 us
   // a step, 128^3: 240 -> 193 us)

@@ -718,16 +718,22 @@ template <int Q> __host__ __device__ constexpr int half_of(int k) {
   if (Q == 15) return nnz == 3 ? 1 : 0;                              // 7 + 8
   return (x == 0 && nnz == 1) ? 1 : 0;                               // 3 + 4
 }
-// D3Q19 in binary32 with 3 or more rows splits each row four ways: {rest,
-// (+-1,+-1,0)}, {(+-1,0,+-1)}, {(0,+-1,+-1)}, {axis directions}; otherwise
-// in halves
-template <int Q, typename T, int ROWS> constexpr int parts() {
-  return (Q == 19 && sizeof(T) == 4 && ROWS >= 3) ? 4 : 2;
+// Binary32 with 3 or more rows splits each row four ways.  D3Q19: {rest,
+// (+-1,+-1,0)}, {(+-1,0,+-1)}, {(0,+-1,+-1)}, {axis directions}, closed
+// under the wall mirrors.  D3Q15 only without walls (a z mirror moves a
+// corner between the last two): {rest, +-x}, {+-y, +-z}, {corners with
+// c_z = +1}, {corners with c_z = -1}.  Each half is two quarters.
+template <int Q, typename T, int ROWS, bool WALLS> constexpr int parts() {
+  return (sizeof(T) == 4 && ROWS >= 3 && (Q == 19 || (Q == 15 && !WALLS))) ? 4 : 2;
 }
 template <int Q, int P> __host__ __device__ constexpr int part_of(int k) {
   if (P == 2) return half_of<Q>(k);
   const int x = ce<Q>(k, 0), y = ce<Q>(k, 1), z = ce<Q>(k, 2);
   const int nnz = (x != 0) + (y != 0) + (z != 0);
+  if (Q == 15) {
+    if (nnz == 3) return z > 0 ? 2 : 3;
+    return (nnz == 0 || x != 0) ? 0 : 1;
+  }
   if (nnz <= 1) return nnz == 0 ? 0 : 3;
   return z == 0 ? 0 : (y == 0 ? 1 : 2);
 }
@@ -750,11 +756,11 @@ template <int Q, int N, typename T, typename SEL> __device__ __forceinline__ T s
     for (int j = 0; j + w < N; j += 2 * w) t[j] += t[j + w];
   return t[0];
 }
-// Sum over this part's directions.  D3Q19 sums each of its four quarters
-// pairwise, a half being quarters 0 + 1 or 2 + 3, so that the total over the
-// parts, (q0 + q1) + (q2 + q3), is the same for two and for four parts.
+// Sum over this part's directions.  D3Q19 and D3Q15 sum each of their four
+// quarters pairwise, a half being quarters 0 + 1 or 2 + 3, so that the total
+// over the parts, (q0 + q1) + (q2 + q3), is the same for two and for four parts.
 template <int Q, int P, int H, typename T> __device__ __forceinline__ T part_sum(const T* v) {
-  if constexpr (Q == 19) {
+  if constexpr (Q == 19 || Q == 15) {
     auto quarter = [&](auto jc) __attribute__((always_inline)) -> T {
       constexpr int J = decltype(jc)::value;
       return sel_sum<Q, part_count<Q, 4, J>()>(v, [](int k) { return part_of<Q, 4>(k) == J; });
@@ -815,21 +821,24 @@ __device__ __forceinline__ void face_out(const Inst3* __restrict__ I, const EQ& 
 }
 
 // LDS bytes of a block with ns staging slots (E coefficients aside)
-template <int Q, int ROWS, typename T> constexpr int lds_p_bytes(int ns) {
-  return (3 + ns) * (ROWS + 2) * Q * kLanes * (int)sizeof(T) + 4 * ROWS * parts<Q, T, ROWS>() * kLanes * (int)sizeof(T);
+template <int Q, int ROWS, typename T, bool WALLS> constexpr int lds_p_bytes(int ns) {
+  return (3 + ns) * (ROWS + 2) * Q * kLanes * (int)sizeof(T) +
+         4 * ROWS * parts<Q, T, ROWS, WALLS>() * kLanes * (int)sizeof(T);
 }
-template <int Q, int ROWS, typename T> struct LdsP {
+template <int Q, int ROWS, typename T, bool WALLS> struct LdsP {
   static constexpr int W = ROWS + 2;             // LDS rows: y0-1 .. y0+ROWS
   static constexpr int WD = sizeof(T) / 4;       // words per element
   // staging slots: binary32 two, unless one slot lets two blocks share a
   // CU's 160 KiB where two slots would not; binary64 one
   static constexpr int NS = WD == 2 ? 1
-                            : (lds_p_bytes<Q, ROWS, T>(2) > 81920 && lds_p_bytes<Q, ROWS, T>(1) <= 81920) ? 1 : 2;
+                            : (lds_p_bytes<Q, ROWS, T, WALLS>(2) > 81920 && lds_p_bytes<Q, ROWS, T, WALLS>(1) <= 81920)
+                                  ? 1
+                                  : 2;
   // E coefficients in vector registers (from LDS) with two slots
   static constexpr bool kVecE = WD == 1 && NS == 2;
   T gsl[3][W][Q][kLanes];                        // g of plane p in slot (p - z0) mod 3
   unsigned raw[NS][W][Q][WD][kLanes];            // staged f~, binary64 as low and high words
-  T psum[4][ROWS][parts<Q, T, ROWS>()][kLanes];  // the parts' interface-g sums of four faces
+  T psum[4][ROWS][parts<Q, T, ROWS, WALLS>()][kLanes];   // the parts' interface-g sums of four faces
 };
 
 // One wave: row rw of the tile, directions of half H.  With two slots plane
@@ -837,9 +846,10 @@ template <int Q, int ROWS, typename T> struct LdsP {
 // slot is refilled once every wave has read it.
 template <int Q, int NC, int ROWS, typename T, int H, bool WALLS>
 __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int parity, int planes, int strips,
-                                            int tiles, LdsP<Q, ROWS, T>& L, const float* ecoef, int w, int rw) {
-  using LP = LdsP<Q, ROWS, T>;
-  constexpr int P = parts<Q, T, ROWS>();
+                                            int tiles, LdsP<Q, ROWS, T, WALLS>& L, const float* ecoef, int w,
+                                            int rw) {
+  using LP = LdsP<Q, ROWS, T, WALLS>;
+  constexpr int P = parts<Q, T, ROWS, WALLS>();
   constexpr int W = LP::W, WD = LP::WD;
   constexpr int NW = P * ROWS;                   // waves per block
   constexpr int HX = (2 * Q + NW - 1) / NW;      // halo-row loads per wave
@@ -1183,17 +1193,17 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
 
 // WALLS = false: every axis periodic, no mirror code
 template <int Q, int NC, int ROWS, typename T, bool WALLS>
-__global__ __launch_bounds__((64 * parts<Q, T, ROWS>() * ROWS)) void k_step3p(const Inst3* __restrict__ I, int parity,
+__global__ __launch_bounds__((64 * parts<Q, T, ROWS, WALLS>() * ROWS)) void k_step3p(const Inst3* __restrict__ I, int parity,
                                                                        int planes, int strips, int tiles) {
-  constexpr int P = parts<Q, T, ROWS>();
-  __shared__ LdsP<Q, ROWS, T> L;
+  constexpr int P = parts<Q, T, ROWS, WALLS>();
+  __shared__ LdsP<Q, ROWS, T, WALLS> L;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int rw = w / P;
   // part of wave w: with four parts rotated by the row, so that each SIMD
   // (waves w, w+4, ...) runs every part once
   const int part = P == 2 ? (w & 1) : ((w + rw) & 3);
   const float* ec = nullptr;
-  if constexpr (LdsP<Q, ROWS, T>::kVecE && NC <= 4) {
+  if constexpr (LdsP<Q, ROWS, T, WALLS>::kVecE && NC <= 4) {
     __shared__ float ecoef[Q * NC];   // E_i coefficients, read into vector registers
     if (w == 0)
       for (int i = threadIdx.x; i < Q * NC; i += kLanes) ecoef[i] = I->ef[i / NC][i % NC];
@@ -1381,7 +1391,7 @@ static void step3_row_waves(const Inst3* d, const Inst3& h, int parity, const La
 template <int Q, int NC, int ROWS, typename T, bool WALLS>
 static void step3p_go(const Inst3* d, int parity, const Launch3& l, int strips, int tiles, dim3 grid,
                       hipStream_t st) {
-  hipLaunchKernelGGL((k_step3p<Q, NC, ROWS, T, WALLS>), grid, dim3(64 * parts<Q, T, ROWS>() * ROWS), 0, st, d,
+  hipLaunchKernelGGL((k_step3p<Q, NC, ROWS, T, WALLS>), grid, dim3(64 * parts<Q, T, ROWS, WALLS>() * ROWS), 0, st, d,
                      parity, l.planes, strips, tiles);
 }
 template <int Q, int NC, typename T, bool WALLS>
@@ -1446,14 +1456,16 @@ int launch_step3(const Inst3* d, const Inst3& h, int parity, const Launch3& l, v
   }
 }
 
-size_t step3_lds_bytes(int storage, int q, const Launch3& l) {
+size_t step3_lds_bytes(int storage, int q, bool walls, const Launch3& l) {
   if (q == 7)   // binary64: g of 3 planes (dynamic); binary32: g of 3 planes and f~ of 2
     return storage == DUGKS_F64 ? step3h_lds_bytes(q, l) : (size_t)5 * (l.rows + 2) * q * kLanes * 4;
   // g of 3 planes and staged f~ of 1 or 2 planes (LdsP), each of rows + 2
   // rows, and the parts' sums of 4 faces per row (static; the binary32 E
   // coefficients aside)
   const size_t e = storage == DUGKS_F64 ? 8 : 4;
-  const size_t np = (q == 19 && storage != DUGKS_F64 && l.rows >= 3) ? 4 : 2;   // parts<Q, T, ROWS>()
+  // parts<Q, T, ROWS, WALLS>() (an upper bound when equilibrium polynomials
+  // of 5 to 8 coefficients take the instantiation with walls)
+  const size_t np = (storage != DUGKS_F64 && l.rows >= 3 && (q == 19 || (q == 15 && !walls))) ? 4 : 2;
   auto bytes = [&](size_t ns) { return (3 + ns) * (l.rows + 2) * q * kLanes * e + (size_t)4 * l.rows * np * kLanes * e; };
   if (storage == DUGKS_F64) return bytes(1);
   return (bytes(2) > 81920 && bytes(1) <= 81920) ? bytes(1) : bytes(2);
