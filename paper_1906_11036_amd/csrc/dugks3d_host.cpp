@@ -201,7 +201,10 @@ struct dugks3_ctx {
 
   // LDS bytes of a block for the launch and the device limit per block
   size_t lds_bytes(const Launch3& l) const {
-    const bool walls = p.bc[0] != DUGKS_BC_PERIODIC || p.bc[1] != DUGKS_BC_PERIODIC || p.bc[2] != DUGKS_BC_PERIODIC;
+    // the instantiation with mirror code runs with walls or with more than
+    // four equilibrium coefficients
+    const bool walls = p.bc[0] != DUGKS_BC_PERIODIC || p.bc[1] != DUGKS_BC_PERIODIC ||
+                       p.bc[2] != DUGKS_BC_PERIODIC || ncoef > 4;
     return step3_lds_bytes(p.storage, q, walls, l);
   }
   size_t lds_limit() const {

@@ -56,7 +56,8 @@ struct Launch3 {
 // Blocks of one step for the launch (x strips x row tiles x plane chunks).
 long long step3_blocks(const Inst3& h, const Launch3& l);
 int launch_step3(const Inst3* d, const Inst3& h, int parity, const Launch3& l, void* stream);
-// LDS bytes of one block of the step kernel (walls: some axis not periodic)
+// LDS bytes of one block of the step kernel (walls: the instantiation with
+// mirror code, for a non-periodic axis or more than four coefficients)
 size_t step3_lds_bytes(int storage, int q, bool walls, const Launch3& l);
 int launch_init3(const Inst3* d, const Inst3& h, const double* phi, int parity, void* stream);
 int launch_set_f3(const Inst3* d, const Inst3& h, const double* f, int parity, void* stream);

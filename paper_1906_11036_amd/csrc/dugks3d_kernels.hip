@@ -723,8 +723,16 @@ template <int Q> __host__ __device__ constexpr int half_of(int k) {
 // under the wall mirrors.  D3Q15 only without walls (a z mirror moves a
 // corner between the last two): {rest, +-x}, {+-y, +-z}, {corners with
 // c_z = +1}, {corners with c_z = -1}.  Each half is two quarters.
+// Binary64 at 2 rows does the same, with its halo rows loaded into
+// registers instead of staged (the LDS holds the four-part sums instead).
 template <int Q, typename T, int ROWS, bool WALLS> constexpr int parts() {
-  return (sizeof(T) == 4 && ROWS >= 3 && (Q == 19 || (Q == 15 && !WALLS))) ? 4 : 2;
+  constexpr bool quarters = Q == 19 || (Q == 15 && !WALLS);
+  return (quarters && ((sizeof(T) == 4 && ROWS >= 3) || (sizeof(T) == 8 && ROWS == 2))) ? 4 : 2;
+}
+// rows of raw f~ staged in LDS: the tile's rows and its two halo rows, or
+// only the tile's rows when binary64 loads the halo rows into registers
+template <int Q, typename T, int ROWS, bool WALLS> constexpr int staged_rows() {
+  return (sizeof(T) == 8 && parts<Q, T, ROWS, WALLS>() == 4) ? ROWS : ROWS + 2;
 }
 template <int Q, int P> __host__ __device__ constexpr int part_of(int k) {
   if (P == 2) return half_of<Q>(k);
@@ -822,7 +830,7 @@ __device__ __forceinline__ void face_out(const Inst3* __restrict__ I, const EQ& 
 
 // LDS bytes of a block with ns staging slots (E coefficients aside)
 template <int Q, int ROWS, typename T, bool WALLS> constexpr int lds_p_bytes(int ns) {
-  return (3 + ns) * (ROWS + 2) * Q * kLanes * (int)sizeof(T) +
+  return 3 * (ROWS + 2) * Q * kLanes * (int)sizeof(T) + ns * staged_rows<Q, T, ROWS, WALLS>() * Q * kLanes * (int)sizeof(T) +
          4 * ROWS * parts<Q, T, ROWS, WALLS>() * kLanes * (int)sizeof(T);
 }
 template <int Q, int ROWS, typename T, bool WALLS> struct LdsP {
@@ -836,8 +844,10 @@ template <int Q, int ROWS, typename T, bool WALLS> struct LdsP {
                                   : 2;
   // E coefficients in vector registers (from LDS) with two slots
   static constexpr bool kVecE = WD == 1 && NS == 2;
+  static constexpr int RR = staged_rows<Q, T, ROWS, WALLS>();
+  static constexpr bool kHD = RR == ROWS;        // halo rows loaded into registers
   T gsl[3][W][Q][kLanes];                        // g of plane p in slot (p - z0) mod 3
-  unsigned raw[NS][W][Q][WD][kLanes];            // staged f~, binary64 as low and high words
+  unsigned raw[NS][RR][Q][WD][kLanes];           // staged f~, binary64 as low and high words
   T psum[4][ROWS][parts<Q, T, ROWS, WALLS>()][kLanes];   // the parts' interface-g sums of four faces
 };
 
@@ -906,9 +916,10 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
   };
   // stage plane zp: this wave's directions of its row, and its share of the
   // two halo rows (offsets advance in a vector register)
+  T HR[LP::kHD ? Q : 1];   // raw f~ of the halo row this wave makes, when not staged
   auto stage = [&](int slot, int zp) __attribute__((always_inline)) {
     unsigned o = cell_index(srow, zp) * ES;
-    const int wme = me;
+    const int wme = LP::kHD ? me - 1 : me;
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
       if (part_of<Q, P>(k) == H) {
@@ -917,6 +928,17 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
           __builtin_amdgcn_raw_ptr_buffer_load_lds(Rin, LDS_PTR(&L.raw[slot][wme][k][h][0]), 4, o + 4u * h, 0, 0, 0);
       }
       o += planeB;
+    }
+    if constexpr (LP::kHD) {
+      if (rw <= 1) {   // every direction of the halo row, into registers
+        unsigned oh = cell_index(rw == 0 ? slo : shi, zp) * ES;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          HR[k] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(Rin, oh, 0u, 0));
+          oh += planeB;
+        }
+      }
+      return;
     }
     const unsigned ilo = cell_index(slo, zp) * ES, ihi = cell_index(shi, zp) * ES;
     const int j0 = w * HX;
@@ -933,15 +955,20 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
                                                  oh + 4u * h, 0, 0, 0);
     }
   };
+  // raw f~ of LDS row `row` (g numbering; with the halo rows in registers
+  // only the tile's rows are staged)
   auto raw_at = [&](int slot, int row, int k) __attribute__((always_inline)) -> T {
+    const int rr = LP::kHD ? row - 1 : row;
     if constexpr (WD == 1)
-      return __builtin_bit_cast(float, L.raw[slot][row][k][0][lane]);
+      return __builtin_bit_cast(float, L.raw[slot][rr][k][0][lane]);
     else
-      return __builtin_bit_cast(double, (unsigned long long)L.raw[slot][row][k][0][lane] |
-                                            ((unsigned long long)L.raw[slot][row][k][1][lane] << 32));
+      return __builtin_bit_cast(double, (unsigned long long)L.raw[slot][rr][k][0][lane] |
+                                            ((unsigned long long)L.raw[slot][rr][k][1][lane] << 32));
   };
   // g = fbar+ / b1 (eq. 2.21 over b1) of this half's directions; phi (binary64) from all of them
-  auto make_g = [&](int slot, int row, bool wy, int zp, T* g, T* f) __attribute__((always_inline)) {
+  // (fromreg: the raw values are the halo row's in HR)
+  auto make_g = [&](int slot, int row, bool wy, int zp, T* g, T* f, auto fromreg) __attribute__((always_inline)) {
+    constexpr bool kReg = decltype(fromreg)::value;
     // binary64: four chains, then a pairwise combine (one wave per SIMD
     // waits out every link of a chain); binary32: one chain
     constexpr int NA = WD == 2 ? 4 : 1;
@@ -950,7 +977,9 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
     for (int a = 0; a < NA; ++a) acc[a] = 0.0;
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-      const T v = raw_at(slot, row, k);
+      T v;
+      if constexpr (kReg) v = HR[k];
+      else v = raw_at(slot, row, k);
       acc[k % NA] += (double)v;
       if (part_of<Q, P>(k) == H) f[k] = v;
     }
@@ -974,8 +1003,10 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
   // g of plane zp for this wave's row (G, and f~+ in FT) and, for the waves
   // of rows 0 and 1, the halo rows; all published to slot `slot`
   auto plane_g = [&](int rs, int zp, int slot, T* G, T* FT) __attribute__((always_inline)) {
+    using Staged = std::integral_constant<bool, false>;
+    using Halo = std::integral_constant<bool, LP::kHD>;
     T f[Q];
-    make_g(rs, me, wall_y, zp, G, f);
+    make_g(rs, me, wall_y, zp, G, f, Staged{});
 #pragma unroll
     for (int k = 0; k < Q; ++k)
       if (part_of<Q, P>(k) == H) FT[k] = fma(kgv, G[k], (T)(-1.0 / 3.0) * f[k]);
@@ -983,10 +1014,10 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
     if (rw <= 1) {
       T gx[Q];
       const int row = rw == 0 ? 0 : W - 1;
-      make_g(rs, row, rw == 0 ? wall_lo : wall_hi, zp, gx, f);
+      make_g(rs, row, rw == 0 ? wall_lo : wall_hi, zp, gx, f, Halo{});
       publish(slot, row, gx);
-      if (ROWS == 1) {  // one row: its waves make both halo rows
-        make_g(rs, W - 1, wall_hi, zp, gx, f);
+      if (ROWS == 1) {  // one row: its waves make both halo rows (always staged)
+        make_g(rs, W - 1, wall_hi, zp, gx, f, Staged{});
         publish(slot, W - 1, gx);
       }
     }
@@ -1463,10 +1494,13 @@ size_t step3_lds_bytes(int storage, int q, bool walls, const Launch3& l) {
   // rows, and the parts' sums of 4 faces per row (static; the binary32 E
   // coefficients aside)
   const size_t e = storage == DUGKS_F64 ? 8 : 4;
-  // parts<Q, T, ROWS, WALLS>() (an upper bound when equilibrium polynomials
-  // of 5 to 8 coefficients take the instantiation with walls)
-  const size_t np = (storage != DUGKS_F64 && l.rows >= 3 && (q == 19 || (q == 15 && !walls))) ? 4 : 2;
-  auto bytes = [&](size_t ns) { return (3 + ns) * (l.rows + 2) * q * kLanes * e + (size_t)4 * l.rows * np * kLanes * e; };
+  // parts<Q, T, ROWS, WALLS>(), walls meaning the instantiation with mirror code
+  const bool quarters = q == 19 || (q == 15 && !walls);
+  const size_t np = (quarters && ((storage != DUGKS_F64 && l.rows >= 3) || (storage == DUGKS_F64 && l.rows == 2))) ? 4 : 2;
+  const size_t rr = (storage == DUGKS_F64 && np == 4) ? l.rows : l.rows + 2;   // staged_rows<>()
+  auto bytes = [&](size_t ns) {
+    return 3 * (l.rows + 2) * q * kLanes * e + ns * rr * q * kLanes * e + (size_t)4 * l.rows * np * kLanes * e;
+  };
   if (storage == DUGKS_F64) return bytes(1);
   return (bytes(2) > 81920 && bytes(1) <= 81920) ? bytes(1) : bytes(2);
 }
