@@ -86,3 +86,25 @@ def test_1d_fp64_random(seed, n, bc, stretched, steps):
     o.step(steps)
     assert rel_max(s.get_f(), o.get_f()) <= TOL64
     assert rel_max(s.get_phi_prev(), o.get_phi_prev()) <= TOL64
+
+
+@settings(max_examples=25, derandomize=True, database=None, deadline=None,
+          suppress_health_check=[HealthCheck.too_slow])
+@given(seed=st.integers(0, 10**6), nx=st.integers(1, 130), ny=st.integers(1, 14), nz=st.integers(1, 10),
+       q=st.sampled_from([19, 15, 7]), bc=st.tuples(*[st.sampled_from([W.PERIODIC, W.MIRROR])] * 3),
+       bdeg=st.integers(1, 4), rows=st.tuples(st.integers(2, 4), st.integers(2, 4)),
+       planes=st.tuples(st.integers(1, 16), st.integers(1, 16)), steps=st.integers(1, 3))
+def test_3d_fp32_launch_shapes_bitwise(seed, nx, ny, nz, q, bc, bdeg, rows, planes, steps):
+    """Binary32: two random launch shapes (two or four waves a row, one or two
+    staging slots, chunk lengths) give bitwise the same distributions."""
+    p = W.random_problem3d(seed, nx, ny, nz, q=q, bc=bc, stretched=True, bdeg=bdeg, ddeg=2)
+    say(f"case 3d f32 seed={seed} {nx}x{ny}x{nz} q={q} bc={bc} bdeg={bdeg} rows={rows} planes={planes}")
+    out = []
+    for r, pl in zip(rows, planes):
+        s = dg.Solver3D(p, storage="f32")
+        s.set_launch(r, pl)
+        s.set_phi(p.phi0)
+        s.step(steps)
+        out.append(s.get_f())
+        s.close()
+    assert np.array_equal(out[0], out[1])
