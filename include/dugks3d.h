@@ -104,16 +104,19 @@ int dugks3_reduce(dugks3_ctx* ctx, const double* ref_dev, double* mass, double* 
 
 /* Launch configuration: rows per block and planes swept per block (>= 1).
  * binary32: 2 to 4 rows; binary64: 1 or 2 rows.  D3Q15 and D3Q19 give each
- * row two waves, one per half of the directions (g of 3 planes, raw f~ of 2
- * (binary32) or 1 (binary64) planes of the rows and the two halo rows, and 4
- * face sums per row, in LDS: (5 or 4) x (rows + 2) x q x 64 x s + 4 x rows x
- * 2 x 64 x s bytes, s the element size).  D3Q7 gives each row one wave
- * (binary32: 5 x (rows + 2) x q x 64 x 4 bytes of LDS; binary64: one more
- * wave per halo row, 3 x (rows + 2) x q x 64 x 8 bytes).  A launch needing
- * more LDS than the device allows per block is refused.  Defaults: 2 rows
- * (binary64), 4 rows (binary32; D3Q15 with walls: 2); 64 planes (D3Q7: 32; D3Q15 and
- * D3Q19 in binary64: 128), halved down to 4 while the grid would have fewer
- * than 512 blocks.
+ * row two or four waves, each holding a part of the directions: four for
+ * D3Q19 in binary32 at 3 or 4 rows and in binary64 at 2 rows, and for D3Q15
+ * the same on periodic meshes; two otherwise.  LDS per block: g of 3 planes
+ * of the rows and the two halo rows, raw f~ of 1 or 2 staged planes (of the
+ * rows and the halo rows; of the rows only in binary64 with four waves a
+ * row, whose halo rows go through registers) and 4 face sums per row and
+ * wave.  D3Q7 gives each row one wave (binary32: 5 x (rows + 2) x q x 64 x 4
+ * bytes of LDS; binary64: one more wave per halo row, 3 x (rows + 2) x q x
+ * 64 x 8 bytes).  A launch needing more LDS than the device allows per block
+ * is refused.  Defaults: 2 rows (binary64), 4 rows (binary32; D3Q15 with
+ * walls: 2); 64 planes (D3Q7: 32; D3Q15 and D3Q19 in binary64: 128), halved
+ * down to 4 while the grid would have fewer than 512 blocks.  Every launch
+ * gives bitwise the same result.
  * Errors: E_ARG. */
 int dugks3_set_launch(dugks3_ctx* ctx, int rows_per_block, int planes_per_block);
 
