@@ -317,9 +317,9 @@ int dugks3_create(dugks3_ctx** out, int nx, int ny, int nz, const double* xf, co
   // planes a block (D3Q7: 32; D3Q15 and D3Q19 in binary64: 128)
   const bool walls = p->bc[0] != DUGKS_BC_PERIODIC || p->bc[1] != DUGKS_BC_PERIODIC || p->bc[2] != DUGKS_BC_PERIODIC;
   x->launch.rows = p->storage == DUGKS_F64 ? 2 : ((q == 15 && walls) ? 2 : 4);
-  // shorter chunks on small grids until there are at least two blocks per CU
-  // of a 256-CU device (a chunk restages two halo planes; 64^3: 233 -> 42 us
-  // a step, 128^3: 240 -> 193 us)
+  // shorter chunks on small grids until the grid has at least 512 blocks (a
+  // chunk restages two halo planes; binary32 D3Q19 64^3: 157 -> 33 us a step,
+  // 128^3: 184 -> 146 us)
   {
     const long long strips = (nx + kCols - 1) / kCols, tiles = (ny + x->launch.rows - 1) / x->launch.rows;
     int planes = q == 7 ? 32 : (p->storage == DUGKS_F64 ? 128 : 64);
