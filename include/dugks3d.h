@@ -114,7 +114,8 @@ int dugks3_reduce(dugks3_ctx* ctx, const double* ref_dev, double* mass, double* 
  * bytes of LDS; binary64: one more wave per halo row, 3 x (rows + 2) x q x
  * 64 x 8 bytes).  A launch needing more LDS than the device allows per block
  * is refused.  Defaults: 2 rows (binary64), 4 rows (binary32; D3Q15 with
- * walls: 2); 64 planes (D3Q7: 32; D3Q15 and D3Q19 in binary64: 128), halved
+ * walls: 2); planes: D3Q15 and D3Q19 the power of two in 4..128 that
+ * minimises (rounds of blocks over 256 CUs) x (planes + 3), D3Q7 32 halved
  * down to 4 while the grid would have fewer than 512 blocks.  Every launch
  * gives bitwise the same result.
  * Errors: E_ARG. */

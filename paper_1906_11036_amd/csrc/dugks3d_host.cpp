@@ -312,19 +312,37 @@ int dugks3_create(dugks3_ctx** out, int nx, int ny, int nz, const double* xf, co
   x->stage_bytes = sizeof(double) * (size_t)q * x->cells();
   x->off_stage = off; off += align256(x->stage_bytes);
   x->total = off;
-  // default launch (fastest measured at 256^3): binary64 two rows; binary32
-  // four rows (D3Q15 with walls: two, which lets two blocks share a CU); 64
-  // planes a block (D3Q7: 32; D3Q15 and D3Q19 in binary64: 128)
+  // default launch: binary64 two rows; binary32 four rows (D3Q15 with
+  // walls: two, which lets two blocks share a CU) -- the fastest at 256^3
   const bool walls = p->bc[0] != DUGKS_BC_PERIODIC || p->bc[1] != DUGKS_BC_PERIODIC || p->bc[2] != DUGKS_BC_PERIODIC;
   x->launch.rows = p->storage == DUGKS_F64 ? 2 : ((q == 15 && walls) ? 2 : 4);
-  // shorter chunks on small grids until the grid has at least 512 blocks (a
-  // chunk restages two halo planes; binary32 D3Q19 64^3: 157 -> 33 us a step,
-  // 128^3: 184 -> 146 us)
+  // Planes a chunk.  D3Q15 and D3Q19: the blocks run in rounds of (CUs x
+  // blocks a CU, from the LDS: 160 KiB a CU) and a block takes about
+  // (planes + 3) plane times (its prologue stages and makes two planes), so
+  // take the length in 4..128 that minimises rounds x (planes + 3), the
+  // longer on a tie; 256 CUs.  This picks the fastest measured length on
+  // D3Q19 binary32 from 48^3 to 256^3 (64^3: 8 planes, 30 us a step; 192^3:
+  // 16, 428 us; 256^3: 64) and on binary64 and D3Q15 at 256^3.  D3Q7, whose
+  // smaller blocks share a CU: 32 planes, halved down to 4 while the grid has
+  // fewer than 512 blocks.
   {
     const long long strips = (nx + kCols - 1) / kCols, tiles = (ny + x->launch.rows - 1) / x->launch.rows;
-    int planes = q == 7 ? 32 : (p->storage == DUGKS_F64 ? 128 : 64);
-    while (planes > 4 && strips * tiles * ((nz + planes - 1) / planes) < 512) planes /= 2;
-    x->launch.planes = planes;
+    int best = 4;
+    if (q == 7) {
+      best = 32;
+      while (best > 4 && strips * tiles * ((nz + best - 1) / best) < 512) best /= 2;
+    } else {
+      const size_t lds = x->lds_bytes(x->launch);
+      const long long per_cu = std::max<long long>(1, (long long)(163840 / std::max<size_t>(lds, 1)));
+      const long long slots = 256 * per_cu;
+      long long best_cost = -1;
+      for (int planes = 128; planes >= 4; planes /= 2) {
+        const long long blocks = strips * tiles * ((nz + planes - 1) / planes);
+        const long long cost = ((blocks + slots - 1) / slots) * (planes + 3);
+        if (best_cost < 0 || cost < best_cost) { best_cost = cost; best = planes; }
+      }
+    }
+    x->launch.planes = best;
   }
   return DUGKS_OK;
 }
