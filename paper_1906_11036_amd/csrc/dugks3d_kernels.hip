@@ -856,8 +856,8 @@ template <int Q, int ROWS, typename T, bool WALLS> struct LdsP {
 // slot is refilled once every wave has read it.
 template <int Q, int NC, int ROWS, typename T, int H, bool WALLS>
 __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int parity, int planes, int strips,
-                                            int tiles, LdsP<Q, ROWS, T, WALLS>& L, const float* ecoef, int w,
-                                            int rw) {
+                                            int tiles, LdsP<Q, ROWS, T, WALLS>& L, const float* ecoef,
+                                            double (*hphi)[4][kLanes], int w, int rw) {
   using LP = LdsP<Q, ROWS, T, WALLS>;
   constexpr int P = parts<Q, T, ROWS, WALLS>();
   constexpr int W = LP::W, WD = LP::WD;
@@ -916,7 +916,7 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
   };
   // stage plane zp: this wave's directions of its row, and its share of the
   // two halo rows (offsets advance in a vector register)
-  T HR[LP::kHD ? Q : 1];   // raw f~ of the halo row this wave makes, when not staged
+  T HR[LP::kHD ? Q : 1];   // raw f~ of this wave's quarter of the halo row it makes, when not staged
   auto stage = [&](int slot, int zp) __attribute__((always_inline)) {
     unsigned o = cell_index(srow, zp) * ES;
     const int wme = LP::kHD ? me - 1 : me;
@@ -930,11 +930,12 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
       o += planeB;
     }
     if constexpr (LP::kHD) {
-      if (rw <= 1) {   // every direction of the halo row, into registers
+      if (rw <= 1) {   // this wave's quarter of the halo row, into registers
         unsigned oh = cell_index(rw == 0 ? slo : shi, zp) * ES;
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
-          HR[k] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(Rin, oh, 0u, 0));
+          if (part_of<Q, P>(k) == H)
+            HR[k] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(Rin, oh, 0u, 0));
           oh += planeB;
         }
       }
@@ -969,22 +970,26 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
   // (fromreg: the raw values are the halo row's in HR)
   auto make_g = [&](int slot, int row, bool wy, int zp, T* g, T* f, auto fromreg) __attribute__((always_inline)) {
     constexpr bool kReg = decltype(fromreg)::value;
-    // binary64: four chains, then a pairwise combine (one wave per SIMD
-    // waits out every link of a chain); binary32: one chain
-    constexpr int NA = WD == 2 ? 4 : 1;
-    double acc[NA];
+    // phi in binary64 as (q0 + q1) + (q2 + q3), qj the sum over quarter j in
+    // index order (four chains); a halo row in registers takes the quarters'
+    // sums from LDS
+    double phi;
+    if constexpr (kReg) {
 #pragma unroll
-    for (int a = 0; a < NA; ++a) acc[a] = 0.0;
+      for (int k = 0; k < Q; ++k)
+        if (part_of<Q, P>(k) == H) f[k] = HR[k];
+      const int hr = rw;   // 0: the lower halo row, 1: the upper
+      phi = (hphi[hr][0][lane] + hphi[hr][1][lane]) + (hphi[hr][2][lane] + hphi[hr][3][lane]);
+    } else {
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int k = 0; k < Q; ++k) {
-      T v;
-      if constexpr (kReg) v = HR[k];
-      else v = raw_at(slot, row, k);
-      acc[k % NA] += (double)v;
-      if (part_of<Q, P>(k) == H) f[k] = v;
+      for (int k = 0; k < Q; ++k) {
+        const T v = raw_at(slot, row, k);
+        acc[part_of<Q, 4>(k)] += (double)v;
+        if (part_of<Q, P>(k) == H) f[k] = v;
+      }
+      phi = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     }
-    double phi = acc[0];
-    if constexpr (NA == 4) phi = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     const T p = (T)phi, ra = C3<T>::ra(I);
 #pragma unroll
     for (int k = 0; k < Q; ++k)
@@ -1002,6 +1007,19 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
   };
   // g of plane zp for this wave's row (G, and f~+ in FT) and, for the waves
   // of rows 0 and 1, the halo rows; all published to slot `slot`
+  // halo rows in registers: this wave's quarter sum of the cell phi of its
+  // halo row, to LDS (the loads must have completed; a barrier before use)
+  auto halo_sums = [&]() __attribute__((always_inline)) {
+    if constexpr (LP::kHD) {
+      if (rw <= 1) {
+        double q = 0.0;
+#pragma unroll
+        for (int k = 0; k < Q; ++k)
+          if (part_of<Q, P>(k) == H) q += (double)HR[k];
+        hphi[rw][H][lane] = q;
+      }
+    }
+  };
   auto plane_g = [&](int rs, int zp, int slot, T* G, T* FT) __attribute__((always_inline)) {
     using Staged = std::integral_constant<bool, false>;
     using Halo = std::integral_constant<bool, LP::kHD>;
@@ -1059,11 +1077,13 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
   } else {
     stage(0, z0 - 1);
     wait_vm_all();
+    halo_sums();
     lds_barrier();
     plane_g(0, z0 - 1, 2, G1, FT1);
     lds_barrier();
     stage(0, z0);
     wait_vm_all();
+    halo_sums();
     lds_barrier();
     plane_g(0, z0, 0, G0, O);
     lds_barrier();
@@ -1089,6 +1109,7 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
   lds_barrier();
   if (inner) face_out<Q, P, H, 2>(I, ev, gbB, total(0, sB), FZb);
   wait_vm_all();
+  halo_sums();   // plane z0+1
   lds_barrier();
 
   auto body = [&](int z, auto rsl) __attribute__((always_inline)) {
@@ -1165,6 +1186,7 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
       put_sum(3, sT);
     }
     wait_vm_all();   // this wave's loads of plane z+2 (and its older stores) are done
+    if (z + 2 <= z1) halo_sums();
     // both halves' sums and the whole staged plane z+2 are in LDS; slot sm
     // (read only above) is free for the next plane's g
     lds_barrier();
@@ -1240,14 +1262,19 @@ __global__ __launch_bounds__((64 * parts<Q, T, ROWS, WALLS>() * ROWS)) void k_st
       for (int i = threadIdx.x; i < Q * NC; i += kLanes) ecoef[i] = I->ef[i / NC][i % NC];
     ec = ecoef;
   }
+  double (*hp)[4][kLanes] = nullptr;
+  if constexpr (LdsP<Q, ROWS, T, WALLS>::kHD) {
+    __shared__ double hphi[2][4][kLanes];   // quarter sums of the cell phi of the two halo rows
+    hp = hphi;
+  }
   switch (part) {
-    case 0: step3p_half<Q, NC, ROWS, T, 0, WALLS>(I, parity, planes, strips, tiles, L, ec, w, rw); break;
-    case 1: step3p_half<Q, NC, ROWS, T, 1, WALLS>(I, parity, planes, strips, tiles, L, ec, w, rw); break;
+    case 0: step3p_half<Q, NC, ROWS, T, 0, WALLS>(I, parity, planes, strips, tiles, L, ec, hp, w, rw); break;
+    case 1: step3p_half<Q, NC, ROWS, T, 1, WALLS>(I, parity, planes, strips, tiles, L, ec, hp, w, rw); break;
     case 2:
-      if constexpr (P > 2) step3p_half<Q, NC, ROWS, T, 2, WALLS>(I, parity, planes, strips, tiles, L, ec, w, rw);
+      if constexpr (P > 2) step3p_half<Q, NC, ROWS, T, 2, WALLS>(I, parity, planes, strips, tiles, L, ec, hp, w, rw);
       break;
     default:
-      if constexpr (P > 2) step3p_half<Q, NC, ROWS, T, 3, WALLS>(I, parity, planes, strips, tiles, L, ec, w, rw);
+      if constexpr (P > 2) step3p_half<Q, NC, ROWS, T, 3, WALLS>(I, parity, planes, strips, tiles, L, ec, hp, w, rw);
       break;
   }
 }
@@ -1498,8 +1525,9 @@ size_t step3_lds_bytes(int storage, int q, bool walls, const Launch3& l) {
   const bool quarters = q == 19 || (q == 15 && !walls);
   const size_t np = (quarters && ((storage != DUGKS_F64 && l.rows >= 3) || (storage == DUGKS_F64 && l.rows == 2))) ? 4 : 2;
   const size_t rr = (storage == DUGKS_F64 && np == 4) ? l.rows : l.rows + 2;   // staged_rows<>()
+  const size_t hs = rr == (size_t)l.rows ? (size_t)2 * 4 * kLanes * 8 : 0;        // halo rows' phi sums
   auto bytes = [&](size_t ns) {
-    return 3 * (l.rows + 2) * q * kLanes * e + ns * rr * q * kLanes * e + (size_t)4 * l.rows * np * kLanes * e;
+    return 3 * (l.rows + 2) * q * kLanes * e + ns * rr * q * kLanes * e + (size_t)4 * l.rows * np * kLanes * e + hs;
   };
   if (storage == DUGKS_F64) return bytes(1);
   return (bytes(2) > 81920 && bytes(1) <= 81920) ? bytes(1) : bytes(2);
