@@ -729,10 +729,11 @@ template <int Q, typename T, int ROWS, bool WALLS> constexpr int parts() {
   constexpr bool quarters = Q == 19 || (Q == 15 && !WALLS);
   return (quarters && ((sizeof(T) == 4 && ROWS >= 3) || (sizeof(T) == 8 && ROWS == 2))) ? 4 : 2;
 }
-// rows of raw f~ staged in LDS: the tile's rows and its two halo rows, or
-// only the tile's rows when binary64 loads the halo rows into registers
+// rows of raw f~ staged in LDS: the tile's rows and its two halo rows, or,
+// with four waves a row, only the tile's rows (each wave that makes a halo
+// row loads its quarter of it into registers)
 template <int Q, typename T, int ROWS, bool WALLS> constexpr int staged_rows() {
-  return (sizeof(T) == 8 && parts<Q, T, ROWS, WALLS>() == 4) ? ROWS : ROWS + 2;
+  return parts<Q, T, ROWS, WALLS>() == 4 ? ROWS : ROWS + 2;
 }
 template <int Q, int P> __host__ __device__ constexpr int part_of(int k) {
   if (P == 2) return half_of<Q>(k);
@@ -934,8 +935,12 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
         unsigned oh = cell_index(rw == 0 ? slo : shi, zp) * ES;
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
-          if (part_of<Q, P>(k) == H)
-            HR[k] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(Rin, oh, 0u, 0));
+          if (part_of<Q, P>(k) == H) {
+            if constexpr (WD == 2)
+              HR[k] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(Rin, oh, 0u, 0));
+            else
+              HR[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(Rin, oh, 0u, 0));
+          }
           oh += planeB;
         }
       }
@@ -1058,7 +1063,28 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
 
   // prologue: planes z0-1 (slot 2 of g) and z0 (slot 0), plane z0+1 staged,
   // the bottom face of plane z0
-  if constexpr (two) {
+  if constexpr (two && LP::kHD) {   // one plane of halo registers: planes one at a time
+    stage(1, z0 - 1);
+    wait_vm_all();
+    halo_sums();
+    lds_barrier();
+    if constexpr (kVecE) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k)
+        if (part_of<Q, P>(k) == H)
+#pragma unroll
+          for (int m = 0; m < NC; ++m) ev.c[k][m] = ecoef[k * NC + m];
+    }
+    plane_g(1, z0 - 1, 2, G1, FT1);
+    lds_barrier();
+    stage(0, z0);
+    wait_vm_all();
+    halo_sums();
+    lds_barrier();
+    plane_g(0, z0, 0, G0, O);
+    lds_barrier();
+    stage(1, z0 + 1);   // z1 >= z0 + 1
+  } else if constexpr (two) {
     stage(1, z0 - 1);
     stage(0, z0);
     wait_vm_all();
@@ -1524,7 +1550,7 @@ size_t step3_lds_bytes(int storage, int q, bool walls, const Launch3& l) {
   // parts<Q, T, ROWS, WALLS>(), walls meaning the instantiation with mirror code
   const bool quarters = q == 19 || (q == 15 && !walls);
   const size_t np = (quarters && ((storage != DUGKS_F64 && l.rows >= 3) || (storage == DUGKS_F64 && l.rows == 2))) ? 4 : 2;
-  const size_t rr = (storage == DUGKS_F64 && np == 4) ? l.rows : l.rows + 2;   // staged_rows<>()
+  const size_t rr = np == 4 ? l.rows : l.rows + 2;   // staged_rows<>()
   const size_t hs = rr == (size_t)l.rows ? (size_t)2 * 4 * kLanes * 8 : 0;        // halo rows' phi sums
   auto bytes = [&](size_t ns) {
     return 3 * (l.rows + 2) * q * kLanes * e + ns * rr * q * kLanes * e + (size_t)4 * l.rows * np * kLanes * e + hs;
