@@ -830,9 +830,12 @@ __device__ __forceinline__ void face_out(const Inst3* __restrict__ I, const EQ& 
 }
 
 // LDS bytes of a block with ns staging slots (E coefficients aside)
+// LDS of a block with ns staging slots, the halo rows' phi sums (binary64,
+// when those rows go through registers) included
 template <int Q, int ROWS, typename T, bool WALLS> constexpr int lds_p_bytes(int ns) {
   return 3 * (ROWS + 2) * Q * kLanes * (int)sizeof(T) + ns * staged_rows<Q, T, ROWS, WALLS>() * Q * kLanes * (int)sizeof(T) +
-         4 * ROWS * parts<Q, T, ROWS, WALLS>() * kLanes * (int)sizeof(T);
+         4 * ROWS * parts<Q, T, ROWS, WALLS>() * kLanes * (int)sizeof(T) +
+         (staged_rows<Q, T, ROWS, WALLS>() == ROWS ? 2 * 4 * kLanes * 8 : 0);
 }
 template <int Q, int ROWS, typename T, bool WALLS> struct LdsP {
   static constexpr int W = ROWS + 2;             // LDS rows: y0-1 .. y0+ROWS
