@@ -108,9 +108,12 @@ int dugks3_reduce(dugks3_ctx* ctx, const double* ref_dev, double* mass, double* 
  * D3Q19 in binary32 at 3 or 4 rows and in binary64 at 2 rows, and for D3Q15
  * the same on periodic meshes; two otherwise.  LDS per block: g of 3 planes
  * of the rows and the two halo rows, raw f~ of 1 or 2 staged planes (of the
- * rows and the halo rows; of the rows only in binary64 with four waves a
- * row, whose halo rows go through registers) and 4 face sums per row and
- * wave.  D3Q7 gives each row one wave (binary32: 5 x (rows + 2) x q x 64 x 4
+ * rows and the halo rows with two waves a row; of the rows only with four,
+ * whose halo rows go through registers), 4 face sums per row and wave, and
+ * with the halo rows in registers their four quarter sums of phi (2 x 4 x 64
+ * binary64).  Binary32 takes one staging slot where that alone brings a
+ * block within 80 KiB (two blocks a CU), else two; binary64 one.  D3Q7
+ * gives each row one wave (binary32: 5 x (rows + 2) x q x 64 x 4
  * bytes of LDS; binary64: one more wave per halo row, 3 x (rows + 2) x q x
  * 64 x 8 bytes).  A launch needing more LDS than the device allows per block
  * is refused.  Defaults: 2 rows (binary64), 4 rows (binary32; D3Q15 with
