@@ -277,3 +277,68 @@ def test_eight_wave_blocks_only_at_two_waves_per_simd():
             assert info.waves_per_block == 4
             assert lib.dugks_set_launch(h, 8, 8, 0, 1) == L.E_ARG
         lib.dugks_destroy(h)
+
+
+def _lds3(q, f32, rows, walls):
+    """LDS bytes of a D3Q15/D3Q19 block as the launch documentation states
+    them: g of 3 planes of rows + 2 rows; staged f~ of 1 or 2 planes (rows + 2
+    rows with two waves a row, the rows alone with four, whose halo rows go
+    through registers); 4 face sums per row and wave; with the halo rows in
+    registers 2 x 4 x 64 binary64 phi sums.  Binary32 takes one slot where that
+    alone brings the block within 80 KiB, binary64 always one."""
+    e = 4 if f32 else 8
+    four = (q == 19 or not walls) and ((f32 and rows >= 3) or (not f32 and rows == 2))
+    parts = 4 if four else 2
+    staged = rows if four else rows + 2
+    hs = 2 * 4 * 64 * 8 if four else 0
+    def size(ns):
+        return 3 * (rows + 2) * q * 64 * e + ns * staged * q * 64 * e + 4 * rows * parts * 64 * e + hs
+    if not f32:
+        return size(1)
+    return size(1) if size(2) > 81920 and size(1) <= 81920 else size(2)
+
+
+def _default_launch3(nx, ny, nz, q, f32, walls):
+    """The default launch as documented: rows 2 (binary64) or 4 (binary32;
+    D3Q15 with walls 2); planes for D3Q15/19 the power of two in 4..128
+    minimising (rounds of blocks over 256 CUs x blocks a CU) x (planes + 3),
+    the longer on a tie; D3Q7 32 halved down to 4 while under 512 blocks."""
+    rows = 2 if not f32 or (q == 15 and walls) else 4
+    strips, tiles = -(-nx // 62), -(-ny // rows)
+    if q == 7:
+        planes = 32
+        while planes > 4 and strips * tiles * -(-nz // planes) < 512:
+            planes //= 2
+    else:
+        slots = 256 * max(1, 163840 // _lds3(q, f32, rows, walls))
+        best = None
+        for pl in (128, 64, 32, 16, 8, 4):
+            cost = -(-(strips * tiles * -(-nz // pl)) // slots) * (pl + 3)
+            if best is None or cost < best[0]:
+                best = (cost, pl)
+        planes = best[1]
+    return rows, planes, strips * tiles * -(-nz // planes)
+
+
+@pytest.mark.parametrize("q", [19, 15, 7])
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+@pytest.mark.parametrize("bc", [(0, 0, 0), (2, 0, 2)])
+def test_3d_default_launch_follows_the_documented_model(q, storage, bc):
+    """Host logic only (no device work): the default rows, chunk length and
+    block count of dugks3_create against the rule the header documents, on
+    cubes and ragged boxes; at 256^3 the measured best (64 planes binary32,
+    128 binary64 for D3Q19)."""
+    lib = L.lib()
+    f32 = storage == "f32"
+    walls = any(b != 0 for b in bc)
+    for nx, ny, nz in ((48, 48, 48), (64, 64, 64), (128, 128, 128), (192, 192, 192), (256, 256, 256),
+                       (100, 37, 211), (31, 5, 300), (300, 200, 150), (1, 1, 1), (700, 3, 9)):
+        rc, h = _create3(nx=nx, ny=ny, nz=nz, q=q, storage=L.F32 if f32 else L.F64, bc=bc)
+        assert rc == L.OK, lib.dugks3_last_error(h)
+        info = L.Info3()
+        assert lib.dugks3_get_info(h, C.byref(info)) == L.OK
+        got = (info.rows_per_block, info.planes_per_block, info.blocks)
+        lib.dugks3_destroy(h)
+        assert got == _default_launch3(nx, ny, nz, q, f32, walls), (nx, ny, nz)
+        if (nx, ny, nz) == (256, 256, 256) and q == 19:
+            assert got[1] == (64 if f32 else 128)
