@@ -66,7 +66,7 @@
 extern "C" {
 #endif
 
-#define DUGKS_ABI_VERSION 2
+#define DUGKS_ABI_VERSION 3
 #define DUGKS_MAX_DEG 4        /* B and D: polynomials in phi of degree <= 4 */
 
 /* return codes */
@@ -127,6 +127,8 @@ typedef struct dugks_info {
   int xcd_remap;
   long long work_items;
   size_t state_bytes;     /* bytes of one f~ buffer (read once and written once per step) */
+  long long graph_steps;  /* steps replayed from captured hipGraphs since dugks_bind */
+  long long eager_steps;  /* steps launched one by one since dugks_bind */
 } dugks_info;
 
 typedef struct dugks_diag {
@@ -202,8 +204,13 @@ int dugks_set_phi(dugks_ctx* ctx, const double* phi, int on_device);
  * format) and reset step and time to 0. */
 int dugks_set_f(dugks_ctx* ctx, const double* f, int on_device);
 
-/* Advance nsteps >= 0 steps, asynchronously on the bound stream.  Errors:
- * E_STATE (not initialised, Dirichlet data exhausted), E_HIP. */
+/* Advance nsteps >= 0 steps, asynchronously on the bound stream.  Runs of
+ * four or more steps that start at a step divisible by 4 are replayed from
+ * captured hipGraphs of 32 and 4 steps (captured on first use on a stream of
+ * the library's own, launched on the bound stream); the rest, and every step
+ * with Dirichlet data or a source (their kernels read the step's time), are
+ * launched one by one.  dugks_info counts both kinds.  Errors: E_STATE (not
+ * initialised, Dirichlet data exhausted), E_HIP. */
 int dugks_step(dugks_ctx* ctx, int nsteps);
 
 /* phi = sum_i f~_i (Sec. 2; plus dt F / 2 at the current time with a source)
@@ -245,8 +252,10 @@ int dugks_set_launch(dugks_ctx* ctx, int rows_per_wave, int waves_per_block, int
                      int xcd_remap);
 
 /* Time trial_steps steps for each candidate launch configuration and keep the
- * fastest.  Writes only the inactive buffer: the state is unchanged.
- * Synchronises.  Errors: E_STATE, E_HIP. */
+ * fastest.  Writes only the inactive buffer: the state is unchanged.  Every
+ * trial step reads the Dirichlet data of the current step.  Synchronises.
+ * Errors: E_STATE (no state, or Dirichlet data not covering the current
+ * step), E_HIP. */
 int dugks_autotune(dugks_ctx* ctx, int trial_steps);
 
 /* Constants and the launch configuration in use. */
@@ -272,7 +281,12 @@ typedef struct dugks_instance_desc {
 int dugks_batch_create(dugks_batch** out, int n, const dugks_instance_desc* desc, int storage);
 size_t dugks_batch_workspace_bytes(const dugks_batch* b);
 int dugks_batch_bind(dugks_batch* b, void* dev_workspace, size_t bytes, void* hip_stream);
-/* f~ = E(phi) for instance i (phi [ny_i][nx_i]); resets the batch clock. */
+/* f~ = E(phi) for instance i (phi [ny_i][nx_i]).  The batch has one clock
+ * (one step count, buffer parity and 16-bit scale phase for all instances):
+ * instance i starts at step 0.  If the batch has stepped since its instances
+ * were last set, every other instance then holds a state of another step and
+ * is marked stale: stepping, autotuning and reading a stale instance return
+ * E_STATE until each instance has been set again. */
 int dugks_batch_set_phi(dugks_batch* b, int i, const double* phi, int on_device);
 /* Source of instance i, as dugks_set_source (g_dev [ny_i][nx_i]).  A launch
  * over a batch in which some instance has a source evaluates the source path
@@ -282,8 +296,9 @@ int dugks_batch_set_source(dugks_batch* b, int i, const double* g_dev, double ga
 int dugks_batch_autotune(dugks_batch* b, int trial_steps);
 int dugks_batch_set_launch(dugks_batch* b, int rows_per_wave, int waves_per_block, int schedule,
                            int xcd_remap);
-/* Advance every instance nsteps steps (each with its own dt); the steps are
- * replayed from a captured hipGraph when nsteps is large enough. */
+/* Advance every instance nsteps steps (each with its own dt), replayed from
+ * captured hipGraphs as dugks_step describes.  Errors: E_STATE (an instance
+ * without a state at the batch clock), E_HIP. */
 int dugks_batch_step(dugks_batch* b, int nsteps);
 int dugks_batch_get_phi(dugks_batch* b, int i, double* out, int on_device);
 int dugks_batch_get_info(const dugks_batch* b, int i, dugks_info* out);

@@ -92,6 +92,8 @@ typedef struct {
   double *f;              /* f~ [q][ny][nx] */
   long step;
   double t;
+  /* work arrays of one step, allocated on the first step and kept */
+  double *wG, *wSY, *wSX, *wFX, *wFY, *wfn;
 } Oracle;
 
 /* ---------------------------------------------------------------- lattice */
@@ -267,6 +269,7 @@ void or_destroy(Oracle* o) {
   if (!o) return;
   free(o->xf); free(o->yf); free(o->wx); free(o->wy); free(o->xc); free(o->yc); free(o->f);
   free(o->src_g);
+  free(o->wG); free(o->wSY); free(o->wSX); free(o->wFX); free(o->wFY); free(o->wfn);
   free(o);
 }
 
@@ -503,15 +506,19 @@ static void step_once(Oracle* o, const double* ring) {
   const int nx = o->nx, ny = o->ny, q = o->q;
   const size_t N = (size_t)nx * ny;
   const int NX2 = nx + 2;
-  double* G = (double*)malloc(sizeof(double) * (size_t)(nx + 2) * (ny + 2) * q);
-  double* SY = (double*)malloc(sizeof(double) * (size_t)(nx + 2) * ny * q);
-  double* SX = (double*)malloc(sizeof(double) * (size_t)nx * (ny + 2) * q);
-  double* FX = (double*)malloc(sizeof(double) * (size_t)(nx + 1) * ny * q);
-  double* FY = (double*)malloc(sizeof(double) * (size_t)nx * (ny + 1) * q);
-  double* fn = (double*)malloc(sizeof(double) * N * q);
+  double *G, *SY, *SX, *FX, *FY, *fn;
   double zx[OR_MAXQ], zy[OR_MAXQ];
   int i, j, k;
 #define GP(i, j) (G + ((size_t)((j) + 1) * NX2 + ((i) + 1)) * q)
+  if (!o->wG) {
+    o->wG = (double*)malloc(sizeof(double) * (size_t)(nx + 2) * (ny + 2) * q);
+    o->wSY = (double*)malloc(sizeof(double) * (size_t)(nx + 2) * ny * q);
+    o->wSX = (double*)malloc(sizeof(double) * (size_t)nx * (ny + 2) * q);
+    o->wFX = (double*)malloc(sizeof(double) * (size_t)(nx + 1) * ny * q);
+    o->wFY = (double*)malloc(sizeof(double) * (size_t)nx * (ny + 1) * q);
+    o->wfn = (double*)malloc(sizeof(double) * N * q);
+  }
+  G = o->wG; SY = o->wSY; SX = o->wSX; FX = o->wFX; FY = o->wFY; fn = o->wfn;
   for (k = 0; k < q; ++k) { zx[k] = o->cx[k]; zy[k] = o->cy[k]; }
   /* 1-2: fbar+ on interior and ghost cells */
 #pragma omp parallel for private(i)
@@ -557,8 +564,9 @@ static void step_once(Oracle* o, const double* ring) {
       for (k = 0; k < q; ++k) fn[k * N + c] = out[k];
     }
 #undef GP
-  memcpy(o->f, fn, sizeof(double) * N * q);
-  free(G); free(SY); free(SX); free(FX); free(FY); free(fn);
+  /* the new state becomes f~; the old array is the next step's output */
+  o->wfn = o->f;
+  o->f = fn;
   o->step += 1;
   o->t += o->dt;
 }

@@ -159,11 +159,15 @@ class Solver:
     def get_phi(self) -> np.ndarray:
         return self.phi_tensor().cpu().numpy()
 
-    def get_f(self) -> np.ndarray:
+    def f_tensor(self):
+        """f~ decoded to binary64 [q][ny][nx], a device tensor."""
         torch = _torch()
         out = torch.empty((self.q, self.ny, self.nx), dtype=torch.float64, device=self.device)
         L.check(self.lib.dugks_get_f(self.h, C.c_void_p(out.data_ptr()), 1), self.h, "dugks_get_f")
-        return out.cpu().numpy()
+        return out
+
+    def get_f(self) -> np.ndarray:
+        return self.f_tensor().cpu().numpy()
 
     def diag(self, check=True) -> dict:
         d = L.Diag()

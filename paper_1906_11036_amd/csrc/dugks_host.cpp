@@ -20,7 +20,10 @@ namespace dugks {
 
 static constexpr uint32_t kMagicCtx = 0x44554731u;    // "DUG1"
 static constexpr uint32_t kMagicBatch = 0x44554742u;  // "DUGB"
-static constexpr int kGraphSteps = 32;                // steps per captured graph (multiple of 4)
+// Steps per captured graph: a long graph for long runs and a short one so that
+// any run of four or more steps from a phase-0 step replays a graph.  Both are
+// multiples of 4, the period of the buffer parity and the 16-bit scale slots.
+static constexpr int kGraphSteps[2] = {32, 4};
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -243,14 +246,15 @@ struct Engine {
   std::vector<WorkItem> items;
   Launch launch;
   int persistent_blocks = 0;
-  // clock
-  bool initialised = false;
+  // clock: every instance whose ready flag is set holds its state at `step`
+  std::vector<char> ready;
   long long step = 0;
   bool need_measure = false;
-  // graph
-  hipGraphExec_t graph_exec = nullptr;
-  hipGraph_t graph = nullptr;
+  // graphs (kGraphSteps[0] and kGraphSteps[1] steps from a phase-0 step)
+  hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+  hipGraph_t graph[2] = {nullptr, nullptr};
   bool use_graph = true;
+  long long graph_steps = 0, eager_steps = 0;   // steps replayed / launched one by one
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
   int ncoef_launch() const {
@@ -436,7 +440,8 @@ struct Engine {
       persistent_blocks = cus * (16 / launch.waves_per_block);
     else
       persistent_blocks = 256 * 4;
-    initialised = false;
+    ready.assign(inst.size(), 0);
+    step = 0;
     int rc = upload_tables();
     if (rc) return rc;
     for (auto& in : inst) {
@@ -448,6 +453,11 @@ struct Engine {
   }
 
   bool bound() const { return ws != nullptr; }
+  int state_error_for(int k) {
+    if (!bound()) return fail(DUGKS_E_STATE, "not bound");
+    if (inst.size() == 1) return fail(DUGKS_E_STATE, "no state (set_phi / set_f)");
+    return fail(DUGKS_E_STATE, "instance " + std::to_string(k) + " holds no state at the batch clock");
+  }
 
   const InstDev* dev_table() const { return (const InstDev*)(ws + off_table); }
   const InstDev* dev_inst(int k) const { return dev_table() + k; }
@@ -469,6 +479,42 @@ struct Engine {
 
   bool neq() const { return storage == DUGKS_F16NEQ || storage == DUGKS_BF16NEQ; }
 
+  bool all_ready() const {
+    if (ready.size() != inst.size()) return false;
+    for (char r : ready)
+      if (!r) return false;
+    return true;
+  }
+  bool is_ready(int k) const { return k >= 0 && k < (int)ready.size() && ready[k]; }
+  int first_unready() const {
+    for (size_t k = 0; k < inst.size(); ++k)
+      if (k >= ready.size() || !ready[k]) return (int)k;
+    return -1;
+  }
+  int state_error() {
+    const int k = first_unready();
+    if (inst.size() == 1) return fail(DUGKS_E_STATE, "state not initialised (set_phi / set_f)");
+    return fail(DUGKS_E_STATE, "instance " + std::to_string(k) +
+                                   " holds no state at the batch clock: after a per-instance "
+                                   "set_phi / set_f on a stepped batch, every instance must be set again");
+  }
+  // A per-instance initialisation puts instance k at step 0.  If the engine has
+  // stepped, the others hold states of another step (and the other buffer
+  // parity and 16-bit slot phase): they are marked stale until set again.
+  void restart_clock_for(int k) {
+    if (step != 0 || ready.size() != inst.size()) ready.assign(inst.size(), 0);
+    step = 0;
+    ready[k] = 1;
+  }
+  // Dirichlet data covers steps [step, step + n)
+  bool rings_cover(long long n) const {
+    for (auto& in : inst)
+      if ((in.bcx == DUGKS_BC_DIRICHLET || in.bcy == DUGKS_BC_DIRICHLET) &&
+          (in.ring == nullptr || step + n > in.ring_steps))
+        return false;
+    return true;
+  }
+
   // Enqueue one step with input index n on stream s.
   int enqueue_step(long long n, hipStream_t s, bool measure) {
     StepArgs a = step_args(n);
@@ -487,22 +533,25 @@ struct Engine {
   }
 
   void drop_graph() {
-    if (graph_exec) { (void)hipGraphExecDestroy(graph_exec); graph_exec = nullptr; }
-    if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
+    for (int w = 0; w < 2; ++w) {
+      if (graph_exec[w]) { (void)hipGraphExecDestroy(graph_exec[w]); graph_exec[w] = nullptr; }
+      if (graph[w]) { (void)hipGraphDestroy(graph[w]); graph[w] = nullptr; }
+    }
   }
 
-  int build_graph() {
-    // kGraphSteps steps starting at an index divisible by 4 (parity 0, slot phase 0)
+  // Capture kGraphSteps[w] steps starting at step index 0; replayed at any step
+  // divisible by 4 (same buffer parity and 16-bit slot phase).
+  int build_graph(int w) {
     hipError_t e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeRelaxed);
     if (e != hipSuccess) return hipfail(e, "begin capture");
     int rc = DUGKS_OK;
-    for (int k = 0; k < kGraphSteps && rc == DUGKS_OK; ++k) rc = enqueue_step(k, cap_stream, false);
+    for (int k = 0; k < kGraphSteps[w] && rc == DUGKS_OK; ++k) rc = enqueue_step(k, cap_stream, false);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(cap_stream, &g);
     if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
     if (e != hipSuccess) return hipfail(e, "end capture");
-    graph = g;
-    e = hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0);
+    graph[w] = g;
+    e = hipGraphInstantiate(&graph_exec[w], graph[w], nullptr, nullptr, 0);
     if (e != hipSuccess) { drop_graph(); return hipfail(e, "instantiate graph"); }
     return DUGKS_OK;
   }
@@ -510,11 +559,8 @@ struct Engine {
   int do_steps(int nsteps) {
     if (nsteps < 0) return fail(DUGKS_E_ARG, "nsteps < 0");
     if (!bound()) return fail(DUGKS_E_STATE, "not bound");
-    if (!initialised) return fail(DUGKS_E_STATE, "state not initialised (set_phi / set_f)");
-    for (auto& in : inst)
-      if ((in.bcx == DUGKS_BC_DIRICHLET || in.bcy == DUGKS_BC_DIRICHLET) &&
-          (in.ring == nullptr || step + nsteps > in.ring_steps))
-        return fail(DUGKS_E_STATE, "Dirichlet data does not cover the requested steps");
+    if (!all_ready()) return state_error();
+    if (!rings_cover(nsteps)) return fail(DUGKS_E_STATE, "Dirichlet data does not cover the requested steps");
     int remaining = nsteps;
     // captured launches keep their step argument: steps whose kernels read the
     // step's time (Dirichlet rings, sources) launch one by one
@@ -525,20 +571,23 @@ struct Engine {
         if (rc) return rc;
         need_measure = false;
       }
-      if (graphable && remaining >= kGraphSteps && (step & 3) == 0) {
-        if (!graph_exec) {
-          int rc = build_graph();
+      const int w = remaining >= kGraphSteps[0] ? 0 : 1;
+      if (graphable && remaining >= kGraphSteps[1] && (step & 3) == 0) {
+        if (!graph_exec[w]) {
+          int rc = build_graph(w);
           if (rc) return rc;
         }
-        hipError_t e = hipGraphLaunch(graph_exec, stream);
+        hipError_t e = hipGraphLaunch(graph_exec[w], stream);
         if (e != hipSuccess) return hipfail(e, "graph launch");
-        step += kGraphSteps;
-        remaining -= kGraphSteps;
+        step += kGraphSteps[w];
+        remaining -= kGraphSteps[w];
+        graph_steps += kGraphSteps[w];
       } else {
         int rc = enqueue_step(step, stream, false);
         if (rc) return rc;
         step += 1;
         remaining -= 1;
+        eager_steps += 1;
       }
     }
     return DUGKS_OK;
@@ -600,8 +649,7 @@ struct Engine {
     if (tmp) (void)hipFree(tmp);
     if (rc) return fail(DUGKS_E_HIP, "init launch failed");
     if (e != hipSuccess) return hipfail(e, "set_phi");
-    step = 0;
-    initialised = true;
+    restart_clock_for(k);
     need_measure = neq();
     return DUGKS_OK;
   }
@@ -629,8 +677,7 @@ struct Engine {
     if (tmp) (void)hipFree(tmp);
     if (rc) return fail(DUGKS_E_HIP, "encode launch failed");
     if (e != hipSuccess) return hipfail(e, "set_f");
-    step = 0;
-    initialised = true;
+    restart_clock_for(k);
     need_measure = neq();
     return DUGKS_OK;
   }
@@ -658,7 +705,7 @@ struct Engine {
   }
 
   int get_phi(int k, double* out, int on_device) {
-    if (!bound() || !initialised) return fail(DUGKS_E_STATE, "no state");
+    if (!bound() || !is_ready(k)) return state_error_for(k);
     if (!out) return fail(DUGKS_E_ARG, "out is NULL");
     const Instance& in = inst[k];
     return read_out((size_t)in.cells() * sizeof(double), out, on_device, [&](double* dst) {
@@ -667,7 +714,7 @@ struct Engine {
   }
 
   int get_f(int k, double* out, int on_device) {
-    if (!bound() || !initialised) return fail(DUGKS_E_STATE, "no state");
+    if (!bound() || !is_ready(k)) return state_error_for(k);
     if (!out) return fail(DUGKS_E_ARG, "out is NULL");
     const Instance& in = inst[k];
     return read_out((size_t)in.cells() * in.q * sizeof(double), out, on_device, [&](double* dst) {
@@ -676,7 +723,7 @@ struct Engine {
   }
 
   int reduce(int k, const double* ref, double out[8], unsigned* flags, float slots[4]) {
-    if (!bound() || !initialised) return fail(DUGKS_E_STATE, "no state");
+    if (!bound() || !is_ready(k)) return state_error_for(k);
     Instance& in = inst[k];
     int rc = launch_reduce_widths(dev_inst(k), host_table[k], ref, (int)(step & 1), step,
                                   (const double*)(ws + in.off_widths), (double*)(ws + off_partial),
@@ -708,9 +755,12 @@ struct Engine {
   // Time candidate launch configurations on the inactive buffer only: the
   // step writes buffer (step+1)&1 and never swaps, so the state is kept.
   int autotune(int trials) {
-    if (!bound() || !initialised) return fail(DUGKS_E_STATE, "no state");
+    if (!bound()) return fail(DUGKS_E_STATE, "not bound");
+    if (!all_ready()) return state_error();
     if (trials < 1) trials = 1;
     if (plain) return DUGKS_OK;
+    // every trial step reads the Dirichlet data of the current step
+    if (!rings_cover(1)) return fail(DUGKS_E_STATE, "Dirichlet data does not cover the current step");
     // keep the 16-bit slots: the trial steps accumulate into them
     std::vector<std::vector<float>> saved(inst.size(), std::vector<float>(4));
     for (size_t k = 0; k < inst.size(); ++k) {
@@ -770,6 +820,8 @@ struct Engine {
     o->xcd_remap = launch.xcd_remap;
     o->work_items = (long long)items.size();
     o->state_bytes = in.buffer_bytes(storage);
+    o->graph_steps = graph_steps;
+    o->eager_steps = eager_steps;
   }
 
   ~Engine() {
@@ -1005,7 +1057,7 @@ int dugks_checkpoint(dugks_ctx* ctx, void* host_buf, size_t* len) {
   const size_t need = sizeof(dugks::CkptHeader) + payload;
   if (!host_buf) { *len = need; return DUGKS_OK; }
   if (*len < need) return ctx->fail(DUGKS_E_ARG, "checkpoint buffer too small");
-  if (!ctx->bound() || !ctx->initialised) return ctx->fail(DUGKS_E_STATE, "no state");
+  if (!ctx->bound() || !ctx->all_ready()) return ctx->fail(DUGKS_E_STATE, "no state");
   dugks::CkptHeader hd;
   memset(&hd, 0, sizeof(hd));
   memcpy(hd.magic, "DUGKSCK1", 8);
@@ -1060,7 +1112,7 @@ int dugks_restore(dugks_ctx* ctx, const void* host_buf, size_t len) {
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return ctx->hipfail(e, "restore copy");
   ctx->step = hd.step;
-  ctx->initialised = true;
+  ctx->ready.assign(1, 1);
   ctx->need_measure = false;
   return DUGKS_OK;
 }

@@ -15,8 +15,11 @@
 //   - Each lane computes exactly two faces per row: the face on its west side
 //     and the face above its cell.  The east face comes from the lane to the
 //     right; the face below was computed on the previous row.
-//   - The interface phi and the cell phi are accumulated in binary64 for the
-//     binary32 storage (the moment sums); everything else runs in the storage's
+//   - Moment sums: the cell phi of the binary64 and binary32 storages and the
+//     stored phi of the new state in the 16-bit formats are accumulated in
+//     binary64 and rounded once; the interface phi is a binary64 sum in
+//     binary64 storage and a balanced binary32 tree sum otherwise (binary64
+//     when DUGKS_FACE_SUM64 is set).  Everything else runs in the storage's
 //     arithmetic type.
 #include <hip/hip_runtime.h>
 
@@ -227,8 +230,13 @@ template <typename T, int Q> struct SrcEq<T, Q, true> {
   }
 };
 
+// Interface phi in binary64 for the binary32 and 16-bit formats too.
+#ifndef DUGKS_FACE_SUM64
+#define DUGKS_FACE_SUM64 0
+#endif
+
 // Sum over directions of the interface values: binary64 for the binary64
-// path, a balanced binary32 tree otherwise.
+// path, a balanced binary32 tree otherwise (or a binary64 sum rounded once).
 template <int Q> __device__ __forceinline__ double dir_sum(const double* v) {
   double s = 0.0;
 #pragma unroll
@@ -236,6 +244,12 @@ template <int Q> __device__ __forceinline__ double dir_sum(const double* v) {
   return s;
 }
 template <int Q> __device__ __forceinline__ float dir_sum(const float* v) {
+  if constexpr (DUGKS_FACE_SUM64) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) s += (double)v[k];
+    return (float)s;
+  }
   float t[Q];
 #pragma unroll
   for (int k = 0; k < Q; ++k) t[k] = v[k];
@@ -650,7 +664,10 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
           }
         }
       } else {
-        const float pf = dir_sum<Q>(o);   // phi(t + dt) = sum_i f~_i
+        double ps = 0.0;                  // phi(t + dt) = sum_i f~_i in binary64,
+#pragma unroll
+        for (int k = 0; k < Q; ++k) ps += (double)o[k];
+        const float pf = (float)ps;       // rounded once to the stored binary32
         bad |= !__builtin_isfinite(pf);
         float m1 = 0.0f;                  // max |f~_i - E_i| over the stored i >= 1
         uint16_t gq[Q - 1];

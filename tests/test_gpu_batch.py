@@ -105,3 +105,60 @@ def test_autotune_keeps_state():
     after = [b.get_phi(i) for i in range(len(probs))]
     for x, y in zip(before, after):
         assert np.array_equal(x, y)
+
+
+def test_per_instance_reset_of_a_stepped_batch():
+    """One clock for the batch: after an odd number of steps, setting one
+    instance again leaves the others stale (another step, buffer parity and
+    16-bit scale phase), so stepping and reading them are refused until each
+    instance is set again; then the batch equals a fresh one."""
+    probs = mixed_batch()[:4]
+    for storage in ("f32", "bf16neq"):
+        say(f"case per-instance reset {storage}")
+        b = dg.Batch(probs, storage=storage)
+        b.set_all_phi()
+        b.step(3)
+        b.set_phi(1, probs[1].phi0)
+        with pytest.raises(dg.DugksError) as ei:
+            b.step(1)
+        assert ei.value.code == dg._lib.E_STATE
+        with pytest.raises(dg.DugksError):
+            b.get_phi(0)
+        with pytest.raises(dg.DugksError):
+            b.autotune(1)
+        assert b.get_phi(1).shape == probs[1].phi0.shape   # the re-set instance is readable
+        for i, p in enumerate(probs):
+            if i != 1:
+                b.set_phi(i, p.phi0)
+        b.step(5)
+        fresh = dg.Batch(probs, storage=storage)
+        fresh.set_all_phi()
+        fresh.step(5)
+        for i in range(len(probs)):
+            assert np.array_equal(b.get_phi(i), fresh.get_phi(i)), (storage, i)
+
+
+def test_graph_replay_any_step_count():
+    """Runs of 4 or more steps from a step divisible by 4 replay captured graphs
+    (32 and 4 steps); the rest launch one by one.  Every split gives the eager
+    result bit for bit, and the launch counters say which path ran."""
+    probs = W.batch_problems(count=5, nmin=64, nmax=200)
+    for storage in ("f32", "f16neq"):
+        say(f"case graph any count {storage}")
+        a = dg.Batch(probs, storage=storage)
+        e = dg.Batch(probs, storage=storage)
+        a.set_all_phi()
+        e.set_all_phi()
+        done = 0
+        for n in (4, 8, 3, 1, 20, 36, 5):
+            a.step(n)
+            for _ in range(n):
+                e.step(1)
+            done += n
+            for i in range(len(probs)):
+                assert np.array_equal(a.get_phi(i), e.get_phi(i)), (storage, n, i)
+        info = a.info()
+        assert info["graph_steps"] + info["eager_steps"] >= done
+        # 4 + 8 from step 0, then 3 + 1 eager, then 20 + 36 from step 16, then 4 of the last 5
+        assert info["graph_steps"] >= 4 + 8 + 20 + 36 + 4
+        assert e.info()["graph_steps"] == 0

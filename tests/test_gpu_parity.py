@@ -241,3 +241,17 @@ def test_dirichlet_data_must_cover_steps():
     s.step(5)
     with pytest.raises(dg.DugksError):
         s.step(1)
+
+
+def test_autotune_refuses_exhausted_dirichlet_data():
+    """Autotune's trial steps read the current step's ghost data: once the data
+    is used up they are refused (no kernel reads past the caller's array)."""
+    p = W.burgers_problem(64, steps=5)
+    s = dg.Solver(p, storage="f64")
+    s.set_phi(p.phi0)
+    s.set_dirichlet(p.rings(5))
+    s.autotune(1)              # data for step 0 is there
+    s.step(5)
+    with pytest.raises(dg.DugksError) as ei:
+        s.autotune(1)
+    assert ei.value.code == dg._lib.E_STATE

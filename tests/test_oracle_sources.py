@@ -111,3 +111,117 @@ def test_source_wave_paper_gre(Pe, paper_gre, tol):
     gre = o.errors(p.exact(X, Y, o.time))[0]
     assert abs(o.time - 3.0) < 1e-9
     assert abs(gre - paper_gre) <= tol * paper_gre, gre
+
+
+# ------------------------------------------- face time of the source term
+
+def _read_lattice_d2q9():
+    path = os.path.join(os.path.dirname(__file__), "golden", "lattices.txt")
+    rows = []
+    for line in open(path):
+        t = line.split()
+        if t and t[0] == "D2Q9":
+            rows.append((int(t[2]), int(t[3]), int(t[4]) / int(t[5])))
+    a = np.array(rows, dtype=float)
+    return a[:, 0], a[:, 1], a[:, 2]
+
+
+def source_step_symbol(kx, ky, n, L, c, alpha, cfl, u, Dm, gamma, t_n, face_time):
+    """One step on a periodic uniform mesh for one Fourier mode: returns
+    (G, s) with  f~^(n+1) = G f~^n + s g  for f~ = F e^{ik.x} and a source
+    F(x, t) = exp(gamma t) g e^{ik.x}, built from the definitions:
+      f~ = f - dt/2 (Omega + S),  fbar = f - h/2 (Omega + S)   (eqs. 2.25, 2.27)
+      fbar+ = (2L-h)/(2L+h) fbar + 2h/(2L+h) E + 2Lh/(2L+h) S (eq. 2.27)
+      f~+ = (2L-dt)/(2L+dt) f~ + 2dt/(2L+dt) E + 2Ldt/(2L+dt) S (eq. 2.25)
+    with S_i = w_i (1 + c_i.u / c_s^2) F (eq. 2.3, Remark 3), phi = sum f~ +
+    dt F / 2 in the cell at t_n, and at a face, where fbar lives at t_n + h,
+    phi_b = sum fbar + h F_b / 2 with F_b the mean of the two cells' G at
+    ``face_time``.  The equilibrium E = e phi solves the moment system of
+    eq. 2.7 for B = u phi, D = Dm phi, C = u u^T phi."""
+    cxl, cyl, w = _read_lattice_d2q9()
+    cx, cy = c * cxl, c * cyl
+    cs2 = c * c / 3.0
+    basis = np.stack([np.ones(9), cx, cy, cx * cx, cx * cy, cy * cy], axis=1)
+    A = np.array([[np.sum(w * r * basis[:, j]) for j in range(6)] for r in basis.T])
+    M2 = cs2 * np.asarray(Dm) + np.outer(u, u)
+    e = w * (basis @ np.linalg.solve(A, [1.0, u[0], u[1], M2[0][0], M2[0][1], M2[1][1]]))
+    rho = w * (1.0 + (cx * u[0] + cy * u[1]) / cs2)
+    dx = L / n
+    lam = alpha / cs2
+    dt = cfl * dx / c
+    h = dt / 2
+    one = np.ones(9)
+    I = np.eye(9)
+    tx, ty = kx * dx, ky * dx
+
+    # affine maps on the vector (F, g) of length 10
+    def cell(Fg):
+        F, g = Fg[:9], Fg[9]
+        Fc = math.exp(gamma * t_n) * g
+        phi = one @ F + dt * Fc / 2
+        S = rho * Fc
+        f = (2 * lam * F + dt * e * phi + lam * dt * S) / (2 * lam + dt)
+        fbar = f + h / (2 * lam) * (f - e * phi) - h / 2 * S
+        fbp = (2 * lam - h) / (2 * lam + h) * fbar + 2 * h / (2 * lam + h) * e * phi + \
+            2 * lam * h / (2 * lam + h) * S
+        ftp = (2 * lam - dt) / (2 * lam + dt) * F + 2 * dt / (2 * lam + dt) * e * phi + \
+            2 * lam * dt / (2 * lam + dt) * S
+        return fbp, ftp
+
+    def face(fbp, g, t_shift, Cn, Ct, tt, tn):
+        # reconstruction of eq. 2.20 and the shift of eq. 2.19 on the low-side face
+        Rec = (1 + np.exp(-1j * tn)) / 2 * (I - h * Ct * 1j * math.sin(tt) / dx) - \
+            h * Cn * (1 - np.exp(-1j * tn)) / dx
+        fb = Rec @ fbp
+        Fb = math.exp(gamma * t_shift) * g * (1 + np.exp(-1j * tn)) / 2
+        phib = one @ fb + h * Fb / 2
+        Sb = rho * Fb
+        return (2 * lam * fb + h * e * phib + lam * h * Sb) / (2 * lam + h)
+
+    def step(Fg):
+        fbp, ftp = cell(Fg)
+        Cx, Cy = np.diag(cx), np.diag(cy)
+        fx = face(fbp, Fg[9], face_time, Cx, Cy, ty, tx)
+        fy = face(fbp, Fg[9], face_time, Cy, Cx, tx, ty)
+        return ftp - dt * ((np.exp(1j * tx) - 1) / dx * cx * fx + (np.exp(1j * ty) - 1) / dx * cy * fy)
+
+    cols = [step(np.eye(10)[j].astype(complex)) for j in range(10)]
+    M = np.stack(cols, axis=1)
+    return M[:, :9], M[:, 9], dt
+
+
+def test_face_time_of_the_source_by_fourier_symbol():
+    """The oracle's step with a source F = exp(gamma t) G(x) on one Fourier
+    mode equals the symbol built from the definitions with the face source at
+    t_n + h (where fbar(x_b, t_n + h) lives, eq. 2.27), to rounding; the same
+    symbol with the face source at t_n differs by far more than that, so this
+    pins the face time."""
+    n, L = 16, 2.0
+    c, alpha, cfl, u, Dm, gamma = 1.0, 2e-2, 0.7, (0.3, -0.2), [[1.0, 0.2], [0.2, 0.6]], 4.0
+    xf = W.uniform_faces(n, -1.0, 1.0)
+    X, Y = np.meshgrid(W.centres(xf), W.centres(xf))
+    rng = np.random.default_rng(31)
+    for (mx, my) in ((1, 0), (0, 1), (2, 3), (5, -7), (8, 8)):
+        kx, ky = 2 * math.pi * mx / L, 2 * math.pi * my / L
+        phase = np.exp(1j * (kx * X + ky * Y))
+        Fh = rng.normal(size=9) + 1j * rng.normal(size=9)
+        gh = complex(rng.normal(), rng.normal())
+        o = Oracle(xf=xf, yf=xf, c=c, cfl=cfl, alpha=alpha, bx=(0.0, u[0]), by=(0.0, u[1]),
+                   dxx=(0.0, Dm[0][0]), dxy=(0.0, Dm[0][1]), dyy=(0.0, Dm[1][1]))
+        o.set_source(np.real(gh * phase), gamma)
+        o.set_f(np.real(Fh[:, None, None] * phase[None]))
+        t_n = 0.37
+        o.set_clock(5, t_n)
+        o.step(1)
+        got = o.get_f()
+        scale = max(np.abs(Fh).max(), abs(gh) * math.exp(gamma * t_n))
+        errs = {}
+        for name, ft in (("t_n + h", None), ("t_n", t_n)):
+            G, s, dt = source_step_symbol(kx, ky, n, L, c, alpha, cfl, u, Dm, gamma, t_n,
+                                          face_time=(t_n + 0.5 * o.dt) if ft is None else ft)
+            assert math.isclose(dt, o.dt, rel_tol=1e-14)
+            expect = np.real((G @ Fh + s * gh)[:, None, None] * phase[None])
+            errs[name] = np.abs(got - expect).max() / scale
+        assert errs["t_n + h"] <= 1e-13, (mx, my, errs)
+        if (mx, my) != (n // 2, n // 2):   # at (8, 8) the face mean of G is zero on both faces
+            assert errs["t_n"] >= 1e3 * max(errs["t_n + h"], 1e-16), (mx, my, errs)
