@@ -230,6 +230,22 @@ int dugks_get_diag(dugks_ctx* ctx, dugks_diag* out);
  * reductions in a fixed order.  Synchronises. */
 int dugks_error_norms(dugks_ctx* ctx, const double* ref_dev, double* rel_l2, double* gre);
 
+/* For callers that cannot allocate (code under hipGraph capture, tight
+ * serving loops, harnesses that forbid allocation): the norms of
+ * dugks_error_norms written to out_dev[0] = relative L2 and out_dev[1] = GRE
+ * (device, binary64, caller-owned), asynchronously on the bound stream; no
+ * synchronisation, no host copy and no allocation (no hipMalloc, hipFree or
+ * allocating library routine).  The binary64 partial sums go to a static
+ * array of the library, one per GPU, of 1024 x 8 doubles (64 KiB), held until
+ * the process ends; its size does not depend on the grid, so no grid size is
+ * refused for lack of room.  Every call on a GPU rewrites that array in full
+ * before reading it: calls that overlap on one GPU (two streams, two threads)
+ * race and must be ordered by the caller.  The sums are those of
+ * dugks_error_norms in the same order.  Errors: E_ARG (NULL pointer), E_STATE
+ * (no state), E_HIP (launch, or the scratch address lookup on first use on a
+ * device). */
+int dugks_error_norms_noalloc(dugks_ctx* ctx, const double* ref_dev, double* out_dev);
+
 /* Serialise the state (header with ABI version, sizes, storage, step, time,
  * scale slots and a hash of mesh, parameters and coefficients, then the
  * active f~ buffer and a checksum) into host_buf.  With host_buf == NULL only

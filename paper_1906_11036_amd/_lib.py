@@ -100,6 +100,7 @@ SIGNATURES = {
     "dugks_get_f": (_int, [_vp, _vp, _int]),
     "dugks_get_diag": (_int, [_vp, C.POINTER(Diag)]),
     "dugks_error_norms": (_int, [_vp, _vp, _dp, _dp]),
+    "dugks_error_norms_noalloc": (_int, [_vp, _vp, _vp]),
     "dugks_checkpoint": (_int, [_vp, _vp, C.POINTER(_sz)]),
     "dugks_restore": (_int, [_vp, _vp, _sz]),
     "dugks_set_launch": (_int, [_vp, _int, _int, _int, _int]),

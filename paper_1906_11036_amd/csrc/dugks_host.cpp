@@ -1049,6 +1049,20 @@ int dugks_error_norms(dugks_ctx* ctx, const double* ref_dev, double* rel_l2, dou
   return DUGKS_OK;
 }
 
+int dugks_error_norms_noalloc(dugks_ctx* ctx, const double* ref_dev, double* out_dev) {
+  GUARD_CTX(ctx);
+  if (!ref_dev || !out_dev) return ctx->fail(DUGKS_E_ARG, "NULL argument");
+  if (!ctx->bound() || !ctx->all_ready()) return ctx->fail(DUGKS_E_STATE, "no state");
+  const dugks::Instance& in = ctx->inst[0];
+  const int rc = dugks::launch_norms_noalloc(ctx->dev_inst(0), ctx->host_table[0], ref_dev,
+                                             (int)(ctx->step & 1), ctx->step,
+                                             (const double*)(ctx->ws + in.off_widths), out_dev,
+                                             ctx->stream);
+  if (rc == -2) return ctx->fail(DUGKS_E_HIP, "hipGetSymbolAddress of the reduction scratch failed");
+  if (rc) return ctx->fail(DUGKS_E_HIP, "norm launch failed");
+  return DUGKS_OK;
+}
+
 int dugks_checkpoint(dugks_ctx* ctx, void* host_buf, size_t* len) {
   GUARD_CTX(ctx);
   if (!len) return ctx->fail(DUGKS_E_ARG, "len is NULL");

@@ -116,6 +116,12 @@ int launch_reduce_widths(const InstDev* d, const InstDev& h, const double* ref, 
                          long long step, const double* widths, double* partial, double* out,
                          void* stream);
 int reduce_partials();
+// Relative L2 and GRE of the instance's phi against ref into out_dev[0..1]
+// (device), with the partial sums in the library's static per-GPU scratch
+// (no allocation, no synchronisation).  Returns 0, -1 (launch failed) or -2
+// (scratch address lookup failed).
+int launch_norms_noalloc(const InstDev* d, const InstDev& h, const double* ref, int parity,
+                         long long step, const double* widths, double* out_dev, void* stream);
 int launch_fill_u32(unsigned* p, unsigned v, long long n, void* stream);
 
 // Power-of-two scale of the 16-bit formats for a maximum |f~ - E| of m.

@@ -25,6 +25,7 @@
 
 #include <stdint.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "dugks_internal.h"
@@ -1078,6 +1079,43 @@ __global__ void k_reduce_final(const double* __restrict__ partial, int nblocks,
   out[v] = s;
 }
 
+// Final pass of the allocation-free norms: the partial sums in block order (as
+// k_reduce_final), then out[0] = relative L2, out[1] = GRE (eq. 4.1).
+__global__ void k_norms_final(const double* __restrict__ partial, int nblocks,
+                              double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double r[5] = {0, 0, 0, 0, 0};
+  for (int v = 1; v < 5; ++v)
+    for (int b = 0; b < nblocks; ++b) r[v] += partial[b * kRedVals + v];
+  out[0] = r[4] > 0 ? sqrt(r[3] / r[4]) : (r[3] > 0 ? INFINITY : 0.0);
+  out[1] = r[2] > 0 ? r[1] / r[2] : (r[1] > 0 ? INFINITY : 0.0);
+}
+
+// Scratch of the allocation-free norms: kRedBlocks x kRedVals partial sums,
+// fully rewritten by every call (nothing needs clearing).  One copy per GPU,
+// held until the process ends; host code uses only the address returned by
+// hipGetSymbolAddress, never the name.
+constexpr int kScratchDoubles = kRedBlocks * kRedVals;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// Address of the current device's scratch, looked up once per device.
+static int scratch_ptr(double** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return -1;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return -1;
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return 0;
+}
+
 __global__ void k_fill_u32(unsigned* p, unsigned v, long long n) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -1256,6 +1294,17 @@ int launch_reduce_widths(const InstDev* d, const InstDev& h, const double* ref, 
                     : reduce_q<5>(d, h, ref, parity, step, widths, partial, stream);
   if (rc) return rc;
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, S(stream), partial, kRedBlocks, out);
+  DUGKS_CHECK_LAUNCH();
+}
+
+int launch_norms_noalloc(const InstDev* d, const InstDev& h, const double* ref, int parity,
+                         long long step, const double* widths, double* out_dev, void* stream) {
+  double* partial = nullptr;
+  if (scratch_ptr(&partial)) return -2;
+  int rc = h.q == 9 ? reduce_q<9>(d, h, ref, parity, step, widths, partial, stream)
+                    : reduce_q<5>(d, h, ref, parity, step, widths, partial, stream);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_norms_final, dim3(1), dim3(64), 0, S(stream), partial, kRedBlocks, out_dev);
   DUGKS_CHECK_LAUNCH();
 }
 
