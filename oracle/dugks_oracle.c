@@ -19,14 +19,20 @@
  *   -> face flux J (eq. 2.9)           -> f~(t+dt) (eq. 2.24)
  *   -> phi = sum f~ (+ dt F / 2 with a source).
  *
- * Source term (eq. 2.1's F), when set: F(x, t) = exp(gamma t) G(x) with G
- * given at the cell centres.  Its distributions are F_i = w_i F (eq. 2.3) and,
- * with C = int B'B'^T, R_i = w_i c_i.B'(phi) F / c_s^2 (Remark 3); they enter
+ * Source term (eq. 2.1's F), when set: a sum of terms
+ *   F(x, t, phi) = sum_j exp(gamma_j t) phi^k_j G_j(x),   k_j in 0..3,
+ * with each G_j given at the cell centres (F(x, t) = exp(gamma t) G(x) is one
+ * term with k = 0).  Its distributions are F_i = w_i F (eq. 2.3) and, with
+ * C = int B'B'^T, R_i = w_i c_i.B'(phi) F / c_s^2 (Remark 3); they enter
  * through the shifted distributions of eqs. 2.25 and 2.27, which this file
  * applies literally: f is recovered from f~ (first line of eq. 2.25), fbar
  * and fbar+ follow from eq. 2.27, f~+ from the second line of eq. 2.25, and
  * f at the face from the first line of eq. 2.27.  Without a source the step
- * uses eqs. 2.13, 2.21 and 2.22 directly.
+ * uses eqs. 2.13, 2.21 and 2.22 directly.  When F depends on phi, the
+ * conserved value is implicit (the paper notes this after eq. 2.27):
+ * phi = sum f~ + dt F(phi) / 2 in a cell and phi_b = sum fbar + h F_b(phi_b) / 2
+ * at a face; each is solved by Newton's method from phi = sum f~ (resp.
+ * sum fbar) until the update is below 1e-15 (1 + |phi|).
  *
  * Readings of points the paper leaves open (each one also listed in the
  * design notes):
@@ -64,6 +70,8 @@
 
 #define OR_MAXQ 9
 #define OR_MAXDEG 4
+#define OR_MAXTERMS 8       /* source terms */
+#define OR_MAXPOW 3         /* highest power of phi in a source term */
 
 enum { OR_PERIODIC = 0, OR_DIRICHLET = 1, OR_MIRROR = 2 };
 
@@ -85,9 +93,13 @@ typedef struct {
   double *xf, *yf;        /* faces, nx+1 / ny+1 */
   double *wx, *wy;        /* widths of cells -1..n */
   double *xc, *yc;        /* centres of cells -1..n */
-  /* source F(x, t) = exp(src_gamma t) src_g(x); src_g [ny][nx] or NULL */
+  /* source F(x, t, phi) = sum_j exp(src_gam[j] t) phi^src_pow[j] G_j(x);
+     src_g holds G_j as [src_n][ny][nx]; src_n = 0: no source */
+  int src_n;
   double *src_g;
-  double src_gamma;
+  int src_pow[OR_MAXTERMS];
+  double src_gam[OR_MAXTERMS];
+  int src_implicit;       /* some term depends on phi */
   /* state */
   double *f;              /* f~ [q][ny][nx] */
   long step;
@@ -192,10 +204,38 @@ static void source_dist(const Oracle* o, double phi, double F, double* S) {
     S[i] = o->w[i] * F + o->w[i] * (o->cx[i] * bpx + o->cy[i] * bpy) * F / o->cs2;
 }
 
-/* F at the centre of interior cell c at time t (0 without a source) */
-static double source_at(const Oracle* o, size_t c, double t) {
-  if (!o->src_g) return 0.0;
-  return exp(o->src_gamma * t) * o->src_g[c];
+/* Coefficients a_k of F as a polynomial in phi, F = sum_k a_k phi^k, at time t
+ * and at a point whose G_j are a weighted mean of two cells' values:
+ * G_j = (1 - r) G_j(cL) + r G_j(cR) (r = 0: the centre of cell cL). */
+static void source_coefs(const Oracle* o, size_t cL, size_t cR, double r, double t, double* a) {
+  size_t N = (size_t)o->nx * o->ny;
+  int j, k;
+  for (k = 0; k <= OR_MAXPOW; ++k) a[k] = 0.0;
+  for (j = 0; j < o->src_n; ++j) {
+    double gL = o->src_g[(size_t)j * N + cL], gR = o->src_g[(size_t)j * N + cR];
+    a[o->src_pow[j]] += exp(o->src_gam[j] * t) * (gL + r * (gR - gL));
+  }
+}
+
+static double poly3(const double* a, double phi) {
+  return a[0] + phi * (a[1] + phi * (a[2] + phi * a[3]));
+}
+
+/* The conserved value phi with phi - tau F(phi) / 2 = s, F = sum_k a_k phi^k
+ * (tau = dt in a cell, eq. 2.25; tau = h at a face, eq. 2.27): explicit when F
+ * does not depend on phi, otherwise Newton's method from phi = s. */
+static double solve_conserved(const Oracle* o, double s, double tau, const double* a) {
+  double phi = s;
+  int it;
+  if (!o->src_implicit) return s + 0.5 * tau * a[0];
+  for (it = 0; it < 60; ++it) {
+    double F = poly3(a, phi);
+    double dF = a[1] + phi * (2.0 * a[2] + phi * 3.0 * a[3]);
+    double d = (phi - 0.5 * tau * F - s) / (1.0 - 0.5 * tau * dF);
+    phi -= d;
+    if (fabs(d) <= 1e-15 * (1.0 + fabs(phi))) break;
+  }
+  return phi;
 }
 
 /* --------------------------------------------------------------- geometry */
@@ -292,17 +332,37 @@ int or_set_D(Oracle* o, int deg, const double* dxx, const double* dxy, const dou
   return 0;
 }
 
-/* Source F(x, t) = exp(gamma t) g(x), g [ny][nx] at the cell centres (copied);
- * g == NULL removes it. */
-void or_set_source(Oracle* o, const double* g, double gamma) {
+/* Source terms F(x, t, phi) = sum_j exp(gam[j] t) phi^pow[j] G_j(x), j < n,
+ * g = G_j as [n][ny][nx] at the cell centres (copied); n == 0 or g == NULL
+ * removes the source.  Returns -1 (nothing changed) for n > 8 or a power
+ * outside 0..3. */
+int or_set_source_terms(Oracle* o, int n, const double* g, const int* pow, const double* gam) {
   size_t N = (size_t)o->nx * o->ny;
+  int j;
+  if (n < 0 || n > OR_MAXTERMS) return -1;
+  for (j = 0; j < n && g; ++j)
+    if (pow[j] < 0 || pow[j] > OR_MAXPOW) return -1;
   free(o->src_g);
   o->src_g = NULL;
-  o->src_gamma = 0.0;
-  if (!g) return;
-  o->src_g = (double*)malloc(sizeof(double) * N);
-  memcpy(o->src_g, g, sizeof(double) * N);
-  o->src_gamma = gamma;
+  o->src_n = 0;
+  o->src_implicit = 0;
+  if (n == 0 || !g) return 0;
+  o->src_g = (double*)malloc(sizeof(double) * N * n);
+  memcpy(o->src_g, g, sizeof(double) * N * n);
+  o->src_n = n;
+  for (j = 0; j < n; ++j) {
+    o->src_pow[j] = pow[j];
+    o->src_gam[j] = gam[j];
+    if (pow[j] > 0) o->src_implicit = 1;
+  }
+  return 0;
+}
+
+/* Source F(x, t) = exp(gamma t) g(x) (one term independent of phi); g == NULL
+ * removes it. */
+void or_set_source(Oracle* o, const double* g, double gamma) {
+  int zero = 0;
+  or_set_source_terms(o, g ? 1 : 0, g, &zero, &gamma);
 }
 
 /* constants: lambda, dt, h, a1, b1, a2, b2, a3, b3, cs2 */
@@ -332,9 +392,11 @@ void or_set_phi(Oracle* o, const double* phi) {
       size_t c = (size_t)j * o->nx + i;
       feq(o, phi[c], E);
       for (k = 0; k < o->q; ++k) o->f[k * N + c] = E[k];
-      if (o->src_g) {
+      if (o->src_n) {
         /* f = E at t = 0, Omega = 0: f~ = f - dt (R + F) / 2 (eq. 2.25) */
-        source_dist(o, phi[c], source_at(o, c, 0.0), S);
+        double a[OR_MAXPOW + 1];
+        source_coefs(o, c, c, 0.0, 0.0, a);
+        source_dist(o, phi[c], poly3(a, phi[c]), S);
         for (k = 0; k < o->q; ++k) o->f[k * N + c] = E[k] - 0.5 * o->dt * S[k];
       }
     }
@@ -351,16 +413,25 @@ void or_set_clock(Oracle* o, long step, double t) { o->step = step; o->t = t; }
 long or_step_index(const Oracle* o) { return o->step; }
 double or_time(const Oracle* o) { return o->t; }
 
-/* phi of cell c at the current time: sum_i f~_i (Sec. 2, after eq. 2.13),
- * plus dt F / 2 with a source (eq. 2.25 summed with the moments of eq. 2.7) */
-static double cell_phi(const Oracle* o, size_t c) {
+/* phi of cell c at the current time: sum_i f~_i (Sec. 2, after eq. 2.13); with
+ * a source the root of phi = sum_i f~_i + dt F(phi) / 2 (eq. 2.25 summed with
+ * the moments of eq. 2.7), and *F = F(phi) there (F may be NULL). */
+static double cell_phi_F(const Oracle* o, size_t c, double* F) {
   size_t N = (size_t)o->nx * o->ny;
-  double s = 0.0;
+  double s = 0.0, a[OR_MAXPOW + 1], phi;
   int k;
   for (k = 0; k < o->q; ++k) s += o->f[k * N + c];
-  if (o->src_g) s += 0.5 * o->dt * source_at(o, c, o->t);
-  return s;
+  if (!o->src_n) {
+    if (F) *F = 0.0;
+    return s;
+  }
+  source_coefs(o, c, c, 0.0, o->t, a);
+  phi = solve_conserved(o, s, o->dt, a);
+  if (F) *F = poly3(a, phi);
+  return phi;
 }
+
+static double cell_phi(const Oracle* o, size_t c) { return cell_phi_F(o, c, NULL); }
 
 void or_get_phi(const Oracle* o, double* phi) {
   size_t i, N = (size_t)o->nx * o->ny;
@@ -392,14 +463,15 @@ static void fbar_plus(const Oracle* o, int i, int j, const double* ring, double*
   int k;
   int xwall = (i < 0 || i >= o->nx) && o->bcx != OR_PERIODIC;
   int ywall = (j < 0 || j >= o->ny) && o->bcy != OR_PERIODIC;
+  double Fc;
   for (k = 0; k < o->q; ++k) ft[k] = o->f[k * N + c];
-  phi = cell_phi(o, c);
+  phi = cell_phi_F(o, c, &Fc);
   feq(o, phi, E);
-  if (!o->src_g) {
+  if (!o->src_n) {
     for (k = 0; k < o->q; ++k) out[k] = o->a1 * ft[k] + o->b1 * E[k];
   } else {
     double S[OR_MAXQ], L = o->lambda, dt = o->dt, h = o->h;
-    source_dist(o, phi, source_at(o, c, o->t), S);
+    source_dist(o, phi, Fc, S);
     for (k = 0; k < o->q; ++k) {
       /* f~ = f - dt/2 Omega - dt/2 S with Omega = -(f - E)/lambda, solved for f */
       double f = (2.0 * L * ft[k] + dt * E[k] + L * dt * S[k]) / (2.0 * L + dt);
@@ -429,14 +501,14 @@ static void fbar_plus(const Oracle* o, int i, int j, const double* ring, double*
  *   tL, tR : central-difference slopes of fbar+ along the face at L and R
  *   dn     : distance between the two centres, wl : face minus L centre
  *   (cn, ct) : velocity components normal / tangential to the face
- *   sL, sR : source G at the two cells (ignored without a source)
+ *   sL, sR : cells whose G the two sides take (ignored without a source)
  * Linear reconstruction (eq. 2.20), Taylor shift back along the
  * characteristic (eq. 2.19 in the form of eq. 2.26), interface phi (sum of
  * fbar), f = a3 fbar + b3 E(phi_b)  (eq. 2.22; with a source, the first line
  * of eq. 2.27 solved for f), flux c_n f  (eq. 2.9). */
 static void face_flux(const Oracle* o, const double* cn, const double* ct, const double* fL,
                       const double* fR, const double* tL, const double* tR, double dn,
-                      double wl, double sL, double sR, double* flux) {
+                      double wl, size_t sL, size_t sR, double* flux) {
   double fb[OR_MAXQ], E[OR_MAXQ], phib = 0.0;
   int k;
   for (k = 0; k < o->q; ++k) {
@@ -446,14 +518,16 @@ static void face_flux(const Oracle* o, const double* cn, const double* ct, const
     fb[k] = v - o->h * (cn[k] * Gn + ct[k] * Gt);
   }
   for (k = 0; k < o->q; ++k) phib += fb[k];
-  if (!o->src_g) {
+  if (!o->src_n) {
     feq(o, phib, E);
     for (k = 0; k < o->q; ++k) flux[k] = cn[k] * (o->a3 * fb[k] + o->b3 * E[k]);
   } else {
-    double S[OR_MAXQ], L = o->lambda, h = o->h;
-    /* F at the face at t_n + h: linear interpolation between the centres */
-    double Fb = exp(o->src_gamma * (o->t + h)) * (sL + wl * (sR - sL) / dn);
-    phib += 0.5 * h * Fb;
+    double S[OR_MAXQ], L = o->lambda, h = o->h, a[OR_MAXPOW + 1], Fb;
+    /* F at the face at t_n + h (where fbar lives, eq. 2.27), each G_j
+       interpolated linearly between the centres; phi_b = sum fbar + h F_b / 2 */
+    source_coefs(o, sL, sR, wl / dn, o->t + h, a);
+    phib = solve_conserved(o, phib, h, a);
+    Fb = poly3(a, phib);
     feq(o, phib, E);
     source_dist(o, phib, Fb, S);
     for (k = 0; k < o->q; ++k)
@@ -461,11 +535,10 @@ static void face_flux(const Oracle* o, const double* cn, const double* ct, const
   }
 }
 
-/* source G of cell (i, j), i in -1..nx, j in -1..ny: a ghost takes the G of
- * the cell its fbar+ comes from */
-static double src_g_at(const Oracle* o, int i, int j) {
-  if (!o->src_g) return 0.0;
-  return o->src_g[(size_t)wrap_or_clamp(j, o->ny, o->bcy) * o->nx + wrap_or_clamp(i, o->nx, o->bcx)];
+/* the cell whose source G_j cell (i, j), i in -1..nx, j in -1..ny, takes: a
+ * ghost takes those of the cell its fbar+ comes from */
+static size_t src_g_at(const Oracle* o, int i, int j) {
+  return (size_t)wrap_or_clamp(j, o->ny, o->bcy) * o->nx + wrap_or_clamp(i, o->nx, o->bcx);
 }
 
 static void slope(const Oracle* o, const double* fm, const double* fp, double dist, double* s) {
@@ -488,14 +561,15 @@ static void ftilde_plus(const Oracle* o, size_t c, double* out) {
   size_t N = (size_t)o->nx * o->ny;
   double ft[OR_MAXQ], E[OR_MAXQ], S[OR_MAXQ], phi;
   int k;
+  double Fc;
   for (k = 0; k < o->q; ++k) ft[k] = o->f[k * N + c];
-  phi = cell_phi(o, c);
+  phi = cell_phi_F(o, c, &Fc);
   feq(o, phi, E);
-  if (!o->src_g) {
+  if (!o->src_n) {
     for (k = 0; k < o->q; ++k) out[k] = o->a2 * ft[k] + o->b2 * E[k]; /* eq. 2.13 */
     return;
   }
-  source_dist(o, phi, source_at(o, c, o->t), S);
+  source_dist(o, phi, Fc, S);
   for (k = 0; k < o->q; ++k) /* eq. 2.25, second line */
     out[k] = o->a2 * ft[k] + o->b2 * E[k] + 2.0 * o->lambda * o->dt / (2.0 * o->lambda + o->dt) * S[k];
 }

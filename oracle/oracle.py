@@ -65,6 +65,7 @@ def _lib(openmp: bool = False):
         lib.or_set_B.argtypes = [C.c_void_p, C.c_int, _d, _d]
         lib.or_set_D.argtypes = [C.c_void_p, C.c_int, _d, _d, _d]
         lib.or_set_source.argtypes = [C.c_void_p, _d, C.c_double]
+        lib.or_set_source_terms.argtypes = [C.c_void_p, C.c_int, _d, C.POINTER(C.c_int), _d]
         lib.or_constants.argtypes = [C.c_void_p, _d]
         lib.or_geometry.argtypes = [C.c_void_p, _d, _d, _d, _d]
         lib.or_feq.argtypes = [C.c_void_p, C.c_double, _d]
@@ -117,6 +118,8 @@ class Oracle:
         self.set_D(dxx, dxy, dyy)
         if problem is not None and getattr(problem, "src_g", None) is not None:
             self.set_source(problem.src_g, problem.src_gamma)
+        if problem is not None and getattr(problem, "src_terms", None):
+            self.set_source_terms(problem.src_terms)
         if problem is not None and problem.phi0 is not None:
             self.set_phi(problem.phi0)
 
@@ -149,6 +152,21 @@ class Oracle:
             return
         self._src = _f64(g).reshape(self.ny, self.nx)
         self.lib.or_set_source(self.h, _p(self._src), float(gamma))
+
+    def set_source_terms(self, terms):
+        """F(x, t, phi) = sum over terms (k, gamma, G) of exp(gamma t) phi^k G(x),
+        G [ny][nx] at the cell centres, k in 0..3, at most 8 terms; an empty list
+        removes the source.  Takes effect for the next set_phi and step."""
+        n = len(terms)
+        if n == 0:
+            self.lib.or_set_source_terms(self.h, 0, None, None, None)
+            return
+        self._src = np.ascontiguousarray(
+            np.stack([_f64(g).reshape(self.ny, self.nx) for _, _, g in terms]))
+        self._pow = (C.c_int * n)(*[int(k) for k, _, _ in terms])
+        self._gam = np.array([float(gm) for _, gm, _ in terms])
+        if self.lib.or_set_source_terms(self.h, n, _p(self._src), self._pow, _p(self._gam)) != 0:
+            raise ValueError("at most 8 source terms, powers of phi 0..3")
 
     @property
     def constants(self) -> dict:

@@ -157,6 +157,8 @@ class Problem:
     seed: Optional[int] = None
     src_g: Optional[np.ndarray] = None       # source F = exp(src_gamma t) src_g, [ny][nx]
     src_gamma: float = 0.0
+    # source terms F(x, t, phi) = sum of exp(gamma t) phi^k G(x) over (k, gamma, G [ny][nx])
+    src_terms: Optional[list] = None
 
     @property
     def nx(self) -> int:
@@ -373,6 +375,101 @@ def source_wave_problem(n=200, Pe=100.0, u=(0.1, 0.1), L=2.0, c=1.0, cfl=0.5, t_
     p.src_gamma = gam
     p.steps = int(round(t_end / p.dt()))
     return p
+
+
+def burgers_fisher(x, y, t, a, b, k, delta):
+    """Travelling wave of the 2-D Burgers-Fisher equation (eq. 4.2.2):
+    phi = [1/2 + 1/2 tanh(A (x + y - m t))]^(1/delta) with A = -a delta / (4 b (delta + 1))
+    and m = (a^2 + 2 b k (delta + 1)^2) / (a (delta + 1)); it solves eq. 4.2.1,
+    phi_t + a phi^delta phi_x = b lap(phi) + k phi (1 - phi^delta)."""
+    A = -a * delta / (4.0 * b * (delta + 1.0))
+    m = (a * a + 2.0 * b * k * (delta + 1.0) ** 2) / (a * (delta + 1.0))
+    w = 0.5 + 0.5 * np.tanh(A * (np.asarray(x) + np.asarray(y) - m * t))
+    return w ** (1.0 / delta)
+
+
+def burgers_fisher_problem(n=300, ny=None, b=0.05, a=6.0, k=1.0, delta=2, c=10.0, cfl=0.1,
+                           t_end=0.5, lo=-1.0, hi=2.0, name="burgers_fisher") -> Problem:
+    """Example 4.2 on [lo, hi]^2 (the paper: [-1, 2]^2, 300 x 300 or 300 x 150,
+    a = 6, k = 1, delta = 2, c = 10, CFL 0.1): B = (a phi^(delta+1) / (delta+1), 0),
+    D = phi I, alpha = b, F = k phi - k phi^(delta+1) (two terms of powers 1 and
+    delta + 1), Dirichlet walls from the closed form eq. 4.2.2, which also gives
+    the initial field.  delta is 1 or 2 (powers of phi up to 3)."""
+    ny = n if ny is None else ny
+    if delta not in (1, 2):
+        raise ValueError("delta must be 1 or 2")
+    xf, yf = uniform_faces(n, lo, hi), uniform_faces(ny, lo, hi)
+    bx = [0.0] * (delta + 2)
+    bx[delta + 1] = a / (delta + 1.0)
+    p = Problem(name=name, xf=xf, yf=yf, c=c, cfl=cfl, alpha=b, bcx=DIRICHLET, bcy=DIRICHLET,
+                bx=tuple(bx), by=(0.0,), dxx=(0.0, 1.0), dxy=(0.0,), dyy=(0.0, 1.0))
+    p.exact = lambda x, y, t: burgers_fisher(x, y, t, a, b, k, delta)
+    X, Y = p.mesh()
+    p.phi0 = p.exact(X, Y, 0.0)
+    one = np.ones((ny, n))
+    p.src_terms = [(1, 0.0, k * one), (delta + 1, 0.0, -k * one)]
+    p.steps = int(round(t_end / p.dt()))
+    return p
+
+
+def nonlinear_source_terms(X, Y, A, alpha, m, nxp, nyp, u):
+    """Example 4.5's source (eq. 4.5.3) as terms (k, gamma, G): with
+    e = exp(-A t), C = cos(2 pi x) cos(2 pi y),
+      F = e A C - 4 n_x pi^2 alpha phi^(n_x-2) [(n_x - 1) e^2 sin^2(2 pi x) cos^2(2 pi y) + e phi C]
+                - 4 n_y pi^2 alpha phi^(n_y-2) [(n_y - 1) e^2 sin^2(2 pi y) cos^2(2 pi x) + e phi C]
+                + 2 pi m e phi^(m-1) [u_x sin(2 pi x) cos(2 pi y) + u_y cos(2 pi x) sin(2 pi y)];
+    terms with equal (k, gamma) are merged.  Needs n_x, n_y >= 2, m >= 1."""
+    cx, sx = np.cos(2 * math.pi * X), np.sin(2 * math.pi * X)
+    cy, sy = np.cos(2 * math.pi * Y), np.sin(2 * math.pi * Y)
+    C = cx * cy
+    pi2 = math.pi ** 2
+    raw = [(0, -A, A * C),
+           (nxp - 2, -2 * A, -4 * nxp * pi2 * alpha * (nxp - 1) * sx ** 2 * cy ** 2),
+           (nxp - 1, -A, -4 * nxp * pi2 * alpha * C),
+           (nyp - 2, -2 * A, -4 * nyp * pi2 * alpha * (nyp - 1) * sy ** 2 * cx ** 2),
+           (nyp - 1, -A, -4 * nyp * pi2 * alpha * C),
+           (m - 1, -A, 2 * math.pi * m * (u[0] * sx * cy + u[1] * cx * sy))]
+    merged = {}
+    for k, gam, G in raw:
+        key = (int(k), float(gam))
+        merged[key] = merged.get(key, 0.0) + G
+    return [(k, gam, np.asarray(G, dtype=np.float64)) for (k, gam), G in merged.items()]
+
+
+def nonlinear_source_problem(n=400, Pe=100.0, kappa=1.1, A=1.0, m=2, nxp=2, nyp=3, u=(0.1, 0.1),
+                             c=1.0, cfl=0.5, t_end=3.0, name="nonlinear_source") -> Problem:
+    """Example 4.5 on [0, 1]^2, periodic: B = phi^m u, D = diag(phi^n_x, phi^n_y),
+    alpha = L u_x / Pe with L = 1, F of eq. 4.5.3, exact phi = kappa -
+    exp(-A t) cos(2 pi x) cos(2 pi y) (eq. 4.5.4).  The paper states Pe but not u;
+    u = (0.1, 0.1) is the velocity of its Example 4.1."""
+    alpha = 1.0 * u[0] / Pe
+    xf = uniform_faces(n, 0.0, 1.0)
+    bx, by = [0.0] * (m + 1), [0.0] * (m + 1)
+    bx[m], by[m] = u[0], u[1]
+    dxx, dyy = [0.0] * (nxp + 1), [0.0] * (nyp + 1)
+    dxx[nxp], dyy[nyp] = 1.0, 1.0
+    p = Problem(name=name, xf=xf, yf=xf.copy(), c=c, cfl=cfl, alpha=alpha, bx=tuple(bx),
+                by=tuple(by), dxx=tuple(dxx), dxy=(0.0,), dyy=tuple(dyy))
+    p.exact = lambda x, y, t: kappa - math.exp(-A * t) * np.cos(2 * math.pi * np.asarray(x)) * \
+        np.cos(2 * math.pi * np.asarray(y))
+    X, Y = p.mesh()
+    p.phi0 = p.exact(X, Y, 0.0)
+    p.src_terms = nonlinear_source_terms(X, Y, A, alpha, m, nxp, nyp, u)
+    p.steps = int(round(t_end / p.dt()))
+    return p
+
+
+def random_source_terms(seed: int, p: Problem, nterms: int = 4, amp: float = 0.5):
+    """Seeded smooth source terms (k, gamma, G) with powers 0..3 for property tests."""
+    rng = np.random.default_rng(seed)
+    X, Y = p.mesh()
+    wn = 2 * math.pi if p.bcx == PERIODIC and p.bcy == PERIODIC else math.pi
+    out = []
+    for j in range(nterms):
+        g = amp * cosine_field(X, Y, seed + 31 * j + 7, modes=3, total=1.0, wavenumber=wn,
+                               phases=(p.bcx == PERIODIC and p.bcy == PERIODIC))
+        out.append((j % 4, float(rng.uniform(-1.0, 1.0)), g + float(rng.uniform(-0.2, 0.2))))
+    return out
 
 
 def random_source(seed: int, p: Problem, amp: float = 0.5):
