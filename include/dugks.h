@@ -2,7 +2,7 @@
  * dugks.h -- C ABI of libdugks: the discrete unified gas kinetic scheme
  * (DUGKS) step for the nonlinear convection-diffusion equation
  *
- *     d_t phi + div B(phi) = div(alpha div D(phi))            (eq. 2.1, F = 0)
+ *     d_t phi + div B(phi) = div(alpha div D(phi)) + F(x, t, phi)      (eq. 2.1)
  *
  * on 2-D Cartesian meshes (uniform or stretched) with the D2Q9 lattice of
  * eq. 2.5 or the D2Q5 lattice of Remark 3, for MI355X (gfx950).
@@ -68,6 +68,8 @@ extern "C" {
 
 #define DUGKS_ABI_VERSION 3
 #define DUGKS_MAX_DEG 4        /* B and D: polynomials in phi of degree <= 4 */
+#define DUGKS_MAX_SRC_TERMS 6  /* terms of a source F(x, t, phi) */
+#define DUGKS_MAX_SRC_POW 3    /* highest power of phi in a source term */
 
 /* return codes */
 #define DUGKS_OK 0
@@ -180,12 +182,33 @@ int dugks_set_D(dugks_ctx* ctx, int deg, const double* dxx, const double* dxy, c
  * C = int B'B'^T, R_i = w_i c_i.B'(phi) F / c_s^2 (Remark 3); they enter
  * through the shifted distributions of eqs. 2.24-2.27, so that
  * phi = sum_i f~_i + dt F / 2.  F at a face is the linear interpolation of G
- * between the two cell centres (as eq. 2.20), at t_n + h; a ghost cell takes
- * the G of the cell whose distribution it copies.  Set the source before
- * dugks_set_phi: the initial f~ is E(phi) - dt (F_i + R_i) / 2.  Steps with a
- * source are launched one by one (no graph replay).  Errors: E_UNSUPPORTED
- * (16-bit storage or the plain kernel), E_ARG (gamma not finite), E_HIP. */
+ * between the two cell centres (as eq. 2.20), at t_n + h (where fbar of eq.
+ * 2.27 lives); a ghost cell takes the G of the cell whose distribution it
+ * copies.  Set the source before dugks_set_phi: the initial f~ is
+ * E(phi) - dt (F_i + R_i) / 2.  Steps with a source are launched one by one
+ * (no graph replay).  Same as dugks_set_source_terms with one term of power 0.
+ * Errors: E_UNSUPPORTED (16-bit storage or the plain kernel), E_ARG (gamma
+ * not finite), E_HIP. */
 int dugks_set_source(dugks_ctx* ctx, const double* g_dev, double gamma);
+
+/* Source term F of eq. 2.1 depending on phi, as a sum of nterms <=
+ * DUGKS_MAX_SRC_TERMS terms
+ *     F(x, t, phi) = sum_j exp(gammas[j] t) phi^powers[j] G_j(x),
+ * powers[j] in 0..DUGKS_MAX_SRC_POW, with the G_j given at the cell centres:
+ * g_dev is a device array [nterms][ny][nx] of binary64 values, caller-owned
+ * and kept alive and unchanged while the source is set; powers and gammas are
+ * host arrays (copied).  nterms == 0 removes the source.  This covers Example
+ * 4.2's k phi (1 - phi^delta) and Example 4.5's eq. 4.5.3.  Distributions,
+ * face rule and initialisation are those of dugks_set_source with F at the
+ * current phi; when some power is > 0 the conserved value is implicit (the
+ * paper notes this after eq. 2.27): phi = sum f~ + dt F(phi) / 2 in a cell and
+ * phi_b = sum fbar + h F_b(phi_b) / 2 at a face, each solved by Newton's method
+ * from the explicit sum until the update is at most 1e-15 (1 + |phi|) in
+ * binary64 (2.4e-7 in binary32), at most 8 (6) updates.  Errors: E_ARG
+ * (nterms, a power out of range, a rate not finite, NULL arrays, more than
+ * 4 GiB of G), E_UNSUPPORTED (16-bit storage or the plain kernel), E_HIP. */
+int dugks_set_source_terms(dugks_ctx* ctx, int nterms, const double* g_dev, const int* powers,
+                           const double* gammas);
 
 /* Dirichlet data: ring_dev (device, caller-owned, must outlive the steps)
  * holds nsteps rings of 2(nx+ny)+4 binary64 values, phi at the ghost
@@ -213,9 +236,9 @@ int dugks_set_f(dugks_ctx* ctx, const double* f, int on_device);
  * initialised, Dirichlet data exhausted), E_HIP. */
 int dugks_step(dugks_ctx* ctx, int nsteps);
 
-/* phi = sum_i f~_i (Sec. 2; plus dt F / 2 at the current time with a source)
- * accumulated in binary64, into out [ny][nx] (host if on_device == 0, else
- * device).  Synchronises. */
+/* phi = sum_i f~_i (Sec. 2) accumulated in binary64 (with a source the root
+ * of phi = sum_i f~_i + dt F(x, t, phi) / 2 at the current time), into
+ * out [ny][nx] (host if on_device == 0, else device).  Synchronises. */
 int dugks_get_phi(dugks_ctx* ctx, double* out, int on_device);
 
 /* f~ decoded to binary64 [q][ny][nx].  Synchronises. */
@@ -227,7 +250,8 @@ int dugks_get_diag(dugks_ctx* ctx, dugks_diag* out);
 
 /* GRE of eq. 4.1 (unweighted sums over cells) and the area-weighted relative
  * L2 error of phi against ref_dev [ny][nx] (device, binary64).  Binary64
- * reductions in a fixed order.  Synchronises. */
+ * reductions in a fixed order.  Synchronises.  Returns E_UNSTABLE, with both
+ * norms NaN, when some cell's phi is not finite. */
 int dugks_error_norms(dugks_ctx* ctx, const double* ref_dev, double* rel_l2, double* gre);
 
 /* For callers that cannot allocate (code under hipGraph capture, tight
@@ -241,7 +265,8 @@ int dugks_error_norms(dugks_ctx* ctx, const double* ref_dev, double* rel_l2, dou
  * refused for lack of room.  Every call on a GPU rewrites that array in full
  * before reading it: calls that overlap on one GPU (two streams, two threads)
  * race and must be ordered by the caller.  The sums are those of
- * dugks_error_norms in the same order.  Errors: E_ARG (NULL pointer), E_STATE
+ * dugks_error_norms in the same order; both norms are NaN when some cell's phi
+ * is not finite.  Errors: E_ARG (NULL pointer), E_STATE
  * (no state), E_HIP (launch, or the scratch address lookup on first use on a
  * device). */
 int dugks_error_norms_noalloc(dugks_ctx* ctx, const double* ref_dev, double* out_dev);
@@ -309,6 +334,9 @@ int dugks_batch_set_phi(dugks_batch* b, int i, const double* phi, int on_device)
  * for every instance; those without one read G = 0 and give the same result
  * as without it.  Errors: E_ARG (bad index), as dugks_set_source. */
 int dugks_batch_set_source(dugks_batch* b, int i, const double* g_dev, double gamma);
+/* Source terms of instance i, as dugks_set_source_terms (g_dev [nterms][ny_i][nx_i]). */
+int dugks_batch_set_source_terms(dugks_batch* b, int i, int nterms, const double* g_dev,
+                                 const int* powers, const double* gammas);
 int dugks_batch_autotune(dugks_batch* b, int trial_steps);
 int dugks_batch_set_launch(dugks_batch* b, int rows_per_wave, int waves_per_block, int schedule,
                            int xcd_remap);

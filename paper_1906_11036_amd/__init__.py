@@ -50,6 +50,27 @@ def _params(problem, storage, kernel):
     return p
 
 
+def _terms_args(terms, ny, nx, device):
+    """(device array [n][ny][nx], host powers, host rates) of source terms (k, gamma,
+    G), or Nones for no terms; the caller keeps the three alive."""
+    torch = _torch()
+    n = len(terms)
+    if n == 0:
+        return None, None, None
+    g = np.ascontiguousarray(np.stack([np.asarray(G, dtype=np.float64).reshape(ny, nx)
+                                       for _, _, G in terms]))
+    t = torch.from_numpy(g).to(device)
+    pw = (C.c_int * n)(*[int(k) for k, _, _ in terms])
+    gm = np.array([float(gam) for _, gam, _ in terms], dtype=np.float64)
+    return t, pw, gm
+
+
+def _terms_ptrs(t, pw, gm):
+    if t is None:
+        return None, None, None
+    return C.c_void_p(t.data_ptr()), pw, _dptr(gm)
+
+
 def _storage_code(storage):
     return L.STORAGE[storage] if isinstance(storage, str) else int(storage)
 
@@ -92,6 +113,8 @@ class Solver:
         self._src = None
         if getattr(problem, "src_g", None) is not None:
             self.set_source(problem.src_g, problem.src_gamma)
+        if getattr(problem, "src_terms", None):
+            self.set_source_terms(problem.src_terms)
 
     # -- coefficients
     def set_B(self, bx, by):
@@ -124,6 +147,15 @@ class Solver:
         L.check(self.lib.dugks_set_source(self.h, C.c_void_p(t.data_ptr()), float(gamma)), self.h,
                 "dugks_set_source")
         self._src = t
+
+    def set_source_terms(self, terms):
+        """F(x, t, phi) = sum over terms (k, gamma, G) of exp(gamma t) phi^k G(x), G
+        [ny][nx] at the cell centres, k in 0..3 (the G are kept alive here); an
+        empty list removes the source.  Call before set_phi."""
+        keep = _terms_args(terms, self.ny, self.nx, self.device)
+        L.check(self.lib.dugks_set_source_terms(self.h, len(terms), *_terms_ptrs(*keep)), self.h,
+                "dugks_set_source_terms")
+        self._src = keep if terms else None
 
     # -- state
     def _dev64(self, a, shape):
@@ -263,6 +295,8 @@ class Batch:
         for k, pb in enumerate(self.problems):
             if getattr(pb, "src_g", None) is not None:
                 self.set_source(k, pb.src_g, pb.src_gamma)
+            if getattr(pb, "src_terms", None):
+                self.set_source_terms(k, pb.src_terms)
 
     def __len__(self):
         return len(self.problems)
@@ -287,6 +321,17 @@ class Batch:
         L.check(self.lib.dugks_batch_set_source(self.h, i, C.c_void_p(t.data_ptr()), float(gamma)),
                 self.h, "dugks_batch_set_source")
         self._src[i] = t
+
+    def set_source_terms(self, i, terms):
+        """Source terms (k, gamma, G) of instance i (see Solver.set_source_terms)."""
+        pb = self.problems[i]
+        keep = _terms_args(terms, pb.ny, pb.nx, self.device)
+        L.check(self.lib.dugks_batch_set_source_terms(self.h, i, len(terms), *_terms_ptrs(*keep)),
+                self.h, "dugks_batch_set_source_terms")
+        if terms:
+            self._src[i] = keep
+        else:
+            self._src.pop(i, None)
 
     def set_all_phi(self):
         for i, pb in enumerate(self.problems):

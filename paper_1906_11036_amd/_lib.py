@@ -92,6 +92,7 @@ SIGNATURES = {
     "dugks_set_B": (_int, [_vp, _int, _dp, _dp]),
     "dugks_set_D": (_int, [_vp, _int, _dp, _dp, _dp]),
     "dugks_set_source": (_int, [_vp, _vp, C.c_double]),
+    "dugks_set_source_terms": (_int, [_vp, _int, _vp, C.POINTER(C.c_int), _dp]),
     "dugks_set_dirichlet": (_int, [_vp, _vp, _int]),
     "dugks_set_phi": (_int, [_vp, _vp, _int]),
     "dugks_set_f": (_int, [_vp, _vp, _int]),
@@ -112,6 +113,7 @@ SIGNATURES = {
     "dugks_batch_bind": (_int, [_vp, _vp, _sz, _vp]),
     "dugks_batch_set_phi": (_int, [_vp, _int, _vp, _int]),
     "dugks_batch_set_source": (_int, [_vp, _int, _vp, C.c_double]),
+    "dugks_batch_set_source_terms": (_int, [_vp, _int, _int, _vp, C.POINTER(C.c_int), _dp]),
     "dugks_batch_autotune": (_int, [_vp, _int]),
     "dugks_batch_set_launch": (_int, [_vp, _int, _int, _int, _int]),
     "dugks_batch_step": (_int, [_vp, _int]),

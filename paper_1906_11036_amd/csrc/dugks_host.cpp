@@ -43,8 +43,17 @@ struct Instance {
   std::vector<float> colgeo_f, rowgeo_f;
   double e[kMaxQ][kMaxCoef] = {{0}};
   double bp[2][kRhoCoef] = {{0}};         // c B'(phi) / cs2 per axis, see InstDev
-  const double* src_g = nullptr;          // source G [ny][nx] (device, caller-owned)
-  double src_gamma = 0.0;
+  // source terms exp(src_gam[j] t) phi^src_pow[j] G_j(x); G_j as [src_n][ny][nx]
+  // (device, caller-owned)
+  const double* src_g = nullptr;
+  int src_n = 0;
+  int src_pow[kMaxSrcTerms] = {0};
+  double src_gam[kMaxSrcTerms] = {0};
+  bool src_implicit() const {
+    for (int j = 0; j < src_n; ++j)
+      if (src_pow[j] > 0) return true;
+    return false;
+  }
   // workspace offsets
   size_t off_buf[2] = {0, 0}, off_colgeo = 0, off_rowgeo = 0, off_colgeo_f = 0, off_rowgeo_f = 0,
          off_widths = 0, off_slots = 0, off_flags = 0;
@@ -264,21 +273,40 @@ struct Engine {
   }
   bool any_source() const {
     for (auto& in : inst)
-      if (in.src_g != nullptr) return true;
+      if (in.src_n > 0) return true;
     return false;
   }
-  // A source on instance k (g == null removes it).  Sources run in binary64 /
-  // binary32 storage with the fused kernel.
-  int set_source(int k, const double* g, double gamma) {
-    if (g != nullptr) {
+  // source kind of a launch: 0 none, 1 all independent of phi, kSrcPow otherwise
+  int source_kind() const {
+    int kind = 0;
+    for (auto& in : inst) {
+      if (in.src_n == 0) continue;
+      kind = std::max(kind, in.src_implicit() ? kSrcPow : 1);
+    }
+    return kind;
+  }
+  // Source terms of instance k (n == 0 removes the source).  Sources run in
+  // binary64 / binary32 storage with the fused kernel.
+  int set_source_terms(int k, int n, const double* g, const int* pw, const double* gam) {
+    if (n < 0 || n > kMaxSrcTerms) return fail(DUGKS_E_ARG, "number of source terms out of range");
+    if (n > 0) {
+      if (!g || !pw || !gam) return fail(DUGKS_E_ARG, "source arrays are NULL");
       if (neq()) return fail(DUGKS_E_UNSUPPORTED, "sources need binary64 or binary32 storage");
       if (plain) return fail(DUGKS_E_UNSUPPORTED, "the plain kernel takes no source");
-      if (!std::isfinite(gamma)) return fail(DUGKS_E_ARG, "source rate is not finite");
-      if (sizeof(double) * (double)inst[k].cells() >= 4294967296.0)
-        return fail(DUGKS_E_ARG, "source array exceeds 4 GiB");
+      for (int j = 0; j < n; ++j) {
+        if (pw[j] < 0 || pw[j] > DUGKS_MAX_SRC_POW) return fail(DUGKS_E_ARG, "source power out of range");
+        if (!std::isfinite(gam[j])) return fail(DUGKS_E_ARG, "source rate is not finite");
+      }
+      if (sizeof(double) * (double)inst[k].cells() * n >= 4294967296.0)
+        return fail(DUGKS_E_ARG, "source arrays exceed 4 GiB");
     }
-    inst[k].src_g = g;
-    inst[k].src_gamma = g ? gamma : 0.0;
+    Instance& in = inst[k];
+    in.src_n = n > 0 ? n : 0;
+    in.src_g = n > 0 ? g : nullptr;
+    for (int j = 0; j < kMaxSrcTerms; ++j) {
+      in.src_pow[j] = j < n ? pw[j] : 0;
+      in.src_gam[j] = j < n ? gam[j] : 0.0;
+    }
     drop_graph();
     if (launch.waves_per_block > 4 && !wide_blocks_ok()) {   // the source path runs 4-wave blocks
       const int rc = set_launch(launch.rows_per_wave, 4, launch.schedule, launch.xcd_remap);
@@ -376,8 +404,14 @@ struct Engine {
           d.ef[i][m] = (float)d.e[i][m];
         }
       d.src_g = in.src_g;
-      d.src_bytes = in.src_g ? (unsigned)(sizeof(double) * in.cells()) : 0u;
-      d.src_gamma = in.src_gamma;
+      d.src_n = in.src_n;
+      d.src_implicit = in.src_implicit() ? 1 : 0;
+      d.src_plane = (unsigned)(sizeof(double) * in.cells());
+      d.src_bytes = (unsigned)(sizeof(double) * in.cells() * in.src_n);
+      for (int j = 0; j < kMaxSrcTerms; ++j) {
+        d.src_pow[j] = in.src_pow[j];
+        d.src_gam[j] = in.src_gam[j];
+      }
       d.dt = in.dt;
       d.lambda = in.lambda;
       d.half_dt = 0.5 * in.dt;
@@ -473,7 +507,7 @@ struct Engine {
     a.storage = storage;
     a.ncoef = ncoef_launch();
     a.persistent_blocks = persistent_blocks;
-    a.src = any_source() ? 1 : 0;
+    a.src = source_kind();
     return a;
   }
 
@@ -976,7 +1010,14 @@ int dugks_set_D(dugks_ctx* ctx, int deg, const double* dxx, const double* dxy, c
 
 int dugks_set_source(dugks_ctx* ctx, const double* g_dev, double gamma) {
   GUARD_CTX(ctx);
-  return ctx->set_source(0, g_dev, gamma);
+  const int zero = 0;
+  return ctx->set_source_terms(0, g_dev ? 1 : 0, g_dev, &zero, &gamma);
+}
+
+int dugks_set_source_terms(dugks_ctx* ctx, int nterms, const double* g_dev, const int* powers,
+                           const double* gammas) {
+  GUARD_CTX(ctx);
+  return ctx->set_source_terms(0, nterms, g_dev, powers, gammas);
 }
 
 int dugks_set_dirichlet(dugks_ctx* ctx, const double* ring_dev, int nsteps) {
@@ -1044,6 +1085,10 @@ int dugks_error_norms(dugks_ctx* ctx, const double* ref_dev, double* rel_l2, dou
   double r[8];
   int rc = ctx->reduce(0, ref_dev, r, nullptr, nullptr);
   if (rc) return rc;
+  if (r[5] > 0) {   // non-finite cells are left out of the sums: no error to report
+    *gre = *rel_l2 = NAN;
+    return ctx->fail(DUGKS_E_UNSTABLE, "non-finite phi on the device");
+  }
   *gre = r[2] > 0 ? r[1] / r[2] : (r[1] > 0 ? INFINITY : 0.0);
   *rel_l2 = r[4] > 0 ? sqrt(r[3] / r[4]) : (r[3] > 0 ? INFINITY : 0.0);
   return DUGKS_OK;
@@ -1207,7 +1252,15 @@ int dugks_batch_set_phi(dugks_batch* b, int i, const double* phi, int on_device)
 int dugks_batch_set_source(dugks_batch* b, int i, const double* g_dev, double gamma) {
   GUARD_BATCH(b);
   if (i < 0 || i >= (int)b->inst.size()) return b->fail(DUGKS_E_ARG, "instance index");
-  return b->set_source(i, g_dev, gamma);
+  const int zero = 0;
+  return b->set_source_terms(i, g_dev ? 1 : 0, g_dev, &zero, &gamma);
+}
+
+int dugks_batch_set_source_terms(dugks_batch* b, int i, int nterms, const double* g_dev,
+                                 const int* powers, const double* gammas) {
+  GUARD_BATCH(b);
+  if (i < 0 || i >= (int)b->inst.size()) return b->fail(DUGKS_E_ARG, "instance index");
+  return b->set_source_terms(i, nterms, g_dev, powers, gammas);
 }
 int dugks_batch_autotune(dugks_batch* b, int trial_steps) {
   GUARD_BATCH(b);

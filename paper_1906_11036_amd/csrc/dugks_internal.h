@@ -21,6 +21,8 @@ constexpr int kStripLanes = 64; // one wave covers 64 columns ...
 constexpr int kStripCols = 62;  // ... of which 62 are updated; lanes 0 and 63 are halo
 constexpr int kGeo = 5;
 constexpr int kRhoCoef = 4;     // B'(phi) has degree <= 3
+constexpr int kMaxSrcTerms = DUGKS_MAX_SRC_TERMS;
+constexpr int kSrcPow = 4;      // a source term carries phi^k, k <= 3
 
 // Per-instance constants and pointers, read by the kernels with scalar loads.
 //
@@ -32,14 +34,16 @@ constexpr int kRhoCoef = 4;     // B'(phi) has degree <= 3
 //   F = f_b / b3 = (a3 b1 / b3) gbar + E(phi_b)                (eq. 2.22 over b3)
 // and the update factor of each column / row carries the b3 back.
 //
-// With a source F(x, t) = exp(gamma t) G(x) (eq. 2.1) its distributions are
-// S_i = F_i + R_i = F rho_i(phi), rho_i = w_i (1 + c_i.B'(phi) / c_s^2) (eq. 2.3,
-// Remark 3), evaluated as w_i (1 + e_xi bp_x(phi) + e_yi bp_y(phi)) with e_i the
-// integer lattice directions and bp = c B' / c_s^2; eqs. 2.25 / 2.27 add
-// lambda S to g and to F:
-//   phi = sum f~ + dt F / 2,  g += lambda F rho(phi),
-//   phi_b = b1 sum gbar + h F_b / 2,  F += lambda F_b rho(phi_b),
-// with F_b the linear interpolation of G between the two centres, at t + h.
+// With a source F(x, t, phi) = sum_j exp(gamma_j t) phi^k_j G_j(x) (eq. 2.1's F,
+// k_j <= 3) its distributions are S_i = F_i + R_i = F rho_i(phi),
+// rho_i = w_i (1 + c_i.B'(phi) / c_s^2) (eq. 2.3, Remark 3), evaluated as
+// w_i (1 + e_xi bp_x(phi) + e_yi bp_y(phi)) with e_i the integer lattice
+// directions and bp = c B' / c_s^2; eqs. 2.25 / 2.27 add lambda S to g and to F:
+//   phi = sum f~ + dt F(phi) / 2,  g += lambda F rho(phi),
+//   phi_b = b1 sum gbar + h F_b(phi_b) / 2,  F += lambda F_b rho(phi_b),
+// with F_b built from each G_j interpolated linearly between the two centres,
+// at t + h.  When some k_j > 0 both relations are implicit and are solved by
+// Newton's method.
 struct alignas(64) InstDev {
   void* buf[2];            // ping-pong f~ buffers
   const double* colgeo;    // (nx+2) x kGeo doubles, column c = -1..nx at [(c+1)*kGeo]
@@ -61,10 +65,15 @@ struct alignas(64) InstDev {
   // E_i(phi) = sum_k e[i][k] phi^k  (eq. 2.3 with C = int_0^phi B'B'^T)
   double e[kMaxQ][kMaxCoef];
   float ef[kMaxQ][kMaxCoef];
-  // source (src_g == null: none); G [ny][nx] binary64, caller-owned
+  // source (src_n == 0: none); G_j as [src_n][ny][nx] binary64, caller-owned
   const double* src_g;
-  unsigned src_bytes;       // nx * ny * 8
-  double src_gamma, dt, lambda, half_dt, half_h;
+  unsigned src_bytes;       // src_n * nx * ny * 8
+  unsigned src_plane;       // nx * ny * 8: bytes of one G_j
+  int src_n;                // number of terms
+  int src_implicit;         // some term depends on phi
+  int src_pow[kMaxSrcTerms];
+  double src_gam[kMaxSrcTerms];
+  double dt, lambda, half_dt, half_h;
   float lambdaf, half_dtf, half_hf;
   double bp[2][kRhoCoef];    // c B'_x / c_s^2 and c B'_y / c_s^2 as polynomials in phi
   float bpf[2][kRhoCoef];
@@ -92,7 +101,7 @@ struct StepArgs {
   int parity;               // index of the buffer read by this step
   long long step;           // step index of the input state
   int q, storage, ncoef;    // template selectors, uniform over the launch
-  int src;                  // some instance has a source
+  int src;                  // 0: no source; 1: sources independent of phi; 4: some depend on phi
   int persistent_blocks;    // blocks of the persistent schedule
 };
 

@@ -197,14 +197,18 @@ template <typename T, int Q, int NC> struct Eq {
 };
 
 // Source constants of an instance (eq. 2.3's F_i and R_i through rho_i, eqs.
-// 2.25 and 2.27); empty without a source.
-template <typename T, int Q, bool SRC> struct SrcEq {
+// 2.25 and 2.27); empty without a source.  NF: 0 without a source, 1 for
+// sources independent of phi, kSrcPow when F is a polynomial in phi.
+template <typename T, int Q, int NF> struct SrcEq;
+template <typename T, int Q> struct SrcEq<T, Q, 0> {
   __device__ __forceinline__ void load(const InstDev*) {}
 };
-template <typename T, int Q> struct SrcEq<T, Q, true> {
+template <typename T, int Q, int NF> struct SrcEq {
   T bx[kRhoCoef], by[kRhoCoef];
   T lam, hdt, hh;
+  bool implicit;   // some term of this instance depends on phi
   __device__ __forceinline__ void load(const InstDev* __restrict__ I) {
+    implicit = NF > 1 && I->src_implicit != 0;
 #pragma unroll
     for (int m = 0; m < kRhoCoef; ++m) {
       bx[m] = Coef<T>::bp(I, 0)[m];
@@ -259,6 +263,35 @@ template <int Q> __device__ __forceinline__ float dir_sum(const float* v) {
 #pragma unroll
     for (int k = 0; k + w < Q; k += 2 * w) t[k] += t[k + w];
   return t[0];
+}
+
+// Conserved value v with v - half_tau P(v) = s, P(v) = sum_{k<NF} a[k] v^k
+// (half_tau = dt/2 in a cell, eq. 2.25; h/2 at a face, eq. 2.27).  Explicit
+// when F does not depend on phi (NF = 1, or an instance whose terms all have
+// power 0 in a launch for sources that do: the same root, rounded the same
+// way as in a launch without such sources); otherwise Newton's method from
+// v = s until the update is at most tol (1 + |v|) (1e-15 in binary64, 2.4e-7
+// in binary32) or after 8 (6) updates.
+template <int NF, typename T>
+__device__ __forceinline__ T solve_conserved(T s, T half_tau, const T* a, bool implicit = true) {
+  if (NF == 1 || !implicit) {
+    return fma(half_tau, a[0], s);
+  } else {
+    constexpr bool dbl = sizeof(T) == 8;
+    const T tol = dbl ? (T)1e-15 : (T)2.4e-7;
+    T v = s;
+#pragma unroll 1
+    for (int it = 0; it < (dbl ? 8 : 6); ++it) {
+      const T P = horner<NF>(a, v);
+      T dP = (T)(NF - 1) * a[NF - 1];
+#pragma unroll
+      for (int m = NF - 2; m >= 1; --m) dP = fma(dP, v, (T)m * a[m]);
+      const T d = (v - half_tau * P - s) / ((T)1 - half_tau * dP);
+      v -= d;
+      if (!(fabs(d) > tol * ((T)1 + fabs(v)))) break;
+    }
+    return v;
+  }
 }
 
 // ------------------------------------------------------------ memory
@@ -332,26 +365,35 @@ struct Scales {
 };
 
 // g = fbar+ / b1 (eq. 2.21) of the source cell and f~+ (eq. 2.23) when wanted.
-// With a source, Fc = F at the cell centre at t_n: phi = sum f~ + dt Fc / 2 and
-// g gains lambda Fc rho(phi) (eqs. 2.25, 2.27).
-template <int Q, int ST, int NC, bool SRC = false>
+// With a source, pc = the coefficients of F at the cell centre at t_n as a
+// polynomial in phi: phi solves phi = sum f~ + dt F(phi) / 2 and g gains
+// lambda F rho(phi) (eqs. 2.25, 2.27).
+template <int Q, int ST, int NC, int NF = 0>
 __device__ __forceinline__ void cell_g(const InstDev* __restrict__ I,
                                        const Eq<typename Stor<ST>::T, Q, NC>& eq,
                                        const Raw<Q, ST>& r, const Scales& sc,
                                        typename Stor<ST>::T* g, typename Stor<ST>::T* ftp,
                                        bool want_ftp, typename Stor<ST>::T& phi_out,
-                                       const SrcEq<typename Stor<ST>::T, Q, SRC>& se = {},
-                                       typename Stor<ST>::T Fc = 0) {
+                                       const SrcEq<typename Stor<ST>::T, Q, NF>& se = {},
+                                       const typename Stor<ST>::T* pc = nullptr) {
   using T = typename Stor<ST>::T;
+  constexpr bool SRC = NF > 0;
   static_assert(!SRC || !Stor<ST>::neq, "sources run in binary64 / binary32 storage");
   if constexpr (!Stor<ST>::neq) {
     double phi = 0.0;  // phi = sum_i f~_i (Sec. 2), binary64
 #pragma unroll
     for (int k = 0; k < Q; ++k) phi += (double)r.v[k];
-    if constexpr (SRC) phi += (double)se.hdt * (double)Fc;
+    T Fc = 0;
+    if constexpr (SRC) {
+      double a[NF];
+#pragma unroll
+      for (int k = 0; k < NF; ++k) a[k] = (double)pc[k];
+      phi = solve_conserved<NF, double>(phi, (double)se.hdt, a, se.implicit);
+    }
     const T p = (T)phi;
     const T ra = eq.ra;
     if constexpr (SRC) {
+      Fc = NF == 1 ? pc[0] : horner<NF>(pc, p);
       T ls[Q];
       se.template lam_s<(1u << Q) - 1u>(Fc, p, ls);
 #pragma unroll
@@ -448,12 +490,14 @@ template <int Q, int NRM> constexpr unsigned normal_mask() {
 // with a normal velocity component.  ts[k] = dL + dR, the sum of the two
 // cells' central-difference numerators along the face (directions with a
 // tangential component).  NRM = 0 for x-faces, 1 for y-faces.
-// With a source, Fb = F at the face point at t_n + h: phi_b gains h Fb / 2 and
-// F gains lambda Fb rho(phi_b) (eq. 2.27 solved for f).
-template <int Q, int NC, int NRM, typename T, bool SRC = false>
+// With a source, pb_c = the coefficients of F at the face point at t_n + h as
+// a polynomial in phi: phi_b solves phi_b = sum fbar + h F(phi_b) / 2 and F
+// gains lambda F(phi_b) rho(phi_b) (eq. 2.27 solved for f).
+template <int Q, int NC, int NRM, typename T, int NF = 0>
 __device__ __forceinline__ void face(const Eq<T, Q, NC>& eq, const T* L, const T* R, const T* ts,
                                      T am, T a0, T ap, T tau, T* out,
-                                     const SrcEq<T, Q, SRC>& se = {}, T Fb = 0) {
+                                     const SrcEq<T, Q, NF>& se = {}, const T* pb_c = nullptr) {
+  constexpr bool SRC = NF > 0;
   T gb[Q];
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
@@ -466,7 +510,11 @@ __device__ __forceinline__ void face(const Eq<T, Q, NC>& eq, const T* L, const T
   }
   // phi(x_b, t + h) = sum_i fbar_i = b1 sum_i gbar_i  (+ h F_b / 2)
   T pb = (T)(dir_sum<Q>(gb) * eq.b1);
-  if constexpr (SRC) pb = fma(se.hh, Fb, pb);
+  T Fb = 0;
+  if constexpr (SRC) {
+    pb = solve_conserved<NF, T>(pb, se.hh, pb_c, se.implicit);
+    Fb = NF == 1 ? pb_c[0] : horner<NF>(pb_c, pb);
+  }
   const T rb = eq.rb;
   T ls[Q];
   if constexpr (SRC) se.template lam_s<normal_mask<Q, NRM>()>(Fb, pb, ls);
@@ -493,18 +541,23 @@ __device__ __forceinline__ int xcd_logical(int b, int nblocks) {
 // ---------------------------------------------------------- fused step
 // GH: the item touches a wall (ghost rules needed); items that do not use a
 // branch-free row computation.
-// SRC: the launch carries a source (an instance without one reads G = 0).
-template <int Q, int ST, int NC, bool GH, bool SRC>
+// NF: 0 without a source; 1 when the launch carries sources independent of
+// phi; kSrcPow when some source is a polynomial in phi (an instance without a
+// source has no terms and gives the result of the source-free step).
+template <int Q, int ST, int NC, bool GH, int NF>
 __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const WorkItem it,
                                           int parity, long long step, int lane, bool measure) {
   using T = typename Stor<ST>::T;
   using C = Coef<T>;
+  constexpr bool SRC = NF > 0;
+  constexpr int NFA = NF > 0 ? NF : 1;   // array extents
+  constexpr int NT = SRC ? kMaxSrcTerms : 1;
   constexpr int PF = Stor<ST>::neq ? DUGKS_PREFETCH_NEQ : DUGKS_PREFETCH;
   static_assert(PF == 1 || PF == 2, "one or two rows ahead");
   static_assert(!SRC || PF == 1, "source rows follow the one-row prefetch");
   Eq<T, Q, NC> eq;
   eq.load(I);
-  SrcEq<T, Q, SRC> se;
+  SrcEq<T, Q, NF> se;
   se.load(I);
   const int nx = I->nx, ny = I->ny, pitch = I->pitch, bcx = I->bcx, bcy = I->bcy;
   const unsigned plane = (unsigned)I->plane;
@@ -533,24 +586,59 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
 
   const double* ring = (I->ring != nullptr) ? I->ring + step * I->ring_len : nullptr;
 
-  // Source: G of each row's cells (a ghost takes the G of the cell it copies),
-  // scaled by exp(gamma t) at t_n for the cells and at t_n + h for the faces.
+  // Source: G_j of each row's cells (a ghost takes the G_j of the cell it
+  // copies), each term scaled by exp(gamma_j t) at t_n for the cells (pc) and
+  // at t_n + h for the faces (FC), and summed by power of phi.
   __amdgpu_buffer_rsrc_t Rg = rsrc(nullptr, 0u);
-  T en = 0, eh = 0;
+  int nt = 0;
+  unsigned gplane = 0;
+  T en[NT], eh[NT];
+  int pw[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) { en[t] = 0; eh[t] = 0; pw[t] = 0; }
   if constexpr (SRC) {
     Rg = rsrc(I->src_g, I->src_bytes);
+    nt = I->src_n;
+    gplane = I->src_plane;
     const double tn = (double)step * I->dt;
-    en = (T)exp(I->src_gamma * tn);
-    eh = (T)exp(I->src_gamma * (tn + I->half_dt));
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+      if (t < nt) {
+        en[t] = (T)exp(I->src_gam[t] * tn);
+        eh[t] = (T)exp(I->src_gam[t] * (tn + I->half_dt));
+        pw[t] = NF == 1 ? 0 : I->src_pow[t];
+      }
   }
-  auto load_gsrc = [&](int r) -> T {
-    return (T)__builtin_bit_cast(
-        double, __builtin_amdgcn_raw_buffer_load_b64(Rg, (unsigned)(src_index(r, ny, bcy) * nx + sc_col) * 8u, 0u, 0));
+  auto load_gsrc = [&](int r, T* gr) {
+    const unsigned off = (unsigned)(src_index(r, ny, bcy) * nx + sc_col) * 8u;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+      gr[t] = t < nt ? (T)__builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                                       Rg, off, (unsigned)t * gplane, 0))
+                     : (T)0;
+  };
+  // coefficients of F as a polynomial in phi at the cell (t_n) and for the faces (t_n + h)
+  auto coefs = [&](const T* gr, T* pc, T* pf) {
+#pragma unroll
+    for (int k = 0; k < NFA; ++k) { pc[k] = 0; pf[k] = 0; }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+      if (t < nt) {
+#pragma unroll
+        for (int k = 0; k < NFA; ++k)
+          if (pw[t] == k) {
+            pc[k] = fma(en[t], gr[t], pc[k]);
+            pf[k] = fma(eh[t], gr[t], pf[k]);
+          }
+      }
   };
 
-  auto make_row = [&](const Raw<Q, ST>& raw, int r, T* g, T* ftp, bool want_ftp, T gsrc) {
+  auto make_row = [&](const Raw<Q, ST>& raw, int r, T* g, T* ftp, bool want_ftp, const T* gr,
+                      T* pf) {
     T phi_a;
-    cell_g<Q, ST, NC, SRC>(I, eq, raw, sc, g, ftp, want_ftp, phi_a, se, en * gsrc);
+    T pc[NFA];
+    coefs(gr, pc, pf);
+    cell_g<Q, ST, NC, NF>(I, eq, raw, sc, g, ftp, want_ftp, phi_a, se, pc);
     if constexpr (!GH) return;
     const bool wall_y = (r < 0 || r >= ny) && bcy != DUGKS_BC_PERIODIC;
     if (wall_y || strip_touches_x_wall) {
@@ -572,19 +660,28 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
   // is a change of register names, not a copy.
   T G[3][Q], LS[3][Q], FT[3][Q], SX[3][Q], FY[3][Q], ts[Q], dy[Q], fW[Q];
   Raw<Q, ST> RW[3];
-  T GQ[3] = {0, 0, 0};   // source G of the row whose raw values sit in RW[.]
+  T GR[3][NT];     // source G_j of the row whose raw values sit in RW[.]
+  T FC[3][NFA];    // face-time coefficients of F of the row made into G[.]
+  T pfb[NFA];      // the same interpolated to a face
+#pragma unroll
+  for (int s3 = 0; s3 < 3; ++s3) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) GR[s3][t] = 0;
+#pragma unroll
+    for (int k = 0; k < NFA; ++k) FC[s3][k] = 0;
+  }
 
   // prologue: row y0-1 in slot 2, row y0 in slot 0, the face below row y0 in FY[2]
   load_raw_buf<Q, ST>(RW[2], Rin, plane, row_idx(y0 - 1));
   load_raw_buf<Q, ST>(RW[0], Rin, plane, row_idx(y0));
   load_raw_buf<Q, ST>(RW[1], Rin, plane, row_idx(y0 + 1));
   if constexpr (SRC) {
-    GQ[2] = load_gsrc(y0 - 1);
-    GQ[0] = load_gsrc(y0);
-    GQ[1] = load_gsrc(y0 + 1);
+    load_gsrc(y0 - 1, GR[2]);
+    load_gsrc(y0, GR[0]);
+    load_gsrc(y0 + 1, GR[1]);
   }
-  make_row(RW[2], y0 - 1, G[2], FT[2], false, GQ[2]);
-  make_row(RW[0], y0, G[0], FT[0], true, GQ[0]);
+  make_row(RW[2], y0 - 1, G[2], FT[2], false, GR[2], FC[2]);
+  make_row(RW[0], y0, G[0], FT[0], true, GR[0], FC[0]);
   if constexpr (PF == 2)  // two rows in flight ahead of the row being consumed
     load_raw_buf<Q, ST>(RW[2], Rin, plane, row_idx(y0 + 2 <= y1 ? y0 + 2 : y1));
 #pragma unroll
@@ -597,8 +694,9 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
   }
   {
     const CPtr<T> g = rg + (long long)(y0 + 1) * kGeo;
-    face<Q, NC, 1, T, SRC>(eq, G[2], G[0], ts, g[0], g[1], g[2], ctau, FY[2], se,
-                           eh * fma(g[1], GQ[0] - GQ[2], GQ[2]));
+#pragma unroll
+    for (int k = 0; k < NFA; ++k) pfb[k] = fma(g[1], FC[0][k] - FC[2][k], FC[2][k]);
+    face<Q, NC, 1, T, NF>(eq, G[2], G[0], ts, g[0], g[1], g[2], ctau, FY[2], se, pfb);
   }
 
   bool bad = false, ovf = false;
@@ -610,8 +708,8 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
       load_raw_buf<Q, ST>(RW[s0], Rin, plane, row_idx(j + 3 <= y1 ? j + 3 : y1));
     else
       load_raw_buf<Q, ST>(RW[sm], Rin, plane, row_idx(j + 2 <= y1 ? j + 2 : y1));
-    if constexpr (SRC) GQ[sm] = load_gsrc(j + 2 <= y1 ? j + 2 : y1);
-    make_row(RW[sp], j + 1, G[sp], FT[sp], true, GQ[sp]);
+    if constexpr (SRC) load_gsrc(j + 2 <= y1 ? j + 2 : y1, GR[sm]);
+    make_row(RW[sp], j + 1, G[sp], FT[sp], true, GR[sp], FC[sp]);
     const CPtr<T> gj = rg + (long long)(j + 1) * kGeo;   // row j: its S face and factors
     const CPtr<T> gn = rg + (long long)(j + 2) * kGeo;   // row j+1: S face = N face of row j
     const T rtau = gj[3], rk = gj[4];
@@ -624,8 +722,9 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
         ts[k] = SX[s0][k] + SX[sp][k];
       }
     }
-    face<Q, NC, 1, T, SRC>(eq, G[s0], G[sp], ts, gn[0], gn[1], gn[2], ctau, FY[s0], se,
-                           eh * fma(gn[1], GQ[sp] - GQ[s0], GQ[s0]));
+#pragma unroll
+    for (int k = 0; k < NFA; ++k) pfb[k] = fma(gn[1], FC[sp][k] - FC[s0][k], FC[s0][k]);
+    face<Q, NC, 1, T, NF>(eq, G[s0], G[sp], ts, gn[0], gn[1], gn[2], ctau, FY[s0], se, pfb);
     // west face of this lane's cell: left state from lane-1; y-slope numerators
 #pragma unroll
     for (int k = 0; k < Q; ++k)
@@ -634,9 +733,12 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
         ts[k] = shr1(dy[k]) + dy[k];
       }
     if constexpr (SRC) {
-      const T gl = shr1(GQ[s0]);
-      face<Q, NC, 0, T, SRC>(eq, LS[s0], G[s0], ts, cam, ca0, cap, rtau, fW, se,
-                             eh * fma(ca0, GQ[s0] - gl, gl));
+#pragma unroll
+      for (int k = 0; k < NFA; ++k) {
+        const T gl = shr1(FC[s0][k]);
+        pfb[k] = fma(ca0, FC[s0][k] - gl, gl);
+      }
+      face<Q, NC, 0, T, NF>(eq, LS[s0], G[s0], ts, cam, ca0, cap, rtau, fW, se, pfb);
     } else {
       face<Q, NC, 0>(eq, LS[s0], G[s0], ts, cam, ca0, cap, rtau, fW);
     }
@@ -727,17 +829,17 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
 #endif
 // The source path holds more per row (G and its window): one wave per SIMD,
 // the full register file, no spills.
-template <int ST, bool SRC> struct Occupancy {
-  static constexpr int value = SRC ? 1 : (ST == DUGKS_F64 ? DUGKS_WAVES_PER_EU_F64 : DUGKS_WAVES_PER_EU_F32);
+template <int ST, int NF> struct Occupancy {
+  static constexpr int value = NF > 0 ? 1 : (ST == DUGKS_F64 ? DUGKS_WAVES_PER_EU_F64 : DUGKS_WAVES_PER_EU_F32);
 };
 // Threads per block: at two waves per SIMD a block may hold 8 waves (fewer,
 // larger blocks to dispatch); at one wave per SIMD at most 4.
-template <int ST, bool SRC> constexpr int step_max_threads() {
-  return Occupancy<ST, SRC>::value >= 2 ? 512 : 256;
+template <int ST, int NF> constexpr int step_max_threads() {
+  return Occupancy<ST, NF>::value >= 2 ? 512 : 256;
 }
 
-template <int Q, int ST, int NC, bool SRC>
-__global__ __launch_bounds__((step_max_threads<ST, SRC>())) __attribute__((amdgpu_waves_per_eu(Occupancy<ST, SRC>::value)))
+template <int Q, int ST, int NC, int NF>
+__global__ __launch_bounds__((step_max_threads<ST, NF>())) __attribute__((amdgpu_waves_per_eu(Occupancy<ST, NF>::value)))
 void k_step(const InstDev* __restrict__ insts,
                                               const WorkItem* __restrict__ items, int nitems,
                                               int parity, long long step, int xcd_remap,
@@ -754,9 +856,9 @@ void k_step(const InstDev* __restrict__ insts,
     const bool wall_x = I->bcx != DUGKS_BC_PERIODIC && (it.x0 == 0 || it.x0 + kStripCols >= I->nx);
     const bool wall_y = I->bcy != DUGKS_BC_PERIODIC && (it.y0 == 0 || it.y1 == I->ny);
     if (wall_x || wall_y)
-      step_item<Q, ST, NC, true, SRC>(I, it, parity, step, lane, measure != 0);
+      step_item<Q, ST, NC, true, NF>(I, it, parity, step, lane, measure != 0);
     else
-      step_item<Q, ST, NC, false, SRC>(I, it, parity, step, lane, measure != 0);
+      step_item<Q, ST, NC, false, NF>(I, it, parity, step, lane, measure != 0);
     if (!persistent) break;
   }
 }
@@ -847,12 +949,23 @@ __device__ __forceinline__ void feq64(const InstDev* __restrict__ I, double phi,
   }
 }
 
-// dt F / 2 at interior cell (i, j) at step `step` (0 without a source): with a
-// source phi = sum f~ + dt F / 2 (eq. 2.25 summed with the moments of eq. 2.7).
-__device__ __forceinline__ double src_phi_shift(const InstDev* __restrict__ I, int i, int j,
-                                                long long step) {
-  if (I->src_g == nullptr) return 0.0;
-  return I->half_dt * exp(I->src_gamma * ((double)step * I->dt)) * I->src_g[(long long)j * I->nx + i];
+// The conserved value of interior cell (i, j) at step `step` from s = sum f~:
+// s without a source; with one the root of phi = s + dt F(x, t, phi) / 2 (eq.
+// 2.25 summed with the moments of eq. 2.7), as the step kernel solves it.
+__device__ __forceinline__ double src_cell_phi(const InstDev* __restrict__ I, int i, int j,
+                                               long long step, double s) {
+  if (I->src_n == 0) return s;
+  const long long N = (long long)I->nx * I->ny;
+  const double t = (double)step * I->dt;
+  double a[kSrcPow] = {0.0, 0.0, 0.0, 0.0};
+  for (int u = 0; u < I->src_n; ++u) {
+    const double g = I->src_g[u * N + (long long)j * I->nx + i];
+    const double e = exp(I->src_gam[u] * t);
+    const int k = I->src_implicit ? I->src_pow[u] : 0;
+    for (int m = 0; m < kSrcPow; ++m)
+      if (m == k) a[m] = fma(e, g, a[m]);
+  }
+  return solve_conserved<kSrcPow, double>(s, I->half_dt, a, I->src_implicit != 0);
 }
 
 // 16-bit encode of f~ (binary64 values) at one cell.
@@ -888,13 +1001,20 @@ __global__ void k_init_eq(const InstDev* __restrict__ I, const double* __restric
   if constexpr (!Stor<ST>::neq) {
     double E[Q];
     feq64<Q>(I, p, E);
-    if (I->src_g != nullptr) {
-      // f = E at t = 0 (Omega = 0): f~ = E - dt S / 2 with S_i = G rho_i(phi) (eq. 2.25)
-      const double G = I->src_g[(long long)j * I->nx + i];
+    if (I->src_n > 0) {
+      // f = E at t = 0 (Omega = 0): f~ = E - dt S / 2 with S_i = F(x, 0, phi)
+      // rho_i(phi) (eq. 2.25), F(x, 0, phi) = sum_j phi^k_j G_j(x)
+      const long long N = (long long)I->nx * I->ny;
+      double F = 0.0;
+      for (int t = 0; t < I->src_n; ++t) {
+        double pk = 1.0;
+        for (int m = 0; m < I->src_pow[t]; ++m) pk *= p;
+        F += pk * I->src_g[t * N + (long long)j * I->nx + i];
+      }
       const double px = horner<kRhoCoef>(I->bp[0], p), py = horner<kRhoCoef>(I->bp[1], p);
 #pragma unroll
       for (int k = 0; k < Q; ++k)
-        E[k] -= I->half_dt * G * lat_w<Q>(k) * (1.0 + lat_cx(k) * px + lat_cy(k) * py);
+        E[k] -= I->half_dt * F * lat_w<Q>(k) * (1.0 + lat_cx(k) * px + lat_cy(k) * py);
     }
     using T = typename Stor<ST>::T;
 #pragma unroll
@@ -985,7 +1105,7 @@ __global__ void k_get_phi(const InstDev* __restrict__ I, double* __restrict__ ou
     phi = 0.0;
 #pragma unroll
     for (int k = 0; k < Q; ++k) phi += f[k];
-    phi += src_phi_shift(I, i, j, step);
+    phi = src_cell_phi(I, i, j, step, phi);
   }
   out[(long long)j * I->nx + i] = phi;
 }
@@ -1038,7 +1158,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const InstDev* __restric
       phi = 0.0;
 #pragma unroll
       for (int k = 0; k < Q; ++k) phi += f[k];
-      phi += src_phi_shift(I, i, j, step);
+      phi = src_cell_phi(I, i, j, step, phi);
     }
     const double vol = widths[i] * widths[I->nx + j];
     if (!__builtin_isfinite(phi)) {
@@ -1080,13 +1200,18 @@ __global__ void k_reduce_final(const double* __restrict__ partial, int nblocks,
 }
 
 // Final pass of the allocation-free norms: the partial sums in block order (as
-// k_reduce_final), then out[0] = relative L2, out[1] = GRE (eq. 4.1).
+// k_reduce_final), then out[0] = relative L2, out[1] = GRE (eq. 4.1); NaN for
+// both when some cell is not finite (those cells are left out of the sums).
 __global__ void k_norms_final(const double* __restrict__ partial, int nblocks,
                               double* __restrict__ out) {
   if (threadIdx.x != 0) return;
-  double r[5] = {0, 0, 0, 0, 0};
-  for (int v = 1; v < 5; ++v)
+  double r[6] = {0, 0, 0, 0, 0, 0};
+  for (int v = 1; v < 6; ++v)
     for (int b = 0; b < nblocks; ++b) r[v] += partial[b * kRedVals + v];
+  if (r[5] > 0) {
+    out[0] = out[1] = __builtin_nan("");
+    return;
+  }
   out[0] = r[4] > 0 ? sqrt(r[3] / r[4]) : (r[3] > 0 ? INFINITY : 0.0);
   out[1] = r[2] > 0 ? r[1] / r[2] : (r[1] > 0 ? INFINITY : 0.0);
 }
@@ -1136,29 +1261,26 @@ static int launch_step_q_st(const StepArgs& a, const Launch& l, void* stream, in
   if (persistent) blocks = a.persistent_blocks;
   if (blocks <= 0) return 0;
   dim3 grid(blocks), block(64 * wpb);
-#define DUGKS_STEP_LAUNCH(NC_, SRC_)                                                          \
-  hipLaunchKernelGGL((k_step<Q, ST, NC_, SRC_>), grid, block, 0, S(stream), a.insts, a.items, \
+#define DUGKS_STEP_LAUNCH(NC_, NF_)                                                          \
+  hipLaunchKernelGGL((k_step<Q, ST, NC_, NF_>), grid, block, 0, S(stream), a.insts, a.items, \
                      a.nitems, a.parity, a.step, l.xcd_remap, persistent, measure)
+#define DUGKS_STEP_NC(NF_)                                \
+  switch (a.ncoef) {                                      \
+    case 2: DUGKS_STEP_LAUNCH(2, NF_); break;             \
+    case 4: DUGKS_STEP_LAUNCH(4, NF_); break;             \
+    default: DUGKS_STEP_LAUNCH(8, NF_); break;            \
+  }
   if constexpr (Stor<ST>::neq) {
     if (a.src) return -1;  // sources run in binary64 / binary32 storage only
-    switch (a.ncoef) {
-      case 2: DUGKS_STEP_LAUNCH(2, false); break;
-      case 4: DUGKS_STEP_LAUNCH(4, false); break;
-      default: DUGKS_STEP_LAUNCH(8, false); break;
-    }
+    DUGKS_STEP_NC(0);
+  } else if (a.src == kSrcPow) {
+    DUGKS_STEP_NC(kSrcPow);
   } else if (a.src) {
-    switch (a.ncoef) {
-      case 2: DUGKS_STEP_LAUNCH(2, true); break;
-      case 4: DUGKS_STEP_LAUNCH(4, true); break;
-      default: DUGKS_STEP_LAUNCH(8, true); break;
-    }
+    DUGKS_STEP_NC(1);
   } else {
-    switch (a.ncoef) {
-      case 2: DUGKS_STEP_LAUNCH(2, false); break;
-      case 4: DUGKS_STEP_LAUNCH(4, false); break;
-      default: DUGKS_STEP_LAUNCH(8, false); break;
-    }
+    DUGKS_STEP_NC(0);
   }
+#undef DUGKS_STEP_NC
 #undef DUGKS_STEP_LAUNCH
   DUGKS_CHECK_LAUNCH();
 }

@@ -342,3 +342,32 @@ def test_3d_default_launch_follows_the_documented_model(q, storage, bc):
         assert got == _default_launch3(nx, ny, nz, q, f32, walls), (nx, ny, nz)
         if (nx, ny, nz) == (256, 256, 256) and q == 19:
             assert got[1] == (64 if f32 else 128)
+
+
+def test_source_terms_validation_without_a_device():
+    """dugks_set_source_terms checks its arguments before any device work."""
+    lib = L.lib()
+    rc, h = _create(nx=10, ny=8)
+    assert rc == L.OK
+    g = C.c_void_p(0x1000)          # never dereferenced on these paths
+    pw = (C.c_int * 7)(*([0] * 7))
+    gm = np.zeros(7)
+    gmp = gm.ctypes.data_as(C.POINTER(C.c_double))
+    assert lib.dugks_set_source_terms(h, 7, g, pw, gmp) == L.E_ARG          # more than 6 terms
+    pw[0] = 4
+    assert lib.dugks_set_source_terms(h, 1, g, pw, gmp) == L.E_ARG          # power above 3
+    pw[0] = 2
+    gm[0] = float("inf")
+    assert lib.dugks_set_source_terms(h, 1, g, pw, gmp) == L.E_ARG          # rate not finite
+    gm[0] = -1.0
+    assert lib.dugks_set_source_terms(h, 1, None, pw, gmp) == L.E_ARG       # no G
+    assert lib.dugks_set_source_terms(h, 1, g, pw, gmp) == L.OK             # not bound: kept
+    assert lib.dugks_set_source_terms(h, 0, None, None, None) == L.OK       # removed
+    lib.dugks_destroy(h)
+    for storage in (L.F16NEQ, L.BF16NEQ):
+        rc, h = _create(nx=10, ny=8, storage=storage)
+        assert lib.dugks_set_source_terms(h, 1, g, pw, gmp) == L.E_UNSUPPORTED
+        lib.dugks_destroy(h)
+    rc, h = _create(nx=10, ny=8, kernel=L.KERNEL_PLAIN)
+    assert lib.dugks_set_source_terms(h, 1, g, pw, gmp) == L.E_UNSUPPORTED
+    lib.dugks_destroy(h)

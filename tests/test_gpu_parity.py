@@ -255,3 +255,25 @@ def test_autotune_refuses_exhausted_dirichlet_data():
     with pytest.raises(dg.DugksError) as ei:
         s.autotune(1)
     assert ei.value.code == dg._lib.E_STATE
+
+
+def test_error_norms_of_a_nonfinite_state_are_refused():
+    """A state with a non-finite cell has no error norm: E_UNSTABLE (and NaN from
+    the allocation-free variant), not the norm of the finite cells."""
+    import ctypes as C
+
+    import torch
+    p = W.random_problem(14, 40, 30)
+    phi = p.phi0.copy()
+    phi[3, 4] = np.inf
+    s = dg.Solver(p, storage="f64")
+    s.set_phi(phi)
+    with pytest.raises(dg.DugksError) as ei:
+        s.error_norms(p.phi0)
+    assert ei.value.code == dg._lib.E_UNSTABLE
+    r = torch.from_numpy(p.phi0).to(s.device)
+    out = torch.zeros(2, dtype=torch.float64, device=s.device)
+    assert dg._lib.lib().dugks_error_norms_noalloc(s.h, C.c_void_p(r.data_ptr()),
+                                                   C.c_void_p(out.data_ptr())) == 0
+    torch.cuda.synchronize()
+    assert np.isnan(out.cpu().numpy()).all()
