@@ -8,8 +8,10 @@ launch per step.  A step is one DUGKS time step of every instance.
 Printed: one JSON line with MLUPS (whole job), the dominant kernel's achieved
 HBM bandwidth against the 8 TB/s peak (hipEvents on the launch stream), the
 binary64 plain-kernel and fused-kernel rates on the same batch, the relative
-L2 difference of the binary32 result from the binary64 one, and the CPU
-oracle timed on a bounded sample.
+L2 difference of the stored format's phi from the binary64 path's after the
+workload's own step count (500 for the batch), how many of the timed steps
+were replayed from captured graphs, and the CPU oracle timed on a bounded
+sample on all host cores and on one.
 """
 from __future__ import annotations
 
@@ -121,8 +123,12 @@ def run_batch(problems, storage, steps, warmup, autotune=True, launch=None):
             one.s.autotune(3)     # trial steps reuse the current step's ghost data
         one.s.step(warmup)
         torch.cuda.synchronize()
+        i0 = one.s.info()
         ms = one.s.time_steps(steps)
         torch.cuda.synchronize()
+        i1 = one.s.info()
+        one.timed_launch = {"graph_steps": i1["graph_steps"] - i0["graph_steps"],
+                            "eager_steps": i1["eager_steps"] - i0["eager_steps"]}
         return one, ms
     b = dg.Batch(problems, storage=storage, launch=launch)
     b.set_all_phi()
@@ -130,9 +136,30 @@ def run_batch(problems, storage, steps, warmup, autotune=True, launch=None):
         b.autotune(3)
     b.step(warmup)
     torch.cuda.synchronize()
+    i0 = b.info(0)
     ms = b.time_steps(steps)   # hipEvents around the launches on the bound stream
     torch.cuda.synchronize()
+    i1 = b.info(0)
+    b.timed_launch = {"graph_steps": i1["graph_steps"] - i0["graph_steps"],
+                      "eager_steps": i1["eager_steps"] - i0["eager_steps"]}
     return b, ms
+
+
+def accuracy_vs_fp64(problems, storage, launch, launch64):
+    """Relative L2 difference (over all instances) of phi in the given storage
+    from the binary64 fused path's after the workload's own step count; both
+    runs start from the same initial fields."""
+    import torch
+    nsteps = max(p.steps for p in problems)
+    out = []
+    for st, ln in ((storage, launch), (0, launch64)):
+        b, _ = run_batch(problems, st, nsteps, 0, autotune=False, launch=ln)
+        out.append([b.get_phi(i) for i in range(len(problems))])
+        del b
+        torch.cuda.empty_cache()
+    num = sum(float(((a - r) ** 2).sum()) for a, r in zip(out[0], out[1]))
+    den = sum(float((r ** 2).sum()) for r in out[1])
+    return math.sqrt(num / den), nsteps
 
 
 def plain_fp64_rate(problems, steps):
@@ -154,21 +181,44 @@ def plain_fp64_rate(problems, steps):
     return cells / (total_ms * 1e-3) / 1e6
 
 
-def cpu_baseline(seconds):
-    """The oracle as it stands, single thread, on one 512^2 batch-like instance."""
+def host_cpu():
+    """CPU model (as lscpu names it) and the cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return model, n
+
+
+def cpu_baseline(seconds, all_cores=True):
+    """The oracle as it stands on one 512^2 batch-like instance: its OpenMP build
+    on every core this process may use, or its serial build on one."""
     from oracle import Oracle
+    from oracle import oracle as OR
     from paper_1906_11036_amd import workloads as W
+    model, ncpu = host_cpu()
+    threads = OR.threads(ncpu, openmp=True) if all_cores else 1
     p = W.batch_problems(count=1, nmin=512, nmax=512)[0]
-    o = Oracle(p)
+    o = Oracle(p, openmp=all_cores)
     o.step(1)
     steps, t0 = 0, time.perf_counter()
     while time.perf_counter() - t0 < seconds:
         o.step(5)
         steps += 5
     el = time.perf_counter() - t0
-    return {"value": p.cells * steps / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+    return {"value": round(p.cells * steps / el / 1e6, 3), "unit": "MLUPS", "cores": threads,
+            "kind": "oracle", "cpu_model": model, "nproc": ncpu,
             "sample": f"one 512x512 periodic D2Q9 instance of the batch recipe (B = a(1,1)phi^2/2, "
-                      f"D = phi I), {steps} steps in {el:.1f} s, binary64, 1 thread"}
+                      f"D = phi I), {steps} steps in {el:.1f} s, binary64, {threads} thread(s)"}
 
 
 def cpu_baseline3d(seconds):
@@ -315,18 +365,28 @@ def main3d(args):
         f"(rows/block={info['rows_per_block']} planes/block={info['planes_per_block']})")
     extras = {}
     if not args.no_extras:
-        phi32 = s.get_phi()
         s.close()
         del s
         torch.cuda.empty_cache()
         s64, ms64 = run("f64")
         fused64 = p.cells * args.steps / (ms64 * 1e-3) / 1e6
-        phi64 = s64.get_phi()
         s64.close()
-        l2 = float(np.sqrt(((phi32 - phi64) ** 2).sum() / (phi64 ** 2).sum()))
-        log(f"f64 fused: {fused64:.0f} MLUPS; rel-L2(f32 vs f64) after {args.warmup + args.steps} steps {l2:.2e}")
+        del s64
+        torch.cuda.empty_cache()
+        # phi after the workload's own step count, from the initial field, in both storages
+        phis = []
+        for st, ln in ((args.storage, launch), ("f64", None)):
+            sa = dg.Solver3D(p, storage=st, launch=ln)
+            sa.set_phi(p.phi0)
+            sa.step(p.steps)
+            phis.append(sa.get_phi())
+            sa.close()
+            del sa
+            torch.cuda.empty_cache()
+        l2 = float(np.sqrt(((phis[0] - phis[1]) ** 2).sum() / (phis[1] ** 2).sum()))
+        log(f"f64 fused: {fused64:.0f} MLUPS; rel-L2({args.storage} vs f64) after {p.steps} steps {l2:.2e}")
         extras = {"fp64_fused_mlups": round(fused64, 1), "rel_l2_vs_fp64": l2,
-                  "rel_l2_after_steps": args.warmup + args.steps}
+                  "rel_l2_after_steps": p.steps}
     launch_s = f"{info['rows_per_block']},{info['planes_per_block']}"
     kernel = "k_step3p" if p.q != 7 else ("k_step3s" if storage else "k_step3h")
     traffic_b = measured_traffic(args.workload, args.storage, launch_s, kernel=kernel,
@@ -425,30 +485,30 @@ def main():
         f"(launch rows/wave={info['rows_per_wave']} waves/block={info['waves_per_block']} "
         f"schedule={info['schedule']})")
 
+    timed_launch = getattr(b, "timed_launch", None)
     extras = {}
     if not args.no_extras:
-        # binary64 runs of the same batch for the L2 difference and the rate comparison
-        nsteps_total = args.warmup + args.steps
+        # binary64 runs of the same batch for the rate comparison and, from the
+        # initial fields again, for the L2 difference after the workload's steps
         launch64 = tune.lookup(args.workload, "f64")
         b64, ms64 = run_batch(problems, L.F64, args.steps, args.warmup,
                               autotune=launch64 is None, launch=launch64)
         fused64 = cells * args.steps / (ms64 * 1e-3) / 1e6
-        num = den = 0.0
-        for i in range(len(problems)):
-            a32, a64 = b.get_phi(i), b64.get_phi(i)
-            num += float(((a32 - a64) ** 2).sum())
-            den += float((a64 ** 2).sum())
-        l2 = math.sqrt(num / den)
         del b64
         torch.cuda.empty_cache()
-        log(f"f64 fused: {fused64:.0f} MLUPS; rel-L2(f32 vs f64) after {nsteps_total} steps {l2:.2e}")
+        launch_used = (info["rows_per_wave"], info["waves_per_block"], info["schedule"], info["xcd_remap"])
+        if storage != L.F64:
+            l2, nsteps_l2 = accuracy_vs_fp64(problems, storage, launch_used, launch64)
+        else:
+            l2, nsteps_l2 = 0.0, max(p.steps for p in problems)
+        log(f"f64 fused: {fused64:.0f} MLUPS; rel-L2({args.storage} vs f64) after {nsteps_l2} steps {l2:.2e}")
         # the plain kernel takes no source term: no plain comparison for source workloads
         plain64 = None if src_cells else plain_fp64_rate(problems, max(2, min(args.steps, 20)))
         log(f"f64 plain: {plain64:.0f} MLUPS" if plain64 else "f64 plain: n/a (source term)")
         extras = {"fp64_fused_mlups": round(fused64, 1),
                   "fp64_plain_mlups": round(plain64, 1) if plain64 else None,
                   "speedup_vs_plain_fp64": round(mlups / plain64, 2) if plain64 else None,
-                  "rel_l2_vs_fp64": l2, "rel_l2_after_steps": nsteps_total}
+                  "rel_l2_vs_fp64": l2, "rel_l2_after_steps": nsteps_l2}
 
     launch_s = f"{info['rows_per_wave']},{info['waves_per_block']},{info['schedule']},{info['xcd_remap']}"
     traffic_b = measured_traffic(args.workload, args.storage, launch_s)
@@ -476,10 +536,13 @@ def main():
                      "traffic": (round(traffic_b / (ms_step * 1e-3) / 1e9, 1)
                                  if traffic_b is not None else None)},
         "traffic_bytes_per_launch": traffic_b,
+        # timed steps replayed from the captured 32- and 4-step graphs vs launched one by one
+        "timed_launch": timed_launch,
     }
     out.update(extras)
     if not args.no_extras:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, all_cores=True)
+        out["cpu_baseline_1core"] = cpu_baseline(args.cpu_seconds, all_cores=False)
     print(json.dumps(out), flush=True)
 
 

@@ -67,6 +67,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OR_MAXQ 9
 #define OR_MAXDEG 4
@@ -363,6 +366,18 @@ int or_set_source_terms(Oracle* o, int n, const double* g, const int* pow, const
 void or_set_source(Oracle* o, const double* g, double gamma) {
   int zero = 0;
   or_set_source_terms(o, g ? 1 : 0, g, &zero, &gamma);
+}
+
+/* Threads of the OpenMP build: n > 0 sets them; returns the number a step
+ * uses (1 in the serial build). */
+int or_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
 }
 
 /* constants: lambda, dt, h, a1, b1, a2, b2, a3, b3, cs2 */

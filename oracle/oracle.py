@@ -67,6 +67,8 @@ def _lib(openmp: bool = False):
         lib.or_set_source.argtypes = [C.c_void_p, _d, C.c_double]
         lib.or_set_source_terms.argtypes = [C.c_void_p, C.c_int, _d, C.POINTER(C.c_int), _d]
         lib.or_constants.argtypes = [C.c_void_p, _d]
+        lib.or_threads.restype = C.c_int
+        lib.or_threads.argtypes = [C.c_int]
         lib.or_geometry.argtypes = [C.c_void_p, _d, _d, _d, _d]
         lib.or_feq.argtypes = [C.c_void_p, C.c_double, _d]
         lib.or_set_phi.argtypes = [C.c_void_p, _d]
@@ -86,6 +88,11 @@ def _lib(openmp: bool = False):
         lib.or_mass.argtypes = [C.c_void_p]
         _LIBS[openmp] = lib
     return _LIBS[openmp]
+
+
+def threads(n: int = 0, openmp: bool = True) -> int:
+    """Threads of the oracle's OpenMP build (n > 0 sets them); the serial build uses 1."""
+    return int(_lib(openmp).or_threads(int(n)))
 
 
 def _p(a):
