@@ -185,8 +185,8 @@ int dugks_set_D(dugks_ctx* ctx, int deg, const double* dxx, const double* dxy, c
  * between the two cell centres (as eq. 2.20), at t_n + h (where fbar of eq.
  * 2.27 lives); a ghost cell takes the G of the cell whose distribution it
  * copies.  Set the source before dugks_set_phi: the initial f~ is
- * E(phi) - dt (F_i + R_i) / 2.  Steps with a source are launched one by one
- * (no graph replay).  Same as dugks_set_source_terms with one term of power 0.
+ * E(phi) - dt (F_i + R_i) / 2.  Same as dugks_set_source_terms with one term
+ * of power 0.
  * Errors: E_UNSUPPORTED (16-bit storage or the plain kernel), E_ARG (gamma
  * not finite), E_HIP. */
 int dugks_set_source(dugks_ctx* ctx, const double* g_dev, double gamma);
@@ -230,10 +230,12 @@ int dugks_set_f(dugks_ctx* ctx, const double* f, int on_device);
 /* Advance nsteps >= 0 steps, asynchronously on the bound stream.  Runs of
  * four or more steps that start at a step divisible by 4 are replayed from
  * captured hipGraphs of 32 and 4 steps (captured on first use on a stream of
- * the library's own, launched on the bound stream); the rest, and every step
- * with Dirichlet data or a source (their kernels read the step's time), are
- * launched one by one.  dugks_info counts both kinds.  Errors: E_STATE (not
- * initialised, Dirichlet data exhausted), E_HIP. */
+ * the library's own, launched on the bound stream after a one-thread kernel
+ * that writes the run's first step index to the workspace, from which the
+ * captured kernels take the time of their Dirichlet data and sources); the
+ * rest, and every step of the plain kernel, are launched one by one.
+ * dugks_info counts both kinds.  Errors: E_STATE (not initialised, Dirichlet
+ * data exhausted), E_HIP. */
 int dugks_step(dugks_ctx* ctx, int nsteps);
 
 /* phi = sum_i f~_i (Sec. 2) accumulated in binary64 (with a source the root

@@ -249,7 +249,7 @@ struct Engine {
   size_t ws_bytes = 0;
   hipStream_t stream = nullptr;
   hipStream_t cap_stream = nullptr;
-  size_t off_table = 0, off_items = 0, off_partial = 0, off_redout = 0;
+  size_t off_table = 0, off_items = 0, off_partial = 0, off_redout = 0, off_stepbase = 0;
   size_t total_bytes = 0;
   std::vector<InstDev> host_table;
   std::vector<WorkItem> items;
@@ -276,12 +276,13 @@ struct Engine {
       if (in.src_n > 0) return true;
     return false;
   }
-  // source kind of a launch: 0 none, 1 all independent of phi, kSrcPow otherwise
+  // source kind of a launch: 0 none, 1 every source one term of power 0 (the
+  // kernel holds one G a row), kSrcPow otherwise (several terms or powers of phi)
   int source_kind() const {
     int kind = 0;
     for (auto& in : inst) {
       if (in.src_n == 0) continue;
-      kind = std::max(kind, in.src_implicit() ? kSrcPow : 1);
+      kind = std::max(kind, (in.src_n == 1 && in.src_pow[0] == 0) ? 1 : kSrcPow);
     }
     return kind;
   }
@@ -316,11 +317,6 @@ struct Engine {
   }
   // 8-wave blocks need the step kernels compiled for two waves per SIMD
   bool wide_blocks_ok() const { return storage != DUGKS_F64 && !any_source(); }
-  bool any_dirichlet() const {
-    for (auto& in : inst)
-      if (in.bcx == DUGKS_BC_DIRICHLET || in.bcy == DUGKS_BC_DIRICHLET) return true;
-    return false;
-  }
   int fail(int rc, const std::string& m) { err = m; return rc; }
   int hipfail(hipError_t e, const char* what) {
     err = std::string(what) + ": " + hipGetErrorString(e);
@@ -336,6 +332,7 @@ struct Engine {
     off += align256(sizeof(WorkItem) * max_items_bound());
     off_partial = off; off += align256(sizeof(double) * 8 * reduce_partials());
     off_redout = off; off += align256(sizeof(double) * 8);
+    off_stepbase = off; off += align256(sizeof(long long));
     for (auto& in : inst) {
       in.buf_bytes = in.buffer_bytes(storage);
       in.off_buf[0] = off; off += align256(in.buf_bytes);
@@ -549,9 +546,11 @@ struct Engine {
     return true;
   }
 
-  // Enqueue one step with input index n on stream s.
-  int enqueue_step(long long n, hipStream_t s, bool measure) {
+  // Enqueue one step with input index n on stream s (captured: index n after
+  // the base written before each replay).
+  int enqueue_step(long long n, hipStream_t s, bool measure, bool captured = false) {
     StepArgs a = step_args(n);
+    if (captured) a.step_base = (const long long*)(ws + off_stepbase);
     int rc;
     if (plain) {
       rc = launch_step_plain(a, inst[0].nx, inst[0].ny, s);
@@ -579,7 +578,7 @@ struct Engine {
     hipError_t e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeRelaxed);
     if (e != hipSuccess) return hipfail(e, "begin capture");
     int rc = DUGKS_OK;
-    for (int k = 0; k < kGraphSteps[w] && rc == DUGKS_OK; ++k) rc = enqueue_step(k, cap_stream, false);
+    for (int k = 0; k < kGraphSteps[w] && rc == DUGKS_OK; ++k) rc = enqueue_step(k, cap_stream, false, true);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(cap_stream, &g);
     if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
@@ -596,9 +595,9 @@ struct Engine {
     if (!all_ready()) return state_error();
     if (!rings_cover(nsteps)) return fail(DUGKS_E_STATE, "Dirichlet data does not cover the requested steps");
     int remaining = nsteps;
-    // captured launches keep their step argument: steps whose kernels read the
-    // step's time (Dirichlet rings, sources) launch one by one
-    const bool graphable = use_graph && !plain && !any_dirichlet() && !any_source();
+    // captured launches read their step index (the time of Dirichlet data and
+    // sources) as an offset from a base written before each replay
+    const bool graphable = use_graph && !plain;
     while (remaining > 0) {
       if (need_measure) {
         int rc = enqueue_step(step, stream, true);
@@ -611,6 +610,8 @@ struct Engine {
           int rc = build_graph(w);
           if (rc) return rc;
         }
+        if (launch_set_i64((long long*)(ws + off_stepbase), step, stream))
+          return fail(DUGKS_E_HIP, "step base launch failed");
         hipError_t e = hipGraphLaunch(graph_exec[w], stream);
         if (e != hipSuccess) return hipfail(e, "graph launch");
         step += kGraphSteps[w];

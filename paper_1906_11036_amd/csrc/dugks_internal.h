@@ -101,8 +101,11 @@ struct StepArgs {
   int parity;               // index of the buffer read by this step
   long long step;           // step index of the input state
   int q, storage, ncoef;    // template selectors, uniform over the launch
-  int src;                  // 0: no source; 1: sources independent of phi; 4: some depend on phi
+  int src;                  // 0: no source; 1: one phi-free term each; kSrcPow: otherwise
   int persistent_blocks;    // blocks of the persistent schedule
+  // when set, the step index is step + *step_base (captured graphs: step is the
+  // offset within the graph, the base is written before each replay)
+  const long long* step_base = nullptr;
 };
 
 int launch_step_fused(const StepArgs& a, const Launch& l, void* stream, int measure);
@@ -132,6 +135,7 @@ int reduce_partials();
 int launch_norms_noalloc(const InstDev* d, const InstDev& h, const double* ref, int parity,
                          long long step, const double* widths, double* out_dev, void* stream);
 int launch_fill_u32(unsigned* p, unsigned v, long long n, void* stream);
+int launch_set_i64(long long* p, long long v, void* stream);
 
 // Power-of-two scale of the 16-bit formats for a maximum |f~ - E| of m.
 float neq_scale_host(float m);

@@ -541,9 +541,11 @@ __device__ __forceinline__ int xcd_logical(int b, int nblocks) {
 // ---------------------------------------------------------- fused step
 // GH: the item touches a wall (ghost rules needed); items that do not use a
 // branch-free row computation.
-// NF: 0 without a source; 1 when the launch carries sources independent of
-// phi; kSrcPow when some source is a polynomial in phi (an instance without a
-// source has no terms and gives the result of the source-free step).
+// NF: 0 without a source; 1 when every source of the launch is one term
+// independent of phi (one G a row); kSrcPow otherwise (up to kMaxSrcTerms
+// terms, F a polynomial in phi).  An instance without a source has no terms
+// and gives the result of the source-free step; one with a single phi-free
+// term gives the same result in either kind of launch.
 template <int Q, int ST, int NC, bool GH, int NF>
 __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const WorkItem it,
                                           int parity, long long step, int lane, bool measure) {
@@ -551,7 +553,7 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
   using C = Coef<T>;
   constexpr bool SRC = NF > 0;
   constexpr int NFA = NF > 0 ? NF : 1;   // array extents
-  constexpr int NT = SRC ? kMaxSrcTerms : 1;
+  constexpr int NT = NF > 1 ? kMaxSrcTerms : 1;
   constexpr int PF = Stor<ST>::neq ? DUGKS_PREFETCH_NEQ : DUGKS_PREFETCH;
   static_assert(PF == 1 || PF == 2, "one or two rows ahead");
   static_assert(!SRC || PF == 1, "source rows follow the one-row prefetch");
@@ -843,7 +845,11 @@ __global__ __launch_bounds__((step_max_threads<ST, NF>())) __attribute__((amdgpu
 void k_step(const InstDev* __restrict__ insts,
                                               const WorkItem* __restrict__ items, int nitems,
                                               int parity, long long step, int xcd_remap,
-                                              int persistent, int measure) {
+                                              int persistent, int measure,
+                                              const long long* __restrict__ step_base) {
+  // a captured launch takes its step index as an offset from a base in device
+  // memory, set before each replay
+  if (step_base != nullptr) step += step_base[0];
   const int wpb = blockDim.x >> 6;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -1241,6 +1247,10 @@ static int scratch_ptr(double** out) {
   return 0;
 }
 
+__global__ void k_set_i64(long long* p, long long v) {
+  if (threadIdx.x == 0) *p = v;
+}
+
 __global__ void k_fill_u32(unsigned* p, unsigned v, long long n) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -1263,7 +1273,7 @@ static int launch_step_q_st(const StepArgs& a, const Launch& l, void* stream, in
   dim3 grid(blocks), block(64 * wpb);
 #define DUGKS_STEP_LAUNCH(NC_, NF_)                                                          \
   hipLaunchKernelGGL((k_step<Q, ST, NC_, NF_>), grid, block, 0, S(stream), a.insts, a.items, \
-                     a.nitems, a.parity, a.step, l.xcd_remap, persistent, measure)
+                     a.nitems, a.parity, a.step, l.xcd_remap, persistent, measure, a.step_base)
 #define DUGKS_STEP_NC(NF_)                                \
   switch (a.ncoef) {                                      \
     case 2: DUGKS_STEP_LAUNCH(2, NF_); break;             \
@@ -1427,6 +1437,11 @@ int launch_norms_noalloc(const InstDev* d, const InstDev& h, const double* ref, 
                     : reduce_q<5>(d, h, ref, parity, step, widths, partial, stream);
   if (rc) return rc;
   hipLaunchKernelGGL(k_norms_final, dim3(1), dim3(64), 0, S(stream), partial, kRedBlocks, out_dev);
+  DUGKS_CHECK_LAUNCH();
+}
+
+int launch_set_i64(long long* p, long long v, void* stream) {
+  hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(64), 0, S(stream), p, v);
   DUGKS_CHECK_LAUNCH();
 }
 

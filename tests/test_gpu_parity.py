@@ -277,3 +277,29 @@ def test_error_norms_of_a_nonfinite_state_are_refused():
                                                    C.c_void_p(out.data_ptr())) == 0
     torch.cuda.synchronize()
     assert np.isnan(out.cpu().numpy()).all()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_graph_replay_with_dirichlet_data_and_sources(storage):
+    """Captured graphs take their step index from a base written before each
+    replay, so runs with Dirichlet data (the ring of each step) and with
+    time-dependent sources replay graphs too: bit for bit the eager steps."""
+    p = W.burgers_problem(100, steps=80)
+    q = W.random_problem(611, 90, 70, bdeg=2, ddeg=2)
+    q.cfl = 0.4   # as drawn (0.79) this problem is unstable within 150 steps, oracle included
+    q.src_terms = W.random_source_terms(612, q, nterms=4, amp=1.0)
+    for prob in (p, q):
+        a = dg.Solver(prob, storage=storage)
+        e = dg.Solver(prob, storage=storage)
+        for s in (a, e):
+            s.set_phi(prob.phi0)
+            if prob.rings(1) is not None:
+                s.set_dirichlet(prob.rings(80))
+        for n in (36, 4, 3, 9, 28):
+            a.step(n)
+            for _ in range(n):
+                e.step(1)
+        assert a.info()["graph_steps"] >= 36 + 4 + 4 + 28
+        fa = a.get_f()
+        assert np.isfinite(fa).all()
+        assert np.array_equal(fa, e.get_f()), prob.name
