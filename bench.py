@@ -39,6 +39,19 @@ def bytes_per_update(storage, q):
     return 2 * per
 
 
+def source_terms(p):
+    """Number of source terms G_j the step reads for problem p (binary64, 8 B a cell each)."""
+    if getattr(p, "src_terms", None):
+        return len(p.src_terms)
+    return 1 if getattr(p, "src_g", None) is not None else 0
+
+
+def algorithmic_bytes(problems, storage):
+    """Algorithmic HBM bytes of one step over all problems: the state read and
+    written once, plus each source term's G read once."""
+    return sum((bytes_per_update(storage, p.q) + 8 * source_terms(p)) * p.cells for p in problems)
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -477,9 +490,9 @@ def main():
     info = b.info(0)
     ms_step = ms / args.steps
     mlups = cells * args.steps / (ms * 1e-3) / 1e6
-    # per launch (one launch per step); a source adds its G read (8 B a cell)
-    src_cells = sum(p.cells for p in problems if getattr(p, "src_g", None) is not None)
-    alg_bytes = sum(bytes_per_update(storage, p.q) * p.cells for p in problems) + 8 * src_cells
+    # per launch (one launch per step); a source adds its G reads (8 B a cell and term)
+    src_cells = sum(p.cells * source_terms(p) for p in problems)
+    alg_bytes = algorithmic_bytes(problems, storage)
     achieved = alg_bytes / (ms_step * 1e-3) / 1e9
     log(f"{args.storage}: {ms_step:.4f} ms/step, {mlups:.0f} MLUPS, {achieved:.0f} GB/s algorithmic "
         f"(launch rows/wave={info['rows_per_wave']} waves/block={info['waves_per_block']} "
