@@ -87,7 +87,8 @@ extern "C" {
 #define DUGKS_F16NEQ 2  /* phi in binary32 + g_i = s (f~_i - E_i(phi)) in binary16 for
                            i >= 1 (g_0 = -sum g_i); s a power of two chosen each step
                            from the previous step's max |f~ - E|; binary32 arithmetic */
-#define DUGKS_BF16NEQ 3 /* as DUGKS_F16NEQ with bfloat16 */
+#define DUGKS_BF16NEQ 3 /* as DUGKS_F16NEQ with bfloat16 and s = 1 (bfloat16 has the exponent
+                           range of binary32) */
 
 /* boundary kinds (per side: west, east, south, north) */
 #define DUGKS_BC_PERIODIC 0

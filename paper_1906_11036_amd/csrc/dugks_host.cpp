@@ -395,6 +395,8 @@ struct Engine {
       d.opra = 1.0 + d.ra;
       d.raf = (float)d.ra; d.rbf = (float)d.rb; d.b1f = (float)d.b1; d.inv_b1f = (float)d.inv_b1;
       d.kgf = (float)d.kg; d.a2f = (float)d.a2; d.oepraf = (float)d.opra; d.a1f = (float)in.a1;
+      d.ra_of = (float)(d.ra / d.opra); d.b1_of = (float)(d.b1 * d.opra);
+      d.rb_of = (float)(d.rb * d.opra); d.inv_b1_of = (float)(1.0 / (d.b1 * d.opra));
       for (int i = 0; i < in.q; ++i)
         for (int m = 0; m < kMaxCoef; ++m) {
           d.e[i][m] = in.e[i][m];
@@ -1072,7 +1074,7 @@ int dugks_get_diag(dugks_ctx* ctx, dugks_diag* out) {
   if (r[5] > 0) out->flags |= DUGKS_FLAG_NONFINITE;
   if (ctx->neq()) {
     out->max_neq = slots[(ctx->step + 2) & 3];
-    out->scale = dugks::neq_scale_host(slots[(ctx->step + 2) & 3]);
+    out->scale = dugks::neq_scale_host(ctx->storage, slots[(ctx->step + 2) & 3]);
   } else {
     out->scale = 1.0;
   }

@@ -62,6 +62,8 @@ struct alignas(64) InstDev {
   int storage;
   double ra, rb, b1, inv_b1, kg, a2, opra;     // a1/b1, a3 b1/b3, b1, 1/b1, 4/3 b1, a2, 1 + a1/b1
   float raf, rbf, b1f, inv_b1f, kgf, a2f, oepraf, a1f;
+  // 16-bit storage holds g / (1 + ra) in registers: ra/(1+ra), b1 (1+ra), rb (1+ra), 1/(b1 (1+ra))
+  float ra_of, b1_of, rb_of, inv_b1_of;
   // E_i(phi) = sum_k e[i][k] phi^k  (eq. 2.3 with C = int_0^phi B'B'^T)
   double e[kMaxQ][kMaxCoef];
   float ef[kMaxQ][kMaxCoef];
@@ -138,6 +140,6 @@ int launch_fill_u32(unsigned* p, unsigned v, long long n, void* stream);
 int launch_set_i64(long long* p, long long v, void* stream);
 
 // Power-of-two scale of the 16-bit formats for a maximum |f~ - E| of m.
-float neq_scale_host(float m);
+float neq_scale_host(int storage, float m);
 
 }  // namespace dugks

@@ -104,6 +104,14 @@ __host__ __device__ inline float neq_scale(float m) {
   return ldexpf(1.0f, k);
 }
 
+// Scale of a 16-bit format.  bfloat16 has the exponent range of binary32, so a
+// power-of-two scale changes none of its rounded values outside the subnormal
+// range: it stores f~ - E unscaled (s = 1).  binary16 stores s (f~ - E).
+template <int ST> __host__ __device__ inline float neq_scale_for(float m) {
+  if constexpr (ST == DUGKS_BF16NEQ) return 1.0f;
+  else return neq_scale(m);
+}
+
 // ------------------------------------------------------------ DPP helpers
 // wave_shr:1 -> lane l receives lane l-1; wave_shl:1 -> lane l receives lane l+1.
 // Lanes without a source (0 for shr, 63 for shl) read 0 (bound_ctrl); their
@@ -189,6 +197,13 @@ template <typename T, int Q, int NC> struct Eq {
     b1 = C::b1(I);
     inv_b1 = C::inv_b1(I);
     kg = C::kg(I);
+  }
+  // The 16-bit formats hold g / (1 + ra) (one FMA a direction at the decode):
+  // the faces and the ghost rule then take b1, rb and 1/b1 times 1 + ra.
+  __device__ __forceinline__ void scale_g_16() {
+    b1 = I->b1_of;
+    rb = I->rb_of;
+    inv_b1 = I->inv_b1_of;
   }
   __device__ __forceinline__ T E(int k, T x) const {
     if constexpr (kHeld) return horner<NC>(c[k], x);
@@ -418,12 +433,13 @@ __device__ __forceinline__ void cell_g(const InstDev* __restrict__ I,
       sum += gs[k];
     }
     gs[0] = -sum;
-    // f~ = E + gs / s:  g = (1 + ra) E + ra gs / s,  f~+ = E + a2 gs / s
-    const float ras = I->raf * sc.inv_in, a2s = I->a2f * sc.inv_in, opra = I->oepraf;
+    // f~ = E + gs / s:  g = (1 + ra) E + ra gs / s, held as g / (1 + ra) =
+    // E + (ra / (1 + ra)) gs / s;  f~+ = E + a2 gs / s
+    const float ras = I->ra_of * sc.inv_in, a2s = I->a2f * sc.inv_in;
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
       const float E = eq.E(k, p);
-      g[k] = fma(ras, gs[k], opra * E);
+      g[k] = fma(ras, gs[k], E);
       if (want_ftp) ftp[k] = fma(a2s, gs[k], E);
     }
     phi_out = p;
@@ -568,8 +584,9 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
 
   Scales sc{1.0f, 1.0f};
   if constexpr (Stor<ST>::neq) {
-    sc.inv_in = 1.0f / neq_scale(I->slots[(step + 2) & 3]);
-    sc.out = neq_scale(I->slots[(step + 3) & 3]);
+    sc.inv_in = 1.0f / neq_scale_for<ST>(I->slots[(step + 2) & 3]);
+    sc.out = neq_scale_for<ST>(I->slots[(step + 3) & 3]);
+    eq.scale_g_16();
   }
 
   const int c = it.x0 - 1 + lane;
@@ -769,9 +786,9 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
           }
         }
       } else {
-        double ps = 0.0;                  // phi(t + dt) = sum_i f~_i in binary64,
+        double ps = (double)o[0];         // phi(t + dt) = sum_i f~_i in binary64,
 #pragma unroll
-        for (int k = 0; k < Q; ++k) ps += (double)o[k];
+        for (int k = 1; k < Q; ++k) ps += (double)o[k];
         const float pf = (float)ps;       // rounded once to the stored binary32
         bad |= !__builtin_isfinite(pf);
         float m1 = 0.0f;                  // max |f~_i - E_i| over the stored i >= 1
@@ -1056,7 +1073,7 @@ __global__ void k_set_f(const InstDev* __restrict__ I, const double* __restrict_
     }
   } else {
     float m = 0.0f;
-    if (in) encode_neq<Q, ST>(I, buf, off, v, pass == 1 ? neq_scale(I->slots[slot]) : 0.0f, &m);
+    if (in) encode_neq<Q, ST>(I, buf, off, v, pass == 1 ? neq_scale_for<ST>(I->slots[slot]) : 0.0f, &m);
     if (pass == 0) {
 #pragma unroll
       for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
@@ -1124,7 +1141,7 @@ __global__ void k_get_f(const InstDev* __restrict__ I, double* __restrict__ out,
   const long long off = (long long)j * I->pitch + i;
   const long long N = (long long)I->nx * I->ny;
   float inv_s = 1.0f;
-  if constexpr (Stor<ST>::neq) inv_s = 1.0f / neq_scale(I->slots[(step + 2) & 3]);
+  if constexpr (Stor<ST>::neq) inv_s = 1.0f / neq_scale_for<ST>(I->slots[(step + 2) & 3]);
   double f[Q];
   decode<Q, ST>(I, (const char*)I->buf[parity], off, inv_s, f);
 #pragma unroll
@@ -1454,5 +1471,7 @@ int launch_fill_u32(unsigned* p, unsigned v, long long n, void* stream) {
 }  // namespace dugks
 
 namespace dugks {
-float neq_scale_host(float m) { return neq_scale(m); }
+float neq_scale_host(int storage, float m) {
+  return storage == DUGKS_BF16NEQ ? neq_scale_for<DUGKS_BF16NEQ>(m) : neq_scale_for<DUGKS_F16NEQ>(m);
+}
 }  // namespace dugks
