@@ -1122,7 +1122,7 @@ int dugks_checkpoint(dugks_ctx* ctx, void* host_buf, size_t* len) {
   if (!ctx->bound() || !ctx->all_ready()) return ctx->fail(DUGKS_E_STATE, "no state");
   dugks::CkptHeader hd;
   memset(&hd, 0, sizeof(hd));
-  memcpy(hd.magic, "DUGKSCK1", 8);
+  memcpy(hd.magic, "DUGKSCK2", 8);
   hd.abi = DUGKS_ABI_VERSION;
   hd.header_bytes = sizeof(hd);
   hd.nx = in.nx; hd.ny = in.ny; hd.q = in.q; hd.storage = ctx->storage;
@@ -1151,7 +1151,7 @@ int dugks_restore(dugks_ctx* ctx, const void* host_buf, size_t len) {
   dugks::CkptHeader hd;
   memcpy(&hd, host_buf, sizeof(hd));
   const dugks::Instance& in = ctx->inst[0];
-  if (memcmp(hd.magic, "DUGKSCK1", 8) != 0) return ctx->fail(DUGKS_E_FORMAT, "bad magic");
+  if (memcmp(hd.magic, "DUGKSCK2", 8) != 0) return ctx->fail(DUGKS_E_FORMAT, "bad magic");
   if (hd.abi != DUGKS_ABI_VERSION || hd.header_bytes != sizeof(hd))
     return ctx->fail(DUGKS_E_FORMAT, "ABI version or header size mismatch");
   if (hd.nx != in.nx || hd.ny != in.ny || hd.q != in.q || hd.storage != ctx->storage)

@@ -90,6 +90,25 @@ template <int ST> __device__ __forceinline__ uint16_t f32_to_g(float x) {
   if constexpr (ST == DUGKS_F16NEQ) return f32_to_h16(x);
   else return f32_to_bf16(x);
 }
+// 16-bit layout: after the phi plane, (Q - 1) / 2 planes of 32-bit words; the
+// word of pair p holds direction 2p + 1 in its low half and 2p + 2 in its high
+// half, so one load or store moves two directions.
+template <int ST> __device__ __forceinline__ float g_lo(unsigned u) {
+  return g_to_f32<ST>((uint16_t)u);
+}
+template <int ST> __device__ __forceinline__ float g_hi(unsigned u) {
+  if constexpr (ST == DUGKS_F16NEQ) return g_to_f32<ST>((uint16_t)(u >> 16));
+  else return __uint_as_float(u & 0xffff0000u);
+}
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef _Float16 h16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+// x and y rounded to nearest even into one word (x low, y high)
+template <int ST> __device__ __forceinline__ unsigned f32x2_to_g(float x, float y) {
+  const f32x2_t v = {x, y};
+  if constexpr (ST == DUGKS_F16NEQ) return __builtin_bit_cast(unsigned, __builtin_convertvector(v, h16x2_t));
+  else return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2_t));
+}
 template <int ST> __device__ __forceinline__ float g_limit() {
   return ST == DUGKS_F16NEQ ? 65504.0f : 3.0e38f;
 }
@@ -321,8 +340,8 @@ template <typename T> __device__ __forceinline__ CPtr<T> as_constant(const T* p)
 template <int Q, int ST> struct Raw;
 template <int Q> struct Raw<Q, DUGKS_F64> { double v[Q]; };
 template <int Q> struct Raw<Q, DUGKS_F32> { float v[Q]; };
-template <int Q> struct Raw<Q, DUGKS_F16NEQ> { float phi; uint16_t g[Q - 1]; };
-template <int Q> struct Raw<Q, DUGKS_BF16NEQ> { float phi; uint16_t g[Q - 1]; };
+template <int Q> struct Raw<Q, DUGKS_F16NEQ> { float phi; unsigned g2[(Q - 1) / 2]; };
+template <int Q> struct Raw<Q, DUGKS_BF16NEQ> { float phi; unsigned g2[(Q - 1) / 2]; };
 
 typedef unsigned v2u __attribute__((ext_vector_type(2)));
 
@@ -346,10 +365,11 @@ __device__ __forceinline__ void load_raw_buf(Raw<Q, ST>& r, __amdgpu_buffer_rsrc
     for (int k = 0; k < Q; ++k)
       r.v[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(R, idx * 4u, (unsigned)k * plane * 4u, 0));
   } else {
+    static_assert((Q - 1) % 2 == 0, "directions 1..Q-1 in pairs");
     r.phi = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(R, idx * 4u, 0u, 0));
 #pragma unroll
-    for (int k = 0; k < Q - 1; ++k)
-      r.g[k] = __builtin_amdgcn_raw_buffer_load_b16(R, idx * 2u, plane * 4u + (unsigned)k * plane * 2u, 0);
+    for (int p = 0; p < (Q - 1) / 2; ++p)
+      r.g2[p] = __builtin_amdgcn_raw_buffer_load_b32(R, idx * 4u, (unsigned)(p + 1) * plane * 4u, 0);
   }
 }
 
@@ -367,9 +387,9 @@ __device__ __forceinline__ void load_raw(Raw<Q, ST>& r, const char* buf, long lo
     for (int k = 0; k < Q; ++k) r.v[k] = b[k * plane + off];
   } else {
     r.phi = ((const float*)buf)[off];
-    const uint16_t* g = (const uint16_t*)(buf + 4 * plane);
+    const unsigned* g = (const unsigned*)buf + plane;
 #pragma unroll
-    for (int k = 0; k < Q - 1; ++k) r.g[k] = g[k * plane + off];
+    for (int p = 0; p < (Q - 1) / 2; ++p) r.g2[p] = g[p * plane + off];
   }
 }
 
@@ -428,10 +448,12 @@ __device__ __forceinline__ void cell_g(const InstDev* __restrict__ I,
     float gs[Q];
     float sum = 0.0f;
 #pragma unroll
-    for (int k = 1; k < Q; ++k) {
-      gs[k] = g_to_f32<ST>(r.g[k - 1]);
-      sum += gs[k];
+    for (int p = 0; p < (Q - 1) / 2; ++p) {
+      gs[2 * p + 1] = g_lo<ST>(r.g2[p]);
+      gs[2 * p + 2] = g_hi<ST>(r.g2[p]);
     }
+#pragma unroll
+    for (int k = 1; k < Q; ++k) sum += gs[k];
     gs[0] = -sum;
     // f~ = E + gs / s:  g = (1 + ra) E + ra gs / s, held as g / (1 + ra) =
     // E + (ra / (1 + ra)) gs / s;  f~+ = E + a2 gs / s
@@ -792,7 +814,7 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
         const float pf = (float)ps;       // rounded once to the stored binary32
         bad |= !__builtin_isfinite(pf);
         float m1 = 0.0f;                  // max |f~_i - E_i| over the stored i >= 1
-        uint16_t gq[Q - 1];
+        float sq[Q];
 #pragma unroll
         for (int k = 1; k < Q; ++k) {
           const float d = o[k] - eq.E(k, pf);
@@ -801,15 +823,16 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
           // binary16: saturate (an overflow is flagged below); bfloat16 has
           // binary32's range
           if constexpr (ST == DUGKS_F16NEQ) s = __builtin_amdgcn_fmed3f(s, -g_limit<ST>(), g_limit<ST>());
-          gq[k - 1] = f32_to_g<ST>(s);
+          sq[k] = s;
         }
         ovf |= !measure && m1 * sc.out > g_limit<ST>();
         mx = fmaxf(mx, fmaxf(m1, fabsf(o[0] - eq.E(0, pf))));
         if (!measure) {
           __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, pf), Rout, idx * 4u, 0u, 0);
 #pragma unroll
-          for (int k = 0; k < Q - 1; ++k)
-            __builtin_amdgcn_raw_buffer_store_b16(gq[k], Rout, idx * 2u, plane * 4u + (unsigned)k * plane * 2u, 0);
+          for (int p = 0; p < (Q - 1) / 2; ++p)
+            __builtin_amdgcn_raw_buffer_store_b32(f32x2_to_g<ST>(sq[2 * p + 1], sq[2 * p + 2]), Rout,
+                                                  idx * 4u, (unsigned)(p + 1) * plane * 4u, 0);
         }
       }
     }
@@ -1001,16 +1024,21 @@ __device__ __forceinline__ void encode_neq(const InstDev* __restrict__ I, char* 
   const float pf = (float)ps;
   const int nc = I->ncoef;
   float m = 0.0f;
-  uint16_t* gb = (uint16_t*)(buf + 4 * I->plane);
+  float sq[Q];
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
     float E = I->ef[k][nc - 1];
     for (int mm = nc - 2; mm >= 0; --mm) E = fmaf(E, pf, I->ef[k][mm]);
     const float d = (float)(f[k] - (double)E);
     m = fmaxf(m, fabsf(d));
-    if (k > 0 && s > 0.0f) gb[(k - 1) * I->plane + off] = f32_to_g<ST>(d * s);
+    sq[k] = d * s;
   }
-  if (s > 0.0f) ((float*)buf)[off] = pf;
+  if (s > 0.0f) {
+    unsigned* gb = (unsigned*)buf + I->plane;
+#pragma unroll
+    for (int p = 0; p < (Q - 1) / 2; ++p) gb[p * I->plane + off] = f32x2_to_g<ST>(sq[2 * p + 1], sq[2 * p + 2]);
+    ((float*)buf)[off] = pf;
+  }
   *maxdev = m;
 }
 
@@ -1045,9 +1073,9 @@ __global__ void k_init_eq(const InstDev* __restrict__ I, const double* __restric
   } else {
     // f~ = E(phi) exactly for the stored phi: g = 0
     ((float*)buf)[off] = (float)p;
-    uint16_t* gb = (uint16_t*)(buf + 4 * I->plane);
+    unsigned* gb = (unsigned*)buf + I->plane;
 #pragma unroll
-    for (int k = 0; k < Q - 1; ++k) gb[k * I->plane + off] = 0;
+    for (int p2 = 0; p2 < (Q - 1) / 2; ++p2) gb[p2 * I->plane + off] = 0u;
   }
 }
 
@@ -1093,15 +1121,18 @@ __device__ __forceinline__ void decode(const InstDev* __restrict__ I, const char
     for (int k = 0; k < Q; ++k) f[k] = (double)((const T*)buf)[k * I->plane + off];
   } else {
     const float p = ((const float*)buf)[off];
-    const uint16_t* gb = (const uint16_t*)(buf + 4 * I->plane);
+    const unsigned* gb = (const unsigned*)buf + I->plane;
     const int nc = I->ncoef;
     float gs = 0.0f;
     float g[Q];
 #pragma unroll
-    for (int k = 1; k < Q; ++k) {
-      g[k] = g_to_f32<ST>(gb[(k - 1) * I->plane + off]);
-      gs += g[k];
+    for (int p = 0; p < (Q - 1) / 2; ++p) {
+      const unsigned u = gb[p * I->plane + off];
+      g[2 * p + 1] = g_lo<ST>(u);
+      g[2 * p + 2] = g_hi<ST>(u);
     }
+#pragma unroll
+    for (int k = 1; k < Q; ++k) gs += g[k];
     g[0] = -gs;
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
