@@ -887,10 +887,18 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
 #ifndef DUGKS_WAVES_PER_EU_F64
 #define DUGKS_WAVES_PER_EU_F64 1
 #endif
-// The source path holds more per row (G and its window): one wave per SIMD,
-// the full register file, no spills.
+#ifndef DUGKS_WAVES_PER_EU_NEQ
+#define DUGKS_WAVES_PER_EU_NEQ 3
+#endif
+// The 16-bit step is bound by its instruction count: three waves per SIMD
+// (168 registers, spills outside the row loop only) hide more of its latency
+// than two.  The source path holds more per row (G and its window): one wave
+// per SIMD, the full register file, no spills.
 template <int ST, int NF> struct Occupancy {
-  static constexpr int value = NF > 0 ? 1 : (ST == DUGKS_F64 ? DUGKS_WAVES_PER_EU_F64 : DUGKS_WAVES_PER_EU_F32);
+  static constexpr int value = NF > 0 ? 1
+                               : ST == DUGKS_F64 ? DUGKS_WAVES_PER_EU_F64
+                               : Stor<ST>::neq   ? DUGKS_WAVES_PER_EU_NEQ
+                                                 : DUGKS_WAVES_PER_EU_F32;
 };
 // Threads per block: at two waves per SIMD a block may hold 8 waves (fewer,
 // larger blocks to dispatch); at one wave per SIMD at most 4.
