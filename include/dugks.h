@@ -86,7 +86,8 @@ extern "C" {
 #define DUGKS_F32 1     /* f~ in binary32, binary32 arithmetic, binary64 moment sums */
 #define DUGKS_F16NEQ 2  /* phi in binary32 + g_i = s (f~_i - E_i(phi)) in binary16 for
                            i >= 1 (g_0 = -sum g_i); s a power of two chosen each step
-                           from the previous step's max |f~ - E|; binary32 arithmetic */
+                           from the previous step's max over i >= 1 of |f~_i - E_i|;
+                           binary32 arithmetic */
 #define DUGKS_BF16NEQ 3 /* as DUGKS_F16NEQ with bfloat16 and s = 1 (bfloat16 has the exponent
                            range of binary32) */
 
@@ -139,7 +140,8 @@ typedef struct dugks_diag {
   double t;       /* step * dt */
   double dt;
   double mass;    /* sum_j phi_j |V_j| */
-  double max_neq; /* max |f~ - E(phi)| of the last step's output (16-bit storage), else 0 */
+  double max_neq; /* max over i >= 1 of |f~_i - E_i(phi)| of the last step's output (16-bit
+                     storage), else 0 */
   double scale;   /* power-of-two scale of the stored state (16-bit storage), else 1 */
   int flags;      /* DUGKS_FLAG_* */
 } dugks_diag;

@@ -113,7 +113,7 @@ template <int ST> __device__ __forceinline__ float g_limit() {
   return ST == DUGKS_F16NEQ ? 65504.0f : 3.0e38f;
 }
 
-// Power-of-two scale s such that max |f~ - E| * s lies in (2^13, 2^14].
+// Power-of-two scale s such that max_{i >= 1} |f~_i - E_i| * s lies in (2^13, 2^14].
 __host__ __device__ inline float neq_scale(float m) {
   if (!(m > 0.0f) || !(m < 3.0e38f)) return 1.0f;
   int e;
@@ -531,6 +531,35 @@ __device__ __forceinline__ int src_index(int i, int n, int bc) {
   return i < 0 ? 0 : n - 1;
 }
 
+// Pairwise sum of N values.
+template <int N, typename T> __device__ __forceinline__ T tree_sum(const T* v) {
+  if constexpr (N == 1) return v[0];
+  else return tree_sum<N / 2>(v) + tree_sum<N - N / 2>(v + N / 2);
+}
+
+// Number of directions with a velocity component normal to an x-face (NRM 0)
+// or a y-face (NRM 1).
+template <int Q, int NRM> constexpr int normal_count() {
+  int n = 0;
+  for (int k = 0; k < Q; ++k)
+    if ((NRM == 0 ? lat_cx(k) : lat_cy(k)) != 0) ++n;
+  return n;
+}
+
+// Sum of g over the directions without a component normal to an x-face (NRM
+// 0) or a y-face (NRM 1).
+template <int Q, int NRM, typename T> __device__ __forceinline__ T zero_normal_sum(const T* g) {
+  T s = 0;
+  bool first = true;
+#pragma unroll
+  for (int k = 0; k < Q; ++k)
+    if ((NRM == 0 ? lat_cx(k) : lat_cy(k)) == 0) {
+      s = first ? g[k] : s + g[k];
+      first = false;
+    }
+  return s;
+}
+
 // Directions with a velocity component normal to an x-face (NRM 0) or a
 // y-face (NRM 1), as a bit mask.
 template <int Q, int NRM> constexpr unsigned normal_mask() {
@@ -548,23 +577,54 @@ template <int Q, int NRM> constexpr unsigned normal_mask() {
 // With a source, pb_c = the coefficients of F at the face point at t_n + h as
 // a polynomial in phi: phi_b solves phi_b = sum fbar + h F(phi_b) / 2 and F
 // gains lambda F(phi_b) rho(phi_b) (eq. 2.27 solved for f).
-template <int Q, int NC, int NRM, typename T, int NF = 0>
+//
+// ZS (the 16-bit step): directions without a normal component enter only
+// phi_b, and they all take the same a0, so their sum is interpolated from the
+// two cells' sums zL, zR of g over those directions (plus their tangential
+// terms) instead of direction by direction.
+template <int Q, int NC, int NRM, typename T, int NF = 0, bool ZS = false>
 __device__ __forceinline__ void face(const Eq<T, Q, NC>& eq, const T* L, const T* R, const T* ts,
                                      T am, T a0, T ap, T tau, T* out,
-                                     const SrcEq<T, Q, NF>& se = {}, const T* pb_c = nullptr) {
+                                     const SrcEq<T, Q, NF>& se = {}, const T* pb_c = nullptr,
+                                     T zL = 0, T zR = 0) {
   constexpr bool SRC = NF > 0;
+  static_assert(!(SRC && ZS), "interpolated sums without a source only");
   T gb[Q];
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
     const int cn = NRM == 0 ? lat_cx(k) : lat_cy(k);
     const int ct = NRM == 0 ? lat_cy(k) : lat_cx(k);
+    if (ZS && cn == 0) continue;
     const T al = cn > 0 ? ap : (cn < 0 ? am : a0);
     T v = fma(al, R[k] - L[k], L[k]);
     if (ct != 0) v = fma((T)(-ct) * tau, ts[k], v);
     gb[k] = v;
   }
   // phi(x_b, t + h) = sum_i fbar_i = b1 sum_i gbar_i  (+ h F_b / 2)
-  T pb = (T)(dir_sum<Q>(gb) * eq.b1);
+  T pb;
+  if constexpr (ZS) {
+    T tz = 0;   // sum of -c_t ts over the directions without a normal component
+    bool first = true;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      const int cn = NRM == 0 ? lat_cx(k) : lat_cy(k);
+      const int ct = NRM == 0 ? lat_cy(k) : lat_cx(k);
+      if (cn == 0 && ct != 0) {
+        const T t = ct > 0 ? -ts[k] : ts[k];
+        tz = first ? t : tz + t;
+        first = false;
+      }
+    }
+    T v[Q];
+    int n = 0;
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+      if ((NRM == 0 ? lat_cx(k) : lat_cy(k)) != 0) v[n++] = gb[k];
+    v[n++] = fma(tau, tz, fma(a0, zR - zL, zL));
+    pb = tree_sum<normal_count<Q, NRM>() + 1>(v) * eq.b1;
+  } else {
+    pb = (T)(dir_sum<Q>(gb) * eq.b1);
+  }
   T Fb = 0;
   if constexpr (SRC) {
     pb = solve_conserved<NF, T>(pb, se.hh, pb_c, se.implicit);
@@ -610,6 +670,7 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
   constexpr int NFA = NF > 0 ? NF : 1;   // array extents
   constexpr int NT = NF > 1 ? kMaxSrcTerms : 1;
   constexpr int PF = Stor<ST>::neq ? DUGKS_PREFETCH_NEQ : DUGKS_PREFETCH;
+  constexpr bool ZS = Stor<ST>::neq;     // faces interpolate the zero-normal sums
   static_assert(PF == 1 || PF == 2, "one or two rows ahead");
   static_assert(!SRC || PF == 1, "source rows follow the one-row prefetch");
   Eq<T, Q, NC> eq;
@@ -719,6 +780,7 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
   // is a change of register names, not a copy.
   T G[3][Q], LS[3][Q], FT[3][Q], SX[3][Q], FY[3][Q], ts[Q], dy[Q], fW[Q];
   Raw<Q, ST> RW[3];
+  T ZX[3], ZY[3];  // g summed over the directions with c_x = 0 / c_y = 0 (ZS)
   T GR[3][NT];     // source G_j of the row whose raw values sit in RW[.]
   T FC[3][NFA];    // face-time coefficients of F of the row made into G[.]
   T pfb[NFA];      // the same interpolated to a face
@@ -741,11 +803,17 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
   }
   make_row(RW[2], y0 - 1, G[2], FT[2], false, GR[2], FC[2]);
   make_row(RW[0], y0, G[0], FT[0], true, GR[0], FC[0]);
+  if constexpr (ZS) {
+    ZX[2] = zero_normal_sum<Q, 0>(G[2]);
+    ZY[2] = zero_normal_sum<Q, 1>(G[2]);
+    ZX[0] = zero_normal_sum<Q, 0>(G[0]);
+    ZY[0] = zero_normal_sum<Q, 1>(G[0]);
+  }
   if constexpr (PF == 2)  // two rows in flight ahead of the row being consumed
     load_raw_buf<Q, ST>(RW[2], Rin, plane, row_idx(y0 + 2 <= y1 ? y0 + 2 : y1));
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
-    LS[0][k] = shr1(G[0][k]);
+    if (!ZS || lat_cx(k) != 0) LS[0][k] = shr1(G[0][k]);
     if (lat_cx(k) != 0) {
       SX[0][k] = shl1(G[0][k]) - LS[0][k];
       ts[k] = (shl1(G[2][k]) - shr1(G[2][k])) + SX[0][k];
@@ -755,7 +823,10 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
     const CPtr<T> g = rg + (long long)(y0 + 1) * kGeo;
 #pragma unroll
     for (int k = 0; k < NFA; ++k) pfb[k] = fma(g[1], FC[0][k] - FC[2][k], FC[2][k]);
-    face<Q, NC, 1, T, NF>(eq, G[2], G[0], ts, g[0], g[1], g[2], ctau, FY[2], se, pfb);
+    if constexpr (ZS)
+      face<Q, NC, 1, T, 0, true>(eq, G[2], G[0], ts, g[0], g[1], g[2], ctau, FY[2], {}, nullptr, ZY[2], ZY[0]);
+    else
+      face<Q, NC, 1, T, NF>(eq, G[2], G[0], ts, g[0], g[1], g[2], ctau, FY[2], se, pfb);
   }
 
   bool bad = false, ovf = false;
@@ -769,13 +840,17 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
       load_raw_buf<Q, ST>(RW[sm], Rin, plane, row_idx(j + 2 <= y1 ? j + 2 : y1));
     if constexpr (SRC) load_gsrc(j + 2 <= y1 ? j + 2 : y1, GR[sm]);
     make_row(RW[sp], j + 1, G[sp], FT[sp], true, GR[sp], FC[sp]);
+    if constexpr (ZS) {
+      ZX[sp] = zero_normal_sum<Q, 0>(G[sp]);
+      ZY[sp] = zero_normal_sum<Q, 1>(G[sp]);
+    }
     const CPtr<T> gj = rg + (long long)(j + 1) * kGeo;   // row j: its S face and factors
     const CPtr<T> gn = rg + (long long)(j + 2) * kGeo;   // row j+1: S face = N face of row j
     const T rtau = gj[3], rk = gj[4];
     // x-slope numerators of row j+1: g(lane+1) - g(lane-1)
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-      LS[sp][k] = shr1(G[sp][k]);
+      if (!ZS || lat_cx(k) != 0) LS[sp][k] = shr1(G[sp][k]);
       if (lat_cx(k) != 0) {
         SX[sp][k] = shl1(G[sp][k]) - LS[sp][k];
         ts[k] = SX[s0][k] + SX[sp][k];
@@ -783,7 +858,11 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
     }
 #pragma unroll
     for (int k = 0; k < NFA; ++k) pfb[k] = fma(gn[1], FC[sp][k] - FC[s0][k], FC[s0][k]);
-    face<Q, NC, 1, T, NF>(eq, G[s0], G[sp], ts, gn[0], gn[1], gn[2], ctau, FY[s0], se, pfb);
+    if constexpr (ZS)
+      face<Q, NC, 1, T, 0, true>(eq, G[s0], G[sp], ts, gn[0], gn[1], gn[2], ctau, FY[s0], {}, nullptr,
+                                 ZY[s0], ZY[sp]);
+    else
+      face<Q, NC, 1, T, NF>(eq, G[s0], G[sp], ts, gn[0], gn[1], gn[2], ctau, FY[s0], se, pfb);
     // west face of this lane's cell: left state from lane-1; y-slope numerators
 #pragma unroll
     for (int k = 0; k < Q; ++k)
@@ -798,6 +877,9 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
         pfb[k] = fma(ca0, FC[s0][k] - gl, gl);
       }
       face<Q, NC, 0, T, NF>(eq, LS[s0], G[s0], ts, cam, ca0, cap, rtau, fW, se, pfb);
+    } else if constexpr (ZS) {
+      face<Q, NC, 0, T, 0, true>(eq, LS[s0], G[s0], ts, cam, ca0, cap, rtau, fW, {}, nullptr,
+                                 shr1(ZX[s0]), ZX[s0]);
     } else {
       face<Q, NC, 0>(eq, LS[s0], G[s0], ts, cam, ca0, cap, rtau, fW);
     }
@@ -844,7 +926,7 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
           sq[k] = s;
         }
         ovf |= !measure && m1 * sc.out > g_limit<ST>();
-        mx = fmaxf(mx, fmaxf(m1, fabsf(o[0] - eq.E(0, pf))));
+        mx = fmaxf(mx, m1);
         if (!measure) {
           __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, pf), Rout, idx * 4u, 0u, 0);
 #pragma unroll
@@ -867,7 +949,7 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
   if (j < y1) body(j, S0{});
   if (j + 1 < y1) body(j + 1, S1{});
   if constexpr (Stor<ST>::neq) {
-    // wave maximum of |f~ - E| over updated cells -> the instance's slot
+    // wave maximum of |f~_i - E_i| (i >= 1) over updated cells -> the instance's slot
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
     if (lane == 0 && mx > 0.0f) {
@@ -1056,7 +1138,7 @@ __device__ __forceinline__ void encode_neq(const InstDev* __restrict__ I, char* 
     float E = I->ef[k][nc - 1];
     for (int mm = nc - 2; mm >= 0; --mm) E = fmaf(E, pf, I->ef[k][mm]);
     const float d = (float)(f[k] - (double)E);
-    m = fmaxf(m, fabsf(d));
+    if (k > 0) m = fmaxf(m, fabsf(d));   // the stored directions
     sq[k] = d * s;
   }
   if (s > 0.0f) {
@@ -1105,7 +1187,7 @@ __global__ void k_init_eq(const InstDev* __restrict__ I, const double* __restric
   }
 }
 
-// pass 0: max |f~ - E| into slots[slot]; pass 1: encode with that slot's scale
+// pass 0: max_{i >= 1} |f~_i - E_i| into slots[slot]; pass 1: encode with that slot's scale
 template <int Q, int ST>
 __global__ void k_set_f(const InstDev* __restrict__ I, const double* __restrict__ f, int parity,
                         int pass, int slot) {
