@@ -26,10 +26,19 @@
  *   - C = int_0^phi B'(s) B'(s)^T ds (Remark 3), integration constant 0;
  *   - D3Q7: weights 0 (rest) and 1/6 (x6) with c_s^2 = c^2/3 and the linear
  *     equilibrium E_i = w_i (phi + c_i.B / c_s^2) of Remark 3 (needs D = phi I);
- *   - walls: periodic (wrapped ghost cell and width) or zero-flux mirror
+ *   - walls: periodic (wrapped ghost cell and width), zero-flux mirror
  *     (fbar+ of the adjacent interior cell with the wall-normal velocity
- *     component reversed, width of the adjacent cell), per axis; a ghost shell
- *     one cell wide, edges and corners included.
+ *     component reversed, width of the adjacent cell) or Dirichlet by
+ *     non-equilibrium extrapolation, per axis; a ghost shell one cell wide,
+ *     edges and corners included.  A ghost with a Dirichlet wall on any of
+ *     its out-of-range axes takes fbar+_g = E(phi_g) + (fbar+_a - E(phi_a)),
+ *     a the nearest interior cell (clamped per axis) and phi_g the caller's
+ *     boundary value at the ghost centre at t_n (the two-dimensional rule,
+ *     per axis); otherwise each mirror axis reflects in turn.
+ *   - boundary values of one step: the shell in the order z = -1 plane and
+ *     z = nz plane (each [ny+2][nx+2], j and i from -1), then the y = -1 and
+ *     y = ny slabs (each [nz][nx+2]), then the x = -1 and x = nx columns (each
+ *     [nz][ny]).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -38,7 +47,7 @@
 #define O3_MAXQ 19
 #define O3_MAXDEG 4
 
-enum { O3_PERIODIC = 0, O3_MIRROR = 2 };
+enum { O3_PERIODIC = 0, O3_DIRICHLET = 1, O3_MIRROR = 2 };
 
 /* D3Q15 (eq. 2.28) and D3Q19 (eq. 2.6): the columns of the printed matrices */
 static const int Q15[15][3] = {{0, 0, 0},  {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
@@ -180,7 +189,7 @@ Oracle3* or3_create(int nx, int ny, int nz, const double* xf, const double* yf, 
       !(alpha > 0))
     return NULL;
   for (a = 0; a < 3; ++a)
-    if (bcs[a] != O3_PERIODIC && bcs[a] != O3_MIRROR) return NULL;
+    if (bcs[a] != O3_PERIODIC && bcs[a] != O3_MIRROR && bcs[a] != O3_DIRICHLET) return NULL;
   o = (Oracle3*)calloc(1, sizeof(Oracle3));
   o->n[0] = nx; o->n[1] = ny; o->n[2] = nz;
   o->q = q; o->c = c; o->cfl = cfl; o->alpha = alpha;
@@ -295,9 +304,22 @@ static int wrap_or_clamp(int i, int n, int bc) {
   return i < 0 ? 0 : n - 1;
 }
 
-/* fbar+ = a1 f~ + b1 E(phi) (eq. 2.21) at cell (i, j, k) of the ghost shell */
-static void fbar_plus(const Oracle3* o, int i, int j, int k, double* out) {
-  int idx[3] = {i, j, k}, s[3], a, m;
+/* position of ghost cell (i, j, k) in one step's boundary values */
+static size_t shell_index(const Oracle3* o, int i, int j, int k) {
+  const size_t nx = o->n[0], ny = o->n[1], nz = o->n[2];
+  const size_t zplane = (nx + 2) * (ny + 2), yslab = (nx + 2) * nz, xcol = ny * nz;
+  if (k == -1) return (size_t)(j + 1) * (nx + 2) + (size_t)(i + 1);
+  if (k == (int)nz) return zplane + (size_t)(j + 1) * (nx + 2) + (size_t)(i + 1);
+  if (j == -1) return 2 * zplane + (size_t)k * (nx + 2) + (size_t)(i + 1);
+  if (j == (int)ny) return 2 * zplane + yslab + (size_t)k * (nx + 2) + (size_t)(i + 1);
+  if (i == -1) return 2 * zplane + 2 * yslab + (size_t)k * ny + (size_t)j;
+  return 2 * zplane + 2 * yslab + xcol + (size_t)k * ny + (size_t)j; /* i == nx */
+}
+
+/* fbar+ = a1 f~ + b1 E(phi) (eq. 2.21) at cell (i, j, k) of the ghost shell;
+ * ring: the step's boundary values (NULL without Dirichlet walls) */
+static void fbar_plus(const Oracle3* o, int i, int j, int k, const double* ring, double* out) {
+  int idx[3] = {i, j, k}, s[3], a, m, dir = 0;
   size_t N = ncells(o), c;
   double ft[O3_MAXQ], E[O3_MAXQ], phi = 0.0, tmp[O3_MAXQ];
   for (a = 0; a < 3; ++a) s[a] = wrap_or_clamp(idx[a], o->n[a], o->bc[a]);
@@ -305,6 +327,15 @@ static void fbar_plus(const Oracle3* o, int i, int j, int k, double* out) {
   for (m = 0; m < o->q; ++m) { ft[m] = o->f[m * N + c]; phi += ft[m]; }
   feq(o, phi, E);
   for (m = 0; m < o->q; ++m) out[m] = o->a1 * ft[m] + o->b1 * E[m];
+  for (a = 0; a < 3; ++a)
+    if ((idx[a] < 0 || idx[a] >= o->n[a]) && o->bc[a] == O3_DIRICHLET) dir = 1;
+  if (dir) {
+    /* non-equilibrium extrapolation from the nearest interior cell */
+    double Eg[O3_MAXQ];
+    feq(o, ring[shell_index(o, i, j, k)], Eg);
+    for (m = 0; m < o->q; ++m) out[m] = Eg[m] + (out[m] - E[m]);
+    return;
+  }
   for (a = 0; a < 3; ++a) {
     int wall = (idx[a] < 0 || idx[a] >= o->n[a]) && o->bc[a] == O3_MIRROR;
     if (!wall) continue;
@@ -397,13 +428,19 @@ typedef struct {
   double* g;  /* fbar+ on cells -1..n per axis, [(k+1)][(j+1)][(i+1)][q] */
 } FullCtx;
 
+/* number of boundary values of one step */
+size_t or3_shell_len(const Oracle3* o) {
+  const size_t nx = o->n[0], ny = o->n[1], nz = o->n[2];
+  return 2 * (nx + 2) * (ny + 2) + 2 * (nx + 2) * nz + 2 * ny * nz;
+}
+
 static const double* full_get(const void* ctx, int i, int j, int k) {
   const FullCtx* F = (const FullCtx*)ctx;
   const Oracle3* o = F->o;
   return F->g + ((((size_t)(k + 1) * (o->n[1] + 2)) + (j + 1)) * (o->n[0] + 2) + (i + 1)) * o->q;
 }
 
-static void step_once(Oracle3* o) {
+static void step_once(Oracle3* o, const double* ring) {
   const int nx = o->n[0], ny = o->n[1], nz = o->n[2], q = o->q;
   const size_t N = ncells(o);
   FullCtx F;
@@ -414,7 +451,7 @@ static void step_once(Oracle3* o) {
 #pragma omp parallel for private(i, j)
   for (k = -1; k <= nz; ++k)
     for (j = -1; j <= ny; ++j)
-      for (i = -1; i <= nx; ++i) fbar_plus(o, i, j, k, (double*)full_get(&F, i, j, k));
+      for (i = -1; i <= nx; ++i) fbar_plus(o, i, j, k, ring, (double*)full_get(&F, i, j, k));
 #pragma omp parallel for private(i, j, m)
   for (k = 0; k < nz; ++k)
     for (j = 0; j < ny; ++j)
@@ -430,9 +467,12 @@ static void step_once(Oracle3* o) {
   o->t += o->dt;
 }
 
-void or3_step(Oracle3* o, int nsteps) {
+/* Advance nsteps.  rings: the boundary values of nsteps consecutive steps
+ * (step s reads rings + s * or3_shell_len), NULL without Dirichlet walls. */
+void or3_step(Oracle3* o, int nsteps, const double* rings) {
   int s;
-  for (s = 0; s < nsteps; ++s) step_once(o);
+  const size_t len = or3_shell_len(o);
+  for (s = 0; s < nsteps; ++s) step_once(o, rings ? rings + (size_t)s * len : NULL);
 }
 
 typedef struct {
@@ -449,7 +489,7 @@ static const double* local_get(const void* ctx, int i, int j, int k) {
 /* One step evaluated only at the listed cells (triples i, j, k), without
  * changing the state; the same face and update code as the full step.
  * out: [ncells][q]. */
-void or3_step_cells(const Oracle3* o, int ncells_, const int* cells, double* out) {
+void or3_step_cells(const Oracle3* o, int ncells_, const int* cells, const double* ring, double* out) {
   int n, a, b, c;
   LocalCtx* L = (LocalCtx*)malloc(sizeof(LocalCtx));
   L->o = o;
@@ -458,7 +498,7 @@ void or3_step_cells(const Oracle3* o, int ncells_, const int* cells, double* out
     L->ci = i; L->cj = j; L->ck = k;
     for (c = -1; c <= 1; ++c)
       for (b = -1; b <= 1; ++b)
-        for (a = -1; a <= 1; ++a) fbar_plus(o, i + a, j + b, k + c, L->g[c + 1][b + 1][a + 1]);
+        for (a = -1; a <= 1; ++a) fbar_plus(o, i + a, j + b, k + c, ring, L->g[c + 1][b + 1][a + 1]);
     update_cell(o, local_get, L, i, j, k, out + (size_t)n * o->q);
   }
   free(L);

@@ -37,8 +37,10 @@ def _lib(openmp: bool = False):
         lib.or3_get_phi.argtypes = [C.c_void_p, _d]
         lib.or3_time.restype = C.c_double
         lib.or3_time.argtypes = [C.c_void_p]
-        lib.or3_step.argtypes = [C.c_void_p, C.c_int]
-        lib.or3_step_cells.argtypes = [C.c_void_p, C.c_int, _i, _d]
+        lib.or3_step.argtypes = [C.c_void_p, C.c_int, _d]
+        lib.or3_step_cells.argtypes = [C.c_void_p, C.c_int, _i, _d, _d]
+        lib.or3_shell_len.restype = C.c_size_t
+        lib.or3_shell_len.argtypes = [C.c_void_p]
         lib.or3_errors.argtypes = [C.c_void_p, _d, _d, _d]
         lib.or3_mass.restype = C.c_double
         lib.or3_mass.argtypes = [C.c_void_p]
@@ -132,14 +134,25 @@ class Oracle3D:
         self.lib.or3_get_phi(self.h, _p(out))
         return out
 
-    def step(self, nsteps: int = 1):
-        self.lib.or3_step(self.h, int(nsteps))
+    def shell_len(self) -> int:
+        """Boundary values of one step (the ghost shell, Dirichlet walls)."""
+        return int(self.lib.or3_shell_len(self.h))
 
-    def step_cells(self, cells) -> np.ndarray:
+    def step(self, nsteps: int = 1, rings=None):
+        """Advance nsteps; rings: [nsteps][shell_len] boundary values at the
+        ghost centres, step by step (needed with Dirichlet walls)."""
+        if rings is not None:
+            rings = _f64(rings).reshape(nsteps, -1)
+            assert rings.shape[1] == self.shell_len()
+        self.lib.or3_step(self.h, int(nsteps), _p(rings) if rings is not None else None)
+
+    def step_cells(self, cells, ring=None) -> np.ndarray:
         """One step evaluated at the listed (i, j, k) cells; the state is unchanged."""
         cells = np.ascontiguousarray(cells, dtype=np.int32).reshape(-1, 3)
         out = np.zeros((len(cells), self.q))
-        self.lib.or3_step_cells(self.h, len(cells), cells.ctypes.data_as(_i), _p(out))
+        r = _f64(ring) if ring is not None else None
+        self.lib.or3_step_cells(self.h, len(cells), cells.ctypes.data_as(_i),
+                                _p(r) if r is not None else None, _p(out))
         return out
 
     def errors(self, phi_a):

@@ -532,7 +532,7 @@ class Problem3D:
 
     b: (B_x, B_y, B_z) coefficient tuples of B(phi) = sum_k b_k phi^k;
     d: (D_xx, D_yy, D_zz, D_xy, D_xz, D_yz) coefficient tuples of D(phi);
-    bc: per axis PERIODIC or MIRROR."""
+    bc: per axis PERIODIC, MIRROR or DIRICHLET (data from exact at the ghost centres)."""
     name: str
     xf: np.ndarray
     yf: np.ndarray
@@ -573,6 +573,37 @@ class Problem3D:
     def dt(self) -> float:
         w = min(np.diff(self.xf).min(), np.diff(self.yf).min(), np.diff(self.zf).min())
         return self.cfl * float(w) / self.c
+
+    def rings(self, nsteps: int, start_step: int = 0) -> Optional[np.ndarray]:
+        """Dirichlet data at the ghost-shell centres for steps
+        start..start+nsteps-1, [nsteps][shell length] (None without a
+        Dirichlet axis)."""
+        if DIRICHLET not in self.bc:
+            return None
+        xs, ys, zs = shell_points3d(self.xf, self.yf, self.zf, self.bc)
+        dt = self.dt()
+        return np.stack([self.exact(xs, ys, zs, (start_step + n) * dt)
+                         for n in range(nsteps)]).astype(np.float64)
+
+
+def shell_points3d(xf: np.ndarray, yf: np.ndarray, zf: np.ndarray, bc):
+    """(x, y, z) of the ghost-shell centres of a 3-D mesh, in the order of one
+    step's Dirichlet data: the z = -1 and z = nz planes ([ny+2][nx+2], j and i
+    from -1), the y = -1 and y = ny slabs ([nz][nx+2]), then the x = -1 and
+    x = nx columns ([nz][ny])."""
+    gx, gy, gz = ghost_centres(xf, bc[0]), ghost_centres(yf, bc[1]), ghost_centres(zf, bc[2])
+    nx, ny, nz = len(xf) - 1, len(yf) - 1, len(zf) - 1
+    parts = []
+    for kk in (0, nz + 1):
+        Y, X = np.meshgrid(gy, gx, indexing="ij")
+        parts.append((X.ravel(), Y.ravel(), np.full(X.size, gz[kk])))
+    for jj in (0, ny + 1):
+        Z, X = np.meshgrid(gz[1:-1], gx, indexing="ij")
+        parts.append((X.ravel(), np.full(X.size, gy[jj]), Z.ravel()))
+    for ii in (0, nx + 1):
+        Z, Y = np.meshgrid(gz[1:-1], gy[1:-1], indexing="ij")
+        parts.append((np.full(Y.size, gx[ii]), Y.ravel(), Z.ravel()))
+    return tuple(np.concatenate([p[a] for p in parts]) for a in range(3))
 
 
 def gaussian_hill3d(x, y, z, t, u, K, sigma0, period=2.0, images=1):
@@ -687,6 +718,9 @@ def random_problem3d(seed: int, nx: int, ny: int, nz: int, q: int = 19,
         ph = rng.uniform(0, 2 * math.pi, size=3) if periodic else np.zeros(3)
         field += a * np.cos(wn * kx * X + ph[0]) * np.cos(wn * ky * Y + ph[1]) * np.cos(wn * kz * Z + ph[2])
     p.phi0 = 0.5 + field
+    amp = float(rng.uniform(0.05, 0.2))   # Dirichlet data (any smooth field of x, y, z, t)
+    p.exact = lambda x, y, z, t: 0.5 + amp * np.sin(2.0 * np.asarray(x) + 3.0 * np.asarray(y)
+                                                    - 1.5 * np.asarray(z) + 5.0 * t)
     return p
 
 

@@ -11,6 +11,12 @@ eq. 2.6, D3Q7 of Remark 3) against what the paper and the mathematics fix:
   step, which tests/test_oracle_pins.py pins independently; checked along all
   three axes, with mirror walls and stretched meshes;
 - invariants: uniform state, mass, axis permutation symmetry;
+- Dirichlet walls (non-equilibrium extrapolation): a linear field between
+  Dirichlet walls with B = 0 and D = phi I is an exact steady state of the
+  scheme (E_i = w_i phi is then linear in phi, so the reconstruction and the
+  ghost rule are exact); the reduction to two dimensions holds with Dirichlet
+  walls, against the two-dimensional oracle's rule, with the shell values that
+  must not be read set to NaN;
 - second-order convergence to the 3-D Gaussian hill closed form.
 """
 import math
@@ -115,11 +121,11 @@ def project_groups(cvec, axis):
 
 @pytest.mark.parametrize("q,q2", [(19, 9), (15, 9), (7, 5)])
 @pytest.mark.parametrize("axis", [0, 1, 2])
-@pytest.mark.parametrize("walls", [False, True])
+@pytest.mark.parametrize("walls", [W.PERIODIC, W.MIRROR, W.DIRICHLET])
 def test_uniform_along_an_axis_reduces_to_2d(q, q2, axis, walls):
     rng = np.random.default_rng(10 * axis + q)
-    p2 = W.random_problem(40 + axis, 11, 9, q=q2, bcx=W.MIRROR if walls else W.PERIODIC,
-                          bcy=W.MIRROR if walls else W.PERIODIC, stretched=walls, bdeg=2, ddeg=2)
+    p2 = W.random_problem(40 + axis, 11, 9, q=q2, bcx=walls, bcy=walls,
+                          stretched=walls != W.PERIODIC, bdeg=2, ddeg=2)
     if q2 == 5:
         p2.dxx, p2.dxy, p2.dyy = (0.0, 1.0), (0.0,), (0.0, 1.0)
     keep = [a for a in range(3) if a != axis]
@@ -145,8 +151,18 @@ def test_uniform_along_an_axis_reduces_to_2d(q, q2, axis, walls):
     p3.phi0 = {0: phi2[:, :, None], 1: phi2[:, None, :], 2: phi2[None, :, :]}[axis]
     o2, o3 = Oracle(p2), Oracle3D(p3)
     assert abs(o2.dt - o3.dt) < 1e-15
-    o2.step(4)
-    o3.step(4)
+    rings2 = p2.rings(4)
+    rings3 = None
+    if rings2 is not None:
+        # the plane's Dirichlet data at every shell point whose projection is a
+        # ghost of the plane; NaN where it is an interior cell of the plane (a
+        # ghost only along the periodic uniform axis: never read)
+        pts = W.shell_points3d(p3.xf, p3.yf, p3.zf, p3.bc)
+        u, v = pts[keep[0]], pts[keep[1]]
+        inside = (u > p2.xf[0]) & (u < p2.xf[-1]) & (v > p2.yf[0]) & (v < p2.yf[-1])
+        rings3 = np.stack([np.where(inside, np.nan, p2.exact(u, v, n * o2.dt)) for n in range(4)])
+    o2.step(4, rings2)
+    o3.step(4, rings3)
     cvec, _ = read_lattice3d(LATTICES[q])
     groups = project_groups(cvec, axis)
     f3 = o3.get_f()
@@ -216,15 +232,35 @@ def test_axis_permutation_symmetry(q):
         assert np.abs(np.transpose(f[i], (2, 0, 1)) - g[j]).max() <= 1e-13 * np.abs(f).max()
 
 
-def test_sampled_step_equals_full_step():
-    p = W.random_problem3d(9, 7, 6, 5, q=19, bc=(W.MIRROR, W.PERIODIC, W.MIRROR), stretched=True)
+@pytest.mark.parametrize("bc", [(W.MIRROR, W.PERIODIC, W.MIRROR), (W.DIRICHLET, W.MIRROR, W.DIRICHLET)])
+def test_sampled_step_equals_full_step(bc):
+    p = W.random_problem3d(9, 7, 6, 5, q=19, bc=bc, stretched=True)
     o = Oracle3D(p)
+    ring = p.rings(1)
     cells = [(0, 0, 0), (6, 5, 4), (3, 2, 1), (0, 5, 2), (6, 0, 4)]
-    s = o.step_cells(cells)
-    o.step(1)
+    s = o.step_cells(cells, ring[0] if ring is not None else None)
+    o.step(1, ring)
     f = o.get_f()
     for n, (i, j, k) in enumerate(cells):
         assert np.array_equal(s[n], f[:, k, j, i])
+
+
+@pytest.mark.parametrize("q", [19, 15, 7])
+@pytest.mark.parametrize("stretched", [False, True])
+def test_linear_steady_state_between_dirichlet_walls(q, stretched):
+    """B = 0, D = phi I, phi = x + 2y - z with Dirichlet walls on every axis
+    (data: the same linear function at the ghost centres): phi stays linear."""
+    faces = [W.tanh_faces(n, 1.3) if stretched else W.uniform_faces(n, 0.0, 1.0) for n in (9, 8, 7)]
+    lin = lambda x, y, z, t: np.asarray(x) + 2.0 * np.asarray(y) - np.asarray(z)
+    p = W.Problem3D(name="linear", xf=faces[0], yf=faces[1], zf=faces[2], q=q, c=1.1, cfl=0.5,
+                    alpha=0.01, bc=(W.DIRICHLET,) * 3, exact=lin)
+    X, Y, Z = p.mesh()
+    p.phi0 = lin(X, Y, Z, 0.0)
+    o = Oracle3D(p)
+    ring = p.rings(1)
+    for _ in range(30):
+        o.step(1, ring)
+        assert np.abs(o.get_phi() - p.phi0).max() <= 1e-12
 
 
 @pytest.mark.parametrize("q", [19, 15])
