@@ -14,11 +14,13 @@
  * Readings (as in the CPU oracle): lambda = alpha / c_s^2, c_s^2 = c^2/3;
  * dt = cfl * (smallest cell width along any axis) / c; C = int_0^phi B'B'^T
  * (Remark 3); each tangential derivative at a face is the mean of the two
- * cells' central differences along that axis; walls per axis are periodic or
+ * cells' central differences along that axis; walls per axis are periodic,
  * zero-flux mirrors (fbar+ of the adjacent cell with the wall-normal velocity
- * reversed); D3Q7 uses weights 0 and 1/6 and the linear equilibrium of
- * Remark 3 (D = phi I only).  Sources and Dirichlet walls are not built in
- * three dimensions (E_UNSUPPORTED).
+ * reversed) or Dirichlet by non-equilibrium extrapolation, the treatment of
+ * Sec. 4 (a ghost with a Dirichlet wall on any of its out-of-range axes takes
+ * fbar+_g = E(phi_g) + fbar+_a - E(phi_a), a the nearest interior cell);
+ * D3Q7 uses weights 0 and 1/6 and the linear equilibrium of Remark 3
+ * (D = phi I only).  Sources are not built in three dimensions.
  */
 #ifndef DUGKS3D_H
 #define DUGKS3D_H
@@ -36,7 +38,8 @@ extern "C" {
 typedef struct dugks3_params {
   int abi_version; /* must be DUGKS3_ABI_VERSION */
   int storage;     /* DUGKS_F64 or DUGKS_F32 */
-  int bc[3];       /* per axis x, y, z: DUGKS_BC_PERIODIC or DUGKS_BC_MIRROR */
+  int bc[3];       /* per axis x, y, z: DUGKS_BC_PERIODIC, DUGKS_BC_MIRROR or
+                      DUGKS_BC_DIRICHLET (data from dugks3_set_dirichlet) */
   double c;        /* lattice speed, > 0 */
   double cfl;      /* CFL number, 0 < cfl < 1 */
   double alpha;    /* diffusion coefficient of eq. 2.1, > 0 */
@@ -86,6 +89,20 @@ int dugks3_set_phi(dugks3_ctx* ctx, const double* phi, int on_device);
 
 /* f~ [q][nz][ny][nx] (binary64) as the state; resets the step count. */
 int dugks3_set_f(dugks3_ctx* ctx, const double* f, int on_device);
+
+/* Dirichlet data: ring_dev (device, caller-owned, must outlive the steps)
+ * holds nsteps blocks of shell-length binary64 values, phi at the ghost-cell
+ * centres at t_n = n dt for step n = 0..nsteps-1 counted from the last
+ * dugks3_set_phi / dugks3_set_f.  Shell length 2(nx+2)(ny+2) + 2(nx+2)nz +
+ * 2 ny nz, in the order: the z = -1 and z = nz planes (each [ny+2][nx+2], j
+ * and i from -1), the y = -1 and y = ny slabs (each [nz][nx+2], i from -1),
+ * the x = -1 and x = nx columns (each [nz][ny]).  A ghost centre lies half
+ * the adjacent interior cell's width outside the wall (half the wrapped
+ * cell's width along a periodic axis); values read: the ghosts with a
+ * Dirichlet wall on one of their out-of-range axes.  Stepping with a
+ * Dirichlet axis past nsteps (or without data) returns E_STATE.  Errors:
+ * E_ARG (nsteps < 0, NULL data with nsteps > 0). */
+int dugks3_set_dirichlet(dugks3_ctx* ctx, const double* ring_dev, int nsteps);
 
 /* Advance nsteps >= 0 steps (asynchronous).  Errors: E_STATE, E_HIP. */
 int dugks3_step(dugks3_ctx* ctx, int nsteps);

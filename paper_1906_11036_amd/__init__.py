@@ -441,6 +441,16 @@ class Solver3D:
         t = self._dev64(f, (self.q, self.nz, self.ny, self.nx))
         L.check3(self.lib.dugks3_set_f(self.h, C.c_void_p(t.data_ptr()), 1), self.h, "dugks3_set_f")
 
+    def set_dirichlet(self, rings):
+        """Dirichlet data, [nsteps][shell length] (workloads.Problem3D.rings),
+        kept on the device while this solver lives."""
+        torch = _torch()
+        t = rings if torch.is_tensor(rings) else torch.from_numpy(np.ascontiguousarray(rings, dtype=np.float64))
+        self._rings = t.to(device=self.device, dtype=torch.float64).contiguous()
+        n = int(self._rings.shape[0]) if self._rings.dim() > 1 else 1
+        L.check3(self.lib.dugks3_set_dirichlet(self.h, C.c_void_p(self._rings.data_ptr()), n), self.h,
+                 "dugks3_set_dirichlet")
+
     def step(self, nsteps=1):
         L.check3(self.lib.dugks3_step(self.h, int(nsteps)), self.h, "dugks3_step")
 

@@ -132,6 +132,7 @@ SIGNATURES = {
     "dugks3_set_phi": (_int, [_vp, _vp, _int]),
     "dugks3_set_f": (_int, [_vp, _vp, _int]),
     "dugks3_step": (_int, [_vp, _int]),
+    "dugks3_set_dirichlet": (_int, [_vp, _vp, _int]),
     "dugks3_get_phi": (_int, [_vp, _vp, _int]),
     "dugks3_get_f": (_int, [_vp, _vp, _int]),
     "dugks3_reduce": (_int, [_vp, _vp, _dp, _dp, _dp]),

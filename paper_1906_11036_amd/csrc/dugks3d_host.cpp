@@ -88,6 +88,8 @@ struct dugks3_ctx {
   Inst3 host{};
   bool initialised = false;
   long long step = 0;
+  const double* ring = nullptr;   // Dirichlet data (device, caller-owned)
+  long long ring_steps = 0;
 
   int fail(int rc, const std::string& m) { err = m; return rc; }
   int hipfail(hipError_t e, const char* what) {
@@ -95,6 +97,9 @@ struct dugks3_ctx {
     return DUGKS_E_HIP;
   }
   long long cells() const { return (long long)n[0] * n[1] * n[2]; }
+  bool any_dirichlet() const {
+    return p.bc[0] == DUGKS_BC_DIRICHLET || p.bc[1] == DUGKS_BC_DIRICHLET || p.bc[2] == DUGKS_BC_DIRICHLET;
+  }
   bool bound() const { return ws != nullptr; }
   size_t elem() const { return p.storage == DUGKS_F64 ? 8 : 4; }
 
@@ -167,7 +172,11 @@ struct dugks3_ctx {
     d3.rb = a3 * b1 / b3;
     d3.b1 = b1;
     d3.kg = 4.0 / 3.0 * b1;
+    d3.inv_b1 = 1.0 / b1;
     d3.raf = (float)d3.ra; d3.rbf = (float)d3.rb; d3.b1f = (float)d3.b1; d3.kgf = (float)d3.kg;
+    d3.inv_b1f = (float)d3.inv_b1;
+    d3.ring = ring;
+    d3.ring_len = shell_len(n[0], n[1], n[2]);
     for (int i = 0; i < q; ++i)
       for (int m = 0; m < kMaxCoef; ++m) {
         d3.e[i][m] = e[i][m];
@@ -262,8 +271,8 @@ int dugks3_create(dugks3_ctx** out, int nx, int ny, int nz, const double* xf, co
   if (p->storage != DUGKS_F64 && p->storage != DUGKS_F32)
     return x->fail(DUGKS_E_UNSUPPORTED, "three-dimensional storage is binary64 or binary32");
   for (int a = 0; a < 3; ++a)
-    if (p->bc[a] != DUGKS_BC_PERIODIC && p->bc[a] != DUGKS_BC_MIRROR)
-      return x->fail(DUGKS_E_UNSUPPORTED, "three-dimensional walls are periodic or mirror");
+    if (p->bc[a] != DUGKS_BC_PERIODIC && p->bc[a] != DUGKS_BC_MIRROR && p->bc[a] != DUGKS_BC_DIRICHLET)
+      return x->fail(DUGKS_E_ARG, "unknown boundary kind");
   const int ns[3] = {nx, ny, nz};
   const double* fs[3] = {xf, yf, zf};
   x->q = q;
@@ -423,6 +432,14 @@ int dugks3_set_f(dugks3_ctx* ctx, const double* f, int on_device) {
   return DUGKS_OK;
 }
 
+int dugks3_set_dirichlet(dugks3_ctx* ctx, const double* ring_dev, int nsteps) {
+  GUARD3(ctx);
+  if (nsteps < 0 || (nsteps > 0 && !ring_dev)) return ctx->fail(DUGKS_E_ARG, "bad Dirichlet data");
+  ctx->ring = nsteps > 0 ? ring_dev : nullptr;
+  ctx->ring_steps = nsteps;
+  return ctx->bound() ? ctx->upload() : DUGKS_OK;
+}
+
 int dugks3_step(dugks3_ctx* ctx, int nsteps) {
   GUARD3(ctx);
   if (nsteps < 0) return ctx->fail(DUGKS_E_ARG, "nsteps < 0");
@@ -430,8 +447,10 @@ int dugks3_step(dugks3_ctx* ctx, int nsteps) {
   if (!ctx->initialised) return ctx->fail(DUGKS_E_STATE, "state not initialised");
   if (ctx->lds_bytes(ctx->launch) > ctx->lds_limit())
     return ctx->fail(DUGKS_E_ARG, "launch needs more LDS than a block may hold");
+  if (ctx->any_dirichlet() && (ctx->ring == nullptr || ctx->step + nsteps > ctx->ring_steps))
+    return ctx->fail(DUGKS_E_STATE, "Dirichlet walls need data for every step (dugks3_set_dirichlet)");
   for (int s = 0; s < nsteps; ++s) {
-    if (launch_step3(ctx->dev(), ctx->host, (int)(ctx->step & 1), ctx->launch, ctx->stream))
+    if (launch_step3(ctx->dev(), ctx->host, (int)(ctx->step & 1), ctx->step, ctx->launch, ctx->stream))
       return ctx->fail(DUGKS_E_HIP, std::string("step launch failed: ") + hipGetErrorString(hipGetLastError()));
     ctx->step += 1;
   }

@@ -40,10 +40,14 @@ struct alignas(64) Inst3 {
   unsigned buf_bytes;      // bytes of one buffer (< 4 GiB)
   int n[3];
   int pitch, q;
-  int bc[3];               // DUGKS_BC_PERIODIC or DUGKS_BC_MIRROR per axis
+  int bc[3];               // DUGKS_BC_PERIODIC, DUGKS_BC_DIRICHLET or DUGKS_BC_MIRROR per axis
   int ncoef, storage;
-  double ra, rb, b1, kg;
-  float raf, rbf, b1f, kgf;
+  double ra, rb, b1, kg, inv_b1;
+  float raf, rbf, b1f, kgf, inv_b1f;
+  // Dirichlet data (caller-owned, binary64): step n reads ring + n * ring_len,
+  // phi at the ghost-shell centres (order: see shell_index)
+  const double* ring;
+  long long ring_len;
   double e[kMaxQ][kMaxCoef];   // E_i(phi) = sum_k e[i][k] phi^k (eq. 2.3)
   float ef[kMaxQ][kMaxCoef];
 };
@@ -53,9 +57,27 @@ struct Launch3 {
   int planes = 64;  // planes swept per block
 };
 
+// Position of ghost cell (i, j, k) (one index out of its range -1..n) in one
+// step's Dirichlet data: the z = -1 and z = nz planes ([ny+2][nx+2], j and i
+// from -1), the y = -1 and y = ny slabs ([nz][nx+2]), then the x = -1 and
+// x = nx columns ([nz][ny]).
+__host__ __device__ inline long long shell_index(int nx, int ny, int nz, int i, int j, int k) {
+  const long long zplane = (long long)(nx + 2) * (ny + 2), yslab = (long long)(nx + 2) * nz;
+  if (k < 0) return (long long)(j + 1) * (nx + 2) + (i + 1);
+  if (k >= nz) return zplane + (long long)(j + 1) * (nx + 2) + (i + 1);
+  if (j < 0) return 2 * zplane + (long long)k * (nx + 2) + (i + 1);
+  if (j >= ny) return 2 * zplane + yslab + (long long)k * (nx + 2) + (i + 1);
+  if (i < 0) return 2 * zplane + 2 * yslab + (long long)k * ny + j;
+  return 2 * zplane + 2 * yslab + (long long)ny * nz + (long long)k * ny + j;
+}
+inline long long shell_len(int nx, int ny, int nz) {
+  return 2LL * (nx + 2) * (ny + 2) + 2LL * (nx + 2) * nz + 2LL * ny * nz;
+}
+
 // Blocks of one step for the launch (x strips x row tiles x plane chunks).
 long long step3_blocks(const Inst3& h, const Launch3& l);
-int launch_step3(const Inst3* d, const Inst3& h, int parity, const Launch3& l, void* stream);
+// step: the step index since the state was set (selects the Dirichlet data)
+int launch_step3(const Inst3* d, const Inst3& h, int parity, long long step, const Launch3& l, void* stream);
 // LDS bytes of one block of the step kernel (walls: the instantiation with
 // mirror code, for a non-periodic axis or more than four coefficients)
 size_t step3_lds_bytes(int storage, int q, bool walls, const Launch3& l);

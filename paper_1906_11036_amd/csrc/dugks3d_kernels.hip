@@ -65,6 +65,7 @@ template <> struct C3<double> {
   __device__ static double rb(const Inst3* I) { return I->rb; }
   __device__ static double b1(const Inst3* I) { return I->b1; }
   __device__ static double kg(const Inst3* I) { return I->kg; }
+  __device__ static double inv_b1(const Inst3* I) { return I->inv_b1; }
   __device__ static const double* geo(const Inst3* I, int a) { return I->geo[a]; }
 };
 template <> struct C3<float> {
@@ -73,6 +74,7 @@ template <> struct C3<float> {
   __device__ static float rb(const Inst3* I) { return I->rbf; }
   __device__ static float b1(const Inst3* I) { return I->b1f; }
   __device__ static float kg(const Inst3* I) { return I->kgf; }
+  __device__ static float inv_b1(const Inst3* I) { return I->inv_b1f; }
   __device__ static const float* geo(const Inst3* I, int a) { return I->geof[a]; }
 };
 
@@ -147,15 +149,37 @@ template <int Q, int NC> struct EqVec {
   __device__ __forceinline__ float operator()(int k, float x) const { return horner<NC>(c[k], x); }
 };
 
-// g = fbar+ / b1 = (a1/b1) f~ + E(phi) (eq. 2.21 over b1); phi in binary64.
+// g = fbar+ / b1 = (a1/b1) f~ + E(phi) (eq. 2.21 over b1); phi in binary64,
+// returned in the storage type.
 template <int Q, typename T, typename EQ>
-__device__ __forceinline__ void cell_g3(const Inst3* __restrict__ I, const EQ& E, const T* f, T* g) {
+__device__ __forceinline__ T cell_g3(const Inst3* __restrict__ I, const EQ& E, const T* f, T* g) {
   double phi = 0.0;
 #pragma unroll
   for (int k = 0; k < Q; ++k) phi += (double)f[k];
   const T p = (T)phi, ra = C3<T>::ra(I);
 #pragma unroll
   for (int k = 0; k < Q; ++k) g[k] = fma(ra, f[k], E(k, p));
+  return p;
+}
+
+// Dirichlet ghost by non-equilibrium extrapolation (the two-dimensional rule):
+// fbar+_g = E(phi_g) + (fbar+_a - E(phi_a)), i.e. g_g = g_a + (E(phi_g) -
+// E(phi_a)) / b1, for the directions k with sel(k); a is the interior cell
+// whose g is in g (phi_a = pa), phi_g the step's data at the ghost (x, y, z).
+template <int Q, typename T, typename EQ, typename SEL>
+__device__ __forceinline__ void nee_ghost(const Inst3* __restrict__ I, const EQ& E, const double* ring, int x,
+                                          int y, int z, T pa, T* g, SEL sel) {
+  const int nx = I->n[0];
+  const T pg = (T)ring[shell_index(nx, I->n[1], I->n[2], x < nx ? x : nx, y, z)];
+  const T ib = C3<T>::inv_b1(I);
+#pragma unroll
+  for (int k = 0; k < Q; ++k)
+    if (sel(k)) g[k] = fma(E(k, pg) - E(k, pa), ib, g[k]);
+}
+// any out-of-range axis of the cell (x wall, y wall, z index) with a Dirichlet wall
+__device__ __forceinline__ bool dirichlet_ghost(const Inst3* __restrict__ I, bool wx, bool wy, int z) {
+  return (wx && I->bc[0] == DUGKS_BC_DIRICHLET) || (wy && I->bc[1] == DUGKS_BC_DIRICHLET) ||
+         ((z < 0 || z >= I->n[2]) && I->bc[2] == DUGKS_BC_DIRICHLET);
 }
 
 template <int Q, typename T> __device__ __forceinline__ void mirror(T* g, int a) {
@@ -228,7 +252,8 @@ extern __shared__ __align__(16) unsigned char dugks3_lds[];
 // 2 interior rows (4 waves): a wave may hold the whole register file of its
 // SIMD.
 template <int Q, int ST, int NC, bool WALLS>
-__global__ __launch_bounds__(256) void k_step3h(const Inst3* __restrict__ I, int parity, int rows,
+__global__ __launch_bounds__(256) void k_step3h(const Inst3* __restrict__ I, int parity,
+                                               const double* __restrict__ ring, int rows,
                                                int planes, int strips, int tiles) {
   using T = typename S3<ST>::T;
   T* lds = (T*)dugks3_lds;
@@ -274,11 +299,15 @@ __global__ __launch_bounds__(256) void k_step3h(const Inst3* __restrict__ I, int
     return (unsigned)((src_index(zp, nz, bcz) * ny + srow) * pitch + scol);
   };
   auto make_g = [&](const T* f, int zp, T* g) {
-    cell_g3<Q, T>(I, EqScalar<NC, T>{I}, f, g);
+    const T pa = cell_g3<Q, T>(I, EqScalar<NC, T>{I}, f, g);
     if constexpr (WALLS) {
-      if (wall_x) mirror<Q, T>(g, 0);
-      if (wall_y) mirror<Q, T>(g, 1);
-      if ((zp < 0 || zp >= nz) && bcz != DUGKS_BC_PERIODIC) mirror<Q, T>(g, 2);
+      if (dirichlet_ghost(I, wall_x, wall_y, zp)) {
+        nee_ghost<Q, T>(I, EqScalar<NC, T>{I}, ring, c, r, zp, pa, g, [](int) { return true; });
+      } else {
+        if (wall_x) mirror<Q, T>(g, 0);
+        if (wall_y) mirror<Q, T>(g, 1);
+        if ((zp < 0 || zp >= nz) && bcz != DUGKS_BC_PERIODIC) mirror<Q, T>(g, 2);
+      }
     }
   };
   auto lds_at = [&](int slot, int row, int k) -> T* {
@@ -457,7 +486,8 @@ __device__ __forceinline__ void wait_vm_all() {
 }
 
 template <int Q, int NC, int ROWS, bool WALLS>
-__global__ __launch_bounds__(64 * ROWS) void k_step3s(const Inst3* __restrict__ I, int parity, int planes,
+__global__ __launch_bounds__(64 * ROWS) void k_step3s(const Inst3* __restrict__ I, int parity,
+                                                       const double* __restrict__ ring, int planes,
                                                        int strips, int tiles) {
   constexpr int W = ROWS + 2;                 // LDS rows: y0-1 .. y0+ROWS
   constexpr int HX = (2 * Q + ROWS - 1) / ROWS;   // halo-row loads per wave
@@ -541,14 +571,19 @@ __global__ __launch_bounds__(64 * ROWS) void k_step3s(const Inst3* __restrict__ 
                                                (hi ? ihi : ilo) + (unsigned)k * plane4, 0, 0, 0);
     }
   };
-  auto make_g = [&](const float (*raw)[Q][kLanes], int row, bool wy, int zp, float* g, float* f) __attribute__((always_inline)) {
+  // yr: the row's index (-1..ny), for the Dirichlet data
+  auto make_g = [&](const float (*raw)[Q][kLanes], int row, bool wy, int yr, int zp, float* g, float* f) __attribute__((always_inline)) {
 #pragma unroll
     for (int k = 0; k < Q; ++k) f[k] = raw[row][k][lane];
-    cell_g3<Q, float>(I, ev, f, g);
+    const float pa = cell_g3<Q, float>(I, ev, f, g);
     if constexpr (WALLS) {
-      if (wall_x) mirror<Q, float>(g, 0);
-      if (wy) mirror<Q, float>(g, 1);
-      if ((zp < 0 || zp >= nz) && bcz != DUGKS_BC_PERIODIC) mirror<Q, float>(g, 2);
+      if (dirichlet_ghost(I, wall_x, wy, zp)) {
+        nee_ghost<Q, float>(I, ev, ring, c, yr, zp, pa, g, [](int) { return true; });
+      } else {
+        if (wall_x) mirror<Q, float>(g, 0);
+        if (wy) mirror<Q, float>(g, 1);
+        if ((zp < 0 || zp >= nz) && bcz != DUGKS_BC_PERIODIC) mirror<Q, float>(g, 2);
+      }
     }
   };
   auto publish = [&](int slot, int row, const float* g) __attribute__((always_inline)) {
@@ -559,14 +594,14 @@ __global__ __launch_bounds__(64 * ROWS) void k_step3s(const Inst3* __restrict__ 
   // 1, the halo rows; all published to slot `slot`
   auto plane_g = [&](const float (*raw)[Q][kLanes], int zp, int slot, float* G, float* FT) __attribute__((always_inline)) {
     float f[Q];
-    make_g(raw, me, wall_y, zp, G, f);
+    make_g(raw, me, wall_y, r, zp, G, f);
 #pragma unroll
     for (int k = 0; k < Q; ++k) FT[k] = fmaf(kgv, G[k], (-1.0f / 3.0f) * f[k]);
     publish(slot, me, G);
     if (w <= 1) {
       float gx[Q];
       const int row = w == 0 ? 0 : W - 1;
-      make_g(raw, row, w == 0 ? wall_lo : wall_hi, zp, gx, f);
+      make_g(raw, row, w == 0 ? wall_lo : wall_hi, w == 0 ? y0 - 1 : y1, zp, gx, f);
       publish(slot, row, gx);
     }
   };
@@ -859,7 +894,8 @@ template <int Q, int ROWS, typename T, bool WALLS> struct LdsP {
 // z+2 is staged into the second while plane z+1 is read from the first; one
 // slot is refilled once every wave has read it.
 template <int Q, int NC, int ROWS, typename T, int H, bool WALLS>
-__device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int parity, int planes, int strips,
+__device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int parity,
+                                            const double* __restrict__ ring, int planes, int strips,
                                             int tiles, LdsP<Q, ROWS, T, WALLS>& L, const float* ecoef,
                                             double (*hphi)[4][kLanes], int w, int rw) {
   using LP = LdsP<Q, ROWS, T, WALLS>;
@@ -976,7 +1012,8 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
   };
   // g = fbar+ / b1 (eq. 2.21 over b1) of this half's directions; phi (binary64) from all of them
   // (fromreg: the raw values are the halo row's in HR)
-  auto make_g = [&](int slot, int row, bool wy, int zp, T* g, T* f, auto fromreg) __attribute__((always_inline)) {
+  // yr: the row's index (-1..ny), for the Dirichlet data
+  auto make_g = [&](int slot, int row, bool wy, int yr, int zp, T* g, T* f, auto fromreg) __attribute__((always_inline)) {
     constexpr bool kReg = decltype(fromreg)::value;
     // phi in binary64 as (q0 + q1) + (q2 + q3), qj the sum over quarter j in
     // index order (four chains); a halo row in registers takes the quarters'
@@ -1003,9 +1040,13 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
     for (int k = 0; k < Q; ++k)
       if (part_of<Q, P>(k) == H) g[k] = fma(ra, f[k], ev(k, p));
     if constexpr (WALLS) {
-      if (wall_x) mirror_part<Q, P, H, T>(g, 0);
-      if (wy) mirror_part<Q, P, H, T>(g, 1);
-      if ((zp < 0 || zp >= nz) && bcz != DUGKS_BC_PERIODIC) mirror_part<Q, P, H, T>(g, 2);
+      if (dirichlet_ghost(I, wall_x, wy, zp)) {
+        nee_ghost<Q, T>(I, ev, ring, c, yr, zp, p, g, [](int k) { return part_of<Q, P>(k) == H; });
+      } else {
+        if (wall_x) mirror_part<Q, P, H, T>(g, 0);
+        if (wy) mirror_part<Q, P, H, T>(g, 1);
+        if ((zp < 0 || zp >= nz) && bcz != DUGKS_BC_PERIODIC) mirror_part<Q, P, H, T>(g, 2);
+      }
     }
   };
   auto publish = [&](int slot, int row, const T* g) __attribute__((always_inline)) {
@@ -1032,7 +1073,7 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
     using Staged = std::integral_constant<bool, false>;
     using Halo = std::integral_constant<bool, LP::kHD>;
     T f[Q];
-    make_g(rs, me, wall_y, zp, G, f, Staged{});
+    make_g(rs, me, wall_y, r, zp, G, f, Staged{});
 #pragma unroll
     for (int k = 0; k < Q; ++k)
       if (part_of<Q, P>(k) == H) FT[k] = fma(kgv, G[k], (T)(-1.0 / 3.0) * f[k]);
@@ -1040,10 +1081,10 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
     if (rw <= 1) {
       T gx[Q];
       const int row = rw == 0 ? 0 : W - 1;
-      make_g(rs, row, rw == 0 ? wall_lo : wall_hi, zp, gx, f, Halo{});
+      make_g(rs, row, rw == 0 ? wall_lo : wall_hi, rw == 0 ? y0 - 1 : y1, zp, gx, f, Halo{});
       publish(slot, row, gx);
       if (ROWS == 1) {  // one row: its waves make both halo rows (always staged)
-        make_g(rs, W - 1, wall_hi, zp, gx, f, Staged{});
+        make_g(rs, W - 1, wall_hi, y1, zp, gx, f, Staged{});
         publish(slot, W - 1, gx);
       }
     }
@@ -1276,6 +1317,7 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
 // WALLS = false: every axis periodic, no mirror code
 template <int Q, int NC, int ROWS, typename T, bool WALLS>
 __global__ __launch_bounds__((64 * parts<Q, T, ROWS, WALLS>() * ROWS)) void k_step3p(const Inst3* __restrict__ I, int parity,
+                                                                       const double* __restrict__ ring,
                                                                        int planes, int strips, int tiles) {
   constexpr int P = parts<Q, T, ROWS, WALLS>();
   __shared__ LdsP<Q, ROWS, T, WALLS> L;
@@ -1297,13 +1339,13 @@ __global__ __launch_bounds__((64 * parts<Q, T, ROWS, WALLS>() * ROWS)) void k_st
     hp = hphi;
   }
   switch (part) {
-    case 0: step3p_half<Q, NC, ROWS, T, 0, WALLS>(I, parity, planes, strips, tiles, L, ec, hp, w, rw); break;
-    case 1: step3p_half<Q, NC, ROWS, T, 1, WALLS>(I, parity, planes, strips, tiles, L, ec, hp, w, rw); break;
+    case 0: step3p_half<Q, NC, ROWS, T, 0, WALLS>(I, parity, ring, planes, strips, tiles, L, ec, hp, w, rw); break;
+    case 1: step3p_half<Q, NC, ROWS, T, 1, WALLS>(I, parity, ring, planes, strips, tiles, L, ec, hp, w, rw); break;
     case 2:
-      if constexpr (P > 2) step3p_half<Q, NC, ROWS, T, 2, WALLS>(I, parity, planes, strips, tiles, L, ec, hp, w, rw);
+      if constexpr (P > 2) step3p_half<Q, NC, ROWS, T, 2, WALLS>(I, parity, ring, planes, strips, tiles, L, ec, hp, w, rw);
       break;
     default:
-      if constexpr (P > 2) step3p_half<Q, NC, ROWS, T, 3, WALLS>(I, parity, planes, strips, tiles, L, ec, hp, w, rw);
+      if constexpr (P > 2) step3p_half<Q, NC, ROWS, T, 3, WALLS>(I, parity, ring, planes, strips, tiles, L, ec, hp, w, rw);
       break;
   }
 }
@@ -1446,65 +1488,65 @@ long long step3_blocks(const Inst3& h, const Launch3& l) {
 static size_t step3h_lds_bytes(int q, const Launch3& l) { return (size_t)3 * (l.rows + 2) * q * kLanes * 8; }
 
 template <int Q, int NC, bool WALLS>
-static void step3s_rows(const Inst3* d, int parity, const Launch3& l, int strips, int tiles, dim3 grid,
+static void step3s_rows(const Inst3* d, int parity, const double* ring, const Launch3& l, int strips, int tiles, dim3 grid,
                         hipStream_t st) {
   switch (l.rows) {
-    case 2: hipLaunchKernelGGL((k_step3s<Q, NC, 2, WALLS>), grid, dim3(128), 0, st, d, parity, l.planes, strips, tiles); break;
-    case 3: hipLaunchKernelGGL((k_step3s<Q, NC, 3, WALLS>), grid, dim3(192), 0, st, d, parity, l.planes, strips, tiles); break;
-    default: hipLaunchKernelGGL((k_step3s<Q, NC, 4, WALLS>), grid, dim3(256), 0, st, d, parity, l.planes, strips, tiles); break;
+    case 2: hipLaunchKernelGGL((k_step3s<Q, NC, 2, WALLS>), grid, dim3(128), 0, st, d, parity, ring, l.planes, strips, tiles); break;
+    case 3: hipLaunchKernelGGL((k_step3s<Q, NC, 3, WALLS>), grid, dim3(192), 0, st, d, parity, ring, l.planes, strips, tiles); break;
+    default: hipLaunchKernelGGL((k_step3s<Q, NC, 4, WALLS>), grid, dim3(256), 0, st, d, parity, ring, l.planes, strips, tiles); break;
   }
 }
 template <int Q, int NC, bool WALLS>
-static void step3h_launch(const Inst3* d, const Inst3& h, int parity, const Launch3& l, int strips, int tiles,
+static void step3h_launch(const Inst3* d, const Inst3& h, int parity, const double* ring, const Launch3& l, int strips, int tiles,
                           dim3 grid, hipStream_t st) {
   hipLaunchKernelGGL((k_step3h<Q, DUGKS_F64, NC, WALLS>), grid, dim3(64 * (l.rows + 2)), step3h_lds_bytes(Q, l),
-                     st, d, parity, l.rows, l.planes, strips, tiles);
+                     st, d, parity, ring, l.rows, l.planes, strips, tiles);
 }
 // D3Q7, one wave a row: the wall-free instantiation when every axis is
 // periodic and the equilibrium polynomials have at most 4 coefficients
 template <int Q, int NC>
-static void step3_row_waves(const Inst3* d, const Inst3& h, int parity, const Launch3& l, int strips,
+static void step3_row_waves(const Inst3* d, const Inst3& h, int parity, const double* ring, const Launch3& l, int strips,
                             int tiles, dim3 grid, hipStream_t st) {
   const bool walls = h.bc[0] != DUGKS_BC_PERIODIC || h.bc[1] != DUGKS_BC_PERIODIC || h.bc[2] != DUGKS_BC_PERIODIC;
   if (h.storage == DUGKS_F64) {
-    if (NC == 8 || walls) step3h_launch<Q, NC, true>(d, h, parity, l, strips, tiles, grid, st);
-    else if constexpr (NC != 8) step3h_launch<Q, NC, false>(d, h, parity, l, strips, tiles, grid, st);
+    if (NC == 8 || walls) step3h_launch<Q, NC, true>(d, h, parity, ring, l, strips, tiles, grid, st);
+    else if constexpr (NC != 8) step3h_launch<Q, NC, false>(d, h, parity, ring, l, strips, tiles, grid, st);
   } else {
-    if (NC == 8 || walls) step3s_rows<Q, NC, true>(d, parity, l, strips, tiles, grid, st);
-    else if constexpr (NC != 8) step3s_rows<Q, NC, false>(d, parity, l, strips, tiles, grid, st);
+    if (NC == 8 || walls) step3s_rows<Q, NC, true>(d, parity, ring, l, strips, tiles, grid, st);
+    else if constexpr (NC != 8) step3s_rows<Q, NC, false>(d, parity, ring, l, strips, tiles, grid, st);
   }
 }
 
 template <int Q, int NC, int ROWS, typename T, bool WALLS>
-static void step3p_go(const Inst3* d, int parity, const Launch3& l, int strips, int tiles, dim3 grid,
+static void step3p_go(const Inst3* d, int parity, const double* ring, const Launch3& l, int strips, int tiles, dim3 grid,
                       hipStream_t st) {
   hipLaunchKernelGGL((k_step3p<Q, NC, ROWS, T, WALLS>), grid, dim3(64 * parts<Q, T, ROWS, WALLS>() * ROWS), 0, st, d,
-                     parity, l.planes, strips, tiles);
+                     parity, ring, l.planes, strips, tiles);
 }
 template <int Q, int NC, typename T, bool WALLS>
-static void step3p_launch(const Inst3* d, int parity, const Launch3& l, int strips, int tiles, dim3 grid,
+static void step3p_launch(const Inst3* d, int parity, const double* ring, const Launch3& l, int strips, int tiles, dim3 grid,
                           hipStream_t st) {
   if constexpr (sizeof(T) == 8) {   // rows 1 and 2 fit the LDS
-    if (l.rows == 1) step3p_go<Q, NC, 1, T, WALLS>(d, parity, l, strips, tiles, grid, st);
-    else step3p_go<Q, NC, 2, T, WALLS>(d, parity, l, strips, tiles, grid, st);
+    if (l.rows == 1) step3p_go<Q, NC, 1, T, WALLS>(d, parity, ring, l, strips, tiles, grid, st);
+    else step3p_go<Q, NC, 2, T, WALLS>(d, parity, ring, l, strips, tiles, grid, st);
   } else {
     switch (l.rows) {
-      case 2: step3p_go<Q, NC, 2, T, WALLS>(d, parity, l, strips, tiles, grid, st); break;
-      case 3: step3p_go<Q, NC, 3, T, WALLS>(d, parity, l, strips, tiles, grid, st); break;
-      default: step3p_go<Q, NC, 4, T, WALLS>(d, parity, l, strips, tiles, grid, st); break;
+      case 2: step3p_go<Q, NC, 2, T, WALLS>(d, parity, ring, l, strips, tiles, grid, st); break;
+      case 3: step3p_go<Q, NC, 3, T, WALLS>(d, parity, ring, l, strips, tiles, grid, st); break;
+      default: step3p_go<Q, NC, 4, T, WALLS>(d, parity, ring, l, strips, tiles, grid, st); break;
     }
   }
 }
 template <int Q, int NC, typename T>
-static void step3p_rows(const Inst3* d, const Inst3& h, int parity, const Launch3& l, int strips, int tiles,
+static void step3p_rows(const Inst3* d, const Inst3& h, int parity, const double* ring, const Launch3& l, int strips, int tiles,
                         dim3 grid, hipStream_t st) {
   const bool walls = h.bc[0] != DUGKS_BC_PERIODIC || h.bc[1] != DUGKS_BC_PERIODIC || h.bc[2] != DUGKS_BC_PERIODIC;
-  if (NC == 8 || walls) step3p_launch<Q, NC, T, true>(d, parity, l, strips, tiles, grid, st);
-  else if constexpr (NC != 8) step3p_launch<Q, NC, T, false>(d, parity, l, strips, tiles, grid, st);
+  if (NC == 8 || walls) step3p_launch<Q, NC, T, true>(d, parity, ring, l, strips, tiles, grid, st);
+  else if constexpr (NC != 8) step3p_launch<Q, NC, T, false>(d, parity, ring, l, strips, tiles, grid, st);
 }
 
 template <int Q>
-static int step3_q(const Inst3* d, const Inst3& h, int parity, const Launch3& l, void* stream) {
+static int step3_q(const Inst3* d, const Inst3& h, int parity, const double* ring, const Launch3& l, void* stream) {
   const int strips = (h.n[0] + kCols - 1) / kCols;
   const int tiles = (h.n[1] + l.rows - 1) / l.rows;
   const long long blocks = step3_blocks(h, l);
@@ -1514,32 +1556,34 @@ static int step3_q(const Inst3* d, const Inst3& h, int parity, const Launch3& l,
   if constexpr (Q != 7) {   // split directions
     if (h.storage == DUGKS_F64) {
       switch (nc) {
-        case 2: step3p_rows<Q, 2, double>(d, h, parity, l, strips, tiles, grid, S(stream)); break;
-        case 4: step3p_rows<Q, 4, double>(d, h, parity, l, strips, tiles, grid, S(stream)); break;
-        default: step3p_rows<Q, 8, double>(d, h, parity, l, strips, tiles, grid, S(stream)); break;
+        case 2: step3p_rows<Q, 2, double>(d, h, parity, ring, l, strips, tiles, grid, S(stream)); break;
+        case 4: step3p_rows<Q, 4, double>(d, h, parity, ring, l, strips, tiles, grid, S(stream)); break;
+        default: step3p_rows<Q, 8, double>(d, h, parity, ring, l, strips, tiles, grid, S(stream)); break;
       }
     } else {
       switch (nc) {
-        case 2: step3p_rows<Q, 2, float>(d, h, parity, l, strips, tiles, grid, S(stream)); break;
-        case 4: step3p_rows<Q, 4, float>(d, h, parity, l, strips, tiles, grid, S(stream)); break;
-        default: step3p_rows<Q, 8, float>(d, h, parity, l, strips, tiles, grid, S(stream)); break;
+        case 2: step3p_rows<Q, 2, float>(d, h, parity, ring, l, strips, tiles, grid, S(stream)); break;
+        case 4: step3p_rows<Q, 4, float>(d, h, parity, ring, l, strips, tiles, grid, S(stream)); break;
+        default: step3p_rows<Q, 8, float>(d, h, parity, ring, l, strips, tiles, grid, S(stream)); break;
       }
     }
   } else {   // D3Q7: a whole row per wave
     switch (nc) {
-      case 2: step3_row_waves<Q, 2>(d, h, parity, l, strips, tiles, grid, S(stream)); break;
-      case 4: step3_row_waves<Q, 4>(d, h, parity, l, strips, tiles, grid, S(stream)); break;
-      default: step3_row_waves<Q, 8>(d, h, parity, l, strips, tiles, grid, S(stream)); break;
+      case 2: step3_row_waves<Q, 2>(d, h, parity, ring, l, strips, tiles, grid, S(stream)); break;
+      case 4: step3_row_waves<Q, 4>(d, h, parity, ring, l, strips, tiles, grid, S(stream)); break;
+      default: step3_row_waves<Q, 8>(d, h, parity, ring, l, strips, tiles, grid, S(stream)); break;
     }
   }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_step3(const Inst3* d, const Inst3& h, int parity, const Launch3& l, void* stream) {
+int launch_step3(const Inst3* d, const Inst3& h, int parity, long long step, const Launch3& l, void* stream) {
+  // the step's Dirichlet data (no reads without a Dirichlet axis)
+  const double* ring = h.ring != nullptr ? h.ring + step * h.ring_len : nullptr;
   switch (h.q) {
-    case 19: return step3_q<19>(d, h, parity, l, stream);
-    case 15: return step3_q<15>(d, h, parity, l, stream);
-    default: return step3_q<7>(d, h, parity, l, stream);
+    case 19: return step3_q<19>(d, h, parity, ring, l, stream);
+    case 15: return step3_q<15>(d, h, parity, ring, l, stream);
+    default: return step3_q<7>(d, h, parity, ring, l, stream);
   }
 }
 

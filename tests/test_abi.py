@@ -167,7 +167,7 @@ def _create3(nx=8, ny=6, nz=5, q=19, **kw):
 
 @pytest.mark.parametrize("kw,code", [
     (dict(q=9), L.E_UNSUPPORTED), (dict(storage=L.F16NEQ), L.E_UNSUPPORTED),
-    (dict(bc=(1, 0, 0)), L.E_UNSUPPORTED), (dict(cfl=1.0), L.E_ARG), (dict(nz=0), L.E_ARG),
+    (dict(bc=(3, 0, 0)), L.E_ARG), (dict(cfl=1.0), L.E_ARG), (dict(nz=0), L.E_ARG),
     (dict(abi=99), L.E_ARG),
 ])
 def test_create3_rejects_bad_arguments(kw, code):
@@ -196,6 +196,19 @@ def test_3d_sizes_and_state_errors():
         for rows in good:
             assert lib.dugks3_set_launch(h, rows, 16) == L.OK
         lib.dugks3_destroy(h)
+
+
+def test_3d_dirichlet_data_arguments():
+    """Dirichlet walls are accepted; their data is checked (no device work)."""
+    lib = L.lib()
+    rc, h = _create3(bc=(1, 2, 0))
+    assert rc == L.OK
+    P = C.POINTER(C.c_double)
+    assert lib.dugks3_set_dirichlet(h, None, 3) == L.E_ARG
+    assert lib.dugks3_set_dirichlet(h, C.cast(C.c_void_p(256), P), -1) == L.E_ARG
+    assert lib.dugks3_set_dirichlet(h, None, 0) == L.OK
+    assert lib.dugks3_step(h, 1) == L.E_STATE        # not bound
+    lib.dugks3_destroy(h)
 
 
 def test_d3q7_accepts_only_identity_diffusion():

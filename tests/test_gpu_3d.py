@@ -52,6 +52,78 @@ def test_fp64_matches_oracle(nx, ny, nz, q, bc):
     assert abs(r["mass"] - o.mass()) <= 1e-12 * abs(o.mass())
 
 
+D = W.DIRICHLET
+DCASES = [
+    (1, 1, 1, 19, (D, D, D)), (5, 4, 3, 19, (D, D, D)), (62, 3, 4, 19, (D, P, M)),
+    (63, 5, 2, 19, (P, D, P)), (64, 2, 7, 15, (M, P, D)), (65, 4, 5, 15, (D, M, D)),
+    (130, 3, 3, 19, (D, D, P)), (17, 9, 11, 19, (P, P, D)), (9, 7, 6, 7, (D, M, P)),
+    (70, 6, 4, 7, (D, D, D)), (130, 67, 20, 19, (D, D, D)),
+]
+
+
+@pytest.mark.parametrize("launch", [(2, 3), (1, 2)])
+@pytest.mark.parametrize("nx,ny,nz,q,bc", DCASES)
+def test_fp64_dirichlet_walls_match_oracle(nx, ny, nz, q, bc, launch):
+    """Dirichlet walls (non-equilibrium extrapolation, data per step on the
+    ghost shell) alone and beside mirror and periodic axes: binary64 equals
+    the oracle to 1e-12, in tiles of 2 and 1 interior rows."""
+    p = W.random_problem3d(900 + nx + 3 * ny + 7 * nz, nx, ny, nz, q=q, bc=bc, stretched=True,
+                           bdeg=2, ddeg=2)
+    steps = 4
+    rings = p.rings(steps)
+    say(f"case 3d dirichlet f64 {nx}x{ny}x{nz} q={q} bc={bc} launch={launch}")
+    s = solver(p, "f64", launch)
+    s.set_phi(p.phi0)
+    s.set_dirichlet(rings)
+    s.step(steps)
+    o = Oracle3D(p, openmp=True)
+    o.step(steps, rings)
+    f, fo = s.get_f(), o.get_f()
+    assert np.abs(f - fo).max() <= 1e-12 * np.abs(fo).max()
+
+
+@pytest.mark.parametrize("q", [19, 15, 7])
+def test_fp32_dirichlet_walls(q):
+    """binary32 with Dirichlet walls: launch shapes bitwise the same, and the
+    oracle within 2 n eps32 (relative L2 of phi)."""
+    bc = (D, M, D) if q != 19 else (D, D, D)
+    p = W.random_problem3d(950 + q, 70, 9, 8, q=q, bc=bc, stretched=True, bdeg=2)
+    steps = 20
+    rings = p.rings(steps)
+    say(f"case 3d dirichlet f32 q={q} bc={bc}")
+    out = []
+    for launch in ((4, 32), (2, 1), (3, 7), (4, 3)):
+        s = solver(p, "f32", launch)
+        s.set_phi(p.phi0)
+        s.set_dirichlet(rings)
+        s.step(steps)
+        out.append(s.get_f())
+        if len(out) == 1:
+            phi = s.get_phi()
+    for f in out[1:]:
+        assert np.array_equal(f, out[0])
+    o = Oracle3D(p, openmp=True)
+    o.step(steps, rings)
+    ref = o.get_phi()
+    err = float(np.sqrt(((phi - ref) ** 2).sum() / (ref ** 2).sum()))
+    say(f"  rel-L2 {err:.2e} (bound {2 * steps * EPS32:.2e})")
+    assert err <= 2 * steps * EPS32
+
+
+def test_dirichlet_data_must_cover_every_step():
+    p = W.random_problem3d(960, 10, 6, 5, q=19, bc=(D, P, P))
+    s = solver(p, "f64")
+    s.set_phi(p.phi0)
+    with pytest.raises(dg.DugksError):
+        s.step(1)                      # no data yet
+    s.set_dirichlet(p.rings(3))
+    s.step(3)
+    with pytest.raises(dg.DugksError):
+        s.step(1)                      # past the data
+    s.set_phi(p.phi0)                  # the clock restarts at step 0
+    s.step(2)
+
+
 @pytest.mark.parametrize("launch", [(2, 1), (2, 5), (3, 2), (3, 7), (4, 1), (4, 3), (2, 32)])
 def test_launch_shapes_give_identical_results(launch):
     """Tiles of 2 to 4 rows and chunks of 1..32 planes: bitwise the same (binary32)."""
