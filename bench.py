@@ -234,22 +234,27 @@ def cpu_baseline(seconds, all_cores=True):
                       f"D = phi I), {steps} steps in {el:.1f} s, binary64, {threads} thread(s)"}
 
 
-def cpu_baseline3d(seconds):
-    """The 3-D oracle as it stands, single thread, on a 64^3 instance of the
-    Gaussian-hill recipe."""
+def cpu_baseline3d(seconds, all_cores=True):
+    """The 3-D oracle as it stands on a 64^3 instance of the Gaussian-hill
+    recipe: its OpenMP build on every core this process may use, or its serial
+    build on one."""
     from oracle import Oracle3D
+    from oracle import oracle3d as OR3
     from paper_1906_11036_amd import workloads as W
+    model, ncpu = host_cpu()
+    threads = OR3.threads(ncpu, openmp=True) if all_cores else 1
     p = W.gaussian_hill3d_problem(64, q=19, u=(0.05, 0.02, 0.01), D=1e-4, sigma0=0.15, images0=0)
-    o = Oracle3D(p)
+    o = Oracle3D(p, openmp=all_cores)
     o.step(1)
     steps, t0 = 0, time.perf_counter()
     while time.perf_counter() - t0 < seconds:
         o.step(1)
         steps += 1
     el = time.perf_counter() - t0
-    return {"value": p.cells * steps / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+    return {"value": round(p.cells * steps / el / 1e6, 3), "unit": "MLUPS", "cores": threads,
+            "kind": "oracle", "cpu_model": model, "nproc": ncpu,
             "sample": f"one 64^3 periodic D3Q19 Gaussian-hill instance, {steps} steps in {el:.1f} s, "
-                      f"binary64, 1 thread"}
+                      f"binary64, {threads} thread(s)"}
 
 
 BYTES_PER_UPDATE3 = {0: 2 * 19 * 8, 1: 2 * 19 * 4}   # D3Q19: read + write of the stored state
@@ -257,8 +262,8 @@ BYTES_PER_UPDATE1 = {0: 2 * 4 * 8, 1: 2 * 4 * 4}     # D1Q3: f~ (3) and phi^{n-1
 
 
 def cpu_baseline1d(seconds):
-    """The 1-D oracle as it stands, single thread, on 2^18 cells of the
-    Fokker-Planck workload recipe."""
+    """The 1-D oracle as it stands (a serial program: one thread) on 2^18 cells
+    of the Fokker-Planck workload recipe."""
     from oracle import Oracle1D
     from paper_1906_11036_amd import workloads as W
     p = W.fokker_planck_problem(1 << 18, t0=0.5, c=50.0, cfl=0.5)
@@ -269,7 +274,9 @@ def cpu_baseline1d(seconds):
         o.step(1)
         steps += 1
     el = time.perf_counter() - t0
-    return {"value": p.cells * steps / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+    model, ncpu = host_cpu()
+    return {"value": round(p.cells * steps / el / 1e6, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "cpu_model": model, "nproc": ncpu,
             "sample": f"one 2^18-cell D1Q3 instance of the Fokker-Planck recipe (Example 4.6, Dirichlet "
                       f"walls), {steps} steps in {el:.1f} s, binary64, 1 thread"}
 
@@ -422,6 +429,7 @@ def main3d(args):
     out.update(extras)
     if not args.no_extras:
         out["cpu_baseline"] = cpu_baseline3d(args.cpu_seconds)
+        out["cpu_baseline_1core"] = cpu_baseline3d(args.cpu_seconds, all_cores=False)
     print(json.dumps(out), flush=True)
 
 

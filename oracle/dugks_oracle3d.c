@@ -43,6 +43,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define O3_MAXQ 19
 #define O3_MAXDEG 4
@@ -219,6 +222,18 @@ Oracle3* or3_create(int nx, int ny, int nz, const double* xf, const double* yf, 
     o->b3 = h / (2.0 * L + h);
   }
   return o;
+}
+
+/* Threads of the OpenMP build: n > 0 sets them; returns the number a step
+ * uses (1 in the serial build). */
+int or3_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
 }
 
 void or3_destroy(Oracle3* o) {

@@ -39,6 +39,8 @@ def _lib(openmp: bool = False):
         lib.or3_time.argtypes = [C.c_void_p]
         lib.or3_step.argtypes = [C.c_void_p, C.c_int, _d]
         lib.or3_step_cells.argtypes = [C.c_void_p, C.c_int, _i, _d, _d]
+        lib.or3_threads.restype = C.c_int
+        lib.or3_threads.argtypes = [C.c_int]
         lib.or3_shell_len.restype = C.c_size_t
         lib.or3_shell_len.argtypes = [C.c_void_p]
         lib.or3_errors.argtypes = [C.c_void_p, _d, _d, _d]
@@ -46,6 +48,11 @@ def _lib(openmp: bool = False):
         lib.or3_mass.argtypes = [C.c_void_p]
         _LIBS[openmp] = lib
     return _LIBS[openmp]
+
+
+def threads(n: int = 0, openmp: bool = True) -> int:
+    """Threads of the 3-D oracle's OpenMP build (n > 0 sets them); the serial build uses 1."""
+    return int(_lib(openmp).or3_threads(int(n)))
 
 
 def _p(a):
