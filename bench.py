@@ -194,6 +194,13 @@ def plain_fp64_rate(problems, steps):
     return cells / (total_ms * 1e-3) / 1e6
 
 
+def device_info():
+    """GPU name and the HIP runtime version torch was built against."""
+    import torch
+    return {"gpu": torch.cuda.get_device_name(0), "hip": torch.version.hip,
+            "torch": torch.__version__}
+
+
 def host_cpu():
     """CPU model (as lscpu names it) and the cores this process may use."""
     model = "unknown"
@@ -346,6 +353,7 @@ def main1d(args):
     out.update(extras)
     if not args.no_extras:
         out["cpu_baseline"] = cpu_baseline1d(args.cpu_seconds)
+    out["device"] = device_info()
     print(json.dumps(out), flush=True)
 
 
@@ -430,6 +438,7 @@ def main3d(args):
     if not args.no_extras:
         out["cpu_baseline"] = cpu_baseline3d(args.cpu_seconds)
         out["cpu_baseline_1core"] = cpu_baseline3d(args.cpu_seconds, all_cores=False)
+    out["device"] = device_info()
     print(json.dumps(out), flush=True)
 
 
@@ -564,6 +573,7 @@ def main():
     if not args.no_extras:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, all_cores=True)
         out["cpu_baseline_1core"] = cpu_baseline(args.cpu_seconds, all_cores=False)
+    out["device"] = device_info()
     print(json.dumps(out), flush=True)
 
 

@@ -505,9 +505,9 @@ static void fbar_plus(const Oracle* o, int i, int j, const double* ring, double*
     return;
   }
   /* mirror walls */
-  memcpy(tmp, out, sizeof(tmp));
+  memcpy(tmp, out, sizeof(double) * (size_t)o->q);
   if (xwall) for (k = 0; k < o->q; ++k) out[k] = tmp[o->mirx[k]];
-  memcpy(tmp, out, sizeof(tmp));
+  memcpy(tmp, out, sizeof(double) * (size_t)o->q);
   if (ywall) for (k = 0; k < o->q; ++k) out[k] = tmp[o->miry[k]];
 }
 

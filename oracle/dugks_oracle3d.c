@@ -354,7 +354,7 @@ static void fbar_plus(const Oracle3* o, int i, int j, int k, const double* ring,
   for (a = 0; a < 3; ++a) {
     int wall = (idx[a] < 0 || idx[a] >= o->n[a]) && o->bc[a] == O3_MIRROR;
     if (!wall) continue;
-    memcpy(tmp, out, sizeof(tmp));
+    memcpy(tmp, out, sizeof(double) * (size_t)o->q);
     for (m = 0; m < o->q; ++m) out[m] = tmp[o->mir[a][m]];
   }
 }
