@@ -54,7 +54,8 @@
  *   MIRROR    zero-flux specular wall: fbar+_g,i = fbar+_a,m(i), m reverses
  *             the wall-normal velocity component.
  * Wall ghosts have the width of the adjacent interior cell; periodic ghosts
- * the width of the wrapped cell.  A DIRICHLET axis may not meet a MIRROR axis.
+ * the width of the wrapped cell.  Where a DIRICHLET axis meets a MIRROR axis, the
+ * corner ghost takes the DIRICHLET rule.
  * Initialisation (Sec. 4): f~ = E(phi).
  */
 #ifndef DUGKS_H

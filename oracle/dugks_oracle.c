@@ -54,7 +54,9 @@
  *                   interior cell (diagonal for corners), phi_g = boundary data
  *                   at the ghost centre at t_n, supplied by the caller;
  *       mirror    : specular zero-flux wall, fbar+_g,i = fbar+_a,m(i) with
- *                   m(i) the direction whose normal component is reversed.
+ *                   m(i) the direction whose normal component is reversed;
+ *       a corner where a Dirichlet axis meets a mirror axis takes the
+ *       Dirichlet rule (the paper gives no corner treatment).
  *     Wall ghosts take the width of the adjacent interior cell.
  *   - With a source: the moments of eq. 2.7 (sum F_i = F, sum R_i = 0) give
  *     phi = sum f~ + dt F / 2 in a cell and phi_b = sum fbar + h F / 2 at a
@@ -270,9 +272,6 @@ Oracle* or_create(int nx, int ny, const double* xf, const double* yf, int q, dou
   if (nx < 1 || ny < 1 || (q != 9 && q != 5) || !(c > 0) || !(cfl > 0) || !(alpha > 0))
     return NULL;
   if (bcx < 0 || bcx > 2 || bcy < 0 || bcy > 2) return NULL;
-  /* a Dirichlet wall meeting a mirror wall has no defined corner rule */
-  if ((bcx == OR_DIRICHLET && bcy == OR_MIRROR) || (bcx == OR_MIRROR && bcy == OR_DIRICHLET))
-    return NULL;
   o = (Oracle*)calloc(1, sizeof(Oracle));
   o->nx = nx; o->ny = ny; o->q = q; o->c = c; o->cfl = cfl; o->alpha = alpha;
   o->bcx = bcx; o->bcy = bcy;

@@ -117,12 +117,6 @@ static int validate_params(const dugks_params* p, std::string& err) {
     err = "both sides of an axis must have the same boundary kind";
     return DUGKS_E_UNSUPPORTED;
   }
-  const int bx = p->bc[0], by = p->bc[2];
-  if ((bx == DUGKS_BC_DIRICHLET && by == DUGKS_BC_MIRROR) ||
-      (bx == DUGKS_BC_MIRROR && by == DUGKS_BC_DIRICHLET)) {
-    err = "a Dirichlet axis may not meet a mirror axis";
-    return DUGKS_E_UNSUPPORTED;
-  }
   if (p->storage < DUGKS_F64 || p->storage > DUGKS_BF16NEQ) {
     err = "unknown storage";
     return DUGKS_E_UNSUPPORTED;

@@ -64,7 +64,7 @@ def _create(nx=8, ny=6, q=9, xf=None, yf=None, **kw):
     (dict(cfl=1.0), L.E_ARG), (dict(cfl=0.0), L.E_ARG), (dict(alpha=0.0), L.E_ARG),
     (dict(c=-1.0), L.E_ARG), (dict(nx=0), L.E_ARG), (dict(q=7), L.E_UNSUPPORTED),
     (dict(storage=9), L.E_UNSUPPORTED), (dict(bc=(0, 1, 0, 0)), L.E_UNSUPPORTED),
-    (dict(bc=(1, 1, 2, 2)), L.E_UNSUPPORTED), (dict(kernel=L.KERNEL_PLAIN, storage=L.F32), L.E_UNSUPPORTED),
+    (dict(bc=(1, 2, 0, 0)), L.E_UNSUPPORTED),   # two kinds on one axis (dict(kernel=L.KERNEL_PLAIN, storage=L.F32), L.E_UNSUPPORTED),
     (dict(xf=[0, 0.5, 0.4, 1.0], nx=3), L.E_ARG),
 ])
 def test_create_rejects_bad_arguments(kw, code):
@@ -147,6 +147,13 @@ def test_source_is_refused_where_it_is_not_built():
         assert "source" in lib.dugks_last_error(h).decode()
         assert lib.dugks_set_source(h, None, 0.0) == L.OK
         lib.dugks_destroy(h)
+
+
+def test_dirichlet_axis_beside_mirror_axis_is_accepted():
+    for bc in ((1, 1, 2, 2), (2, 2, 1, 1)):
+        rc, h = _create(bc=bc)
+        assert rc == L.OK, L.lib().dugks_last_error(h).decode()
+        L.lib().dugks_destroy(h)
 
 
 def _create3(nx=8, ny=6, nz=5, q=19, **kw):

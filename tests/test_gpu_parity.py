@@ -68,7 +68,8 @@ def test_fp64_fused_random_problems(nx, ny, bc):
 
 @pytest.mark.parametrize("q", [9, 5])
 @pytest.mark.parametrize("bcx,bcy", [(W.PERIODIC, W.DIRICHLET), (W.DIRICHLET, W.PERIODIC),
-                                     (W.PERIODIC, W.MIRROR), (W.MIRROR, W.PERIODIC)])
+                                     (W.PERIODIC, W.MIRROR), (W.MIRROR, W.PERIODIC),
+                                     (W.DIRICHLET, W.MIRROR), (W.MIRROR, W.DIRICHLET)])
 def test_fp64_mixed_axes_and_d2q5(q, bcx, bcy):
     p = W.random_problem(7 + q + 3 * bcx + bcy, 70, 23, q=q, bcx=bcx, bcy=bcy, stretched=True,
                          bdeg=3, ddeg=1)

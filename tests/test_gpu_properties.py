@@ -38,10 +38,6 @@ def test_2d_fp64_random(seed, nx, ny, q, bcx, bcy, stretched, bdeg, ddeg, rows, 
     if (bcx != W.PERIODIC and nx < 2) or (bcy != W.PERIODIC and ny < 2):
         return   # walls need two cells per axis for distinct ghosts
     p = W.random_problem(seed, nx, ny, q=q, bcx=bcx, bcy=bcy, stretched=stretched, bdeg=bdeg, ddeg=ddeg)
-    if {bcx, bcy} == {W.DIRICHLET, W.MIRROR}:   # no corner rule: the library refuses, as the oracle does
-        with pytest.raises(dg.DugksError):
-            dg.Solver(p, storage="f64")
-        return
     say(f"case 2d seed={seed} {nx}x{ny} q={q} bc=({bcx},{bcy}) stretched={stretched} "
         f"deg=({bdeg},{ddeg}) launch=({rows},{wpb},{sched}) steps={steps}")
     s = dg.Solver(p, storage="f64", launch=(rows, wpb, sched, 1))
@@ -57,7 +53,8 @@ def test_2d_fp64_random(seed, nx, ny, q, bcx, bcy, stretched, bdeg, ddeg, rows, 
 
 @PROPS
 @given(seed=st.integers(0, 10**6), nx=st.integers(1, 130), ny=st.integers(1, 12), nz=st.integers(1, 10),
-       q=st.sampled_from([19, 15, 7]), bc=st.tuples(*[st.sampled_from([W.PERIODIC, W.MIRROR])] * 3),
+       q=st.sampled_from([19, 15, 7]),
+       bc=st.tuples(*[st.sampled_from([W.PERIODIC, W.MIRROR, W.DIRICHLET])] * 3),
        stretched=st.booleans(), bdeg=st.integers(1, 4), rows=st.sampled_from([1, 2]),
        planes=st.integers(1, 16), steps=st.integers(1, 3))
 def test_3d_fp64_random(seed, nx, ny, nz, q, bc, stretched, bdeg, rows, planes, steps):
@@ -67,9 +64,12 @@ def test_3d_fp64_random(seed, nx, ny, nz, q, bc, stretched, bdeg, rows, planes, 
     s = dg.Solver3D(p, storage="f64")
     s.set_launch(rows, planes)
     s.set_phi(p.phi0)
+    rings = p.rings(steps)
+    if rings is not None:
+        s.set_dirichlet(rings)
     s.step(steps)
     o = Oracle3D(p)
-    o.step(steps)
+    o.step(steps, rings)
     assert rel_max(s.get_f(), o.get_f()) <= TOL64
 
 
@@ -91,7 +91,8 @@ def test_1d_fp64_random(seed, n, bc, stretched, steps):
 @settings(max_examples=25, derandomize=True, database=None, deadline=None,
           suppress_health_check=[HealthCheck.too_slow])
 @given(seed=st.integers(0, 10**6), nx=st.integers(1, 130), ny=st.integers(1, 14), nz=st.integers(1, 10),
-       q=st.sampled_from([19, 15, 7]), bc=st.tuples(*[st.sampled_from([W.PERIODIC, W.MIRROR])] * 3),
+       q=st.sampled_from([19, 15, 7]),
+       bc=st.tuples(*[st.sampled_from([W.PERIODIC, W.MIRROR, W.DIRICHLET])] * 3),
        bdeg=st.integers(1, 4), rows=st.tuples(st.integers(2, 4), st.integers(2, 4)),
        planes=st.tuples(st.integers(1, 16), st.integers(1, 16)), steps=st.integers(1, 3))
 def test_3d_fp32_launch_shapes_bitwise(seed, nx, ny, nz, q, bc, bdeg, rows, planes, steps):
@@ -104,6 +105,8 @@ def test_3d_fp32_launch_shapes_bitwise(seed, nx, ny, nz, q, bc, bdeg, rows, plan
         s = dg.Solver3D(p, storage="f32")
         s.set_launch(r, pl)
         s.set_phi(p.phi0)
+        if p.rings(1) is not None:
+            s.set_dirichlet(p.rings(steps))
         s.step(steps)
         out.append(s.get_f())
         s.close()

@@ -247,13 +247,18 @@ def test_sampled_step_equals_full_step(bc):
 
 @pytest.mark.parametrize("q", [19, 15, 7])
 @pytest.mark.parametrize("stretched", [False, True])
-def test_linear_steady_state_between_dirichlet_walls(q, stretched):
-    """B = 0, D = phi I, phi = x + 2y - z with Dirichlet walls on every axis
-    (data: the same linear function at the ghost centres): phi stays linear."""
+@pytest.mark.parametrize("bc", [(W.DIRICHLET,) * 3, (W.DIRICHLET, W.MIRROR, W.MIRROR),
+                                (W.MIRROR, W.DIRICHLET, W.PERIODIC)])
+def test_linear_steady_state_between_dirichlet_walls(q, stretched, bc):
+    """B = 0, D = phi I, phi linear along the Dirichlet axes (x + 2y - z with
+    Dirichlet walls on every axis; along the Dirichlet axis only beside mirror
+    and periodic axes, corners where the kinds meet included; data: the same
+    function at the ghost centres): phi stays linear."""
     faces = [W.tanh_faces(n, 1.3) if stretched else W.uniform_faces(n, 0.0, 1.0) for n in (9, 8, 7)]
-    lin = lambda x, y, z, t: np.asarray(x) + 2.0 * np.asarray(y) - np.asarray(z)
+    k = [(1.0, 2.0, -1.0)[a] if bc[a] == W.DIRICHLET else 0.0 for a in range(3)]
+    lin = lambda x, y, z, t: 0.2 + k[0] * np.asarray(x) + k[1] * np.asarray(y) + k[2] * np.asarray(z)
     p = W.Problem3D(name="linear", xf=faces[0], yf=faces[1], zf=faces[2], q=q, c=1.1, cfl=0.5,
-                    alpha=0.01, bc=(W.DIRICHLET,) * 3, exact=lin)
+                    alpha=0.01, bc=bc, exact=lin)
     X, Y, Z = p.mesh()
     p.phi0 = lin(X, Y, Z, 0.0)
     o = Oracle3D(p)

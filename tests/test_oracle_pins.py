@@ -358,6 +358,25 @@ def test_linear_steady_state_dirichlet(stretched):
         assert np.abs(o.get_phi() - (X + Y)).max() <= 1e-12
 
 
+@pytest.mark.parametrize("bcx,bcy", [(W.DIRICHLET, W.MIRROR), (W.MIRROR, W.DIRICHLET)])
+@pytest.mark.parametrize("stretched", [False, True])
+def test_linear_steady_state_dirichlet_beside_mirror(bcx, bcy, stretched):
+    """B = 0, D = phi I, phi linear along the Dirichlet axis between zero-flux
+    mirror walls (no gradient across them): phi stays exactly linear, corners
+    (where the two kinds meet) included."""
+    xf = W.tanh_faces(18, 1.4) if stretched else W.uniform_faces(18, 0.0, 1.0)
+    yf = W.tanh_faces(14, 1.1) if stretched else W.uniform_faces(14, 0.0, 1.0)
+    o = Oracle(xf=xf, yf=yf, c=1.0, cfl=0.5, alpha=0.01, bcx=bcx, bcy=bcy)
+    X, Y = np.meshgrid(W.centres(xf), W.centres(yf))
+    lin = 2.0 * X + 0.3 if bcx == W.DIRICHLET else 0.3 - 1.5 * Y
+    o.set_phi(lin)
+    xs, ys = W.ring_points(xf, yf, bcx, bcy)
+    ring = (2.0 * xs + 0.3 if bcx == W.DIRICHLET else 0.3 - 1.5 * ys)[None]
+    for _ in range(50):
+        o.step(1, ring)
+        assert np.abs(o.get_phi() - lin).max() <= 1e-12
+
+
 # ------------------------------------------------------- internal checks
 
 def test_sampled_step_equals_full_step():
