@@ -35,6 +35,16 @@
  *     a the nearest interior cell (clamped per axis) and phi_g the caller's
  *     boundary value at the ghost centre at t_n (the two-dimensional rule,
  *     per axis); otherwise each mirror axis reflects in turn.
+ *   - sources F(x, t, phi) = sum_j exp(gamma_j t) phi^k_j G_j(x) (k_j <= 3,
+ *     at most 8 terms), the two-dimensional treatment per axis: F_i = w_i F
+ *     and R_i = w_i c_i.B'(phi) F / c_s^2 (eq. 2.3, Remark 3), f~ and fbar
+ *     shifted by the sources (eqs. 2.25, 2.27); the conserved value solves
+ *     phi = sum f~ + dt F(phi) / 2 in a cell at t_n and phi_b = sum fbar +
+ *     h F(phi_b) / 2 at a face at t_n + h, each G_j interpolated linearly
+ *     between the two centres; Newton's method from the explicit sum when F
+ *     depends on phi (update <= 1e-15 (1 + |phi|), at most 60 updates);
+ *     f~ = E(phi0) - dt S(phi0) / 2 at t = 0; a ghost takes the G_j of the
+ *     cell its fbar+ comes from.
  *   - boundary values of one step: the shell in the order z = -1 plane and
  *     z = nz plane (each [ny+2][nx+2], j and i from -1), then the y = -1 and
  *     y = ny slabs (each [nz][nx+2]), then the x = -1 and x = nx columns (each
@@ -49,6 +59,8 @@
 
 #define O3_MAXQ 19
 #define O3_MAXDEG 4
+#define O3_MAXTERMS 8
+#define O3_MAXPOW 3
 
 enum { O3_PERIODIC = 0, O3_DIRICHLET = 1, O3_MIRROR = 2 };
 
@@ -80,6 +92,10 @@ typedef struct {
   double* f;              /* f~ [q][nz][ny][nx] */
   long step;
   double t;
+  int src_n, src_implicit;       /* source terms (0: none); some term depends on phi */
+  double* src_g;                 /* G_j [src_n][nz][ny][nx] */
+  int src_pow[O3_MAXTERMS];
+  double src_gam[O3_MAXTERMS];
 } Oracle3;
 
 /* ------------------------------------------------------------ lattice */
@@ -241,6 +257,7 @@ void or3_destroy(Oracle3* o) {
   if (!o) return;
   for (a = 0; a < 3; ++a) { free(o->fc[a]); free(o->wd[a]); free(o->cc[a]); }
   free(o->f);
+  free(o->src_g);
   free(o);
 }
 
@@ -284,14 +301,111 @@ static size_t cidx(const Oracle3* o, int i, int j, int k) {
   return ((size_t)k * o->n[1] + j) * o->n[0] + i;
 }
 
-/* Initialisation (Sec. 4): f~ = E(phi) with point values at the centres. */
+/* ------------------------------------------------------------ sources */
+
+/* n terms: G_j (g, [n][nz][ny][nx], copied), powers k_j in 0..3 and growth
+ * rates gamma_j; n = 0 removes the source.  Returns -1 on a bad argument. */
+int or3_set_source_terms(Oracle3* o, int n, const double* g, const int* pw, const double* gam) {
+  const size_t N = ncells(o);
+  int j;
+  if (n < 0 || n > O3_MAXTERMS || (n > 0 && (!g || !pw || !gam))) return -1;
+  for (j = 0; j < n; ++j)
+    if (pw[j] < 0 || pw[j] > O3_MAXPOW) return -1;
+  free(o->src_g);
+  o->src_g = NULL;
+  o->src_n = n;
+  o->src_implicit = 0;
+  if (n == 0) return 0;
+  o->src_g = (double*)malloc(sizeof(double) * N * n);
+  memcpy(o->src_g, g, sizeof(double) * N * n);
+  for (j = 0; j < n; ++j) {
+    o->src_pow[j] = pw[j];
+    o->src_gam[j] = gam[j];
+    if (pw[j] > 0) o->src_implicit = 1;
+  }
+  return 0;
+}
+
+/* S_i = F_i + R_i for a source value F at phi: F_i = w_i F (eq. 2.3),
+ * R_i = w_i c_i.B'(phi) F / c_s^2 (Remark 3, C = int B'B'^T) */
+static void source_dist(const Oracle3* o, double phi, double F, double* S) {
+  double bp[3] = {0.0, 0.0, 0.0}, p = 1.0;
+  int a, k, i;
+  for (k = 1; k <= o->bdeg; ++k) {
+    for (a = 0; a < 3; ++a) bp[a] += (double)k * o->b[a][k] * p;
+    p *= phi;
+  }
+  for (i = 0; i < o->q; ++i) {
+    double cb = 0.0;
+    for (a = 0; a < 3; ++a) cb += o->cv[i][a] * bp[a];
+    S[i] = o->w[i] * F + o->w[i] * cb * F / o->cs2;
+  }
+}
+
+/* coefficients a_k of F = sum_k a_k phi^k at time t, G_j = (1 - r) G_j(cL) +
+ * r G_j(cR) (r = 0: the centre of cell cL) */
+static void source_coefs(const Oracle3* o, size_t cL, size_t cR, double r, double t, double* a) {
+  const size_t N = ncells(o);
+  int j, k;
+  for (k = 0; k <= O3_MAXPOW; ++k) a[k] = 0.0;
+  for (j = 0; j < o->src_n; ++j) {
+    double gL = o->src_g[(size_t)j * N + cL], gR = o->src_g[(size_t)j * N + cR];
+    a[o->src_pow[j]] += exp(o->src_gam[j] * t) * (gL + r * (gR - gL));
+  }
+}
+
+static double poly3(const double* a, double phi) {
+  return a[0] + phi * (a[1] + phi * (a[2] + phi * a[3]));
+}
+
+/* phi with phi - tau F(phi) / 2 = s (tau = dt in a cell, eq. 2.25; tau = h at
+ * a face, eq. 2.27): explicit when F does not depend on phi, else Newton's
+ * method from phi = s */
+static double solve_conserved(const Oracle3* o, double s, double tau, const double* a) {
+  double phi = s;
+  int it;
+  if (!o->src_implicit) return s + 0.5 * tau * a[0];
+  for (it = 0; it < 60; ++it) {
+    double F = poly3(a, phi);
+    double dF = a[1] + phi * (2.0 * a[2] + phi * 3.0 * a[3]);
+    double d = (phi - 0.5 * tau * F - s) / (1.0 - 0.5 * tau * dF);
+    phi -= d;
+    if (fabs(d) <= 1e-15 * (1.0 + fabs(phi))) break;
+  }
+  return phi;
+}
+
+/* phi of interior cell c at the current time (Sec. 2: sum f~; with a source
+ * the root of phi = sum f~ + dt F(phi) / 2) and F there (F may be NULL) */
+static double cell_phi_F(const Oracle3* o, size_t c, double* F) {
+  const size_t N = ncells(o);
+  double s = 0.0, a[O3_MAXPOW + 1], phi;
+  int m;
+  for (m = 0; m < o->q; ++m) s += o->f[m * N + c];
+  if (!o->src_n) {
+    if (F) *F = 0.0;
+    return s;
+  }
+  source_coefs(o, c, c, 0.0, o->t, a);
+  phi = solve_conserved(o, s, o->dt, a);
+  if (F) *F = poly3(a, phi);
+  return phi;
+}
+
+/* Initialisation (Sec. 4): f~ = E(phi) with point values at the centres; with
+ * a source f = E at t = 0 (Omega = 0), so f~ = E - dt S / 2 (eq. 2.25). */
 void or3_set_phi(Oracle3* o, const double* phi) {
   size_t c, N = ncells(o);
   int k;
-  double E[O3_MAXQ];
+  double E[O3_MAXQ], S[O3_MAXQ], a[O3_MAXPOW + 1];
   for (c = 0; c < N; ++c) {
     feq(o, phi[c], E);
     for (k = 0; k < o->q; ++k) o->f[k * N + c] = E[k];
+    if (o->src_n) {
+      source_coefs(o, c, c, 0.0, 0.0, a);
+      source_dist(o, phi[c], poly3(a, phi[c]), S);
+      for (k = 0; k < o->q; ++k) o->f[k * N + c] = E[k] - 0.5 * o->dt * S[k];
+    }
   }
   o->step = 0; o->t = 0.0;
 }
@@ -300,15 +414,10 @@ void or3_set_f(Oracle3* o, const double* f) { memcpy(o->f, f, sizeof(double) * o
 void or3_get_f(const Oracle3* o, double* f) { memcpy(f, o->f, sizeof(double) * o->q * ncells(o)); }
 double or3_time(const Oracle3* o) { return o->t; }
 
-/* phi = sum_i f~_i (Sec. 2, after eq. 2.13) */
+/* phi = sum_i f~_i (Sec. 2, after eq. 2.13; with a source, cell_phi_F) */
 void or3_get_phi(const Oracle3* o, double* phi) {
   size_t c, N = ncells(o);
-  int k;
-  for (c = 0; c < N; ++c) {
-    double s = 0.0;
-    for (k = 0; k < o->q; ++k) s += o->f[k * N + c];
-    phi[c] = s;
-  }
+  for (c = 0; c < N; ++c) phi[c] = cell_phi_F(o, c, NULL);
 }
 
 /* ------------------------------------------------------------ step */
@@ -339,9 +448,25 @@ static void fbar_plus(const Oracle3* o, int i, int j, int k, const double* ring,
   double ft[O3_MAXQ], E[O3_MAXQ], phi = 0.0, tmp[O3_MAXQ];
   for (a = 0; a < 3; ++a) s[a] = wrap_or_clamp(idx[a], o->n[a], o->bc[a]);
   c = cidx(o, s[0], s[1], s[2]);
-  for (m = 0; m < o->q; ++m) { ft[m] = o->f[m * N + c]; phi += ft[m]; }
-  feq(o, phi, E);
-  for (m = 0; m < o->q; ++m) out[m] = o->a1 * ft[m] + o->b1 * E[m];
+  for (m = 0; m < o->q; ++m) ft[m] = o->f[m * N + c];
+  if (!o->src_n) {
+    for (m = 0; m < o->q; ++m) phi += ft[m];
+    feq(o, phi, E);
+    for (m = 0; m < o->q; ++m) out[m] = o->a1 * ft[m] + o->b1 * E[m];
+  } else {
+    double S[O3_MAXQ], L = o->lambda, dt = o->dt, h = o->h, F;
+    phi = cell_phi_F(o, c, &F);
+    feq(o, phi, E);
+    source_dist(o, phi, F, S);
+    for (m = 0; m < o->q; ++m) {
+      /* f~ = f - dt/2 Omega - dt/2 S with Omega = -(f - E)/lambda, solved for f */
+      double f = (2.0 * L * ft[m] + dt * E[m] + L * dt * S[m]) / (2.0 * L + dt);
+      /* fbar = f - h/2 Omega - h/2 S (eq. 2.27, first line), then fbar+ (second line) */
+      double fb = f + h / (2.0 * L) * (f - E[m]) - 0.5 * h * S[m];
+      out[m] = (2.0 * L - h) / (2.0 * L + h) * fb + 2.0 * h / (2.0 * L + h) * E[m] +
+               2.0 * L * h / (2.0 * L + h) * S[m];
+    }
+  }
   for (a = 0; a < 3; ++a)
     if ((idx[a] < 0 || idx[a] >= o->n[a]) && o->bc[a] == O3_DIRICHLET) dir = 1;
   if (dir) {
@@ -359,14 +484,19 @@ static void fbar_plus(const Oracle3* o, int i, int j, int k, const double* ring,
   }
 }
 
-/* f~+ = a2 f~ + b2 E(phi) (eq. 2.13) at interior cell c */
+/* f~+ = a2 f~ + b2 E(phi) (eq. 2.13) at interior cell c; with a source the
+ * second line of eq. 2.25 adds 2 lambda dt / (2 lambda + dt) S */
 static void ftilde_plus(const Oracle3* o, size_t c, double* out) {
   size_t N = ncells(o);
-  double ft[O3_MAXQ], E[O3_MAXQ], phi = 0.0;
+  double ft[O3_MAXQ], E[O3_MAXQ], S[O3_MAXQ], phi, F;
   int m;
-  for (m = 0; m < o->q; ++m) { ft[m] = o->f[m * N + c]; phi += ft[m]; }
+  for (m = 0; m < o->q; ++m) ft[m] = o->f[m * N + c];
+  phi = cell_phi_F(o, c, &F);
   feq(o, phi, E);
   for (m = 0; m < o->q; ++m) out[m] = o->a2 * ft[m] + o->b2 * E[m];
+  if (!o->src_n) return;
+  source_dist(o, phi, F, S);
+  for (m = 0; m < o->q; ++m) out[m] += 2.0 * o->lambda * o->dt / (2.0 * o->lambda + o->dt) * S[m];
 }
 
 /* Access to fbar+ of the ghost shell through a callback so that the full
@@ -416,8 +546,27 @@ static void face_flux(const Oracle3* o, GetG G, const void* ctx, int a, int i, i
     fb[m] = v - o->h * shift;
   }
   for (m = 0; m < o->q; ++m) phib += fb[m];
-  feq(o, phib, E);
-  for (m = 0; m < o->q; ++m) flux[m] = o->cv[m][a] * (o->a3 * fb[m] + o->b3 * E[m]);
+  if (!o->src_n) {
+    feq(o, phib, E);
+    for (m = 0; m < o->q; ++m) flux[m] = o->cv[m][a] * (o->a3 * fb[m] + o->b3 * E[m]);
+  } else {
+    /* F at the face at t_n + h (where fbar lives, eq. 2.27), each G_j
+       interpolated linearly between the centres (a ghost takes its source
+       cell's); phi_b = sum fbar + h F_b / 2; f from the first line of eq. 2.27 */
+    double S[O3_MAXQ], Lm = o->lambda, h = o->h, ac[O3_MAXPOW + 1], Fb;
+    int sl[3], sr[3], b2;
+    for (b2 = 0; b2 < 3; ++b2) {
+      sl[b2] = wrap_or_clamp(L[b2], o->n[b2], o->bc[b2]);
+      sr[b2] = wrap_or_clamp(R[b2], o->n[b2], o->bc[b2]);
+    }
+    source_coefs(o, cidx(o, sl[0], sl[1], sl[2]), cidx(o, sr[0], sr[1], sr[2]), wl / dn, o->t + h, ac);
+    phib = solve_conserved(o, phib, h, ac);
+    Fb = poly3(ac, phib);
+    feq(o, phib, E);
+    source_dist(o, phib, Fb, S);
+    for (m = 0; m < o->q; ++m)
+      flux[m] = o->cv[m][a] * (2.0 * Lm * fb[m] + h * E[m] + Lm * h * S[m]) / (2.0 * Lm + h);
+  }
 }
 
 /* eq. 2.24 on a Cartesian cell: the surface integral of eq. 2.9 with the
@@ -521,15 +670,13 @@ void or3_step_cells(const Oracle3* o, int ncells_, const int* cells, const doubl
 
 /* GRE (eq. 4.1, unweighted) and area-weighted relative L2 against phi_a */
 void or3_errors(const Oracle3* o, const double* phi_a, double* gre, double* rel_l2) {
-  int i, j, k, m;
-  size_t N = ncells(o);
+  int i, j, k;
   double num = 0.0, den = 0.0, e2 = 0.0, r2 = 0.0;
   for (k = 0; k < o->n[2]; ++k)
     for (j = 0; j < o->n[1]; ++j)
       for (i = 0; i < o->n[0]; ++i) {
         size_t c = cidx(o, i, j, k);
-        double phi = 0.0, v = WD(o, 0, i) * WD(o, 1, j) * WD(o, 2, k);
-        for (m = 0; m < o->q; ++m) phi += o->f[m * N + c];
+        double phi = cell_phi_F(o, c, NULL), v = WD(o, 0, i) * WD(o, 1, j) * WD(o, 2, k);
         num += fabs(phi_a[c] - phi);
         den += fabs(phi_a[c]);
         e2 += v * (phi - phi_a[c]) * (phi - phi_a[c]);
@@ -540,16 +687,13 @@ void or3_errors(const Oracle3* o, const double* phi_a, double* gre, double* rel_
 }
 
 double or3_mass(const Oracle3* o) {
-  int i, j, k, m;
-  size_t N = ncells(o);
+  int i, j, k;
   double s = 0.0;
   for (k = 0; k < o->n[2]; ++k)
     for (j = 0; j < o->n[1]; ++j)
       for (i = 0; i < o->n[0]; ++i) {
         size_t c = cidx(o, i, j, k);
-        double phi = 0.0;
-        for (m = 0; m < o->q; ++m) phi += o->f[m * N + c];
-        s += phi * WD(o, 0, i) * WD(o, 1, j) * WD(o, 2, k);
+        s += cell_phi_F(o, c, NULL) * WD(o, 0, i) * WD(o, 1, j) * WD(o, 2, k);
       }
   return s;
 }

@@ -39,6 +39,7 @@ def _lib(openmp: bool = False):
         lib.or3_time.argtypes = [C.c_void_p]
         lib.or3_step.argtypes = [C.c_void_p, C.c_int, _d]
         lib.or3_step_cells.argtypes = [C.c_void_p, C.c_int, _i, _d, _d]
+        lib.or3_set_source_terms.argtypes = [C.c_void_p, C.c_int, _d, _i, _d]
         lib.or3_threads.restype = C.c_int
         lib.or3_threads.argtypes = [C.c_int]
         lib.or3_shell_len.restype = C.c_size_t
@@ -95,6 +96,9 @@ class Oracle3D:
         d = np.concatenate([_pad(v, deg + 1) for v in problem.d])
         if self.lib.or3_set_D(self.h, deg, _p(d)) != 0:
             raise ValueError("D degree out of range")
+        terms = getattr(problem, "src_terms", None)
+        if terms:
+            self.set_source_terms(terms)
         if problem.phi0 is not None:
             self.set_phi(problem.phi0)
 
@@ -140,6 +144,19 @@ class Oracle3D:
         out = np.zeros((self.nz, self.ny, self.nx))
         self.lib.or3_get_phi(self.h, _p(out))
         return out
+
+    def set_source_terms(self, terms):
+        """F(x, t, phi) = sum_j exp(gamma_j t) phi^k_j G_j(x): terms as (k_j,
+        gamma_j, G_j [nz][ny][nx]); an empty list removes the source.  Call
+        before set_phi (the initial state depends on the source)."""
+        n = len(terms)
+        g = _f64(np.stack([np.asarray(G, dtype=np.float64).reshape(self.nz, self.ny, self.nx)
+                           for _, _, G in terms])) if n else np.zeros(1)
+        pw = np.ascontiguousarray([int(k) for k, _, _ in terms] or [0], dtype=np.int32)
+        gm = _f64([float(gam) for _, gam, _ in terms] or [0.0])
+        self._src = g
+        if self.lib.or3_set_source_terms(self.h, n, _p(g), pw.ctypes.data_as(_i), _p(gm)) != 0:
+            raise ValueError("bad source terms")
 
     def shell_len(self) -> int:
         """Boundary values of one step (the ghost shell, Dirichlet walls)."""

@@ -472,6 +472,19 @@ def random_source_terms(seed: int, p: Problem, nterms: int = 4, amp: float = 0.5
     return out
 
 
+def random_source_terms3d(seed: int, p: "Problem3D", nterms: int = 4, amp: float = 0.5):
+    """Seeded smooth 3-D source terms (k, gamma, G [nz][ny][nx]) with powers 0..3."""
+    rng = np.random.default_rng(seed)
+    X, Y, Z = p.mesh()
+    out = []
+    for j in range(nterms):
+        kx, ky, kz = rng.integers(0, 3, size=3)
+        ph = rng.uniform(0, 2 * math.pi, size=3)
+        g = amp * np.cos(math.pi * kx * X + ph[0]) * np.cos(math.pi * ky * Y + ph[1]) * np.cos(math.pi * kz * Z + ph[2])
+        out.append((j % 4, float(rng.uniform(-1.0, 1.0)), g + float(rng.uniform(-0.2, 0.2))))
+    return out
+
+
 def random_source(seed: int, p: Problem, amp: float = 0.5):
     """A smooth seeded source shape G [ny][nx] and rate gamma for property tests."""
     rng = np.random.default_rng(seed)
@@ -548,6 +561,7 @@ class Problem3D:
     steps: int = 1
     exact: Optional[Callable] = None         # (x, y, z, t) -> phi
     seed: Optional[int] = None
+    src_terms: Optional[list] = None         # source F = sum exp(g t) phi^k G: (k, g, G [nz][ny][nx])
 
     @property
     def nx(self) -> int:

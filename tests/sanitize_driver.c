@@ -27,6 +27,7 @@ int or3_set_D(void* o, int deg, const double* d);
 void or3_set_phi(void* o, const double* phi);
 void or3_get_phi(const void* o, double* phi);
 size_t or3_shell_len(const void* o);
+int or3_set_source_terms(void* o, int n, const double* g, const int* pow, const double* gam);
 void or3_step(void* o, int nsteps, const double* rings);
 void or3_step_cells(const void* o, int ncells, const int* cells, const double* ring, double* out);
 
@@ -85,7 +86,7 @@ static void two_d(int q, int bc, int src) {
   free(xf); free(yf); free(phi); free(ring); free(g); free(gp);
 }
 
-static void three_d(int q, int bx_, int by_, int bz_) {
+static void three_d(int q, int bx_, int by_, int bz_, int src) {
   const int nx = 6, ny = 5, nz = 4, steps = 2, n = nx * ny * nz;
   double *xf = faces(nx, 1), *yf = faces(ny, 0), *zf = faces(nz, 1);
   double b[9] = {0.0, 0.1, 0.05, 0.0, -0.1, 0.0, 0.0, 0.05, 0.1};
@@ -99,6 +100,14 @@ static void three_d(int q, int bx_, int by_, int bz_) {
   or3_set_B(o, 2, b);
   or3_set_D(o, 1, d);
   len = or3_shell_len(o);
+  if (src) {
+    double* g = malloc(sizeof(double) * 2 * n);
+    int pw[2] = {1, 0};
+    double gam[2] = {0.0, 0.4};
+    for (i = 0; i < 2 * n; ++i) g[i] = 0.3 * cos(0.17 * i);
+    if (or3_set_source_terms(o, 2, g, pw, gam) != 0) bad = 1;
+    free(g);
+  }
   ring = malloc(sizeof(double) * len * steps);
   for (i = 0; i < n; ++i) phi[i] = 0.5 + 0.1 * cos(0.37 * i);
   for (i = 0; i < (int)(len * steps); ++i) ring[i] = 0.5 + 0.05 * sin(0.21 * i);
@@ -135,10 +144,10 @@ int main(void) {
   int q, bc;
   for (q = 9; q >= 5; q -= 4)
     for (bc = 0; bc <= 2; ++bc) two_d(q, bc, q == 9 && bc != 2);
-  three_d(19, 1, 2, 0);
-  three_d(19, 0, 0, 0);
-  three_d(15, 2, 1, 1);
-  three_d(7, 1, 1, 2);
+  three_d(19, 1, 2, 0, 1);
+  three_d(19, 0, 0, 0, 0);
+  three_d(15, 2, 1, 1, 1);
+  three_d(7, 1, 1, 2, 1);
   one_d();
   if (!bad) printf("sanitized oracle runs: ok\n");
   return bad;

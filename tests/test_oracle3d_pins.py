@@ -17,6 +17,13 @@ eq. 2.6, D3Q7 of Remark 3) against what the paper and the mathematics fix:
   ghost rule are exact); the reduction to two dimensions holds with Dirichlet
   walls, against the two-dimensional oracle's rule, with the shell values that
   must not be read set to NaN;
+- sources F(x, t, phi) = sum_j exp(gamma_j t) phi^k_j G_j(x): the reduction
+  to two dimensions with the plane's source terms spread along the uniform
+  axis, against the two-dimensional oracle's sources (pinned in their own
+  tests); a uniform field follows the implicit trapezoidal rule phi' = phi +
+  dt/2 [F(t_n, phi) + F(t_n+1, phi')] (solved here with scipy) on all three
+  lattices; on a periodic mesh the mass changes by exactly dt/2 [sum F(t_n,
+  phi^n)|V| + sum F(t_n+1, phi^n+1)|V|];
 - second-order convergence to the 3-D Gaussian hill closed form.
 """
 import math
@@ -121,8 +128,9 @@ def project_groups(cvec, axis):
 
 @pytest.mark.parametrize("q,q2", [(19, 9), (15, 9), (7, 5)])
 @pytest.mark.parametrize("axis", [0, 1, 2])
-@pytest.mark.parametrize("walls", [W.PERIODIC, W.MIRROR, W.DIRICHLET])
-def test_uniform_along_an_axis_reduces_to_2d(q, q2, axis, walls):
+@pytest.mark.parametrize("walls,src", [(W.PERIODIC, False), (W.MIRROR, False), (W.DIRICHLET, False),
+                                       (W.PERIODIC, True), (W.DIRICHLET, True)])
+def test_uniform_along_an_axis_reduces_to_2d(q, q2, axis, walls, src):
     rng = np.random.default_rng(10 * axis + q)
     p2 = W.random_problem(40 + axis, 11, 9, q=q2, bcx=walls, bcy=walls,
                           stretched=walls != W.PERIODIC, bdeg=2, ddeg=2)
@@ -148,7 +156,11 @@ def test_uniform_along_an_axis_reduces_to_2d(q, q2, axis, walls):
     # the plane's field [ny2][nx2] as [nz][ny][nx] with the uniform axis of length 1;
     # the plane's (x2, y2) are the 3-D axes keep[0] < keep[1]
     phi2 = p2.phi0
-    p3.phi0 = {0: phi2[:, :, None], 1: phi2[:, None, :], 2: phi2[None, :, :]}[axis]
+    spread = lambda a2: {0: a2[:, :, None], 1: a2[:, None, :], 2: a2[None, :, :]}[axis]
+    p3.phi0 = spread(phi2)
+    if src:
+        p2.src_terms = W.random_source_terms(90 + axis + q, p2, nterms=4, amp=0.8)
+        p3.src_terms = [(k, gam, spread(G)) for k, gam, G in p2.src_terms]
     o2, o3 = Oracle(p2), Oracle3D(p3)
     assert abs(o2.dt - o3.dt) < 1e-15
     rings2 = p2.rings(4)
@@ -232,9 +244,13 @@ def test_axis_permutation_symmetry(q):
         assert np.abs(np.transpose(f[i], (2, 0, 1)) - g[j]).max() <= 1e-13 * np.abs(f).max()
 
 
-@pytest.mark.parametrize("bc", [(W.MIRROR, W.PERIODIC, W.MIRROR), (W.DIRICHLET, W.MIRROR, W.DIRICHLET)])
-def test_sampled_step_equals_full_step(bc):
+@pytest.mark.parametrize("bc,src", [((W.MIRROR, W.PERIODIC, W.MIRROR), False),
+                                    ((W.DIRICHLET, W.MIRROR, W.DIRICHLET), False),
+                                    ((W.DIRICHLET, W.PERIODIC, W.MIRROR), True)])
+def test_sampled_step_equals_full_step(bc, src):
     p = W.random_problem3d(9, 7, 6, 5, q=19, bc=bc, stretched=True)
+    if src:
+        p.src_terms = W.random_source_terms3d(10, p, nterms=3)
     o = Oracle3D(p)
     ring = p.rings(1)
     cells = [(0, 0, 0), (6, 5, 4), (3, 2, 1), (0, 5, 2), (6, 0, 4)]
@@ -283,3 +299,53 @@ def test_gaussian_hill_3d_second_order(q):
         errs.append(o.errors(p.exact(X, Y, Z, o.time))[0])
     order = math.log(errs[1] / errs[2]) / math.log(ns[2] / ns[1])
     assert order >= 1.8, (errs, order)
+
+
+def eval_terms(terms, t, phi):
+    F = np.zeros_like(phi)
+    for k, gam, G in terms:
+        F = F + math.exp(gam * t) * phi ** k * G
+    return F
+
+
+@pytest.mark.parametrize("q", [19, 15, 7])
+def test_uniform_field_with_source_follows_the_trapezoidal_rule(q):
+    from scipy.optimize import brentq
+    f = W.uniform_faces(4, 0.0, 1.0)
+    d = ((0.0, 1.0, 0.2), (0.0, 0.8, 0.0, 0.1), (0.0, 1.2), (0.0,), (0.0,), (0.0,)) if q != 7 else \
+        ((0.0, 1.0),) * 3 + ((0.0,),) * 3
+    p = W.Problem3D(name="uniform", xf=f, yf=f, zf=f, q=q, c=2.0, cfl=0.6, alpha=3e-3,
+                    b=((0.0, 0.0, 0.3), (0.0, -0.2), (0.0, 0.1, 0.1)), d=d)
+    one = np.ones((4, 4, 4))
+    p.src_terms = [(1, 0.0, 1.5 * one), (3, 0.0, -2.0 * one), (0, 0.7, 0.3 * one)]
+    p.phi0 = np.full((4, 4, 4), 0.4)
+    o = Oracle3D(p)
+    dt = o.dt
+
+    def F(t, v):
+        return 1.5 * v - 2.0 * v ** 3 + 0.3 * math.exp(0.7 * t)
+
+    v, t = 0.4, 0.0
+    for n in range(30):
+        o.step(1)
+        rhs = v + 0.5 * dt * F(t, v)
+        v = brentq(lambda w: w - 0.5 * dt * F(t + dt, w) - rhs, v - 1.0, v + 1.0, xtol=1e-16, rtol=1e-15)
+        t += dt
+        assert np.abs(o.get_phi() - v).max() <= 1e-14 * abs(v), (n, v)
+
+
+@pytest.mark.parametrize("q", [19, 7])
+def test_mass_balance_with_phi_dependent_source_3d(q):
+    p = W.random_problem3d(31 + q, 9, 7, 6, q=q, bc=(W.PERIODIC,) * 3, stretched=True, bdeg=2)
+    p.src_terms = W.random_source_terms3d(32, p, nterms=5, amp=1.5)
+    o = Oracle3D(p)
+    wx, wy, wz = (np.diff(f) for f in (p.xf, p.yf, p.zf))
+    V = wz[:, None, None] * wy[None, :, None] * wx[None, None, :]
+    dt = o.dt
+    for _ in range(5):
+        m0, t0, pa = o.mass(), o.time, o.get_phi()
+        o.step(1)
+        m1, t1, pb = o.mass(), o.time, o.get_phi()
+        expect = 0.5 * dt * float((eval_terms(p.src_terms, t0, pa) * V).sum() +
+                                  (eval_terms(p.src_terms, t1, pb) * V).sum())
+        assert abs((m1 - m0) - expect) <= 1e-13 * abs(m0), (m1 - m0, expect)
