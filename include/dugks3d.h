@@ -20,7 +20,9 @@
  * Sec. 4 (a ghost with a Dirichlet wall on any of its out-of-range axes takes
  * fbar+_g = E(phi_g) + fbar+_a - E(phi_a), a the nearest interior cell);
  * D3Q7 uses weights 0 and 1/6 and the linear equilibrium of Remark 3
- * (D = phi I only).  Sources are not built in three dimensions.
+ * (D = phi I only).  Sources F(x, t, phi) as in two dimensions
+ * (dugks3_set_source_terms) run a two-pass step with a caller-provided
+ * scratch array.
  */
 #ifndef DUGKS3D_H
 #define DUGKS3D_H
@@ -89,6 +91,28 @@ int dugks3_set_phi(dugks3_ctx* ctx, const double* phi, int on_device);
 
 /* f~ [q][nz][ny][nx] (binary64) as the state; resets the step count. */
 int dugks3_set_f(dugks3_ctx* ctx, const double* f, int on_device);
+
+/* Bytes of the scratch array the source path needs (g of every cell and of
+ * the ghost shell: q (nx+2)(ny+2)(nz+2) values of the storage type). */
+size_t dugks3_source_scratch_bytes(const dugks3_ctx* ctx);
+
+/* Source F(x, t, phi) = sum_{j < nterms} exp(gammas[j] t) phi^powers[j] G_j(x)
+ * of eq. 2.1, with F_i = w_i F and R_i = w_i c_i.B'(phi) F / c_s^2 (eq. 2.3,
+ * Remark 3) in eqs. 2.25 and 2.27, as dugks_set_source_terms: g_dev (device,
+ * binary64, caller-owned, must outlive the steps) holds nterms shapes of
+ * [nz][ny][nx]; powers in 0..DUGKS_MAX_SRC_POW; nterms <= DUGKS_MAX_SRC_TERMS
+ * (0 removes the source).  The conserved value solves phi = sum f~ +
+ * dt F(phi) / 2 in a cell at t_n and phi_b = sum fbar + h F(phi_b) / 2 at a
+ * face at t_n + h (each G_j interpolated between the two centres; a ghost
+ * takes the G_j of the cell it copies), by Newton's method when F depends on
+ * phi (binary64: update <= 1e-15 (1 + |phi|), at most 8; binary32: 2.4e-7,
+ * at most 6).  Set before dugks3_set_phi (f~ = E(phi) - dt S / 2 at t = 0).
+ * With a source the step runs two passes through scratch_dev (device,
+ * caller-owned, 256-byte aligned, >= dugks3_source_scratch_bytes).  Errors:
+ * E_ARG (nterms, a power out of range, a rate not finite, NULL arrays or
+ * scratch), E_NOMEM (scratch too small). */
+int dugks3_set_source_terms(dugks3_ctx* ctx, int nterms, const double* g_dev, const int* powers,
+                            const double* gammas, void* scratch_dev, size_t scratch_bytes);
 
 /* Dirichlet data: ring_dev (device, caller-owned, must outlive the steps)
  * holds nsteps blocks of shell-length binary64 values, phi at the ghost-cell

@@ -424,6 +424,8 @@ class Solver3D:
                                           _stream_handle(self.device)), self.h, "dugks3_bind")
         if launch is not None:
             self.set_launch(*launch)
+        if getattr(problem, "src_terms", None):
+            self.set_source_terms(problem.src_terms)
 
     def _dev64(self, a, shape):
         torch = _torch()
@@ -440,6 +442,28 @@ class Solver3D:
     def set_f(self, f):
         t = self._dev64(f, (self.q, self.nz, self.ny, self.nx))
         L.check3(self.lib.dugks3_set_f(self.h, C.c_void_p(t.data_ptr()), 1), self.h, "dugks3_set_f")
+
+    def set_source_terms(self, terms):
+        """F(x, t, phi) = sum_j exp(gamma_j t) phi^k_j G_j(x), terms as (k_j,
+        gamma_j, G_j [nz][ny][nx]); an empty list removes the source.  Set
+        before set_phi.  The G_j and the source path's scratch stay on the
+        device while this solver lives."""
+        torch = _torch()
+        n = len(terms)
+        if n == 0:
+            L.check3(self.lib.dugks3_set_source_terms(self.h, 0, None, None, None, None, 0), self.h,
+                     "dugks3_set_source_terms")
+            self._src = None
+            return
+        g = np.stack([np.asarray(G, dtype=np.float64).reshape(self.nz, self.ny, self.nx) for _, _, G in terms])
+        self._src_g = torch.from_numpy(np.ascontiguousarray(g)).to(self.device)
+        nb = self.lib.dugks3_source_scratch_bytes(self.h)
+        self._scratch = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
+        sp = (self._scratch.data_ptr() + 255) & ~255
+        pw = (C.c_int * n)(*[int(k) for k, _, _ in terms])
+        gm = (C.c_double * n)(*[float(gam) for _, gam, _ in terms])
+        L.check3(self.lib.dugks3_set_source_terms(self.h, n, C.c_void_p(self._src_g.data_ptr()), pw, gm,
+                                                  C.c_void_p(sp), nb), self.h, "dugks3_set_source_terms")
 
     def set_dirichlet(self, rings):
         """Dirichlet data, [nsteps][shell length] (workloads.Problem3D.rings),

@@ -133,6 +133,8 @@ SIGNATURES = {
     "dugks3_set_f": (_int, [_vp, _vp, _int]),
     "dugks3_step": (_int, [_vp, _int]),
     "dugks3_set_dirichlet": (_int, [_vp, _vp, _int]),
+    "dugks3_source_scratch_bytes": (_sz, [_vp]),
+    "dugks3_set_source_terms": (_int, [_vp, _int, _vp, C.POINTER(_int), C.POINTER(C.c_double), _vp, _sz]),
     "dugks3_get_phi": (_int, [_vp, _vp, _int]),
     "dugks3_get_f": (_int, [_vp, _vp, _int]),
     "dugks3_reduce": (_int, [_vp, _vp, _dp, _dp, _dp]),

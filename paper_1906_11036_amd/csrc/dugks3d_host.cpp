@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 
 #include <math.h>
+
+#include <cmath>
 #include <stdint.h>
 #include <string.h>
 
@@ -90,6 +92,15 @@ struct dugks3_ctx {
   long long step = 0;
   const double* ring = nullptr;   // Dirichlet data (device, caller-owned)
   long long ring_steps = 0;
+  // sources (device, caller-owned): G_j, and the scratch of the source path
+  const double* src_g = nullptr;
+  int src_n = 0;
+  int src_pow[DUGKS_MAX_SRC_TERMS] = {0};
+  double src_gam[DUGKS_MAX_SRC_TERMS] = {0};
+  void* src_scratch = nullptr;
+  size_t scratch_bytes() const {
+    return align256((size_t)q * (n[0] + 2) * (n[1] + 2) * (n[2] + 2) * elem());
+  }
 
   int fail(int rc, const std::string& m) { err = m; return rc; }
   int hipfail(hipError_t e, const char* what) {
@@ -177,6 +188,20 @@ struct dugks3_ctx {
     d3.inv_b1f = (float)d3.inv_b1;
     d3.ring = ring;
     d3.ring_len = shell_len(n[0], n[1], n[2]);
+    d3.src_g = src_g;
+    d3.src_plane = cells();
+    d3.src_n = src_n;
+    d3.src_implicit = 0;
+    for (int t = 0; t < src_n; ++t) {
+      d3.src_pow[t] = src_pow[t];
+      d3.src_gam[t] = src_gam[t];
+      if (src_pow[t] > 0) d3.src_implicit = 1;
+    }
+    d3.dt = dt;
+    d3.lambda = lambda;
+    for (int a = 0; a < 3; ++a)
+      for (int m = 0; m < 4; ++m) d3.bp[a][m] = p.c * (m + 1) * b[a][m + 1] / cs2;
+    d3.gscr = src_scratch;
     for (int i = 0; i < q; ++i)
       for (int m = 0; m < kMaxCoef; ++m) {
         d3.e[i][m] = e[i][m];
@@ -239,7 +264,7 @@ struct dugks3_ctx {
     double* dst = on_device ? out : (double*)(ws + off_stage);
     if (!on_device && count * sizeof(double) > stage_bytes) return fail(DUGKS_E_ARG, "too large");
     const int rc = want_f ? launch_get_f3(dev(), host, dst, (int)(step & 1), stream)
-                          : launch_get_phi3(dev(), host, dst, (int)(step & 1), stream);
+                          : launch_get_phi3(dev(), host, dst, (int)(step & 1), step, stream);
     if (rc) return fail(DUGKS_E_HIP, "read-out launch failed");
     hipError_t er = on_device ? hipSuccess
                               : hipMemcpyAsync(out, dst, count * sizeof(double), hipMemcpyDeviceToHost, stream);
@@ -432,6 +457,34 @@ int dugks3_set_f(dugks3_ctx* ctx, const double* f, int on_device) {
   return DUGKS_OK;
 }
 
+size_t dugks3_source_scratch_bytes(const dugks3_ctx* ctx) {
+  return (ctx && ctx->magic == kMagic3) ? ctx->scratch_bytes() : 0;
+}
+
+int dugks3_set_source_terms(dugks3_ctx* ctx, int nterms, const double* g_dev, const int* powers,
+                            const double* gammas, void* scratch_dev, size_t scratch_bytes) {
+  GUARD3(ctx);
+  if (nterms < 0 || nterms > DUGKS_MAX_SRC_TERMS) return ctx->fail(DUGKS_E_ARG, "nterms out of range");
+  if (nterms > 0) {
+    if (!g_dev || !powers || !gammas) return ctx->fail(DUGKS_E_ARG, "source arrays are NULL");
+    for (int t = 0; t < nterms; ++t) {
+      if (powers[t] < 0 || powers[t] > DUGKS_MAX_SRC_POW) return ctx->fail(DUGKS_E_ARG, "power out of range");
+      if (!std::isfinite(gammas[t])) return ctx->fail(DUGKS_E_ARG, "growth rate not finite");
+    }
+    if (!scratch_dev || ((uintptr_t)scratch_dev & 255) != 0)
+      return ctx->fail(DUGKS_E_ARG, "scratch must be a 256-byte aligned device buffer");
+    if (scratch_bytes < ctx->scratch_bytes()) return ctx->fail(DUGKS_E_NOMEM, "scratch too small");
+  }
+  ctx->src_n = nterms;
+  ctx->src_g = nterms > 0 ? g_dev : nullptr;
+  ctx->src_scratch = nterms > 0 ? scratch_dev : nullptr;
+  for (int t = 0; t < DUGKS_MAX_SRC_TERMS; ++t) {
+    ctx->src_pow[t] = t < nterms ? powers[t] : 0;
+    ctx->src_gam[t] = t < nterms ? gammas[t] : 0.0;
+  }
+  return ctx->bound() ? ctx->upload() : DUGKS_OK;
+}
+
 int dugks3_set_dirichlet(dugks3_ctx* ctx, const double* ring_dev, int nsteps) {
   GUARD3(ctx);
   if (nsteps < 0 || (nsteps > 0 && !ring_dev)) return ctx->fail(DUGKS_E_ARG, "bad Dirichlet data");
@@ -450,7 +503,10 @@ int dugks3_step(dugks3_ctx* ctx, int nsteps) {
   if (ctx->any_dirichlet() && (ctx->ring == nullptr || ctx->step + nsteps > ctx->ring_steps))
     return ctx->fail(DUGKS_E_STATE, "Dirichlet walls need data for every step (dugks3_set_dirichlet)");
   for (int s = 0; s < nsteps; ++s) {
-    if (launch_step3(ctx->dev(), ctx->host, (int)(ctx->step & 1), ctx->step, ctx->launch, ctx->stream))
+    const int rc = ctx->src_n > 0
+                       ? launch_src3_step(ctx->dev(), ctx->host, (int)(ctx->step & 1), ctx->step, ctx->stream)
+                       : launch_step3(ctx->dev(), ctx->host, (int)(ctx->step & 1), ctx->step, ctx->launch, ctx->stream);
+    if (rc)
       return ctx->fail(DUGKS_E_HIP, std::string("step launch failed: ") + hipGetErrorString(hipGetLastError()));
     ctx->step += 1;
   }
@@ -472,7 +528,7 @@ int dugks3_reduce(dugks3_ctx* ctx, const double* ref_dev, double* mass, double* 
   if (!ctx->bound()) return ctx->fail(DUGKS_E_STATE, "not bound");
   if (!ctx->initialised) return ctx->fail(DUGKS_E_STATE, "state not initialised");
   double* o = (double*)(ctx->ws + ctx->off_out);
-  if (launch_reduce3(ctx->dev(), ctx->host, ref_dev, (int)(ctx->step & 1),
+  if (launch_reduce3(ctx->dev(), ctx->host, ref_dev, (int)(ctx->step & 1), ctx->step,
                      (const double*)(ctx->ws + ctx->off_widths), (double*)(ctx->ws + ctx->off_partial), o,
                      ctx->stream))
     return ctx->fail(DUGKS_E_HIP, "reduction launch failed");

@@ -50,6 +50,16 @@ struct alignas(64) Inst3 {
   long long ring_len;
   double e[kMaxQ][kMaxCoef];   // E_i(phi) = sum_k e[i][k] phi^k (eq. 2.3)
   float ef[kMaxQ][kMaxCoef];
+  // sources (src_n = 0: none): F(x, t, phi) = sum_j exp(src_gam[j] t)
+  // phi^src_pow[j] G_j(x), G_j as [src_n][nz][ny][nx] binary64 (caller-owned)
+  const double* src_g;
+  long long src_plane;     // nx * ny * nz
+  int src_n, src_implicit; // implicit: some term depends on phi
+  int src_pow[DUGKS_MAX_SRC_TERMS];
+  double src_gam[DUGKS_MAX_SRC_TERMS];
+  double dt, lambda;
+  double bp[3][4];         // c B'_a(phi) / c_s^2 as polynomials in phi (B' has degree <= 3)
+  void* gscr;              // source path: g of every cell and ghost, [q][nz+2][ny+2][nx+2]
 };
 
 struct Launch3 {
@@ -78,17 +88,20 @@ inline long long shell_len(int nx, int ny, int nz) {
 long long step3_blocks(const Inst3& h, const Launch3& l);
 // step: the step index since the state was set (selects the Dirichlet data)
 int launch_step3(const Inst3* d, const Inst3& h, int parity, long long step, const Launch3& l, void* stream);
+// the step with sources: g of every cell and ghost into h.gscr, then the
+// faces and the update, one thread per cell
+int launch_src3_step(const Inst3* d, const Inst3& h, int parity, long long step, void* stream);
 // LDS bytes of one block of the step kernel (walls: the instantiation with
 // mirror code, for a non-periodic axis or more than four coefficients)
 size_t step3_lds_bytes(int storage, int q, bool walls, const Launch3& l);
 int launch_init3(const Inst3* d, const Inst3& h, const double* phi, int parity, void* stream);
 int launch_set_f3(const Inst3* d, const Inst3& h, const double* f, int parity, void* stream);
-int launch_get_phi3(const Inst3* d, const Inst3& h, double* out, int parity, void* stream);
+int launch_get_phi3(const Inst3* d, const Inst3& h, double* out, int parity, long long step, void* stream);
 int launch_get_f3(const Inst3* d, const Inst3& h, double* out, int parity, void* stream);
 // out[0] mass, [1] sum|phi-ref|, [2] sum|ref|, [3] sum (phi-ref)^2 |V|, [4] sum ref^2 |V|,
 // [5] non-finite cells; widths = dx[0..nx) dy[0..ny) dz[0..nz); partial holds
 // reduce3_partials() * 8 doubles.
-int launch_reduce3(const Inst3* d, const Inst3& h, const double* ref, int parity,
+int launch_reduce3(const Inst3* d, const Inst3& h, const double* ref, int parity, long long step,
                    const double* widths, double* partial, double* out, void* stream);
 int reduce3_partials();
 

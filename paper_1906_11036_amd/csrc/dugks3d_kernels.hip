@@ -1362,6 +1362,63 @@ __device__ __forceinline__ void feq64(const Inst3* __restrict__ I, double phi, d
   }
 }
 
+// ------------------------------------------------------------- sources
+// F(x, t, phi) = sum_j exp(gamma_j t) phi^k_j G_j(x) (k_j <= 3): its
+// coefficients as a polynomial in phi at time t, each G_j interpolated as
+// G_j(c0) + r (G_j(c1) - G_j(c0)) (r = 0: the centre of cell c0).
+__device__ inline void src_coefs3(const Inst3* __restrict__ I, long long c0, long long c1, double r, double t,
+                                  double* a) {
+  for (int m = 0; m < 4; ++m) a[m] = 0.0;
+  for (int j = 0; j < I->src_n; ++j) {
+    const double g0 = I->src_g[j * I->src_plane + c0], g1 = I->src_g[j * I->src_plane + c1];
+    a[I->src_pow[j]] += exp(I->src_gam[j] * t) * fma(r, g1 - g0, g0);
+  }
+}
+template <typename T> __device__ inline T poly4(const T* a, T x) {
+  return fma(fma(fma(a[3], x, a[2]), x, a[1]), x, a[0]);
+}
+// The conserved value v with v - tau F(v) / 2 = s (tau = dt in a cell, eq.
+// 2.25; h at a face, eq. 2.27): explicit when F does not depend on phi, else
+// Newton's method from v = s (binary64: update <= 1e-15 (1 + |v|), at most 8;
+// binary32: 2.4e-7, at most 6).
+template <typename T> __device__ inline T solve_conserved3(T s, T half_tau, const T* a, bool implicit) {
+  if (!implicit) return fma(half_tau, a[0], s);
+  constexpr bool dbl = sizeof(T) == 8;
+  const T tol = dbl ? (T)1e-15 : (T)2.4e-7;
+  T v = s;
+#pragma unroll 1
+  for (int it = 0; it < (dbl ? 8 : 6); ++it) {
+    const T P = poly4(a, v);
+    const T dP = fma(fma((T)3 * a[3], v, (T)2 * a[2]), v, a[1]);
+    const T d = (v - half_tau * P - s) / ((T)1 - half_tau * dP);
+    v -= d;
+    if (!(fabs(d) > tol * ((T)1 + fabs(v)))) break;
+  }
+  return v;
+}
+// weights of D3Q19 (eq. 2.6), D3Q15 (eq. 2.28) and D3Q7 (Remark 3)
+template <int Q> __host__ __device__ constexpr double w3(int k) {
+  return Q == 19 ? (k == 0 ? 1.0 / 3.0 : (k <= 6 ? 1.0 / 18.0 : 1.0 / 36.0))
+         : Q == 15 ? (k == 0 ? 2.0 / 9.0 : (k <= 6 ? 1.0 / 9.0 : 1.0 / 72.0))
+                   : (k == 0 ? 0.0 : 1.0 / 6.0);
+}
+// S_k / F = w_k (1 + c_k.B'(phi) / c_s^2): F_k and R_k of eq. 2.3 and Remark 3
+template <int Q> __device__ inline double rho3(const Inst3* __restrict__ I, int k, double phi) {
+  double v = 1.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    if (ce<Q>(k, a) != 0) v += ce<Q>(k, a) * poly4(I->bp[a], phi);
+  return w3<Q>(k) * v;
+}
+// phi of interior cell `cell` at time t from the sum of its f~ (the root of
+// phi = s + dt F(phi) / 2 with a source)
+__device__ inline double src_phi3(const Inst3* __restrict__ I, long long cell, double s, double t) {
+  if (I->src_n == 0) return s;
+  double a[4];
+  src_coefs3(I, cell, cell, 0.0, t, a);
+  return solve_conserved3<double>(s, 0.5 * I->dt, a, I->src_implicit != 0);
+}
+
 template <int Q, int ST>
 __global__ void k_init3(const Inst3* __restrict__ I, const double* __restrict__ phi, int parity) {
   using T = typename S3<ST>::T;
@@ -1371,6 +1428,14 @@ __global__ void k_init3(const Inst3* __restrict__ I, const double* __restrict__ 
   const long long off = ((long long)k * I->n[1] + j) * I->pitch + i;
   double E[Q];
   feq64<Q>(I, phi[cell], E);
+  if (I->src_n > 0) {
+    // f = E at t = 0 (Omega = 0): f~ = E - dt S / 2 (eq. 2.25)
+    double a[4];
+    src_coefs3(I, cell, cell, 0.0, 0.0, a);
+    const double F = poly4(a, phi[cell]);
+#pragma unroll
+    for (int m = 0; m < Q; ++m) E[m] -= 0.5 * I->dt * F * rho3<Q>(I, m, phi[cell]);
+  }
   T* buf = (T*)I->buf[parity];
 #pragma unroll
   for (int m = 0; m < Q; ++m) buf[m * I->plane + off] = (T)E[m];
@@ -1390,7 +1455,8 @@ __global__ void k_set_f3(const Inst3* __restrict__ I, const double* __restrict__
 }
 
 template <int Q, int ST>
-__global__ void k_get3(const Inst3* __restrict__ I, double* __restrict__ out, int parity, int want_f) {
+__global__ void k_get3(const Inst3* __restrict__ I, double* __restrict__ out, int parity, int want_f,
+                       long long step) {
   using T = typename S3<ST>::T;
   const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
   if (i >= I->n[0]) return;
@@ -1405,7 +1471,7 @@ __global__ void k_get3(const Inst3* __restrict__ I, double* __restrict__ out, in
     double phi = 0.0;
 #pragma unroll
     for (int m = 0; m < Q; ++m) phi += (double)buf[m * I->plane + off];
-    out[cell] = phi;
+    out[cell] = src_phi3(I, cell, phi, (double)step * I->dt);
   }
 }
 
@@ -1422,7 +1488,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 template <int Q, int ST>
 __global__ __launch_bounds__(kRedThreads) void k_reduce3(const Inst3* __restrict__ I,
                                                          const double* __restrict__ ref, int parity,
-                                                         const double* __restrict__ widths,
+                                                         long long step, const double* __restrict__ widths,
                                                          double* __restrict__ partial) {
   using T = typename S3<ST>::T;
   const int nx = I->n[0], ny = I->n[1];
@@ -1438,6 +1504,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce3(const Inst3* __restrict
     double phi = 0.0;
 #pragma unroll
     for (int m = 0; m < Q; ++m) phi += (double)buf[m * I->plane + off];
+    phi = src_phi3(I, n, phi, (double)step * I->dt);
     const double vol = widths[i] * widths[nx + j] * widths[nx + ny + k];
     if (!__builtin_isfinite(phi)) {
       acc[5] += 1.0;
@@ -1626,6 +1693,189 @@ size_t step3_lds_bytes(int storage, int q, bool walls, const Launch3& l) {
     }                                                                                              \
   } while (0)
 
+// ------------------------------------------------ the step with sources
+// Two passes, one thread per cell: g of every cell and ghost (with the source
+// and the ghost rules) into the scratch array, then each cell's six faces and
+// its update from that array.  Not the fused design of the source-free step:
+// each face is formed twice and g is written and read once more.
+
+// E_k(x) with the instance's runtime number of coefficients
+template <typename T> __device__ inline T eq_rt(const Inst3* __restrict__ I, int k, T x) {
+  const T* c = C3<T>::e(I, k);
+  const int nc = I->ncoef;
+  T r = c[nc - 1];
+  for (int m = nc - 2; m >= 0; --m) r = fma(r, x, c[m]);
+  return r;
+}
+
+// g = fbar+ / b1 with the source (eqs. 2.25, 2.27 over b1):
+// g = (a1/b1) f~ + E(phi) + lambda F(phi) rho(phi), phi the root of
+// phi = sum f~ + dt F(phi) / 2 at t_n (binary64); a ghost takes the g of the
+// cell it copies, then the Dirichlet or mirror rule.
+template <int Q, int ST>
+__global__ __launch_bounds__(256) void k_src3_g(const Inst3* __restrict__ I, int parity,
+                                                const double* __restrict__ ring, long long step) {
+  using T = typename S3<ST>::T;
+  const int nx = I->n[0], ny = I->n[1], nz = I->n[2];
+  const int px = nx + 2, py = ny + 2;
+  const long long NP = (long long)px * py * (nz + 2);
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= NP) return;
+  const int i = (int)(n % px) - 1;
+  const long long rest = n / px;
+  const int j = (int)(rest % py) - 1, k = (int)(rest / py) - 1;
+  const int si = src_index(i, nx, I->bc[0]), sj = src_index(j, ny, I->bc[1]), sk = src_index(k, nz, I->bc[2]);
+  const long long off = ((long long)sk * ny + sj) * I->pitch + si;
+  const long long cell = ((long long)sk * ny + sj) * nx + si;
+  const T* buf = (const T*)I->buf[parity];
+  T f[Q];
+  double s = 0.0;
+#pragma unroll
+  for (int m = 0; m < Q; ++m) {
+    f[m] = buf[m * I->plane + off];
+    s += (double)f[m];
+  }
+  double a[4];
+  src_coefs3(I, cell, cell, 0.0, (double)step * I->dt, a);
+  const double phi = solve_conserved3<double>(s, 0.5 * I->dt, a, I->src_implicit != 0);
+  const double lf = I->lambda * poly4(a, phi);
+  const T p = (T)phi, ra = C3<T>::ra(I);
+  T g[Q];
+#pragma unroll
+  for (int m = 0; m < Q; ++m) g[m] = fma(ra, f[m], eq_rt<T>(I, m, p) + (T)(lf * rho3<Q>(I, m, phi)));
+  const bool wx = (i < 0 || i >= nx) && I->bc[0] != DUGKS_BC_PERIODIC;
+  const bool wy = (j < 0 || j >= ny) && I->bc[1] != DUGKS_BC_PERIODIC;
+  const bool wz = (k < 0 || k >= nz) && I->bc[2] != DUGKS_BC_PERIODIC;
+  if (wx || wy || wz) {
+    if (dirichlet_ghost(I, wx, wy, k)) {
+      const T pg = (T)ring[shell_index(nx, ny, nz, i, j, k)], ib = C3<T>::inv_b1(I);
+#pragma unroll
+      for (int m = 0; m < Q; ++m) g[m] = fma(eq_rt<T>(I, m, pg) - eq_rt<T>(I, m, p), ib, g[m]);
+    } else {
+      if (wx) mirror<Q, T>(g, 0);
+      if (wy) mirror<Q, T>(g, 1);
+      if (wz) mirror<Q, T>(g, 2);
+    }
+  }
+  T* gs = (T*)I->gscr;
+#pragma unroll
+  for (int m = 0; m < Q; ++m) gs[m * NP + n] = g[m];
+}
+
+// Faces and update of one cell from the scratch g: reconstruction (eq. 2.20)
+// and characteristic shift (eq. 2.19 as eq. 2.26) on the scaled g, phi_b =
+// b1 sum gbar solved with F at the face at t_n + h (phi_b = sum fbar + h
+// F(phi_b) / 2, each G_j interpolated between the two cells' centres),
+// F = f_b / b3 = (a3 b1/b3) gbar + E(phi_b) + lambda F(phi_b) rho(phi_b)
+// (eq. 2.27 solved for f), and f~(t+dt) = f~+ - dt c.(flux differences) /
+// width (eq. 2.24) with f~+ = (4/3) b1 g - f~ / 3.
+template <int Q, int ST>
+__global__ __launch_bounds__(256) void k_src3_step(const Inst3* __restrict__ I, int parity, long long step) {
+  using T = typename S3<ST>::T;
+  const int nx = I->n[0], ny = I->n[1], nz = I->n[2];
+  const long long N = (long long)nx * ny * nz;
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const int i = (int)(n % nx), j = (int)((n / nx) % ny), k = (int)(n / ((long long)nx * ny));
+  const int px = nx + 2, py = ny + 2;
+  const long long NP = (long long)px * py * (nz + 2);
+  const T* gs = (const T*)I->gscr;
+  auto G = [&](int ii, int jj, int kk, int m) -> T {
+    return gs[m * NP + ((long long)(kk + 1) * py + (jj + 1)) * px + (ii + 1)];
+  };
+  const long long off = ((long long)k * ny + j) * I->pitch + i;
+  const T* buf = (const T*)I->buf[parity];
+  const T kg = C3<T>::kg(I), rb = C3<T>::rb(I), b1 = C3<T>::b1(I), lam = (T)I->lambda;
+  const T hh = (T)(0.25 * I->dt);   // h / 2
+  const double tf = ((double)step + 0.5) * I->dt;
+  T O[Q];
+#pragma unroll
+  for (int m = 0; m < Q; ++m) O[m] = fma(kg, G(i, j, k, m), (T)(-1.0 / 3.0) * buf[m * I->plane + off]);
+  const int idx[3] = {i, j, k};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const T* ga = C3<T>::geo(I, a);
+    const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
+    const T tau1 = C3<T>::geo(I, t1)[(idx[t1] + 1) * kGeo + 3];
+    const T tau2 = C3<T>::geo(I, t2)[(idx[t2] + 1) * kGeo + 3];
+    T flux[2][Q];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      int L[3] = {i, j, k}, R[3] = {i, j, k};
+      if (side == 0) L[a] -= 1; else R[a] += 1;
+      const int m = R[a];
+      const T am = ga[(m + 1) * kGeo + 0], a0 = ga[(m + 1) * kGeo + 1], ap = ga[(m + 1) * kGeo + 2];
+      T gb[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int cn = ce<Q>(q, a), c1 = ce<Q>(q, t1), c2 = ce<Q>(q, t2);
+        const T gl = G(L[0], L[1], L[2], q), gr = G(R[0], R[1], R[2], q);
+        const T al = cn > 0 ? ap : (cn < 0 ? am : a0);
+        T v = fma(al, gr - gl, gl);
+        if (c1 != 0) {
+          int lp[3] = {L[0], L[1], L[2]}, lm[3] = {L[0], L[1], L[2]}, rp[3] = {R[0], R[1], R[2]}, rm[3] = {R[0], R[1], R[2]};
+          lp[t1] += 1; lm[t1] -= 1; rp[t1] += 1; rm[t1] -= 1;
+          const T ts = (G(lp[0], lp[1], lp[2], q) - G(lm[0], lm[1], lm[2], q)) +
+                       (G(rp[0], rp[1], rp[2], q) - G(rm[0], rm[1], rm[2], q));
+          v = fma((T)(-c1) * tau1, ts, v);
+        }
+        if (c2 != 0) {
+          int lp[3] = {L[0], L[1], L[2]}, lm[3] = {L[0], L[1], L[2]}, rp[3] = {R[0], R[1], R[2]}, rm[3] = {R[0], R[1], R[2]};
+          lp[t2] += 1; lm[t2] -= 1; rp[t2] += 1; rm[t2] -= 1;
+          const T ts = (G(lp[0], lp[1], lp[2], q) - G(lm[0], lm[1], lm[2], q)) +
+                       (G(rp[0], rp[1], rp[2], q) - G(rm[0], rm[1], rm[2], q));
+          v = fma((T)(-c2) * tau2, ts, v);
+        }
+        gb[q] = v;
+      }
+      T pb = (T)(dir_sum<Q>(gb) * b1);
+      const long long cL = ((long long)src_index(L[2], nz, I->bc[2]) * ny + src_index(L[1], ny, I->bc[1])) * nx +
+                           src_index(L[0], nx, I->bc[0]);
+      const long long cR = ((long long)src_index(R[2], nz, I->bc[2]) * ny + src_index(R[1], ny, I->bc[1])) * nx +
+                           src_index(R[0], nx, I->bc[0]);
+      double ad[4];
+      src_coefs3(I, cL, cR, (double)a0, tf, ad);
+      const T af[4] = {(T)ad[0], (T)ad[1], (T)ad[2], (T)ad[3]};
+      pb = solve_conserved3<T>(pb, hh, af, I->src_implicit != 0);
+      const T lfb = lam * poly4(af, pb);
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+        if (ce<Q>(q, a) != 0)
+          flux[side][q] = fma(rb, gb[q], eq_rt<T>(I, q, pb) + lfb * (T)rho3<Q>(I, q, (double)pb));
+    }
+    const T ka = ga[(idx[a] + 1) * kGeo + 4];
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+      if (ce<Q>(q, a) != 0) O[q] = fma((T)(-ce<Q>(q, a)) * ka, flux[1][q] - flux[0][q], O[q]);
+  }
+  T* out = (T*)I->buf[parity ^ 1];
+#pragma unroll
+  for (int m = 0; m < Q; ++m) out[m * I->plane + off] = O[m];
+}
+
+template <int Q, int ST>
+static int src3_go(const Inst3* d, const Inst3& h, int parity, const double* ring, long long step, hipStream_t st) {
+  const long long NP = (long long)(h.n[0] + 2) * (h.n[1] + 2) * (h.n[2] + 2);
+  const long long N = (long long)h.n[0] * h.n[1] * h.n[2];
+  if ((NP + 255) / 256 > 0x7fffffffLL) return -1;
+  hipLaunchKernelGGL((k_src3_g<Q, ST>), dim3((unsigned)((NP + 255) / 256)), dim3(256), 0, st, d, parity, ring, step);
+  hipLaunchKernelGGL((k_src3_step<Q, ST>), dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, d, parity, step);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_src3_step(const Inst3* d, const Inst3& h, int parity, long long step, void* stream) {
+  const double* ring = h.ring != nullptr ? h.ring + step * h.ring_len : nullptr;
+  const bool f64 = h.storage == DUGKS_F64;
+  switch (h.q) {
+    case 19: return f64 ? src3_go<19, DUGKS_F64>(d, h, parity, ring, step, S(stream))
+                        : src3_go<19, DUGKS_F32>(d, h, parity, ring, step, S(stream));
+    case 15: return f64 ? src3_go<15, DUGKS_F64>(d, h, parity, ring, step, S(stream))
+                        : src3_go<15, DUGKS_F32>(d, h, parity, ring, step, S(stream));
+    default: return f64 ? src3_go<7, DUGKS_F64>(d, h, parity, ring, step, S(stream))
+                        : src3_go<7, DUGKS_F32>(d, h, parity, ring, step, S(stream));
+  }
+}
+
 int launch_init3(const Inst3* d, const Inst3& h, const double* phi, int parity, void* stream) {
   DUGKS3_PER_CELL(k_init3, d, phi, parity);
   return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -1634,33 +1884,33 @@ int launch_set_f3(const Inst3* d, const Inst3& h, const double* f, int parity, v
   DUGKS3_PER_CELL(k_set_f3, d, f, parity);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
-int launch_get_phi3(const Inst3* d, const Inst3& h, double* out, int parity, void* stream) {
-  DUGKS3_PER_CELL(k_get3, d, out, parity, 0);
+int launch_get_phi3(const Inst3* d, const Inst3& h, double* out, int parity, long long step, void* stream) {
+  DUGKS3_PER_CELL(k_get3, d, out, parity, 0, step);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 int launch_get_f3(const Inst3* d, const Inst3& h, double* out, int parity, void* stream) {
-  DUGKS3_PER_CELL(k_get3, d, out, parity, 1);
+  DUGKS3_PER_CELL(k_get3, d, out, parity, 1, 0LL);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int reduce3_partials() { return kRedBlocks; }
 
-int launch_reduce3(const Inst3* d, const Inst3& h, const double* ref, int parity,
+int launch_reduce3(const Inst3* d, const Inst3& h, const double* ref, int parity, long long step,
                    const double* widths, double* partial, double* out, void* stream) {
   dim3 grid(kRedBlocks), block(kRedThreads);
   const bool f64 = h.storage == DUGKS_F64;
   switch (h.q) {
     case 19:
-      if (f64) hipLaunchKernelGGL((k_reduce3<19, DUGKS_F64>), grid, block, 0, S(stream), d, ref, parity, widths, partial);
-      else hipLaunchKernelGGL((k_reduce3<19, DUGKS_F32>), grid, block, 0, S(stream), d, ref, parity, widths, partial);
+      if (f64) hipLaunchKernelGGL((k_reduce3<19, DUGKS_F64>), grid, block, 0, S(stream), d, ref, parity, step, widths, partial);
+      else hipLaunchKernelGGL((k_reduce3<19, DUGKS_F32>), grid, block, 0, S(stream), d, ref, parity, step, widths, partial);
       break;
     case 15:
-      if (f64) hipLaunchKernelGGL((k_reduce3<15, DUGKS_F64>), grid, block, 0, S(stream), d, ref, parity, widths, partial);
-      else hipLaunchKernelGGL((k_reduce3<15, DUGKS_F32>), grid, block, 0, S(stream), d, ref, parity, widths, partial);
+      if (f64) hipLaunchKernelGGL((k_reduce3<15, DUGKS_F64>), grid, block, 0, S(stream), d, ref, parity, step, widths, partial);
+      else hipLaunchKernelGGL((k_reduce3<15, DUGKS_F32>), grid, block, 0, S(stream), d, ref, parity, step, widths, partial);
       break;
     default:
-      if (f64) hipLaunchKernelGGL((k_reduce3<7, DUGKS_F64>), grid, block, 0, S(stream), d, ref, parity, widths, partial);
-      else hipLaunchKernelGGL((k_reduce3<7, DUGKS_F32>), grid, block, 0, S(stream), d, ref, parity, widths, partial);
+      if (f64) hipLaunchKernelGGL((k_reduce3<7, DUGKS_F64>), grid, block, 0, S(stream), d, ref, parity, step, widths, partial);
+      else hipLaunchKernelGGL((k_reduce3<7, DUGKS_F32>), grid, block, 0, S(stream), d, ref, parity, step, widths, partial);
       break;
   }
   if (hipGetLastError() != hipSuccess) return -1;

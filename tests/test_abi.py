@@ -218,6 +218,28 @@ def test_3d_dirichlet_data_arguments():
     lib.dugks3_destroy(h)
 
 
+def test_3d_source_term_arguments():
+    lib = L.lib()
+    rc, h = _create3(bc=(0, 2, 1))
+    assert rc == L.OK
+    nb = lib.dugks3_source_scratch_bytes(h)
+    assert nb >= 19 * 10 * 8 * 7 * 8
+    g, sc = C.c_void_p(256), C.c_void_p(4096)
+    pw = (C.c_int * 2)(0, 3)
+    gm = (C.c_double * 2)(0.1, -0.2)
+    assert lib.dugks3_set_source_terms(h, 7, g, pw, gm, sc, nb) == L.E_ARG          # too many terms
+    bad = (C.c_int * 2)(0, 4)
+    assert lib.dugks3_set_source_terms(h, 2, g, bad, gm, sc, nb) == L.E_ARG         # power
+    nan = (C.c_double * 2)(0.1, float("nan"))
+    assert lib.dugks3_set_source_terms(h, 2, g, pw, nan, sc, nb) == L.E_ARG         # rate
+    assert lib.dugks3_set_source_terms(h, 2, None, pw, gm, sc, nb) == L.E_ARG       # no G
+    assert lib.dugks3_set_source_terms(h, 2, g, pw, gm, C.c_void_p(4100), nb) == L.E_ARG   # alignment
+    assert lib.dugks3_set_source_terms(h, 2, g, pw, gm, sc, nb - 1) == L.E_NOMEM
+    assert lib.dugks3_set_source_terms(h, 2, g, pw, gm, sc, nb) == L.OK
+    assert lib.dugks3_set_source_terms(h, 0, None, None, None, None, 0) == L.OK
+    lib.dugks3_destroy(h)
+
+
 def test_d3q7_accepts_only_identity_diffusion():
     lib = L.lib()
     rc, h = _create3(q=7)
