@@ -332,10 +332,15 @@ int dugks3_create(dugks3_ctx** out, int nx, int ny, int nz, const double* xf, co
   const size_t plane = (size_t)nz * ny * x->pitch;
   x->buf_bytes = plane * q * x->elem();
   if (x->buf_bytes >= 4294967296ull) return x->fail(DUGKS_E_ARG, "one state buffer exceeds 4 GiB");
-  size_t off = 0;
-  x->off_table = off; off += align256(sizeof(Inst3));
+  // The state buffers start 2 KiB into the workspace, the instance table
+  // after them, so that the table's size does not move them: the step's
+  // speed depends on where they sit (HBM channel and L2 mapping).  Over
+  // offsets from 0 to 2 MiB on a 256^3 D3Q19 mesh, 2 KiB is among the
+  // fastest in both storages, while 2304 B costs binary64 9%.
+  size_t off = 2048;
   x->off_buf[0] = off; off += align256(x->buf_bytes);
   x->off_buf[1] = off; off += align256(x->buf_bytes);
+  x->off_table = off; off += align256(sizeof(Inst3));
   for (int a = 0; a < 3; ++a) {
     x->off_geo[a] = off; off += align256(sizeof(double) * x->geo[a].size());
     x->off_geof[a] = off; off += align256(sizeof(float) * x->geo[a].size());
