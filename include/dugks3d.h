@@ -21,7 +21,7 @@
  * fbar+_g = E(phi_g) + fbar+_a - E(phi_a), a the nearest interior cell);
  * D3Q7 uses weights 0 and 1/6 and the linear equilibrium of Remark 3
  * (D = phi I only).  Sources F(x, t, phi) as in two dimensions
- * (dugks3_set_source_terms) run a two-pass step with a caller-provided
+ * (dugks3_set_source_terms) run a three-pass step with a caller-provided
  * scratch array.
  */
 #ifndef DUGKS3D_H
@@ -92,8 +92,11 @@ int dugks3_set_phi(dugks3_ctx* ctx, const double* phi, int on_device);
 /* f~ [q][nz][ny][nx] (binary64) as the state; resets the step count. */
 int dugks3_set_f(dugks3_ctx* ctx, const double* f, int on_device);
 
-/* Bytes of the scratch array the source path needs (g of every cell and of
- * the ghost shell: q (nx+2)(ny+2)(nz+2) values of the storage type). */
+/* Bytes of the scratch array the source path needs, in values of the storage
+ * type: g of every cell and of the ghost shell (q (nx+2)(ny+2)(nz+2)), then
+ * the fluxes of every face for the directions that cross it (10 for D3Q15
+ * and D3Q19, 2 for D3Q7) per axis ((nx+1) ny nz faces normal to x, nx (ny+1)
+ * nz to y, nx ny (nz+1) to z), each part rounded up to 256 bytes. */
 size_t dugks3_source_scratch_bytes(const dugks3_ctx* ctx);
 
 /* Source F(x, t, phi) = sum_{j < nterms} exp(gammas[j] t) phi^powers[j] G_j(x)
@@ -107,10 +110,11 @@ size_t dugks3_source_scratch_bytes(const dugks3_ctx* ctx);
  * takes the G_j of the cell it copies), by Newton's method when F depends on
  * phi (binary64: update <= 1e-15 (1 + |phi|), at most 8; binary32: 2.4e-7,
  * at most 6).  Set before dugks3_set_phi (f~ = E(phi) - dt S / 2 at t = 0).
- * With a source the step runs two passes through scratch_dev (device,
+ * With a source the step runs three passes through scratch_dev (device,
  * caller-owned, 256-byte aligned, >= dugks3_source_scratch_bytes).  Errors:
  * E_ARG (nterms, a power out of range, a rate not finite, NULL arrays or
- * scratch), E_NOMEM (scratch too small). */
+ * scratch, a mesh whose g array, the first part of the scratch, would reach
+ * 4 GiB), E_NOMEM (scratch too small). */
 int dugks3_set_source_terms(dugks3_ctx* ctx, int nterms, const double* g_dev, const int* powers,
                             const double* gammas, void* scratch_dev, size_t scratch_bytes);
 

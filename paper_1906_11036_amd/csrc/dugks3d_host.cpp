@@ -98,8 +98,12 @@ struct dugks3_ctx {
   int src_pow[DUGKS_MAX_SRC_TERMS] = {0};
   double src_gam[DUGKS_MAX_SRC_TERMS] = {0};
   void* src_scratch = nullptr;
+  // the source path's scratch: g of every cell and ghost, then the three
+  // axes' flux arrays, each from a 256-byte boundary
+  size_t scratch_g_bytes() const { return align256((size_t)q * (n[0] + 2) * (n[1] + 2) * (n[2] + 2) * elem()); }
+  size_t scratch_flux_bytes(int a) const { return align256(src3_flux_values(q, a, n[0], n[1], n[2]) * elem()); }
   size_t scratch_bytes() const {
-    return align256((size_t)q * (n[0] + 2) * (n[1] + 2) * (n[2] + 2) * elem());
+    return scratch_g_bytes() + scratch_flux_bytes(0) + scratch_flux_bytes(1) + scratch_flux_bytes(2);
   }
 
   int fail(int rc, const std::string& m) { err = m; return rc; }
@@ -202,6 +206,14 @@ struct dugks3_ctx {
     for (int a = 0; a < 3; ++a)
       for (int m = 0; m < 4; ++m) d3.bp[a][m] = p.c * (m + 1) * b[a][m + 1] / cs2;
     d3.gscr = src_scratch;
+    d3.gscr_bytes = src_scratch ? (unsigned)((size_t)q * (n[0] + 2) * (n[1] + 2) * (n[2] + 2) * elem()) : 0u;
+    {
+      size_t o = scratch_g_bytes();
+      for (int a = 0; a < 3; ++a) {
+        d3.fscr[a] = src_scratch ? (void*)((char*)src_scratch + o) : nullptr;
+        o += scratch_flux_bytes(a);
+      }
+    }
     for (int i = 0; i < q; ++i)
       for (int m = 0; m < kMaxCoef; ++m) {
         d3.e[i][m] = e[i][m];
@@ -476,6 +488,8 @@ int dugks3_set_source_terms(dugks3_ctx* ctx, int nterms, const double* g_dev, co
       if (powers[t] < 0 || powers[t] > DUGKS_MAX_SRC_POW) return ctx->fail(DUGKS_E_ARG, "power out of range");
       if (!std::isfinite(gammas[t])) return ctx->fail(DUGKS_E_ARG, "growth rate not finite");
     }
+    if (ctx->scratch_g_bytes() >= 4294967296ull)
+      return ctx->fail(DUGKS_E_ARG, "mesh too large for the source path (g of all cells reaches 4 GiB)");
     if (!scratch_dev || ((uintptr_t)scratch_dev & 255) != 0)
       return ctx->fail(DUGKS_E_ARG, "scratch must be a 256-byte aligned device buffer");
     if (scratch_bytes < ctx->scratch_bytes()) return ctx->fail(DUGKS_E_NOMEM, "scratch too small");

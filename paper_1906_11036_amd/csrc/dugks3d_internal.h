@@ -60,6 +60,8 @@ struct alignas(64) Inst3 {
   double dt, lambda;
   double bp[3][4];         // c B'_a(phi) / c_s^2 as polynomials in phi (B' has degree <= 3)
   void* gscr;              // source path: g of every cell and ghost, [q][nz+2][ny+2][nx+2]
+  unsigned gscr_bytes;     // its size (< 4 GiB)
+  void* fscr[3];           // source path: fluxes of the faces normal to x, y, z, [slot][face]
 };
 
 struct Launch3 {
@@ -88,9 +90,12 @@ inline long long shell_len(int nx, int ny, int nz) {
 long long step3_blocks(const Inst3& h, const Launch3& l);
 // step: the step index since the state was set (selects the Dirichlet data)
 int launch_step3(const Inst3* d, const Inst3& h, int parity, long long step, const Launch3& l, void* stream);
-// the step with sources: g of every cell and ghost into h.gscr, then the
-// faces and the update, one thread per cell
+// the step with sources: g of every cell and ghost into h.gscr, each face's
+// fluxes into h.fscr, then the update
 int launch_src3_step(const Inst3* d, const Inst3& h, int parity, long long step, void* stream);
+// values in the source path's flux array of one axis: the directions that
+// cross a face normal to it times the faces ((nx+1) ny nz for x, ...)
+size_t src3_flux_values(int q, int axis, int nx, int ny, int nz);
 // LDS bytes of one block of the step kernel (walls: the instantiation with
 // mirror code, for a non-periodic axis or more than four coefficients)
 size_t step3_lds_bytes(int storage, int q, bool walls, const Launch3& l);

@@ -88,6 +88,9 @@ template <int NC, typename T> __device__ __forceinline__ T horner(const T* c, T 
 // Uniform reads through the constant address space become scalar loads.
 template <typename T> using CPtr = const __attribute__((address_space(4))) T*;
 template <typename T> __device__ __forceinline__ CPtr<T> as_constant(const T* p) { return (CPtr<T>)p; }
+// global memory (plain vector loads and stores, not flat ones)
+template <typename T> using GPtr = __attribute__((address_space(1))) T*;
+template <typename T> __device__ __forceinline__ GPtr<T> as_global(T* p) { return (GPtr<T>)p; }
 
 // ------------------------------------------------------------ lane shifts
 // wave_shr:1 -> lane l receives lane l-1; wave_shl:1 -> lane l receives lane l+1
@@ -1694,10 +1697,10 @@ size_t step3_lds_bytes(int storage, int q, bool walls, const Launch3& l) {
   } while (0)
 
 // ------------------------------------------------ the step with sources
-// Two passes, one thread per cell: g of every cell and ghost (with the source
-// and the ghost rules) into the scratch array, then each cell's six faces and
-// its update from that array.  Not the fused design of the source-free step:
-// each face is formed twice and g is written and read once more.
+// Three passes through the scratch array, one thread per cell or face: g of
+// every cell and ghost (with the source and the ghost rules); each face once,
+// its fluxes into per-axis arrays; each cell's update from them.  Not the fused
+// design of the source-free step: g and the fluxes cross HBM once more.
 
 // E_k(x) with the instance's runtime number of coefficients
 template <typename T> __device__ inline T eq_rt(const Inst3* __restrict__ I, int k, T x) {
@@ -1762,15 +1765,112 @@ __global__ __launch_bounds__(256) void k_src3_g(const Inst3* __restrict__ I, int
   for (int m = 0; m < Q; ++m) gs[m * NP + n] = g[m];
 }
 
-// Faces and update of one cell from the scratch g: reconstruction (eq. 2.20)
-// and characteristic shift (eq. 2.19 as eq. 2.26) on the scaled g, phi_b =
-// b1 sum gbar solved with F at the face at t_n + h (phi_b = sum fbar + h
-// F(phi_b) / 2, each G_j interpolated between the two cells' centres),
+// Number of directions with a nonzero velocity component along axis A
+// before direction k (the slot of k among the directions that cross a face
+// normal to A), and their count.
+template <int Q, int A> __host__ __device__ constexpr int cross_slot(int k) {
+  int n = 0;
+  for (int m = 0; m < k; ++m) n += ce<Q>(m, A) != 0;
+  return n;
+}
+template <int Q, int A> __host__ __device__ constexpr int cross_count() { return cross_slot<Q, A>(Q); }
+
+// Index of the face normal to axis A between cells (i,j,k) - e_A and (i,j,k)
+// (the coordinate along A runs over 0..n_A): x fastest, then y, then z.
+template <int A> __device__ __forceinline__ unsigned face_index(int nx, int ny, int i, int j, int k) {
+  if constexpr (A == 0) return ((unsigned)k * ny + j) * (nx + 1) + i;
+  else if constexpr (A == 1) return ((unsigned)k * (ny + 1) + j) * nx + i;
+  else return ((unsigned)k * ny + j) * nx + i;
+}
+
+// One face normal to axis A from the scratch g: reconstruction (eq. 2.20) and
+// characteristic shift (eq. 2.19 as eq. 2.26) on the scaled g, phi_b = b1 sum
+// gbar solved with F at the face at t_n + h (phi_b = sum fbar + h F(phi_b) /
+// 2, each G_j interpolated between the two cells' centres), and
 // F = f_b / b3 = (a3 b1/b3) gbar + E(phi_b) + lambda F(phi_b) rho(phi_b)
-// (eq. 2.27 solved for f), and f~(t+dt) = f~+ - dt c.(flux differences) /
-// width (eq. 2.24) with f~+ = (4/3) b1 g - f~ / 3.
+// (eq. 2.27 solved for f) of each direction that crosses the face, into the
+// axis's flux array [slot][face].
+template <int Q, int ST, int A>
+__global__ __launch_bounds__(256) void k_src3_face(const Inst3* __restrict__ I, long long step) {
+  using T = typename S3<ST>::T;
+  constexpr int t1 = A == 0 ? 1 : 0, t2 = A == 2 ? 1 : 2;
+  const int nx = I->n[0], ny = I->n[1], nz = I->n[2];
+  const int fx = nx + (A == 0), fy = ny + (A == 1);
+  const long long nf = (long long)fx * fy * (nz + (A == 2));
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nf) return;
+  int R[3];
+  R[0] = (int)(n % fx);
+  R[1] = (int)((n / fx) % fy);
+  R[2] = (int)(n / ((long long)fx * fy));
+  int L[3] = {R[0], R[1], R[2]};
+  L[A] -= 1;
+  const int px = nx + 2, py = ny + 2;
+  const long long NP = (long long)px * py * (nz + 2);
+  // g through a buffer resource: a 32-bit byte offset per neighbour, the
+  // direction's plane offset in a scalar register
+  const __amdgpu_buffer_rsrc_t Rg = rsrc(I->gscr, I->gscr_bytes);
+  const unsigned pl = (unsigned)NP * (unsigned)sizeof(T);
+  auto at = [&](const int* c, int da, int db) -> unsigned {   // byte offset of c + da e_t1 + db e_t2
+    int x[3] = {c[0], c[1], c[2]};
+    x[t1] += da;
+    x[t2] += db;
+    return (((unsigned)(x[2] + 1) * py + (x[1] + 1)) * px + (x[0] + 1)) * (unsigned)sizeof(T);
+  };
+  auto G = [&](unsigned o, int m) -> T {
+    if constexpr (sizeof(T) == 8)
+      return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(Rg, o, (unsigned)m * pl, 0));
+    else
+      return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(Rg, o, (unsigned)m * pl, 0));
+  };
+  const unsigned oL = at(L, 0, 0), oR = at(R, 0, 0);
+  const unsigned oL1p = at(L, 1, 0), oL1m = at(L, -1, 0), oR1p = at(R, 1, 0), oR1m = at(R, -1, 0);
+  const unsigned oL2p = at(L, 0, 1), oL2m = at(L, 0, -1), oR2p = at(R, 0, 1), oR2m = at(R, 0, -1);
+  const T* ga = C3<T>::geo(I, A);
+  const int m = R[A];
+  const T am = ga[(m + 1) * kGeo + 0], a0 = ga[(m + 1) * kGeo + 1], ap = ga[(m + 1) * kGeo + 2];
+  const T tau1 = C3<T>::geo(I, t1)[(R[t1] + 1) * kGeo + 3];
+  const T tau2 = C3<T>::geo(I, t2)[(R[t2] + 1) * kGeo + 3];
+  T gb[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int cn = ce<Q>(q, A), c1 = ce<Q>(q, t1), c2 = ce<Q>(q, t2);
+    const T gl = G(oL, q), gr = G(oR, q);
+    const T al = cn > 0 ? ap : (cn < 0 ? am : a0);
+    T v = fma(al, gr - gl, gl);
+    if (c1 != 0) {
+      const T ts = (G(oL1p, q) - G(oL1m, q)) + (G(oR1p, q) - G(oR1m, q));
+      v = fma((T)(-c1) * tau1, ts, v);
+    }
+    if (c2 != 0) {
+      const T ts = (G(oL2p, q) - G(oL2m, q)) + (G(oR2p, q) - G(oR2m, q));
+      v = fma((T)(-c2) * tau2, ts, v);
+    }
+    gb[q] = v;
+  }
+  const T b1 = C3<T>::b1(I), rb = C3<T>::rb(I), lam = (T)I->lambda;
+  const T hh = (T)(0.25 * I->dt);   // h / 2
+  T pb = (T)(dir_sum<Q>(gb) * b1);
+  const long long cL = ((long long)src_index(L[2], nz, I->bc[2]) * ny + src_index(L[1], ny, I->bc[1])) * nx +
+                       src_index(L[0], nx, I->bc[0]);
+  const long long cR = ((long long)src_index(R[2], nz, I->bc[2]) * ny + src_index(R[1], ny, I->bc[1])) * nx +
+                       src_index(R[0], nx, I->bc[0]);
+  double ad[4];
+  src_coefs3(I, cL, cR, (double)a0, ((double)step + 0.5) * I->dt, ad);
+  const T af[4] = {(T)ad[0], (T)ad[1], (T)ad[2], (T)ad[3]};
+  pb = solve_conserved3<T>(pb, hh, af, I->src_implicit != 0);
+  const T lfb = lam * poly4(af, pb);
+  const GPtr<T> fl = as_global((T*)I->fscr[A]);
+#pragma unroll
+  for (int q = 0; q < Q; ++q)
+    if (ce<Q>(q, A) != 0)
+      fl[cross_slot<Q, A>(q) * nf + n] = fma(rb, gb[q], eq_rt<T>(I, q, pb) + lfb * (T)rho3<Q>(I, q, (double)pb));
+}
+
+// The update of one cell: f~(t+dt) = f~+ - dt c.(flux differences) / width
+// (eq. 2.24) with f~+ = (4/3) b1 g - f~ / 3, the fluxes of x, y and z in turn.
 template <int Q, int ST>
-__global__ __launch_bounds__(256) void k_src3_step(const Inst3* __restrict__ I, int parity, long long step) {
+__global__ __launch_bounds__(256) void k_src3_update(const Inst3* __restrict__ I, int parity) {
   using T = typename S3<ST>::T;
   const int nx = I->n[0], ny = I->n[1], nz = I->n[2];
   const long long N = (long long)nx * ny * nz;
@@ -1779,88 +1879,61 @@ __global__ __launch_bounds__(256) void k_src3_step(const Inst3* __restrict__ I, 
   const int i = (int)(n % nx), j = (int)((n / nx) % ny), k = (int)(n / ((long long)nx * ny));
   const int px = nx + 2, py = ny + 2;
   const long long NP = (long long)px * py * (nz + 2);
-  const T* gs = (const T*)I->gscr;
-  auto G = [&](int ii, int jj, int kk, int m) -> T {
-    return gs[m * NP + ((long long)(kk + 1) * py + (jj + 1)) * px + (ii + 1)];
-  };
+  const long long cp = ((long long)(k + 1) * py + (j + 1)) * px + (i + 1);
   const long long off = ((long long)k * ny + j) * I->pitch + i;
-  const T* buf = (const T*)I->buf[parity];
-  const T kg = C3<T>::kg(I), rb = C3<T>::rb(I), b1 = C3<T>::b1(I), lam = (T)I->lambda;
-  const T hh = (T)(0.25 * I->dt);   // h / 2
-  const double tf = ((double)step + 0.5) * I->dt;
+  const GPtr<const T> gs = as_global((const T*)I->gscr);
+  const GPtr<const T> buf = as_global((const T*)I->buf[parity]);
+  const T kg = C3<T>::kg(I);
   T O[Q];
 #pragma unroll
-  for (int m = 0; m < Q; ++m) O[m] = fma(kg, G(i, j, k, m), (T)(-1.0 / 3.0) * buf[m * I->plane + off]);
+  for (int m = 0; m < Q; ++m) O[m] = fma(kg, gs[m * NP + cp], (T)(-1.0 / 3.0) * buf[m * I->plane + off]);
+  const long long nf[3] = {(long long)(nx + 1) * ny * nz, (long long)nx * (ny + 1) * nz,
+                           (long long)nx * ny * (nz + 1)};
+  const unsigned f0[3] = {face_index<0>(nx, ny, i, j, k), face_index<1>(nx, ny, i, j, k),
+                          face_index<2>(nx, ny, i, j, k)};
+  const unsigned step_a[3] = {1u, (unsigned)nx, (unsigned)nx * ny};   // the next face along the axis
   const int idx[3] = {i, j, k};
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const T* ga = C3<T>::geo(I, a);
-    const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
-    const T tau1 = C3<T>::geo(I, t1)[(idx[t1] + 1) * kGeo + 3];
-    const T tau2 = C3<T>::geo(I, t2)[(idx[t2] + 1) * kGeo + 3];
-    T flux[2][Q];
+    const T ka = C3<T>::geo(I, a)[(idx[a] + 1) * kGeo + 4];
+    const GPtr<const T> fl = as_global((const T*)I->fscr[a]);
 #pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      int L[3] = {i, j, k}, R[3] = {i, j, k};
-      if (side == 0) L[a] -= 1; else R[a] += 1;
-      const int m = R[a];
-      const T am = ga[(m + 1) * kGeo + 0], a0 = ga[(m + 1) * kGeo + 1], ap = ga[(m + 1) * kGeo + 2];
-      T gb[Q];
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        const int cn = ce<Q>(q, a), c1 = ce<Q>(q, t1), c2 = ce<Q>(q, t2);
-        const T gl = G(L[0], L[1], L[2], q), gr = G(R[0], R[1], R[2], q);
-        const T al = cn > 0 ? ap : (cn < 0 ? am : a0);
-        T v = fma(al, gr - gl, gl);
-        if (c1 != 0) {
-          int lp[3] = {L[0], L[1], L[2]}, lm[3] = {L[0], L[1], L[2]}, rp[3] = {R[0], R[1], R[2]}, rm[3] = {R[0], R[1], R[2]};
-          lp[t1] += 1; lm[t1] -= 1; rp[t1] += 1; rm[t1] -= 1;
-          const T ts = (G(lp[0], lp[1], lp[2], q) - G(lm[0], lm[1], lm[2], q)) +
-                       (G(rp[0], rp[1], rp[2], q) - G(rm[0], rm[1], rm[2], q));
-          v = fma((T)(-c1) * tau1, ts, v);
-        }
-        if (c2 != 0) {
-          int lp[3] = {L[0], L[1], L[2]}, lm[3] = {L[0], L[1], L[2]}, rp[3] = {R[0], R[1], R[2]}, rm[3] = {R[0], R[1], R[2]};
-          lp[t2] += 1; lm[t2] -= 1; rp[t2] += 1; rm[t2] -= 1;
-          const T ts = (G(lp[0], lp[1], lp[2], q) - G(lm[0], lm[1], lm[2], q)) +
-                       (G(rp[0], rp[1], rp[2], q) - G(rm[0], rm[1], rm[2], q));
-          v = fma((T)(-c2) * tau2, ts, v);
-        }
-        gb[q] = v;
-      }
-      T pb = (T)(dir_sum<Q>(gb) * b1);
-      const long long cL = ((long long)src_index(L[2], nz, I->bc[2]) * ny + src_index(L[1], ny, I->bc[1])) * nx +
-                           src_index(L[0], nx, I->bc[0]);
-      const long long cR = ((long long)src_index(R[2], nz, I->bc[2]) * ny + src_index(R[1], ny, I->bc[1])) * nx +
-                           src_index(R[0], nx, I->bc[0]);
-      double ad[4];
-      src_coefs3(I, cL, cR, (double)a0, tf, ad);
-      const T af[4] = {(T)ad[0], (T)ad[1], (T)ad[2], (T)ad[3]};
-      pb = solve_conserved3<T>(pb, hh, af, I->src_implicit != 0);
-      const T lfb = lam * poly4(af, pb);
-#pragma unroll
-      for (int q = 0; q < Q; ++q)
-        if (ce<Q>(q, a) != 0)
-          flux[side][q] = fma(rb, gb[q], eq_rt<T>(I, q, pb) + lfb * (T)rho3<Q>(I, q, (double)pb));
+    for (int q = 0; q < Q; ++q) {
+      const int c = ce<Q>(q, a);
+      if (c == 0) continue;
+      const int sl = a == 0 ? cross_slot<Q, 0>(q) : (a == 1 ? cross_slot<Q, 1>(q) : cross_slot<Q, 2>(q));
+      const GPtr<const T> row = fl + sl * nf[a];
+      O[q] = fma((T)(-c) * ka, row[f0[a] + step_a[a]] - row[f0[a]], O[q]);
     }
-    const T ka = ga[(idx[a] + 1) * kGeo + 4];
-#pragma unroll
-    for (int q = 0; q < Q; ++q)
-      if (ce<Q>(q, a) != 0) O[q] = fma((T)(-ce<Q>(q, a)) * ka, flux[1][q] - flux[0][q], O[q]);
   }
-  T* out = (T*)I->buf[parity ^ 1];
+  const GPtr<T> out = as_global((T*)I->buf[parity ^ 1]);
 #pragma unroll
   for (int m = 0; m < Q; ++m) out[m * I->plane + off] = O[m];
 }
 
 template <int Q, int ST>
 static int src3_go(const Inst3* d, const Inst3& h, int parity, const double* ring, long long step, hipStream_t st) {
-  const long long NP = (long long)(h.n[0] + 2) * (h.n[1] + 2) * (h.n[2] + 2);
-  const long long N = (long long)h.n[0] * h.n[1] * h.n[2];
+  const long long nx = h.n[0], ny = h.n[1], nz = h.n[2];
+  const long long NP = (nx + 2) * (ny + 2) * (nz + 2);
+  const long long N = nx * ny * nz;
+  const long long nf[3] = {(nx + 1) * ny * nz, nx * (ny + 1) * nz, nx * ny * (nz + 1)};
   if ((NP + 255) / 256 > 0x7fffffffLL) return -1;
   hipLaunchKernelGGL((k_src3_g<Q, ST>), dim3((unsigned)((NP + 255) / 256)), dim3(256), 0, st, d, parity, ring, step);
-  hipLaunchKernelGGL((k_src3_step<Q, ST>), dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, d, parity, step);
+  hipLaunchKernelGGL((k_src3_face<Q, ST, 0>), dim3((unsigned)((nf[0] + 255) / 256)), dim3(256), 0, st, d, step);
+  hipLaunchKernelGGL((k_src3_face<Q, ST, 1>), dim3((unsigned)((nf[1] + 255) / 256)), dim3(256), 0, st, d, step);
+  hipLaunchKernelGGL((k_src3_face<Q, ST, 2>), dim3((unsigned)((nf[2] + 255) / 256)), dim3(256), 0, st, d, step);
+  hipLaunchKernelGGL((k_src3_update<Q, ST>), dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, d, parity);
   return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+static_assert(cross_count<19, 0>() == 10 && cross_count<19, 1>() == 10 && cross_count<19, 2>() == 10, "D3Q19");
+static_assert(cross_count<15, 0>() == 10 && cross_count<15, 1>() == 10 && cross_count<15, 2>() == 10, "D3Q15");
+static_assert(cross_count<7, 0>() == 2 && cross_count<7, 1>() == 2 && cross_count<7, 2>() == 2, "D3Q7");
+
+size_t src3_flux_values(int q, int axis, int nx, int ny, int nz) {
+  const int cross = q == 7 ? 2 : 10;   // cross_count of the lattice (the same for every axis)
+  const size_t faces = (size_t)(nx + (axis == 0)) * (ny + (axis == 1)) * (nz + (axis == 2));
+  return cross * faces;
 }
 
 int launch_src3_step(const Inst3* d, const Inst3& h, int parity, long long step, void* stream) {
