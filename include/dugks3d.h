@@ -172,6 +172,17 @@ int dugks3_set_launch(dugks3_ctx* ctx, int rows_per_block, int planes_per_block)
 /* Time nsteps steps with hipEvents on the bound stream (the state advances). */
 int dugks3_time_steps(dugks3_ctx* ctx, int nsteps, float* ms_total);
 
+/* Time trial_steps steps (at least 1, after one untimed step) for every
+ * valid launch shape (rows per block in the storage's range, planes per
+ * block 4, 8, ..., 128, within the LDS limit) and keep the fastest.  Trial
+ * steps read the current state and the current step's Dirichlet data and
+ * write only the inactive buffer: the state and the step count are
+ * unchanged, and since every launch gives bitwise the same result, so is
+ * every later step.  With sources set the step has no launch shape and the
+ * call changes nothing.  Synchronises.  Errors: E_STATE (not bound, no
+ * state, Dirichlet data not covering the current step), E_HIP. */
+int dugks3_autotune(dugks3_ctx* ctx, int trial_steps);
+
 int dugks3_get_info(const dugks3_ctx* ctx, dugks3_info* out);
 const char* dugks3_last_error(const dugks3_ctx* ctx);
 void dugks3_destroy(dugks3_ctx* ctx);

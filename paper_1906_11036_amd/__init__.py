@@ -505,6 +505,10 @@ class Solver3D:
         L.check3(self.lib.dugks3_set_launch(self.h, int(rows_per_block), int(planes_per_block)), self.h,
                  "dugks3_set_launch")
 
+    def autotune(self, trial_steps=3):
+        """Keep the fastest launch shape (dugks3_autotune; the state is unchanged)."""
+        L.check3(self.lib.dugks3_autotune(self.h, int(trial_steps)), self.h, "dugks3_autotune")
+
     def info(self) -> dict:
         inf = L.Info3()
         L.check3(self.lib.dugks3_get_info(self.h, C.byref(inf)), self.h, "dugks3_get_info")

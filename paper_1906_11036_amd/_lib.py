@@ -140,6 +140,7 @@ SIGNATURES = {
     "dugks3_reduce": (_int, [_vp, _vp, _dp, _dp, _dp]),
     "dugks3_set_launch": (_int, [_vp, _int, _int]),
     "dugks3_time_steps": (_int, [_vp, _int, C.POINTER(C.c_float)]),
+    "dugks3_autotune": (_int, [_vp, _int]),
     "dugks3_get_info": (_int, [_vp, C.POINTER(Info3)]),
     "dugks3_last_error": (C.c_char_p, [_vp]),
     "dugks3_destroy": (None, [_vp]),

@@ -594,6 +594,59 @@ int dugks3_time_steps(dugks3_ctx* ctx, int nsteps, float* ms) {
   return er == hipSuccess ? DUGKS_OK : ctx->hipfail(er, "timing");
 }
 
+int dugks3_autotune(dugks3_ctx* ctx, int trial_steps) {
+  GUARD3(ctx);
+  if (!ctx->bound()) return ctx->fail(DUGKS_E_STATE, "not bound");
+  if (!ctx->initialised) return ctx->fail(DUGKS_E_STATE, "state not initialised");
+  if (ctx->any_dirichlet() && (ctx->ring == nullptr || ctx->step + 1 > ctx->ring_steps))
+    return ctx->fail(DUGKS_E_STATE, "Dirichlet data does not cover the current step");
+  if (ctx->src_n > 0) return DUGKS_OK;   // the source step has no launch shape to choose
+  if (trial_steps < 1) trial_steps = 1;
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return ctx->fail(DUGKS_E_HIP, "event create");
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return ctx->fail(DUGKS_E_HIP, "event create");
+  }
+  // every trial reads the current buffer and writes only the other one, with
+  // the current step's Dirichlet data: the state does not change
+  const int parity = (int)(ctx->step & 1);
+  const bool f64 = ctx->p.storage == DUGKS_F64;
+  const int rmin = f64 ? kMinRows64 : kMinRows32, rmax = f64 ? kMaxRows64 : kMaxRows32;
+  const int planes_c[] = {4, 8, 16, 32, 64, 128};
+  Launch3 best = ctx->launch;
+  float best_ms = 1e30f;
+  int rc = DUGKS_OK;
+  hipError_t er = hipSuccess;
+  for (int rows = rmin; rows <= rmax && rc == DUGKS_OK && er == hipSuccess; ++rows)
+    for (int planes : planes_c) {
+      Launch3 l;
+      l.rows = rows;
+      l.planes = planes;
+      if (ctx->lds_bytes(l) > ctx->lds_limit()) continue;
+      if (launch_step3(ctx->dev(), ctx->host, parity, ctx->step, l, ctx->stream)) { rc = DUGKS_E_HIP; break; }
+      er = hipEventRecord(a, ctx->stream);
+      for (int t = 0; t < trial_steps && er == hipSuccess && rc == DUGKS_OK; ++t)
+        if (launch_step3(ctx->dev(), ctx->host, parity, ctx->step, l, ctx->stream)) rc = DUGKS_E_HIP;
+      if (rc != DUGKS_OK) break;
+      if (er == hipSuccess) er = hipEventRecord(b, ctx->stream);
+      if (er == hipSuccess) er = hipEventSynchronize(b);
+      float ms = 0.0f;
+      if (er == hipSuccess) er = hipEventElapsedTime(&ms, a, b);
+      if (er != hipSuccess) break;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = l;
+      }
+    }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (rc != DUGKS_OK) return ctx->fail(rc, "autotune launch failed");
+  if (er != hipSuccess) return ctx->hipfail(er, "autotune timing");
+  ctx->launch = best;
+  return DUGKS_OK;
+}
+
 int dugks3_get_info(const dugks3_ctx* ctx, dugks3_info* out) {
   if (!ctx || ctx->magic != kMagic3 || !out) return DUGKS_E_ARG;
   memset(out, 0, sizeof(*out));

@@ -196,6 +196,7 @@ def test_3d_sizes_and_state_errors():
         assert info.nz == 5 and info.q == 19
         assert lib.dugks3_workspace_bytes(h) >= 2 * info.state_bytes
         assert lib.dugks3_step(h, 1) == L.E_STATE
+        assert lib.dugks3_autotune(h, 2) == L.E_STATE      # not bound: no trial step
         # rows per block: binary64 1..2 interior rows, binary32 2..4 rows
         bad, good = ((3, 0), (1, 2)) if storage == L.F64 else ((5, 1), (2, 4))
         for rows in bad:

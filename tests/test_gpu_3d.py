@@ -166,6 +166,43 @@ def test_fp64_launch_shapes_give_identical_results(launch, q):
     assert np.array_equal(s.get_f(), ref.get_f())
 
 
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+@pytest.mark.parametrize("q,bc", [(19, (P, P, P)), (15, (M, P, D)), (7, (D, M, P))])
+def test_autotune_keeps_state_and_results(storage, q, bc):
+    """dugks3_autotune after some steps: the state is unchanged, the launch it keeps is a
+    valid shape, and later steps equal bitwise those of a run without it (with
+    Dirichlet walls, the trials read the current step's data only)."""
+    p = W.random_problem3d(83, 70, 9, 7, q=q, bc=bc, bdeg=2)
+    say(f"case 3d autotune {storage} q={q} bc={bc}")
+    ref = solver(p, storage)
+    ref.set_phi(p.phi0)
+    s = solver(p, storage)
+    s.set_phi(p.phi0)
+    if D in bc:
+        ref.set_dirichlet(p.rings(5))
+        s.set_dirichlet(p.rings(5))
+    ref.step(5)
+    s.step(2)
+    f0 = s.get_f()
+    s.autotune(2)
+    assert np.array_equal(s.get_f(), f0)
+    inf = s.info()
+    assert inf["rows_per_block"] in ((1, 2) if storage == "f64" else (2, 3, 4))
+    assert inf["planes_per_block"] in (4, 8, 16, 32, 64, 128)
+    s.step(3)
+    assert np.array_equal(s.get_f(), ref.get_f())
+
+
+def test_autotune_needs_the_current_steps_dirichlet_data():
+    p = W.random_problem3d(84, 12, 6, 5, q=19, bc=(D, P, P))
+    s = solver(p, "f64")
+    s.set_phi(p.phi0)
+    s.set_dirichlet(p.rings(2))
+    s.step(2)
+    with pytest.raises(dg.DugksError):
+        s.autotune(1)                  # the data ends at the current step: no trial is launched
+
+
 @pytest.mark.parametrize("q", [19, 15, 7])
 def test_fp32_against_oracle(q):
     p = W.random_problem3d(88 + q, 40, 12, 10, q=q, bc=(P, P, M), bdeg=2)
