@@ -559,7 +559,9 @@ def main():
                    "lattice": f"D2Q{problems[0].q}", "storage": args.storage,
                    "state_bytes": state_bytes, "rows_per_wave": info["rows_per_wave"],
                    "waves_per_block": info["waves_per_block"], "schedule": info["schedule"],
-                   "launch_from": tuned_from},
+                   "launch_from": tuned_from,
+                   # every instance x<->y symmetric: the binary32 and 16-bit steps share E between swapped pairs
+                   "xy_symmetric": bool(info["xy_symmetric"])},
         "hbm_gbps_algorithmic": round(achieved, 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),

@@ -67,7 +67,7 @@
 extern "C" {
 #endif
 
-#define DUGKS_ABI_VERSION 3
+#define DUGKS_ABI_VERSION 4
 #define DUGKS_MAX_DEG 4        /* B and D: polynomials in phi of degree <= 4 */
 #define DUGKS_MAX_SRC_TERMS 6  /* terms of a source F(x, t, phi) */
 #define DUGKS_MAX_SRC_POW 3    /* highest power of phi in a source term */
@@ -134,6 +134,11 @@ typedef struct dugks_info {
   size_t state_bytes;     /* bytes of one f~ buffer (read once and written once per step) */
   long long graph_steps;  /* steps replayed from captured hipGraphs since dugks_bind */
   long long eager_steps;  /* steps launched one by one since dugks_bind */
+  int xy_symmetric;       /* 1: E_i and E_j have bitwise the same coefficients for every pair
+                             i, j whose velocities differ by swapping x and y (B_x = B_y,
+                             D_xx = D_yy), in every instance of the context or batch; the
+                             binary32 and 16-bit steps without a source then evaluate one
+                             polynomial per pair (same values) */
 } dugks_info;
 
 typedef struct dugks_diag {

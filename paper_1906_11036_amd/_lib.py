@@ -10,7 +10,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdugks.so")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 ABI3_VERSION = 1
 ABI1_VERSION = 1
 MAX_DEG = 4
@@ -38,7 +38,7 @@ class Info(C.Structure):
                 ("q", C.c_int), ("storage", C.c_int), ("pitch", C.c_int), ("eq_degree", C.c_int),
                 ("rows_per_wave", C.c_int), ("waves_per_block", C.c_int), ("schedule", C.c_int),
                 ("xcd_remap", C.c_int), ("work_items", C.c_longlong), ("state_bytes", C.c_size_t),
-                ("graph_steps", C.c_longlong), ("eager_steps", C.c_longlong)]
+                ("graph_steps", C.c_longlong), ("eager_steps", C.c_longlong), ("xy_symmetric", C.c_int)]
 
 
 class Diag(C.Structure):

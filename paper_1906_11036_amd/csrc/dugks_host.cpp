@@ -42,6 +42,9 @@ struct Instance {
   std::vector<double> colgeo, rowgeo, widths;
   std::vector<float> colgeo_f, rowgeo_f;
   double e[kMaxQ][kMaxCoef] = {{0}};
+  // E_k = E_swap(k) bitwise for the pairs of directions that swapping x and y
+  // exchanges (1-2, 3-4, and 6-8 of D2Q9): the kernels then evaluate one of each
+  bool xy_sym = false;
   double bp[2][kRhoCoef] = {{0}};         // c B'(phi) / cs2 per axis, see InstDev
   // source terms exp(src_gam[j] t) phi^src_pow[j] G_j(x); G_j as [src_n][ny][nx]
   // (device, caller-owned)
@@ -220,6 +223,8 @@ static void equilibrium_polys(Instance& in) {
     }
   }
   in.ncoef = deg + 1;
+  auto same = [&](int i, int j) { return memcmp(in.e[i], in.e[j], sizeof(in.e[i])) == 0; };
+  in.xy_sym = same(1, 2) && same(3, 4) && (in.q == 5 || same(6, 8));
   // F_i + R_i = F w_i (1 + c_i.B'(phi) / cs2) (eq. 2.3, Remark 3) with
   // B'(phi) = sum_{k>=1} k b_k phi^(k-1); the kernels take c B' / cs2 per axis
   memset(in.bp, 0, sizeof(in.bp));
@@ -501,6 +506,8 @@ struct Engine {
     a.ncoef = ncoef_launch();
     a.persistent_blocks = persistent_blocks;
     a.src = source_kind();
+    a.sym = 1;
+    for (auto& in : inst) a.sym &= in.xy_sym ? 1 : 0;
     return a;
   }
 
@@ -853,6 +860,7 @@ struct Engine {
     o->state_bytes = in.buffer_bytes(storage);
     o->graph_steps = graph_steps;
     o->eager_steps = eager_steps;
+    o->xy_symmetric = step_args(0).sym;
   }
 
   ~Engine() {

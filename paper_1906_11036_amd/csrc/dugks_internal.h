@@ -104,6 +104,7 @@ struct StepArgs {
   long long step;           // step index of the input state
   int q, storage, ncoef;    // template selectors, uniform over the launch
   int src;                  // 0: no source; 1: one phi-free term each; kSrcPow: otherwise
+  int sym;                  // every instance x<->y symmetric (E_k = E_swap(k) bitwise)
   int persistent_blocks;    // blocks of the persistent schedule
   // when set, the step index is step + *step_base (captured graphs: step is the
   // offset within the graph, the base is written before each replay)

@@ -192,6 +192,22 @@ __device__ __forceinline__ float to_vgpr(float s) {
   return v;
 }
 
+// The direction whose velocity is direction k's with x and y swapped, and the
+// smaller index of the two.  When B_x = B_y and D_xx = D_yy, E_k = E_swap(k)
+// (eq. 2.3 is symmetric under the swap), so an x<->y symmetric instance
+// evaluates one polynomial for each such pair.
+template <int Q> __host__ __device__ constexpr int swap_xy(int k) {
+  for (int j = 0; j < Q; ++j)
+    if (lat_cx(j) == lat_cy(k) && lat_cy(j) == lat_cx(k)) return j;
+  return k;
+}
+template <int Q> __host__ __device__ constexpr int sym_rep(int k) {
+  return swap_xy<Q>(k) < k ? swap_xy<Q>(k) : k;
+}
+static_assert(sym_rep<9>(2) == 1 && sym_rep<9>(4) == 3 && sym_rep<9>(8) == 6 && sym_rep<9>(5) == 5 &&
+                  sym_rep<9>(7) == 7 && sym_rep<5>(2) == 1 && sym_rep<5>(4) == 3,
+              "D2Q9 / D2Q5 direction order");
+
 // p(x) = sum_{m < NC} c[m] x^m by Horner's rule
 template <int NC, typename T> __device__ __forceinline__ T horner(const T* c, T x) {
   T r = c[NC - 1];
@@ -203,8 +219,12 @@ template <int NC, typename T> __device__ __forceinline__ T horner(const T* c, T 
 // Coefficients of one instance for a work item.  Binary32 equilibria of
 // degree <= 3 (36 values for D2Q9) are loaded once into wave-uniform
 // registers and shared by the cell, the faces and the 16-bit encode; larger
-// sets are read through the scalar cache where they are used.
-template <typename T, int Q, int NC> struct Eq {
+// sets are read through the scalar cache where they are used.  SYM: every
+// instance of the launch is x<->y symmetric (E_k and E_swap(k) have the same
+// coefficients, checked bitwise on the host), and E_k evaluates the
+// polynomial of sym_rep(k), which the compiler then shares within a cell or
+// face: the same values with fewer instructions.
+template <typename T, int Q, int NC, bool SYM = false> struct Eq {
   static constexpr bool kHeld = sizeof(T) == 4 && NC <= 4;
   T c[kHeld ? Q : 1][kHeld ? NC : 1];
   const InstDev* I;
@@ -242,8 +262,9 @@ template <typename T, int Q, int NC> struct Eq {
     inv_b1 = I->inv_b1_of;
   }
   __device__ __forceinline__ T E(int k, T x) const {
-    if constexpr (kHeld) return horner<NC>(c[k], x);
-    else return horner<NC>(Coef<T>::e(I, k), x);
+    const int r = SYM ? sym_rep<Q>(k) : k;
+    if constexpr (kHeld) return horner<NC>(c[r], x);
+    else return horner<NC>(Coef<T>::e(I, r), x);
   }
 };
 
@@ -420,9 +441,9 @@ struct Scales {
 // With a source, pc = the coefficients of F at the cell centre at t_n as a
 // polynomial in phi: phi solves phi = sum f~ + dt F(phi) / 2 and g gains
 // lambda F rho(phi) (eqs. 2.25, 2.27).
-template <int Q, int ST, int NC, int NF = 0>
+template <int Q, int ST, int NC, int NF = 0, bool SYM = false>
 __device__ __forceinline__ void cell_g(const InstDev* __restrict__ I,
-                                       const Eq<typename Stor<ST>::T, Q, NC>& eq,
+                                       const Eq<typename Stor<ST>::T, Q, NC, SYM>& eq,
                                        const Raw<Q, ST>& r, const Scales& sc,
                                        typename Stor<ST>::T* g, typename Stor<ST>::T* ftp,
                                        bool want_ftp, typename Stor<ST>::T& phi_out,
@@ -486,9 +507,9 @@ __device__ __forceinline__ void cell_g(const InstDev* __restrict__ I,
 }
 
 // Ghost rules on g of the source cell a (already in g).
-template <int Q, int ST, int NC>
+template <int Q, int ST, int NC, bool SYM = false>
 __device__ __forceinline__ void ghost_g(const InstDev* __restrict__ I,
-                                        const Eq<typename Stor<ST>::T, Q, NC>& eq,
+                                        const Eq<typename Stor<ST>::T, Q, NC, SYM>& eq,
                                         typename Stor<ST>::T* g, typename Stor<ST>::T phi_a,
                                         bool wall_x, bool wall_y, double phi_g) {
   using T = typename Stor<ST>::T;
@@ -582,8 +603,8 @@ template <int Q, int NRM> constexpr unsigned normal_mask() {
 // phi_b, and they all take the same a0, so their sum is interpolated from the
 // two cells' sums zL, zR of g over those directions (plus their tangential
 // terms) instead of direction by direction.
-template <int Q, int NC, int NRM, typename T, int NF = 0, bool ZS = false>
-__device__ __forceinline__ void face(const Eq<T, Q, NC>& eq, const T* L, const T* R, const T* ts,
+template <int Q, int NC, int NRM, typename T, int NF = 0, bool ZS = false, bool SYM = false>
+__device__ __forceinline__ void face(const Eq<T, Q, NC, SYM>& eq, const T* L, const T* R, const T* ts,
                                      T am, T a0, T ap, T tau, T* out,
                                      const SrcEq<T, Q, NF>& se = {}, const T* pb_c = nullptr,
                                      T zL = 0, T zR = 0) {
@@ -661,7 +682,7 @@ __device__ __forceinline__ int xcd_logical(int b, int nblocks) {
 // terms, F a polynomial in phi).  An instance without a source has no terms
 // and gives the result of the source-free step; one with a single phi-free
 // term gives the same result in either kind of launch.
-template <int Q, int ST, int NC, bool GH, int NF>
+template <int Q, int ST, int NC, bool GH, int NF, bool SYM = false>
 __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const WorkItem it,
                                           int parity, long long step, int lane, bool measure) {
   using T = typename Stor<ST>::T;
@@ -673,7 +694,7 @@ __device__ __forceinline__ void step_item(const InstDev* __restrict__ I, const W
   constexpr bool ZS = Stor<ST>::neq;     // faces interpolate the zero-normal sums
   static_assert(PF == 1 || PF == 2, "one or two rows ahead");
   static_assert(!SRC || PF == 1, "source rows follow the one-row prefetch");
-  Eq<T, Q, NC> eq;
+  Eq<T, Q, NC, SYM> eq;
   eq.load(I);
   SrcEq<T, Q, NF> se;
   se.load(I);
@@ -988,7 +1009,7 @@ template <int ST, int NF> constexpr int step_max_threads() {
   return Occupancy<ST, NF>::value >= 2 ? 512 : 256;
 }
 
-template <int Q, int ST, int NC, int NF>
+template <int Q, int ST, int NC, int NF, bool SYM>
 __global__ __launch_bounds__((step_max_threads<ST, NF>())) __attribute__((amdgpu_waves_per_eu(Occupancy<ST, NF>::value)))
 void k_step(const InstDev* __restrict__ insts,
                                               const WorkItem* __restrict__ items, int nitems,
@@ -1010,9 +1031,9 @@ void k_step(const InstDev* __restrict__ insts,
     const bool wall_x = I->bcx != DUGKS_BC_PERIODIC && (it.x0 == 0 || it.x0 + kStripCols >= I->nx);
     const bool wall_y = I->bcy != DUGKS_BC_PERIODIC && (it.y0 == 0 || it.y1 == I->ny);
     if (wall_x || wall_y)
-      step_item<Q, ST, NC, true, NF>(I, it, parity, step, lane, measure != 0);
+      step_item<Q, ST, NC, true, NF, SYM>(I, it, parity, step, lane, measure != 0);
     else
-      step_item<Q, ST, NC, false, NF>(I, it, parity, step, lane, measure != 0);
+      step_item<Q, ST, NC, false, NF, SYM>(I, it, parity, step, lane, measure != 0);
     if (!persistent) break;
   }
 }
@@ -1427,24 +1448,30 @@ static int launch_step_q_st(const StepArgs& a, const Launch& l, void* stream, in
   if (persistent) blocks = a.persistent_blocks;
   if (blocks <= 0) return 0;
   dim3 grid(blocks), block(64 * wpb);
-#define DUGKS_STEP_LAUNCH(NC_, NF_)                                                          \
-  hipLaunchKernelGGL((k_step<Q, ST, NC_, NF_>), grid, block, 0, S(stream), a.insts, a.items, \
+#define DUGKS_STEP_LAUNCH(NC_, NF_, SYM_)                                                          \
+  hipLaunchKernelGGL((k_step<Q, ST, NC_, NF_, SYM_>), grid, block, 0, S(stream), a.insts, a.items, \
                      a.nitems, a.parity, a.step, l.xcd_remap, persistent, measure, a.step_base)
-#define DUGKS_STEP_NC(NF_)                                \
+#define DUGKS_STEP_NC(NF_, SYM_)                          \
   switch (a.ncoef) {                                      \
-    case 2: DUGKS_STEP_LAUNCH(2, NF_); break;             \
-    case 4: DUGKS_STEP_LAUNCH(4, NF_); break;             \
-    default: DUGKS_STEP_LAUNCH(8, NF_); break;            \
+    case 2: DUGKS_STEP_LAUNCH(2, NF_, SYM_); break;       \
+    case 4: DUGKS_STEP_LAUNCH(4, NF_, SYM_); break;       \
+    default: DUGKS_STEP_LAUNCH(8, NF_, SYM_); break;      \
   }
-  if constexpr (Stor<ST>::neq) {
+  if constexpr (Stor<ST>::neq) {   // bound by instructions: the symmetric variant pays most here
     if (a.src) return -1;  // sources run in binary64 / binary32 storage only
-    DUGKS_STEP_NC(0);
+    if (a.sym) {
+      DUGKS_STEP_NC(0, true);
+    } else {
+      DUGKS_STEP_NC(0, false);
+    }
   } else if (a.src == kSrcPow) {
-    DUGKS_STEP_NC(kSrcPow);
+    DUGKS_STEP_NC(kSrcPow, false);
   } else if (a.src) {
-    DUGKS_STEP_NC(1);
+    DUGKS_STEP_NC(1, false);
+  } else if (a.sym && ST == DUGKS_F32) {   // binary32 without a source: a little faster too
+    DUGKS_STEP_NC(0, true);
   } else {
-    DUGKS_STEP_NC(0);
+    DUGKS_STEP_NC(0, false);
   }
 #undef DUGKS_STEP_NC
 #undef DUGKS_STEP_LAUNCH

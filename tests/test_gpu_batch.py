@@ -60,6 +60,43 @@ def test_batch_equals_single_instances_bitwise(storage):
         assert np.array_equal(b.get_phi(i), s.get_phi()), (storage, i)
 
 
+def symmetric(p):
+    """p with B_y = B_x and D_yy = D_xx (x<->y symmetric equilibrium)."""
+    p.by, p.dyy = p.bx, p.dxx
+    return p
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16neq", "bf16neq"])
+@pytest.mark.parametrize("q", [9, 5])
+def test_xy_symmetric_kernel_gives_the_general_kernels_values(storage, q):
+    """Instances with B_x = B_y and D_xx = D_yy run alone in the kernel that evaluates
+    one equilibrium polynomial per x<->y pair of directions (binary32 and 16-bit storage,
+    no source); in a batch with an asymmetric instance the general kernel runs them.
+    Bitwise the same (ragged strips, mirror walls)."""
+    specs = [(70, 33, W.PERIODIC, 3), (64, 64, W.MIRROR, 2), (130, 9, W.PERIODIC, 1)]
+    syms = []
+    for k, (nx, ny, bc, bdeg) in enumerate(specs):
+        p = symmetric(W.random_problem(700 + k, nx, ny, q=q, bcx=bc, bcy=bc, stretched=(bc == W.MIRROR),
+                                       bdeg=bdeg, ddeg=2))
+        if bc == W.MIRROR:
+            p.bx = p.by = (0.0,)
+        syms.append(p)
+    asym = W.random_problem(710, 50, 30, q=q, bdeg=2)
+    assert asym.bx != asym.by
+    say(f"case xy-symmetric kernel {storage} q={q}")
+    b = dg.Batch(syms + [asym], storage=storage)
+    assert b.info(0)["xy_symmetric"] == 0
+    b.set_all_phi()
+    b.step(9)
+    for i, p in enumerate(syms):
+        s = dg.Solver(p, storage=storage)
+        assert s.info()["xy_symmetric"] == 1
+        s.set_phi(p.phi0)
+        s.step(9)
+        assert np.array_equal(b.get_phi(i), s.get_phi()), (storage, q, i)
+        s.close()
+
+
 @pytest.mark.parametrize("storage", ["f32", "f16neq"])
 def test_graph_replays_match_eager_steps(storage):
     """dugks_batch_step replays a captured hipGraph of 32 steps; single steps
