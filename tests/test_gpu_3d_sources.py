@@ -107,3 +107,39 @@ def test_zero_source_equals_fused_step(q):
     b.set_dirichlet(rings)
     b.step(4)
     assert rel_max(b.get_f(), a.get_f()) <= 1e-12
+
+
+def test_full_size_source_step_sampled():
+    """The 256^3 D3Q19 mesh with two source terms (one depending on phi), binary64: one step of
+    the three-pass source path from a seeded non-equilibrium state, checked at sampled cells
+    (faces, edges, corners and random interior cells) against the oracle's per-cell step.  Here
+    the offset of a direction's plane in the g array passes 2^31 bytes."""
+    p = W.workload3d("gaussian_hill3d_256")
+    n = p.nx
+    X, Y, Z = p.mesh()
+    p.src_terms = [(1, 0.2, 0.3 * np.cos(np.pi * X) * np.sin(np.pi * Y)), (0, -0.4, 0.1 + 0.05 * Z)]
+    del X, Y, Z
+    say(f"case full size 3-D source step {n}^3 f64")
+    f0 = W.random_distributions3d(4343, p.q, p.nz, p.ny, p.nx)
+    s = dg.Solver3D(p, storage="f64")
+    s.set_f(f0)
+    s.step(1)
+    gpu = s.get_f()
+    s.close()
+    o = Oracle3D(p)
+    o.set_f(f0)
+    del f0
+    rng = np.random.default_rng(n + 1)
+    pts = set()
+    for i in (0, 1, 61, 62, 63, 64, n - 2, n - 1):
+        for j in (0, 1, n // 2, n - 1):
+            for k in (0, 1, n - 2, n - 1):
+                pts.add((i, j, k))
+    for _ in range(300):
+        pts.add(tuple(int(v) for v in rng.integers(0, n, size=3)))
+    cells = np.array(sorted(pts))
+    ref = o.step_cells(cells)
+    got = gpu[:, cells[:, 2], cells[:, 1], cells[:, 0]].T
+    err = rel_max(got, ref)
+    say(f"  sampled max rel err {err:.2e} over {len(cells)} cells")
+    assert err <= 1e-12
