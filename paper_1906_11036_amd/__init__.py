@@ -446,8 +446,8 @@ class Solver3D:
     def set_source_terms(self, terms):
         """F(x, t, phi) = sum_j exp(gamma_j t) phi^k_j G_j(x), terms as (k_j,
         gamma_j, G_j [nz][ny][nx]); an empty list removes the source.  Set
-        before set_phi.  The G_j and the source path's scratch stay on the
-        device while this solver lives."""
+        before set_phi.  The G_j (and, for D3Q7's three-pass step, its scratch)
+        stay on the device while this solver lives."""
         torch = _torch()
         n = len(terms)
         if n == 0:
@@ -457,9 +457,9 @@ class Solver3D:
             return
         g = np.stack([np.asarray(G, dtype=np.float64).reshape(self.nz, self.ny, self.nx) for _, _, G in terms])
         self._src_g = torch.from_numpy(np.ascontiguousarray(g)).to(self.device)
-        nb = self.lib.dugks3_source_scratch_bytes(self.h)
-        self._scratch = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
-        sp = (self._scratch.data_ptr() + 255) & ~255
+        nb = self.lib.dugks3_source_scratch_bytes(self.h)   # 0: the fused step needs none
+        self._scratch = torch.empty(nb + 256, dtype=torch.uint8, device=self.device) if nb else None
+        sp = (self._scratch.data_ptr() + 255) & ~255 if nb else None
         pw = (C.c_int * n)(*[int(k) for k, _, _ in terms])
         gm = (C.c_double * n)(*[float(gam) for _, gam, _ in terms])
         L.check3(self.lib.dugks3_set_source_terms(self.h, n, C.c_void_p(self._src_g.data_ptr()), pw, gm,

@@ -80,6 +80,8 @@ struct dugks3_ctx {
   double e[kMaxQ][kMaxCoef] = {{0}};
   std::vector<double> geo[3], widths;
   Launch3 launch;
+  int default_rows = 4;          // rows of the default launch without a source
+  bool launch_chosen = false;    // set by dugks3_set_launch or dugks3_autotune
   // device
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -98,11 +100,14 @@ struct dugks3_ctx {
   int src_pow[DUGKS_MAX_SRC_TERMS] = {0};
   double src_gam[DUGKS_MAX_SRC_TERMS] = {0};
   void* src_scratch = nullptr;
-  // the source path's scratch: g of every cell and ghost, then the three
-  // axes' flux arrays, each from a 256-byte boundary
+  // D3Q15 and D3Q19 take sources in the fused step; D3Q7 in three passes
+  // through a scratch array: g of every cell and ghost, then the three axes'
+  // flux arrays, each from a 256-byte boundary
+  bool src_passes() const { return q == 7; }
   size_t scratch_g_bytes() const { return align256((size_t)q * (n[0] + 2) * (n[1] + 2) * (n[2] + 2) * elem()); }
   size_t scratch_flux_bytes(int a) const { return align256(src3_flux_values(q, a, n[0], n[1], n[2]) * elem()); }
   size_t scratch_bytes() const {
+    if (!src_passes()) return 0;
     return scratch_g_bytes() + scratch_flux_bytes(0) + scratch_flux_bytes(1) + scratch_flux_bytes(2);
   }
 
@@ -247,10 +252,10 @@ struct dugks3_ctx {
 
   // LDS bytes of a block for the launch and the device limit per block
   size_t lds_bytes(const Launch3& l) const {
-    // the instantiation with mirror code runs with walls or with more than
-    // four equilibrium coefficients
+    // the instantiation with mirror code runs with walls, with more than four
+    // equilibrium coefficients or with a source
     const bool walls = p.bc[0] != DUGKS_BC_PERIODIC || p.bc[1] != DUGKS_BC_PERIODIC ||
-                       p.bc[2] != DUGKS_BC_PERIODIC || ncoef > 4;
+                       p.bc[2] != DUGKS_BC_PERIODIC || ncoef > 4 || src_n > 0;
     return step3_lds_bytes(p.storage, q, walls, l);
   }
   size_t lds_limit() const {
@@ -367,6 +372,7 @@ int dugks3_create(dugks3_ctx** out, int nx, int ny, int nz, const double* xf, co
   // walls: two, which lets two blocks share a CU) -- the fastest at 256^3
   const bool walls = p->bc[0] != DUGKS_BC_PERIODIC || p->bc[1] != DUGKS_BC_PERIODIC || p->bc[2] != DUGKS_BC_PERIODIC;
   x->launch.rows = p->storage == DUGKS_F64 ? 2 : ((q == 15 && walls) ? 2 : 4);
+  x->default_rows = x->launch.rows;
   // Planes a chunk.  D3Q15 and D3Q19: the blocks run in rounds of (CUs x
   // blocks a CU, from the LDS: 160 KiB a CU) and a block takes about
   // (planes + 3) plane times (its prologue stages and makes two planes), so
@@ -488,15 +494,21 @@ int dugks3_set_source_terms(dugks3_ctx* ctx, int nterms, const double* g_dev, co
       if (powers[t] < 0 || powers[t] > DUGKS_MAX_SRC_POW) return ctx->fail(DUGKS_E_ARG, "power out of range");
       if (!std::isfinite(gammas[t])) return ctx->fail(DUGKS_E_ARG, "growth rate not finite");
     }
-    if (ctx->scratch_g_bytes() >= 4294967296ull)
-      return ctx->fail(DUGKS_E_ARG, "mesh too large for the source path (g of all cells reaches 4 GiB)");
-    if (!scratch_dev || ((uintptr_t)scratch_dev & 255) != 0)
-      return ctx->fail(DUGKS_E_ARG, "scratch must be a 256-byte aligned device buffer");
-    if (scratch_bytes < ctx->scratch_bytes()) return ctx->fail(DUGKS_E_NOMEM, "scratch too small");
+    if (ctx->src_passes()) {
+      if (ctx->scratch_g_bytes() >= 4294967296ull)
+        return ctx->fail(DUGKS_E_ARG, "mesh too large for the source path (g of all cells reaches 4 GiB)");
+      if (!scratch_dev || ((uintptr_t)scratch_dev & 255) != 0)
+        return ctx->fail(DUGKS_E_ARG, "scratch must be a 256-byte aligned device buffer");
+      if (scratch_bytes < ctx->scratch_bytes()) return ctx->fail(DUGKS_E_NOMEM, "scratch too small");
+    }
   }
   ctx->src_n = nterms;
+  // binary32 D3Q15 / D3Q19 with a source run fastest at 2 rows a block (the
+  // fused kernel's registers); a launch the caller chose is kept
+  if (!ctx->launch_chosen && ctx->p.storage == DUGKS_F32 && !ctx->src_passes())
+    ctx->launch.rows = nterms > 0 ? 2 : ctx->default_rows;
   ctx->src_g = nterms > 0 ? g_dev : nullptr;
-  ctx->src_scratch = nterms > 0 ? scratch_dev : nullptr;
+  ctx->src_scratch = nterms > 0 && ctx->src_passes() ? scratch_dev : nullptr;
   for (int t = 0; t < DUGKS_MAX_SRC_TERMS; ++t) {
     ctx->src_pow[t] = t < nterms ? powers[t] : 0;
     ctx->src_gam[t] = t < nterms ? gammas[t] : 0.0;
@@ -522,7 +534,7 @@ int dugks3_step(dugks3_ctx* ctx, int nsteps) {
   if (ctx->any_dirichlet() && (ctx->ring == nullptr || ctx->step + nsteps > ctx->ring_steps))
     return ctx->fail(DUGKS_E_STATE, "Dirichlet walls need data for every step (dugks3_set_dirichlet)");
   for (int s = 0; s < nsteps; ++s) {
-    const int rc = ctx->src_n > 0
+    const int rc = ctx->src_n > 0 && ctx->src_passes()
                        ? launch_src3_step(ctx->dev(), ctx->host, (int)(ctx->step & 1), ctx->step, ctx->stream)
                        : launch_step3(ctx->dev(), ctx->host, (int)(ctx->step & 1), ctx->step, ctx->launch, ctx->stream);
     if (rc)
@@ -574,6 +586,7 @@ int dugks3_set_launch(dugks3_ctx* ctx, int rows, int planes) {
   if (ctx->bound() && ctx->lds_bytes(l) > ctx->lds_limit())
     return ctx->fail(DUGKS_E_ARG, "launch needs more LDS than a block may hold");
   ctx->launch = l;
+  ctx->launch_chosen = true;
   return DUGKS_OK;
 }
 
@@ -600,7 +613,7 @@ int dugks3_autotune(dugks3_ctx* ctx, int trial_steps) {
   if (!ctx->initialised) return ctx->fail(DUGKS_E_STATE, "state not initialised");
   if (ctx->any_dirichlet() && (ctx->ring == nullptr || ctx->step + 1 > ctx->ring_steps))
     return ctx->fail(DUGKS_E_STATE, "Dirichlet data does not cover the current step");
-  if (ctx->src_n > 0) return DUGKS_OK;   // the source step has no launch shape to choose
+  if (ctx->src_n > 0 && ctx->src_passes()) return DUGKS_OK;   // D3Q7's source passes have no launch shape
   if (trial_steps < 1) trial_steps = 1;
   hipEvent_t a, b;
   if (hipEventCreate(&a) != hipSuccess) return ctx->fail(DUGKS_E_HIP, "event create");
@@ -644,6 +657,7 @@ int dugks3_autotune(dugks3_ctx* ctx, int trial_steps) {
   if (rc != DUGKS_OK) return ctx->fail(rc, "autotune launch failed");
   if (er != hipSuccess) return ctx->hipfail(er, "autotune timing");
   ctx->launch = best;
+  ctx->launch_chosen = true;
   return DUGKS_OK;
 }
 

@@ -241,6 +241,101 @@ __device__ __forceinline__ void face3(const Inst3* __restrict__ I, const EQ& E, 
     if (ce<Q>(k, A) != 0) out[k] = fma(rb, gb[k], E(k, pb));
 }
 
+// ------------------------------------------------------------- sources
+// F(x, t, phi) = sum_j exp(gamma_j t) phi^k_j G_j(x) (k_j <= 3): its
+// coefficients as a polynomial in phi at time t, each G_j interpolated as
+// G_j(c0) + r (G_j(c1) - G_j(c0)) (r = 0: the centre of cell c0).
+__device__ inline void src_coefs3(const Inst3* __restrict__ I, long long c0, long long c1, double r, double t,
+                                  double* a) {
+  for (int m = 0; m < 4; ++m) a[m] = 0.0;
+  for (int j = 0; j < I->src_n; ++j) {
+    const double g0 = I->src_g[j * I->src_plane + c0], g1 = I->src_g[j * I->src_plane + c1];
+    a[I->src_pow[j]] += exp(I->src_gam[j] * t) * fma(r, g1 - g0, g0);
+  }
+}
+template <typename T> __device__ inline T poly4(const T* a, T x) {
+  return fma(fma(fma(a[3], x, a[2]), x, a[1]), x, a[0]);
+}
+// The conserved value v with v - tau F(v) / 2 = s (tau = dt in a cell, eq.
+// 2.25; h at a face, eq. 2.27): explicit when F does not depend on phi, else
+// Newton's method from v = s (binary64: update <= 1e-15 (1 + |v|), at most 8;
+// binary32: 2.4e-7, at most 6).
+template <typename T> __device__ inline T solve_conserved3(T s, T half_tau, const T* a, bool implicit) {
+  if (!implicit) return fma(half_tau, a[0], s);
+  constexpr bool dbl = sizeof(T) == 8;
+  const T tol = dbl ? (T)1e-15 : (T)2.4e-7;
+  T v = s;
+#pragma unroll 1
+  for (int it = 0; it < (dbl ? 8 : 6); ++it) {
+    const T P = poly4(a, v);
+    const T dP = fma(fma((T)3 * a[3], v, (T)2 * a[2]), v, a[1]);
+    const T d = (v - half_tau * P - s) / ((T)1 - half_tau * dP);
+    v -= d;
+    if (!(fabs(d) > tol * ((T)1 + fabs(v)))) break;
+  }
+  return v;
+}
+// weights of D3Q19 (eq. 2.6), D3Q15 (eq. 2.28) and D3Q7 (Remark 3)
+template <int Q> __host__ __device__ constexpr double w3(int k) {
+  return Q == 19 ? (k == 0 ? 1.0 / 3.0 : (k <= 6 ? 1.0 / 18.0 : 1.0 / 36.0))
+         : Q == 15 ? (k == 0 ? 2.0 / 9.0 : (k <= 6 ? 1.0 / 9.0 : 1.0 / 72.0))
+                   : (k == 0 ? 0.0 : 1.0 / 6.0);
+}
+// S_k / F = w_k (1 + c_k.B'(phi) / c_s^2): F_k and R_k of eq. 2.3 and Remark 3
+template <int Q> __device__ inline double rho3(const Inst3* __restrict__ I, int k, double phi) {
+  double v = 1.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    if (ce<Q>(k, a) != 0) v += ce<Q>(k, a) * poly4(I->bp[a], phi);
+  return w3<Q>(k) * v;
+}
+// The source terms' time factors exp(gamma_j t) at the cells' time t_n and at
+// the faces' time t_n + h, computed on the host once a step and passed by value
+struct SrcTab {
+  double en[DUGKS_MAX_SRC_TERMS], ef[DUGKS_MAX_SRC_TERMS];
+};
+using STab = const SrcTab*;
+// The source's coefficients as polynomials in phi at cell `cell` (index of
+// [nz][ny][nx]): an at t_n (the cell's own phi), af at t_n + h (its faces)
+__device__ __forceinline__ void src_cell_coefs3(const Inst3* __restrict__ I, STab tb, long long cell,
+                                                double* an, double* af) {
+  const GPtr<const double> G = as_global(I->src_g);
+  const int n = I->src_n;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) an[m] = af[m] = 0.0;
+#pragma unroll
+  for (int j = 0; j < DUGKS_MAX_SRC_TERMS; ++j) {
+    if (j >= n) break;
+    const double gj = G[j * I->src_plane + cell];
+    const int pw = I->src_pow[j];
+    const double en = tb->en[j], ef = tb->ef[j];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      if (pw == m) {
+        an[m] += en * gj;
+        af[m] += ef * gj;
+      }
+  }
+}
+
+// A face's coefficients in the storage type: each G_j interpolated linearly
+// between the two cells' centres (afL, afR: the cells' af; r the face's factor)
+template <typename T>
+__device__ __forceinline__ void src_face_coefs3(const double* afL, const double* afR, T r, T* a) {
+#pragma unroll
+  for (int m = 0; m < 4; ++m) a[m] = (T)fma((double)r, afR[m] - afL[m], afL[m]);
+}
+
+// phi of interior cell `cell` at time t from the sum of its f~ (the root of
+// phi = s + dt F(phi) / 2 with a source)
+__device__ inline double src_phi3(const Inst3* __restrict__ I, long long cell, double s, double t) {
+  if (I->src_n == 0) return s;
+  double a[4];
+  src_coefs3(I, cell, cell, 0.0, t, a);
+  return solve_conserved3<double>(s, 0.5 * I->dt, a, I->src_implicit != 0);
+}
+
+
 extern __shared__ __align__(16) unsigned char dugks3_lds[];
 
 // --------------------------------- fused step, binary64 storage (D3Q7)
@@ -867,6 +962,22 @@ __device__ __forceinline__ void face_out(const Inst3* __restrict__ I, const EQ& 
     if (part_of<Q, P>(k) == H && ce<Q>(k, A) != 0) out[k] = fma(rb, gb[k], E(k, pb));
 }
 
+// The same with a source (eqs. 2.27 and 2.22 with F_b): phi_b solves phi_b =
+// b1 sum gbar + h F(phi_b) / 2 with the face's coefficients sa, and F gains
+// lambda F(phi_b) rho(phi_b)
+template <int Q, int P, int H, int A, typename T, typename EQ>
+__device__ __forceinline__ void face_out_src(const Inst3* __restrict__ I, const EQ& E, const T* gb, T s, const T* sa,
+                                             T* out) {
+  T pb = (T)(s * C3<T>::b1(I));
+  pb = solve_conserved3<T>(pb, (T)(0.25 * I->dt), sa, I->src_implicit != 0);
+  const T lfb = (T)I->lambda * poly4(sa, pb);
+  const T rb = C3<T>::rb(I);
+#pragma unroll
+  for (int k = 0; k < Q; ++k)
+    if (part_of<Q, P>(k) == H && ce<Q>(k, A) != 0)
+      out[k] = fma(rb, gb[k], E(k, pb) + lfb * (T)rho3<Q>(I, k, (double)pb));
+}
+
 // LDS bytes of a block with ns staging slots (E coefficients aside)
 // LDS of a block with ns staging slots, the halo rows' phi sums (binary64,
 // when those rows go through registers) included
@@ -896,11 +1007,11 @@ template <int Q, int ROWS, typename T, bool WALLS> struct LdsP {
 // One wave: row rw of the tile, directions of half H.  With two slots plane
 // z+2 is staged into the second while plane z+1 is read from the first; one
 // slot is refilled once every wave has read it.
-template <int Q, int NC, int ROWS, typename T, int H, bool WALLS>
+template <int Q, int NC, int ROWS, typename T, int H, bool WALLS, bool SRC>
 __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int parity,
-                                            const double* __restrict__ ring, int planes, int strips,
-                                            int tiles, LdsP<Q, ROWS, T, WALLS>& L, const float* ecoef,
-                                            double (*hphi)[4][kLanes], int w, int rw) {
+                                            const double* __restrict__ ring, STab tb, int planes,
+                                            int strips, int tiles, LdsP<Q, ROWS, T, WALLS>& L,
+                                            const float* ecoef, double (*hphi)[4][kLanes], int w, int rw) {
   using LP = LdsP<Q, ROWS, T, WALLS>;
   constexpr int P = parts<Q, T, ROWS, WALLS>();
   constexpr int W = LP::W, WD = LP::WD;
@@ -1016,7 +1127,10 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
   // g = fbar+ / b1 (eq. 2.21 over b1) of this half's directions; phi (binary64) from all of them
   // (fromreg: the raw values are the halo row's in HR)
   // yr: the row's index (-1..ny), for the Dirichlet data
-  auto make_g = [&](int slot, int row, bool wy, int yr, int zp, T* g, T* f, auto fromreg) __attribute__((always_inline)) {
+  // With a source: phi solves phi = sum f~ + dt F(phi) / 2 (eq. 2.25) and g
+  // gains lambda F(phi) rho(phi); afo receives the cell's coefficients at t_n + h.
+  auto make_g = [&](int slot, int row, bool wy, int yr, int zp, T* g, T* f, auto fromreg,
+                    double* afo) __attribute__((always_inline)) {
     constexpr bool kReg = decltype(fromreg)::value;
     // phi in binary64 as (q0 + q1) + (q2 + q3), qj the sum over quarter j in
     // index order (four chains); a halo row in registers takes the quarters'
@@ -1038,10 +1152,21 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
       }
       phi = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     }
+    double lf = 0.0;
+    if constexpr (SRC) {
+      const long long cell = ((long long)src_index(zp, nz, bcz) * ny + src_index(yr, ny, bcy)) * nx + scol;
+      double an[4];
+      src_cell_coefs3(I, tb, cell, an, afo);
+      phi = solve_conserved3<double>(phi, 0.5 * I->dt, an, I->src_implicit != 0);
+      lf = I->lambda * poly4(an, phi);
+    }
     const T p = (T)phi, ra = C3<T>::ra(I);
 #pragma unroll
-    for (int k = 0; k < Q; ++k)
-      if (part_of<Q, P>(k) == H) g[k] = fma(ra, f[k], ev(k, p));
+    for (int k = 0; k < Q; ++k) {
+      if (part_of<Q, P>(k) != H) continue;
+      if constexpr (SRC) g[k] = fma(ra, f[k], ev(k, p) + (T)(lf * rho3<Q>(I, k, phi)));
+      else g[k] = fma(ra, f[k], ev(k, p));
+    }
     if constexpr (WALLS) {
       if (dirichlet_ghost(I, wall_x, wy, zp)) {
         nee_ghost<Q, T>(I, ev, ring, c, yr, zp, p, g, [](int k) { return part_of<Q, P>(k) == H; });
@@ -1072,11 +1197,12 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
       }
     }
   };
-  auto plane_g = [&](int rs, int zp, int slot, T* G, T* FT) __attribute__((always_inline)) {
+  auto plane_g = [&](int rs, int zp, int slot, T* G, T* FT, double* AF) __attribute__((always_inline)) {
     using Staged = std::integral_constant<bool, false>;
     using Halo = std::integral_constant<bool, LP::kHD>;
     T f[Q];
-    make_g(rs, me, wall_y, r, zp, G, f, Staged{});
+    double afx[4];   // a halo row's coefficients (not kept)
+    make_g(rs, me, wall_y, r, zp, G, f, Staged{}, AF);
 #pragma unroll
     for (int k = 0; k < Q; ++k)
       if (part_of<Q, P>(k) == H) FT[k] = fma(kgv, G[k], (T)(-1.0 / 3.0) * f[k]);
@@ -1084,10 +1210,10 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
     if (rw <= 1) {
       T gx[Q];
       const int row = rw == 0 ? 0 : W - 1;
-      make_g(rs, row, rw == 0 ? wall_lo : wall_hi, rw == 0 ? y0 - 1 : y1, zp, gx, f, Halo{});
+      make_g(rs, row, rw == 0 ? wall_lo : wall_hi, rw == 0 ? y0 - 1 : y1, zp, gx, f, Halo{}, afx);
       publish(slot, row, gx);
       if (ROWS == 1) {  // one row: its waves make both halo rows (always staged)
-        make_g(rs, W - 1, wall_hi, y1, zp, gx, f, Staged{});
+        make_g(rs, W - 1, wall_hi, y1, zp, gx, f, Staged{}, afx);
         publish(slot, W - 1, gx);
       }
     }
@@ -1104,6 +1230,7 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
   };
 
   T G0[Q], G1[Q], O[Q], FT1[Q], FZb[Q], FZt[Q];
+  double AF0[4], AF1[4];   // with a source: the own row's face coefficients at planes z and z+1
   // one part of the pipeline differs: binary32 stages plane z+2 before the
   // first barrier of plane z (other slot), binary64 after it (same slot)
   constexpr bool two = LP::NS == 2;
@@ -1122,13 +1249,13 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
 #pragma unroll
           for (int m = 0; m < NC; ++m) ev.c[k][m] = ecoef[k * NC + m];
     }
-    plane_g(1, z0 - 1, 2, G1, FT1);
+    plane_g(1, z0 - 1, 2, G1, FT1, AF1);
     lds_barrier();
     stage(0, z0);
     wait_vm_all();
     halo_sums();
     lds_barrier();
-    plane_g(0, z0, 0, G0, O);
+    plane_g(0, z0, 0, G0, O, AF0);
     lds_barrier();
     stage(1, z0 + 1);   // z1 >= z0 + 1
   } else if constexpr (two) {
@@ -1143,8 +1270,8 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
 #pragma unroll
           for (int m = 0; m < NC; ++m) ev.c[k][m] = ecoef[k * NC + m];
     }
-    plane_g(1, z0 - 1, 2, G1, FT1);
-    plane_g(0, z0, 0, G0, O);
+    plane_g(1, z0 - 1, 2, G1, FT1, AF1);
+    plane_g(0, z0, 0, G0, O, AF0);
     lds_barrier();
     stage(1, z0 + 1);   // z1 >= z0 + 1
   } else {
@@ -1152,13 +1279,13 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
     wait_vm_all();
     halo_sums();
     lds_barrier();
-    plane_g(0, z0 - 1, 2, G1, FT1);
+    plane_g(0, z0 - 1, 2, G1, FT1, AF1);
     lds_barrier();
     stage(0, z0);
     wait_vm_all();
     halo_sums();
     lds_barrier();
-    plane_g(0, z0, 0, G0, O);
+    plane_g(0, z0, 0, G0, O, AF0);
     lds_barrier();
     stage(0, z0 + 1);
   }
@@ -1180,7 +1307,15 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
     put_sum(0, sB);
   }
   lds_barrier();
-  if (inner) face_out<Q, P, H, 2>(I, ev, gbB, total(0, sB), FZb);
+  if (inner) {
+    if constexpr (SRC) {
+      T sa[4];
+      src_face_coefs3<T>(AF1, AF0, (T)zg[zb * kGeo + 1], sa);
+      face_out_src<Q, P, H, 2>(I, ev, gbB, total(0, sB), sa, FZb);
+    } else {
+      face_out<Q, P, H, 2>(I, ev, gbB, total(0, sB), FZb);
+    }
+  }
   wait_vm_all();
   halo_sums();   // plane z0+1
   lds_barrier();
@@ -1189,7 +1324,7 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
     constexpr int RS = decltype(rsl)::value;   // staging slot of plane z+1
     const int d = z - z0;
     const int s0 = d % 3, sp = (d + 1) % 3, sm = (d + 2) % 3;
-    plane_g(RS, z + 1, sp, G1, FT1);
+    plane_g(RS, z + 1, sp, G1, FT1, AF1);
     if constexpr (two) {
       if (z + 2 <= z1) stage(1 - RS, z + 2);
       lds_barrier();
@@ -1267,10 +1402,30 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
       const int zi = z + 1;
       const T kz = zg[zi * kGeo + 4];
       T fW[Q], fN[Q], fS[Q];
-      face_out<Q, P, H, 0>(I, ev, gbW, total(0, sW), fW);
-      face_out<Q, P, H, 1>(I, ev, gbN, total(1, sN), fN);
-      face_out<Q, P, H, 1>(I, ev, gbS, total(2, sS), fS);
-      face_out<Q, P, H, 2>(I, ev, gbT, total(3, sT), FZt);
+      if constexpr (SRC) {
+        // the neighbouring rows' coefficients at plane z, the west cell's
+        // from lane - 1
+        const long long cz = (long long)src_index(z, nz, bcz) * ny;
+        double AFN[4], AFS[4], AFW[4], an[4];
+        src_cell_coefs3(I, tb, (cz + src_index(r + 1, ny, bcy)) * nx + scol, an, AFN);
+        src_cell_coefs3(I, tb, (cz + src_index(r - 1, ny, bcy)) * nx + scol, an, AFS);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) AFW[m] = shr1(AF0[m]);
+        T sa[4];
+        src_face_coefs3<T>(AFW, AF0, ca0, sa);
+        face_out_src<Q, P, H, 0>(I, ev, gbW, total(0, sW), sa, fW);
+        src_face_coefs3<T>(AF0, AFN, yN1, sa);
+        face_out_src<Q, P, H, 1>(I, ev, gbN, total(1, sN), sa, fN);
+        src_face_coefs3<T>(AFS, AF0, yS1, sa);
+        face_out_src<Q, P, H, 1>(I, ev, gbS, total(2, sS), sa, fS);
+        src_face_coefs3<T>(AF0, AF1, (T)zg[(z + 2) * kGeo + 1], sa);
+        face_out_src<Q, P, H, 2>(I, ev, gbT, total(3, sT), sa, FZt);
+      } else {
+        face_out<Q, P, H, 0>(I, ev, gbW, total(0, sW), fW);
+        face_out<Q, P, H, 1>(I, ev, gbN, total(1, sN), fN);
+        face_out<Q, P, H, 1>(I, ev, gbS, total(2, sS), fS);
+        face_out<Q, P, H, 2>(I, ev, gbT, total(3, sT), FZt);
+      }
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
         if (part_of<Q, P>(k) != H) continue;
@@ -1302,6 +1457,10 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
       O[k] = FT1[k];
       if (ce<Q>(k, 2) != 0) FZb[k] = FZt[k];
     }
+    if constexpr (SRC) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) AF0[m] = AF1[m];
+    }
   };
   using R0 = std::integral_constant<int, 0>;
   using R1 = std::integral_constant<int, 1>;
@@ -1318,10 +1477,11 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
 }
 
 // WALLS = false: every axis periodic, no mirror code
-template <int Q, int NC, int ROWS, typename T, bool WALLS>
+template <int Q, int NC, int ROWS, typename T, bool WALLS, bool SRC>
 __global__ __launch_bounds__((64 * parts<Q, T, ROWS, WALLS>() * ROWS)) void k_step3p(const Inst3* __restrict__ I, int parity,
                                                                        const double* __restrict__ ring,
-                                                                       int planes, int strips, int tiles) {
+                                                                       const SrcTab st, int planes, int strips,
+                                                                       int tiles) {
   constexpr int P = parts<Q, T, ROWS, WALLS>();
   __shared__ LdsP<Q, ROWS, T, WALLS> L;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1336,19 +1496,20 @@ __global__ __launch_bounds__((64 * parts<Q, T, ROWS, WALLS>() * ROWS)) void k_st
       for (int i = threadIdx.x; i < Q * NC; i += kLanes) ecoef[i] = I->ef[i / NC][i % NC];
     ec = ecoef;
   }
+  const STab tb = &st;
   double (*hp)[4][kLanes] = nullptr;
   if constexpr (LdsP<Q, ROWS, T, WALLS>::kHD) {
     __shared__ double hphi[2][4][kLanes];   // quarter sums of the cell phi of the two halo rows
     hp = hphi;
   }
   switch (part) {
-    case 0: step3p_half<Q, NC, ROWS, T, 0, WALLS>(I, parity, ring, planes, strips, tiles, L, ec, hp, w, rw); break;
-    case 1: step3p_half<Q, NC, ROWS, T, 1, WALLS>(I, parity, ring, planes, strips, tiles, L, ec, hp, w, rw); break;
+    case 0: step3p_half<Q, NC, ROWS, T, 0, WALLS, SRC>(I, parity, ring, tb, planes, strips, tiles, L, ec, hp, w, rw); break;
+    case 1: step3p_half<Q, NC, ROWS, T, 1, WALLS, SRC>(I, parity, ring, tb, planes, strips, tiles, L, ec, hp, w, rw); break;
     case 2:
-      if constexpr (P > 2) step3p_half<Q, NC, ROWS, T, 2, WALLS>(I, parity, ring, planes, strips, tiles, L, ec, hp, w, rw);
+      if constexpr (P > 2) step3p_half<Q, NC, ROWS, T, 2, WALLS, SRC>(I, parity, ring, tb, planes, strips, tiles, L, ec, hp, w, rw);
       break;
     default:
-      if constexpr (P > 2) step3p_half<Q, NC, ROWS, T, 3, WALLS>(I, parity, ring, planes, strips, tiles, L, ec, hp, w, rw);
+      if constexpr (P > 2) step3p_half<Q, NC, ROWS, T, 3, WALLS, SRC>(I, parity, ring, tb, planes, strips, tiles, L, ec, hp, w, rw);
       break;
   }
 }
@@ -1363,63 +1524,6 @@ __device__ __forceinline__ void feq64(const Inst3* __restrict__ I, double phi, d
     for (int m = nc - 2; m >= 0; --m) r = fma(r, phi, I->e[k][m]);
     E[k] = r;
   }
-}
-
-// ------------------------------------------------------------- sources
-// F(x, t, phi) = sum_j exp(gamma_j t) phi^k_j G_j(x) (k_j <= 3): its
-// coefficients as a polynomial in phi at time t, each G_j interpolated as
-// G_j(c0) + r (G_j(c1) - G_j(c0)) (r = 0: the centre of cell c0).
-__device__ inline void src_coefs3(const Inst3* __restrict__ I, long long c0, long long c1, double r, double t,
-                                  double* a) {
-  for (int m = 0; m < 4; ++m) a[m] = 0.0;
-  for (int j = 0; j < I->src_n; ++j) {
-    const double g0 = I->src_g[j * I->src_plane + c0], g1 = I->src_g[j * I->src_plane + c1];
-    a[I->src_pow[j]] += exp(I->src_gam[j] * t) * fma(r, g1 - g0, g0);
-  }
-}
-template <typename T> __device__ inline T poly4(const T* a, T x) {
-  return fma(fma(fma(a[3], x, a[2]), x, a[1]), x, a[0]);
-}
-// The conserved value v with v - tau F(v) / 2 = s (tau = dt in a cell, eq.
-// 2.25; h at a face, eq. 2.27): explicit when F does not depend on phi, else
-// Newton's method from v = s (binary64: update <= 1e-15 (1 + |v|), at most 8;
-// binary32: 2.4e-7, at most 6).
-template <typename T> __device__ inline T solve_conserved3(T s, T half_tau, const T* a, bool implicit) {
-  if (!implicit) return fma(half_tau, a[0], s);
-  constexpr bool dbl = sizeof(T) == 8;
-  const T tol = dbl ? (T)1e-15 : (T)2.4e-7;
-  T v = s;
-#pragma unroll 1
-  for (int it = 0; it < (dbl ? 8 : 6); ++it) {
-    const T P = poly4(a, v);
-    const T dP = fma(fma((T)3 * a[3], v, (T)2 * a[2]), v, a[1]);
-    const T d = (v - half_tau * P - s) / ((T)1 - half_tau * dP);
-    v -= d;
-    if (!(fabs(d) > tol * ((T)1 + fabs(v)))) break;
-  }
-  return v;
-}
-// weights of D3Q19 (eq. 2.6), D3Q15 (eq. 2.28) and D3Q7 (Remark 3)
-template <int Q> __host__ __device__ constexpr double w3(int k) {
-  return Q == 19 ? (k == 0 ? 1.0 / 3.0 : (k <= 6 ? 1.0 / 18.0 : 1.0 / 36.0))
-         : Q == 15 ? (k == 0 ? 2.0 / 9.0 : (k <= 6 ? 1.0 / 9.0 : 1.0 / 72.0))
-                   : (k == 0 ? 0.0 : 1.0 / 6.0);
-}
-// S_k / F = w_k (1 + c_k.B'(phi) / c_s^2): F_k and R_k of eq. 2.3 and Remark 3
-template <int Q> __device__ inline double rho3(const Inst3* __restrict__ I, int k, double phi) {
-  double v = 1.0;
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-    if (ce<Q>(k, a) != 0) v += ce<Q>(k, a) * poly4(I->bp[a], phi);
-  return w3<Q>(k) * v;
-}
-// phi of interior cell `cell` at time t from the sum of its f~ (the root of
-// phi = s + dt F(phi) / 2 with a source)
-__device__ inline double src_phi3(const Inst3* __restrict__ I, long long cell, double s, double t) {
-  if (I->src_n == 0) return s;
-  double a[4];
-  src_coefs3(I, cell, cell, 0.0, t, a);
-  return solve_conserved3<double>(s, 0.5 * I->dt, a, I->src_implicit != 0);
 }
 
 template <int Q, int ST>
@@ -1587,36 +1691,39 @@ static void step3_row_waves(const Inst3* d, const Inst3& h, int parity, const do
   }
 }
 
-template <int Q, int NC, int ROWS, typename T, bool WALLS>
-static void step3p_go(const Inst3* d, int parity, const double* ring, const Launch3& l, int strips, int tiles, dim3 grid,
-                      hipStream_t st) {
-  hipLaunchKernelGGL((k_step3p<Q, NC, ROWS, T, WALLS>), grid, dim3(64 * parts<Q, T, ROWS, WALLS>() * ROWS), 0, st, d,
-                     parity, ring, l.planes, strips, tiles);
+template <int Q, int NC, int ROWS, typename T, bool WALLS, bool SRC>
+static void step3p_go(const Inst3* d, int parity, const double* ring, const SrcTab& ss, const Launch3& l, int strips,
+                      int tiles, dim3 grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_step3p<Q, NC, ROWS, T, WALLS, SRC>), grid, dim3(64 * parts<Q, T, ROWS, WALLS>() * ROWS), 0, st,
+                     d, parity, ring, ss, l.planes, strips, tiles);
 }
-template <int Q, int NC, typename T, bool WALLS>
-static void step3p_launch(const Inst3* d, int parity, const double* ring, const Launch3& l, int strips, int tiles, dim3 grid,
-                          hipStream_t st) {
+template <int Q, int NC, typename T, bool WALLS, bool SRC>
+static void step3p_launch(const Inst3* d, int parity, const double* ring, const SrcTab& ss, const Launch3& l,
+                          int strips, int tiles, dim3 grid, hipStream_t st) {
   if constexpr (sizeof(T) == 8) {   // rows 1 and 2 fit the LDS
-    if (l.rows == 1) step3p_go<Q, NC, 1, T, WALLS>(d, parity, ring, l, strips, tiles, grid, st);
-    else step3p_go<Q, NC, 2, T, WALLS>(d, parity, ring, l, strips, tiles, grid, st);
+    if (l.rows == 1) step3p_go<Q, NC, 1, T, WALLS, SRC>(d, parity, ring, ss, l, strips, tiles, grid, st);
+    else step3p_go<Q, NC, 2, T, WALLS, SRC>(d, parity, ring, ss, l, strips, tiles, grid, st);
   } else {
     switch (l.rows) {
-      case 2: step3p_go<Q, NC, 2, T, WALLS>(d, parity, ring, l, strips, tiles, grid, st); break;
-      case 3: step3p_go<Q, NC, 3, T, WALLS>(d, parity, ring, l, strips, tiles, grid, st); break;
-      default: step3p_go<Q, NC, 4, T, WALLS>(d, parity, ring, l, strips, tiles, grid, st); break;
+      case 2: step3p_go<Q, NC, 2, T, WALLS, SRC>(d, parity, ring, ss, l, strips, tiles, grid, st); break;
+      case 3: step3p_go<Q, NC, 3, T, WALLS, SRC>(d, parity, ring, ss, l, strips, tiles, grid, st); break;
+      default: step3p_go<Q, NC, 4, T, WALLS, SRC>(d, parity, ring, ss, l, strips, tiles, grid, st); break;
     }
   }
 }
+// With a source: the instantiation with mirror code (it serves periodic axes too)
 template <int Q, int NC, typename T>
-static void step3p_rows(const Inst3* d, const Inst3& h, int parity, const double* ring, const Launch3& l, int strips, int tiles,
-                        dim3 grid, hipStream_t st) {
+static void step3p_rows(const Inst3* d, const Inst3& h, int parity, const double* ring, const SrcTab& ss,
+                        const Launch3& l, int strips, int tiles, dim3 grid, hipStream_t st) {
   const bool walls = h.bc[0] != DUGKS_BC_PERIODIC || h.bc[1] != DUGKS_BC_PERIODIC || h.bc[2] != DUGKS_BC_PERIODIC;
-  if (NC == 8 || walls) step3p_launch<Q, NC, T, true>(d, parity, ring, l, strips, tiles, grid, st);
-  else if constexpr (NC != 8) step3p_launch<Q, NC, T, false>(d, parity, ring, l, strips, tiles, grid, st);
+  if (h.src_n > 0) step3p_launch<Q, NC, T, true, true>(d, parity, ring, ss, l, strips, tiles, grid, st);
+  else if (NC == 8 || walls) step3p_launch<Q, NC, T, true, false>(d, parity, ring, ss, l, strips, tiles, grid, st);
+  else if constexpr (NC != 8) step3p_launch<Q, NC, T, false, false>(d, parity, ring, ss, l, strips, tiles, grid, st);
 }
 
 template <int Q>
-static int step3_q(const Inst3* d, const Inst3& h, int parity, const double* ring, const Launch3& l, void* stream) {
+static int step3_q(const Inst3* d, const Inst3& h, int parity, const double* ring, const SrcTab& ss,
+                   const Launch3& l, void* stream) {
   const int strips = (h.n[0] + kCols - 1) / kCols;
   const int tiles = (h.n[1] + l.rows - 1) / l.rows;
   const long long blocks = step3_blocks(h, l);
@@ -1626,15 +1733,15 @@ static int step3_q(const Inst3* d, const Inst3& h, int parity, const double* rin
   if constexpr (Q != 7) {   // split directions
     if (h.storage == DUGKS_F64) {
       switch (nc) {
-        case 2: step3p_rows<Q, 2, double>(d, h, parity, ring, l, strips, tiles, grid, S(stream)); break;
-        case 4: step3p_rows<Q, 4, double>(d, h, parity, ring, l, strips, tiles, grid, S(stream)); break;
-        default: step3p_rows<Q, 8, double>(d, h, parity, ring, l, strips, tiles, grid, S(stream)); break;
+        case 2: step3p_rows<Q, 2, double>(d, h, parity, ring, ss, l, strips, tiles, grid, S(stream)); break;
+        case 4: step3p_rows<Q, 4, double>(d, h, parity, ring, ss, l, strips, tiles, grid, S(stream)); break;
+        default: step3p_rows<Q, 8, double>(d, h, parity, ring, ss, l, strips, tiles, grid, S(stream)); break;
       }
     } else {
       switch (nc) {
-        case 2: step3p_rows<Q, 2, float>(d, h, parity, ring, l, strips, tiles, grid, S(stream)); break;
-        case 4: step3p_rows<Q, 4, float>(d, h, parity, ring, l, strips, tiles, grid, S(stream)); break;
-        default: step3p_rows<Q, 8, float>(d, h, parity, ring, l, strips, tiles, grid, S(stream)); break;
+        case 2: step3p_rows<Q, 2, float>(d, h, parity, ring, ss, l, strips, tiles, grid, S(stream)); break;
+        case 4: step3p_rows<Q, 4, float>(d, h, parity, ring, ss, l, strips, tiles, grid, S(stream)); break;
+        default: step3p_rows<Q, 8, float>(d, h, parity, ring, ss, l, strips, tiles, grid, S(stream)); break;
       }
     }
   } else {   // D3Q7: a whole row per wave
@@ -1650,10 +1757,16 @@ static int step3_q(const Inst3* d, const Inst3& h, int parity, const double* rin
 int launch_step3(const Inst3* d, const Inst3& h, int parity, long long step, const Launch3& l, void* stream) {
   // the step's Dirichlet data (no reads without a Dirichlet axis)
   const double* ring = h.ring != nullptr ? h.ring + step * h.ring_len : nullptr;
+  // the source terms' time factors at t_n (cells) and t_n + h (faces)
+  SrcTab ss{};
+  for (int j = 0; j < h.src_n; ++j) {
+    ss.en[j] = exp(h.src_gam[j] * ((double)step * h.dt));
+    ss.ef[j] = exp(h.src_gam[j] * (((double)step + 0.5) * h.dt));
+  }
   switch (h.q) {
-    case 19: return step3_q<19>(d, h, parity, ring, l, stream);
-    case 15: return step3_q<15>(d, h, parity, ring, l, stream);
-    default: return step3_q<7>(d, h, parity, ring, l, stream);
+    case 19: return step3_q<19>(d, h, parity, ring, ss, l, stream);
+    case 15: return step3_q<15>(d, h, parity, ring, ss, l, stream);
+    default: return h.src_n > 0 ? -1 : step3_q<7>(d, h, parity, ring, ss, l, stream);   // D3Q7: three passes
   }
 }
 

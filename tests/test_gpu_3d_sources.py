@@ -1,5 +1,6 @@
 """Three-dimensional sources F(x, t, phi) = sum_j exp(gamma_j t) phi^k_j G_j(x)
-on the GPU (the three-pass source step, through the C ABI of include/dugks3d.h)
+on the GPU (the fused source step of D3Q15 and D3Q19, the three-pass step of
+D3Q7; through the C ABI of include/dugks3d.h)
 against the 3-D CPU oracle: binary64 to 1e-12 (max-norm relative to max |f~|)
 on all three lattices and every wall kind; binary32 within 2 n eps32 (relative
 L2 of phi); a uniform field follows the implicit trapezoidal rule; with all
@@ -111,9 +112,9 @@ def test_zero_source_equals_fused_step(q):
 
 def test_full_size_source_step_sampled():
     """The 256^3 D3Q19 mesh with two source terms (one depending on phi), binary64: one step of
-    the three-pass source path from a seeded non-equilibrium state, checked at sampled cells
-    (faces, edges, corners and random interior cells) against the oracle's per-cell step.  Here
-    the offset of a direction's plane in the g array passes 2^31 bytes."""
+    the fused source step from a seeded non-equilibrium state, checked at sampled cells
+    (faces, edges, corners, strip seams and random interior cells) against the oracle's per-cell
+    step, in the default launch."""
     p = W.workload3d("gaussian_hill3d_256")
     n = p.nx
     X, Y, Z = p.mesh()
