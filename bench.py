@@ -65,7 +65,8 @@ def parse():
                     choices=["batch256", "gaussian_hill_4096", "burgers_512",
                              "nonlinear_diffusion_1024", "gaussian_hill_128", "source_wave_4096",
                              "gaussian_hill3d_256", "fokker_planck_64m", "gaussian_hill_4096_d2q5",
-                             "gaussian_hill3d_256_d3q15", "gaussian_hill3d_256_d3q7"])
+                             "gaussian_hill3d_256_d3q15", "gaussian_hill3d_256_d3q7",
+                             "gaussian_hill3d_256_src"])
     ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16neq", "bf16neq"])
     ap.add_argument("--launch3", default=None,
                     help="three-dimensional launch rows_per_block,planes_per_block")
@@ -241,16 +242,18 @@ def cpu_baseline(seconds, all_cores=True):
                       f"D = phi I), {steps} steps in {el:.1f} s, binary64, {threads} thread(s)"}
 
 
-def cpu_baseline3d(seconds, all_cores=True):
+def cpu_baseline3d(seconds, all_cores=True, sources=False):
     """The 3-D oracle as it stands on a 64^3 instance of the Gaussian-hill
-    recipe: its OpenMP build on every core this process may use, or its serial
-    build on one."""
+    recipe (with the source workload's two terms when asked): its OpenMP build
+    on every core this process may use, or its serial build on one."""
     from oracle import Oracle3D
     from oracle import oracle3d as OR3
     from paper_1906_11036_amd import workloads as W
     model, ncpu = host_cpu()
     threads = OR3.threads(ncpu, openmp=True) if all_cores else 1
     p = W.gaussian_hill3d_problem(64, q=19, u=(0.05, 0.02, 0.01), D=1e-4, sigma0=0.15, images0=0)
+    if sources:
+        p = W.with_sources3d(p)
     o = Oracle3D(p, openmp=all_cores)
     o.step(1)
     steps, t0 = 0, time.perf_counter()
@@ -260,8 +263,8 @@ def cpu_baseline3d(seconds, all_cores=True):
     el = time.perf_counter() - t0
     return {"value": round(p.cells * steps / el / 1e6, 3), "unit": "MLUPS", "cores": threads,
             "kind": "oracle", "cpu_model": model, "nproc": ncpu,
-            "sample": f"one 64^3 periodic D3Q19 Gaussian-hill instance, {steps} steps in {el:.1f} s, "
-                      f"binary64, {threads} thread(s)"}
+            "sample": f"one 64^3 periodic D3Q19 Gaussian-hill instance{' with two source terms' if sources else ''}, "
+                      f"{steps} steps in {el:.1f} s, binary64, {threads} thread(s)"}
 
 
 BYTES_PER_UPDATE3 = {0: 2 * 19 * 8, 1: 2 * 19 * 4}   # D3Q19: read + write of the stored state
@@ -387,7 +390,8 @@ def main3d(args):
     info = s.info()
     ms_step = ms / args.steps
     mlups = p.cells * args.steps / (ms * 1e-3) / 1e6
-    alg_bytes = 2 * p.q * (8 if storage == 0 else 4) * p.cells
+    # the state read and written once, and each source term's G read once
+    alg_bytes = (2 * p.q * (8 if storage == 0 else 4) + 8 * source_terms(p)) * p.cells
     achieved = alg_bytes / (ms_step * 1e-3) / 1e9
     log(f"{args.storage}: {ms_step:.4f} ms/step, {mlups:.0f} MLUPS, {achieved:.0f} GB/s algorithmic "
         f"(rows/block={info['rows_per_block']} planes/block={info['planes_per_block']})")
@@ -436,8 +440,9 @@ def main3d(args):
     }
     out.update(extras)
     if not args.no_extras:
-        out["cpu_baseline"] = cpu_baseline3d(args.cpu_seconds)
-        out["cpu_baseline_1core"] = cpu_baseline3d(args.cpu_seconds, all_cores=False)
+        src = source_terms(p) > 0
+        out["cpu_baseline"] = cpu_baseline3d(args.cpu_seconds, sources=src)
+        out["cpu_baseline_1core"] = cpu_baseline3d(args.cpu_seconds, all_cores=False, sources=src)
     out["device"] = device_info()
     print(json.dumps(out), flush=True)
 

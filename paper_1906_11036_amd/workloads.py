@@ -679,8 +679,21 @@ def workload3d(name: str, **kw) -> Problem3D:
         "gaussian_hill3d_256_d3q7": lambda: gaussian_hill3d_problem(
             256, q=7, u=(0.05, 0.02, 0.01), D=1e-4, sigma0=0.15, steps=1000,
             name="gaussian_hill3d_256_d3q7", images0=0, **kw),
+        # the D3Q19 hill with a source of two terms: 0.1 cos(pi x) cos(pi y) phi (depends on
+        # phi: Newton's method in cells and faces) and 0.05 e^{0.3 t}
+        "gaussian_hill3d_256_src": lambda: with_sources3d(gaussian_hill3d_problem(
+            256, q=19, u=(0.05, 0.02, 0.01),
+            K=[[1.0e-4, 2e-5, 1e-5], [2e-5, 1.5e-4, -1e-5], [1e-5, -1e-5, 0.8e-4]], D=1e-4,
+            sigma0=0.15, steps=1000, name="gaussian_hill3d_256_src", images0=0, **kw)),
     }
     return table[name]()
+
+
+def with_sources3d(p: "Problem3D") -> "Problem3D":
+    """p with the source of the gaussian_hill3d_256_src workload (two terms)."""
+    X, Y, Z = p.mesh()
+    p.src_terms = [(1, 0.0, 0.1 * np.cos(np.pi * X) * np.cos(np.pi * Y)), (0, 0.3, np.full_like(X, 0.05))]
+    return p
 
 
 def random_distributions3d(seed: int, q: int, nz: int, ny: int, nx: int, mean: float = 0.5,
