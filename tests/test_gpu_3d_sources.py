@@ -144,3 +144,49 @@ def test_full_size_source_step_sampled():
     err = rel_max(got, ref)
     say(f"  sampled max rel err {err:.2e} over {len(cells)} cells")
     assert err <= 1e-12
+
+
+@pytest.mark.parametrize("storage,launches", [("f32", [(2, 1), (3, 5), (4, 2), (2, 32)]),
+                                              ("f64", [(1, 3), (2, 1), (2, 32)])])
+@pytest.mark.parametrize("q,bc", [(19, (P, P, P)), (15, (M, D, P))])
+def test_fused_source_launch_shapes_give_identical_results(storage, launches, q, bc):
+    """The fused source step: tiles of 1 to 4 rows and chunks of 1 to 32 planes give bitwise the
+    same state (ragged strips, tiles and chunks; walls of every kind)."""
+    p = W.random_problem3d(950 + q, 67, 7, 9, q=q, bc=bc, stretched=True, bdeg=2)
+    p.src_terms = W.random_source_terms3d(960 + q, p, nterms=3, amp=1.0)
+    say(f"case 3d fused source launch shapes {storage} q={q} bc={bc}")
+    out = []
+    for ln in launches:
+        s = dg.Solver3D(p, storage=storage)
+        try:
+            s.set_launch(*ln)
+        except dg.DugksError as e:
+            pytest.skip(f"launch {ln} not available on this device: {e}")
+        s.set_phi(p.phi0)
+        if D in bc:
+            s.set_dirichlet(p.rings(4))
+        s.step(4)
+        out.append(s.get_f())
+        s.close()
+    for f in out[1:]:
+        assert np.array_equal(f, out[0])
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_fused_source_autotune_keeps_state(storage):
+    """dugks3_autotune with a source: the state is unchanged and later steps equal a run
+    without it, bitwise."""
+    p = W.random_problem3d(970, 70, 9, 7, q=19, bc=(P, M, P), bdeg=2)
+    p.src_terms = W.random_source_terms3d(971, p, nterms=2, amp=0.8)
+    say(f"case 3d fused source autotune {storage}")
+    ref = dg.Solver3D(p, storage=storage)
+    ref.set_phi(p.phi0)
+    ref.step(5)
+    s = dg.Solver3D(p, storage=storage)
+    s.set_phi(p.phi0)
+    s.step(2)
+    f0 = s.get_f()
+    s.autotune(2)
+    assert np.array_equal(s.get_f(), f0)
+    s.step(3)
+    assert np.array_equal(s.get_f(), ref.get_f())
