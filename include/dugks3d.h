@@ -189,6 +189,44 @@ int dugks3_time_steps(dugks3_ctx* ctx, int nsteps, float* ms_total);
 int dugks3_autotune(dugks3_ctx* ctx, int trial_steps);
 
 int dugks3_get_info(const dugks3_ctx* ctx, dugks3_info* out);
+
+/* ------------------------------------------------------------------ batches
+ * Many D3Q15 or D3Q19 instances (one lattice, one storage; sizes, meshes,
+ * walls and coefficients their own) advanced by one launch per step, as the
+ * two-dimensional batch: each instance keeps its context (created, set up,
+ * bound and given its state as usual; caller-owned, kept bound to the same
+ * workspace while in the batch), and the batch's launch covers the blocks of
+ * all of them (rows and planes per block shared; the instantiation for the
+ * largest coefficient count, with mirror code if any instance has a wall).
+ * D3Q19 instances get bitwise what they get alone; D3Q15 ones the same up to
+ * the order of the face sums when a walled batch holds periodic instances
+ * (the walled instantiation splits the directions in two parts, the periodic
+ * one in four).  Sources are not batched (E_UNSUPPORTED at the step).
+ * Create: E_ARG (n < 1, an invalid context, a mix of lattices or storages),
+ * E_UNSUPPORTED (D3Q7). */
+typedef struct dugks3_batch dugks3_batch;
+int dugks3_batch_create(dugks3_batch** out, int n, dugks3_ctx* const* ctxs);
+/* Device bytes of the batch's table (instance pointers and block offsets). */
+size_t dugks3_batch_workspace_bytes(const dugks3_batch* b);
+/* Workspace (device, 256-byte aligned) and stream; every instance must be
+ * bound.  Errors: E_ARG, E_NOMEM, E_STATE, E_HIP. */
+int dugks3_batch_bind(dugks3_batch* b, void* dev_workspace, size_t bytes, void* hip_stream);
+/* Rows and planes per block for the batch's launch (ranges as
+ * dugks3_set_launch; defaults 2 rows binary64, 4 binary32, 32 planes). */
+int dugks3_batch_set_launch(dugks3_batch* b, int rows_per_block, int planes_per_block);
+/* nsteps steps of every instance, one launch each; the instances must be at
+ * the same step count, with Dirichlet data covering the steps (E_STATE) and
+ * no source (E_UNSUPPORTED).  Asynchronous; each context's step count
+ * advances. */
+int dugks3_batch_step(dugks3_batch* b, int nsteps);
+/* dugks3_batch_step timed with hipEvents on the batch's stream. */
+int dugks3_batch_time_steps(dugks3_batch* b, int nsteps, float* ms_total);
+/* The launch shape, the grid's blocks and the cells of all instances (any
+ * pointer may be NULL). */
+int dugks3_batch_get_info(const dugks3_batch* b, int* rows_per_block, int* planes_per_block,
+                          long long* blocks, long long* cells);
+const char* dugks3_batch_last_error(const dugks3_batch* b);
+void dugks3_batch_destroy(dugks3_batch* b);
 const char* dugks3_last_error(const dugks3_ctx* ctx);
 void dugks3_destroy(dugks3_ctx* ctx);
 

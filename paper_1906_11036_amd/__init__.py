@@ -15,7 +15,7 @@ from . import _lib as L
 from ._lib import (BC_DIRICHLET, BC_MIRROR, BC_PERIODIC, BF16NEQ, F16NEQ, F32, F64,  # noqa: F401
                    KERNEL_FUSED, KERNEL_PLAIN, SCHED_GRID, SCHED_PERSISTENT, STORAGE, DugksError)
 
-__all__ = ["Solver", "Batch", "Solver3D", "Solver1D", "DugksError", "F64", "F32", "F16NEQ", "BF16NEQ"]
+__all__ = ["Solver", "Batch", "Solver3D", "Batch3D", "Solver1D", "DugksError", "F64", "F32", "F16NEQ", "BF16NEQ"]
 
 
 def _torch():
@@ -519,6 +519,61 @@ class Solver3D:
             self.lib.dugks3_destroy(self.h)
             self.h = None
         self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch3D:
+    """Many D3Q15 or D3Q19 instances stepped by one launch per step
+    (``dugks3_batch``): ``solvers`` are ``Solver3D`` objects of one lattice and
+    storage, set up and given their states; they stay alive and bound while the
+    batch lives, and their own accessors read the results."""
+
+    def __init__(self, solvers, launch=None):
+        torch = _torch()
+        self.lib = L.lib()
+        self.solvers = list(solvers)
+        self.device = self.solvers[0].device
+        self.h = C.c_void_p()
+        arr = (C.c_void_p * len(self.solvers))(*[s.h.value for s in self.solvers])
+        rc = self.lib.dugks3_batch_create(C.byref(self.h), len(self.solvers), arr)
+        L.check_b3(rc, self.h, "dugks3_batch_create")
+        nbytes = self.lib.dugks3_batch_workspace_bytes(self.h)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            ptr = (self.workspace.data_ptr() + 255) & ~255
+            L.check_b3(self.lib.dugks3_batch_bind(self.h, C.c_void_p(ptr), nbytes, _stream_handle(self.device)),
+                       self.h, "dugks3_batch_bind")
+        if launch is not None:
+            self.set_launch(*launch)
+
+    def set_launch(self, rows_per_block, planes_per_block):
+        L.check_b3(self.lib.dugks3_batch_set_launch(self.h, int(rows_per_block), int(planes_per_block)), self.h,
+                   "dugks3_batch_set_launch")
+
+    def step(self, nsteps=1):
+        L.check_b3(self.lib.dugks3_batch_step(self.h, int(nsteps)), self.h, "dugks3_batch_step")
+
+    def time_steps(self, nsteps):
+        ms = C.c_float()
+        L.check_b3(self.lib.dugks3_batch_time_steps(self.h, int(nsteps), C.byref(ms)), self.h,
+                   "dugks3_batch_time_steps")
+        return ms.value
+
+    def info(self) -> dict:
+        r, p, b, c = C.c_int(), C.c_int(), C.c_longlong(), C.c_longlong()
+        L.check_b3(self.lib.dugks3_batch_get_info(self.h, C.byref(r), C.byref(p), C.byref(b), C.byref(c)), self.h,
+                   "dugks3_batch_get_info")
+        return {"rows_per_block": r.value, "planes_per_block": p.value, "blocks": b.value, "cells": c.value}
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            self.lib.dugks3_batch_destroy(self.h)
+            self.h = C.c_void_p()
 
     def __del__(self):
         try:

@@ -141,6 +141,16 @@ SIGNATURES = {
     "dugks3_set_launch": (_int, [_vp, _int, _int]),
     "dugks3_time_steps": (_int, [_vp, _int, C.POINTER(C.c_float)]),
     "dugks3_autotune": (_int, [_vp, _int]),
+    "dugks3_batch_create": (_int, [C.POINTER(_vp), _int, C.POINTER(_vp)]),
+    "dugks3_batch_workspace_bytes": (C.c_size_t, [_vp]),
+    "dugks3_batch_bind": (_int, [_vp, _vp, C.c_size_t, _vp]),
+    "dugks3_batch_set_launch": (_int, [_vp, _int, _int]),
+    "dugks3_batch_step": (_int, [_vp, _int]),
+    "dugks3_batch_time_steps": (_int, [_vp, _int, C.POINTER(C.c_float)]),
+    "dugks3_batch_get_info": (_int, [_vp, C.POINTER(_int), C.POINTER(_int), C.POINTER(C.c_longlong),
+                                     C.POINTER(C.c_longlong)]),
+    "dugks3_batch_last_error": (C.c_char_p, [_vp]),
+    "dugks3_batch_destroy": (None, [_vp]),
     "dugks3_get_info": (_int, [_vp, C.POINTER(Info3)]),
     "dugks3_last_error": (C.c_char_p, [_vp]),
     "dugks3_destroy": (None, [_vp]),
@@ -198,6 +208,14 @@ def check1(rc, handle, what=""):
     """check() for a one-dimensional handle."""
     if rc != OK:
         msg = lib().dugks1_last_error(handle).decode() if handle else ""
+        raise DugksError(rc, f"{what}: {msg}" if what else msg)
+    return rc
+
+
+def check_b3(rc, handle, what=""):
+    """check() for a three-dimensional batch handle."""
+    if rc != OK:
+        msg = lib().dugks3_batch_last_error(handle).decode() if handle else ""
         raise DugksError(rc, f"{what}: {msg}" if what else msg)
     return rc
 

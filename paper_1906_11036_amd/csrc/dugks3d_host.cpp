@@ -691,3 +691,203 @@ void dugks3_destroy(dugks3_ctx* ctx) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ batches
+namespace {
+constexpr uint32_t kMagicB3 = 0x44554242u;  // "DUBB"
+}
+
+struct dugks3_batch {
+  uint32_t magic = kMagicB3;
+  std::string err;
+  std::vector<dugks3_ctx*> inst;   // caller-owned, bound, kept bound while in the batch
+  int q = 19, storage = 0;
+  Launch3 launch;
+  std::vector<long long> first;    // blocks before instance k (n + 1 entries)
+  char* ws = nullptr;              // device: the instance pointers, then `first`
+  size_t ws_bytes = 0;
+  hipStream_t stream = nullptr;
+  size_t off_first = 0, total = 0;
+
+  int fail(int rc, const std::string& m) { err = m; return rc; }
+  int ncoef() const {
+    int m = 2;
+    for (auto* c : inst) m = std::max(m, c->ncoef);
+    return m;
+  }
+  // the instantiation with mirror code runs if any instance has a wall or
+  // more than four equilibrium coefficients
+  bool walls() const {
+    for (auto* c : inst)
+      if (c->p.bc[0] != DUGKS_BC_PERIODIC || c->p.bc[1] != DUGKS_BC_PERIODIC || c->p.bc[2] != DUGKS_BC_PERIODIC ||
+          c->ncoef > 4)
+        return true;
+    return false;
+  }
+  size_t lds_bytes(const Launch3& l) const { return step3_lds_bytes(storage, q, walls(), l); }
+  void layout() {
+    off_first = align256(sizeof(const Inst3*) * inst.size());
+    total = off_first + align256(sizeof(long long) * (inst.size() + 1));
+  }
+  // the blocks of each instance for the launch, and the device table
+  int upload() {
+    first.assign(inst.size() + 1, 0);
+    for (size_t k = 0; k < inst.size(); ++k) {
+      Inst3 t{};
+      for (int a = 0; a < 3; ++a) t.n[a] = inst[k]->n[a];
+      first[k + 1] = first[k] + step3_blocks(t, launch);
+    }
+    if (first.back() > 0x7fffffffLL) return fail(DUGKS_E_ARG, "the batch needs more than 2^31 blocks");
+    if (!ws) return DUGKS_OK;
+    std::vector<const Inst3*> ptr(inst.size());
+    for (size_t k = 0; k < inst.size(); ++k) ptr[k] = inst[k]->dev();
+    hipError_t e = hipMemcpyAsync(ws, ptr.data(), sizeof(const Inst3*) * ptr.size(), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(ws + off_first, first.data(), sizeof(long long) * first.size(), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+      err = std::string("batch table upload: ") + hipGetErrorString(e);
+      return DUGKS_E_HIP;
+    }
+    return DUGKS_OK;
+  }
+};
+
+#define GUARDB3(b)                                                       \
+  do {                                                                   \
+    if (!(b) || (b)->magic != kMagicB3) return DUGKS_E_ARG;              \
+  } while (0)
+
+extern "C" {
+
+int dugks3_batch_create(dugks3_batch** out, int n, dugks3_ctx* const* ctxs) {
+  if (!out) return DUGKS_E_ARG;
+  *out = nullptr;
+  auto* b = new dugks3_batch();
+  *out = b;
+  if (n < 1 || !ctxs) return b->fail(DUGKS_E_ARG, "a batch needs n >= 1 contexts");
+  for (int k = 0; k < n; ++k) {
+    dugks3_ctx* c = ctxs[k];
+    if (!c || c->magic != kMagic3) return b->fail(DUGKS_E_ARG, "invalid context in the batch");
+    if (c->q == 7) return b->fail(DUGKS_E_UNSUPPORTED, "D3Q7 is not batched");
+    if (k > 0 && (c->q != b->q || c->p.storage != b->storage))
+      return b->fail(DUGKS_E_ARG, "the instances of a batch share the lattice and the storage");
+    if (k == 0) {
+      b->q = c->q;
+      b->storage = c->p.storage;
+    }
+    b->inst.push_back(c);
+  }
+  b->launch.rows = b->storage == DUGKS_F64 ? 2 : 4;
+  b->launch.planes = 32;
+  b->layout();
+  return b->upload();
+}
+
+size_t dugks3_batch_workspace_bytes(const dugks3_batch* b) {
+  return (b && b->magic == kMagicB3) ? b->total : 0;
+}
+
+int dugks3_batch_bind(dugks3_batch* b, void* ws, size_t bytes, void* stream) {
+  GUARDB3(b);
+  if (!ws) return b->fail(DUGKS_E_ARG, "workspace is NULL");
+  if (((uintptr_t)ws & 255) != 0) return b->fail(DUGKS_E_ARG, "workspace must be 256-byte aligned");
+  if (bytes < b->total) return b->fail(DUGKS_E_NOMEM, "workspace too small");
+  for (auto* c : b->inst)
+    if (!c->bound()) return b->fail(DUGKS_E_STATE, "every instance must be bound first");
+  b->ws = (char*)ws;
+  b->ws_bytes = bytes;
+  b->stream = (hipStream_t)stream;
+  return b->upload();
+}
+
+int dugks3_batch_set_launch(dugks3_batch* b, int rows, int planes) {
+  GUARDB3(b);
+  if (b->storage == DUGKS_F64 ? (rows < kMinRows64 || rows > kMaxRows64) : (rows < kMinRows32 || rows > kMaxRows32))
+    return b->fail(DUGKS_E_ARG, "rows_per_block out of range for the storage");
+  if (planes < 1) return b->fail(DUGKS_E_ARG, "planes_per_block must be >= 1");
+  Launch3 l;
+  l.rows = rows;
+  l.planes = planes;
+  if (b->ws && b->lds_bytes(l) > b->inst[0]->lds_limit())
+    return b->fail(DUGKS_E_ARG, "launch needs more LDS than a block may hold");
+  const Launch3 keep = b->launch;
+  b->launch = l;
+  const int rc = b->upload();
+  if (rc) b->launch = keep;
+  return rc;
+}
+
+int dugks3_batch_step(dugks3_batch* b, int nsteps) {
+  GUARDB3(b);
+  if (nsteps < 0) return b->fail(DUGKS_E_ARG, "nsteps < 0");
+  if (!b->ws) return b->fail(DUGKS_E_STATE, "not bound");
+  const long long step = b->inst[0]->step;
+  for (auto* c : b->inst) {
+    if (!c->bound() || !c->initialised) return b->fail(DUGKS_E_STATE, "an instance has no state");
+    if (c->step != step) return b->fail(DUGKS_E_STATE, "the instances of a batch must be at the same step");
+    if (c->src_n > 0) return b->fail(DUGKS_E_UNSUPPORTED, "sources are not batched");
+    if (c->any_dirichlet() && (c->ring == nullptr || c->step + nsteps > c->ring_steps))
+      return b->fail(DUGKS_E_STATE, "Dirichlet data does not cover the requested steps");
+  }
+  if (b->lds_bytes(b->launch) > b->inst[0]->lds_limit())
+    return b->fail(DUGKS_E_ARG, "launch needs more LDS than a block may hold");
+  Inst3 h = b->inst[0]->host;   // template selectors: the largest coefficient count of the batch
+  h.ncoef = b->ncoef();
+  const Batch3 base{(const Inst3* const*)b->ws, (const long long*)(b->ws + b->off_first), (int)b->inst.size(), 0};
+  for (int s = 0; s < nsteps; ++s) {
+    Batch3 bt = base;
+    bt.step = step + s;
+    if (launch_step3_batch(bt, h, (int)(bt.step & 1), b->walls(), b->first.back(), b->launch, b->stream))
+      return b->fail(DUGKS_E_HIP, std::string("batch step launch failed: ") + hipGetErrorString(hipGetLastError()));
+    for (auto* c : b->inst) c->step += 1;
+  }
+  return DUGKS_OK;
+}
+
+int dugks3_batch_time_steps(dugks3_batch* b, int nsteps, float* ms) {
+  GUARDB3(b);
+  if (!ms) return b->fail(DUGKS_E_ARG, "ms is NULL");
+  if (!b->ws) return b->fail(DUGKS_E_STATE, "not bound");
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return b->fail(DUGKS_E_HIP, "event create");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return b->fail(DUGKS_E_HIP, "event create");
+  }
+  hipError_t er = hipEventRecord(e0, b->stream);
+  int rc = er == hipSuccess ? dugks3_batch_step(b, nsteps) : DUGKS_E_HIP;
+  if (rc == DUGKS_OK) er = hipEventRecord(e1, b->stream);
+  if (rc == DUGKS_OK && er == hipSuccess) er = hipEventSynchronize(e1);
+  if (rc == DUGKS_OK && er == hipSuccess) er = hipEventElapsedTime(ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  return er == hipSuccess ? DUGKS_OK : b->fail(DUGKS_E_HIP, "timing");
+}
+
+int dugks3_batch_get_info(const dugks3_batch* b, int* rows, int* planes, long long* blocks, long long* cells) {
+  if (!b || b->magic != kMagicB3) return DUGKS_E_ARG;
+  if (rows) *rows = b->launch.rows;
+  if (planes) *planes = b->launch.planes;
+  if (blocks) *blocks = b->first.empty() ? 0 : b->first.back();
+  if (cells) {
+    long long c = 0;
+    for (auto* x : b->inst) c += x->cells();
+    *cells = c;
+  }
+  return DUGKS_OK;
+}
+
+const char* dugks3_batch_last_error(const dugks3_batch* b) {
+  if (!b || b->magic != kMagicB3) return "invalid handle";
+  return b->err.c_str();
+}
+
+void dugks3_batch_destroy(dugks3_batch* b) {
+  if (!b || b->magic != kMagicB3) return;
+  b->magic = 0;
+  delete b;
+}
+
+}  // extern "C"

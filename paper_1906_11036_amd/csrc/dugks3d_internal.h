@@ -64,6 +64,16 @@ struct alignas(64) Inst3 {
   void* fscr[3];           // source path: fluxes of the faces normal to x, y, z, [slot][face]
 };
 
+// A batch of instances stepped by one launch: instance k takes blocks
+// first[k] .. first[k+1] - 1 (after the XCD remap) with its own strips, tiles
+// and plane chunks; insts == nullptr: one instance (the kernel's arguments).
+struct Batch3 {
+  const Inst3* const* insts;
+  const long long* first;
+  int n;
+  long long step;   // the step index (selects each instance's Dirichlet data)
+};
+
 struct Launch3 {
   int rows = 4;     // rows per block (see kMinRows32 .. kMaxRows64)
   int planes = 64;  // planes swept per block
@@ -96,6 +106,11 @@ int launch_src3_step(const Inst3* d, const Inst3& h, int parity, long long step,
 // values in the source path's flux array of one axis: the directions that
 // cross a face normal to it times the faces ((nx+1) ny nz for x, ...)
 size_t src3_flux_values(int q, int axis, int nx, int ny, int nz);
+// one step of a batch (D3Q15 / D3Q19, no source): ncoef the largest of the
+// instances, walls whether any has a wall (the instantiation with mirror
+// code then runs them all), blocks the grid (first[n] of the table)
+int launch_step3_batch(const Batch3& bt, const Inst3& h, int parity, bool walls, long long blocks,
+                       const Launch3& l, void* stream);
 // LDS bytes of one block of the step kernel (walls: the instantiation with
 // mirror code, for a non-periodic axis or more than four coefficients)
 size_t step3_lds_bytes(int storage, int q, bool walls, const Launch3& l);

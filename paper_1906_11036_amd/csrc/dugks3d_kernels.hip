@@ -1011,7 +1011,8 @@ template <int Q, int NC, int ROWS, typename T, int H, bool WALLS, bool SRC>
 __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int parity,
                                             const double* __restrict__ ring, STab tb, int planes,
                                             int strips, int tiles, LdsP<Q, ROWS, T, WALLS>& L,
-                                            const float* ecoef, double (*hphi)[4][kLanes], int w, int rw) {
+                                            const float* ecoef, double (*hphi)[4][kLanes], int w, int rw,
+                                            int blk) {
   using LP = LdsP<Q, ROWS, T, WALLS>;
   constexpr int P = parts<Q, T, ROWS, WALLS>();
   constexpr int W = LP::W, WD = LP::WD;
@@ -1020,7 +1021,7 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
   constexpr unsigned ES = sizeof(T);
   constexpr bool kVecE = LP::kVecE && NC <= 4;
   const int lane = threadIdx.x & 63;
-  int b = xcd_contiguous(blockIdx.x, gridDim.x);
+  int b = blk;   // the block within its instance
   const int sx = b % strips;
   b /= strips;
   const int tj = b % tiles, tk = b / tiles;
@@ -1477,13 +1478,28 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
 }
 
 // WALLS = false: every axis periodic, no mirror code
-template <int Q, int NC, int ROWS, typename T, bool WALLS, bool SRC>
+// BATCH: the blocks of many instances (Batch3) in one launch
+template <int Q, int NC, int ROWS, typename T, bool WALLS, bool SRC, bool BATCH>
 __global__ __launch_bounds__((64 * parts<Q, T, ROWS, WALLS>() * ROWS)) void k_step3p(const Inst3* __restrict__ I, int parity,
                                                                        const double* __restrict__ ring,
                                                                        const SrcTab st, int planes, int strips,
-                                                                       int tiles) {
+                                                                       int tiles, const Batch3 bt) {
   constexpr int P = parts<Q, T, ROWS, WALLS>();
   __shared__ LdsP<Q, ROWS, T, WALLS> L;
+  int blk = xcd_contiguous(blockIdx.x, gridDim.x);
+  if constexpr (BATCH) {   // this block's instance: the last k with first[k] <= blk
+    int lo = 0, hi = bt.n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (bt.first[mid] <= blk) lo = mid;
+      else hi = mid - 1;
+    }
+    I = bt.insts[lo];
+    blk -= (int)bt.first[lo];
+    strips = (I->n[0] + kCols - 1) / kCols;
+    tiles = (I->n[1] + ROWS - 1) / ROWS;
+    ring = I->ring != nullptr ? I->ring + bt.step * I->ring_len : nullptr;
+  }
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int rw = w / P;
   // part of wave w: with four parts rotated by the row, so that each SIMD
@@ -1503,13 +1519,13 @@ __global__ __launch_bounds__((64 * parts<Q, T, ROWS, WALLS>() * ROWS)) void k_st
     hp = hphi;
   }
   switch (part) {
-    case 0: step3p_half<Q, NC, ROWS, T, 0, WALLS, SRC>(I, parity, ring, tb, planes, strips, tiles, L, ec, hp, w, rw); break;
-    case 1: step3p_half<Q, NC, ROWS, T, 1, WALLS, SRC>(I, parity, ring, tb, planes, strips, tiles, L, ec, hp, w, rw); break;
+    case 0: step3p_half<Q, NC, ROWS, T, 0, WALLS, SRC>(I, parity, ring, tb, planes, strips, tiles, L, ec, hp, w, rw, blk); break;
+    case 1: step3p_half<Q, NC, ROWS, T, 1, WALLS, SRC>(I, parity, ring, tb, planes, strips, tiles, L, ec, hp, w, rw, blk); break;
     case 2:
-      if constexpr (P > 2) step3p_half<Q, NC, ROWS, T, 2, WALLS, SRC>(I, parity, ring, tb, planes, strips, tiles, L, ec, hp, w, rw);
+      if constexpr (P > 2) step3p_half<Q, NC, ROWS, T, 2, WALLS, SRC>(I, parity, ring, tb, planes, strips, tiles, L, ec, hp, w, rw, blk);
       break;
     default:
-      if constexpr (P > 2) step3p_half<Q, NC, ROWS, T, 3, WALLS, SRC>(I, parity, ring, tb, planes, strips, tiles, L, ec, hp, w, rw);
+      if constexpr (P > 2) step3p_half<Q, NC, ROWS, T, 3, WALLS, SRC>(I, parity, ring, tb, planes, strips, tiles, L, ec, hp, w, rw, blk);
       break;
   }
 }
@@ -1691,57 +1707,65 @@ static void step3_row_waves(const Inst3* d, const Inst3& h, int parity, const do
   }
 }
 
-template <int Q, int NC, int ROWS, typename T, bool WALLS, bool SRC>
-static void step3p_go(const Inst3* d, int parity, const double* ring, const SrcTab& ss, const Launch3& l, int strips,
-                      int tiles, dim3 grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_step3p<Q, NC, ROWS, T, WALLS, SRC>), grid, dim3(64 * parts<Q, T, ROWS, WALLS>() * ROWS), 0, st,
-                     d, parity, ring, ss, l.planes, strips, tiles);
+// The launch arguments of the staged kernel
+struct Args3 {
+  const Inst3* d;
+  int parity;
+  const double* ring;
+  SrcTab ss;
+  int strips, tiles;
+  Batch3 bt;
+};
+template <int Q, int NC, int ROWS, typename T, bool WALLS, bool SRC, bool BATCH>
+static void step3p_go(const Args3& a, const Launch3& l, dim3 grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_step3p<Q, NC, ROWS, T, WALLS, SRC, BATCH>), grid, dim3(64 * parts<Q, T, ROWS, WALLS>() * ROWS),
+                     0, st, a.d, a.parity, a.ring, a.ss, l.planes, a.strips, a.tiles, a.bt);
 }
-template <int Q, int NC, typename T, bool WALLS, bool SRC>
-static void step3p_launch(const Inst3* d, int parity, const double* ring, const SrcTab& ss, const Launch3& l,
-                          int strips, int tiles, dim3 grid, hipStream_t st) {
+template <int Q, int NC, typename T, bool WALLS, bool SRC, bool BATCH = false>
+static void step3p_launch(const Args3& a, const Launch3& l, dim3 grid, hipStream_t st) {
   if constexpr (sizeof(T) == 8) {   // rows 1 and 2 fit the LDS
-    if (l.rows == 1) step3p_go<Q, NC, 1, T, WALLS, SRC>(d, parity, ring, ss, l, strips, tiles, grid, st);
-    else step3p_go<Q, NC, 2, T, WALLS, SRC>(d, parity, ring, ss, l, strips, tiles, grid, st);
+    if (l.rows == 1) step3p_go<Q, NC, 1, T, WALLS, SRC, BATCH>(a, l, grid, st);
+    else step3p_go<Q, NC, 2, T, WALLS, SRC, BATCH>(a, l, grid, st);
   } else {
     switch (l.rows) {
-      case 2: step3p_go<Q, NC, 2, T, WALLS, SRC>(d, parity, ring, ss, l, strips, tiles, grid, st); break;
-      case 3: step3p_go<Q, NC, 3, T, WALLS, SRC>(d, parity, ring, ss, l, strips, tiles, grid, st); break;
-      default: step3p_go<Q, NC, 4, T, WALLS, SRC>(d, parity, ring, ss, l, strips, tiles, grid, st); break;
+      case 2: step3p_go<Q, NC, 2, T, WALLS, SRC, BATCH>(a, l, grid, st); break;
+      case 3: step3p_go<Q, NC, 3, T, WALLS, SRC, BATCH>(a, l, grid, st); break;
+      default: step3p_go<Q, NC, 4, T, WALLS, SRC, BATCH>(a, l, grid, st); break;
     }
   }
 }
 // With a source: the instantiation with mirror code (it serves periodic axes too)
 template <int Q, int NC, typename T>
-static void step3p_rows(const Inst3* d, const Inst3& h, int parity, const double* ring, const SrcTab& ss,
-                        const Launch3& l, int strips, int tiles, dim3 grid, hipStream_t st) {
-  const bool walls = h.bc[0] != DUGKS_BC_PERIODIC || h.bc[1] != DUGKS_BC_PERIODIC || h.bc[2] != DUGKS_BC_PERIODIC;
-  if (h.src_n > 0) step3p_launch<Q, NC, T, true, true>(d, parity, ring, ss, l, strips, tiles, grid, st);
-  else if (NC == 8 || walls) step3p_launch<Q, NC, T, true, false>(d, parity, ring, ss, l, strips, tiles, grid, st);
-  else if constexpr (NC != 8) step3p_launch<Q, NC, T, false, false>(d, parity, ring, ss, l, strips, tiles, grid, st);
+static void step3p_rows(const Args3& a, const Inst3& h, bool walls, const Launch3& l, dim3 grid, hipStream_t st) {
+  if (a.bt.insts != nullptr) {   // a batch
+    if (NC == 8 || walls) step3p_launch<Q, NC, T, true, false, true>(a, l, grid, st);
+    else if constexpr (NC != 8) step3p_launch<Q, NC, T, false, false, true>(a, l, grid, st);
+  } else if (h.src_n > 0) step3p_launch<Q, NC, T, true, true>(a, l, grid, st);
+  else if (NC == 8 || walls) step3p_launch<Q, NC, T, true, false>(a, l, grid, st);
+  else if constexpr (NC != 8) step3p_launch<Q, NC, T, false, false>(a, l, grid, st);
 }
 
 template <int Q>
-static int step3_q(const Inst3* d, const Inst3& h, int parity, const double* ring, const SrcTab& ss,
-                   const Launch3& l, void* stream) {
-  const int strips = (h.n[0] + kCols - 1) / kCols;
-  const int tiles = (h.n[1] + l.rows - 1) / l.rows;
-  const long long blocks = step3_blocks(h, l);
+static int step3_q(const Args3& a, const Inst3& h, bool walls, long long blocks, const Launch3& l, void* stream) {
+  const int strips = a.strips, tiles = a.tiles;
+  const Inst3* d = a.d;
+  const int parity = a.parity;
+  const double* ring = a.ring;
   if (blocks <= 0 || blocks > 0x7fffffffLL) return -1;
   const dim3 grid((unsigned)blocks);
   const int nc = h.ncoef <= 2 ? 2 : (h.ncoef <= 4 ? 4 : 8);
   if constexpr (Q != 7) {   // split directions
     if (h.storage == DUGKS_F64) {
       switch (nc) {
-        case 2: step3p_rows<Q, 2, double>(d, h, parity, ring, ss, l, strips, tiles, grid, S(stream)); break;
-        case 4: step3p_rows<Q, 4, double>(d, h, parity, ring, ss, l, strips, tiles, grid, S(stream)); break;
-        default: step3p_rows<Q, 8, double>(d, h, parity, ring, ss, l, strips, tiles, grid, S(stream)); break;
+        case 2: step3p_rows<Q, 2, double>(a, h, walls, l, grid, S(stream)); break;
+        case 4: step3p_rows<Q, 4, double>(a, h, walls, l, grid, S(stream)); break;
+        default: step3p_rows<Q, 8, double>(a, h, walls, l, grid, S(stream)); break;
       }
     } else {
       switch (nc) {
-        case 2: step3p_rows<Q, 2, float>(d, h, parity, ring, ss, l, strips, tiles, grid, S(stream)); break;
-        case 4: step3p_rows<Q, 4, float>(d, h, parity, ring, ss, l, strips, tiles, grid, S(stream)); break;
-        default: step3p_rows<Q, 8, float>(d, h, parity, ring, ss, l, strips, tiles, grid, S(stream)); break;
+        case 2: step3p_rows<Q, 2, float>(a, h, walls, l, grid, S(stream)); break;
+        case 4: step3p_rows<Q, 4, float>(a, h, walls, l, grid, S(stream)); break;
+        default: step3p_rows<Q, 8, float>(a, h, walls, l, grid, S(stream)); break;
       }
     }
   } else {   // D3Q7: a whole row per wave
@@ -1763,10 +1787,25 @@ int launch_step3(const Inst3* d, const Inst3& h, int parity, long long step, con
     ss.en[j] = exp(h.src_gam[j] * ((double)step * h.dt));
     ss.ef[j] = exp(h.src_gam[j] * (((double)step + 0.5) * h.dt));
   }
+  Args3 a{d, parity, ring, ss, (h.n[0] + kCols - 1) / kCols, (h.n[1] + l.rows - 1) / l.rows, Batch3{nullptr, nullptr, 0, 0}};
+  const bool walls = h.bc[0] != DUGKS_BC_PERIODIC || h.bc[1] != DUGKS_BC_PERIODIC || h.bc[2] != DUGKS_BC_PERIODIC;
+  const long long blocks = step3_blocks(h, l);
   switch (h.q) {
-    case 19: return step3_q<19>(d, h, parity, ring, ss, l, stream);
-    case 15: return step3_q<15>(d, h, parity, ring, ss, l, stream);
-    default: return h.src_n > 0 ? -1 : step3_q<7>(d, h, parity, ring, ss, l, stream);   // D3Q7: three passes
+    case 19: return step3_q<19>(a, h, walls, blocks, l, stream);
+    case 15: return step3_q<15>(a, h, walls, blocks, l, stream);
+    default: return h.src_n > 0 ? -1 : step3_q<7>(a, h, walls, blocks, l, stream);   // D3Q7: three passes
+  }
+}
+
+int launch_step3_batch(const Batch3& bt, const Inst3& h, int parity, bool walls, long long blocks,
+                       const Launch3& l, void* stream) {
+  if (h.src_n > 0 || bt.insts == nullptr || bt.n < 1) return -1;
+  // the instance pointer, strips, tiles and Dirichlet data come from the table
+  const Args3 a{nullptr, parity, nullptr, SrcTab{}, 0, 0, bt};
+  switch (h.q) {
+    case 19: return step3_q<19>(a, h, walls, blocks, l, stream);
+    case 15: return step3_q<15>(a, h, walls, blocks, l, stream);
+    default: return -1;
   }
 }
 

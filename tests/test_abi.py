@@ -255,6 +255,43 @@ def test_3d_source_term_arguments():
     lib.dugks3_destroy(h)
 
 
+def test_3d_batch_arguments():
+    """Batch creation and binding are checked on the host, with no device work."""
+    lib = L.lib()
+    P = C.c_void_p
+    hs = [_create3(nx=20 + k, q=19)[1] for k in range(2)]
+    h15 = _create3(q=15)[1]
+    h7 = _create3(q=7)[1]
+    h32 = _create3(q=19, storage=L.F32)[1]
+    b = P()
+    assert lib.dugks3_batch_create(C.byref(b), 0, (P * 1)(hs[0])) == L.E_ARG
+    lib.dugks3_batch_destroy(b)
+    assert lib.dugks3_batch_create(C.byref(b), 2, (P * 2)(hs[0], h15)) == L.E_ARG        # lattices
+    lib.dugks3_batch_destroy(b)
+    assert lib.dugks3_batch_create(C.byref(b), 2, (P * 2)(hs[0], h32)) == L.E_ARG        # storages
+    lib.dugks3_batch_destroy(b)
+    assert lib.dugks3_batch_create(C.byref(b), 1, (P * 1)(h7)) == L.E_UNSUPPORTED         # D3Q7
+    lib.dugks3_batch_destroy(b)
+    assert lib.dugks3_batch_create(C.byref(b), 2, (P * 2)(*hs)) == L.OK
+    nb = lib.dugks3_batch_workspace_bytes(b)
+    assert nb >= 2 * 8 + 3 * 8
+    assert lib.dugks3_batch_step(b, 1) == L.E_STATE                                       # not bound
+    assert lib.dugks3_batch_bind(b, P(4096), nb, None) == L.E_STATE                        # instances unbound
+    assert lib.dugks3_batch_bind(b, P(4100), nb, None) == L.E_ARG                          # alignment
+    assert lib.dugks3_batch_bind(b, P(4096), nb - 1, None) == L.E_NOMEM
+    assert lib.dugks3_batch_set_launch(b, 3, 8) == L.E_ARG                                 # binary64 rows
+    assert lib.dugks3_batch_set_launch(b, 2, 0) == L.E_ARG
+    assert lib.dugks3_batch_set_launch(b, 1, 16) == L.OK
+    rows, planes, blocks, cells = C.c_int(), C.c_int(), C.c_longlong(), C.c_longlong()
+    assert lib.dugks3_batch_get_info(b, C.byref(rows), C.byref(planes), C.byref(blocks), C.byref(cells)) == L.OK
+    assert (rows.value, planes.value, cells.value) == (1, 16, (20 + 21) * 6 * 5)
+    assert blocks.value == sum(((20 + k + 61) // 62) * 6 * 1 for k in range(2))
+    assert lib.dugks3_batch_last_error(b).decode()
+    lib.dugks3_batch_destroy(b)
+    for h in hs + [h15, h7, h32]:
+        lib.dugks3_destroy(h)
+
+
 def test_d3q7_accepts_only_identity_diffusion():
     lib = L.lib()
     rc, h = _create3(q=7)
