@@ -1,9 +1,11 @@
 // Drives the host side of libdugks (create, coefficient setters, source and
 // Dirichlet arguments, launch settings, checkpoint format checks, batches, the
-// 3-D and 1-D families) without a GPU, for a build of the host code with
+// 3-D family with its sources, autotuner and batches, and the 1-D family)
+// without a GPU, for a build of the host code with
 // AddressSanitizer and UndefinedBehaviorSanitizer
 // (tests/test_host_sanitize.py).  Every call must return its documented code.
 #include <math.h>
+#include <stdint.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -175,6 +177,79 @@ static void three_d() {
       }
 }
 
+static dugks3_ctx* make3(int q, int storage, int nx, int bcx) {
+  std::vector<double> xf = faces(nx, 1.2), yf = faces(9, 0), zf = faces(7, 1.5);
+  dugks3_params p;
+  memset(&p, 0, sizeof(p));
+  p.abi_version = DUGKS3_ABI_VERSION;
+  p.storage = storage;
+  p.bc[0] = bcx; p.bc[1] = DUGKS_BC_PERIODIC; p.bc[2] = DUGKS_BC_MIRROR;
+  p.c = 1.1; p.cfl = 0.5; p.alpha = 1e-3;
+  dugks3_ctx* h = nullptr;
+  EXPECT(dugks3_create(&h, nx, 9, 7, xf.data(), yf.data(), zf.data(), q, &p), DUGKS_OK);
+  return h;
+}
+
+// 3-D sources (scratch only for D3Q7), autotune and batch arguments
+static void three_d_sources_and_batches() {
+  const int pw[2] = {1, 0};
+  const double gm[2] = {0.2, -0.4};
+  void* g = (void*)(uintptr_t)256;
+  for (int q : {19, 15, 7}) {
+    dugks3_ctx* h = make3(q, DUGKS_F64, 40, DUGKS_BC_PERIODIC);
+    const size_t nb = dugks3_source_scratch_bytes(h);
+    if (q == 7) {
+      EXPECT(nb > 0, 1);
+      EXPECT(dugks3_set_source_terms(h, 2, (const double*)g, pw, gm, nullptr, nb), DUGKS_E_ARG);
+      EXPECT(dugks3_set_source_terms(h, 2, (const double*)g, pw, gm, (void*)(uintptr_t)4096, nb - 1),
+             DUGKS_E_NOMEM);
+      EXPECT(dugks3_set_source_terms(h, 2, (const double*)g, pw, gm, (void*)(uintptr_t)4096, nb), DUGKS_OK);
+    } else {
+      EXPECT((int)nb, 0);
+      EXPECT(dugks3_set_source_terms(h, 2, (const double*)g, pw, gm, nullptr, 0), DUGKS_OK);
+    }
+    EXPECT(dugks3_autotune(h, 2), DUGKS_E_STATE);
+    EXPECT(dugks3_set_source_terms(h, 0, nullptr, nullptr, nullptr, nullptr, 0), DUGKS_OK);
+    dugks3_destroy(h);
+  }
+  for (int storage : {DUGKS_F64, DUGKS_F32}) {
+    dugks3_ctx* hs[3] = {make3(19, storage, 40, DUGKS_BC_PERIODIC), make3(19, storage, 130, DUGKS_BC_MIRROR),
+                         make3(19, storage, 9, DUGKS_BC_DIRICHLET)};
+    dugks3_ctx* h15 = make3(15, storage, 40, DUGKS_BC_PERIODIC);
+    dugks3_ctx* h7 = make3(7, storage, 40, DUGKS_BC_PERIODIC);
+    dugks3_batch* b = nullptr;
+    EXPECT(dugks3_batch_create(&b, 0, hs), DUGKS_E_ARG);
+    dugks3_batch_destroy(b);
+    dugks3_ctx* mixed[2] = {hs[0], h15};
+    EXPECT(dugks3_batch_create(&b, 2, mixed), DUGKS_E_ARG);
+    dugks3_batch_destroy(b);
+    EXPECT(dugks3_batch_create(&b, 1, &h7), DUGKS_E_UNSUPPORTED);
+    dugks3_batch_destroy(b);
+    EXPECT(dugks3_batch_create(&b, 3, hs), DUGKS_OK);
+    const size_t nb = dugks3_batch_workspace_bytes(b);
+    EXPECT(nb >= 3 * sizeof(void*) + 4 * sizeof(long long), 1);
+    EXPECT(dugks3_batch_step(b, 1), DUGKS_E_STATE);
+    EXPECT(dugks3_batch_bind(b, (void*)(uintptr_t)4096, nb, nullptr), DUGKS_E_STATE);
+    EXPECT(dugks3_batch_bind(b, nullptr, nb, nullptr), DUGKS_E_ARG);
+    EXPECT(dugks3_batch_set_launch(b, storage == DUGKS_F64 ? 3 : 5, 8), DUGKS_E_ARG);
+    EXPECT(dugks3_batch_set_launch(b, 2, 0), DUGKS_E_ARG);
+    EXPECT(dugks3_batch_set_launch(b, 2, 5), DUGKS_OK);
+    int rows = 0, planes = 0;
+    long long blocks = 0, cells = 0;
+    EXPECT(dugks3_batch_get_info(b, &rows, &planes, &blocks, &cells), DUGKS_OK);
+    EXPECT(rows == 2 && planes == 5 && cells == (40LL + 130 + 9) * 9 * 7, 1);
+    float ms = 0;
+    EXPECT(dugks3_batch_time_steps(b, 1, &ms), DUGKS_E_STATE);
+    EXPECT(dugks3_batch_last_error(b)[0] != 0, 1);
+    dugks3_batch_destroy(b);
+    for (dugks3_ctx* h : hs) dugks3_destroy(h);
+    dugks3_destroy(h15);
+    dugks3_destroy(h7);
+  }
+  EXPECT(dugks3_batch_step(nullptr, 1), DUGKS_E_ARG);
+  dugks3_batch_destroy(nullptr);
+}
+
 static void one_d() {
   for (int storage : {DUGKS_F64, DUGKS_F32}) {
     std::vector<double> xf = faces(50, 1.3);
@@ -200,6 +275,7 @@ int main() {
   two_d();
   batch();
   three_d();
+  three_d_sources_and_batches();
   one_d();
   if (fails == 0) printf("sanitized host runs: ok\n");
   return fails != 0;
