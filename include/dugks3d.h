@@ -21,8 +21,7 @@
  * fbar+_g = E(phi_g) + fbar+_a - E(phi_a), a the nearest interior cell);
  * D3Q7 uses weights 0 and 1/6 and the linear equilibrium of Remark 3
  * (D = phi I only).  Sources F(x, t, phi) as in two dimensions
- * (dugks3_set_source_terms) run in the fused step (D3Q15, D3Q19) or in a
- * three-pass step with a caller-provided scratch array (D3Q7).
+ * (dugks3_set_source_terms) run in the fused step.
  */
 #ifndef DUGKS3D_H
 #define DUGKS3D_H
@@ -92,12 +91,8 @@ int dugks3_set_phi(dugks3_ctx* ctx, const double* phi, int on_device);
 /* f~ [q][nz][ny][nx] (binary64) as the state; resets the step count. */
 int dugks3_set_f(dugks3_ctx* ctx, const double* f, int on_device);
 
-/* Bytes of the scratch array the source path needs: 0 for D3Q15 and D3Q19,
- * whose sources run in the fused step; for D3Q7, in values of the storage
- * type, g of every cell and of the ghost shell (7 (nx+2)(ny+2)(nz+2)), then
- * the fluxes of every face for the 2 directions that cross it per axis
- * ((nx+1) ny nz faces normal to x, nx (ny+1) nz to y, nx ny (nz+1) to z),
- * each part rounded up to 256 bytes. */
+/* Bytes of scratch the source path needs: 0 (every lattice takes the source
+ * in the fused step; kept for callers that size a scratch array). */
 size_t dugks3_source_scratch_bytes(const dugks3_ctx* ctx);
 
 /* Source F(x, t, phi) = sum_{j < nterms} exp(gammas[j] t) phi^powers[j] G_j(x)
@@ -111,12 +106,9 @@ size_t dugks3_source_scratch_bytes(const dugks3_ctx* ctx);
  * takes the G_j of the cell it copies), by Newton's method when F depends on
  * phi (binary64: update <= 1e-15 (1 + |phi|), at most 8; binary32: 2.4e-7,
  * at most 6).  Set before dugks3_set_phi (f~ = E(phi) - dt S / 2 at t = 0).
- * D3Q15 and D3Q19 take the source in the fused step (scratch_dev unused, may
- * be NULL); D3Q7 runs three passes through scratch_dev (device, caller-owned,
- * 256-byte aligned, >= dugks3_source_scratch_bytes).  Errors: E_ARG (nterms,
- * a power out of range, a rate not finite, NULL arrays, for D3Q7 a NULL
- * scratch or a mesh whose g array, the first part of the scratch, would reach
- * 4 GiB), E_NOMEM (D3Q7: scratch too small). */
+ * The step takes the source in the fused kernel; scratch_dev and
+ * scratch_bytes are not used (may be NULL and 0).  Errors: E_ARG (nterms, a
+ * power out of range, a rate not finite, NULL arrays). */
 int dugks3_set_source_terms(dugks3_ctx* ctx, int nterms, const double* g_dev, const int* powers,
                             const double* gammas, void* scratch_dev, size_t scratch_bytes);
 
@@ -163,11 +155,12 @@ int dugks3_reduce(dugks3_ctx* ctx, const double* ref_dev, double* mass, double* 
  * gives each row one wave (binary32: 5 x (rows + 2) x q x 64 x 4
  * bytes of LDS; binary64: one more wave per halo row, 3 x (rows + 2) x q x
  * 64 x 8 bytes).  A launch needing more LDS than the device allows per block
- * is refused.  With a source the D3Q15 and D3Q19 step takes the
- * instantiation with mirror code for every mesh (the LDS of a walled mesh).
- * Defaults: 2 rows (binary64), 4 rows (binary32; D3Q15 with walls, and any
- * binary32 D3Q15 / D3Q19 step with a source unless a launch was set or
- * autotuned: 2); planes: D3Q15 and D3Q19 the power of two in 4..128 that
+ * is refused.  With a source the step takes the split-direction kernel's
+ * instantiation with mirror code for every mesh and lattice (D3Q7 then with
+ * two waves a row).  Defaults: 2 rows (binary64), 4
+ * rows (binary32; D3Q15 with walls, and any binary32 step with a source
+ * unless a launch was set or autotuned: 2); planes: D3Q15 and D3Q19 the power
+ * of two in 4..128 that
  * minimises (rounds of blocks over 256 CUs) x (planes + 3), D3Q7 32 halved
  * down to 4 while the grid would have fewer than 512 blocks.  Every launch
  * gives bitwise the same result.
@@ -183,8 +176,7 @@ int dugks3_time_steps(dugks3_ctx* ctx, int nsteps, float* ms_total);
  * steps read the current state and the current step's Dirichlet data and
  * write only the inactive buffer: the state and the step count are
  * unchanged, and since every launch gives bitwise the same result, so is
- * every later step.  For D3Q7 with sources (a three-pass step without
- * launch shapes) the call changes nothing.  Synchronises.  Errors: E_STATE (not bound, no
+ * every later step.  Synchronises.  Errors: E_STATE (not bound, no
  * state, Dirichlet data not covering the current step), E_HIP. */
 int dugks3_autotune(dugks3_ctx* ctx, int trial_steps);
 

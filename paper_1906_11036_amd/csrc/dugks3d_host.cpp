@@ -94,22 +94,11 @@ struct dugks3_ctx {
   long long step = 0;
   const double* ring = nullptr;   // Dirichlet data (device, caller-owned)
   long long ring_steps = 0;
-  // sources (device, caller-owned): G_j, and the scratch of the source path
+  // sources (device, caller-owned): the shapes G_j
   const double* src_g = nullptr;
   int src_n = 0;
   int src_pow[DUGKS_MAX_SRC_TERMS] = {0};
   double src_gam[DUGKS_MAX_SRC_TERMS] = {0};
-  void* src_scratch = nullptr;
-  // D3Q15 and D3Q19 take sources in the fused step; D3Q7 in three passes
-  // through a scratch array: g of every cell and ghost, then the three axes'
-  // flux arrays, each from a 256-byte boundary
-  bool src_passes() const { return q == 7; }
-  size_t scratch_g_bytes() const { return align256((size_t)q * (n[0] + 2) * (n[1] + 2) * (n[2] + 2) * elem()); }
-  size_t scratch_flux_bytes(int a) const { return align256(src3_flux_values(q, a, n[0], n[1], n[2]) * elem()); }
-  size_t scratch_bytes() const {
-    if (!src_passes()) return 0;
-    return scratch_g_bytes() + scratch_flux_bytes(0) + scratch_flux_bytes(1) + scratch_flux_bytes(2);
-  }
 
   int fail(int rc, const std::string& m) { err = m; return rc; }
   int hipfail(hipError_t e, const char* what) {
@@ -210,15 +199,6 @@ struct dugks3_ctx {
     d3.lambda = lambda;
     for (int a = 0; a < 3; ++a)
       for (int m = 0; m < 4; ++m) d3.bp[a][m] = p.c * (m + 1) * b[a][m + 1] / cs2;
-    d3.gscr = src_scratch;
-    d3.gscr_bytes = src_scratch ? (unsigned)((size_t)q * (n[0] + 2) * (n[1] + 2) * (n[2] + 2) * elem()) : 0u;
-    {
-      size_t o = scratch_g_bytes();
-      for (int a = 0; a < 3; ++a) {
-        d3.fscr[a] = src_scratch ? (void*)((char*)src_scratch + o) : nullptr;
-        o += scratch_flux_bytes(a);
-      }
-    }
     for (int i = 0; i < q; ++i)
       for (int m = 0; m < kMaxCoef; ++m) {
         d3.e[i][m] = e[i][m];
@@ -256,7 +236,7 @@ struct dugks3_ctx {
     // equilibrium coefficients or with a source
     const bool walls = p.bc[0] != DUGKS_BC_PERIODIC || p.bc[1] != DUGKS_BC_PERIODIC ||
                        p.bc[2] != DUGKS_BC_PERIODIC || ncoef > 4 || src_n > 0;
-    return step3_lds_bytes(p.storage, q, walls, l);
+    return step3_lds_bytes(p.storage, q, walls, l, src_n > 0);
   }
   size_t lds_limit() const {
     int dev = 0, v = 65536;
@@ -480,12 +460,12 @@ int dugks3_set_f(dugks3_ctx* ctx, const double* f, int on_device) {
   return DUGKS_OK;
 }
 
-size_t dugks3_source_scratch_bytes(const dugks3_ctx* ctx) {
-  return (ctx && ctx->magic == kMagic3) ? ctx->scratch_bytes() : 0;
+size_t dugks3_source_scratch_bytes(const dugks3_ctx*) {
+  return 0;   // every lattice takes the source in the fused step
 }
 
 int dugks3_set_source_terms(dugks3_ctx* ctx, int nterms, const double* g_dev, const int* powers,
-                            const double* gammas, void* scratch_dev, size_t scratch_bytes) {
+                            const double* gammas, void* /*scratch_dev*/, size_t /*scratch_bytes*/) {
   GUARD3(ctx);
   if (nterms < 0 || nterms > DUGKS_MAX_SRC_TERMS) return ctx->fail(DUGKS_E_ARG, "nterms out of range");
   if (nterms > 0) {
@@ -494,21 +474,13 @@ int dugks3_set_source_terms(dugks3_ctx* ctx, int nterms, const double* g_dev, co
       if (powers[t] < 0 || powers[t] > DUGKS_MAX_SRC_POW) return ctx->fail(DUGKS_E_ARG, "power out of range");
       if (!std::isfinite(gammas[t])) return ctx->fail(DUGKS_E_ARG, "growth rate not finite");
     }
-    if (ctx->src_passes()) {
-      if (ctx->scratch_g_bytes() >= 4294967296ull)
-        return ctx->fail(DUGKS_E_ARG, "mesh too large for the source path (g of all cells reaches 4 GiB)");
-      if (!scratch_dev || ((uintptr_t)scratch_dev & 255) != 0)
-        return ctx->fail(DUGKS_E_ARG, "scratch must be a 256-byte aligned device buffer");
-      if (scratch_bytes < ctx->scratch_bytes()) return ctx->fail(DUGKS_E_NOMEM, "scratch too small");
-    }
   }
   ctx->src_n = nterms;
-  // binary32 D3Q15 / D3Q19 with a source run fastest at 2 rows a block (the
-  // fused kernel's registers); a launch the caller chose is kept
-  if (!ctx->launch_chosen && ctx->p.storage == DUGKS_F32 && !ctx->src_passes())
+  // binary32 with a source runs fastest at 2 rows a block (the fused
+  // kernel's registers); a launch the caller chose is kept
+  if (!ctx->launch_chosen && ctx->p.storage == DUGKS_F32)
     ctx->launch.rows = nterms > 0 ? 2 : ctx->default_rows;
   ctx->src_g = nterms > 0 ? g_dev : nullptr;
-  ctx->src_scratch = nterms > 0 && ctx->src_passes() ? scratch_dev : nullptr;
   for (int t = 0; t < DUGKS_MAX_SRC_TERMS; ++t) {
     ctx->src_pow[t] = t < nterms ? powers[t] : 0;
     ctx->src_gam[t] = t < nterms ? gammas[t] : 0.0;
@@ -534,9 +506,7 @@ int dugks3_step(dugks3_ctx* ctx, int nsteps) {
   if (ctx->any_dirichlet() && (ctx->ring == nullptr || ctx->step + nsteps > ctx->ring_steps))
     return ctx->fail(DUGKS_E_STATE, "Dirichlet walls need data for every step (dugks3_set_dirichlet)");
   for (int s = 0; s < nsteps; ++s) {
-    const int rc = ctx->src_n > 0 && ctx->src_passes()
-                       ? launch_src3_step(ctx->dev(), ctx->host, (int)(ctx->step & 1), ctx->step, ctx->stream)
-                       : launch_step3(ctx->dev(), ctx->host, (int)(ctx->step & 1), ctx->step, ctx->launch, ctx->stream);
+    const int rc = launch_step3(ctx->dev(), ctx->host, (int)(ctx->step & 1), ctx->step, ctx->launch, ctx->stream);
     if (rc)
       return ctx->fail(DUGKS_E_HIP, std::string("step launch failed: ") + hipGetErrorString(hipGetLastError()));
     ctx->step += 1;
@@ -613,7 +583,6 @@ int dugks3_autotune(dugks3_ctx* ctx, int trial_steps) {
   if (!ctx->initialised) return ctx->fail(DUGKS_E_STATE, "state not initialised");
   if (ctx->any_dirichlet() && (ctx->ring == nullptr || ctx->step + 1 > ctx->ring_steps))
     return ctx->fail(DUGKS_E_STATE, "Dirichlet data does not cover the current step");
-  if (ctx->src_n > 0 && ctx->src_passes()) return DUGKS_OK;   // D3Q7's source passes have no launch shape
   if (trial_steps < 1) trial_steps = 1;
   hipEvent_t a, b;
   if (hipEventCreate(&a) != hipSuccess) return ctx->fail(DUGKS_E_HIP, "event create");

@@ -59,9 +59,6 @@ struct alignas(64) Inst3 {
   double src_gam[DUGKS_MAX_SRC_TERMS];
   double dt, lambda;
   double bp[3][4];         // c B'_a(phi) / c_s^2 as polynomials in phi (B' has degree <= 3)
-  void* gscr;              // source path: g of every cell and ghost, [q][nz+2][ny+2][nx+2]
-  unsigned gscr_bytes;     // its size (< 4 GiB)
-  void* fscr[3];           // source path: fluxes of the faces normal to x, y, z, [slot][face]
 };
 
 // A batch of instances stepped by one launch: instance k takes blocks
@@ -100,12 +97,6 @@ inline long long shell_len(int nx, int ny, int nz) {
 long long step3_blocks(const Inst3& h, const Launch3& l);
 // step: the step index since the state was set (selects the Dirichlet data)
 int launch_step3(const Inst3* d, const Inst3& h, int parity, long long step, const Launch3& l, void* stream);
-// the step with sources: g of every cell and ghost into h.gscr, each face's
-// fluxes into h.fscr, then the update
-int launch_src3_step(const Inst3* d, const Inst3& h, int parity, long long step, void* stream);
-// values in the source path's flux array of one axis: the directions that
-// cross a face normal to it times the faces ((nx+1) ny nz for x, ...)
-size_t src3_flux_values(int q, int axis, int nx, int ny, int nz);
 // one step of a batch (D3Q15 / D3Q19, no source): ncoef the largest of the
 // instances, walls whether any has a wall (the instantiation with mirror
 // code then runs them all), blocks the grid (first[n] of the table)
@@ -113,7 +104,8 @@ int launch_step3_batch(const Batch3& bt, const Inst3& h, int parity, bool walls,
                        const Launch3& l, void* stream);
 // LDS bytes of one block of the step kernel (walls: the instantiation with
 // mirror code, for a non-periodic axis or more than four coefficients)
-size_t step3_lds_bytes(int storage, int q, bool walls, const Launch3& l);
+// src: the source instantiation (D3Q7 then runs the staged kernel too)
+size_t step3_lds_bytes(int storage, int q, bool walls, const Launch3& l, bool src = false);
 int launch_init3(const Inst3* d, const Inst3& h, const double* phi, int parity, void* stream);
 int launch_set_f3(const Inst3* d, const Inst3& h, const double* f, int parity, void* stream);
 int launch_get_phi3(const Inst3* d, const Inst3& h, double* out, int parity, long long step, void* stream);

@@ -1768,6 +1768,20 @@ static int step3_q(const Args3& a, const Inst3& h, bool walls, long long blocks,
         default: step3p_rows<Q, 8, float>(a, h, walls, l, grid, S(stream)); break;
       }
     }
+  } else if (h.src_n > 0) {   // D3Q7 with a source: the staged kernel, two parts a row
+    if (h.storage == DUGKS_F64) {
+      switch (nc) {
+        case 2: step3p_launch<Q, 2, double, true, true>(a, l, grid, S(stream)); break;
+        case 4: step3p_launch<Q, 4, double, true, true>(a, l, grid, S(stream)); break;
+        default: step3p_launch<Q, 8, double, true, true>(a, l, grid, S(stream)); break;
+      }
+    } else {
+      switch (nc) {
+        case 2: step3p_launch<Q, 2, float, true, true>(a, l, grid, S(stream)); break;
+        case 4: step3p_launch<Q, 4, float, true, true>(a, l, grid, S(stream)); break;
+        default: step3p_launch<Q, 8, float, true, true>(a, l, grid, S(stream)); break;
+      }
+    }
   } else {   // D3Q7: a whole row per wave
     switch (nc) {
       case 2: step3_row_waves<Q, 2>(d, h, parity, ring, l, strips, tiles, grid, S(stream)); break;
@@ -1793,7 +1807,7 @@ int launch_step3(const Inst3* d, const Inst3& h, int parity, long long step, con
   switch (h.q) {
     case 19: return step3_q<19>(a, h, walls, blocks, l, stream);
     case 15: return step3_q<15>(a, h, walls, blocks, l, stream);
-    default: return h.src_n > 0 ? -1 : step3_q<7>(a, h, walls, blocks, l, stream);   // D3Q7: three passes
+    default: return step3_q<7>(a, h, walls, blocks, l, stream);
   }
 }
 
@@ -1809,8 +1823,8 @@ int launch_step3_batch(const Batch3& bt, const Inst3& h, int parity, bool walls,
   }
 }
 
-size_t step3_lds_bytes(int storage, int q, bool walls, const Launch3& l) {
-  if (q == 7)   // binary64: g of 3 planes (dynamic); binary32: g of 3 planes and f~ of 2
+size_t step3_lds_bytes(int storage, int q, bool walls, const Launch3& l, bool src) {
+  if (q == 7 && !src)   // binary64: g of 3 planes (dynamic); binary32: g of 3 planes and f~ of 2
     return storage == DUGKS_F64 ? step3h_lds_bytes(q, l) : (size_t)5 * (l.rows + 2) * q * kLanes * 4;
   // g of 3 planes and staged f~ of 1 or 2 planes (LdsP), each of rows + 2
   // rows, and the parts' sums of 4 faces per row (static; the binary32 E
@@ -1847,259 +1861,6 @@ size_t step3_lds_bytes(int storage, int q, bool walls, const Launch3& l) {
         break;                                                                                     \
     }                                                                                              \
   } while (0)
-
-// ------------------------------------------------ the step with sources
-// Three passes through the scratch array, one thread per cell or face: g of
-// every cell and ghost (with the source and the ghost rules); each face once,
-// its fluxes into per-axis arrays; each cell's update from them.  Not the fused
-// design of the source-free step: g and the fluxes cross HBM once more.
-
-// E_k(x) with the instance's runtime number of coefficients
-template <typename T> __device__ inline T eq_rt(const Inst3* __restrict__ I, int k, T x) {
-  const T* c = C3<T>::e(I, k);
-  const int nc = I->ncoef;
-  T r = c[nc - 1];
-  for (int m = nc - 2; m >= 0; --m) r = fma(r, x, c[m]);
-  return r;
-}
-
-// g = fbar+ / b1 with the source (eqs. 2.25, 2.27 over b1):
-// g = (a1/b1) f~ + E(phi) + lambda F(phi) rho(phi), phi the root of
-// phi = sum f~ + dt F(phi) / 2 at t_n (binary64); a ghost takes the g of the
-// cell it copies, then the Dirichlet or mirror rule.
-template <int Q, int ST>
-__global__ __launch_bounds__(256) void k_src3_g(const Inst3* __restrict__ I, int parity,
-                                                const double* __restrict__ ring, long long step) {
-  using T = typename S3<ST>::T;
-  const int nx = I->n[0], ny = I->n[1], nz = I->n[2];
-  const int px = nx + 2, py = ny + 2;
-  const long long NP = (long long)px * py * (nz + 2);
-  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= NP) return;
-  const int i = (int)(n % px) - 1;
-  const long long rest = n / px;
-  const int j = (int)(rest % py) - 1, k = (int)(rest / py) - 1;
-  const int si = src_index(i, nx, I->bc[0]), sj = src_index(j, ny, I->bc[1]), sk = src_index(k, nz, I->bc[2]);
-  const long long off = ((long long)sk * ny + sj) * I->pitch + si;
-  const long long cell = ((long long)sk * ny + sj) * nx + si;
-  const T* buf = (const T*)I->buf[parity];
-  T f[Q];
-  double s = 0.0;
-#pragma unroll
-  for (int m = 0; m < Q; ++m) {
-    f[m] = buf[m * I->plane + off];
-    s += (double)f[m];
-  }
-  double a[4];
-  src_coefs3(I, cell, cell, 0.0, (double)step * I->dt, a);
-  const double phi = solve_conserved3<double>(s, 0.5 * I->dt, a, I->src_implicit != 0);
-  const double lf = I->lambda * poly4(a, phi);
-  const T p = (T)phi, ra = C3<T>::ra(I);
-  T g[Q];
-#pragma unroll
-  for (int m = 0; m < Q; ++m) g[m] = fma(ra, f[m], eq_rt<T>(I, m, p) + (T)(lf * rho3<Q>(I, m, phi)));
-  const bool wx = (i < 0 || i >= nx) && I->bc[0] != DUGKS_BC_PERIODIC;
-  const bool wy = (j < 0 || j >= ny) && I->bc[1] != DUGKS_BC_PERIODIC;
-  const bool wz = (k < 0 || k >= nz) && I->bc[2] != DUGKS_BC_PERIODIC;
-  if (wx || wy || wz) {
-    if (dirichlet_ghost(I, wx, wy, k)) {
-      const T pg = (T)ring[shell_index(nx, ny, nz, i, j, k)], ib = C3<T>::inv_b1(I);
-#pragma unroll
-      for (int m = 0; m < Q; ++m) g[m] = fma(eq_rt<T>(I, m, pg) - eq_rt<T>(I, m, p), ib, g[m]);
-    } else {
-      if (wx) mirror<Q, T>(g, 0);
-      if (wy) mirror<Q, T>(g, 1);
-      if (wz) mirror<Q, T>(g, 2);
-    }
-  }
-  T* gs = (T*)I->gscr;
-#pragma unroll
-  for (int m = 0; m < Q; ++m) gs[m * NP + n] = g[m];
-}
-
-// Number of directions with a nonzero velocity component along axis A
-// before direction k (the slot of k among the directions that cross a face
-// normal to A), and their count.
-template <int Q, int A> __host__ __device__ constexpr int cross_slot(int k) {
-  int n = 0;
-  for (int m = 0; m < k; ++m) n += ce<Q>(m, A) != 0;
-  return n;
-}
-template <int Q, int A> __host__ __device__ constexpr int cross_count() { return cross_slot<Q, A>(Q); }
-
-// Index of the face normal to axis A between cells (i,j,k) - e_A and (i,j,k)
-// (the coordinate along A runs over 0..n_A): x fastest, then y, then z.
-template <int A> __device__ __forceinline__ unsigned face_index(int nx, int ny, int i, int j, int k) {
-  if constexpr (A == 0) return ((unsigned)k * ny + j) * (nx + 1) + i;
-  else if constexpr (A == 1) return ((unsigned)k * (ny + 1) + j) * nx + i;
-  else return ((unsigned)k * ny + j) * nx + i;
-}
-
-// One face normal to axis A from the scratch g: reconstruction (eq. 2.20) and
-// characteristic shift (eq. 2.19 as eq. 2.26) on the scaled g, phi_b = b1 sum
-// gbar solved with F at the face at t_n + h (phi_b = sum fbar + h F(phi_b) /
-// 2, each G_j interpolated between the two cells' centres), and
-// F = f_b / b3 = (a3 b1/b3) gbar + E(phi_b) + lambda F(phi_b) rho(phi_b)
-// (eq. 2.27 solved for f) of each direction that crosses the face, into the
-// axis's flux array [slot][face].
-template <int Q, int ST, int A>
-__global__ __launch_bounds__(256) void k_src3_face(const Inst3* __restrict__ I, long long step) {
-  using T = typename S3<ST>::T;
-  constexpr int t1 = A == 0 ? 1 : 0, t2 = A == 2 ? 1 : 2;
-  const int nx = I->n[0], ny = I->n[1], nz = I->n[2];
-  const int fx = nx + (A == 0), fy = ny + (A == 1);
-  const long long nf = (long long)fx * fy * (nz + (A == 2));
-  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= nf) return;
-  int R[3];
-  R[0] = (int)(n % fx);
-  R[1] = (int)((n / fx) % fy);
-  R[2] = (int)(n / ((long long)fx * fy));
-  int L[3] = {R[0], R[1], R[2]};
-  L[A] -= 1;
-  const int px = nx + 2, py = ny + 2;
-  const long long NP = (long long)px * py * (nz + 2);
-  // g through a buffer resource: a 32-bit byte offset per neighbour, the
-  // direction's plane offset in a scalar register
-  const __amdgpu_buffer_rsrc_t Rg = rsrc(I->gscr, I->gscr_bytes);
-  const unsigned pl = (unsigned)NP * (unsigned)sizeof(T);
-  auto at = [&](const int* c, int da, int db) -> unsigned {   // byte offset of c + da e_t1 + db e_t2
-    int x[3] = {c[0], c[1], c[2]};
-    x[t1] += da;
-    x[t2] += db;
-    return (((unsigned)(x[2] + 1) * py + (x[1] + 1)) * px + (x[0] + 1)) * (unsigned)sizeof(T);
-  };
-  auto G = [&](unsigned o, int m) -> T {
-    if constexpr (sizeof(T) == 8)
-      return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(Rg, o, (unsigned)m * pl, 0));
-    else
-      return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(Rg, o, (unsigned)m * pl, 0));
-  };
-  const unsigned oL = at(L, 0, 0), oR = at(R, 0, 0);
-  const unsigned oL1p = at(L, 1, 0), oL1m = at(L, -1, 0), oR1p = at(R, 1, 0), oR1m = at(R, -1, 0);
-  const unsigned oL2p = at(L, 0, 1), oL2m = at(L, 0, -1), oR2p = at(R, 0, 1), oR2m = at(R, 0, -1);
-  const T* ga = C3<T>::geo(I, A);
-  const int m = R[A];
-  const T am = ga[(m + 1) * kGeo + 0], a0 = ga[(m + 1) * kGeo + 1], ap = ga[(m + 1) * kGeo + 2];
-  const T tau1 = C3<T>::geo(I, t1)[(R[t1] + 1) * kGeo + 3];
-  const T tau2 = C3<T>::geo(I, t2)[(R[t2] + 1) * kGeo + 3];
-  T gb[Q];
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int cn = ce<Q>(q, A), c1 = ce<Q>(q, t1), c2 = ce<Q>(q, t2);
-    const T gl = G(oL, q), gr = G(oR, q);
-    const T al = cn > 0 ? ap : (cn < 0 ? am : a0);
-    T v = fma(al, gr - gl, gl);
-    if (c1 != 0) {
-      const T ts = (G(oL1p, q) - G(oL1m, q)) + (G(oR1p, q) - G(oR1m, q));
-      v = fma((T)(-c1) * tau1, ts, v);
-    }
-    if (c2 != 0) {
-      const T ts = (G(oL2p, q) - G(oL2m, q)) + (G(oR2p, q) - G(oR2m, q));
-      v = fma((T)(-c2) * tau2, ts, v);
-    }
-    gb[q] = v;
-  }
-  const T b1 = C3<T>::b1(I), rb = C3<T>::rb(I), lam = (T)I->lambda;
-  const T hh = (T)(0.25 * I->dt);   // h / 2
-  T pb = (T)(dir_sum<Q>(gb) * b1);
-  const long long cL = ((long long)src_index(L[2], nz, I->bc[2]) * ny + src_index(L[1], ny, I->bc[1])) * nx +
-                       src_index(L[0], nx, I->bc[0]);
-  const long long cR = ((long long)src_index(R[2], nz, I->bc[2]) * ny + src_index(R[1], ny, I->bc[1])) * nx +
-                       src_index(R[0], nx, I->bc[0]);
-  double ad[4];
-  src_coefs3(I, cL, cR, (double)a0, ((double)step + 0.5) * I->dt, ad);
-  const T af[4] = {(T)ad[0], (T)ad[1], (T)ad[2], (T)ad[3]};
-  pb = solve_conserved3<T>(pb, hh, af, I->src_implicit != 0);
-  const T lfb = lam * poly4(af, pb);
-  const GPtr<T> fl = as_global((T*)I->fscr[A]);
-#pragma unroll
-  for (int q = 0; q < Q; ++q)
-    if (ce<Q>(q, A) != 0)
-      fl[cross_slot<Q, A>(q) * nf + n] = fma(rb, gb[q], eq_rt<T>(I, q, pb) + lfb * (T)rho3<Q>(I, q, (double)pb));
-}
-
-// The update of one cell: f~(t+dt) = f~+ - dt c.(flux differences) / width
-// (eq. 2.24) with f~+ = (4/3) b1 g - f~ / 3, the fluxes of x, y and z in turn.
-template <int Q, int ST>
-__global__ __launch_bounds__(256) void k_src3_update(const Inst3* __restrict__ I, int parity) {
-  using T = typename S3<ST>::T;
-  const int nx = I->n[0], ny = I->n[1], nz = I->n[2];
-  const long long N = (long long)nx * ny * nz;
-  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
-  const int i = (int)(n % nx), j = (int)((n / nx) % ny), k = (int)(n / ((long long)nx * ny));
-  const int px = nx + 2, py = ny + 2;
-  const long long NP = (long long)px * py * (nz + 2);
-  const long long cp = ((long long)(k + 1) * py + (j + 1)) * px + (i + 1);
-  const long long off = ((long long)k * ny + j) * I->pitch + i;
-  const GPtr<const T> gs = as_global((const T*)I->gscr);
-  const GPtr<const T> buf = as_global((const T*)I->buf[parity]);
-  const T kg = C3<T>::kg(I);
-  T O[Q];
-#pragma unroll
-  for (int m = 0; m < Q; ++m) O[m] = fma(kg, gs[m * NP + cp], (T)(-1.0 / 3.0) * buf[m * I->plane + off]);
-  const long long nf[3] = {(long long)(nx + 1) * ny * nz, (long long)nx * (ny + 1) * nz,
-                           (long long)nx * ny * (nz + 1)};
-  const unsigned f0[3] = {face_index<0>(nx, ny, i, j, k), face_index<1>(nx, ny, i, j, k),
-                          face_index<2>(nx, ny, i, j, k)};
-  const unsigned step_a[3] = {1u, (unsigned)nx, (unsigned)nx * ny};   // the next face along the axis
-  const int idx[3] = {i, j, k};
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const T ka = C3<T>::geo(I, a)[(idx[a] + 1) * kGeo + 4];
-    const GPtr<const T> fl = as_global((const T*)I->fscr[a]);
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int c = ce<Q>(q, a);
-      if (c == 0) continue;
-      const int sl = a == 0 ? cross_slot<Q, 0>(q) : (a == 1 ? cross_slot<Q, 1>(q) : cross_slot<Q, 2>(q));
-      const GPtr<const T> row = fl + sl * nf[a];
-      O[q] = fma((T)(-c) * ka, row[f0[a] + step_a[a]] - row[f0[a]], O[q]);
-    }
-  }
-  const GPtr<T> out = as_global((T*)I->buf[parity ^ 1]);
-#pragma unroll
-  for (int m = 0; m < Q; ++m) out[m * I->plane + off] = O[m];
-}
-
-template <int Q, int ST>
-static int src3_go(const Inst3* d, const Inst3& h, int parity, const double* ring, long long step, hipStream_t st) {
-  const long long nx = h.n[0], ny = h.n[1], nz = h.n[2];
-  const long long NP = (nx + 2) * (ny + 2) * (nz + 2);
-  const long long N = nx * ny * nz;
-  const long long nf[3] = {(nx + 1) * ny * nz, nx * (ny + 1) * nz, nx * ny * (nz + 1)};
-  if ((NP + 255) / 256 > 0x7fffffffLL) return -1;
-  hipLaunchKernelGGL((k_src3_g<Q, ST>), dim3((unsigned)((NP + 255) / 256)), dim3(256), 0, st, d, parity, ring, step);
-  hipLaunchKernelGGL((k_src3_face<Q, ST, 0>), dim3((unsigned)((nf[0] + 255) / 256)), dim3(256), 0, st, d, step);
-  hipLaunchKernelGGL((k_src3_face<Q, ST, 1>), dim3((unsigned)((nf[1] + 255) / 256)), dim3(256), 0, st, d, step);
-  hipLaunchKernelGGL((k_src3_face<Q, ST, 2>), dim3((unsigned)((nf[2] + 255) / 256)), dim3(256), 0, st, d, step);
-  hipLaunchKernelGGL((k_src3_update<Q, ST>), dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, d, parity);
-  return hipGetLastError() == hipSuccess ? 0 : -1;
-}
-
-static_assert(cross_count<19, 0>() == 10 && cross_count<19, 1>() == 10 && cross_count<19, 2>() == 10, "D3Q19");
-static_assert(cross_count<15, 0>() == 10 && cross_count<15, 1>() == 10 && cross_count<15, 2>() == 10, "D3Q15");
-static_assert(cross_count<7, 0>() == 2 && cross_count<7, 1>() == 2 && cross_count<7, 2>() == 2, "D3Q7");
-
-size_t src3_flux_values(int q, int axis, int nx, int ny, int nz) {
-  const int cross = q == 7 ? 2 : 10;   // cross_count of the lattice (the same for every axis)
-  const size_t faces = (size_t)(nx + (axis == 0)) * (ny + (axis == 1)) * (nz + (axis == 2));
-  return cross * faces;
-}
-
-int launch_src3_step(const Inst3* d, const Inst3& h, int parity, long long step, void* stream) {
-  const double* ring = h.ring != nullptr ? h.ring + step * h.ring_len : nullptr;
-  const bool f64 = h.storage == DUGKS_F64;
-  switch (h.q) {
-    case 19: return f64 ? src3_go<19, DUGKS_F64>(d, h, parity, ring, step, S(stream))
-                        : src3_go<19, DUGKS_F32>(d, h, parity, ring, step, S(stream));
-    case 15: return f64 ? src3_go<15, DUGKS_F64>(d, h, parity, ring, step, S(stream))
-                        : src3_go<15, DUGKS_F32>(d, h, parity, ring, step, S(stream));
-    default: return f64 ? src3_go<7, DUGKS_F64>(d, h, parity, ring, step, S(stream))
-                        : src3_go<7, DUGKS_F32>(d, h, parity, ring, step, S(stream));
-  }
-}
 
 int launch_init3(const Inst3* d, const Inst3& h, const double* phi, int parity, void* stream) {
   DUGKS3_PER_CELL(k_init3, d, phi, parity);

@@ -190,24 +190,18 @@ static dugks3_ctx* make3(int q, int storage, int nx, int bcx) {
   return h;
 }
 
-// 3-D sources (scratch only for D3Q7), autotune and batch arguments
+// 3-D source arguments (no scratch), autotune and batch arguments
 static void three_d_sources_and_batches() {
   const int pw[2] = {1, 0};
   const double gm[2] = {0.2, -0.4};
   void* g = (void*)(uintptr_t)256;
   for (int q : {19, 15, 7}) {
     dugks3_ctx* h = make3(q, DUGKS_F64, 40, DUGKS_BC_PERIODIC);
-    const size_t nb = dugks3_source_scratch_bytes(h);
-    if (q == 7) {
-      EXPECT(nb > 0, 1);
-      EXPECT(dugks3_set_source_terms(h, 2, (const double*)g, pw, gm, nullptr, nb), DUGKS_E_ARG);
-      EXPECT(dugks3_set_source_terms(h, 2, (const double*)g, pw, gm, (void*)(uintptr_t)4096, nb - 1),
-             DUGKS_E_NOMEM);
-      EXPECT(dugks3_set_source_terms(h, 2, (const double*)g, pw, gm, (void*)(uintptr_t)4096, nb), DUGKS_OK);
-    } else {
-      EXPECT((int)nb, 0);
-      EXPECT(dugks3_set_source_terms(h, 2, (const double*)g, pw, gm, nullptr, 0), DUGKS_OK);
-    }
+    EXPECT((int)dugks3_source_scratch_bytes(h), 0);
+    const int bad[2] = {1, 4};
+    EXPECT(dugks3_set_source_terms(h, 2, (const double*)g, bad, gm, nullptr, 0), DUGKS_E_ARG);
+    EXPECT(dugks3_set_source_terms(h, 2, nullptr, pw, gm, nullptr, 0), DUGKS_E_ARG);
+    EXPECT(dugks3_set_source_terms(h, 2, (const double*)g, pw, gm, nullptr, 0), DUGKS_OK);
     EXPECT(dugks3_autotune(h, 2), DUGKS_E_STATE);
     EXPECT(dugks3_set_source_terms(h, 0, nullptr, nullptr, nullptr, nullptr, 0), DUGKS_OK);
     dugks3_destroy(h);

@@ -1,6 +1,5 @@
 """Three-dimensional sources F(x, t, phi) = sum_j exp(gamma_j t) phi^k_j G_j(x)
-on the GPU (the fused source step of D3Q15 and D3Q19, the three-pass step of
-D3Q7; through the C ABI of include/dugks3d.h)
+on the GPU (the fused source step, through the C ABI of include/dugks3d.h)
 against the 3-D CPU oracle: binary64 to 1e-12 (max-norm relative to max |f~|)
 on all three lattices and every wall kind; binary32 within 2 n eps32 (relative
 L2 of phi); a uniform field follows the implicit trapezoidal rule; with all
