@@ -965,17 +965,28 @@ __device__ __forceinline__ void face_out(const Inst3* __restrict__ I, const EQ& 
 // The same with a source (eqs. 2.27 and 2.22 with F_b): phi_b solves phi_b =
 // b1 sum gbar + h F(phi_b) / 2 with the face's coefficients sa, and F gains
 // lambda F(phi_b) rho(phi_b)
-template <int Q, int P, int H, int A, typename T, typename EQ>
-__device__ __forceinline__ void face_out_src(const Inst3* __restrict__ I, const EQ& E, const T* gb, T s, const T* sa,
-                                             T* out) {
-  T pb = (T)(s * C3<T>::b1(I));
+// (phi_b and lambda F(phi_b) from the face's sum s, then F of part H from them)
+template <typename T>
+__device__ __forceinline__ void face_phi_src(const Inst3* __restrict__ I, T s, const T* sa, T& pb, T& lfb) {
+  pb = (T)(s * C3<T>::b1(I));
   pb = solve_conserved3<T>(pb, (T)(0.25 * I->dt), sa, I->src_implicit != 0);
-  const T lfb = (T)I->lambda * poly4(sa, pb);
+  lfb = (T)I->lambda * poly4(sa, pb);
+}
+template <int Q, int P, int H, int A, typename T, typename EQ>
+__device__ __forceinline__ void face_out_phi(const Inst3* __restrict__ I, const EQ& E, const T* gb, T pb, T lfb,
+                                             T* out) {
   const T rb = C3<T>::rb(I);
 #pragma unroll
   for (int k = 0; k < Q; ++k)
     if (part_of<Q, P>(k) == H && ce<Q>(k, A) != 0)
       out[k] = fma(rb, gb[k], E(k, pb) + lfb * (T)rho3<Q>(I, k, (double)pb));
+}
+template <int Q, int P, int H, int A, typename T, typename EQ>
+__device__ __forceinline__ void face_out_src(const Inst3* __restrict__ I, const EQ& E, const T* gb, T s, const T* sa,
+                                             T* out) {
+  T pb, lfb;
+  face_phi_src<T>(I, s, sa, pb, lfb);
+  face_out_phi<Q, P, H, A>(I, E, gb, pb, lfb, out);
 }
 
 // LDS bytes of a block with ns staging slots (E coefficients aside)
@@ -1399,28 +1410,61 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
     // both halves' sums and the whole staged plane z+2 are in LDS; slot sm
     // (read only above) is free for the next plane's g
     lds_barrier();
+    if constexpr (SRC) {
+      // Each part solves phi_b of 4 / P of the four faces (west, north,
+      // south, top) and writes it with lambda F(phi_b) over the face's sums,
+      // which only that part reads; after a barrier every part reads all
+      // four.  The coefficients of the neighbouring rows at plane z are
+      // loaded, the west cell's taken from lane - 1.
+      if (inner) {
+        constexpr int FP = 4 / P;
+        auto put_phi = [&](int face, T pb, T lf) __attribute__((always_inline)) {
+          L.psum[face][rw][0][lane] = pb;
+          L.psum[face][rw][1][lane] = lf;
+        };
+        const long long cz = (long long)src_index(z, nz, bcz) * ny;
+        T sa[4], pb, lf;
+        if constexpr (0 / FP == H) {
+          double AFW[4];
+#pragma unroll
+          for (int m = 0; m < 4; ++m) AFW[m] = shr1(AF0[m]);
+          src_face_coefs3<T>(AFW, AF0, ca0, sa);
+          face_phi_src<T>(I, total(0, sW), sa, pb, lf);
+          put_phi(0, pb, lf);
+        }
+        if constexpr (1 / FP == H) {
+          double AFN[4], an[4];
+          src_cell_coefs3(I, tb, (cz + src_index(r + 1, ny, bcy)) * nx + scol, an, AFN);
+          src_face_coefs3<T>(AF0, AFN, yN1, sa);
+          face_phi_src<T>(I, total(1, sN), sa, pb, lf);
+          put_phi(1, pb, lf);
+        }
+        if constexpr (2 / FP == H) {
+          double AFS[4], an[4];
+          src_cell_coefs3(I, tb, (cz + src_index(r - 1, ny, bcy)) * nx + scol, an, AFS);
+          src_face_coefs3<T>(AFS, AF0, yS1, sa);
+          face_phi_src<T>(I, total(2, sS), sa, pb, lf);
+          put_phi(2, pb, lf);
+        }
+        if constexpr (3 / FP == H) {
+          src_face_coefs3<T>(AF0, AF1, (T)zg[(z + 2) * kGeo + 1], sa);
+          face_phi_src<T>(I, total(3, sT), sa, pb, lf);
+          put_phi(3, pb, lf);
+        }
+      }
+      lds_barrier();
+    }
     if (inner) {
       const int zi = z + 1;
       const T kz = zg[zi * kGeo + 4];
       T fW[Q], fN[Q], fS[Q];
       if constexpr (SRC) {
-        // the neighbouring rows' coefficients at plane z, the west cell's
-        // from lane - 1
-        const long long cz = (long long)src_index(z, nz, bcz) * ny;
-        double AFN[4], AFS[4], AFW[4], an[4];
-        src_cell_coefs3(I, tb, (cz + src_index(r + 1, ny, bcy)) * nx + scol, an, AFN);
-        src_cell_coefs3(I, tb, (cz + src_index(r - 1, ny, bcy)) * nx + scol, an, AFS);
-#pragma unroll
-        for (int m = 0; m < 4; ++m) AFW[m] = shr1(AF0[m]);
-        T sa[4];
-        src_face_coefs3<T>(AFW, AF0, ca0, sa);
-        face_out_src<Q, P, H, 0>(I, ev, gbW, total(0, sW), sa, fW);
-        src_face_coefs3<T>(AF0, AFN, yN1, sa);
-        face_out_src<Q, P, H, 1>(I, ev, gbN, total(1, sN), sa, fN);
-        src_face_coefs3<T>(AFS, AF0, yS1, sa);
-        face_out_src<Q, P, H, 1>(I, ev, gbS, total(2, sS), sa, fS);
-        src_face_coefs3<T>(AF0, AF1, (T)zg[(z + 2) * kGeo + 1], sa);
-        face_out_src<Q, P, H, 2>(I, ev, gbT, total(3, sT), sa, FZt);
+        auto pbv = [&](int face) __attribute__((always_inline)) { return L.psum[face][rw][0][lane]; };
+        auto lfv = [&](int face) __attribute__((always_inline)) { return L.psum[face][rw][1][lane]; };
+        face_out_phi<Q, P, H, 0>(I, ev, gbW, pbv(0), lfv(0), fW);
+        face_out_phi<Q, P, H, 1>(I, ev, gbN, pbv(1), lfv(1), fN);
+        face_out_phi<Q, P, H, 1>(I, ev, gbS, pbv(2), lfv(2), fS);
+        face_out_phi<Q, P, H, 2>(I, ev, gbT, pbv(3), lfv(3), FZt);
       } else {
         face_out<Q, P, H, 0>(I, ev, gbW, total(0, sW), fW);
         face_out<Q, P, H, 1>(I, ev, gbN, total(1, sN), fN);
@@ -1449,8 +1493,9 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
         o += planeB;
       }
     }
-    // no third barrier: the next plane's first barrier separates these reads
-    // of the sums from its writes of them
+    // no further barrier: the next plane's first barrier separates these
+    // reads of the sums (with a source, of the faces' phi_b) from its writes
+    // of them
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
       if (part_of<Q, P>(k) != H) continue;
