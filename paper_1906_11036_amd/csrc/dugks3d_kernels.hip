@@ -303,18 +303,21 @@ __device__ __forceinline__ void src_cell_coefs3(const Inst3* __restrict__ I, STa
   const int n = I->src_n;
 #pragma unroll
   for (int m = 0; m < 4; ++m) an[m] = af[m] = 0.0;
+  // branch-free in the power: a term adds its G_j times the time factor to
+  // the coefficient of its power and zero times G_j to the others (the same
+  // sums; branches on the power made the compiler copy the arrays)
 #pragma unroll
   for (int j = 0; j < DUGKS_MAX_SRC_TERMS; ++j) {
-    if (j >= n) break;
-    const double gj = G[j * I->src_plane + cell];
-    const int pw = I->src_pow[j];
-    const double en = tb->en[j], ef = tb->ef[j];
+    if (j < n) {
+      const double gj = G[j * I->src_plane + cell];
+      const int pw = I->src_pow[j];
+      const double en = tb->en[j], ef = tb->ef[j];
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
-      if (pw == m) {
-        an[m] += en * gj;
-        af[m] += ef * gj;
+      for (int m = 0; m < 4; ++m) {
+        an[m] = fma(pw == m ? en : 0.0, gj, an[m]);
+        af[m] = fma(pw == m ? ef : 0.0, gj, af[m]);
       }
+    }
   }
 }
 
