@@ -157,9 +157,8 @@ int dugks3_reduce(dugks3_ctx* ctx, const double* ref_dev, double* mass, double* 
  * 64 x 8 bytes).  A launch needing more LDS than the device allows per block
  * is refused.  With a source the step takes the split-direction kernel's
  * instantiation with mirror code for every mesh and lattice (D3Q7 then with
- * two waves a row).  Defaults: 2 rows (binary64), 4
- * rows (binary32; D3Q15 with walls, and any binary32 step with a source
- * unless a launch was set or autotuned: 2); planes: D3Q15 and D3Q19 the power
+ * two waves a row).  Defaults, with a source or without: 2 rows (binary64),
+ * 4 rows (binary32; D3Q15 with walls: 2); planes: D3Q15 and D3Q19 the power
  * of two in 4..128 that
  * minimises (rounds of blocks over 256 CUs) x (planes + 3), D3Q7 32 halved
  * down to 4 while the grid would have fewer than 512 blocks.  Every launch

@@ -80,8 +80,6 @@ struct dugks3_ctx {
   double e[kMaxQ][kMaxCoef] = {{0}};
   std::vector<double> geo[3], widths;
   Launch3 launch;
-  int default_rows = 4;          // rows of the default launch without a source
-  bool launch_chosen = false;    // set by dugks3_set_launch or dugks3_autotune
   // device
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -352,7 +350,6 @@ int dugks3_create(dugks3_ctx** out, int nx, int ny, int nz, const double* xf, co
   // walls: two, which lets two blocks share a CU) -- the fastest at 256^3
   const bool walls = p->bc[0] != DUGKS_BC_PERIODIC || p->bc[1] != DUGKS_BC_PERIODIC || p->bc[2] != DUGKS_BC_PERIODIC;
   x->launch.rows = p->storage == DUGKS_F64 ? 2 : ((q == 15 && walls) ? 2 : 4);
-  x->default_rows = x->launch.rows;
   // Planes a chunk.  D3Q15 and D3Q19: the blocks run in rounds of (CUs x
   // blocks a CU, from the LDS: 160 KiB a CU) and a block takes about
   // (planes + 3) plane times (its prologue stages and makes two planes), so
@@ -476,10 +473,6 @@ int dugks3_set_source_terms(dugks3_ctx* ctx, int nterms, const double* g_dev, co
     }
   }
   ctx->src_n = nterms;
-  // binary32 with a source runs fastest at 2 rows a block (the fused
-  // kernel's registers); a launch the caller chose is kept
-  if (!ctx->launch_chosen && ctx->p.storage == DUGKS_F32)
-    ctx->launch.rows = nterms > 0 ? 2 : ctx->default_rows;
   ctx->src_g = nterms > 0 ? g_dev : nullptr;
   for (int t = 0; t < DUGKS_MAX_SRC_TERMS; ++t) {
     ctx->src_pow[t] = t < nterms ? powers[t] : 0;
@@ -556,7 +549,6 @@ int dugks3_set_launch(dugks3_ctx* ctx, int rows, int planes) {
   if (ctx->bound() && ctx->lds_bytes(l) > ctx->lds_limit())
     return ctx->fail(DUGKS_E_ARG, "launch needs more LDS than a block may hold");
   ctx->launch = l;
-  ctx->launch_chosen = true;
   return DUGKS_OK;
 }
 
@@ -626,7 +618,6 @@ int dugks3_autotune(dugks3_ctx* ctx, int trial_steps) {
   if (rc != DUGKS_OK) return ctx->fail(rc, "autotune launch failed");
   if (er != hipSuccess) return ctx->hipfail(er, "autotune timing");
   ctx->launch = best;
-  ctx->launch_chosen = true;
   return DUGKS_OK;
 }
 
