@@ -406,8 +406,8 @@ def _default_launch3(nx, ny, nz, q, f32, walls):
 def test_3d_default_launch_follows_the_documented_model(q, storage, bc):
     """Host logic only (no device work): the default rows, chunk length and
     block count of dugks3_create against the rule the header documents, on
-    cubes and ragged boxes; at 256^3 the measured best (64 planes binary32,
-    128 binary64 for D3Q19)."""
+    cubes and ragged boxes, unchanged by source terms; at 256^3 the measured
+    best (64 planes binary32, 128 binary64 for D3Q19)."""
     lib = L.lib()
     f32 = storage == "f32"
     walls = any(b != 0 for b in bc)
@@ -418,6 +418,11 @@ def test_3d_default_launch_follows_the_documented_model(q, storage, bc):
         info = L.Info3()
         assert lib.dugks3_get_info(h, C.byref(info)) == L.OK
         got = (info.rows_per_block, info.planes_per_block, info.blocks)
+        # a source keeps the default launch (unbound: the terms are only recorded)
+        pw, gm = (C.c_int * 2)(0, 1), (C.c_double * 2)(0.0, 0.3)
+        assert lib.dugks3_set_source_terms(h, 2, C.c_void_p(256), pw, gm, None, 0) == L.OK
+        assert lib.dugks3_get_info(h, C.byref(info)) == L.OK
+        assert (info.rows_per_block, info.planes_per_block, info.blocks) == got, (nx, ny, nz)
         lib.dugks3_destroy(h)
         assert got == _default_launch3(nx, ny, nz, q, f32, walls), (nx, ny, nz)
         if (nx, ny, nz) == (256, 256, 256) and q == 19:
