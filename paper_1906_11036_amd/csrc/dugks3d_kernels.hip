@@ -297,9 +297,16 @@ struct SrcTab {
 using STab = const SrcTab*;
 // The source's coefficients as polynomials in phi at cell `cell` (index of
 // [nz][ny][nx]): an at t_n (the cell's own phi), af at t_n + h (its faces)
-__device__ __forceinline__ void src_cell_coefs3(const Inst3* __restrict__ I, STab tb, long long cell,
-                                                double* an, double* af) {
+// (the loads of the cell's G_j, then the sums from them)
+__device__ __forceinline__ void src_load3(const Inst3* __restrict__ I, long long cell, double* g) {
   const GPtr<const double> G = as_global(I->src_g);
+  const int n = I->src_n;
+#pragma unroll
+  for (int j = 0; j < DUGKS_MAX_SRC_TERMS; ++j)
+    if (j < n) g[j] = G[j * I->src_plane + cell];
+}
+__device__ __forceinline__ void src_coefs_from3(const Inst3* __restrict__ I, STab tb, const double* g,
+                                                double* an, double* af) {
   const int n = I->src_n;
 #pragma unroll
   for (int m = 0; m < 4; ++m) an[m] = af[m] = 0.0;
@@ -309,7 +316,7 @@ __device__ __forceinline__ void src_cell_coefs3(const Inst3* __restrict__ I, STa
 #pragma unroll
   for (int j = 0; j < DUGKS_MAX_SRC_TERMS; ++j) {
     if (j < n) {
-      const double gj = G[j * I->src_plane + cell];
+      const double gj = g[j];
       const int pw = I->src_pow[j];
       const double en = tb->en[j], ef = tb->ef[j];
 #pragma unroll
@@ -319,6 +326,12 @@ __device__ __forceinline__ void src_cell_coefs3(const Inst3* __restrict__ I, STa
       }
     }
   }
+}
+__device__ __forceinline__ void src_cell_coefs3(const Inst3* __restrict__ I, STab tb, long long cell,
+                                                double* an, double* af) {
+  double g[DUGKS_MAX_SRC_TERMS];
+  src_load3(I, cell, g);
+  src_coefs_from3(I, tb, g, an, af);
 }
 
 // A face's coefficients in the storage type: each G_j interpolated linearly
@@ -1348,6 +1361,16 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
       if (z + 2 <= z1) stage(0, z + 2);
     }
     T gbW[Q], gbN[Q], gbS[Q], gbT[Q], sW = 0, sN = 0, sS = 0, sT = 0;
+    // binary64 with a source, four parts: the parts that solve the north and
+    // south faces load the G_j of that neighbouring row here, so that the
+    // face work below hides the loads' latency (used after the next barrier)
+    constexpr bool kPreG = SRC && sizeof(T) == 8 && P == 4;
+    double gpre[DUGKS_MAX_SRC_TERMS];
+    if constexpr (kPreG && (H == 1 || H == 2)) {
+      if (inner)
+        src_load3(I, ((long long)src_index(z, nz, bcz) * ny + src_index(H == 1 ? r + 1 : r - 1, ny, bcy)) * nx + scol,
+                  gpre);
+    }
     if (inner) {
       T sx0[Q], dY[Q], dZ[Q], t1[Q], t2[Q];
       const int zi = z + 1;
@@ -1437,14 +1460,16 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
         }
         if constexpr (1 / FP == H) {
           double AFN[4], an[4];
-          src_cell_coefs3(I, tb, (cz + src_index(r + 1, ny, bcy)) * nx + scol, an, AFN);
+          if constexpr (kPreG) src_coefs_from3(I, tb, gpre, an, AFN);
+          else src_cell_coefs3(I, tb, (cz + src_index(r + 1, ny, bcy)) * nx + scol, an, AFN);
           src_face_coefs3<T>(AF0, AFN, yN1, sa);
           face_phi_src<T>(I, total(1, sN), sa, pb, lf);
           put_phi(1, pb, lf);
         }
         if constexpr (2 / FP == H) {
           double AFS[4], an[4];
-          src_cell_coefs3(I, tb, (cz + src_index(r - 1, ny, bcy)) * nx + scol, an, AFS);
+          if constexpr (kPreG) src_coefs_from3(I, tb, gpre, an, AFS);
+          else src_cell_coefs3(I, tb, (cz + src_index(r - 1, ny, bcy)) * nx + scol, an, AFS);
           src_face_coefs3<T>(AFS, AF0, yS1, sa);
           face_phi_src<T>(I, total(2, sS), sa, pb, lf);
           put_phi(2, pb, lf);
