@@ -1156,9 +1156,13 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
   // (fromreg: the raw values are the halo row's in HR)
   // yr: the row's index (-1..ny), for the Dirichlet data
   // With a source: phi solves phi = sum f~ + dt F(phi) / 2 (eq. 2.25) and g
-  // gains lambda F(phi) rho(phi); afo receives the cell's coefficients at t_n + h.
+  // gains lambda F(phi) rho(phi); afo receives the cell's coefficients at t_n + h
+  // (from the cell's G_j in gin when given, else loaded here).
+  // binary64 with a source and four parts (two waves a SIMD) issues the
+  // loads of the source's G_j early (registers allow it there)
+  constexpr bool kPreG = SRC && sizeof(T) == 8 && P == 4;
   auto make_g = [&](int slot, int row, bool wy, int yr, int zp, T* g, T* f, auto fromreg,
-                    double* afo) __attribute__((always_inline)) {
+                    double* afo, const double* gin) __attribute__((always_inline)) {
     constexpr bool kReg = decltype(fromreg)::value;
     // phi in binary64 as (q0 + q1) + (q2 + q3), qj the sum over quarter j in
     // index order (four chains); a halo row in registers takes the quarters'
@@ -1184,7 +1188,8 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
     if constexpr (SRC) {
       const long long cell = ((long long)src_index(zp, nz, bcz) * ny + src_index(yr, ny, bcy)) * nx + scol;
       double an[4];
-      src_cell_coefs3(I, tb, cell, an, afo);
+      if (gin) src_coefs_from3(I, tb, gin, an, afo);
+      else src_cell_coefs3(I, tb, cell, an, afo);
       phi = solve_conserved3<double>(phi, 0.5 * I->dt, an, I->src_implicit != 0);
       lf = I->lambda * poly4(an, phi);
     }
@@ -1230,7 +1235,15 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
     using Halo = std::integral_constant<bool, LP::kHD>;
     T f[Q];
     double afx[4];   // a halo row's coefficients (not kept)
-    make_g(rs, me, wall_y, r, zp, G, f, Staged{}, AF);
+    // binary64 with a source, four parts: the G_j of this wave's row and of
+    // its halo row are loaded before either is used
+    double gme[DUGKS_MAX_SRC_TERMS], gho[DUGKS_MAX_SRC_TERMS];
+    if constexpr (kPreG) {
+      const long long zr = (long long)src_index(zp, nz, bcz) * ny;
+      src_load3(I, (zr + src_index(r, ny, bcy)) * nx + scol, gme);
+      if (rw <= 1) src_load3(I, (zr + src_index(rw == 0 ? y0 - 1 : y1, ny, bcy)) * nx + scol, gho);
+    }
+    make_g(rs, me, wall_y, r, zp, G, f, Staged{}, AF, kPreG ? gme : nullptr);
 #pragma unroll
     for (int k = 0; k < Q; ++k)
       if (part_of<Q, P>(k) == H) FT[k] = fma(kgv, G[k], (T)(-1.0 / 3.0) * f[k]);
@@ -1238,10 +1251,11 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
     if (rw <= 1) {
       T gx[Q];
       const int row = rw == 0 ? 0 : W - 1;
-      make_g(rs, row, rw == 0 ? wall_lo : wall_hi, rw == 0 ? y0 - 1 : y1, zp, gx, f, Halo{}, afx);
+      make_g(rs, row, rw == 0 ? wall_lo : wall_hi, rw == 0 ? y0 - 1 : y1, zp, gx, f, Halo{}, afx,
+             kPreG ? gho : nullptr);
       publish(slot, row, gx);
       if (ROWS == 1) {  // one row: its waves make both halo rows (always staged)
-        make_g(rs, W - 1, wall_hi, y1, zp, gx, f, Staged{}, afx);
+        make_g(rs, W - 1, wall_hi, y1, zp, gx, f, Staged{}, afx, nullptr);
         publish(slot, W - 1, gx);
       }
     }
@@ -1364,7 +1378,6 @@ __device__ __forceinline__ void step3p_half(const Inst3* __restrict__ I, int par
     // binary64 with a source, four parts: the parts that solve the north and
     // south faces load the G_j of that neighbouring row here, so that the
     // face work below hides the loads' latency (used after the next barrier)
-    constexpr bool kPreG = SRC && sizeof(T) == 8 && P == 4;
     double gpre[DUGKS_MAX_SRC_TERMS];
     if constexpr (kPreG && (H == 1 || H == 2)) {
       if (inner)
